@@ -1,0 +1,164 @@
+"""Pins of the oracle's G_{eta,h}, A, A^{-1} and coefficients against the paper's
+statements: symmetry/definiteness (section 6.1), the weak form B (section 3.1),
+the pointwise matrix M of Appendix A, the flat special case, the number-matrix
+eigenvalues and Theorem 4.1's eigenvalue interval (dense, tiny grids)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import operators as op
+from oracle import spectral as sp
+from paper_2506_16045_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _random_problem(g, rng, flat=False):
+    eta = I.random_positive_depth(g, rng, 0.6, 1.8)
+    if flat:
+        h = np.full(g.shape, 1.0)
+    else:
+        h = 1.0 + 0.3 * I.random_smooth_field(g, rng, modes=3)
+    gh, fl = op.bathy_gradient(h, g)
+    return eta, h, gh, fl
+
+
+GRIDS = [I.grid1d(24, 3.0), I.grid2d(8, 6, 2.0, 1.5)]
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=["1d", "2d"])
+def test_dense_G_symmetric_positive_definite(g, rng):
+    eta, h, gh, fl = _random_problem(g, rng)
+    G = op.dense_G(eta, gh, g)
+    assert np.max(np.abs(G - G.T)) <= 1e-12 * np.max(np.abs(G))
+    assert np.min(np.linalg.eigvalsh(G)) > 0
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=["1d", "2d"])
+def test_strong_form_equals_weak_assembly(g, rng):
+    eta, h, gh, fl = _random_problem(g, rng)
+    G = op.dense_G(eta, gh, g)
+    u = rng.normal(size=(g.d,) + g.shape)
+    Gu = op.apply_G(eta, gh, u, g)
+    assert np.max(np.abs(Gu.ravel() - G @ u.ravel())) <= 1e-11 * np.max(np.abs(Gu))
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=["1d", "2d"])
+def test_quadratic_form_is_pointwise_M(g, rng):
+    """u^T G u = sum_x (u, div u)^T M(x) (u, div u) with M of Appendix A (Def:MatrixM)."""
+    eta, h, gh, fl = _random_problem(g, rng)
+    u = rng.normal(size=(g.d,) + g.shape)
+    lhs = np.sum(u * op.apply_G(eta, gh, u, g))
+    vec = np.concatenate([u, sp.div(u, g)[None]], axis=0)       # (d+1, ...)
+    vec = np.moveaxis(vec, 0, -1)
+    M = op.pointwise_M(eta, gh)
+    rhs = np.sum(np.einsum("...i,...ij,...j->...", vec, M, vec))
+    assert lhs == pytest.approx(rhs, rel=1e-11)
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=["1d", "2d"])
+def test_G_equals_A_for_constant_depth_flat_bottom(g, rng):
+    eta0 = 1.7
+    eta = np.full(g.shape, eta0)
+    gh, fl = op.bathy_gradient(np.full(g.shape, 0.9), g)
+    assert fl and not np.any(gh)
+    s, a, k = op.coefficients(eta, gh, fl)
+    assert (s, a, k) == (eta0, eta0 ** 3 / 3.0, 1.0)
+    u = rng.normal(size=(g.d,) + g.shape)
+    assert np.allclose(op.apply_G(eta, gh, u, g), op.apply_A(s, a, u, g), rtol=1e-12, atol=1e-12)
+
+
+def test_2d_constant_in_y_reduces_to_1d(rng):
+    """Section 6.3: a 1D case extended constantly in y with v = 0 reproduces 1D."""
+    g1 = I.grid1d(32, 2.0)
+    g2 = I.grid2d(32, 4, 2.0, 1.0)
+    eta1, h1, gh1, _ = _random_problem(g1, rng)
+    u1 = rng.normal(size=(1, 32))
+    eta2 = np.tile(eta1, (4, 1))
+    h2 = np.tile(h1, (4, 1))
+    gh2, _ = op.bathy_gradient(h2, g2)
+    u2 = np.stack([np.tile(u1[0], (4, 1)), np.zeros((4, 32))])
+    G1 = op.apply_G(eta1, gh1, u1, g1)
+    G2 = op.apply_G(eta2, gh2, u2, g2)
+    assert np.allclose(G2[0], np.tile(G1[0], (4, 1)), rtol=1e-12, atol=1e-12)
+    assert np.max(np.abs(G2[1])) < 1e-12
+
+
+def test_number_matrix_eigenvalues():
+    ev = np.linalg.eigvalsh(np.array([[1.0, 0.5], [0.5, 1.0 / 3.0]]))
+    assert ev[0] == pytest.approx(op.LAMBDA_MINUS, rel=1e-13)
+    assert ev[1] == pytest.approx(op.LAMBDA_PLUS, rel=1e-13)
+    assert op.LAMBDA_PLUS / op.LAMBDA_MINUS == pytest.approx((4 + math.sqrt(13)) / (4 - math.sqrt(13)))
+
+
+def test_coefficients_closed_form_hand_values():
+    g = I.grid1d(2, 1.0)
+    eta = np.array([1.0, 2.0])
+    gh = np.array([[0.5, 0.0]])
+    lp, lm = op.LAMBDA_PLUS, op.LAMBDA_MINUS
+    s, a, k = op.coefficients(eta, gh, False)
+    assert s == pytest.approx(max(1.0 + lp * 0.25, 2.0))
+    assert a == pytest.approx(lp * 8.0)
+    assert k == pytest.approx(max(s / 1.0, lp / lm * 8.0))
+    s, a, k = op.coefficients(eta, gh, True)
+    assert (s, a, k) == (2.0, 8.0 / 3.0, 8.0)
+    s2, a2, k2 = op.coefficients(eta, gh, False, kind="replacement")
+    assert s2 == pytest.approx(2.0 * (1 + lp * 0.25))
+    assert a2 == pytest.approx(lp * 8.0)
+    with pytest.raises(ValueError):
+        op.coefficients(np.array([1.0, -0.1]), gh, False)
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=["1d", "2d"])
+def test_pointwise_matrix_inequality(g, rng):
+    """(MI) of Appendix A: kappa_ub^{-1} diag(s,s,a) <= M(x) <= diag(s,s,a) at every point."""
+    for flat in (True, False):
+        eta, h, gh, fl = _random_problem(g, rng, flat=flat)
+        s, a, k = op.coefficients(eta, gh, fl)
+        M = op.pointwise_M(eta, gh)
+        Dg = np.diag([s] * g.d + [a])
+        up = np.linalg.eigvalsh(Dg - M)
+        lo = np.linalg.eigvalsh(M - Dg / k)
+        assert up.min() >= -1e-12 * s and lo.min() >= -1e-12 * s
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=["1d", "2d"])
+def test_solve_A_inverts_dense_A(g, rng):
+    s, a = 1.3, 0.7
+    A = op.dense_A(s, a, g)
+    r = rng.normal(size=(g.d,) + g.shape)
+    z = op.solve_A(s, a, r, g)
+    assert np.allclose(A @ z.ravel(), r.ravel(), rtol=1e-11, atol=1e-11)
+    assert np.allclose(op.apply_A(s, a, z, g).ravel(), r.ravel(), rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("g", [I.grid1d(32, 2.0), I.grid2d(8, 8, 1.0, 1.0)], ids=["1d", "2d"])
+@pytest.mark.parametrize("flat", [True, False])
+def test_theorem_4_1_eigenvalue_interval(g, flat, rng):
+    eta, h, gh, fl = _random_problem(g, rng, flat=flat)
+    s, a, k = op.coefficients(eta, gh, fl)
+    lam = scipy.linalg.eigh(op.dense_G(eta, gh, g), op.dense_A(s, a, g), eigvals_only=True)
+    assert lam.min() >= (1.0 / k) * (1 - 1e-9)
+    assert lam.max() <= 1.0 + 1e-9
+    assert lam.max() / lam.min() <= k * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_eigenvalues_of_section_6_2_test_problem(n):
+    """eta0 = h0 = 1: every eigenvalue in [1/kappa_ub, 1]; the bulk of the spectrum in
+    ~[3e-2, 3e-1] with a handful of isolated values outside (qualitative, as printed)."""
+    with open(os.path.join(GOLDEN, "paper_numbers.json")) as fh:
+        gold = json.load(fh)["eig_bulk_interval_eta0_h0_1"]
+    lo_b, hi_b = gold["value"]
+    g, eta, h, b = I.pcg_test_problem_1d(n, 1.0, 1.0)
+    gh, fl = op.bathy_gradient(h, g)
+    s, a, k = op.coefficients(eta, gh, fl)
+    lam = scipy.linalg.eigh(op.dense_G(eta, gh, g), op.dense_A(s, a, g), eigvals_only=True)
+    assert lam.min() >= 1.0 / k and lam.max() <= 1.0
+    outside = int(np.sum((lam < lo_b) | (lam > hi_b)))
+    assert 1 <= outside <= 2 * gold["isolated_about"]
+    assert outside <= 0.15 * n
