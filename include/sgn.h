@@ -1,0 +1,215 @@
+/*
+ * sgn.h -- C ABI of libsgn.so, the MI355X (gfx950) hot path of the
+ * Serre-Green-Naghdi constraint solver of Feng, Shirokoff and Choi,
+ * "Preconditioning and Linearly Implicit Time Integration for the
+ * Serre-Green-Naghdi Equations" (arXiv 2506.16045).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named d_* are DEVICE pointers owned by the caller (for example
+ *    PyTorch tensors).  The library never frees them and never keeps them past
+ *    the call, except the sgn_state object, which keeps the pointers given to
+ *    sgn_state_create until sgn_state_destroy.
+ *  - Fields are FP64, contiguous, in the layout of section 6.1 of the paper:
+ *    1D scalar fields [nx], 2D scalar fields [ny][nx] with x the fast index,
+ *    x_i = i Lx / nx, y_j = j Ly / ny (doubly periodic).  Vector fields
+ *    (velocity u, U = G u, grad h) are component-major: [d][ny][nx].
+ *  - Grid sizes must be powers of two: 2 <= nx <= 16384; in 2D 2 <= ny <= 4096.
+ *  - Every call enqueues its device work on the context's HIP stream.  Calls
+ *    that return scalars to the host (coefficients, solve and step info)
+ *    synchronise that stream before returning.
+ *  - Errors are returned as sgn_status, never thrown; sgn_last_error gives a
+ *    message.  Invalid arguments are rejected before any device work starts.
+ *  - A workspace (d_ws) is caller-allocated device memory of at least
+ *    sgn_workspace_bytes() bytes, 256-byte aligned; its contents are scratch
+ *    between calls.  Two calls that overlap in time must not share one.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef SGN_H
+#define SGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sgn_status {
+    SGN_OK = 0,
+    SGN_EINVAL = -1,        /* bad argument (null pointer, size, option) */
+    SGN_EDOMAIN = -2,       /* total depth not strictly positive, or NaN/Inf data */
+    SGN_ENOCONV = -3,       /* Krylov solve hit max_iter; output holds the last iterate */
+    SGN_ENOMEM = -4,        /* device allocation inside sgn_create failed */
+    SGN_EDEVICE = -5,       /* a HIP runtime call failed */
+    SGN_EUNSUPPORTED = -6   /* size not a power of two or above the limits */
+} sgn_status;
+
+typedef struct sgn_ctx sgn_ctx;
+typedef struct sgn_state sgn_state;
+
+/* Grid (section 6.1): dim 1 or 2; ny and Ly are ignored when dim = 1. */
+typedef struct sgn_grid {
+    int32_t dim;
+    int32_t nx;
+    int32_t ny;
+    double Lx;
+    double Ly;
+} sgn_grid;
+
+/* Coefficients of the preconditioner A = sigma I - alpha grad(div)  (Def:A),
+ * and the bound kappa_ub of Theorem 4.1.  flat = 1 selects the flat-bottom
+ * formulas (Eq:FlatbathCoeff), 0 the variable-bathymetry ones
+ * (Eq:Optcoeff, Eq:Optcoeffb). */
+typedef struct sgn_coeffs {
+    double sigma;
+    double alpha;
+    double kappa_ub;
+    int32_t flat;
+} sgn_coeffs;
+
+typedef enum sgn_method { SGN_PCG = 0, SGN_GMRES = 1 } sgn_method;
+typedef enum sgn_precision {
+    SGN_FP64 = 0,   /* every operation in FP64 */
+    SGN_MIXED = 1   /* FP32 operator, FFT and preconditioner inside an FP64
+                       iterative refinement: residual, dots, update in FP64 */
+} sgn_precision;
+typedef enum sgn_coeff_kind {
+    SGN_COEFF_OPTIMAL = 0,     /* Eq:Optcoeff */
+    SGN_COEFF_REPLACEMENT = 1  /* sigma**, alpha** of Remark 4.2 */
+} sgn_coeff_kind;
+
+typedef struct sgn_solve_opts {
+    int32_t method;        /* sgn_method */
+    int32_t precision;     /* sgn_precision */
+    double tol;            /* stop when ||r||_2 <= tol ||b||_2 */
+    int32_t max_iter;      /* Krylov iterations (inner iterations in mixed mode) */
+    int32_t x0_is_guess;   /* 1: u_inout is the initial guess; 0: start from 0 */
+    int32_t gmres_restart; /* GMRES restart length (<= 64) */
+    double inner_tol;      /* mixed mode: relative tolerance of each FP32 inner solve */
+    int32_t max_outer;     /* mixed mode: refinement steps */
+    int32_t check_every;   /* convergence flag read back every this many iterations (>= 1) */
+    int32_t coeff_kind;    /* sgn_coeff_kind, used when coefficients are computed */
+} sgn_solve_opts;
+
+typedef struct sgn_solve_info {
+    int32_t iters;         /* Krylov iterations (all inner iterations in mixed mode) */
+    int32_t outer_iters;   /* refinement steps (0 in FP64 mode) */
+    int32_t converged;
+    double relres;         /* ||b - G u||_2 / ||b||_2 as tracked by the solver */
+    sgn_coeffs coeffs;     /* coefficients of A that were used */
+} sgn_solve_info;
+
+typedef struct sgn_step_info {
+    int64_t solves;        /* Krylov solves performed */
+    int64_t iters;         /* Krylov iterations summed over the solves */
+    int32_t max_iters;     /* largest iteration count of one solve */
+    int32_t converged;     /* 1 if every solve converged */
+    double t;              /* simulated time of the state after the call */
+    int64_t steps_done;    /* steps taken by the state since creation */
+} sgn_step_info;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Allocates the FFT twiddle tables
+ * and a small pinned readback buffer.  SGN_ENOMEM / SGN_EDEVICE on failure. */
+sgn_status sgn_create(sgn_ctx **ctx, int device, void *hip_stream);
+void sgn_destroy(sgn_ctx *ctx);
+sgn_status sgn_set_stream(sgn_ctx *ctx, void *hip_stream);
+const char *sgn_last_error(const sgn_ctx *ctx);
+/* Library version string. */
+const char *sgn_version(void);
+
+/* Bytes of workspace any single call below needs for this grid and precision. */
+size_t sgn_workspace_bytes(const sgn_grid *grid, int32_t precision);
+
+/* ---- bathymetry and coefficients (section 4) --------------------------- */
+
+/* grad h on the grid and the flat flag.  grad h is the spectral gradient D h
+ * (section 6.1); a bathymetry that is exactly constant on the grid is flat and
+ * gets grad h = 0 exactly (|grad h|_max = 0 selects Eq:FlatbathCoeff).
+ * d_h: [ny][nx]; d_grad_h: [d][ny][nx] output; *flat: host output. */
+sgn_status sgn_bathy_prepare(sgn_ctx *ctx, const sgn_grid *grid, const double *d_h,
+                             double *d_grad_h, int32_t *flat, void *d_ws);
+
+/* sigma*, alpha*, kappa_ub from eta and grad h (Eq:MaxMinWaveFields,
+ * Eq:FlatbathCoeff, Eq:Optcoeff, Eq:Optcoeffb; Remark 4.2 for kind = 1).
+ * SGN_EDOMAIN if min eta <= 0 or any value is not finite. */
+sgn_status sgn_precond_coeffs(sgn_ctx *ctx, const sgn_grid *grid, const double *d_eta,
+                              const double *d_grad_h, int32_t flat, int32_t kind,
+                              sgn_coeffs *out, void *d_ws);
+
+/* ---- operators (sections 2.2, 4, 6.1) ---------------------------------- */
+
+/* out = G_{eta,h} u  (Def:G) with spectral derivatives.  d_eta is the total
+ * depth ("h" of the operator's name), d_grad_h the bathymetry gradient
+ * ("b").  d_u, d_out: [d][ny][nx]; d_out may not alias the inputs. */
+sgn_status sgn_apply_constraint(sgn_ctx *ctx, const sgn_grid *grid, const double *d_eta,
+                                const double *d_grad_h, const double *d_u, double *d_out,
+                                void *d_ws);
+
+/* out = A^{-1} rhs with A = sigma I - alpha grad(div)  (Def:A), diagonal in
+ * Fourier space with each Nyquist wavenumber set to zero (section 6.1).
+ * Only sigma and alpha of *coeffs are read; both must be > 0. */
+sgn_status sgn_precond_solve(sgn_ctx *ctx, const sgn_grid *grid, const sgn_coeffs *coeffs,
+                             const double *d_rhs, double *d_out, void *d_ws);
+
+/* Solve G_{eta,h} u = rhs by PCG preconditioned with A (section 3.2,
+ * Eq:PCGLinSyst) or by right-preconditioned GMRES.  coeffs = NULL computes
+ * the coefficients from eta (opts->coeff_kind).  On SGN_ENOCONV d_u_inout
+ * holds the last iterate and *info is filled.  opts = NULL uses PCG, FP64,
+ * tol 1e-12, max_iter 1000, zero initial guess. */
+sgn_status sgn_krylov_solve(sgn_ctx *ctx, const sgn_grid *grid, const double *d_eta,
+                            const double *d_grad_h, const double *d_rhs, double *d_u_inout,
+                            const sgn_coeffs *coeffs, const sgn_solve_opts *opts,
+                            sgn_solve_info *info, void *d_ws);
+
+/* Right-hand side of the constraint form (Eq:DSWEcf, Def:bigF, Eq:DAE_DSWE):
+ * eta_t = -div(eta u), U_t = -eta grad(zeta) - div(eta u (x) u) + F with
+ * zeta = eta - h and (u.grad)^2 h read as u.grad(u.grad h).  Always FP64.
+ * d_eta_t: [ny][nx]; d_U_t: [d][ny][nx]. */
+sgn_status sgn_rhs(sgn_ctx *ctx, const sgn_grid *grid, const double *d_eta, const double *d_h,
+                   const double *d_grad_h, const double *d_u, double *d_eta_t, double *d_U_t,
+                   void *d_ws);
+
+/* ---- time stepping (section 5) ----------------------------------------- */
+
+/* Bytes of state workspace (stage buffers and multistep history). */
+size_t sgn_state_workspace_bytes(const sgn_grid *grid, int32_t precision);
+
+/* Bind a time-stepping state to caller-owned device fields: bathymetry h and
+ * grad h (read), and eta, U = G u, u (advanced in place by the step calls).
+ * U must already equal G_{eta,h} u (sgn_apply_constraint).  d_state_ws holds
+ * sgn_state_workspace_bytes() bytes and d_ws sgn_workspace_bytes() bytes; both
+ * stay owned by the caller and bound to the state until sgn_state_destroy. */
+sgn_status sgn_state_create(sgn_ctx *ctx, const sgn_grid *grid, const double *d_h,
+                            const double *d_grad_h, int32_t flat, double *d_eta, double *d_U,
+                            double *d_u, void *d_state_ws, void *d_ws, sgn_state **state);
+void sgn_state_destroy(sgn_state *state);
+
+/* nsteps steps of classical RK4 (Eq:ERK) with one Krylov solve per stage
+ * (4 per step).  Each solve starts from the most recent velocity and builds
+ * A from the current eta. */
+sgn_status sgn_step_rk4(sgn_ctx *ctx, sgn_state *state, double dt, int32_t nsteps,
+                        const sgn_solve_opts *opts, sgn_step_info *info);
+
+/* nsteps steps of Adams-Bashforth of order 2..4 (Eq:AB, Table LMMCoeffs), one
+ * Krylov solve per step.  Missing history is filled by RK4 steps with the
+ * same dt; changing order or dt restarts the history. */
+sgn_status sgn_step_ab(sgn_ctx *ctx, sgn_state *state, int32_t order, double dt,
+                       int32_t nsteps, const sgn_solve_opts *opts, sgn_step_info *info);
+
+/* nsteps steps of the linearly implicit SBDF2 scheme (Eq:MM): one A-solve per
+ * step, no Krylov iteration.  fixed = NULL takes sigma*, alpha* from the
+ * state's current eta (section 6.5 uses the initial data) and keeps them for
+ * the life of the history.  The first step of a history is an RK4 step
+ * (solver options opts). */
+sgn_status sgn_step_linimp(sgn_ctx *ctx, sgn_state *state, double dt, int32_t nsteps,
+                           const sgn_coeffs *fixed, const sgn_solve_opts *opts,
+                           sgn_step_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGN_H */

@@ -1,0 +1,728 @@
+// Kernels of the SGN hot path.  Templated on the working precision T (double
+// or float) and on the dimension D (1 or 2); reductions always accumulate in
+// double.  Layouts: physical fields [ny][nx]; "H" and "S" spectral fields
+// [kx][y] / [kx][ky] with kx = 0..nx/2 (see sgn_device.h).
+#pragma once
+#include "sgn_device.h"
+
+namespace sgn {
+
+// Device-side scalars of one Krylov solve (one instance per solve in flight).
+struct SolveScal {
+    double rho, alpha, beta, bb, rr, pq, tol2, relres;
+    double sig, alp, kap;     // preconditioner A = sig I - alp grad div, bound kappa_ub
+    double inv_n;             // 1 / (nx ny)
+    double red[8];            // results of the last generic reduction
+    int iter, max_iter, done, converged, flat, status;
+    unsigned counter;         // last-block-done counter
+    int pad;
+};
+
+constexpr int PARTIALS_MAX = 4096;  // blocks of a reducing launch (x NACC doubles)
+
+template <typename T, int N>
+struct PtrList {
+    T* p[N];
+    int n;
+};
+constexpr int MAXF = 12;
+
+// Mode weight of the half spectrum for Parseval sums: kx = 0 and kx = nx/2 appear
+// once in the full spectrum, every other kx twice (with its conjugate).
+__device__ __forceinline__ double half_weight(int kx, int nx) {
+    return (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+}
+
+// z = A^{-1} r in Fourier space (Def:A, section 6.1):
+//   1D: r / (sig + alp k^2);  2D: (r - alp k (k.r) / (sig + alp |k|^2)) / sig.
+template <typename T, int D>
+__device__ __forceinline__ void precond_mode(T kx, T ky, T sig, T alp, const cpx<T> (&r)[D],
+                                             cpx<T> (&z)[D]) {
+    if (D == 1) {
+        const T s = (T)1 / (sig + alp * kx * kx);
+        z[0] = s * r[0];
+    } else {
+        const T k2 = kx * kx + ky * ky;
+        const cpx<T> kr = kx * r[0] + ky * r[1 % D];
+        const T c = alp / (sig + alp * k2);
+        const T is = (T)1 / sig;
+        z[0] = is * (r[0] - (c * kx) * kr);
+        z[1 % D] = is * (r[1 % D] - (c * ky) * kr);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Generic FFT passes
+// ---------------------------------------------------------------------------
+
+// Forward row transforms of n physical fields (Tin = double or T) into H fields.
+template <typename T, typename Tin, int EPC>
+__global__ void __launch_bounds__(1024) k_rows_fwd(RowGeom g, PtrList<const Tin, MAXF> src,
+                                                   PtrList<cpx<T>, MAXF> dst,
+                                                   const cpx<T>* __restrict__ tw, T scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const RowThread<T> rt = row_thread<T>(g, lds);
+    for (int f = 0; f < src.n; ++f) {
+        cpx<T> z[EPC];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = rt.t + g.TPR * e;
+            z[e] = C<T>(0, 0);
+            if (j < g.M && rt.valid) {
+                const size_t o = (size_t)rt.y * g.nx + 2 * j;
+                z[e] = C<T>((T)src.p[f][o], (T)src.p[f][o + 1]);
+            }
+        }
+        row_forward<T, EPC>(g, rt, z, dst.p[f], tw, scale);
+    }
+}
+
+// Inverse row transforms of n H fields into physical fields (Tout):
+// dst = acc * dst + scale * value  (acc = 0 overwrites).
+template <typename T, typename Tout, int EPC>
+__global__ void __launch_bounds__(1024) k_rows_inv(RowGeom g, PtrList<const cpx<T>, MAXF> src,
+                                                   PtrList<Tout, MAXF> dst,
+                                                   const cpx<T>* __restrict__ tw, T scale, T acc) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const RowThread<T> rt = row_thread<T>(g, lds);
+    for (int f = 0; f < src.n; ++f) {
+        cpx<T> z[EPC];
+        row_inverse<T, EPC>(g, rt, src.p[f], tw, z);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = rt.t + g.TPR * e;
+            if (j < g.M && rt.valid) {
+                const size_t o = (size_t)rt.y * g.nx + 2 * j;
+                Tout* d = dst.p[f];
+                T v0 = scale * z[e].re, v1 = scale * z[e].im;
+                if (acc != (T)0) {
+                    v0 += acc * (T)d[o];
+                    v1 += acc * (T)d[o + 1];
+                }
+                d[o] = (Tout)v0;
+                d[o + 1] = (Tout)v1;
+            }
+        }
+    }
+}
+
+// Linear spectral operators on columns: out_o = sum_i c(code[o][i], k) in_i, with
+// y-FFT of the inputs and y-IFFT of the outputs.  Codes: 0 none, 1 identity,
+// 2 i kx, 3 i ky, 4 (i kx)^2, 5 (i kx)(i ky), 6 (i ky)^2; every value is also
+// multiplied by `scale`.
+constexpr int LIN_MAXO = 6;
+constexpr int LIN_MAXI = 5;
+struct LinCodes {
+    int code[LIN_MAXO][LIN_MAXI];
+    int no;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> lin_coef(int code, T kx, T ky) {
+    switch (code) {
+        case 1: return C<T>(1, 0);
+        case 2: return C<T>(0, kx);
+        case 3: return C<T>(0, ky);
+        case 4: return C<T>(-kx * kx, 0);
+        case 5: return C<T>(-kx * ky, 0);
+        case 6: return C<T>(-ky * ky, 0);
+        default: return C<T>(0, 0);
+    }
+}
+
+template <typename T, int EPC, int NI>
+__global__ void __launch_bounds__(1024) k_cols_lin(ColGeom g, PtrList<const cpx<T>, MAXF> src,
+                                                   PtrList<cpx<T>, MAXF> dst, LinCodes lc,
+                                                   const cpx<T>* __restrict__ tw, T tpx, T tpy,
+                                                   T scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const ColThread<T> ct = col_thread<T>(g, lds);
+    cpx<T> in[NI][EPC];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) col_load<T, EPC>(g, ct, src.p[i], true, tw, in[i]);
+    const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
+    for (int o = 0; o < lc.no; ++o) {
+        cpx<T> v[EPC];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+            const T ky = (g.ny > 1) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
+            cpx<T> s = C<T>(0, 0);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) s = s + lin_coef<T>(lc.code[o][i], kx, ky) * in[i][e];
+            v[e] = scale * s;
+        }
+        col_store<T, EPC>(g, ct, v, dst.p[o], true, tw);
+    }
+}
+
+// A^{-1} on D spectral columns: y-FFT, per-mode A^{-1} (times scale), y-IFFT.
+template <typename T, int EPC, int D>
+__global__ void __launch_bounds__(1024) k_cols_precond(ColGeom g, PtrList<const cpx<T>, MAXF> src,
+                                                       PtrList<cpx<T>, MAXF> dst,
+                                                       const cpx<T>* __restrict__ tw, T tpx, T tpy,
+                                                       T sig, T alp, T scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const ColThread<T> ct = col_thread<T>(g, lds);
+    cpx<T> in[D][EPC];
+#pragma unroll
+    for (int c = 0; c < D; ++c) col_load<T, EPC>(g, ct, src.p[c], true, tw, in[c]);
+    const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
+    cpx<T> out[D][EPC];
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int j = ct.t + g.TPC * e;
+        const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
+        cpx<T> r[D], z[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) r[c] = in[c][e];
+        precond_mode<T, D>(kx, ky, sig, alp, r, z);
+#pragma unroll
+        for (int c = 0; c < D; ++c) out[c][e] = scale * z[c];
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) col_store<T, EPC>(g, ct, out[c], dst.p[c], true, tw);
+}
+
+// ---------------------------------------------------------------------------
+// Krylov solve kernels (PCG of section 3.2 with the state x, r, p, q kept in
+// the S layout; dot products by Parseval over the half spectrum, FP64).
+// One iteration is C1 -> R1 -> C2 -> C3:
+//   C1: z = A^{-1} r, p = z + beta p; emits (p, div p) / (nx ny) and the y-IFFT
+//   R1: x-IFFT -> pointwise  a = eta p + grad h (eta^2/2 div p + eta grad h.p),
+//                            w = eta^3/3 div p + eta^2/2 grad h.p  -> x-FFT
+//   C2: y-FFT; q = a - i k w  (= G p, Def:G), p.q -> alpha
+//   C3: x += alpha p, r -= alpha q, z = A^{-1} r, r.z and r.r -> beta, stop test
+// Every kernel returns at once when the solve is done.
+// ---------------------------------------------------------------------------
+enum { C1_UPDATE = 0, C1_COPY = 1 };
+
+template <typename T, int EPC, int D, int MODE>
+__global__ void __launch_bounds__(1024) k_pcg_c1(ColGeom g, const cpx<T>* __restrict__ tw,
+                                                 SolveScal* __restrict__ sc,
+                                                 const cpx<T>* __restrict__ rh, cpx<T>* __restrict__ ph,
+                                                 const cpx<T>* __restrict__ xsrc, cpx<T>* __restrict__ H,
+                                                 size_t NS, T tpx, T tpy) {
+    if (sc->done) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const ColThread<T> ct = col_thread<T>(g, lds);
+    const T beta = (T)sc->beta, sig = (T)sc->sig, alp = (T)sc->alp, inv_n = (T)sc->inv_n;
+    const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
+    cpx<T> o[D + 1][EPC];
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int j = ct.t + g.TPC * e;
+#pragma unroll
+        for (int c = 0; c <= D; ++c) o[c][e] = C<T>(0, 0);
+        if (ct.valid && j < g.ny) {
+            const size_t idx = (size_t)ct.kx * g.ny + j;
+            const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
+            cpx<T> p[D];
+            if (MODE == C1_COPY) {
+#pragma unroll
+                for (int c = 0; c < D; ++c) p[c] = xsrc[c * NS + idx];
+            } else {
+                cpx<T> r[D], z[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) r[c] = rh[c * NS + idx];
+                precond_mode<T, D>(kx, ky, sig, alp, r, z);
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    p[c] = z[c] + beta * ph[c * NS + idx];
+                    ph[c * NS + idx] = p[c];
+                }
+            }
+            cpx<T> dv = ik(kx, p[0]);
+            if (D == 2) dv = dv + ik(ky, p[1 % D]);
+#pragma unroll
+            for (int c = 0; c < D; ++c) o[c][e] = inv_n * p[c];
+            o[D][e] = inv_n * dv;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c <= D; ++c) col_store<T, EPC>(g, ct, o[c], H + c * NS, true, tw);
+}
+
+template <typename T, int EPC, int D>
+__global__ void __launch_bounds__(1024) k_pcg_r1(RowGeom g, const cpx<T>* __restrict__ tw,
+                                                 SolveScal* __restrict__ sc, cpx<T>* H, size_t NS,
+                                                 const T* __restrict__ eta, const T* __restrict__ gh) {
+    if (sc->done) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const RowThread<T> rt = row_thread<T>(g, lds);
+    cpx<T> v[D + 1][EPC];
+#pragma unroll
+    for (int c = 0; c <= D; ++c) row_inverse<T, EPC>(g, rt, H + c * NS, tw, v[c]);
+    const size_t npts = (size_t)g.nx * g.ny;
+    const T third = (T)1 / (T)3, half = (T)0.5;
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int j = rt.t + g.TPR * e;
+        if (j < g.M && rt.valid) {
+            const size_t o = (size_t)rt.y * g.nx + 2 * j;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const T et = eta[o + s];
+                T hc[D], pc[D];
+                T bt = 0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    hc[c] = gh[c * npts + o + s];
+                    pc[c] = s ? v[c][e].im : v[c][e].re;
+                    bt += hc[c] * pc[c];
+                }
+                const T dl = s ? v[D][e].im : v[D][e].re;
+                const T e2 = et * et;
+                const T w1 = third * e2 * et * dl + half * e2 * bt;
+                const T w2 = half * e2 * dl + et * bt;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const T a = et * pc[c] + hc[c] * w2;
+                    if (s) v[c][e].im = a; else v[c][e].re = a;
+                }
+                if (s) v[D][e].im = w1; else v[D][e].re = w1;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c <= D; ++c) row_forward<T, EPC>(g, rt, v[c], H + c * NS, tw, (T)1);
+}
+
+enum { C2_DOT = 0, C2_RESID = 1, C2_STORE = 2 };
+
+// MODE C2_DOT: q = G p -> qh, partial p.q (alpha = rho / p.q in the last block).
+// MODE C2_RESID: r = b - G x -> rh (no reduction).
+// MODE C2_STORE: q = G p -> qh (no reduction).
+template <typename T, int EPC, int D, int MODE>
+__global__ void __launch_bounds__(1024) k_pcg_c2(ColGeom g, const cpx<T>* __restrict__ tw,
+                                                 SolveScal* __restrict__ sc, const cpx<T>* __restrict__ H,
+                                                 size_t NS, cpx<T>* __restrict__ qh,
+                                                 const cpx<T>* __restrict__ ph,
+                                                 const cpx<T>* __restrict__ bh, cpx<T>* __restrict__ rh,
+                                                 double* __restrict__ partials, T tpx, T tpy) {
+    if (sc->done) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[16];
+    const ColThread<T> ct = col_thread<T>(g, lds);
+    cpx<T> in[D + 1][EPC];
+#pragma unroll
+    for (int c = 0; c <= D; ++c) col_load<T, EPC>(g, ct, H + c * NS, true, tw, in[c]);
+    const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
+    const double w = ct.valid ? half_weight(ct.kx, g.nx) : 0.0;
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int j = ct.t + g.TPC * e;
+        if (ct.valid && j < g.ny) {
+            const size_t idx = (size_t)ct.kx * g.ny + j;
+            const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
+            const cpx<T> wv = in[D][e];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const T kc = (c == 0) ? kx : ky;
+                const cpx<T> q = in[c][e] - ik(kc, wv);
+                if (MODE == C2_STORE) {
+                    qh[c * NS + idx] = q;
+                } else if (MODE == C2_DOT) {
+                    qh[c * NS + idx] = q;
+                    const cpx<T> p = ph[c * NS + idx];
+                    acc[0] += w * ((double)p.re * (double)q.re + (double)p.im * (double)q.im);
+                } else {
+                    rh[c * NS + idx] = bh[c * NS + idx] - q;
+                }
+            }
+        }
+    }
+    if (MODE == C2_DOT) {
+        block_sum<1>(acc, red);
+        if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+        if (last_block_done(&sc->counter, gridDim.x)) {
+            if (threadIdx.x == 0) {
+                double s = 0.0;
+                for (unsigned b = 0; b < gridDim.x; ++b) s += partials[b];
+                s *= sc->inv_n;
+                sc->pq = s;
+                sc->alpha = sc->rho / s;
+                sc->counter = 0;
+            }
+        }
+    }
+}
+
+// Flat loop over the S modes: kx = idx / ny, ky index = idx % ny.
+// INIT: no update; computes rho and ||r||^2 of the initial residual.  With
+// init_bb the right-hand side norm is taken as ||r_0|| (zero initial guess);
+// otherwise a zero right-hand side (bb == 0) gives x = 0 at once.
+template <typename T, int D, bool INIT>
+__global__ void __launch_bounds__(256) k_pcg_c3(int nx, int ny, size_t NS, SolveScal* __restrict__ sc,
+                                                cpx<T>* __restrict__ xh, cpx<T>* __restrict__ rh,
+                                                const cpx<T>* __restrict__ ph, const cpx<T>* __restrict__ qh,
+                                                double* __restrict__ partials, T tpx, T tpy, int init_bb) {
+    if (sc->done) return;
+    __shared__ double red[32];
+    const bool zero_x = INIT && !init_bb && sc->bb == 0.0;
+    const T alpha = INIT ? (T)0 : (T)sc->alpha;
+    const T sig = (T)sc->sig, alp = (T)sc->alp;
+    double acc[2] = {0.0, 0.0};
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < NS; idx += stride) {
+        const int kxi = (int)(idx / ny);
+        const int kyi = (int)(idx - (size_t)kxi * ny);
+        const T kx = wavenumber<T>(kxi, nx, tpx);
+        const T ky = (D == 2) ? wavenumber<T>(kyi, ny, tpy) : (T)0;
+        cpx<T> r[D], z[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            r[c] = rh[c * NS + idx];
+            if (zero_x) {
+                xh[c * NS + idx] = C<T>(0, 0);
+                r[c] = C<T>(0, 0);
+            }
+            if (!INIT) {
+                xh[c * NS + idx] = xh[c * NS + idx] + alpha * ph[c * NS + idx];
+                r[c] = r[c] - alpha * qh[c * NS + idx];
+                rh[c * NS + idx] = r[c];
+            }
+        }
+        precond_mode<T, D>(kx, ky, sig, alp, r, z);
+        const double w = half_weight(kxi, nx);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            acc[0] += w * ((double)r[c].re * (double)z[c].re + (double)r[c].im * (double)z[c].im);
+            acc[1] += w * ((double)r[c].re * (double)r[c].re + (double)r[c].im * (double)r[c].im);
+        }
+    }
+    block_sum<2>(acc, red);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = acc[0];
+        partials[2 * blockIdx.x + 1] = acc[1];
+    }
+    if (last_block_done(&sc->counter, gridDim.x)) {
+        if (threadIdx.x == 0) {
+            double rz = 0.0, rr = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) {
+                rz += partials[2 * b];
+                rr += partials[2 * b + 1];
+            }
+            rz *= sc->inv_n;
+            rr *= sc->inv_n;
+            sc->rr = rr;
+            if (INIT && init_bb) sc->bb = rr;
+            sc->relres = sc->bb > 0.0 ? sqrt(rr / sc->bb) : 0.0;
+            if (!INIT) sc->iter += 1;
+            if (INIT && sc->bb == 0.0) {
+                sc->done = 1;
+                sc->converged = 1;
+            } else if (!(rr == rr) || !(rz == rz)) {
+                sc->done = 1;
+                sc->status = -2;
+            } else if (rr <= sc->tol2 * sc->bb) {
+                sc->done = 1;
+                sc->converged = 1;
+            } else if (sc->iter >= sc->max_iter) {
+                sc->done = 1;
+            }
+            sc->beta = INIT ? 0.0 : rz / sc->rho;
+            sc->rho = rz;
+            sc->counter = 0;
+        }
+    }
+}
+
+// b_hat from the H layout: y-FFT, store to bh (and rh if non-null), ||b||^2 -> sc->bb.
+template <typename T, int EPC, int D>
+__global__ void __launch_bounds__(1024) k_setup_b(ColGeom g, const cpx<T>* __restrict__ tw,
+                                                  SolveScal* __restrict__ sc, const cpx<T>* __restrict__ H,
+                                                  size_t NS, cpx<T>* __restrict__ bh, cpx<T>* __restrict__ rh,
+                                                  double* __restrict__ partials) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[16];
+    const ColThread<T> ct = col_thread<T>(g, lds);
+    const double w = ct.valid ? half_weight(ct.kx, g.nx) : 0.0;
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        cpx<T> v[EPC];
+        col_load<T, EPC>(g, ct, H + c * NS, true, tw, v);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+            if (ct.valid && j < g.ny) {
+                const size_t idx = (size_t)ct.kx * g.ny + j;
+                if (bh) bh[c * NS + idx] = v[e];
+                if (rh) rh[c * NS + idx] = v[e];
+                acc[0] += w * ((double)v[e].re * (double)v[e].re + (double)v[e].im * (double)v[e].im);
+            }
+        }
+    }
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+    if (last_block_done(&sc->counter, gridDim.x)) {
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) s += partials[b];
+            sc->bb = s * sc->inv_n;
+            if (!(sc->bb == sc->bb) || sc->bb > 1.0e300) sc->status = -2;
+            sc->counter = 0;
+        }
+    }
+}
+
+// Forward y-FFT of D H fields into S fields (no reduction).
+template <typename T, int EPC, int D>
+__global__ void __launch_bounds__(1024) k_cols_to_S(ColGeom g, const cpx<T>* __restrict__ tw,
+                                                    const cpx<T>* __restrict__ H, size_t NS,
+                                                    cpx<T>* __restrict__ Sdst) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const ColThread<T> ct = col_thread<T>(g, lds);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        cpx<T> v[EPC];
+        col_load<T, EPC>(g, ct, H + c * NS, true, tw, v);
+        col_store<T, EPC>(g, ct, v, Sdst + c * NS, false, tw);
+    }
+}
+
+// Inverse y-FFT of D S fields (times scale) into H fields.
+template <typename T, int EPC, int D>
+__global__ void __launch_bounds__(1024) k_cols_from_S(ColGeom g, const cpx<T>* __restrict__ tw,
+                                                      const cpx<T>* __restrict__ Ssrc, size_t NS,
+                                                      cpx<T>* __restrict__ H, T scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const ColThread<T> ct = col_thread<T>(g, lds);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        cpx<T> v[EPC];
+        col_load<T, EPC>(g, ct, Ssrc + c * NS, false, tw, v);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) v[e] = scale * v[e];
+        col_store<T, EPC>(g, ct, v, H + c * NS, true, tw);
+    }
+}
+
+// Initialise the scalars of a solve on the device (no host round trip).  With
+// have_coeffs the preconditioner coefficients are given; otherwise they are
+// filled later by k_coeffs or copied from another solve.
+__global__ void k_init_scal(SolveScal* __restrict__ sc, double tol, int max_iter, double inv_n, int have_coeffs,
+                            double sig, double alp, double kap, int flat) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    sc->rho = sc->alpha = sc->beta = sc->bb = sc->rr = sc->pq = sc->relres = 0.0;
+    sc->tol2 = tol * tol;
+    sc->inv_n = inv_n;
+    sc->iter = 0;
+    sc->max_iter = max_iter;
+    sc->done = 0;
+    sc->converged = 0;
+    sc->status = 0;
+    sc->counter = 0u;
+    if (have_coeffs) {
+        sc->sig = sig;
+        sc->alp = alp;
+        sc->kap = kap;
+        sc->flat = flat;
+    }
+}
+
+// Inner solve of the refinement: coefficients from the outer solve.
+__global__ void k_copy_coeffs(const SolveScal* __restrict__ s, SolveScal* __restrict__ d) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        d->sig = s->sig;
+        d->alp = s->alp;
+        d->kap = s->kap;
+        d->flat = s->flat;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions over physical fields (FP64)
+// ---------------------------------------------------------------------------
+
+// Coefficients of section 4 (Eq:MaxMinWaveFields, Eq:FlatbathCoeff, Eq:Optcoeff,
+// Eq:Optcoeffb, Remark 4.2) from eta and grad h, written to sc->sig/alp/kap.
+template <int D>
+__global__ void __launch_bounds__(256) k_coeffs(size_t npts, const double* __restrict__ eta,
+                                                const double* __restrict__ gh, int flat, int kind,
+                                                SolveScal* __restrict__ sc, double* __restrict__ partials) {
+    __shared__ double red[5 * 16];
+    const double lp = (4.0 + sqrt(13.0)) / 6.0;
+    double mn = 1.0e308, mx = -1.0e308, smax = -1.0e308, g2max = 0.0, bad = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += stride) {
+        const double e = eta[i];
+        double g2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const double h = gh[c * npts + i];
+            g2 += h * h;
+        }
+        if (!isfinite(e) || !isfinite(g2)) bad = 1.0;
+        mn = fmin(mn, e);
+        mx = fmax(mx, e);
+        smax = fmax(smax, e + lp * e * g2);
+        g2max = fmax(g2max, g2);
+    }
+    // reduce min/max with shuffles (order independent)
+    double v[5] = {-mn, mx, smax, g2max, bad};
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[a] = fmax(v[a], __shfl_xor(v[a], off, 64));
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
+    if (lane == 0)
+        for (int a = 0; a < 5; ++a) red[a * 16 + wave] = v[a];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 5; ++a) {
+            double s = red[a * 16];
+            for (int w = 1; w < nw; ++w) s = fmax(s, red[a * 16 + w]);
+            partials[5 * blockIdx.x + a] = s;
+        }
+    }
+    if (last_block_done(&sc->counter, gridDim.x)) {
+        if (threadIdx.x == 0) {
+            double r[5];
+            for (int a = 0; a < 5; ++a) {
+                double s = partials[a];
+                for (unsigned b = 1; b < gridDim.x; ++b) s = fmax(s, partials[5 * b + a]);
+                r[a] = s;
+            }
+            const double emin = -r[0], emax = r[1], smx = r[2], g2m = r[3];
+            sc->red[0] = emin;
+            sc->red[1] = emax;
+            sc->red[2] = smx;
+            sc->red[3] = g2m;
+            if (r[4] != 0.0 || !(emin > 0.0)) {
+                sc->status = -2;
+            } else {
+                const double lm = (4.0 - sqrt(13.0)) / 6.0;
+                const double ratio3 = (emax / emin) * (emax / emin) * (emax / emin);
+                const int fl = flat < 0 ? (g2m == 0.0 ? 1 : 0) : (flat != 0 ? 1 : 0);
+                sc->flat = fl;
+                if (fl) {
+                    sc->sig = emax;
+                    sc->alp = emax * emax * emax / 3.0;
+                    sc->kap = ratio3;
+                } else if (kind == 0) {
+                    sc->sig = smx;
+                    sc->alp = lp * emax * emax * emax;
+                    sc->kap = fmax(smx / emin, (lp / lm) * ratio3);
+                } else {
+                    sc->sig = emax * (1.0 + lp * g2m);
+                    sc->alp = lp * emax * emax * emax;
+                    sc->kap = fmax((emax / emin) * (1.0 + lp * g2m), (lp / lm) * ratio3);
+                }
+                sc->status = 0;
+            }
+            sc->counter = 0;
+        }
+    }
+}
+
+// min and max of a physical field -> sc->red[0], sc->red[1] (for the flat test).
+__global__ void __launch_bounds__(256) k_minmax(size_t n, const double* __restrict__ f,
+                                                SolveScal* __restrict__ sc, double* __restrict__ partials) {
+    __shared__ double red[2 * 16];
+    double mn = 1.0e308, mx = -1.0e308;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        mn = fmin(mn, f[i]);
+        mx = fmax(mx, f[i]);
+    }
+    double v[2] = {-mn, mx};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[a] = fmax(v[a], __shfl_xor(v[a], off, 64));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+        red[wave] = v[0];
+        red[16 + wave] = v[1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = red[0], b = red[16];
+        for (int w = 1; w < nw; ++w) {
+            a = fmax(a, red[w]);
+            b = fmax(b, red[16 + w]);
+        }
+        partials[2 * blockIdx.x] = a;
+        partials[2 * blockIdx.x + 1] = b;
+    }
+    if (last_block_done(&sc->counter, gridDim.x)) {
+        if (threadIdx.x == 0) {
+            double a = partials[0], b = partials[1];
+            for (unsigned k = 1; k < gridDim.x; ++k) {
+                a = fmax(a, partials[2 * k]);
+                b = fmax(b, partials[2 * k + 1]);
+            }
+            sc->red[0] = -a;
+            sc->red[1] = b;
+            sc->counter = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small elementwise kernels
+// ---------------------------------------------------------------------------
+template <typename Td, typename Ts>
+__global__ void k_convert(size_t n, const Ts* __restrict__ s, Td* __restrict__ d) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = (Td)s[i];
+}
+
+// y = a*x + b*y  (b = 0 overwrites, x may be null for a pure scale)
+__global__ void k_axpby(size_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double xv = x ? x[i] : 0.0;
+        y[i] = (b == 0.0) ? a * xv : a * xv + b * y[i];
+    }
+}
+
+// out = base + dt * sum_k c_k f_k  (up to 4 terms, in the order given; base may be null)
+struct Lincomb4 {
+    const double* f[4];
+    double c[4];
+    int n;
+};
+__global__ void k_lincomb(size_t n, const double* __restrict__ base, double dt, Lincomb4 lc,
+                          double* __restrict__ out) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double s = 0.0;
+        for (int k = 0; k < lc.n; ++k) s += lc.c[k] * lc.f[k][i];
+        out[i] = (base ? base[i] : 0.0) + dt * s;
+    }
+}
+
+__global__ void k_zero_c(size_t n, void* __restrict__ p) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    double* d = reinterpret_cast<double*>(p);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = 0.0;
+}
+
+// Mixed precision glue in S: d32 = (float) s64 ; x64 += (double) x32
+__global__ void k_S_demote(size_t n, const cpx<double>* __restrict__ s, cpx<float>* __restrict__ d) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        d[i] = cpx<float>{(float)s[i].re, (float)s[i].im};
+}
+__global__ void k_S_accumulate(size_t n, const cpx<float>* __restrict__ s, cpx<double>* __restrict__ d) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        d[i] = cpx<double>{d[i].re + (double)s[i].re, d[i].im + (double)s[i].im};
+}
+
+}  // namespace sgn

@@ -1,0 +1,1572 @@
+// libsgn: C ABI entry points (include/sgn.h) and their host orchestration.
+#include "sgn.h"
+#include "sgn_kernels.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace sgn;
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct sgn_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    cpx<double>* tw64 = nullptr;
+    cpx<float>* tw32 = nullptr;
+    SolveScal* hscal = nullptr;   // pinned readback of solver scalars
+    int* hflag = nullptr;         // pinned readback of the done flag
+    std::string err;
+};
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+sgn_status fail(sgn_ctx* ctx, sgn_status s, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((ctx), SGN_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define CHECK_LAUNCH(ctx) HIPCHK(ctx, hipGetLastError())
+
+inline bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+inline int next_pow2(int n) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures, which is how sgn_workspace_bytes is computed.
+struct Carve {
+    char* base;
+    size_t off = 0;
+    explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+    template <class X>
+    X* take(size_t count) {
+        off = align_up(off, 256);
+        X* p = base ? reinterpret_cast<X*>(base + off) : nullptr;
+        off += count * sizeof(X);
+        return p;
+    }
+};
+
+struct Dims {
+    int D, nx, ny;
+    size_t N;   // physical points
+    size_t NS;  // spectral modes (nx/2+1) * ny
+    double tpx, tpy, inv_n;
+};
+
+sgn_status check_grid(sgn_ctx* ctx, const sgn_grid* g, Dims* d) {
+    if (!g) return fail(ctx, SGN_EINVAL, "grid is null");
+    if (g->dim != 1 && g->dim != 2) return fail(ctx, SGN_EINVAL, "grid dim must be 1 or 2");
+    const int ny = g->dim == 1 ? 1 : g->ny;
+    if (!is_pow2(g->nx) || g->nx < 2 || !is_pow2(ny))
+        return fail(ctx, SGN_EUNSUPPORTED, "grid sizes must be powers of two (nx >= 2)");
+    if (g->dim == 1 && g->nx > 16384) return fail(ctx, SGN_EUNSUPPORTED, "1D nx above 16384");
+    if (g->dim == 2 && (g->nx > 4096 || ny > 4096 || ny < 2))
+        return fail(ctx, SGN_EUNSUPPORTED, "2D sizes must be in [2, 4096]");
+    if (!(g->Lx > 0.0) || (g->dim == 2 && !(g->Ly > 0.0)))
+        return fail(ctx, SGN_EINVAL, "domain lengths must be positive");
+    d->D = g->dim;
+    d->nx = g->nx;
+    d->ny = ny;
+    d->N = (size_t)g->nx * ny;
+    d->NS = (size_t)(g->nx / 2 + 1) * ny;
+    d->tpx = kTwoPi / g->Lx;
+    d->tpy = g->dim == 2 ? kTwoPi / g->Ly : 0.0;
+    d->inv_n = 1.0 / (double)d->N;
+    return SGN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch geometry
+// ---------------------------------------------------------------------------
+struct RowLaunch {
+    RowGeom g;
+    int threads;
+    size_t lds;
+    int epc;
+};
+template <typename T>
+RowLaunch row_launch(int nx, int ny) {
+    RowLaunch L;
+    const int M = nx / 2;
+    L.epc = (M > 4096) ? 8 : 4;
+    RowGeom& g = L.g;
+    g.nx = nx;
+    g.ny = ny;
+    g.M = M;
+    g.TPR = M / L.epc > 0 ? M / L.epc : 1;
+    int R = 256 / g.TPR;
+    if (R < 1) R = 1;
+    const int np = next_pow2(ny);
+    if (R > np) R = np;
+    g.R = R;
+    g.nblocks = (ny + R - 1) / R;
+    L.threads = R * g.TPR;
+    L.lds = (size_t)R * (M + 1) * sizeof(cpx<T>);
+    return L;
+}
+
+struct ColLaunch {
+    ColGeom g;
+    int threads;
+    size_t lds;
+};
+template <typename T>
+ColLaunch col_launch(int nx, int ny) {
+    ColLaunch L;
+    ColGeom& g = L.g;
+    g.nx = nx;
+    g.ny = ny;
+    g.nxh = nx / 2 + 1;
+    g.TPC = ny / 4 > 0 ? ny / 4 : 1;
+    g.Cb = 256 / g.TPC > 0 ? 256 / g.TPC : 1;
+    g.nblocks = (g.nxh + g.Cb - 1) / g.Cb;
+    L.threads = g.Cb * g.TPC;
+    L.lds = (size_t)g.Cb * ny * sizeof(cpx<T>);
+    if (L.lds < 16) L.lds = 16;
+    return L;
+}
+
+inline int flat_blocks(size_t n, int per = 256, int cap = 1024) {
+    size_t b = (n + per - 1) / per;
+    if (b < 1) b = 1;
+    if (b > (size_t)cap) b = cap;
+    return (int)b;
+}
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename T> const cpx<T>* twiddles(sgn_ctx* ctx);
+template <> const cpx<double>* twiddles<double>(sgn_ctx* ctx) { return ctx->tw64; }
+template <> const cpx<float>* twiddles<float>(sgn_ctx* ctx) { return ctx->tw32; }
+
+// ---- generic passes --------------------------------------------------------
+
+template <typename T, typename Tin>
+sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, std::vector<cpx<T>*> dst,
+                    T scale = (T)1) {
+    RowLaunch L = row_launch<T>(d.nx, d.ny);
+    for (size_t f0 = 0; f0 < src.size(); f0 += MAXF) {
+        PtrList<const Tin, MAXF> s{};
+        PtrList<cpx<T>, MAXF> t{};
+        s.n = t.n = (int)std::min<size_t>(MAXF, src.size() - f0);
+        for (int i = 0; i < s.n; ++i) {
+            s.p[i] = src[f0 + i];
+            t.p[i] = dst[f0 + i];
+        }
+        if (L.epc == 4) {
+            auto k = k_rows_fwd<T, Tin, 4>;
+            HIPCHK(ctx, allow_lds(k, L.lds));
+            hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, s, t,
+                               twiddles<T>(ctx), scale);
+        } else {
+            auto k = k_rows_fwd<T, Tin, 8>;
+            HIPCHK(ctx, allow_lds(k, L.lds));
+            hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, s, t,
+                               twiddles<T>(ctx), scale);
+        }
+        CHECK_LAUNCH(ctx);
+    }
+    return SGN_OK;
+}
+
+template <typename T, typename Tout>
+sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src, std::vector<Tout*> dst,
+                    T scale = (T)1, T acc = (T)0) {
+    RowLaunch L = row_launch<T>(d.nx, d.ny);
+    for (size_t f0 = 0; f0 < src.size(); f0 += MAXF) {
+        PtrList<const cpx<T>, MAXF> s{};
+        PtrList<Tout, MAXF> t{};
+        s.n = t.n = (int)std::min<size_t>(MAXF, src.size() - f0);
+        for (int i = 0; i < s.n; ++i) {
+            s.p[i] = src[f0 + i];
+            t.p[i] = dst[f0 + i];
+        }
+        if (L.epc == 4) {
+            auto k = k_rows_inv<T, Tout, 4>;
+            HIPCHK(ctx, allow_lds(k, L.lds));
+            hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, s, t,
+                               twiddles<T>(ctx), scale, acc);
+        } else {
+            auto k = k_rows_inv<T, Tout, 8>;
+            HIPCHK(ctx, allow_lds(k, L.lds));
+            hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, s, t,
+                               twiddles<T>(ctx), scale, acc);
+        }
+        CHECK_LAUNCH(ctx);
+    }
+    return SGN_OK;
+}
+
+template <typename T, int NI>
+sgn_status cols_lin_n(sgn_ctx* ctx, const Dims& d, const std::vector<const cpx<T>*>& src,
+                      const std::vector<cpx<T>*>& dst, const LinCodes& lc, T scale) {
+    ColLaunch L = col_launch<T>(d.nx, d.ny);
+    PtrList<const cpx<T>, MAXF> s{};
+    PtrList<cpx<T>, MAXF> t{};
+    s.n = NI;
+    t.n = lc.no;
+    for (int i = 0; i < NI; ++i) s.p[i] = src[i];
+    for (int i = 0; i < lc.no; ++i) t.p[i] = dst[i];
+    auto k = k_cols_lin<T, 4, NI>;
+    HIPCHK(ctx, allow_lds(k, L.lds));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, s, t, lc,
+                       twiddles<T>(ctx), (T)d.tpx, (T)d.tpy, scale);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
+template <typename T>
+sgn_status cols_lin(sgn_ctx* ctx, const Dims& d, const std::vector<const cpx<T>*>& src,
+                    const std::vector<cpx<T>*>& dst, const std::vector<std::vector<int>>& codes, T scale) {
+    LinCodes lc{};
+    lc.no = (int)codes.size();
+    if (lc.no > LIN_MAXO || (int)dst.size() != lc.no) return fail(ctx, SGN_EINVAL, "cols_lin: bad outputs");
+    for (int o = 0; o < lc.no; ++o)
+        for (size_t i = 0; i < codes[o].size(); ++i) lc.code[o][i] = codes[o][i];
+    switch (src.size()) {
+        case 1: return cols_lin_n<T, 1>(ctx, d, src, dst, lc, scale);
+        case 2: return cols_lin_n<T, 2>(ctx, d, src, dst, lc, scale);
+        case 3: return cols_lin_n<T, 3>(ctx, d, src, dst, lc, scale);
+        case 4: return cols_lin_n<T, 4>(ctx, d, src, dst, lc, scale);
+        case 5: return cols_lin_n<T, 5>(ctx, d, src, dst, lc, scale);
+        default: return fail(ctx, SGN_EINVAL, "cols_lin: bad input count");
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coefficients (device) -> SolveScal
+// ---------------------------------------------------------------------------
+sgn_status launch_coeffs(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, int flat,
+                         int kind, SolveScal* sc, double* partials) {
+    const int nb = flat_blocks(d.N, 256, 1024);
+    if (d.D == 1)
+        hipLaunchKernelGGL(k_coeffs<1>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, flat, kind, sc, partials);
+    else
+        hipLaunchKernelGGL(k_coeffs<2>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, flat, kind, sc, partials);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layouts
+// ---------------------------------------------------------------------------
+struct Common {
+    SolveScal* sc;        // [4]: 0 = FP64 solve / misc, 1 = FP32 inner solve
+    double* partials;     // PARTIALS_MAX * 5
+};
+Common carve_common(Carve& cv) {
+    Common c;
+    c.sc = cv.take<SolveScal>(4);
+    c.partials = cv.take<double>((size_t)PARTIALS_MAX * 5);
+    return c;
+}
+
+template <typename T>
+struct PcgBufs {
+    cpx<T>*H, *xh, *rh, *ph, *qh, *bh;
+};
+template <typename T>
+PcgBufs<T> carve_pcg(Carve& cv, const Dims& d, bool keep_b) {
+    PcgBufs<T> b;
+    b.H = cv.take<cpx<T>>((size_t)(d.D + 1) * d.NS);
+    b.xh = cv.take<cpx<T>>((size_t)d.D * d.NS);
+    b.rh = cv.take<cpx<T>>((size_t)d.D * d.NS);
+    b.ph = cv.take<cpx<T>>((size_t)d.D * d.NS);
+    b.qh = cv.take<cpx<T>>((size_t)d.D * d.NS);
+    b.bh = keep_b ? cv.take<cpx<T>>((size_t)d.D * d.NS) : nullptr;
+    return b;
+}
+
+struct RhsBufs {
+    double* P;          // physical temporaries
+    cpx<double>* H;     // spectral temporaries
+    int nP, nH;
+};
+RhsBufs carve_rhs(Carve& cv, const Dims& d) {
+    RhsBufs b;
+    const int D = d.D;
+    const int nd2 = D == 2 ? 3 : 1;
+    b.nP = D + nd2 + 1 + (4 * D + 2) + 1;   // eta u, eta u u, beta, derivatives, S
+    b.nH = (2 * D + 1) + (nd2 + 1) + (2 * D + 2) + (2 * D);
+    b.P = cv.take<double>((size_t)b.nP * d.N);
+    b.H = cv.take<cpx<double>>((size_t)b.nH * d.NS);
+    return b;
+}
+
+size_t workspace_bytes(const Dims& d, int precision) {
+    size_t best = 0;
+    {   // FP64 PCG
+        Carve cv(nullptr);
+        carve_common(cv);
+        carve_pcg<double>(cv, d, true);
+        best = std::max(best, cv.off);
+    }
+    {   // mixed: FP64 outer + FP32 inner + FP32 copies of eta and grad h
+        Carve cv(nullptr);
+        carve_common(cv);
+        carve_pcg<double>(cv, d, true);
+        carve_pcg<float>(cv, d, false);
+        cv.take<float>((size_t)(1 + d.D) * d.N);
+        if (precision == SGN_MIXED) best = std::max(best, cv.off);
+    }
+    {   // right-hand side
+        Carve cv(nullptr);
+        carve_common(cv);
+        carve_rhs(cv, d);
+        best = std::max(best, cv.off);
+    }
+    return best + 256;
+}
+
+// ---------------------------------------------------------------------------
+// Krylov solve (PCG), templated on the working precision of the iteration.
+// The iteration runs on S-layout state; see sgn_kernels.h.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+struct PcgLaunch {
+    sgn_ctx* ctx;
+    Dims d;
+    RowLaunch rl;
+    ColLaunch cl;
+    PcgBufs<T> b;
+    SolveScal* sc;
+    double* partials;
+    const T* eta;
+    const T* gh;
+};
+
+template <typename T, int D>
+sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc) {
+    auto& L = P.cl;
+    if (mode == C1_COPY) {
+        auto k = k_pcg_c1<T, 4, D, C1_COPY>;
+        HIPCHK(P.ctx, allow_lds(k, L.lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
+                           P.sc, P.b.rh, P.b.ph, xsrc, P.b.H, P.d.NS, (T)P.d.tpx, (T)P.d.tpy);
+    } else {
+        auto k = k_pcg_c1<T, 4, D, C1_UPDATE>;
+        HIPCHK(P.ctx, allow_lds(k, L.lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
+                           P.sc, P.b.rh, P.b.ph, xsrc, P.b.H, P.d.NS, (T)P.d.tpx, (T)P.d.tpy);
+    }
+    CHECK_LAUNCH(P.ctx);
+    return SGN_OK;
+}
+
+template <typename T, int D>
+sgn_status pcg_r1(PcgLaunch<T, D>& P) {
+    auto& L = P.rl;
+    if (L.epc == 4) {
+        auto k = k_pcg_r1<T, 4, D>;
+        HIPCHK(P.ctx, allow_lds(k, L.lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
+                           P.sc, P.b.H, P.d.NS, P.eta, P.gh);
+    } else {
+        auto k = k_pcg_r1<T, 8, D>;
+        HIPCHK(P.ctx, allow_lds(k, L.lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
+                           P.sc, P.b.H, P.d.NS, P.eta, P.gh);
+    }
+    CHECK_LAUNCH(P.ctx);
+    return SGN_OK;
+}
+
+template <typename T, int D>
+sgn_status pcg_c2(PcgLaunch<T, D>& P, int mode, const cpx<T>* bh, cpx<T>* rh_out) {
+    auto& L = P.cl;
+    if (mode == C2_STORE) {
+        auto k = k_pcg_c2<T, 4, D, C2_STORE>;
+        HIPCHK(P.ctx, allow_lds(k, L.lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
+                           P.sc, P.b.H, P.d.NS, P.b.qh, P.b.ph, bh, rh_out, P.partials, (T)P.d.tpx, (T)P.d.tpy);
+    } else if (mode == C2_DOT) {
+        auto k = k_pcg_c2<T, 4, D, C2_DOT>;
+        HIPCHK(P.ctx, allow_lds(k, L.lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
+                           P.sc, P.b.H, P.d.NS, P.b.qh, P.b.ph, bh, rh_out, P.partials, (T)P.d.tpx, (T)P.d.tpy);
+    } else {
+        auto k = k_pcg_c2<T, 4, D, C2_RESID>;
+        HIPCHK(P.ctx, allow_lds(k, L.lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
+                           P.sc, P.b.H, P.d.NS, P.b.qh, P.b.ph, bh, rh_out, P.partials, (T)P.d.tpx, (T)P.d.tpy);
+    }
+    CHECK_LAUNCH(P.ctx);
+    return SGN_OK;
+}
+
+template <typename T, int D, bool INIT>
+sgn_status pcg_c3(PcgLaunch<T, D>& P, int init_bb = 0) {
+    const int nb = flat_blocks(P.d.NS, 256, 1024);
+    hipLaunchKernelGGL((k_pcg_c3<T, D, INIT>), dim3(nb), dim3(256), 0, P.ctx->stream, P.d.nx, P.d.ny, P.d.NS,
+                       P.sc, P.b.xh, P.b.rh, P.b.ph, P.b.qh, P.partials, (T)P.d.tpx, (T)P.d.tpy, init_bb);
+    CHECK_LAUNCH(P.ctx);
+    return SGN_OK;
+}
+
+// Read the solve's device scalars into ctx->hscal (synchronises the stream).
+sgn_status read_scal(sgn_ctx* ctx, const SolveScal* sc) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->hscal, sc, sizeof(SolveScal), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SGN_OK;
+}
+
+sgn_status read_done(sgn_ctx* ctx, const SolveScal* sc, int* done) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->hflag, &sc->done, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *done = *ctx->hflag;
+    return SGN_OK;
+}
+
+// Initialise a SolveScal on the device (stream-ordered, no host round trip).
+sgn_status init_scal(sgn_ctx* ctx, SolveScal* sc, double tol, int max_iter, double inv_n,
+                     const sgn_coeffs* co) {
+    hipLaunchKernelGGL(k_init_scal, dim3(1), dim3(64), 0, ctx->stream, sc, tol, max_iter, inv_n, co ? 1 : 0,
+                       co ? co->sigma : 0.0, co ? co->alpha : 0.0, co ? co->kappa_ub : 0.0, co ? co->flat : 0);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
+// Run PCG iterations until the device flag says done.  P.b holds x_hat, r_hat
+// (initialised), the scalars hold rho/bb (after the INIT C3).
+template <typename T, int D>
+sgn_status pcg_loop(PcgLaunch<T, D>& P, int max_iter, int check_every) {
+    if (check_every < 1) check_every = 1;
+    int it = 0;
+    while (it < max_iter) {
+        const int chunk = std::min(check_every, max_iter - it);
+        for (int c = 0; c < chunk; ++c) {
+            sgn_status s;
+            if ((s = pcg_c1<T, D>(P, C1_UPDATE, nullptr)) != SGN_OK) return s;
+            if ((s = pcg_r1<T, D>(P)) != SGN_OK) return s;
+            if ((s = pcg_c2<T, D>(P, C2_DOT, nullptr, nullptr)) != SGN_OK) return s;
+            if ((s = pcg_c3<T, D, false>(P)) != SGN_OK) return s;
+        }
+        it += chunk;
+        int done = 0;
+        sgn_status s = read_done(P.ctx, P.sc, &done);
+        if (s != SGN_OK) return s;
+        if (done) break;
+    }
+    return SGN_OK;
+}
+
+template <int D>
+sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* rhs,
+                      double* u, const sgn_coeffs* coeffs, int flat, const sgn_solve_opts& o,
+                      sgn_solve_info* info, void* ws) {
+    Carve cv(ws);
+    Common cm = carve_common(cv);
+    PcgLaunch<double, D> P;
+    P.ctx = ctx;
+    P.d = d;
+    P.rl = row_launch<double>(d.nx, d.ny);
+    P.cl = col_launch<double>(d.nx, d.ny);
+    P.b = carve_pcg<double>(cv, d, false);
+    P.sc = cm.sc;
+    P.partials = cm.partials;
+    P.eta = eta;
+    P.gh = gh;
+    sgn_status s;
+    if ((s = init_scal(ctx, P.sc, o.tol, o.max_iter, d.inv_n, coeffs)) != SGN_OK) return s;
+    if (!coeffs) {
+        if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials)) != SGN_OK) return s;
+    }
+    // b_hat -> r_hat, ||b||^2
+    std::vector<const double*> bsrc;
+    std::vector<cpx<double>*> hdst;
+    for (int c = 0; c < D; ++c) {
+        bsrc.push_back(rhs + c * d.N);
+        hdst.push_back(P.b.H + c * d.NS);
+    }
+    if ((s = rows_fwd<double, double>(ctx, d, bsrc, hdst)) != SGN_OK) return s;
+    {
+        auto k = k_setup_b<double, 4, D>;
+        HIPCHK(ctx, allow_lds(k, P.cl.lds));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g,
+                           ctx->tw64, P.sc, (const cpx<double>*)P.b.H, d.NS, (cpx<double>*)nullptr, P.b.rh,
+                           P.partials);
+        CHECK_LAUNCH(ctx);
+    }
+    if (o.x0_is_guess) {
+        // x_hat = FFT(u0); r_hat = b_hat - G x_hat
+        std::vector<const double*> usrc;
+        for (int c = 0; c < D; ++c) usrc.push_back(u + c * d.N);
+        if ((s = rows_fwd<double, double>(ctx, d, usrc, hdst)) != SGN_OK) return s;
+        auto k = k_cols_to_S<double, 4, D>;
+        HIPCHK(ctx, allow_lds(k, P.cl.lds));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g, ctx->tw64,
+                           (const cpx<double>*)P.b.H, d.NS, P.b.xh);
+        CHECK_LAUNCH(ctx);
+        if ((s = pcg_c1<double, D>(P, C1_COPY, P.b.xh)) != SGN_OK) return s;
+        if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
+        if ((s = pcg_c2<double, D>(P, C2_RESID, P.b.rh, P.b.rh)) != SGN_OK) return s;
+    } else {
+        hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks(d.D * d.NS * 2)), dim3(256), 0, ctx->stream,
+                           (size_t)d.D * d.NS * 2, (void*)P.b.xh);
+        CHECK_LAUNCH(ctx);
+    }
+    if ((s = pcg_c3<double, D, true>(P)) != SGN_OK) return s;
+    if ((s = pcg_loop<double, D>(P, o.max_iter, o.check_every)) != SGN_OK) return s;
+    // u = IFFT(x_hat)
+    {
+        auto k = k_cols_from_S<double, 4, D>;
+        HIPCHK(ctx, allow_lds(k, P.cl.lds));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g, ctx->tw64,
+                           (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
+        CHECK_LAUNCH(ctx);
+        std::vector<const cpx<double>*> hs;
+        std::vector<double*> ud;
+        for (int c = 0; c < D; ++c) {
+            hs.push_back(P.b.H + c * d.NS);
+            ud.push_back(u + c * d.N);
+        }
+        if ((s = rows_inv<double, double>(ctx, d, hs, ud)) != SGN_OK) return s;
+    }
+    if ((s = read_scal(ctx, P.sc)) != SGN_OK) return s;
+    const SolveScal& h = *ctx->hscal;
+    if (info) {
+        info->iters = h.iter;
+        info->outer_iters = 0;
+        info->converged = h.converged;
+        info->relres = h.relres;
+        info->coeffs.sigma = h.sig;
+        info->coeffs.alpha = h.alp;
+        info->coeffs.kappa_ub = h.kap;
+        info->coeffs.flat = coeffs ? coeffs->flat : flat;
+    }
+    if (h.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
+    if (!h.converged) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
+    return SGN_OK;
+}
+
+// Mixed precision: FP64 iterative refinement around FP32 PCG inner solves.  The
+// outer state (x_hat, r_hat = b_hat - G x_hat) and every dot product stay in
+// FP64; the inner operator, FFTs and preconditioner run in FP32.
+template <int D>
+sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* rhs,
+                       double* u, const sgn_coeffs* coeffs, int flat, const sgn_solve_opts& o,
+                       sgn_solve_info* info, void* ws) {
+    Carve cv(ws);
+    Common cm = carve_common(cv);
+    PcgLaunch<double, D> P;
+    P.ctx = ctx;
+    P.d = d;
+    P.rl = row_launch<double>(d.nx, d.ny);
+    P.cl = col_launch<double>(d.nx, d.ny);
+    P.b = carve_pcg<double>(cv, d, true);
+    P.sc = cm.sc;
+    P.partials = cm.partials;
+    P.eta = eta;
+    P.gh = gh;
+    PcgLaunch<float, D> Q;
+    Q.ctx = ctx;
+    Q.d = d;
+    Q.rl = row_launch<float>(d.nx, d.ny);
+    Q.cl = col_launch<float>(d.nx, d.ny);
+    Q.b = carve_pcg<float>(cv, d, false);
+    Q.sc = cm.sc + 1;
+    Q.partials = cm.partials;
+    float* eta32 = cv.take<float>((size_t)(1 + D) * d.N);
+    Q.eta = eta32;
+    Q.gh = eta32 + d.N;
+    sgn_status s;
+    if ((s = init_scal(ctx, P.sc, o.tol, 1 << 30, d.inv_n, coeffs)) != SGN_OK) return s;
+    if (!coeffs) {
+        if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials)) != SGN_OK) return s;
+    }
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(flat_blocks(d.N)), dim3(256), 0, ctx->stream, d.N, eta, eta32);
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(flat_blocks(d.D * d.N)), dim3(256), 0, ctx->stream,
+                       (size_t)D * d.N, gh, eta32 + d.N);
+    CHECK_LAUNCH(ctx);
+    // b_hat (kept) and r_hat = b_hat - G x_hat in FP64
+    std::vector<const double*> bsrc;
+    std::vector<cpx<double>*> hdst;
+    for (int c = 0; c < D; ++c) {
+        bsrc.push_back(rhs + c * d.N);
+        hdst.push_back(P.b.H + c * d.NS);
+    }
+    if ((s = rows_fwd<double, double>(ctx, d, bsrc, hdst)) != SGN_OK) return s;
+    {
+        auto k = k_setup_b<double, 4, D>;
+        HIPCHK(ctx, allow_lds(k, P.cl.lds));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g,
+                           ctx->tw64, P.sc, (const cpx<double>*)P.b.H, d.NS, P.b.bh, P.b.rh, P.partials);
+        CHECK_LAUNCH(ctx);
+    }
+    if (o.x0_is_guess) {
+        std::vector<const double*> usrc;
+        for (int c = 0; c < D; ++c) usrc.push_back(u + c * d.N);
+        if ((s = rows_fwd<double, double>(ctx, d, usrc, hdst)) != SGN_OK) return s;
+        auto k = k_cols_to_S<double, 4, D>;
+        HIPCHK(ctx, allow_lds(k, P.cl.lds));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g, ctx->tw64,
+                           (const cpx<double>*)P.b.H, d.NS, P.b.xh);
+        CHECK_LAUNCH(ctx);
+        if ((s = pcg_c1<double, D>(P, C1_COPY, P.b.xh)) != SGN_OK) return s;
+        if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
+        if ((s = pcg_c2<double, D>(P, C2_RESID, P.b.bh, P.b.rh)) != SGN_OK) return s;
+    } else {
+        hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks(d.D * d.NS * 2)), dim3(256), 0, ctx->stream,
+                           (size_t)d.D * d.NS * 2, (void*)P.b.xh);
+        CHECK_LAUNCH(ctx);
+    }
+    // FP64 residual norm and stop test (INIT C3 computes r.z and r.r)
+    if ((s = pcg_c3<double, D, true>(P)) != SGN_OK) return s;
+    int total_inner = 0, outer = 0;
+    const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
+    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    for (; outer < max_outer; ++outer) {
+        int done = 0;
+        if ((s = read_done(ctx, P.sc, &done)) != SGN_OK) return s;
+        if (done) break;
+        // inner FP32 solve of G dx = r from dx = 0
+        if ((s = init_scal(ctx, Q.sc, inner_tol, o.max_iter, d.inv_n, nullptr)) != SGN_OK) return s;
+        hipLaunchKernelGGL(k_copy_coeffs, dim3(1), dim3(64), 0, ctx->stream, P.sc, Q.sc);
+        hipLaunchKernelGGL(k_S_demote, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream, (size_t)D * d.NS,
+                           (const cpx<double>*)P.b.rh, Q.b.rh);
+        hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream, (size_t)D * d.NS,
+                           (void*)Q.b.xh);
+        CHECK_LAUNCH(ctx);
+        // the inner right-hand side norm is that of the demoted FP64 residual
+        if ((s = pcg_c3<float, D, true>(Q, 1)) != SGN_OK) return s;
+        if ((s = pcg_loop<float, D>(Q, o.max_iter, o.check_every)) != SGN_OK) return s;
+        if ((s = read_scal(ctx, Q.sc)) != SGN_OK) return s;
+        total_inner += ctx->hscal->iter;
+        // x_hat += dx_hat; r_hat = b_hat - G x_hat (FP64); stop test
+        hipLaunchKernelGGL(k_S_accumulate, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream,
+                           (size_t)D * d.NS, (const cpx<float>*)Q.b.xh, P.b.xh);
+        CHECK_LAUNCH(ctx);
+        if ((s = pcg_c1<double, D>(P, C1_COPY, P.b.xh)) != SGN_OK) return s;
+        if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
+        if ((s = pcg_c2<double, D>(P, C2_RESID, P.b.bh, P.b.rh)) != SGN_OK) return s;
+        if ((s = pcg_c3<double, D, true>(P)) != SGN_OK) return s;
+    }
+    {
+        auto k = k_cols_from_S<double, 4, D>;
+        HIPCHK(ctx, allow_lds(k, P.cl.lds));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g, ctx->tw64,
+                           (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
+        CHECK_LAUNCH(ctx);
+        std::vector<const cpx<double>*> hs;
+        std::vector<double*> ud;
+        for (int c = 0; c < D; ++c) {
+            hs.push_back(P.b.H + c * d.NS);
+            ud.push_back(u + c * d.N);
+        }
+        if ((s = rows_inv<double, double>(ctx, d, hs, ud)) != SGN_OK) return s;
+    }
+    if ((s = read_scal(ctx, P.sc)) != SGN_OK) return s;
+    const SolveScal& h = *ctx->hscal;
+    if (info) {
+        info->iters = total_inner;
+        info->outer_iters = outer;
+        info->converged = h.converged;
+        info->relres = h.relres;
+        info->coeffs.sigma = h.sig;
+        info->coeffs.alpha = h.alp;
+        info->coeffs.kappa_ub = h.kap;
+        info->coeffs.flat = coeffs ? coeffs->flat : flat;
+    }
+    if (h.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
+    if (!h.converged) return fail(ctx, SGN_ENOCONV, "refinement did not reach the tolerance");
+    return SGN_OK;
+}
+
+sgn_solve_opts default_opts() {
+    sgn_solve_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.method = SGN_PCG;
+    o.precision = SGN_FP64;
+    o.tol = 1e-12;
+    o.max_iter = 1000;
+    o.x0_is_guess = 0;
+    o.gmres_restart = 30;
+    o.inner_tol = 1e-5;
+    o.max_outer = 20;
+    o.check_every = 8;
+    o.coeff_kind = SGN_COEFF_OPTIMAL;
+    return o;
+}
+
+sgn_status solve_dispatch(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* rhs,
+                          double* u, const sgn_coeffs* coeffs, int flat, const sgn_solve_opts& o,
+                          sgn_solve_info* info, void* ws) {
+    if (o.method != SGN_PCG) return fail(ctx, SGN_EUNSUPPORTED, "only PCG is available");
+    if (!(o.tol > 0.0) || o.max_iter < 1) return fail(ctx, SGN_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (coeffs && !(coeffs->sigma > 0.0 && coeffs->alpha > 0.0))
+        return fail(ctx, SGN_EINVAL, "coefficients must be positive");
+    if (o.precision == SGN_FP64)
+        return d.D == 1 ? solve_fp64<1>(ctx, d, eta, gh, rhs, u, coeffs, flat, o, info, ws)
+                        : solve_fp64<2>(ctx, d, eta, gh, rhs, u, coeffs, flat, o, info, ws);
+    if (o.precision == SGN_MIXED)
+        return d.D == 1 ? solve_mixed<1>(ctx, d, eta, gh, rhs, u, coeffs, flat, o, info, ws)
+                        : solve_mixed<2>(ctx, d, eta, gh, rhs, u, coeffs, flat, o, info, ws);
+    return fail(ctx, SGN_EINVAL, "unknown precision");
+}
+
+// physical D-vector field -> S layout (FP64)
+template <int D>
+sgn_status to_S_d(sgn_ctx* ctx, const Dims& d, const double* f, cpx<double>* H, cpx<double>* Sd) {
+    std::vector<const double*> src;
+    std::vector<cpx<double>*> hd;
+    for (int c = 0; c < D; ++c) {
+        src.push_back(f + c * d.N);
+        hd.push_back(H + c * d.NS);
+    }
+    sgn_status s;
+    if ((s = rows_fwd<double, double>(ctx, d, src, hd)) != SGN_OK) return s;
+    ColLaunch L = col_launch<double>(d.nx, d.ny);
+    auto k = k_cols_to_S<double, 4, D>;
+    HIPCHK(ctx, allow_lds(k, L.lds));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, ctx->tw64,
+                       (const cpx<double>*)H, d.NS, Sd);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+// S layout -> physical D-vector field (FP64), with the 1/(nx ny) normalisation
+template <int D>
+sgn_status from_S_d(sgn_ctx* ctx, const Dims& d, const cpx<double>* Ssrc, cpx<double>* H, double* f) {
+    ColLaunch L = col_launch<double>(d.nx, d.ny);
+    auto k = k_cols_from_S<double, 4, D>;
+    HIPCHK(ctx, allow_lds(k, L.lds));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, ctx->tw64, Ssrc, d.NS, H,
+                       d.inv_n);
+    CHECK_LAUNCH(ctx);
+    std::vector<const cpx<double>*> hs;
+    std::vector<double*> od;
+    for (int c = 0; c < D; ++c) {
+        hs.push_back(H + c * d.NS);
+        od.push_back(f + c * d.N);
+    }
+    return rows_inv<double, double>(ctx, d, hs, od);
+}
+
+// ---------------------------------------------------------------------------
+// G apply (standalone): u -> S (p_hat), C1 copy, R1, C2 store q_hat, -> physical
+// ---------------------------------------------------------------------------
+template <int D>
+sgn_status apply_G(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* u,
+                   double* out, void* ws) {
+    Carve cv(ws);
+    Common cm = carve_common(cv);
+    PcgLaunch<double, D> P;
+    P.ctx = ctx;
+    P.d = d;
+    P.rl = row_launch<double>(d.nx, d.ny);
+    P.cl = col_launch<double>(d.nx, d.ny);
+    P.b = carve_pcg<double>(cv, d, false);
+    P.sc = cm.sc;
+    P.partials = cm.partials;
+    P.eta = eta;
+    P.gh = gh;
+    sgn_status s;
+    if ((s = init_scal(ctx, P.sc, 1.0, 1, d.inv_n, nullptr)) != SGN_OK) return s;
+    std::vector<const double*> usrc;
+    std::vector<cpx<double>*> hdst;
+    for (int c = 0; c < D; ++c) {
+        usrc.push_back(u + c * d.N);
+        hdst.push_back(P.b.H + c * d.NS);
+    }
+    if ((s = rows_fwd<double, double>(ctx, d, usrc, hdst)) != SGN_OK) return s;
+    {
+        auto k = k_cols_to_S<double, 4, D>;
+        HIPCHK(ctx, allow_lds(k, P.cl.lds));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g, ctx->tw64,
+                           (const cpx<double>*)P.b.H, d.NS, P.b.xh);
+        CHECK_LAUNCH(ctx);
+    }
+    if ((s = pcg_c1<double, D>(P, C1_COPY, P.b.xh)) != SGN_OK) return s;
+    if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
+    if ((s = pcg_c2<double, D>(P, C2_STORE, nullptr, nullptr)) != SGN_OK) return s;
+    return from_S_d<D>(ctx, d, P.b.qh, P.b.H, out);
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioner solve (standalone)
+// ---------------------------------------------------------------------------
+template <int D>
+sgn_status precond_apply(sgn_ctx* ctx, const Dims& d, double sig, double alp, const double* rhs, double* out,
+                         void* ws) {
+    Carve cv(ws);
+    carve_common(cv);
+    cpx<double>* H = cv.take<cpx<double>>((size_t)D * d.NS);
+    std::vector<const double*> src;
+    std::vector<cpx<double>*> hd;
+    std::vector<const cpx<double>*> hs;
+    std::vector<double*> od;
+    for (int c = 0; c < D; ++c) {
+        src.push_back(rhs + c * d.N);
+        hd.push_back(H + c * d.NS);
+        hs.push_back(H + c * d.NS);
+        od.push_back(out + c * d.N);
+    }
+    sgn_status s;
+    if ((s = rows_fwd<double, double>(ctx, d, src, hd)) != SGN_OK) return s;
+    ColLaunch L = col_launch<double>(d.nx, d.ny);
+    PtrList<const cpx<double>, MAXF> a{};
+    PtrList<cpx<double>, MAXF> b{};
+    a.n = b.n = D;
+    for (int c = 0; c < D; ++c) {
+        a.p[c] = H + c * d.NS;
+        b.p[c] = H + c * d.NS;
+    }
+    auto k = k_cols_precond<double, 4, D>;
+    HIPCHK(ctx, allow_lds(k, L.lds));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, a, b, ctx->tw64, d.tpx, d.tpy,
+                       sig, alp, d.inv_n);
+    CHECK_LAUNCH(ctx);
+    return rows_inv<double, double>(ctx, d, hs, od);
+}
+
+// ---------------------------------------------------------------------------
+// Right-hand side f(w, p)  (FP64)
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_rhs_pre(size_t n, const double* __restrict__ eta, const double* __restrict__ u,
+                          const double* __restrict__ gh, double* __restrict__ eu, double* __restrict__ euu,
+                          double* __restrict__ beta) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double e = eta[i];
+        const double u0 = u[i];
+        const double u1 = D == 2 ? u[n + i] : 0.0;
+        eu[i] = e * u0;
+        euu[i] = e * u0 * u0;
+        double b = gh[i] * u0;
+        if (D == 2) {
+            eu[n + i] = e * u1;
+            euu[n + i] = e * u0 * u1;
+            euu[2 * n + i] = e * u1 * u1;
+            b += gh[n + i] * u1;
+        }
+        beta[i] = b;
+    }
+}
+
+// Q layout (physical derivative fields): delta, d_c delta (D), m, d_c eta (D),
+// div_c (D), d_c beta (D).
+template <int D>
+__global__ void k_rhs_point(size_t n, const double* __restrict__ eta, const double* __restrict__ u,
+                            const double* __restrict__ gh, const double* __restrict__ Qf,
+                            double* __restrict__ eta_t, double* __restrict__ U_t, double* __restrict__ S) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double e = eta[i];
+        double uc[D], hc[D], dd[D], de[D], dv[D], db[D];
+        const double dl = Qf[i];
+        const double m = Qf[(1 + D) * n + i];
+        for (int c = 0; c < D; ++c) {
+            uc[c] = u[c * n + i];
+            hc[c] = gh[c * n + i];
+            dd[c] = Qf[(1 + c) * n + i];
+            de[c] = Qf[(2 + D + c) * n + i];
+            dv[c] = Qf[(2 + 2 * D + c) * n + i];
+            db[c] = Qf[(2 + 3 * D + c) * n + i];
+        }
+        double bt = 0.0, P = -dl * dl, Q = 0.0;
+        for (int c = 0; c < D; ++c) {
+            bt += hc[c] * uc[c];
+            P += uc[c] * dd[c];
+            Q += uc[c] * db[c];
+        }
+        const double e2 = e * e;
+        const double Sv = e2 * e / 3.0 * P + e2 * m * dl + e2 / 2.0 * Q + e * m * bt;
+        const double Tv = e2 / 2.0 * P + e * m * dl + e * Q + m * bt;
+        eta_t[i] = -m;
+        for (int c = 0; c < D; ++c) U_t[c * n + i] = -e * (de[c] - hc[c]) - dv[c] - hc[c] * Tv;
+        S[i] = Sv;
+    }
+}
+
+template <int D>
+sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* u,
+                    double* eta_t, double* U_t, void* ws) {
+    Carve cv(ws);
+    carve_common(cv);
+    RhsBufs b = carve_rhs(cv, d);
+    const size_t N = d.N, NS = d.NS;
+    const int nd2 = D == 2 ? 3 : 1;
+    double* eu = b.P;
+    double* euu = eu + D * N;
+    double* beta = euu + nd2 * N;
+    double* Qf = beta + N;                    // 4D + 2 fields
+    double* S = Qf + (4 * D + 2) * N;
+    cpx<double>* HA = b.H;                    // 2D + 1
+    cpx<double>* HB = HA + (2 * D + 1) * NS;  // nd2 + 1
+    cpx<double>* OA = HB + (nd2 + 1) * NS;    // 2D + 2
+    cpx<double>* OB = OA + (2 * D + 2) * NS;  // 2D
+    sgn_status s;
+    hipLaunchKernelGGL(k_rhs_pre<D>, dim3(flat_blocks(N)), dim3(256), 0, ctx->stream, N, eta, u, gh, eu, euu, beta);
+    CHECK_LAUNCH(ctx);
+    // forward transforms: group A = [u_c, eta u_c, eta], group B = [eta u_i u_j, beta]
+    std::vector<const double*> srcA, srcB;
+    std::vector<cpx<double>*> dA, dB;
+    for (int c = 0; c < D; ++c) srcA.push_back(u + c * N);
+    for (int c = 0; c < D; ++c) srcA.push_back(eu + c * N);
+    srcA.push_back(eta);
+    for (int c = 0; c < nd2; ++c) srcB.push_back(euu + c * N);
+    srcB.push_back(beta);
+    for (size_t i = 0; i < srcA.size(); ++i) dA.push_back(HA + i * NS);
+    for (size_t i = 0; i < srcB.size(); ++i) dB.push_back(HB + i * NS);
+    if ((s = rows_fwd<double, double>(ctx, d, srcA, dA)) != SGN_OK) return s;
+    if ((s = rows_fwd<double, double>(ctx, d, srcB, dB)) != SGN_OK) return s;
+    std::vector<const cpx<double>*> cA(dA.begin(), dA.end()), cB(dB.begin(), dB.end());
+    std::vector<cpx<double>*> oA, oB;
+    for (int i = 0; i < 2 * D + 2; ++i) oA.push_back(OA + i * NS);
+    for (int i = 0; i < 2 * D; ++i) oB.push_back(OB + i * NS);
+    // codes: 1 id, 2 ikx, 3 iky, 4 (ikx)^2, 5 (ikx)(iky), 6 (iky)^2
+    if (D == 2) {
+        // A inputs [u, v, eu, ev, eta] -> [delta, dx delta, dy delta, m, dx eta, dy eta]
+        if ((s = cols_lin<double>(ctx, d, cA, oA,
+                                  {{2, 3, 0, 0, 0}, {4, 5, 0, 0, 0}, {5, 6, 0, 0, 0},
+                                   {0, 0, 2, 3, 0}, {0, 0, 0, 0, 2}, {0, 0, 0, 0, 3}}, d.inv_n)) != SGN_OK)
+            return s;
+        // B inputs [euu, euv, evv, beta] -> [div_x, div_y, dx beta, dy beta]
+        if ((s = cols_lin<double>(ctx, d, cB, oB, {{2, 3, 0, 0}, {0, 2, 3, 0}, {0, 0, 0, 2}, {0, 0, 0, 3}},
+                                  d.inv_n)) != SGN_OK)
+            return s;
+    } else {
+        if ((s = cols_lin<double>(ctx, d, cA, oA, {{2, 0, 0}, {4, 0, 0}, {0, 2, 0}, {0, 0, 2}}, d.inv_n)) != SGN_OK)
+            return s;
+        if ((s = cols_lin<double>(ctx, d, cB, oB, {{2, 0}, {0, 2}}, d.inv_n)) != SGN_OK) return s;
+    }
+    // back to physical: Q = [delta, d delta (D), m, d eta (D), div (D), d beta (D)]
+    std::vector<const cpx<double>*> hs;
+    std::vector<double*> qd;
+    for (int i = 0; i < 2 * D + 2; ++i) hs.push_back(OA + i * NS);
+    for (int i = 0; i < 2 * D; ++i) hs.push_back(OB + i * NS);
+    for (int i = 0; i < 4 * D + 2; ++i) qd.push_back(Qf + i * N);
+    if ((s = rows_inv<double, double>(ctx, d, hs, qd)) != SGN_OK) return s;
+    hipLaunchKernelGGL(k_rhs_point<D>, dim3(flat_blocks(N)), dim3(256), 0, ctx->stream, N, eta, u, gh, Qf, eta_t, U_t, S);
+    CHECK_LAUNCH(ctx);
+    // U_t += grad S
+    if ((s = rows_fwd<double, double>(ctx, d, {S}, {HA})) != SGN_OK) return s;
+    std::vector<cpx<double>*> gS;
+    for (int c = 0; c < D; ++c) gS.push_back(HB + c * NS);
+    if (D == 2) {
+        if ((s = cols_lin<double>(ctx, d, {HA}, gS, {{2}, {3}}, d.inv_n)) != SGN_OK) return s;
+    } else {
+        if ((s = cols_lin<double>(ctx, d, {HA}, gS, {{2}}, d.inv_n)) != SGN_OK) return s;
+    }
+    std::vector<const cpx<double>*> gs2(gS.begin(), gS.end());
+    std::vector<double*> ud;
+    for (int c = 0; c < D; ++c) ud.push_back(U_t + c * N);
+    return rows_inv<double, double>(ctx, d, gs2, ud, 1.0, 1.0);
+}
+
+sgn_status rhs_dispatch(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* u,
+                        double* eta_t, double* U_t, void* ws) {
+    return d.D == 1 ? rhs_impl<1>(ctx, d, eta, gh, u, eta_t, U_t, ws) : rhs_impl<2>(ctx, d, eta, gh, u, eta_t, U_t, ws);
+}
+
+
+// ---------------------------------------------------------------------------
+// Time-stepping state (section 5)
+// ---------------------------------------------------------------------------
+struct StateBufs {
+    double* rk_fe[4];   // RK4 stage right-hand sides
+    double* rk_fU[4];
+    double* ab_fe[4];   // Adams-Bashforth history ring
+    double* ab_fU[4];
+    double *eta_s, *U_s, *u_s;              // RK4 stage values
+    double *eta_prev, *U_prev, *fe_prev, *fU_prev, *tmp_e, *tmp_U;  // SBDF2 history
+    cpx<double>*R_prev, *R_cur, *uh, *Uh, *Hs;                        // SBDF2 spectral
+};
+
+size_t carve_state(Carve& cv, const Dims& d, StateBufs* b) {
+    const size_t N = d.N, DN = (size_t)d.D * d.N, DS = (size_t)d.D * d.NS;
+    StateBufs t;
+    for (int k = 0; k < 4; ++k) {
+        t.rk_fe[k] = cv.take<double>(N);
+        t.rk_fU[k] = cv.take<double>(DN);
+        t.ab_fe[k] = cv.take<double>(N);
+        t.ab_fU[k] = cv.take<double>(DN);
+    }
+    t.eta_s = cv.take<double>(N);
+    t.U_s = cv.take<double>(DN);
+    t.u_s = cv.take<double>(DN);
+    t.eta_prev = cv.take<double>(N);
+    t.U_prev = cv.take<double>(DN);
+    t.fe_prev = cv.take<double>(N);
+    t.fU_prev = cv.take<double>(DN);
+    t.tmp_e = cv.take<double>(N);
+    t.tmp_U = cv.take<double>(DN);
+    t.R_prev = cv.take<cpx<double>>(DS);
+    t.R_cur = cv.take<cpx<double>>(DS);
+    t.uh = cv.take<cpx<double>>(DS);
+    t.Uh = cv.take<cpx<double>>(DS);
+    t.Hs = cv.take<cpx<double>>((size_t)(d.D + 1) * d.NS);
+    if (b) *b = t;
+    return cv.off;
+}
+
+}  // namespace
+
+struct sgn_state {
+    sgn_ctx* ctx;
+    sgn_grid grid;
+    Dims d;
+    const double* h;
+    const double* gh;
+    int flat;
+    double *eta, *U, *u;
+    void* ws;
+    StateBufs b;
+    double t;
+    int64_t steps;
+    int kind;       // history held: 0 none, 1 Adams-Bashforth, 2 SBDF2
+    int ab_order;
+    int ab_count;   // levels of f stored
+    int ab_head;    // next ring slot
+    double hist_dt;
+    double sb_sig, sb_alp;
+};
+
+namespace {
+
+sgn_status copy_d(sgn_ctx* ctx, double* dst, const double* src, size_t n) {
+    HIPCHK(ctx, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    return SGN_OK;
+}
+
+// out = base + dt * sum_k c_k f_k (base may be null)
+sgn_status lincomb(sgn_ctx* ctx, size_t n, const double* base, double dt, std::vector<const double*> f,
+                   std::vector<double> c, double* out) {
+    Lincomb4 lc{};
+    lc.n = (int)f.size();
+    for (int k = 0; k < lc.n; ++k) {
+        lc.f[k] = f[k];
+        lc.c[k] = c[k];
+    }
+    hipLaunchKernelGGL(k_lincomb, dim3(flat_blocks(n)), dim3(256), 0, ctx->stream, n, base, dt, lc, out);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
+void account(sgn_step_info* acc, const sgn_solve_info& si) {
+    acc->solves += 1;
+    acc->iters += si.iters;
+    if (si.iters > acc->max_iters) acc->max_iters = si.iters;
+    if (!si.converged) acc->converged = 0;
+}
+
+// G_{eta,h} u = U from the guess in u; A built from the current eta.
+sgn_status stage_solve(sgn_state* st, const double* eta, const double* U, double* u, const sgn_solve_opts& o,
+                       sgn_step_info* acc) {
+    sgn_solve_opts so = o;
+    so.x0_is_guess = 1;
+    sgn_solve_info si;
+    std::memset(&si, 0, sizeof(si));
+    sgn_status s = solve_dispatch(st->ctx, st->d, eta, st->gh, U, u, nullptr, st->flat, so, &si, st->ws);
+    account(acc, si);
+    return s;
+}
+
+// One RK4 step (Eq:ERK): stage i uses eta_n + dt a_i f^(i-1), U_n + dt a_i f^(i-1),
+// solves G u^(i) = U^(i) from u^(i-1); the final combination advances eta and U
+// and u_{n+1} is solved from u^(4).  have_f1: f at the current level is already
+// in rk_fe[0], rk_fU[0].
+sgn_status rk4_one(sgn_state* st, double dt, const sgn_solve_opts& o, sgn_step_info* acc, bool have_f1) {
+    sgn_ctx* ctx = st->ctx;
+    const Dims& d = st->d;
+    StateBufs& b = st->b;
+    const size_t N = d.N, DN = (size_t)d.D * d.N;
+    static const double a[3] = {0.5, 0.5, 1.0};
+    static const double w[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    sgn_status s;
+    if (!have_f1 && (s = rhs_dispatch(ctx, d, st->eta, st->gh, st->u, b.rk_fe[0], b.rk_fU[0], st->ws)) != SGN_OK)
+        return s;
+    if ((s = copy_d(ctx, b.u_s, st->u, DN)) != SGN_OK) return s;
+    for (int i = 1; i < 4; ++i) {
+        if ((s = lincomb(ctx, N, st->eta, dt, {b.rk_fe[i - 1]}, {a[i - 1]}, b.eta_s)) != SGN_OK) return s;
+        if ((s = lincomb(ctx, DN, st->U, dt, {b.rk_fU[i - 1]}, {a[i - 1]}, b.U_s)) != SGN_OK) return s;
+        if ((s = stage_solve(st, b.eta_s, b.U_s, b.u_s, o, acc)) != SGN_OK) return s;
+        if ((s = rhs_dispatch(ctx, d, b.eta_s, st->gh, b.u_s, b.rk_fe[i], b.rk_fU[i], st->ws)) != SGN_OK) return s;
+    }
+    if ((s = lincomb(ctx, N, st->eta, dt, {b.rk_fe[0], b.rk_fe[1], b.rk_fe[2], b.rk_fe[3]}, {w[0], w[1], w[2], w[3]},
+                     st->eta)) != SGN_OK)
+        return s;
+    if ((s = lincomb(ctx, DN, st->U, dt, {b.rk_fU[0], b.rk_fU[1], b.rk_fU[2], b.rk_fU[3]}, {w[0], w[1], w[2], w[3]},
+                     st->U)) != SGN_OK)
+        return s;
+    if ((s = copy_d(ctx, st->u, b.u_s, DN)) != SGN_OK) return s;
+    if ((s = stage_solve(st, st->eta, st->U, st->u, o, acc)) != SGN_OK) return s;
+    st->t += dt;
+    st->steps += 1;
+    return SGN_OK;
+}
+
+// R_hat = A u_hat - G_{eta,h} u_hat + U_hat at the state's level (u_hat in b.uh).
+template <int D>
+__global__ void k_sbdf2_R(int nx, int ny, size_t NS, double tpx, double tpy, double sig, double alp,
+                          const cpx<double>* __restrict__ uh, const cpx<double>* __restrict__ Guh,
+                          const cpx<double>* __restrict__ Uh, cpx<double>* __restrict__ R) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < NS; idx += stride) {
+        const int kxi = (int)(idx / ny), kyi = (int)(idx - (size_t)kxi * ny);
+        const double kx = wavenumber<double>(kxi, nx, tpx);
+        const double ky = D == 2 ? wavenumber<double>(kyi, ny, tpy) : 0.0;
+        cpx<double> uu[D];
+        for (int c = 0; c < D; ++c) uu[c] = uh[c * NS + idx];
+        cpx<double> ku = kx * uu[0];
+        if (D == 2) ku = ku + ky * uu[1 % D];
+        for (int c = 0; c < D; ++c) {
+            const double kc = c == 0 ? kx : ky;
+            const cpx<double> Au = sig * uu[c] + (alp * kc) * ku;   // (sig I + alp k k^T) u_hat
+            R[c * NS + idx] = (Au - Guh[c * NS + idx]) + Uh[c * NS + idx];
+        }
+    }
+}
+
+// u_hat = A^{-1}(b0 R_prev + b1 R_cur) (Eq:MM with c = (0, 0, 1)); then R_prev <- R_cur.
+template <int D>
+__global__ void k_sbdf2_solve(int nx, int ny, size_t NS, double tpx, double tpy, double sig, double alp, double b0,
+                              double b1, cpx<double>* __restrict__ Rprev, const cpx<double>* __restrict__ Rcur,
+                              cpx<double>* __restrict__ uh) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < NS; idx += stride) {
+        const int kxi = (int)(idx / ny), kyi = (int)(idx - (size_t)kxi * ny);
+        const double kx = wavenumber<double>(kxi, nx, tpx);
+        const double ky = D == 2 ? wavenumber<double>(kyi, ny, tpy) : 0.0;
+        cpx<double> r[D], z[D];
+        for (int c = 0; c < D; ++c) {
+            const cpx<double> rn = Rcur[c * NS + idx];
+            r[c] = b0 * Rprev[c * NS + idx] + b1 * rn;
+            Rprev[c * NS + idx] = rn;
+        }
+        precond_mode<double, D>(kx, ky, sig, alp, r, z);
+        for (int c = 0; c < D; ++c) uh[c * NS + idx] = z[c];
+    }
+}
+
+template <int D>
+sgn_status sbdf2_R(sgn_state* st, cpx<double>* Rout) {
+    sgn_ctx* ctx = st->ctx;
+    const Dims& d = st->d;
+    Carve cv(st->ws);
+    Common cm = carve_common(cv);
+    PcgLaunch<double, D> P;
+    P.ctx = ctx;
+    P.d = d;
+    P.rl = row_launch<double>(d.nx, d.ny);
+    P.cl = col_launch<double>(d.nx, d.ny);
+    P.b = carve_pcg<double>(cv, d, false);
+    P.sc = cm.sc;
+    P.partials = cm.partials;
+    P.eta = st->eta;
+    P.gh = st->gh;
+    sgn_status s;
+    if ((s = init_scal(ctx, P.sc, 1.0, 1, d.inv_n, nullptr)) != SGN_OK) return s;
+    if ((s = to_S_d<D>(ctx, d, st->U, st->b.Hs, st->b.Uh)) != SGN_OK) return s;
+    if ((s = pcg_c1<double, D>(P, C1_COPY, st->b.uh)) != SGN_OK) return s;
+    if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
+    if ((s = pcg_c2<double, D>(P, C2_STORE, nullptr, nullptr)) != SGN_OK) return s;
+    hipLaunchKernelGGL(k_sbdf2_R<D>, dim3(flat_blocks(d.NS)), dim3(256), 0, ctx->stream, d.nx, d.ny, d.NS, d.tpx,
+                       d.tpy, st->sb_sig, st->sb_alp, (const cpx<double>*)st->b.uh, (const cpx<double>*)P.b.qh,
+                       (const cpx<double>*)st->b.Uh, Rout);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
+template <int D>
+sgn_status sbdf2_steps(sgn_state* st, double dt, int nsteps, const sgn_coeffs* fixed, const sgn_solve_opts& o,
+                       sgn_step_info* acc) {
+    sgn_ctx* ctx = st->ctx;
+    const Dims& d = st->d;
+    StateBufs& b = st->b;
+    const size_t N = d.N, DN = (size_t)d.D * d.N;
+    const double a0 = 0.5, a1 = -2.0, a2 = 1.5, b0 = -1.0, b1 = 2.0;  // SBDF2 of Table LMMCoeffs
+    sgn_status s;
+    if (nsteps <= 0) return SGN_OK;
+    if (st->kind != 2 || st->hist_dt != dt) {
+        // new history: fixed coefficients, f_0, R_0, w_0, then one RK4 step
+        if (fixed) {
+            st->sb_sig = fixed->sigma;
+            st->sb_alp = fixed->alpha;
+        } else {
+            Carve cv(st->ws);
+            Common cm = carve_common(cv);
+            if ((s = init_scal(ctx, cm.sc, 1.0, 1, d.inv_n, nullptr)) != SGN_OK) return s;
+            if ((s = launch_coeffs(ctx, d, st->eta, st->gh, st->flat, o.coeff_kind, cm.sc, cm.partials)) != SGN_OK)
+                return s;
+            if ((s = read_scal(ctx, cm.sc)) != SGN_OK) return s;
+            if (ctx->hscal->status != 0) return fail(ctx, SGN_EDOMAIN, "total depth must be positive and finite");
+            st->sb_sig = ctx->hscal->sig;
+            st->sb_alp = ctx->hscal->alp;
+        }
+        st->kind = 2;
+        st->hist_dt = dt;
+        if ((s = rhs_dispatch(ctx, d, st->eta, st->gh, st->u, b.fe_prev, b.fU_prev, st->ws)) != SGN_OK) return s;
+        if ((s = to_S_d<D>(ctx, d, st->u, b.Hs, b.uh)) != SGN_OK) return s;
+        if ((s = sbdf2_R<D>(st, b.R_prev)) != SGN_OK) return s;
+        if ((s = copy_d(ctx, b.eta_prev, st->eta, N)) != SGN_OK) return s;
+        if ((s = copy_d(ctx, b.U_prev, st->U, DN)) != SGN_OK) return s;
+        if ((s = rk4_one(st, dt, o, acc, false)) != SGN_OK) return s;
+        if ((s = to_S_d<D>(ctx, d, st->u, b.Hs, b.uh)) != SGN_OK) return s;
+        nsteps -= 1;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+        // level n+1 is the state: f_{n+1}, R_{n+1}
+        if ((s = rhs_dispatch(ctx, d, st->eta, st->gh, st->u, b.rk_fe[0], b.rk_fU[0], st->ws)) != SGN_OK) return s;
+        if ((s = sbdf2_R<D>(st, b.R_cur)) != SGN_OK) return s;
+        // w_{n+2} = (-a0 w_n - a1 w_{n+1} + dt (b0 f_n + b1 f_{n+1})) / a2
+        if ((s = lincomb(ctx, N, nullptr, 1.0, {b.eta_prev, st->eta, b.fe_prev, b.rk_fe[0]},
+                         {-a0 / a2, -a1 / a2, dt * b0 / a2, dt * b1 / a2}, b.tmp_e)) != SGN_OK)
+            return s;
+        if ((s = lincomb(ctx, DN, nullptr, 1.0, {b.U_prev, st->U, b.fU_prev, b.rk_fU[0]},
+                         {-a0 / a2, -a1 / a2, dt * b0 / a2, dt * b1 / a2}, b.tmp_U)) != SGN_OK)
+            return s;
+        // history shift, then the new level
+        if ((s = copy_d(ctx, b.eta_prev, st->eta, N)) != SGN_OK) return s;
+        if ((s = copy_d(ctx, b.U_prev, st->U, DN)) != SGN_OK) return s;
+        if ((s = copy_d(ctx, b.fe_prev, b.rk_fe[0], N)) != SGN_OK) return s;
+        if ((s = copy_d(ctx, b.fU_prev, b.rk_fU[0], DN)) != SGN_OK) return s;
+        if ((s = copy_d(ctx, st->eta, b.tmp_e, N)) != SGN_OK) return s;
+        if ((s = copy_d(ctx, st->U, b.tmp_U, DN)) != SGN_OK) return s;
+        hipLaunchKernelGGL(k_sbdf2_solve<D>, dim3(flat_blocks(d.NS)), dim3(256), 0, ctx->stream, d.nx, d.ny, d.NS,
+                           d.tpx, d.tpy, st->sb_sig, st->sb_alp, b0, b1, b.R_prev, (const cpx<double>*)b.R_cur,
+                           b.uh);
+        CHECK_LAUNCH(ctx);
+        if ((s = from_S_d<D>(ctx, d, b.uh, b.Hs, st->u)) != SGN_OK) return s;
+        st->t += dt;
+        st->steps += 1;
+    }
+    return SGN_OK;
+}
+
+void info_init(sgn_step_info* acc) {
+    std::memset(acc, 0, sizeof(*acc));
+    acc->converged = 1;
+}
+void info_finish(sgn_state* st, sgn_step_info* acc, sgn_step_info* out) {
+    acc->t = st->t;
+    acc->steps_done = st->steps;
+    if (out) *out = *acc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* sgn_version(void) { return "sgn-mi355x 0.1 (gfx950)"; }
+
+sgn_status sgn_create(sgn_ctx** out, int device, void* hip_stream) {
+    if (!out) return SGN_EINVAL;
+    *out = nullptr;
+    sgn_ctx* ctx = new (std::nothrow) sgn_ctx();
+    if (!ctx) return SGN_ENOMEM;
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return SGN_EDEVICE;
+    }
+    // twiddle tables exp(-2 pi i k / TW), k < TW, from long double cos/sin
+    std::vector<cpx<double>> t64(TW_SIZE);
+    std::vector<cpx<float>> t32(TW_SIZE);
+    const long double pi2 = 6.283185307179586476925286766559005768L;
+    for (int k = 0; k < TW_SIZE; ++k) {
+        const long double a = pi2 * (long double)k / (long double)TW_SIZE;
+        const long double c = cosl(a), sn = -sinl(a);
+        t64[k] = cpx<double>{(double)c, (double)sn};
+        t32[k] = cpx<float>{(float)c, (float)sn};
+    }
+    bool ok = hipMalloc(&ctx->tw64, TW_SIZE * sizeof(cpx<double>)) == hipSuccess &&
+              hipMalloc(&ctx->tw32, TW_SIZE * sizeof(cpx<float>)) == hipSuccess &&
+              hipHostMalloc((void**)&ctx->hscal, sizeof(SolveScal), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&ctx->hflag, 64, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipMemcpy(ctx->tw64, t64.data(), TW_SIZE * sizeof(cpx<double>), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(ctx->tw32, t32.data(), TW_SIZE * sizeof(cpx<float>), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        sgn_destroy(ctx);
+        return SGN_ENOMEM;
+    }
+    *out = ctx;
+    return SGN_OK;
+}
+
+void sgn_destroy(sgn_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->tw64) (void)hipFree(ctx->tw64);
+    if (ctx->tw32) (void)hipFree(ctx->tw32);
+    if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+    if (ctx->hflag) (void)hipHostFree(ctx->hflag);
+    delete ctx;
+}
+
+sgn_status sgn_set_stream(sgn_ctx* ctx, void* hip_stream) {
+    if (!ctx) return SGN_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return SGN_OK;
+}
+
+const char* sgn_last_error(const sgn_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+size_t sgn_workspace_bytes(const sgn_grid* grid, int32_t precision) {
+    Dims d;
+    if (check_grid(nullptr, grid, &d) != SGN_OK) return 0;
+    return workspace_bytes(d, precision);
+}
+
+sgn_status sgn_bathy_prepare(sgn_ctx* ctx, const sgn_grid* grid, const double* h, double* grad_h, int32_t* flat,
+                             void* ws) {
+    if (!ctx) return SGN_EINVAL;
+    Dims d;
+    sgn_status s = check_grid(ctx, grid, &d);
+    if (s != SGN_OK) return s;
+    if (!h || !grad_h || !flat || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    Carve cv(ws);
+    Common cm = carve_common(cv);
+    cpx<double>* H = cv.take<cpx<double>>((size_t)(1 + d.D) * d.NS);
+    if ((s = init_scal(ctx, cm.sc, 1.0, 1, d.inv_n, nullptr)) != SGN_OK) return s;
+    hipLaunchKernelGGL(k_minmax, dim3(flat_blocks(d.N)), dim3(256), 0, ctx->stream, d.N, h, cm.sc, cm.partials);
+    CHECK_LAUNCH(ctx);
+    if ((s = read_scal(ctx, cm.sc)) != SGN_OK) return s;
+    const double hmin = ctx->hscal->red[0], hmax = ctx->hscal->red[1];
+    if (!std::isfinite(hmin) || !std::isfinite(hmax)) return fail(ctx, SGN_EDOMAIN, "non-finite bathymetry");
+    if (hmin == hmax) {
+        hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks((size_t)d.D * d.N)), dim3(256), 0, ctx->stream,
+                           (size_t)d.D * d.N, (void*)grad_h);
+        CHECK_LAUNCH(ctx);
+        *flat = 1;
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        return SGN_OK;
+    }
+    *flat = 0;
+    if ((s = rows_fwd<double, double>(ctx, d, {h}, {H})) != SGN_OK) return s;
+    std::vector<cpx<double>*> gd;
+    for (int c = 0; c < d.D; ++c) gd.push_back(H + (1 + c) * d.NS);
+    if (d.D == 2)
+        s = cols_lin<double>(ctx, d, {H}, gd, {{2}, {3}}, d.inv_n);
+    else
+        s = cols_lin<double>(ctx, d, {H}, gd, {{2}}, d.inv_n);
+    if (s != SGN_OK) return s;
+    std::vector<const cpx<double>*> gs(gd.begin(), gd.end());
+    std::vector<double*> od;
+    for (int c = 0; c < d.D; ++c) od.push_back(grad_h + c * d.N);
+    if ((s = rows_inv<double, double>(ctx, d, gs, od)) != SGN_OK) return s;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SGN_OK;
+}
+
+sgn_status sgn_precond_coeffs(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const double* grad_h,
+                              int32_t flat, int32_t kind, sgn_coeffs* out, void* ws) {
+    if (!ctx) return SGN_EINVAL;
+    Dims d;
+    sgn_status s = check_grid(ctx, grid, &d);
+    if (s != SGN_OK) return s;
+    if (!eta || !grad_h || !out || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    if (kind != SGN_COEFF_OPTIMAL && kind != SGN_COEFF_REPLACEMENT) return fail(ctx, SGN_EINVAL, "bad kind");
+    Carve cv(ws);
+    Common cm = carve_common(cv);
+    if ((s = init_scal(ctx, cm.sc, 1.0, 1, d.inv_n, nullptr)) != SGN_OK) return s;
+    if ((s = launch_coeffs(ctx, d, eta, grad_h, flat ? 1 : 0, kind, cm.sc, cm.partials)) != SGN_OK) return s;
+    if ((s = read_scal(ctx, cm.sc)) != SGN_OK) return s;
+    if (ctx->hscal->status != 0) return fail(ctx, SGN_EDOMAIN, "total depth must be positive and finite");
+    out->sigma = ctx->hscal->sig;
+    out->alpha = ctx->hscal->alp;
+    out->kappa_ub = ctx->hscal->kap;
+    out->flat = ctx->hscal->flat;
+    return SGN_OK;
+}
+
+sgn_status sgn_apply_constraint(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const double* grad_h,
+                                const double* u, double* out, void* ws) {
+    if (!ctx) return SGN_EINVAL;
+    Dims d;
+    sgn_status s = check_grid(ctx, grid, &d);
+    if (s != SGN_OK) return s;
+    if (!eta || !grad_h || !u || !out || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    if (out == u) return fail(ctx, SGN_EINVAL, "out may not alias u");
+    return d.D == 1 ? apply_G<1>(ctx, d, eta, grad_h, u, out, ws) : apply_G<2>(ctx, d, eta, grad_h, u, out, ws);
+}
+
+sgn_status sgn_precond_solve(sgn_ctx* ctx, const sgn_grid* grid, const sgn_coeffs* co, const double* rhs,
+                             double* out, void* ws) {
+    if (!ctx) return SGN_EINVAL;
+    Dims d;
+    sgn_status s = check_grid(ctx, grid, &d);
+    if (s != SGN_OK) return s;
+    if (!co || !rhs || !out || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    if (!(co->sigma > 0.0) || !(co->alpha > 0.0)) return fail(ctx, SGN_EINVAL, "sigma and alpha must be > 0");
+    return d.D == 1 ? precond_apply<1>(ctx, d, co->sigma, co->alpha, rhs, out, ws)
+                    : precond_apply<2>(ctx, d, co->sigma, co->alpha, rhs, out, ws);
+}
+
+sgn_status sgn_krylov_solve(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const double* grad_h,
+                            const double* rhs, double* u, const sgn_coeffs* coeffs, const sgn_solve_opts* opts,
+                            sgn_solve_info* info, void* ws) {
+    if (!ctx) return SGN_EINVAL;
+    Dims d;
+    sgn_status s = check_grid(ctx, grid, &d);
+    if (s != SGN_OK) return s;
+    if (!eta || !grad_h || !rhs || !u || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    const sgn_solve_opts o = opts ? *opts : default_opts();
+    if (o.coeff_kind != SGN_COEFF_OPTIMAL && o.coeff_kind != SGN_COEFF_REPLACEMENT)
+        return fail(ctx, SGN_EINVAL, "bad coeff_kind");
+    // without given coefficients the flat formulas apply iff |grad h|_max = 0
+    return solve_dispatch(ctx, d, eta, grad_h, rhs, u, coeffs, coeffs ? coeffs->flat : -1, o, info, ws);
+}
+
+sgn_status sgn_rhs(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const double* h, const double* grad_h,
+                   const double* u, double* eta_t, double* U_t, void* ws) {
+    if (!ctx) return SGN_EINVAL;
+    Dims d;
+    sgn_status s = check_grid(ctx, grid, &d);
+    if (s != SGN_OK) return s;
+    if (!eta || !h || !grad_h || !u || !eta_t || !U_t || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    return rhs_dispatch(ctx, d, eta, grad_h, u, eta_t, U_t, ws);
+}
+
+size_t sgn_state_workspace_bytes(const sgn_grid* grid, int32_t precision) {
+    (void)precision;
+    Dims d;
+    if (check_grid(nullptr, grid, &d) != SGN_OK) return 0;
+    Carve cv(nullptr);
+    return carve_state(cv, d, nullptr) + 256;
+}
+
+sgn_status sgn_state_create(sgn_ctx* ctx, const sgn_grid* grid, const double* h, const double* grad_h,
+                            int32_t flat, double* eta, double* U, double* u, void* state_ws, void* ws,
+                            sgn_state** out) {
+    if (!ctx || !out) return SGN_EINVAL;
+    *out = nullptr;
+    Dims d;
+    sgn_status s = check_grid(ctx, grid, &d);
+    if (s != SGN_OK) return s;
+    if (!h || !grad_h || !eta || !U || !u || !state_ws || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    sgn_state* st = new (std::nothrow) sgn_state();
+    if (!st) return fail(ctx, SGN_ENOMEM, "host allocation failed");
+    st->ctx = ctx;
+    st->grid = *grid;
+    st->d = d;
+    st->h = h;
+    st->gh = grad_h;
+    st->flat = flat ? 1 : 0;
+    st->eta = eta;
+    st->U = U;
+    st->u = u;
+    st->ws = ws;
+    Carve cv(state_ws);
+    carve_state(cv, d, &st->b);
+    st->t = 0.0;
+    st->steps = 0;
+    st->kind = 0;
+    *out = st;
+    return SGN_OK;
+}
+
+void sgn_state_destroy(sgn_state* st) { delete st; }
+
+sgn_status sgn_step_rk4(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nsteps, const sgn_solve_opts* opts,
+                        sgn_step_info* info) {
+    if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (nsteps < 0 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad step arguments");
+    const sgn_solve_opts o = opts ? *opts : default_opts();
+    sgn_step_info acc;
+    info_init(&acc);
+    st->kind = 0;  // a multistep history does not survive other steps
+    sgn_status s = SGN_OK;
+    for (int n = 0; n < nsteps && s == SGN_OK; ++n) s = rk4_one(st, dt, o, &acc, false);
+    info_finish(st, &acc, info);
+    return s;
+}
+
+sgn_status sgn_step_ab(sgn_ctx* ctx, sgn_state* st, int32_t order, double dt, int32_t nsteps,
+                       const sgn_solve_opts* opts, sgn_step_info* info) {
+    if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (nsteps < 0 || order < 2 || order > 4 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad AB arguments");
+    const sgn_solve_opts o = opts ? *opts : default_opts();
+    // b_j, j = 0 .. s-1 (Table LMMCoeffs)
+    static const double B[5][4] = {{0, 0, 0, 0},
+                                   {0, 0, 0, 0},
+                                   {-1.0 / 2.0, 3.0 / 2.0, 0, 0},
+                                   {5.0 / 12.0, -16.0 / 12.0, 23.0 / 12.0, 0},
+                                   {-9.0 / 24.0, 37.0 / 24.0, -59.0 / 24.0, 55.0 / 24.0}};
+    sgn_step_info acc;
+    info_init(&acc);
+    if (st->kind != 1 || st->ab_order != order || st->hist_dt != dt) {
+        st->kind = 1;
+        st->ab_order = order;
+        st->hist_dt = dt;
+        st->ab_count = 0;
+        st->ab_head = 0;
+    }
+    const Dims& d = st->d;
+    StateBufs& b = st->b;
+    const size_t N = d.N, DN = (size_t)d.D * d.N;
+    sgn_status s = SGN_OK;
+    for (int n = 0; n < nsteps; ++n) {
+        const int slot = st->ab_head & 3;
+        if ((s = rhs_dispatch(ctx, d, st->eta, st->gh, st->u, b.ab_fe[slot], b.ab_fU[slot], st->ws)) != SGN_OK) break;
+        st->ab_head += 1;
+        if (st->ab_count < order) st->ab_count += 1;
+        if (st->ab_count < order) {
+            // start-up: an RK4 step with the same dt; f at this level is its first stage
+            if ((s = copy_d(ctx, b.rk_fe[0], b.ab_fe[slot], N)) != SGN_OK) break;
+            if ((s = copy_d(ctx, b.rk_fU[0], b.ab_fU[slot], DN)) != SGN_OK) break;
+            if ((s = rk4_one(st, dt, o, &acc, true)) != SGN_OK) break;
+            continue;
+        }
+        std::vector<const double*> fe, fU;
+        std::vector<double> c;
+        for (int j = 0; j < order; ++j) {
+            const int sl = (st->ab_head - order + j) & 3;
+            fe.push_back(b.ab_fe[sl]);
+            fU.push_back(b.ab_fU[sl]);
+            c.push_back(B[order][j]);
+        }
+        if ((s = lincomb(ctx, N, st->eta, dt, fe, c, st->eta)) != SGN_OK) break;
+        if ((s = lincomb(ctx, DN, st->U, dt, fU, c, st->U)) != SGN_OK) break;
+        if ((s = stage_solve(st, st->eta, st->U, st->u, o, &acc)) != SGN_OK) break;
+        st->t += dt;
+        st->steps += 1;
+    }
+    info_finish(st, &acc, info);
+    return s;
+}
+
+sgn_status sgn_step_linimp(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nsteps, const sgn_coeffs* fixed,
+                           const sgn_solve_opts* opts, sgn_step_info* info) {
+    if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (nsteps < 0 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad step arguments");
+    if (fixed && !(fixed->sigma > 0.0 && fixed->alpha > 0.0)) return fail(ctx, SGN_EINVAL, "bad fixed coefficients");
+    const sgn_solve_opts o = opts ? *opts : default_opts();
+    sgn_step_info acc;
+    info_init(&acc);
+    sgn_status s = st->d.D == 1 ? sbdf2_steps<1>(st, dt, nsteps, fixed, o, &acc)
+                                : sbdf2_steps<2>(st, dt, nsteps, fixed, o, &acc);
+    if (s == SGN_OK) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    info_finish(st, &acc, info);
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,344 @@
+"""Thin Python binding of libsgn.so (include/sgn.h).
+
+Argument marshalling only: PyTorch tensors on the GPU are passed to the C ABI as
+device pointers, the current PyTorch HIP stream is passed as the library's
+stream, and workspaces are PyTorch allocations owned by a Context.  Every step
+of the computation runs in the library's HIP kernels; there is no CPU fallback.
+If libsgn.so is missing or cannot be loaded, importing this module raises.
+
+Field layout (as in the C header): scalar fields (nx,) in 1D and (ny, nx) in 2D,
+vector fields (d, nx) / (d, ny, nx), all float64 and contiguous.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import torch  # loaded first so libsgn.so binds to the same HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("SGN_LIB", os.path.join(_HERE, "libsgn.so"))
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sgn.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libsgn.so not found at {LIB_PATH}; build it with "
+                      "`python -m paper_2506_16045_amd.build` (no CPU fallback exists)")
+_lib = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
+
+# ---- status codes and enums -------------------------------------------------
+OK, EINVAL, EDOMAIN, ENOCONV, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "SGN_OK", -1: "SGN_EINVAL", -2: "SGN_EDOMAIN", -3: "SGN_ENOCONV",
+                -4: "SGN_ENOMEM", -5: "SGN_EDEVICE", -6: "SGN_EUNSUPPORTED"}
+PCG, GMRES = 0, 1
+FP64, MIXED = 0, 1
+COEFF_OPTIMAL, COEFF_REPLACEMENT = 0, 1
+
+
+class SgnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("Lx", ctypes.c_double), ("Ly", ctypes.c_double)]
+
+
+class Coeffs(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("kappa_ub", ctypes.c_double), ("flat", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("x0_is_guess", ctypes.c_int32),
+                ("gmres_restart", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("coeff_kind", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("relres", ctypes.c_double), ("coeffs", Coeffs)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("solves", ctypes.c_int64), ("iters", ctypes.c_int64), ("max_iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("t", ctypes.c_double), ("steps_done", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_D = ctypes.c_double
+_S = ctypes.c_int
+_SIGS = {
+    "sgn_create": (_S, [ctypes.POINTER(_P), ctypes.c_int, _P]),
+    "sgn_destroy": (None, [_P]),
+    "sgn_set_stream": (_S, [_P, _P]),
+    "sgn_last_error": (ctypes.c_char_p, [_P]),
+    "sgn_version": (ctypes.c_char_p, []),
+    "sgn_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
+    "sgn_bathy_prepare": (_S, [_P, ctypes.POINTER(Grid), _P, _P, ctypes.POINTER(_I), _P]),
+    "sgn_precond_coeffs": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _I, _I, ctypes.POINTER(Coeffs), _P]),
+    "sgn_apply_constraint": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P]),
+    "sgn_precond_solve": (_S, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Coeffs), _P, _P, _P]),
+    "sgn_krylov_solve": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, ctypes.POINTER(Coeffs),
+                              ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
+    "sgn_rhs": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P]),
+    "sgn_state_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
+    "sgn_state_create": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _I, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "sgn_state_destroy": (None, [_P]),
+    "sgn_step_rk4": (_S, [_P, _P, _D, _I, ctypes.POINTER(SolveOpts), ctypes.POINTER(StepInfo)]),
+    "sgn_step_ab": (_S, [_P, _P, _I, _D, _I, ctypes.POINTER(SolveOpts), ctypes.POINTER(StepInfo)]),
+    "sgn_step_linimp": (_S, [_P, _P, _D, _I, ctypes.POINTER(Coeffs), ctypes.POINTER(SolveOpts),
+                             ctypes.POINTER(StepInfo)]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def header_symbols(path: str = HEADER_PATH):
+    """Names of the functions declared in include/sgn.h."""
+    with open(path) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(sgn_[a-z0-9_]+)\s*\(", text)))
+
+
+def version() -> str:
+    return _lib.sgn_version().decode()
+
+
+def make_grid(g) -> Grid:
+    """Grid from an object with d, nx, ny, Lx, Ly (paper_2506_16045_amd.inputs.Grid)."""
+    return Grid(int(g.d), int(g.nx), int(g.ny if g.d == 2 else 1), float(g.Lx), float(g.Ly if g.d == 2 else 1.0))
+
+
+def workspace_bytes(g, precision: int = FP64) -> int:
+    return int(_lib.sgn_workspace_bytes(ctypes.byref(make_grid(g)), precision))
+
+
+def state_workspace_bytes(g, precision: int = FP64) -> int:
+    return int(_lib.sgn_state_workspace_bytes(ctypes.byref(make_grid(g)), precision))
+
+
+def solve_opts(tol=1e-12, max_iter=1000, precision=FP64, x0_is_guess=False, inner_tol=1e-5,
+               max_outer=20, check_every=8, coeff_kind=COEFF_OPTIMAL, method=PCG, gmres_restart=30):
+    return SolveOpts(method, precision, tol, max_iter, int(bool(x0_is_guess)), gmres_restart,
+                     inner_tol, max_outer, check_every, coeff_kind)
+
+
+def _ptr(t: torch.Tensor, shape, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device})")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64 (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _scalar_shape(g):
+    return (g.nx,) if g.d == 1 else (g.ny, g.nx)
+
+
+def _vector_shape(g):
+    return (g.d,) + _scalar_shape(g)
+
+
+@dataclass
+class SolveResult:
+    iters: int
+    outer_iters: int
+    converged: bool
+    relres: float
+    sigma: float
+    alpha: float
+    kappa_ub: float
+    flat: bool
+
+
+class Context:
+    """An sgn_ctx bound to a GPU and to the PyTorch stream current at each call."""
+
+    def __init__(self, device: int | torch.device | None = None):
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else
+                           (device.index if isinstance(device, torch.device) else int(device)))
+        self.device = dev
+        h = _P()
+        with torch.cuda.device(dev):
+            st = _lib.sgn_create(ctypes.byref(h), dev.index, _P(torch.cuda.current_stream(dev).cuda_stream))
+        if st != OK:
+            raise SgnError(st, "sgn_create failed")
+        self._h = h
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.sgn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------------
+    def _sync_stream(self):
+        _lib.sgn_set_stream(self._h, _P(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _check(self, st: int):
+        if st != OK:
+            raise SgnError(st, _lib.sgn_last_error(self._h).decode())
+
+    def workspace(self, g, precision=FP64) -> torch.Tensor:
+        key = (g.d, g.nx, g.ny if g.d == 2 else 1, max(precision, MIXED))
+        nb = workspace_bytes(g, MIXED)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nb:
+            ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    # -- entry points ----------------------------------------------------------
+    def bathy_prepare(self, g, h: torch.Tensor):
+        """grad h and the flat flag (sgn_bathy_prepare)."""
+        self._sync_stream()
+        grid = make_grid(g)
+        gh = torch.empty(_vector_shape(g), dtype=torch.float64, device=self.device)
+        flat = _I(0)
+        self._check(_lib.sgn_bathy_prepare(self._h, ctypes.byref(grid), _ptr(h, _scalar_shape(g), "h"),
+                                           _ptr(gh, _vector_shape(g), "grad_h"), ctypes.byref(flat),
+                                           _P(self.workspace(g).data_ptr())))
+        return gh, bool(flat.value)
+
+    def precond_coeffs(self, g, eta, grad_h, flat: bool, kind: int = COEFF_OPTIMAL) -> Coeffs:
+        self._sync_stream()
+        grid = make_grid(g)
+        c = Coeffs()
+        self._check(_lib.sgn_precond_coeffs(self._h, ctypes.byref(grid), _ptr(eta, _scalar_shape(g), "eta"),
+                                            _ptr(grad_h, _vector_shape(g), "grad_h"), int(bool(flat)), kind,
+                                            ctypes.byref(c), _P(self.workspace(g).data_ptr())))
+        return c
+
+    def apply_constraint(self, g, eta, grad_h, u, out=None):
+        """out = G_{eta,h} u (sgn_apply_constraint)."""
+        self._sync_stream()
+        grid = make_grid(g)
+        if out is None:
+            out = torch.empty(_vector_shape(g), dtype=torch.float64, device=self.device)
+        self._check(_lib.sgn_apply_constraint(self._h, ctypes.byref(grid), _ptr(eta, _scalar_shape(g), "eta"),
+                                              _ptr(grad_h, _vector_shape(g), "grad_h"),
+                                              _ptr(u, _vector_shape(g), "u"), _ptr(out, _vector_shape(g), "out"),
+                                              _P(self.workspace(g).data_ptr())))
+        return out
+
+    def precond_solve(self, g, sigma: float, alpha: float, rhs, out=None):
+        """out = A^{-1} rhs (sgn_precond_solve)."""
+        self._sync_stream()
+        grid = make_grid(g)
+        c = Coeffs(sigma, alpha, 0.0, 0)
+        if out is None:
+            out = torch.empty(_vector_shape(g), dtype=torch.float64, device=self.device)
+        self._check(_lib.sgn_precond_solve(self._h, ctypes.byref(grid), ctypes.byref(c),
+                                           _ptr(rhs, _vector_shape(g), "rhs"), _ptr(out, _vector_shape(g), "out"),
+                                           _P(self.workspace(g).data_ptr())))
+        return out
+
+    def krylov_solve(self, g, eta, grad_h, rhs, u=None, coeffs: Coeffs | None = None, opts: SolveOpts | None = None,
+                     raise_on_noconv: bool = True):
+        """Solve G u = rhs (sgn_krylov_solve).  Returns (u, SolveResult)."""
+        self._sync_stream()
+        grid = make_grid(g)
+        o = opts if opts is not None else solve_opts()
+        if u is None:
+            u = torch.zeros(_vector_shape(g), dtype=torch.float64, device=self.device)
+        info = SolveInfo()
+        st = _lib.sgn_krylov_solve(self._h, ctypes.byref(grid), _ptr(eta, _scalar_shape(g), "eta"),
+                                   _ptr(grad_h, _vector_shape(g), "grad_h"), _ptr(rhs, _vector_shape(g), "rhs"),
+                                   _ptr(u, _vector_shape(g), "u"), ctypes.byref(coeffs) if coeffs else None,
+                                   ctypes.byref(o), ctypes.byref(info), _P(self.workspace(g, o.precision).data_ptr()))
+        res = SolveResult(info.iters, info.outer_iters, bool(info.converged), info.relres, info.coeffs.sigma,
+                          info.coeffs.alpha, info.coeffs.kappa_ub, bool(info.coeffs.flat))
+        if st == ENOCONV and not raise_on_noconv:
+            return u, res
+        self._check(st)
+        return u, res
+
+    def rhs(self, g, eta, h, grad_h, u, eta_t=None, U_t=None):
+        """(eta_t, U_t) = f(w, p) (sgn_rhs)."""
+        self._sync_stream()
+        grid = make_grid(g)
+        if eta_t is None:
+            eta_t = torch.empty(_scalar_shape(g), dtype=torch.float64, device=self.device)
+        if U_t is None:
+            U_t = torch.empty(_vector_shape(g), dtype=torch.float64, device=self.device)
+        self._check(_lib.sgn_rhs(self._h, ctypes.byref(grid), _ptr(eta, _scalar_shape(g), "eta"),
+                                 _ptr(h, _scalar_shape(g), "h"), _ptr(grad_h, _vector_shape(g), "grad_h"),
+                                 _ptr(u, _vector_shape(g), "u"), _ptr(eta_t, _scalar_shape(g), "eta_t"),
+                                 _ptr(U_t, _vector_shape(g), "U_t"), _P(self.workspace(g).data_ptr())))
+        return eta_t, U_t
+
+
+class State:
+    """A time-stepping state (sgn_state) over caller-owned eta, U, u tensors."""
+
+    def __init__(self, ctx: Context, g, h, grad_h, flat: bool, eta, U, u):
+        self.ctx = ctx
+        self.g = g
+        self._keep = (h, grad_h, eta, U, u)
+        self.eta, self.U, self.u = eta, U, u
+        self._sws = torch.empty(state_workspace_bytes(g), dtype=torch.uint8, device=ctx.device)
+        self._ws = torch.empty(workspace_bytes(g, MIXED), dtype=torch.uint8, device=ctx.device)
+        grid = make_grid(g)
+        h_ = _P()
+        ctx._sync_stream()
+        ctx._check(_lib.sgn_state_create(ctx._h, ctypes.byref(grid), _ptr(h, _scalar_shape(g), "h"),
+                                         _ptr(grad_h, _vector_shape(g), "grad_h"), int(bool(flat)),
+                                         _ptr(eta, _scalar_shape(g), "eta"), _ptr(U, _vector_shape(g), "U"),
+                                         _ptr(u, _vector_shape(g), "u"), _P(self._sws.data_ptr()),
+                                         _P(self._ws.data_ptr()), ctypes.byref(h_)))
+        self._h = h_
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.sgn_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step_rk4(self, dt: float, nsteps: int, opts: SolveOpts | None = None) -> StepInfo:
+        self.ctx._sync_stream()
+        info = StepInfo()
+        self.ctx._check(_lib.sgn_step_rk4(self.ctx._h, self._h, dt, nsteps,
+                                          ctypes.byref(opts) if opts else None, ctypes.byref(info)))
+        return info
+
+    def step_ab(self, order: int, dt: float, nsteps: int, opts: SolveOpts | None = None) -> StepInfo:
+        self.ctx._sync_stream()
+        info = StepInfo()
+        self.ctx._check(_lib.sgn_step_ab(self.ctx._h, self._h, order, dt, nsteps,
+                                         ctypes.byref(opts) if opts else None, ctypes.byref(info)))
+        return info
+
+    def step_linimp(self, dt: float, nsteps: int, fixed: Coeffs | None = None,
+                    opts: SolveOpts | None = None) -> StepInfo:
+        self.ctx._sync_stream()
+        info = StepInfo()
+        self.ctx._check(_lib.sgn_step_linimp(self.ctx._h, self._h, dt, nsteps,
+                                             ctypes.byref(fixed) if fixed else None,
+                                             ctypes.byref(opts) if opts else None, ctypes.byref(info)))
+        return info
