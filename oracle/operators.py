@@ -97,13 +97,32 @@ def solve_A(sigma, alpha, r, g):
     """z = A^{-1} r, diagonal in Fourier space (section 6.1).
 
     1D: z_hat = r_hat / (sigma + alpha k^2).
-    2D: per mode solve (sigma I + alpha k k^T) z_hat = r_hat, k = (kx, ky)
-    with each Nyquist wavenumber set to zero.
+    2D: the symbol of A = sigma I - alpha grad(div) (Def:A) at wavevector k is
+    sigma I + alpha k k^T (each Nyquist wavenumber set to zero); k is its
+    eigenvector with eigenvalue sigma + alpha |k|^2 and the direction across k
+    has eigenvalue sigma, so with r_par = k (k . r_hat) / |k|^2
+        z_hat = (r_hat - r_par) / sigma + r_par / (sigma + alpha |k|^2).
+    (Solving the assembled 2x2 symbol instead loses the digits of sigma
+    whenever alpha |k|^2 >> sigma.)
     """
     if g.d == 1:
         k = sp.wavenumbers(g.nx, g.Lx)
         rh = np.fft.fft(r[0])
         return np.real(np.fft.ifft(rh / (sigma + alpha * k * k)))[None]
+    kx = np.broadcast_to(sp.wavenumbers(g.nx, g.Lx)[None, :], g.shape)
+    ky = np.broadcast_to(sp.wavenumbers(g.ny, g.Ly)[:, None], g.shape)
+    k2 = kx * kx + ky * ky
+    rx, ry = np.fft.fft2(r[0]), np.fft.fft2(r[1])
+    proj = np.where(k2 > 0, (kx * rx + ky * ry) / np.where(k2 > 0, k2, 1.0), 0.0)
+    px, py = kx * proj, ky * proj
+    zx = (rx - px) / sigma + px / (sigma + alpha * k2)
+    zy = (ry - py) / sigma + py / (sigma + alpha * k2)
+    return np.stack([np.real(np.fft.ifft2(zx)), np.real(np.fft.ifft2(zy))])
+
+
+def solve_A_assembled(sigma, alpha, r, g):
+    """A^{-1} r in 2D by solving the assembled 2x2 symbol at every mode (a plain
+    library solve); used only to pin solve_A on well-conditioned cases."""
     kx = sp.wavenumbers(g.nx, g.Lx)[None, :]
     ky = sp.wavenumbers(g.ny, g.Ly)[:, None]
     KX = np.broadcast_to(kx, g.shape)
@@ -113,7 +132,7 @@ def solve_A(sigma, alpha, r, g):
     M[..., 0, 1] = alpha * KX * KY
     M[..., 1, 0] = alpha * KX * KY
     M[..., 1, 1] = sigma + alpha * KY * KY
-    rh = np.stack([np.fft.fft2(r[0]), np.fft.fft2(r[1])], axis=-1)   # (ny, nx, 2)
+    rh = np.stack([np.fft.fft2(r[0]), np.fft.fft2(r[1])], axis=-1)
     zh = np.linalg.solve(M.astype(np.complex128), rh[..., None])[..., 0]
     return np.stack([np.real(np.fft.ifft2(zh[..., 0])), np.real(np.fft.ifft2(zh[..., 1]))])
 

@@ -136,6 +136,14 @@ def test_solve_A_inverts_dense_A(g, rng):
     assert np.allclose(op.apply_A(s, a, z, g).ravel(), r.ravel(), rtol=1e-11, atol=1e-11)
 
 
+def test_solve_A_split_form_matches_assembled_symbol_solve(rng):
+    g = I.grid2d(32, 64, 3.0, 5.0)
+    r = rng.normal(size=(2,) + g.shape)
+    z1 = op.solve_A(1.3, 0.02, r, g)
+    z2 = op.solve_A_assembled(1.3, 0.02, r, g)
+    assert np.max(np.abs(z1 - z2)) < 1e-13 * np.max(np.abs(z1)) * 50
+
+
 @pytest.mark.parametrize("g", [I.grid1d(32, 2.0), I.grid2d(8, 8, 1.0, 1.0)], ids=["1d", "2d"])
 @pytest.mark.parametrize("flat", [True, False])
 def test_theorem_4_1_eigenvalue_interval(g, flat, rng):
