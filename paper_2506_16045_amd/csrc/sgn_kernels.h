@@ -33,8 +33,13 @@ __device__ __forceinline__ double half_weight(int kx, int nx) {
     return (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
 }
 
-// z = A^{-1} r in Fourier space (Def:A, section 6.1):
-//   1D: r / (sig + alp k^2);  2D: (r - alp k (k.r) / (sig + alp |k|^2)) / sig.
+// z = A^{-1} r in Fourier space (Def:A, section 6.1): the symbol of A is
+//   1D: sig + alp k^2;   2D: sig I + alp k k^T.
+// In 2D the inverse splits r into its parts along k and across k,
+//   z = r_perp / sig + r_par / (sig + alp |k|^2),  r_par = k (k.r) / |k|^2,
+// which keeps full relative accuracy in both parts (the equivalent
+// Sherman-Morrison form r/sig - alp k (k.r)/(sig (sig + alp |k|^2)) cancels
+// digits along k when alp |k|^2 >> sig).
 template <typename T, int D>
 __device__ __forceinline__ void precond_mode(T kx, T ky, T sig, T alp, const cpx<T> (&r)[D],
                                              cpx<T> (&z)[D]) {
@@ -43,11 +48,17 @@ __device__ __forceinline__ void precond_mode(T kx, T ky, T sig, T alp, const cpx
         z[0] = s * r[0];
     } else {
         const T k2 = kx * kx + ky * ky;
-        const cpx<T> kr = kx * r[0] + ky * r[1 % D];
-        const T c = alp / (sig + alp * k2);
         const T is = (T)1 / sig;
-        z[0] = is * (r[0] - (c * kx) * kr);
-        z[1 % D] = is * (r[1 % D] - (c * ky) * kr);
+        if (k2 == (T)0) {
+            z[0] = is * r[0];
+            z[1 % D] = is * r[1 % D];
+        } else {
+            const cpx<T> kr = ((T)1 / k2) * (kx * r[0] + ky * r[1 % D]);   // (k.r) / |k|^2
+            const cpx<T> px = kx * kr, py = ky * kr;                       // r_par
+            const T ip = (T)1 / (sig + alp * k2);
+            z[0] = is * (r[0] - px) + ip * px;
+            z[1 % D] = is * (r[1 % D] - py) + ip * py;
+        }
     }
 }
 
@@ -233,7 +244,9 @@ __global__ void __launch_bounds__(1024) k_pcg_c1(ColGeom g, const cpx<T>* __rest
                 precond_mode<T, D>(kx, ky, sig, alp, r, z);
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
-                    p[c] = z[c] + beta * ph[c * NS + idx];
+                    // beta = 0 on the first iteration: p = z without reading the
+                    // previous (unset) direction
+                    p[c] = (beta != (T)0) ? z[c] + beta * ph[c * NS + idx] : z[c];
                     ph[c * NS + idx] = p[c];
                 }
             }
