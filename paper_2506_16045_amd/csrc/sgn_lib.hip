@@ -556,7 +556,7 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
         info->coeffs.sigma = h.sig;
         info->coeffs.alpha = h.alp;
         info->coeffs.kappa_ub = h.kap;
-        info->coeffs.flat = coeffs ? coeffs->flat : flat;
+        info->coeffs.flat = h.flat;
     }
     if (h.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
     if (!h.converged) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
@@ -689,7 +689,7 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
         info->coeffs.sigma = h.sig;
         info->coeffs.alpha = h.alp;
         info->coeffs.kappa_ub = h.kap;
-        info->coeffs.flat = coeffs ? coeffs->flat : flat;
+        info->coeffs.flat = h.flat;
     }
     if (h.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
     if (!h.converged) return fail(ctx, SGN_ENOCONV, "refinement did not reach the tolerance");
