@@ -1,0 +1,208 @@
+#!/usr/bin/env python
+"""Benchmark of the SGN hot path on one MI355X.
+
+Workload (the 2D configuration the grid-point-steps metric is quoted on):
+2D doubly periodic SGN over a Gaussian bump, 1024 x 1024 grid on 200 x 200,
+still-water depth 1, bump height 0.5 and radius 10 at the centre, line
+solitary wave a = 0.2 travelling in x (crest at x = 50), classical RK4 with
+dt = 0.02, preconditioned Krylov (PCG with the constant-coefficient operator
+A) to a relative residual of 1e-10 at every stage.  Default precision: FP32
+operator/FFT/preconditioner inside FP64 iterative refinement (FP64 residual,
+dot products, right-hand side and state); --precision fp64 runs everything in
+FP64.
+
+One step = one RK4 step of the whole hot path (4 right-hand sides, 4 Krylov
+solves, the stage combinations).  `value` = grid points x timed steps / wall
+seconds, with every field already resident in HBM.  The line also carries
+the roofline of the dominant kernel (HIP events around each of its launches
+over the timed region) and the CPU oracle timed on the host on one RK4 step of
+the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--precision mixed|fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0    # MI355X HBM3E, 8 TB/s
+
+
+def kernel_bytes(kind: str, d: int, nx: int, ny: int, word: int) -> float:
+    """Algorithmic HBM bytes of one launch of a PCG kernel family: every field
+    the kernel must read once plus every field it must write once.
+    NS = (nx/2+1) ny complex modes per spectral field (2 words), N = nx ny points."""
+    ns = (nx // 2 + 1) * ny
+    n = nx * ny
+    cw = 2 * word
+    if kind == "pcg_c1":      # read r_hat, p_hat (2d fields); write p_hat (d) and d+1 transformed fields
+        return (2 * d + d + (d + 1)) * ns * cw
+    if kind == "pcg_r1":      # read/write d+1 half-spectral fields; read eta and grad h (1 + d reals)
+        return 2 * (d + 1) * ns * cw + (1 + d) * n * word
+    if kind == "pcg_c2":      # read d+1 half-spectral fields and p_hat (d); write q_hat (d)
+        return ((d + 1) + d + d) * ns * cw
+    if kind == "pcg_c3":      # read x, r, p, q hats (4d); write x, r hats (2d)
+        return (4 * d + 2 * d) * ns * cw
+    raise ValueError(kind)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(cfg, steps: int = 1):
+    """The oracle, as it stands, on `steps` RK4 steps of the same workload."""
+    import numpy as np
+    from oracle import stepping as ost
+    pb = ost.Problem.from_h(cfg["grid"], cfg["h"], tol=cfg["tol"])
+    U0 = pb.G(cfg["eta"], cfg["u"])
+    t0 = time.perf_counter()
+    ost.run_rk4(pb, cfg["eta"], U0, cfg["u"], cfg["dt"], steps)
+    dt = time.perf_counter() - t0
+    g = cfg["grid"]
+    return {"value": g.npts * steps / dt, "unit": "grid-pt-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} RK4 step(s) of the {g.nx}x{g.ny} workload from its initial data "
+                      f"({dt:.1f} s, FP64 NumPy, single thread; iterations/solve "
+                      f"{np.mean(pb.iters):.1f})"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--n", type=int, default=1024, help="grid points per side (default 1024)")
+    ap.add_argument("--check-every", type=int, default=8)
+    ap.add_argument("--inner-tol", type=float, default=1e-5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
+              "(multi-GPU sharding is described in the design notes, not run)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2506_16045_amd import inputs as I
+    from paper_2506_16045_amd import sgn
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    cfg = I.config_c3(args.n)
+    g = cfg["grid"]
+    prec = sgn.MIXED if args.precision == "mixed" else sgn.FP64
+    opts = sgn.solve_opts(tol=cfg["tol"], precision=prec, check_every=args.check_every, inner_tol=args.inner_tol)
+
+    ctx = sgn.Context(0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    h = to(cfg["h"])
+    gh, flat = ctx.bathy_prepare(g, h)
+    eta = to(cfg["eta"])
+    u = to(cfg["u"])
+    U = ctx.apply_constraint(g, eta, gh, u)
+    state = sgn.State(ctx, g, h, gh, flat, eta, U, u)
+    mass0 = float(torch.sum(eta - h).item())
+
+    if args.warmup > 0:
+        state.step_rk4(cfg["dt"], args.warmup, opts)
+    torch.cuda.synchronize()
+
+    lat = []
+    solves = iters = 0
+    max_iters = 0
+    ctx.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        info = state.step_rk4(cfg["dt"], 1, opts)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - s0) * 1e3)
+        solves += info.solves
+        iters += info.iters
+        max_iters = max(max_iters, info.max_iters)
+        if not info.converged:
+            raise RuntimeError("a Krylov solve did not converge")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_end()
+    elapsed = t1 - t0
+
+    # device-side property checks of the final state (not part of the timed region)
+    Gu = ctx.apply_constraint(g, state.eta, gh, state.u)
+    constraint_relres = float((torch.linalg.vector_norm(Gu - state.U) / torch.linalg.vector_norm(state.U)).item())
+    mass_drift = abs(float(torch.sum(state.eta - h).item()) - mass0) / max(abs(mass0), 1e-300)
+
+    word = 4 if prec == sgn.MIXED else 8
+    kstats = {}
+    for kind in ("pcg_c1", "pcg_r1", "pcg_c2", "pcg_c3"):
+        n_launch, ms = prof[kind]
+        if n_launch:
+            kstats[kind] = {"launches": n_launch, "avg_us": 1e3 * ms / n_launch, "total_ms": ms}
+    # in mixed mode some launches of each family are the FP64 residual passes;
+    # the roofline is quoted for the dominant family with the inner (FP32) word size
+    dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
+    nbytes = kernel_bytes(dom, g.d, g.nx, g.ny, word)
+    achieved = nbytes / (kstats[dom]["avg_us"] * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": nbytes, "avg_launch_us": round(kstats[dom]["avg_us"], 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, 1)
+
+    out = {
+        "metric": "2D SGN grid-pt-steps/s at 1e-9 rel err; Krylov iters/solve; p50/p99 latency",
+        "value": g.npts * args.steps / elapsed,
+        "unit": "grid-pt-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == sgn.MIXED else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"2D SGN over a Gaussian bump, RK4: {g.nx}x{g.ny} grid on {g.Lx:g}x{g.Ly:g}, "
+                         "h0=1, bump height 0.5 radius 10 at the centre, line solitary wave a=0.2 at x=50, "
+                         f"dt={cfg['dt']}, Krylov tol {cfg['tol']:g}"),
+            "scheme": "rk4", "precision": args.precision, "grid": [g.nx, g.ny], "dt": cfg["dt"],
+            "tol": cfg["tol"], "parallelism": "single GPU",
+        },
+        "krylov_iters_per_solve": iters / max(solves, 1),
+        "krylov_max_iters": max_iters,
+        "solves": solves,
+        "step_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)},
+        "checks": {"constraint_relres": constraint_relres, "mass_rel_drift": mass_drift},
+        "kernels": kstats,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out), flush=True)
+    state.close()
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -14,7 +14,8 @@
  *    1D scalar fields [nx], 2D scalar fields [ny][nx] with x the fast index,
  *    x_i = i Lx / nx, y_j = j Ly / ny (doubly periodic).  Vector fields
  *    (velocity u, U = G u, grad h) are component-major: [d][ny][nx].
- *  - Grid sizes must be powers of two: 2 <= nx <= 16384; in 2D 2 <= ny <= 4096.
+ *  - Grid sizes must be powers of two: 1D 2 <= nx <= 16384; 2D 2 <= nx <= 4096
+ *    and 2 <= ny <= 1024.
  *  - Every call enqueues its device work on the context's HIP stream.  Calls
  *    that return scalars to the host (coefficients, solve and step info)
  *    synchronise that stream before returning.
@@ -120,6 +121,24 @@ sgn_status sgn_set_stream(sgn_ctx *ctx, void *hip_stream);
 const char *sgn_last_error(const sgn_ctx *ctx);
 /* Library version string. */
 const char *sgn_version(void);
+
+/* Kernel timing for measurement (off by default).  Between sgn_profile_begin
+ * and sgn_profile_end every launch of the kernel families below is bracketed
+ * by HIP events on the context's stream; sgn_profile_end synchronises the
+ * stream and returns, per family index k < nkinds, the launch count and the
+ * summed event time in milliseconds (host arrays of nkinds entries).
+ * The events may add a few microseconds per launch. */
+typedef enum sgn_kernel_kind {
+    SGN_KERNEL_PCG_C1 = 0,   /* A^{-1}, search direction, y-IFFT (column pass) */
+    SGN_KERNEL_PCG_R1 = 1,   /* x-IFFT, pointwise operator, x-FFT (row pass)   */
+    SGN_KERNEL_PCG_C2 = 2,   /* y-FFT, q = G p, p.q (column pass)              */
+    SGN_KERNEL_PCG_C3 = 3,   /* x, r update, A^{-1} r, r.z and r.r             */
+    SGN_KERNEL_ROWS = 4,     /* generic row transforms (right-hand side etc.)  */
+    SGN_KERNEL_COLS = 5,     /* generic column operators                       */
+    SGN_KERNEL_KINDS = 6
+} sgn_kernel_kind;
+sgn_status sgn_profile_begin(sgn_ctx *ctx);
+sgn_status sgn_profile_end(sgn_ctx *ctx, int64_t *launches, double *total_ms, int32_t nkinds);
 
 /* Bytes of workspace any single call below needs for this grid and precision. */
 size_t sgn_workspace_bytes(const sgn_grid *grid, int32_t precision);

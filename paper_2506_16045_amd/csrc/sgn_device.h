@@ -387,19 +387,52 @@ __device__ __forceinline__ void block_sum(double (&v)[NACC], double* red /*LDS, 
     __syncthreads();
 }
 
-// Returns true in every thread of the block that finished last.  Call after the
-// block's thread 0 wrote its partials.
-__device__ __forceinline__ bool last_block_done(unsigned* counter, unsigned nblocks) {
-    __shared__ int am_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(counter, 1u);
-        am_last = (prev == nblocks - 1) ? 1 : 0;
+// Sum of the per-block partials (layout partials[NACC*b + a]) by the whole
+// last block: thread t adds blocks t, t+blockDim, ... in order, then the fixed
+// block tree; the result is in thread 0.  Every thread of the block must call it.
+template <int NACC>
+__device__ __forceinline__ void final_sum(const double* __restrict__ partials, unsigned nblocks,
+                                          double (&v)[NACC], double* red) {
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) v[a] = 0.0;
+    for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) v[a] += partials[(size_t)NACC * b + a];
+    }
+    block_sum<NACC>(v, red);
+}
+
+// Maximum of the per-block partials by the whole last block (order independent);
+// the result is in thread 0.
+template <int NACC>
+__device__ __forceinline__ void final_max(const double* __restrict__ partials, unsigned nblocks,
+                                          double (&v)[NACC], double* red) {
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) v[a] = -1.0e308;
+    for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) v[a] = fmax(v[a], partials[(size_t)NACC * b + a]);
+    }
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[a] = fmax(v[a], __shfl_xor(v[a], off, 64));
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) red[a * 16 + wave] = v[a];
     }
     __syncthreads();
-    if (am_last) __threadfence();
-    return am_last != 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+            double m = red[a * 16];
+            for (int w = 1; w < nw; ++w) m = fmax(m, red[a * 16 + w]);
+            v[a] = m;
+        }
+    }
+    __syncthreads();
 }
 
 }  // namespace sgn

@@ -8,17 +8,27 @@
 namespace sgn {
 
 // Device-side scalars of one Krylov solve (one instance per solve in flight).
+// Protocol (no device-scope fences or atomics): a reducing kernel writes one
+// partial sum per block; the next kernel in the stream reduces those partials
+// in every block, in a fixed order, and block 0 publishes the scalars.
 struct SolveScal {
-    double rho, alpha, beta, bb, rr, pq, tol2, relres;
+    double rho;        // r.z of the current search direction
+    double rho_prev;   // r.z used by the last x, r update
+    double alpha, beta, bb, rr, pq, tol2, relres;
     double sig, alp, kap;     // preconditioner A = sig I - alp grad div, bound kappa_ub
     double inv_n;             // 1 / (nx ny)
     double red[8];            // results of the last generic reduction
     int iter, max_iter, done, converged, flat, status;
-    unsigned counter;         // last-block-done counter
-    int pad;
+    int first;                // 1 until the first update (beta = 0)
+    int init_bb;              // 1: ||b|| is the norm of the initial residual
 };
 
-constexpr int PARTIALS_MAX = 4096;  // blocks of a reducing launch (x NACC doubles)
+constexpr int PARTIALS_MAX = 4096;  // blocks of a reducing launch
+// regions of the partials buffer (doubles)
+constexpr int PART_C2 = 0;                       // p.Gp of the row pass (one per row block)
+constexpr int PART_C3 = 4096;                    // (r.z, r.r) of the update pass (two per column block)
+constexpr int PART_GEN = 4096 + 2 * 4096;        // one-off reductions (up to 5 per block)
+constexpr int PART_TOTAL = PART_GEN + 5 * PARTIALS_MAX;
 
 template <typename T, int N>
 struct PtrList {
@@ -144,7 +154,7 @@ __device__ __forceinline__ cpx<T> lin_coef(int code, T kx, T ky) {
 }
 
 template <typename T, int EPC, int NI>
-__global__ void __launch_bounds__(1024) k_cols_lin(ColGeom g, PtrList<const cpx<T>, MAXF> src,
+__global__ void __launch_bounds__(256) k_cols_lin(ColGeom g, PtrList<const cpx<T>, MAXF> src,
                                                    PtrList<cpx<T>, MAXF> dst, LinCodes lc,
                                                    const cpx<T>* __restrict__ tw, T tpx, T tpy,
                                                    T scale) {
@@ -172,7 +182,7 @@ __global__ void __launch_bounds__(1024) k_cols_lin(ColGeom g, PtrList<const cpx<
 
 // A^{-1} on D spectral columns: y-FFT, per-mode A^{-1} (times scale), y-IFFT.
 template <typename T, int EPC, int D>
-__global__ void __launch_bounds__(1024) k_cols_precond(ColGeom g, PtrList<const cpx<T>, MAXF> src,
+__global__ void __launch_bounds__(256) k_cols_precond(ColGeom g, PtrList<const cpx<T>, MAXF> src,
                                                        PtrList<cpx<T>, MAXF> dst,
                                                        const cpx<T>* __restrict__ tw, T tpx, T tpy,
                                                        T sig, T alp, T scale) {
@@ -201,28 +211,77 @@ __global__ void __launch_bounds__(1024) k_cols_precond(ColGeom g, PtrList<const 
 
 // ---------------------------------------------------------------------------
 // Krylov solve kernels (PCG of section 3.2 with the state x, r, p, q kept in
-// the S layout; dot products by Parseval over the half spectrum, FP64).
-// One iteration is C1 -> R1 -> C2 -> C3:
-//   C1: z = A^{-1} r, p = z + beta p; emits (p, div p) / (nx ny) and the y-IFFT
+// the S layout; dot products by Parseval over the half spectrum, in FP64).
+// One iteration is C1 -> R1 -> C2:
+//   C1: reduce the previous update's (r.z, r.r) -> stop test, beta;
+//       z = A^{-1} r, p = z + beta p; emits (p, div p) / (nx ny) and the y-IFFT
 //   R1: x-IFFT -> pointwise  a = eta p + grad h (eta^2/2 div p + eta grad h.p),
-//                            w = eta^3/3 div p + eta^2/2 grad h.p  -> x-FFT
-//   C2: y-FFT; q = a - i k w  (= G p, Def:G), p.q -> alpha
-//   C3: x += alpha p, r -= alpha q, z = A^{-1} r, r.z and r.r -> beta, stop test
+//                            w = eta^3/3 div p + eta^2/2 grad h.p  -> x-FFT;
+//       partial p.Gp as the grid sum of the weak form B[p, p] (section 3.1),
+//       sum_x (p, div p)^T M(x) (p, div p) with M of Appendix A
+//   C2: reduce p.Gp -> alpha; y-FFT; q = a - i k w (= G p, Def:G);
+//       x += alpha p, r -= alpha q, z = A^{-1} r; partial r.z, r.r
+// p.Gp equals B[p, p] exactly for the spectral D (real antisymmetric), so the
+// curvature is known before q is formed and the update needs no extra pass.
 // Every kernel returns at once when the solve is done.
 // ---------------------------------------------------------------------------
+
+// Broadcast thread 0's value to the block.
+__device__ __forceinline__ double bcast(double v, double* slot) {
+    if (threadIdx.x == 0) *slot = v;
+    __syncthreads();
+    const double r = *slot;
+    __syncthreads();
+    return r;
+}
+
+// Stop test and beta from the partials of the last update pass (or of the
+// initial residual).  Identical in every block; block 0 publishes.  Returns done.
+__device__ __forceinline__ bool pcg_iterate_state(SolveScal* __restrict__ sc, const double* __restrict__ part,
+                                                  int nb3, double* red, double* slot, double& beta_out) {
+    double tot[2];
+    final_sum<2>(part + PART_C3, nb3, tot, red);
+    const double rz = bcast(tot[0], slot) * sc->inv_n;
+    const double rr = bcast(tot[1], slot + 1) * sc->inv_n;
+    const int first = sc->first;
+    const double bb = (sc->init_bb && first && sc->iter == 0) ? rr : sc->bb;
+    const bool bad = !(rr == rr) || !(rz == rz);
+    const bool conv = !bad && (bb == 0.0 || rr <= sc->tol2 * bb);
+    const bool done = bad || conv || sc->iter >= sc->max_iter;
+    const double beta = first ? 0.0 : rz / sc->rho_prev;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rr = rr;
+        sc->bb = bb;
+        sc->relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+        sc->rho = rz;
+        sc->beta = beta;
+        sc->converged = conv ? 1 : 0;
+        if (bad) sc->status = -2;
+        sc->done = done ? 1 : 0;
+    }
+    beta_out = beta;
+    return done;
+}
+
 enum { C1_UPDATE = 0, C1_COPY = 1 };
 
 template <typename T, int EPC, int D, int MODE>
-__global__ void __launch_bounds__(1024) k_pcg_c1(ColGeom g, const cpx<T>* __restrict__ tw,
-                                                 SolveScal* __restrict__ sc,
-                                                 const cpx<T>* __restrict__ rh, cpx<T>* __restrict__ ph,
+__global__ void __launch_bounds__(256) k_pcg_c1(ColGeom g, const cpx<T>* __restrict__ tw,
+                                                 SolveScal* __restrict__ sc, const double* __restrict__ part,
+                                                 int nb3, const cpx<T>* __restrict__ rh, cpx<T>* __restrict__ ph,
                                                  const cpx<T>* __restrict__ xsrc, cpx<T>* __restrict__ H,
                                                  size_t NS, T tpx, T tpy) {
     if (sc->done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[32];
+    __shared__ double slot[2];
+    double beta_d = 0.0;
+    if (MODE == C1_UPDATE) {
+        if (pcg_iterate_state(sc, part, nb3, red, slot, beta_d)) return;
+    }
     const ColThread<T> ct = col_thread<T>(g, lds);
-    const T beta = (T)sc->beta, sig = (T)sc->sig, alp = (T)sc->alp, inv_n = (T)sc->inv_n;
+    const T beta = (T)beta_d, sig = (T)sc->sig, alp = (T)sc->alp, inv_n = (T)sc->inv_n;
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
     cpx<T> o[D + 1][EPC];
 #pragma unroll
@@ -261,14 +320,28 @@ __global__ void __launch_bounds__(1024) k_pcg_c1(ColGeom g, const cpx<T>* __rest
     for (int c = 0; c <= D; ++c) col_store<T, EPC>(g, ct, o[c], H + c * NS, true, tw);
 }
 
+// Stop test only (one block): closes a chunk of iterations so the host can
+// read the done flag.  Idempotent with the C1 that follows.
+__global__ void __launch_bounds__(256) k_pcg_check(SolveScal* __restrict__ sc, const double* __restrict__ part,
+                                                   int nb3) {
+    if (sc->done) return;
+    __shared__ double red[32];
+    __shared__ double slot[2];
+    double beta;
+    pcg_iterate_state(sc, part, nb3, red, slot, beta);
+}
+
 template <typename T, int EPC, int D>
 __global__ void __launch_bounds__(1024) k_pcg_r1(RowGeom g, const cpx<T>* __restrict__ tw,
                                                  SolveScal* __restrict__ sc, cpx<T>* H, size_t NS,
-                                                 const T* __restrict__ eta, const T* __restrict__ gh) {
+                                                 const T* __restrict__ eta, const T* __restrict__ gh,
+                                                 double* __restrict__ part) {
     if (sc->done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[16];
     const RowThread<T> rt = row_thread<T>(g, lds);
+    double acc[1] = {0.0};
     cpx<T> v[D + 1][EPC];
 #pragma unroll
     for (int c = 0; c <= D; ++c) row_inverse<T, EPC>(g, rt, H + c * NS, tw, v[c]);
@@ -294,6 +367,11 @@ __global__ void __launch_bounds__(1024) k_pcg_r1(RowGeom g, const cpx<T>* __rest
                 const T e2 = et * et;
                 const T w1 = third * e2 * et * dl + half * e2 * bt;
                 const T w2 = half * e2 * dl + et * bt;
+                // B-density: eta |p|^2 + eta^3/3 dl^2 + eta^2 dl bt + eta bt^2 = p.a + dl w1
+                double pp = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) pp += (double)pc[c] * (double)pc[c];
+                acc[0] += (double)et * pp + (double)dl * (double)w1 + (double)bt * (double)w2;
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
                     const T a = et * pc[c] + hc[c] * w2;
@@ -305,31 +383,53 @@ __global__ void __launch_bounds__(1024) k_pcg_r1(RowGeom g, const cpx<T>* __rest
     }
 #pragma unroll
     for (int c = 0; c <= D; ++c) row_forward<T, EPC>(g, rt, v[c], H + c * NS, tw, (T)1);
+    if (part) {
+        block_sum<1>(acc, red);
+        if (threadIdx.x == 0) part[PART_C2 + blockIdx.x] = acc[0];
+    }
 }
 
-enum { C2_DOT = 0, C2_RESID = 1, C2_STORE = 2 };
+enum { C2_RESID = 1, C2_STORE = 2, C2_UPDATE = 3 };
 
-// MODE C2_DOT: q = G p -> qh, partial p.q (alpha = rho / p.q in the last block).
-// MODE C2_RESID: r = b - G x -> rh (no reduction).
-// MODE C2_STORE: q = G p -> qh (no reduction).
+// MODE C2_UPDATE: reduce p.Gp (row-pass partials, nb_r1 blocks) -> alpha;
+//   q = G p; x += alpha p; r -= alpha q; z = A^{-1} r; partial r.z, r.r.
+// MODE C2_RESID: r = b - G x -> rh.
+// MODE C2_STORE: q = G p -> qh.
 template <typename T, int EPC, int D, int MODE>
-__global__ void __launch_bounds__(1024) k_pcg_c2(ColGeom g, const cpx<T>* __restrict__ tw,
+__global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restrict__ tw,
                                                  SolveScal* __restrict__ sc, const cpx<T>* __restrict__ H,
-                                                 size_t NS, cpx<T>* __restrict__ qh,
-                                                 const cpx<T>* __restrict__ ph,
-                                                 const cpx<T>* __restrict__ bh, cpx<T>* __restrict__ rh,
-                                                 double* __restrict__ partials, T tpx, T tpy) {
+                                                 size_t NS, cpx<T>* __restrict__ qh, const cpx<T>* __restrict__ ph,
+                                                 cpx<T>* __restrict__ xh, const cpx<T>* __restrict__ bh,
+                                                 cpx<T>* __restrict__ rh, double* __restrict__ part, int nb_r1,
+                                                 T tpx, T tpy) {
     if (sc->done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[16];
+    __shared__ double red[32];
+    __shared__ double slot[1];
+    T alpha = (T)0;
+    if (MODE == C2_UPDATE) {
+        double tot[1];
+        final_sum<1>(part + PART_C2, nb_r1, tot, red);
+        const double pq = bcast(tot[0], slot);
+        const double a = sc->rho / pq;
+        alpha = (T)a;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->pq = pq;
+            sc->alpha = a;
+            sc->rho_prev = sc->rho;
+            sc->iter = sc->iter + 1;
+            sc->first = 0;
+        }
+    }
     const ColThread<T> ct = col_thread<T>(g, lds);
     cpx<T> in[D + 1][EPC];
 #pragma unroll
     for (int c = 0; c <= D; ++c) col_load<T, EPC>(g, ct, H + c * NS, true, tw, in[c]);
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
+    const T sig = (T)sc->sig, alp = (T)sc->alp;
     const double w = ct.valid ? half_weight(ct.kx, g.nx) : 0.0;
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < EPC; ++e) {
         const int j = ct.t + g.TPC * e;
@@ -337,57 +437,59 @@ __global__ void __launch_bounds__(1024) k_pcg_c2(ColGeom g, const cpx<T>* __rest
             const size_t idx = (size_t)ct.kx * g.ny + j;
             const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
             const cpx<T> wv = in[D][e];
+            cpx<T> r[D], z[D];
 #pragma unroll
             for (int c = 0; c < D; ++c) {
                 const T kc = (c == 0) ? kx : ky;
                 const cpx<T> q = in[c][e] - ik(kc, wv);
                 if (MODE == C2_STORE) {
                     qh[c * NS + idx] = q;
-                } else if (MODE == C2_DOT) {
-                    qh[c * NS + idx] = q;
-                    const cpx<T> p = ph[c * NS + idx];
-                    acc[0] += w * ((double)p.re * (double)q.re + (double)p.im * (double)q.im);
-                } else {
+                } else if (MODE == C2_RESID) {
                     rh[c * NS + idx] = bh[c * NS + idx] - q;
+                } else {
+                    xh[c * NS + idx] = xh[c * NS + idx] + alpha * ph[c * NS + idx];
+                    r[c] = rh[c * NS + idx] - alpha * q;
+                    rh[c * NS + idx] = r[c];
+                }
+            }
+            if (MODE == C2_UPDATE) {
+                precond_mode<T, D>(kx, ky, sig, alp, r, z);
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    acc[0] += w * ((double)r[c].re * (double)z[c].re + (double)r[c].im * (double)z[c].im);
+                    acc[1] += w * ((double)r[c].re * (double)r[c].re + (double)r[c].im * (double)r[c].im);
                 }
             }
         }
     }
-    if (MODE == C2_DOT) {
-        block_sum<1>(acc, red);
-        if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
-        if (last_block_done(&sc->counter, gridDim.x)) {
-            if (threadIdx.x == 0) {
-                double s = 0.0;
-                for (unsigned b = 0; b < gridDim.x; ++b) s += partials[b];
-                s *= sc->inv_n;
-                sc->pq = s;
-                sc->alpha = sc->rho / s;
-                sc->counter = 0;
-            }
+    if (MODE == C2_UPDATE) {
+        block_sum<2>(acc, red);
+        if (threadIdx.x == 0) {
+            part[PART_C3 + 2 * blockIdx.x] = acc[0];
+            part[PART_C3 + 2 * blockIdx.x + 1] = acc[1];
         }
     }
 }
 
-// Flat loop over the S modes: kx = idx / ny, ky index = idx % ny.
-// INIT: no update; computes rho and ||r||^2 of the initial residual.  With
-// init_bb the right-hand side norm is taken as ||r_0|| (zero initial guess);
-// otherwise a zero right-hand side (bb == 0) gives x = 0 at once.
-template <typename T, int D, bool INIT>
-__global__ void __launch_bounds__(256) k_pcg_c3(int nx, int ny, size_t NS, SolveScal* __restrict__ sc,
-                                                cpx<T>* __restrict__ xh, cpx<T>* __restrict__ rh,
-                                                const cpx<T>* __restrict__ ph, const cpx<T>* __restrict__ qh,
-                                                double* __restrict__ partials, T tpx, T tpy, int init_bb) {
+// Initial residual pass over the S modes (kx = idx / ny, ky index = idx % ny):
+// partials of r.z and r.r of r_0 for the first stop test.  Unless init_bb is
+// set, a zero right-hand side (bb == 0) gives x = 0 at once.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_pcg_init(int nx, int ny, size_t NS, SolveScal* __restrict__ sc,
+                                                  cpx<T>* __restrict__ xh, cpx<T>* __restrict__ rh,
+                                                  double* __restrict__ part, T tpx, T tpy) {
     if (sc->done) return;
     __shared__ double red[32];
-    const bool zero_x = INIT && !init_bb && sc->bb == 0.0;
-    const T alpha = INIT ? (T)0 : (T)sc->alpha;
+    const bool zero_x = !sc->init_bb && sc->bb == 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->first = 1;
     const T sig = (T)sc->sig, alp = (T)sc->alp;
     double acc[2] = {0.0, 0.0};
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < NS; idx += stride) {
-        const int kxi = (int)(idx / ny);
-        const int kyi = (int)(idx - (size_t)kxi * ny);
+    const int nsi = (int)NS;
+    const int lny = ilog2(ny);
+    const int stride = gridDim.x * blockDim.x;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nsi; idx += stride) {
+        const int kxi = idx >> lny;
+        const int kyi = idx & (ny - 1);
         const T kx = wavenumber<T>(kxi, nx, tpx);
         const T ky = (D == 2) ? wavenumber<T>(kyi, ny, tpy) : (T)0;
         cpx<T> r[D], z[D];
@@ -397,11 +499,6 @@ __global__ void __launch_bounds__(256) k_pcg_c3(int nx, int ny, size_t NS, Solve
             if (zero_x) {
                 xh[c * NS + idx] = C<T>(0, 0);
                 r[c] = C<T>(0, 0);
-            }
-            if (!INIT) {
-                xh[c * NS + idx] = xh[c * NS + idx] + alpha * ph[c * NS + idx];
-                r[c] = r[c] - alpha * qh[c * NS + idx];
-                rh[c * NS + idx] = r[c];
             }
         }
         precond_mode<T, D>(kx, ky, sig, alp, r, z);
@@ -414,47 +511,17 @@ __global__ void __launch_bounds__(256) k_pcg_c3(int nx, int ny, size_t NS, Solve
     }
     block_sum<2>(acc, red);
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = acc[0];
-        partials[2 * blockIdx.x + 1] = acc[1];
-    }
-    if (last_block_done(&sc->counter, gridDim.x)) {
-        if (threadIdx.x == 0) {
-            double rz = 0.0, rr = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) {
-                rz += partials[2 * b];
-                rr += partials[2 * b + 1];
-            }
-            rz *= sc->inv_n;
-            rr *= sc->inv_n;
-            sc->rr = rr;
-            if (INIT && init_bb) sc->bb = rr;
-            sc->relres = sc->bb > 0.0 ? sqrt(rr / sc->bb) : 0.0;
-            if (!INIT) sc->iter += 1;
-            if (INIT && sc->bb == 0.0) {
-                sc->done = 1;
-                sc->converged = 1;
-            } else if (!(rr == rr) || !(rz == rz)) {
-                sc->done = 1;
-                sc->status = -2;
-            } else if (rr <= sc->tol2 * sc->bb) {
-                sc->done = 1;
-                sc->converged = 1;
-            } else if (sc->iter >= sc->max_iter) {
-                sc->done = 1;
-            }
-            sc->beta = INIT ? 0.0 : rz / sc->rho;
-            sc->rho = rz;
-            sc->counter = 0;
-        }
+        part[PART_C3 + 2 * blockIdx.x] = acc[0];
+        part[PART_C3 + 2 * blockIdx.x + 1] = acc[1];
     }
 }
 
-// b_hat from the H layout: y-FFT, store to bh (and rh if non-null), ||b||^2 -> sc->bb.
+// b_hat from the H layout: y-FFT, store to bh and/or rh, partial ||b||^2.
 template <typename T, int EPC, int D>
-__global__ void __launch_bounds__(1024) k_setup_b(ColGeom g, const cpx<T>* __restrict__ tw,
-                                                  SolveScal* __restrict__ sc, const cpx<T>* __restrict__ H,
-                                                  size_t NS, cpx<T>* __restrict__ bh, cpx<T>* __restrict__ rh,
-                                                  double* __restrict__ partials) {
+__global__ void __launch_bounds__(256) k_setup_b(ColGeom g, const cpx<T>* __restrict__ tw,
+                                                  const cpx<T>* __restrict__ H, size_t NS,
+                                                  cpx<T>* __restrict__ bh, cpx<T>* __restrict__ rh,
+                                                  double* __restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     __shared__ double red[16];
@@ -477,21 +544,27 @@ __global__ void __launch_bounds__(1024) k_setup_b(ColGeom g, const cpx<T>* __res
         }
     }
     block_sum<1>(acc, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
-    if (last_block_done(&sc->counter, gridDim.x)) {
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) s += partials[b];
-            sc->bb = s * sc->inv_n;
-            if (!(sc->bb == sc->bb) || sc->bb > 1.0e300) sc->status = -2;
-            sc->counter = 0;
+    if (threadIdx.x == 0) part[PART_GEN + blockIdx.x] = acc[0];
+}
+
+// One block: ||b||^2 from the k_setup_b partials.
+__global__ void __launch_bounds__(256) k_finish_bb(SolveScal* __restrict__ sc, const double* __restrict__ part,
+                                                   int nb) {
+    __shared__ double red[16];
+    double tot[1];
+    final_sum<1>(part + PART_GEN, nb, tot, red);
+    if (threadIdx.x == 0) {
+        sc->bb = tot[0] * sc->inv_n;
+        if (!(sc->bb == sc->bb) || sc->bb > 1.0e300) {
+            sc->status = -2;
+            sc->done = 1;
         }
     }
 }
 
 // Forward y-FFT of D H fields into S fields (no reduction).
 template <typename T, int EPC, int D>
-__global__ void __launch_bounds__(1024) k_cols_to_S(ColGeom g, const cpx<T>* __restrict__ tw,
+__global__ void __launch_bounds__(256) k_cols_to_S(ColGeom g, const cpx<T>* __restrict__ tw,
                                                     const cpx<T>* __restrict__ H, size_t NS,
                                                     cpx<T>* __restrict__ Sdst) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -507,7 +580,7 @@ __global__ void __launch_bounds__(1024) k_cols_to_S(ColGeom g, const cpx<T>* __r
 
 // Inverse y-FFT of D S fields (times scale) into H fields.
 template <typename T, int EPC, int D>
-__global__ void __launch_bounds__(1024) k_cols_from_S(ColGeom g, const cpx<T>* __restrict__ tw,
+__global__ void __launch_bounds__(256) k_cols_from_S(ColGeom g, const cpx<T>* __restrict__ tw,
                                                       const cpx<T>* __restrict__ Ssrc, size_t NS,
                                                       cpx<T>* __restrict__ H, T scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -525,11 +598,11 @@ __global__ void __launch_bounds__(1024) k_cols_from_S(ColGeom g, const cpx<T>* _
 
 // Initialise the scalars of a solve on the device (no host round trip).  With
 // have_coeffs the preconditioner coefficients are given; otherwise they are
-// filled later by k_coeffs or copied from another solve.
+// filled later by k_coeffs_finish or copied from another solve.
 __global__ void k_init_scal(SolveScal* __restrict__ sc, double tol, int max_iter, double inv_n, int have_coeffs,
-                            double sig, double alp, double kap, int flat) {
+                            double sig, double alp, double kap, int flat, int init_bb) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    sc->rho = sc->alpha = sc->beta = sc->bb = sc->rr = sc->pq = sc->relres = 0.0;
+    sc->rho = sc->rho_prev = sc->alpha = sc->beta = sc->bb = sc->rr = sc->pq = sc->relres = 0.0;
     sc->tol2 = tol * tol;
     sc->inv_n = inv_n;
     sc->iter = 0;
@@ -537,7 +610,8 @@ __global__ void k_init_scal(SolveScal* __restrict__ sc, double tol, int max_iter
     sc->done = 0;
     sc->converged = 0;
     sc->status = 0;
-    sc->counter = 0u;
+    sc->first = 1;
+    sc->init_bb = init_bb;
     if (have_coeffs) {
         sc->sig = sig;
         sc->alp = alp;
@@ -560,12 +634,11 @@ __global__ void k_copy_coeffs(const SolveScal* __restrict__ s, SolveScal* __rest
 // Reductions over physical fields (FP64)
 // ---------------------------------------------------------------------------
 
-// Coefficients of section 4 (Eq:MaxMinWaveFields, Eq:FlatbathCoeff, Eq:Optcoeff,
-// Eq:Optcoeffb, Remark 4.2) from eta and grad h, written to sc->sig/alp/kap.
+// Per-block extremes for the coefficients of section 4: min eta, max eta,
+// max(eta + lambda_+ eta |grad h|^2), max |grad h|^2 and a non-finite flag.
 template <int D>
 __global__ void __launch_bounds__(256) k_coeffs(size_t npts, const double* __restrict__ eta,
-                                                const double* __restrict__ gh, int flat, int kind,
-                                                SolveScal* __restrict__ sc, double* __restrict__ partials) {
+                                                const double* __restrict__ gh, double* __restrict__ part) {
     __shared__ double red[5 * 16];
     const double lp = (4.0 + sqrt(13.0)) / 6.0;
     double mn = 1.0e308, mx = -1.0e308, smax = -1.0e308, g2max = 0.0, bad = 0.0;
@@ -584,7 +657,6 @@ __global__ void __launch_bounds__(256) k_coeffs(size_t npts, const double* __res
         smax = fmax(smax, e + lp * e * g2);
         g2max = fmax(g2max, g2);
     }
-    // reduce min/max with shuffles (order independent)
     double v[5] = {-mn, mx, smax, g2max, bad};
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
@@ -599,52 +671,52 @@ __global__ void __launch_bounds__(256) k_coeffs(size_t npts, const double* __res
         for (int a = 0; a < 5; ++a) {
             double s = red[a * 16];
             for (int w = 1; w < nw; ++w) s = fmax(s, red[a * 16 + w]);
-            partials[5 * blockIdx.x + a] = s;
-        }
-    }
-    if (last_block_done(&sc->counter, gridDim.x)) {
-        if (threadIdx.x == 0) {
-            double r[5];
-            for (int a = 0; a < 5; ++a) {
-                double s = partials[a];
-                for (unsigned b = 1; b < gridDim.x; ++b) s = fmax(s, partials[5 * b + a]);
-                r[a] = s;
-            }
-            const double emin = -r[0], emax = r[1], smx = r[2], g2m = r[3];
-            sc->red[0] = emin;
-            sc->red[1] = emax;
-            sc->red[2] = smx;
-            sc->red[3] = g2m;
-            if (r[4] != 0.0 || !(emin > 0.0)) {
-                sc->status = -2;
-            } else {
-                const double lm = (4.0 - sqrt(13.0)) / 6.0;
-                const double ratio3 = (emax / emin) * (emax / emin) * (emax / emin);
-                const int fl = flat < 0 ? (g2m == 0.0 ? 1 : 0) : (flat != 0 ? 1 : 0);
-                sc->flat = fl;
-                if (fl) {
-                    sc->sig = emax;
-                    sc->alp = emax * emax * emax / 3.0;
-                    sc->kap = ratio3;
-                } else if (kind == 0) {
-                    sc->sig = smx;
-                    sc->alp = lp * emax * emax * emax;
-                    sc->kap = fmax(smx / emin, (lp / lm) * ratio3);
-                } else {
-                    sc->sig = emax * (1.0 + lp * g2m);
-                    sc->alp = lp * emax * emax * emax;
-                    sc->kap = fmax((emax / emin) * (1.0 + lp * g2m), (lp / lm) * ratio3);
-                }
-                sc->status = 0;
-            }
-            sc->counter = 0;
+            part[PART_GEN + 5 * blockIdx.x + a] = s;
         }
     }
 }
 
-// min and max of a physical field -> sc->red[0], sc->red[1] (for the flat test).
-__global__ void __launch_bounds__(256) k_minmax(size_t n, const double* __restrict__ f,
-                                                SolveScal* __restrict__ sc, double* __restrict__ partials) {
+// One block: (sigma*, alpha*, kappa_ub) of Eq:FlatbathCoeff, Eq:Optcoeff,
+// Eq:Optcoeffb (kind 0) or Remark 4.2 (kind 1).  flat < 0 selects the flat
+// formulas iff |grad h|_max = 0.
+__global__ void __launch_bounds__(256) k_coeffs_finish(SolveScal* __restrict__ sc, const double* __restrict__ part,
+                                                       int nb, int flat, int kind) {
+    __shared__ double red[5 * 16];
+    double r[5];
+    final_max<5>(part + PART_GEN, nb, r, red);
+    if (threadIdx.x != 0) return;
+    const double lp = (4.0 + sqrt(13.0)) / 6.0;
+    const double lm = (4.0 - sqrt(13.0)) / 6.0;
+    const double emin = -r[0], emax = r[1], smx = r[2], g2m = r[3];
+    sc->red[0] = emin;
+    sc->red[1] = emax;
+    sc->red[2] = smx;
+    sc->red[3] = g2m;
+    if (r[4] != 0.0 || !(emin > 0.0)) {
+        sc->status = -2;
+        sc->done = 1;
+        return;
+    }
+    const double ratio3 = (emax / emin) * (emax / emin) * (emax / emin);
+    const int fl = flat < 0 ? (g2m == 0.0 ? 1 : 0) : (flat != 0 ? 1 : 0);
+    sc->flat = fl;
+    if (fl) {
+        sc->sig = emax;
+        sc->alp = emax * emax * emax / 3.0;
+        sc->kap = ratio3;
+    } else if (kind == 0) {
+        sc->sig = smx;
+        sc->alp = lp * emax * emax * emax;
+        sc->kap = fmax(smx / emin, (lp / lm) * ratio3);
+    } else {
+        sc->sig = emax * (1.0 + lp * g2m);
+        sc->alp = lp * emax * emax * emax;
+        sc->kap = fmax((emax / emin) * (1.0 + lp * g2m), (lp / lm) * ratio3);
+    }
+}
+
+// Per-block min and max of a physical field (the flat-bottom test).
+__global__ void __launch_bounds__(256) k_minmax(size_t n, const double* __restrict__ f, double* __restrict__ part) {
     __shared__ double red[2 * 16];
     double mn = 1.0e308, mx = -1.0e308;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -669,20 +741,18 @@ __global__ void __launch_bounds__(256) k_minmax(size_t n, const double* __restri
             a = fmax(a, red[w]);
             b = fmax(b, red[16 + w]);
         }
-        partials[2 * blockIdx.x] = a;
-        partials[2 * blockIdx.x + 1] = b;
+        part[PART_GEN + 2 * blockIdx.x] = a;
+        part[PART_GEN + 2 * blockIdx.x + 1] = b;
     }
-    if (last_block_done(&sc->counter, gridDim.x)) {
-        if (threadIdx.x == 0) {
-            double a = partials[0], b = partials[1];
-            for (unsigned k = 1; k < gridDim.x; ++k) {
-                a = fmax(a, partials[2 * k]);
-                b = fmax(b, partials[2 * k + 1]);
-            }
-            sc->red[0] = -a;
-            sc->red[1] = b;
-            sc->counter = 0;
-        }
+}
+__global__ void __launch_bounds__(256) k_minmax_finish(SolveScal* __restrict__ sc, const double* __restrict__ part,
+                                                       int nb) {
+    __shared__ double red[2 * 16];
+    double r[2];
+    final_max<2>(part + PART_GEN, nb, r, red);
+    if (threadIdx.x == 0) {
+        sc->red[0] = -r[0];
+        sc->red[1] = r[1];
     }
 }
 

@@ -22,6 +22,11 @@ struct sgn_ctx {
     SolveScal* hscal = nullptr;   // pinned readback of solver scalars
     int* hflag = nullptr;         // pinned readback of the done flag
     std::string err;
+    // opt-in kernel timing: HIP events around every launch of each kernel family
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_next = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_marks;
 };
 
 namespace {
@@ -79,8 +84,8 @@ sgn_status check_grid(sgn_ctx* ctx, const sgn_grid* g, Dims* d) {
     if (!is_pow2(g->nx) || g->nx < 2 || !is_pow2(ny))
         return fail(ctx, SGN_EUNSUPPORTED, "grid sizes must be powers of two (nx >= 2)");
     if (g->dim == 1 && g->nx > 16384) return fail(ctx, SGN_EUNSUPPORTED, "1D nx above 16384");
-    if (g->dim == 2 && (g->nx > 4096 || ny > 4096 || ny < 2))
-        return fail(ctx, SGN_EUNSUPPORTED, "2D sizes must be in [2, 4096]");
+    if (g->dim == 2 && (g->nx > 4096 || ny > 1024 || ny < 2))
+        return fail(ctx, SGN_EUNSUPPORTED, "2D sizes: nx in [2, 4096], ny in [2, 1024]");
     if (!(g->Lx > 0.0) || (g->dim == 2 && !(g->Ly > 0.0)))
         return fail(ctx, SGN_EINVAL, "domain lengths must be positive");
     d->D = g->dim;
@@ -152,6 +157,7 @@ inline int flat_blocks(size_t n, int per = 256, int cap = 1024) {
     return (int)b;
 }
 
+
 template <typename K>
 hipError_t allow_lds(K kernel, size_t lds) {
     if (lds <= 65536) return hipSuccess;
@@ -163,11 +169,38 @@ template <typename T> const cpx<T>* twiddles(sgn_ctx* ctx);
 template <> const cpx<double>* twiddles<double>(sgn_ctx* ctx) { return ctx->tw64; }
 template <> const cpx<float>* twiddles<float>(sgn_ctx* ctx) { return ctx->tw32; }
 
+// ---- kernel timing ---------------------------------------------------------
+hipEvent_t prof_event(sgn_ctx* ctx) {
+    if (ctx->ev_next == ctx->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ctx->ev_pool.push_back(e);
+    }
+    return ctx->ev_pool[ctx->ev_next++];
+}
+// Scoped marker: records an event pair around the launches in its scope.
+struct ProfScope {
+    sgn_ctx* ctx;
+    int id;
+    hipEvent_t a = nullptr;
+    ProfScope(sgn_ctx* c, int kid) : ctx(c), id(kid) {
+        if (ctx->prof_on && (a = prof_event(ctx)) != nullptr) (void)hipEventRecord(a, ctx->stream);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = prof_event(ctx);
+        if (!b) return;
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->prof_marks.push_back({id, {a, b}});
+    }
+};
+
 // ---- generic passes --------------------------------------------------------
 
 template <typename T, typename Tin>
 sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, std::vector<cpx<T>*> dst,
                     T scale = (T)1) {
+    ProfScope ps(ctx, SGN_KERNEL_ROWS);
     RowLaunch L = row_launch<T>(d.nx, d.ny);
     for (size_t f0 = 0; f0 < src.size(); f0 += MAXF) {
         PtrList<const Tin, MAXF> s{};
@@ -196,6 +229,7 @@ sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, st
 template <typename T, typename Tout>
 sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src, std::vector<Tout*> dst,
                     T scale = (T)1, T acc = (T)0) {
+    ProfScope ps(ctx, SGN_KERNEL_ROWS);
     RowLaunch L = row_launch<T>(d.nx, d.ny);
     for (size_t f0 = 0; f0 < src.size(); f0 += MAXF) {
         PtrList<const cpx<T>, MAXF> s{};
@@ -224,6 +258,7 @@ sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src,
 template <typename T, int NI>
 sgn_status cols_lin_n(sgn_ctx* ctx, const Dims& d, const std::vector<const cpx<T>*>& src,
                       const std::vector<cpx<T>*>& dst, const LinCodes& lc, T scale) {
+    ProfScope ps(ctx, SGN_KERNEL_COLS);
     ColLaunch L = col_launch<T>(d.nx, d.ny);
     PtrList<const cpx<T>, MAXF> s{};
     PtrList<cpx<T>, MAXF> t{};
@@ -264,9 +299,11 @@ sgn_status launch_coeffs(sgn_ctx* ctx, const Dims& d, const double* eta, const d
                          int kind, SolveScal* sc, double* partials) {
     const int nb = flat_blocks(d.N, 256, 1024);
     if (d.D == 1)
-        hipLaunchKernelGGL(k_coeffs<1>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, flat, kind, sc, partials);
+        hipLaunchKernelGGL(k_coeffs<1>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, partials);
     else
-        hipLaunchKernelGGL(k_coeffs<2>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, flat, kind, sc, partials);
+        hipLaunchKernelGGL(k_coeffs<2>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, partials);
+    hipLaunchKernelGGL(k_coeffs_finish, dim3(1), dim3(256), 0, ctx->stream, sc, (const double*)partials, nb, flat,
+                       kind);
     CHECK_LAUNCH(ctx);
     return SGN_OK;
 }
@@ -276,12 +313,12 @@ sgn_status launch_coeffs(sgn_ctx* ctx, const Dims& d, const double* eta, const d
 // ---------------------------------------------------------------------------
 struct Common {
     SolveScal* sc;        // [4]: 0 = FP64 solve / misc, 1 = FP32 inner solve
-    double* partials;     // PARTIALS_MAX * 5
+    double* partials;     // PART_TOTAL doubles (see sgn_kernels.h)
 };
 Common carve_common(Carve& cv) {
     Common c;
     c.sc = cv.take<SolveScal>(4);
-    c.partials = cv.take<double>((size_t)PARTIALS_MAX * 5);
+    c.partials = cv.take<double>((size_t)PART_TOTAL);
     return c;
 }
 
@@ -361,68 +398,71 @@ struct PcgLaunch {
 
 template <typename T, int D>
 sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc) {
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C1);
     auto& L = P.cl;
     if (mode == C1_COPY) {
         auto k = k_pcg_c1<T, 4, D, C1_COPY>;
         HIPCHK(P.ctx, allow_lds(k, L.lds));
         hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, P.b.rh, P.b.ph, xsrc, P.b.H, P.d.NS, (T)P.d.tpx, (T)P.d.tpy);
+                           P.sc, (const double*)P.partials, P.cl.g.nblocks, P.b.rh, P.b.ph, xsrc, P.b.H, P.d.NS,
+                           (T)P.d.tpx, (T)P.d.tpy);
     } else {
         auto k = k_pcg_c1<T, 4, D, C1_UPDATE>;
         HIPCHK(P.ctx, allow_lds(k, L.lds));
         hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, P.b.rh, P.b.ph, xsrc, P.b.H, P.d.NS, (T)P.d.tpx, (T)P.d.tpy);
+                           P.sc, (const double*)P.partials, P.cl.g.nblocks, P.b.rh, P.b.ph, xsrc, P.b.H, P.d.NS,
+                           (T)P.d.tpx, (T)P.d.tpy);
     }
     CHECK_LAUNCH(P.ctx);
     return SGN_OK;
 }
 
 template <typename T, int D>
-sgn_status pcg_r1(PcgLaunch<T, D>& P) {
+sgn_status pcg_r1(PcgLaunch<T, D>& P, bool curvature = false) {
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_R1);
+    double* part = curvature ? P.partials : nullptr;
     auto& L = P.rl;
     if (L.epc == 4) {
         auto k = k_pcg_r1<T, 4, D>;
         HIPCHK(P.ctx, allow_lds(k, L.lds));
         hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, P.b.H, P.d.NS, P.eta, P.gh);
+                           P.sc, P.b.H, P.d.NS, P.eta, P.gh, part);
     } else {
         auto k = k_pcg_r1<T, 8, D>;
         HIPCHK(P.ctx, allow_lds(k, L.lds));
         hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, P.b.H, P.d.NS, P.eta, P.gh);
+                           P.sc, P.b.H, P.d.NS, P.eta, P.gh, part);
     }
+    CHECK_LAUNCH(P.ctx);
+    return SGN_OK;
+}
+
+template <typename T, int D, int MODE>
+sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out) {
+    auto& L = P.cl;
+    auto k = k_pcg_c2<T, 4, D, MODE>;
+    HIPCHK(P.ctx, allow_lds(k, L.lds));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx), P.sc,
+                       (const cpx<T>*)P.b.H, P.d.NS, P.b.qh, (const cpx<T>*)P.b.ph, P.b.xh, bh, rh_out, P.partials,
+                       P.rl.g.nblocks, (T)P.d.tpx, (T)P.d.tpy);
     CHECK_LAUNCH(P.ctx);
     return SGN_OK;
 }
 
 template <typename T, int D>
 sgn_status pcg_c2(PcgLaunch<T, D>& P, int mode, const cpx<T>* bh, cpx<T>* rh_out) {
-    auto& L = P.cl;
-    if (mode == C2_STORE) {
-        auto k = k_pcg_c2<T, 4, D, C2_STORE>;
-        HIPCHK(P.ctx, allow_lds(k, L.lds));
-        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, P.b.H, P.d.NS, P.b.qh, P.b.ph, bh, rh_out, P.partials, (T)P.d.tpx, (T)P.d.tpy);
-    } else if (mode == C2_DOT) {
-        auto k = k_pcg_c2<T, 4, D, C2_DOT>;
-        HIPCHK(P.ctx, allow_lds(k, L.lds));
-        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, P.b.H, P.d.NS, P.b.qh, P.b.ph, bh, rh_out, P.partials, (T)P.d.tpx, (T)P.d.tpy);
-    } else {
-        auto k = k_pcg_c2<T, 4, D, C2_RESID>;
-        HIPCHK(P.ctx, allow_lds(k, L.lds));
-        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, P.b.H, P.d.NS, P.b.qh, P.b.ph, bh, rh_out, P.partials, (T)P.d.tpx, (T)P.d.tpy);
-    }
-    CHECK_LAUNCH(P.ctx);
-    return SGN_OK;
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C2);
+    if (mode == C2_STORE) return pcg_c2_mode<T, D, C2_STORE>(P, bh, rh_out);
+    if (mode == C2_RESID) return pcg_c2_mode<T, D, C2_RESID>(P, bh, rh_out);
+    return pcg_c2_mode<T, D, C2_UPDATE>(P, nullptr, P.b.rh);
 }
 
-template <typename T, int D, bool INIT>
-sgn_status pcg_c3(PcgLaunch<T, D>& P, int init_bb = 0) {
-    const int nb = flat_blocks(P.d.NS, 256, 1024);
-    hipLaunchKernelGGL((k_pcg_c3<T, D, INIT>), dim3(nb), dim3(256), 0, P.ctx->stream, P.d.nx, P.d.ny, P.d.NS,
-                       P.sc, P.b.xh, P.b.rh, P.b.ph, P.b.qh, P.partials, (T)P.d.tpx, (T)P.d.tpy, init_bb);
+// Initial residual pass: partials of r.z, r.r on the column grid.
+template <typename T, int D>
+sgn_status pcg_init(PcgLaunch<T, D>& P) {
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C3);
+    hipLaunchKernelGGL((k_pcg_init<T, D>), dim3(P.cl.g.nblocks), dim3(256), 0, P.ctx->stream, P.d.nx, P.d.ny,
+                       P.d.NS, P.sc, P.b.xh, P.b.rh, P.partials, (T)P.d.tpx, (T)P.d.tpy);
     CHECK_LAUNCH(P.ctx);
     return SGN_OK;
 }
@@ -443,10 +483,19 @@ sgn_status read_done(sgn_ctx* ctx, const SolveScal* sc, int* done) {
 
 // Initialise a SolveScal on the device (stream-ordered, no host round trip).
 sgn_status init_scal(sgn_ctx* ctx, SolveScal* sc, double tol, int max_iter, double inv_n,
-                     const sgn_coeffs* co) {
+                     const sgn_coeffs* co, int init_bb = 0) {
     hipLaunchKernelGGL(k_init_scal, dim3(1), dim3(64), 0, ctx->stream, sc, tol, max_iter, inv_n, co ? 1 : 0,
-                       co ? co->sigma : 0.0, co ? co->alpha : 0.0, co ? co->kappa_ub : 0.0, co ? co->flat : 0);
+                       co ? co->sigma : 0.0, co ? co->alpha : 0.0, co ? co->kappa_ub : 0.0, co ? co->flat : 0,
+                       init_bb);
     CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
+template <typename T, int D>
+sgn_status pcg_check(PcgLaunch<T, D>& P) {
+    hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, P.ctx->stream, P.sc, (const double*)P.partials,
+                       P.cl.g.nblocks);
+    CHECK_LAUNCH(P.ctx);
     return SGN_OK;
 }
 
@@ -461,13 +510,14 @@ sgn_status pcg_loop(PcgLaunch<T, D>& P, int max_iter, int check_every) {
         for (int c = 0; c < chunk; ++c) {
             sgn_status s;
             if ((s = pcg_c1<T, D>(P, C1_UPDATE, nullptr)) != SGN_OK) return s;
-            if ((s = pcg_r1<T, D>(P)) != SGN_OK) return s;
-            if ((s = pcg_c2<T, D>(P, C2_DOT, nullptr, nullptr)) != SGN_OK) return s;
-            if ((s = pcg_c3<T, D, false>(P)) != SGN_OK) return s;
+            if ((s = pcg_r1<T, D>(P, true)) != SGN_OK) return s;
+            if ((s = pcg_c2<T, D>(P, C2_UPDATE, nullptr, nullptr)) != SGN_OK) return s;
         }
         it += chunk;
         int done = 0;
-        sgn_status s = read_done(P.ctx, P.sc, &done);
+        sgn_status s = pcg_check<T, D>(P);
+        if (s != SGN_OK) return s;
+        s = read_done(P.ctx, P.sc, &done);
         if (s != SGN_OK) return s;
         if (done) break;
     }
@@ -507,8 +557,9 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
         auto k = k_setup_b<double, 4, D>;
         HIPCHK(ctx, allow_lds(k, P.cl.lds));
         hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g,
-                           ctx->tw64, P.sc, (const cpx<double>*)P.b.H, d.NS, (cpx<double>*)nullptr, P.b.rh,
-                           P.partials);
+                           ctx->tw64, (const cpx<double>*)P.b.H, d.NS, (cpx<double>*)nullptr, P.b.rh, P.partials);
+        hipLaunchKernelGGL(k_finish_bb, dim3(1), dim3(256), 0, ctx->stream, P.sc, (const double*)P.partials,
+                           P.cl.g.nblocks);
         CHECK_LAUNCH(ctx);
     }
     if (o.x0_is_guess) {
@@ -529,7 +580,7 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
                            (size_t)d.D * d.NS * 2, (void*)P.b.xh);
         CHECK_LAUNCH(ctx);
     }
-    if ((s = pcg_c3<double, D, true>(P)) != SGN_OK) return s;
+    if ((s = pcg_init<double, D>(P)) != SGN_OK) return s;
     if ((s = pcg_loop<double, D>(P, o.max_iter, o.check_every)) != SGN_OK) return s;
     // u = IFFT(x_hat)
     {
@@ -614,7 +665,9 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
         auto k = k_setup_b<double, 4, D>;
         HIPCHK(ctx, allow_lds(k, P.cl.lds));
         hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g,
-                           ctx->tw64, P.sc, (const cpx<double>*)P.b.H, d.NS, P.b.bh, P.b.rh, P.partials);
+                           ctx->tw64, (const cpx<double>*)P.b.H, d.NS, P.b.bh, P.b.rh, P.partials);
+        hipLaunchKernelGGL(k_finish_bb, dim3(1), dim3(256), 0, ctx->stream, P.sc, (const double*)P.partials,
+                           P.cl.g.nblocks);
         CHECK_LAUNCH(ctx);
     }
     if (o.x0_is_guess) {
@@ -635,24 +688,24 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
         CHECK_LAUNCH(ctx);
     }
     // FP64 residual norm and stop test (INIT C3 computes r.z and r.r)
-    if ((s = pcg_c3<double, D, true>(P)) != SGN_OK) return s;
+    if ((s = pcg_init<double, D>(P)) != SGN_OK) return s;
     int total_inner = 0, outer = 0;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
     for (; outer < max_outer; ++outer) {
         int done = 0;
+        if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
         if ((s = read_done(ctx, P.sc, &done)) != SGN_OK) return s;
         if (done) break;
-        // inner FP32 solve of G dx = r from dx = 0
-        if ((s = init_scal(ctx, Q.sc, inner_tol, o.max_iter, d.inv_n, nullptr)) != SGN_OK) return s;
+        // inner FP32 solve of G dx = r from dx = 0; ||b_inner|| = ||r_outer||
+        if ((s = init_scal(ctx, Q.sc, inner_tol, o.max_iter, d.inv_n, nullptr, 1)) != SGN_OK) return s;
         hipLaunchKernelGGL(k_copy_coeffs, dim3(1), dim3(64), 0, ctx->stream, P.sc, Q.sc);
         hipLaunchKernelGGL(k_S_demote, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream, (size_t)D * d.NS,
                            (const cpx<double>*)P.b.rh, Q.b.rh);
         hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream, (size_t)D * d.NS,
                            (void*)Q.b.xh);
         CHECK_LAUNCH(ctx);
-        // the inner right-hand side norm is that of the demoted FP64 residual
-        if ((s = pcg_c3<float, D, true>(Q, 1)) != SGN_OK) return s;
+        if ((s = pcg_init<float, D>(Q)) != SGN_OK) return s;
         if ((s = pcg_loop<float, D>(Q, o.max_iter, o.check_every)) != SGN_OK) return s;
         if ((s = read_scal(ctx, Q.sc)) != SGN_OK) return s;
         total_inner += ctx->hscal->iter;
@@ -663,8 +716,9 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
         if ((s = pcg_c1<double, D>(P, C1_COPY, P.b.xh)) != SGN_OK) return s;
         if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
         if ((s = pcg_c2<double, D>(P, C2_RESID, P.b.bh, P.b.rh)) != SGN_OK) return s;
-        if ((s = pcg_c3<double, D, true>(P)) != SGN_OK) return s;
+        if ((s = pcg_init<double, D>(P)) != SGN_OK) return s;
     }
+    if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
     {
         auto k = k_cols_from_S<double, 4, D>;
         HIPCHK(ctx, allow_lds(k, P.cl.lds));
@@ -1319,7 +1373,38 @@ void sgn_destroy(sgn_ctx* ctx) {
     if (ctx->tw32) (void)hipFree(ctx->tw32);
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     if (ctx->hflag) (void)hipHostFree(ctx->hflag);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
+}
+
+sgn_status sgn_profile_begin(sgn_ctx* ctx) {
+    if (!ctx) return SGN_EINVAL;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->prof_marks.clear();
+    ctx->ev_next = 0;
+    ctx->prof_on = true;
+    return SGN_OK;
+}
+
+sgn_status sgn_profile_end(sgn_ctx* ctx, int64_t* launches, double* total_ms, int32_t nkinds) {
+    if (!ctx || !launches || !total_ms || nkinds < 1) return SGN_EINVAL;
+    ctx->prof_on = false;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < nkinds; ++k) {
+        launches[k] = 0;
+        total_ms[k] = 0.0;
+    }
+    for (auto& m : ctx->prof_marks) {
+        float ms = 0.0f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, m.second.first, m.second.second));
+        if (m.first >= 0 && m.first < nkinds) {
+            launches[m.first] += 1;
+            total_ms[m.first] += ms;
+        }
+    }
+    ctx->prof_marks.clear();
+    ctx->ev_next = 0;
+    return SGN_OK;
 }
 
 sgn_status sgn_set_stream(sgn_ctx* ctx, void* hip_stream) {
@@ -1347,7 +1432,9 @@ sgn_status sgn_bathy_prepare(sgn_ctx* ctx, const sgn_grid* grid, const double* h
     Common cm = carve_common(cv);
     cpx<double>* H = cv.take<cpx<double>>((size_t)(1 + d.D) * d.NS);
     if ((s = init_scal(ctx, cm.sc, 1.0, 1, d.inv_n, nullptr)) != SGN_OK) return s;
-    hipLaunchKernelGGL(k_minmax, dim3(flat_blocks(d.N)), dim3(256), 0, ctx->stream, d.N, h, cm.sc, cm.partials);
+    hipLaunchKernelGGL(k_minmax, dim3(flat_blocks(d.N)), dim3(256), 0, ctx->stream, d.N, h, cm.partials);
+    hipLaunchKernelGGL(k_minmax_finish, dim3(1), dim3(256), 0, ctx->stream, cm.sc, (const double*)cm.partials,
+                       flat_blocks(d.N));
     CHECK_LAUNCH(ctx);
     if ((s = read_scal(ctx, cm.sc)) != SGN_OK) return s;
     const double hmin = ctx->hscal->red[0], hmax = ctx->hscal->red[1];

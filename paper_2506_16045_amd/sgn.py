@@ -80,6 +80,8 @@ _SIGS = {
     "sgn_set_stream": (_S, [_P, _P]),
     "sgn_last_error": (ctypes.c_char_p, [_P]),
     "sgn_version": (ctypes.c_char_p, []),
+    "sgn_profile_begin": (_S, [_P]),
+    "sgn_profile_end": (_S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), _I]),
     "sgn_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
     "sgn_bathy_prepare": (_S, [_P, ctypes.POINTER(Grid), _P, _P, ctypes.POINTER(_I), _P]),
     "sgn_precond_coeffs": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _I, _I, ctypes.POINTER(Coeffs), _P]),
@@ -208,6 +210,21 @@ class Context:
             ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
             self._ws[key] = ws
         return ws
+
+    # -- kernel timing ---------------------------------------------------------
+    KERNEL_KINDS = ("pcg_c1", "pcg_r1", "pcg_c2", "pcg_c3", "rows", "cols")
+
+    def profile_begin(self):
+        self._sync_stream()
+        self._check(_lib.sgn_profile_begin(self._h))
+
+    def profile_end(self):
+        """{kernel family: (launches, total milliseconds)} since profile_begin."""
+        n = len(self.KERNEL_KINDS)
+        cnt = (ctypes.c_int64 * n)()
+        ms = (ctypes.c_double * n)()
+        self._check(_lib.sgn_profile_end(self._h, cnt, ms, n))
+        return {k: (int(cnt[i]), float(ms[i])) for i, k in enumerate(self.KERNEL_KINDS)}
 
     # -- entry points ----------------------------------------------------------
     def bathy_prepare(self, g, h: torch.Tensor):

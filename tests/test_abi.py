@@ -51,7 +51,7 @@ def test_version_and_workspace_sizes(lib):
     assert 100e6 < big < 1e9
 
 
-@pytest.mark.parametrize("dim,nx,ny", [(1, 3, 1), (1, 32768, 1), (2, 64, 1), (2, 8192, 8), (3, 8, 8), (1, 0, 1)])
+@pytest.mark.parametrize("dim,nx,ny", [(1, 3, 1), (1, 32768, 1), (2, 64, 1), (2, 8192, 8), (2, 64, 2048), (3, 8, 8), (1, 0, 1)])
 def test_unsupported_grids_report_zero_workspace(dim, nx, ny):
     from paper_2506_16045_amd import sgn
     g = sgn.Grid(dim, nx, ny, 1.0, 1.0)
