@@ -36,6 +36,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0    # MI355X HBM3E, 8 TB/s
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_16045_amd", "csrc", f) for f in ("sgn_device.h", "sgn_kernels.h")]
+
+
 def kernel_bytes(kind: str, d: int, nx: int, ny: int, word: int) -> float:
     """Algorithmic HBM bytes of one launch of a PCG kernel family: every field
     the kernel must read once plus every field it must write once.
@@ -43,15 +47,41 @@ def kernel_bytes(kind: str, d: int, nx: int, ny: int, word: int) -> float:
     ns = (nx // 2 + 1) * ny
     n = nx * ny
     cw = 2 * word
-    if kind == "pcg_c1":      # read r_hat, p_hat (2d fields); write p_hat (d) and d+1 transformed fields
+    base = kind.replace("_f32", "")
+    if base == "pcg_c1":      # read r_hat, p_hat (2d fields); write p_hat (d) and d+1 transformed fields
         return (2 * d + d + (d + 1)) * ns * cw
-    if kind == "pcg_r1":      # read/write d+1 half-spectral fields; read eta and grad h (1 + d reals)
+    if base == "pcg_r1":      # read/write d+1 half-spectral fields; read eta and grad h (1 + d reals)
         return 2 * (d + 1) * ns * cw + (1 + d) * n * word
-    if kind == "pcg_c2":      # read d+1 half-spectral fields and p_hat (d); write q_hat (d)
-        return ((d + 1) + d + d) * ns * cw
-    if kind == "pcg_c3":      # read x, r, p, q hats (4d); write x, r hats (2d)
-        return (4 * d + 2 * d) * ns * cw
+    if base == "pcg_c2":      # read d+1 half-spectral fields and p, x, r hats (3d); write x, r hats (2d)
+        return ((d + 1) + 3 * d + 2 * d) * ns * cw
+    if base == "pcg_init":    # read r hat (d)
+        return d * ns * cw
     raise ValueError(kind)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind: str, n: int):
+    """HBM bytes per launch from the committed counter runs, if they were taken on
+    the current kernel sources (else None)."""
+    path = os.path.join(PROFILES, "pcg_traffic_2d_1024.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha") != kernel_source_hash() or rec.get("n") != n:
+        return None
+    prec_key = "f32" if kind.endswith("_f32") else "f64"
+    ent = rec.get("kernels", {}).get(prec_key, {}).get(kind.replace("_f32", ""))
+    return ent.get("hbm_bytes_per_launch") if ent else None
 
 
 def percentile(xs, q):
@@ -89,7 +119,35 @@ def main(argv=None):
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--inner-tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true", help="skip the per-kernel HIP-event timing pass")
+    ap.add_argument("--timing-steps", type=int, default=5, help="steps of the per-kernel timing pass")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before the timed region "
+                         "(reference kernel for scaling the HBM byte counters of a profiler run)")
+    ap.add_argument("--summarize-kernels", metavar="DB", help="write a kernel-duration summary of a "
+                    "rocprofv3 --kernel-trace results database (no GPU needed) and exit")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="HBM bytes per launch of the PCG passes from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
+                         "runs of this script with --calib-copy-mib (no GPU needed) and exit")
+    ap.add_argument("--command", default="", help="command line recorded in a summary")
+    ap.add_argument("--out", help="summary output path")
     args = ap.parse_args(argv)
+
+    if args.summarize_kernels or args.summarize_traffic:
+        from paper_2506_16045_amd import profiling
+        if args.summarize_kernels:
+            text = profiling.kernel_summary_md(args.summarize_kernels, args.command,
+                                               f"Kernel durations: {args.precision}, {args.n}x{args.n} RK4 workload")
+        else:
+            rec = profiling.traffic(args.summarize_traffic[0], args.summarize_traffic[1],
+                                    args.calib_copy_mib * (1 << 20))
+            rec.update({"n": args.n, "kernel_source_sha": kernel_source_hash(), "command": args.command})
+            text = json.dumps(rec, indent=1) + "\n"
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write(text)
+        print(text)
+        return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
@@ -119,14 +177,22 @@ def main(argv=None):
     state = sgn.State(ctx, g, h, gh, flat, eta, U, u)
     mass0 = float(torch.sum(eta - h).item())
 
+    if args.calib_copy_mib > 0:
+        nel = args.calib_copy_mib * (1 << 20) // 8
+        src_c = torch.rand(nel, dtype=torch.float64, device=dev)
+        dst_c = torch.empty_like(src_c)
+        torch.cuda.synchronize()
+        dst_c.copy_(src_c)
+        torch.cuda.synchronize()
+        del src_c, dst_c
     if args.warmup > 0:
         state.step_rk4(cfg["dt"], args.warmup, opts)
     torch.cuda.synchronize()
 
+    # timed region: K steps, no instrumentation
     lat = []
     solves = iters = 0
     max_iters = 0
-    ctx.profile_begin()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -141,8 +207,16 @@ def main(argv=None):
             raise RuntimeError("a Krylov solve did not converge")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ctx.profile_end()
     elapsed = t1 - t0
+
+    # kernel timing: HIP events around every launch of each kernel family on the
+    # library's stream, over further steps of the same run (events between
+    # launches slow the step down, so they stay out of the timed region above)
+    prof = {k: (0, 0.0) for k in ctx.KERNEL_KINDS}
+    if not args.no_kernel_timing and args.timing_steps > 0:
+        ctx.profile_begin()
+        state.step_rk4(cfg["dt"], args.timing_steps, opts)
+        prof = ctx.profile_end()
 
     # device-side property checks of the final state (not part of the timed region)
     Gu = ctx.apply_constraint(g, state.eta, gh, state.u)
@@ -151,18 +225,24 @@ def main(argv=None):
 
     word = 4 if prec == sgn.MIXED else 8
     kstats = {}
-    for kind in ("pcg_c1", "pcg_r1", "pcg_c2", "pcg_c3"):
+    kinds = ("pcg_c1_f32", "pcg_r1_f32", "pcg_c2_f32", "pcg_init_f32") if prec == sgn.MIXED else \
+        ("pcg_c1", "pcg_r1", "pcg_c2", "pcg_init")
+    for kind in kinds:
         n_launch, ms = prof[kind]
         if n_launch:
             kstats[kind] = {"launches": n_launch, "avg_us": 1e3 * ms / n_launch, "total_ms": ms}
-    # in mixed mode some launches of each family are the FP64 residual passes;
-    # the roofline is quoted for the dominant family with the inner (FP32) word size
-    dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
-    nbytes = kernel_bytes(dom, g.d, g.nx, g.ny, word)
-    achieved = nbytes / (kstats[dom]["avg_us"] * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": nbytes, "avg_launch_us": round(kstats[dom]["avg_us"], 2)}
+    # the roofline is quoted for the dominant family of the working precision
+    # (FP32 inner passes in mixed mode; the FP64 residual passes are separate families)
+    roofline = None
+    if kstats:
+        dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
+        nbytes = kernel_bytes(dom, g.d, g.nx, g.ny, word)
+        achieved = nbytes / (kstats[dom]["avg_us"] * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(dom, args.n),
+                    "bytes_per_launch": nbytes, "avg_launch_us": round(kstats[dom]["avg_us"], 2),
+                    "timing": f"HIP events around every launch over {args.timing_steps} further steps"}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -129,13 +129,17 @@ const char *sgn_version(void);
  * summed event time in milliseconds (host arrays of nkinds entries).
  * The events may add a few microseconds per launch. */
 typedef enum sgn_kernel_kind {
-    SGN_KERNEL_PCG_C1 = 0,   /* A^{-1}, search direction, y-IFFT (column pass) */
-    SGN_KERNEL_PCG_R1 = 1,   /* x-IFFT, pointwise operator, x-FFT (row pass)   */
-    SGN_KERNEL_PCG_C2 = 2,   /* y-FFT, q = G p, p.q (column pass)              */
-    SGN_KERNEL_PCG_C3 = 3,   /* x, r update, A^{-1} r, r.z and r.r             */
-    SGN_KERNEL_ROWS = 4,     /* generic row transforms (right-hand side etc.)  */
-    SGN_KERNEL_COLS = 5,     /* generic column operators                       */
-    SGN_KERNEL_KINDS = 6
+    SGN_KERNEL_PCG_C1 = 0,   /* FP64: A^{-1}, search direction, y-IFFT (column pass) */
+    SGN_KERNEL_PCG_R1 = 1,   /* FP64: x-IFFT, pointwise operator, p.Gp, x-FFT (row pass) */
+    SGN_KERNEL_PCG_C2 = 2,   /* FP64: y-FFT, q = G p, x and r update, r.z, r.r (column pass) */
+    SGN_KERNEL_PCG_INIT = 3, /* FP64: initial residual pass */
+    SGN_KERNEL_ROWS = 4,     /* generic FP64 row transforms (right-hand side etc.) */
+    SGN_KERNEL_COLS = 5,     /* generic FP64 column operators */
+    SGN_KERNEL_PCG_C1_F32 = 6,   /* the same PCG passes in FP32 (mixed precision) */
+    SGN_KERNEL_PCG_R1_F32 = 7,
+    SGN_KERNEL_PCG_C2_F32 = 8,
+    SGN_KERNEL_PCG_INIT_F32 = 9,
+    SGN_KERNEL_KINDS = 10
 } sgn_kernel_kind;
 sgn_status sgn_profile_begin(sgn_ctx *ctx);
 sgn_status sgn_profile_end(sgn_ctx *ctx, int64_t *launches, double *total_ms, int32_t nkinds);

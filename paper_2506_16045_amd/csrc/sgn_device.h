@@ -12,10 +12,10 @@
 // All transforms are unnormalised; callers apply 1/(nx*ny) once per round trip.
 //
 // FFTs run in LDS as radix-4 Stockham passes (autosort, decimation in time)
-// with a final radix-2 pass when log2 M is odd.  A real row of length nx is
-// transformed as a complex sequence of length M = nx/2 (z_j = x_2j + i x_2j+1)
-// followed by the usual even/odd split; twiddles come from one table of
-// W^k = exp(-2 pi i k / TW), TW = 16384.
+// with a final radix-2 pass when log2 M is odd; the fields a pass needs are
+// transformed in lockstep so they share the block barriers.  A real row of
+// length nx is transformed as a complex sequence of length M = nx/2
+// (z_j = x_2j + i x_2j+1) followed by the usual even/odd split.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,7 +23,8 @@
 namespace sgn {
 
 constexpr int TW_LOG = 14;
-constexpr int TW_SIZE = 1 << TW_LOG;
+constexpr int TW_SIZE = 1 << TW_LOG;          // largest transform length
+constexpr int TW_ALL = 2 * TW_SIZE - 1;       // entries of the per-size twiddle table
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cpx {
@@ -55,36 +56,65 @@ __device__ __forceinline__ T wavenumber(int j, int n, T two_pi_over_L) {
 }
 
 // ---------------------------------------------------------------------------
-// Stockham FFT of length M (power of two) in LDS buffer `buf`, executed by TPX
-// cooperating threads (thread index t).  Every thread of the block must call
-// it (it contains block barriers); EPC bounds the elements per thread
-// (M <= EPC * TPX).  Forward: exp(-i ...); inverse: exp(+i ...), unnormalised.
+// Twiddles.  The global table holds, for every power of two L <= TW_SIZE, the
+// L-th roots of unity W_L^j = exp(-2 pi i j / L) contiguously at offset L - 1
+// (2 TW_SIZE - 1 entries).  An FFT of length M reads W_M^m; kernels copy the M
+// entries into LDS once per block when they fit (see twl_setup).
 // ---------------------------------------------------------------------------
-template <typename T, int EPC>
-__device__ __forceinline__ void lds_fft(cpx<T>* buf, int M, int t, int TPX,
-                                        const cpx<T>* __restrict__ tw, bool inverse) {
+template <typename T>
+__device__ __forceinline__ const cpx<T>* tw_size(const cpx<T>* __restrict__ tw_all, int L) {
+    return tw_all + (L - 1);
+}
+
+constexpr int TWL_MAX = 2048;  // largest FFT length whose twiddles are staged in LDS
+
+// Stage W_M^m (m < M) in LDS when M <= TWL_MAX; returns the table to use (LDS or
+// global).  Contains a block barrier; every thread must call it.
+template <typename T>
+__device__ __forceinline__ const cpx<T>* twl_setup(const cpx<T>* __restrict__ tw_all, int M, cpx<T>* lds_tw) {
+    const cpx<T>* g = tw_size(tw_all, M);
+    if (M > TWL_MAX || M < 4) return g;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) lds_tw[j] = g[j];
+    __syncthreads();
+    return lds_tw;
+}
+
+// ---------------------------------------------------------------------------
+// Stockham FFT of length M (power of two) on NF buffers at buf + f * fstride,
+// transformed in lockstep by TPX cooperating threads (thread index t): radix-4
+// passes, then one radix-2 pass when log2 M is odd.  Every thread of the block
+// must call it (it contains block barriers); M <= EPC * TPX.  twm[m] = W_M^m.
+// Forward: exp(-i ...); inverse: exp(+i ...); unnormalised.
+// ---------------------------------------------------------------------------
+template <typename T, int EPC, int NF>
+__device__ __forceinline__ void lds_fft(cpx<T>* buf, int fstride, int M, int t, int TPX,
+                                        const cpx<T>* __restrict__ twm, bool inverse) {
     constexpr int NB4 = EPC / 4 > 0 ? EPC / 4 : 1;
     constexpr int NB2 = EPC / 2 > 0 ? EPC / 2 : 1;
     const int M4 = M >> 2;
+    const int logM = ilog2(M);
     int Ns = 1;
     int logNs = 0;
     for (; Ns * 4 <= M; Ns <<= 2, logNs += 2) {
-        cpx<T> v[NB4][4];
-        const int sh = TW_LOG - (logNs + 2);
+        cpx<T> v[NB4][NF][4];
+        const int sh = logM - (logNs + 2);   // W_{4Ns}^{kr} = W_M^{kr M / 4Ns}
 #pragma unroll
         for (int i = 0; i < NB4; ++i) {
             const int j = t + i * TPX;
             if (j < M4) {
                 const int k = j & (Ns - 1);
+                cpx<T> w[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    cpx<T> a = buf[j + r * M4];
-                    if (r > 0) {
-                        cpx<T> w = tw[(k * r) << sh];
-                        if (inverse) w.im = -w.im;
-                        a = a * w;
-                    }
-                    v[i][r] = a;
+                for (int r = 1; r < 4; ++r) {
+                    w[r] = twm[(k * r) << sh];
+                    if (inverse) w[r].im = -w[r].im;
+                }
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const cpx<T>* bf = buf + f * fstride;
+                    v[i][f][0] = bf[j];
+#pragma unroll
+                    for (int r = 1; r < 4; ++r) v[i][f][r] = bf[j + r * M4] * w[r];
                 }
             }
         }
@@ -94,33 +124,41 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int M, int t, int TPX,
             const int j = t + i * TPX;
             if (j < M4) {
                 const int k = j & (Ns - 1);
-                const cpx<T> a0 = v[i][0] + v[i][2];
-                const cpx<T> a1 = v[i][0] - v[i][2];
-                const cpx<T> a2 = v[i][1] + v[i][3];
-                const cpx<T> d = v[i][1] - v[i][3];
-                const cpx<T> a3 = inverse ? mul_i(d) : mul_mi(d);
                 const int o = ((j - k) << 2) + k;
-                buf[o] = a0 + a2;
-                buf[o + Ns] = a1 + a3;
-                buf[o + 2 * Ns] = a0 - a2;
-                buf[o + 3 * Ns] = a1 - a3;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const cpx<T> a0 = v[i][f][0] + v[i][f][2];
+                    const cpx<T> a1 = v[i][f][0] - v[i][f][2];
+                    const cpx<T> a2 = v[i][f][1] + v[i][f][3];
+                    const cpx<T> d = v[i][f][1] - v[i][f][3];
+                    const cpx<T> a3 = inverse ? mul_i(d) : mul_mi(d);
+                    cpx<T>* bf = buf + f * fstride;
+                    bf[o] = a0 + a2;
+                    bf[o + Ns] = a1 + a3;
+                    bf[o + 2 * Ns] = a0 - a2;
+                    bf[o + 3 * Ns] = a1 - a3;
+                }
             }
         }
         __syncthreads();
     }
     if (Ns < M) {  // one radix-2 pass remains (log2 M odd)
         const int M2 = M >> 1;
-        const int sh = TW_LOG - (logNs + 1);
-        cpx<T> v[NB2][2];
+        const int sh = logM - (logNs + 1);
+        cpx<T> v[NB2][NF][2];
 #pragma unroll
         for (int i = 0; i < NB2; ++i) {
             const int j = t + i * TPX;
             if (j < M2) {
                 const int k = j & (Ns - 1);
-                cpx<T> w = tw[k << sh];
+                cpx<T> w = twm[k << sh];
                 if (inverse) w.im = -w.im;
-                v[i][0] = buf[j];
-                v[i][1] = buf[j + M2] * w;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const cpx<T>* bf = buf + f * fstride;
+                    v[i][f][0] = bf[j];
+                    v[i][f][1] = bf[j + M2] * w;
+                }
             }
         }
         __syncthreads();
@@ -130,8 +168,12 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int M, int t, int TPX,
             if (j < M2) {
                 const int k = j & (Ns - 1);
                 const int o = ((j - k) << 1) + k;
-                buf[o] = v[i][0] + v[i][1];
-                buf[o + Ns] = v[i][0] - v[i][1];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    cpx<T>* bf = buf + f * fstride;
+                    bf[o] = v[i][f][0] + v[i][f][1];
+                    bf[o + Ns] = v[i][f][0] - v[i][f][1];
+                }
             }
         }
         __syncthreads();
@@ -141,7 +183,8 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int M, int t, int TPX,
 // ---------------------------------------------------------------------------
 // Row geometry: a block holds R rows of TPR threads each; row r of the block is
 // grid row row0 + r.  Thread t of a row owns complex positions j = t + TPR*e
-// (e < EPC), i.e. real positions 2j and 2j+1.
+// (e < EPC), i.e. real positions 2j and 2j+1.  LDS: NF fields x R rows of M+1
+// complex entries (field stride R (M+1)), then the twiddle table.
 // ---------------------------------------------------------------------------
 struct RowGeom {
     int nx, ny, M, TPR, R, nblocks;
@@ -151,8 +194,8 @@ template <typename T>
 struct RowThread {
     int r, t, y, row0;
     bool valid;
-    cpx<T>* buf;  // this row's LDS buffer, M+1 entries
-    cpx<T>* lds;  // block LDS base (R rows of stride M+1)
+    cpx<T>* lds;  // block LDS base
+    int fstride;  // R (M+1)
 };
 
 // Map a launch block index to a row group so that consecutive row groups land on
@@ -172,106 +215,124 @@ __device__ __forceinline__ RowThread<T> row_thread(const RowGeom& g, cpx<T>* lds
     rt.y = rt.row0 + rt.r;
     rt.valid = rt.y < g.ny;
     rt.lds = lds;
-    rt.buf = lds + rt.r * (g.M + 1);
+    rt.fstride = g.R * (g.M + 1);
     return rt;
 }
 
-// Inverse row transform: H[kx][y] (kx = 0..M) -> real pairs z[e] = (x_2j, x_2j+1),
-// unnormalised (returns nx times the inverse DFT).  The imaginary parts of the
-// kx = 0 and kx = nx/2 entries are ignored (real signal).
-template <typename T, int EPC>
+// LDS entries a row kernel with NF fields needs before its twiddle table.
+__host__ __device__ inline int row_lds_data(const RowGeom& g, int NF) { return NF * g.R * (g.M + 1); }
+
+// Inverse row transforms of NF fields: H_f[kx][y] (kx = 0..M) -> real pairs
+// z[f][e] = (x_2j, x_2j+1), unnormalised (nx times the inverse DFT).  The
+// imaginary parts of the kx = 0 and kx = nx/2 entries are ignored (real signal).
+template <typename T, int EPC, int NF>
 __device__ __forceinline__ void row_inverse(const RowGeom& g, const RowThread<T>& rt,
-                                            const cpx<T>* __restrict__ H,
-                                            const cpx<T>* __restrict__ tw, cpx<T> (&z)[EPC]) {
+                                            const cpx<T>* const (&H)[NF],
+                                            const cpx<T>* __restrict__ tw_all, const cpx<T>* twm,
+                                            cpx<T> (&z)[NF][EPC]) {
     const int M = g.M, R = g.R, ny = g.ny;
     const int total = R * (M + 1);
-    for (int i = threadIdx.x; i < total; i += blockDim.x) {
-        const int r = i & (R - 1);
-        const int kx = i / R;
-        const int y = rt.row0 + r;
-        rt.lds[r * (M + 1) + kx] = (y < ny) ? H[(size_t)kx * ny + y] : C<T>(0, 0);
-    }
-    __syncthreads();
-    const int sh = TW_LOG - ilog2(2 * M);  // W_nx^k = tw[k << sh]
-    for (int p = rt.t; p <= M / 2; p += g.TPR) {
-        cpx<T>* b = rt.buf;
-        if (p == 0) {
-            const T x0 = b[0].re, xm = b[M].re;
-            b[0] = C<T>(x0 + xm, x0 - xm);
-        } else {
-            const int k = p, m = M - p;
-            const cpx<T> Xk = b[k], Xm = b[m];
-            cpx<T> wk = tw[k << sh];
-            wk.im = -wk.im;
-            const cpx<T> Zk = (Xk + cj(Xm)) + mul_i((Xk - cj(Xm)) * wk);
-            if (m != k) {
-                cpx<T> wm = tw[m << sh];
-                wm.im = -wm.im;
-                const cpx<T> Zm = (Xm + cj(Xk)) + mul_i((Xm - cj(Xk)) * wm);
-                b[m] = Zm;
-            }
-            b[k] = Zk;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        for (int i = threadIdx.x; i < total; i += blockDim.x) {
+            const int r = i & (R - 1);
+            const int kx = i / R;
+            const int y = rt.row0 + r;
+            rt.lds[f * rt.fstride + r * (M + 1) + kx] = (y < ny) ? H[f][(size_t)kx * ny + y] : C<T>(0, 0);
         }
     }
     __syncthreads();
-    lds_fft<T, EPC>(rt.buf, M, rt.t, g.TPR, tw, true);
+    const cpx<T>* tw2 = tw_size(tw_all, 2 * M);  // W_nx^k
+    cpx<T>* rowb = rt.lds + rt.r * (M + 1);
+    for (int p = rt.t; p <= M / 2; p += g.TPR) {
+        const int k = p, m = M - p;
+        cpx<T> wk = tw2[k], wm = tw2[m < 2 * M ? m : 0];
+        wk.im = -wk.im;
+        wm.im = -wm.im;
 #pragma unroll
-    for (int e = 0; e < EPC; ++e) {
-        const int j = rt.t + g.TPR * e;
-        if (j < M) z[e] = rt.buf[j];
+        for (int f = 0; f < NF; ++f) {
+            cpx<T>* b = rowb + f * rt.fstride;
+            if (p == 0) {
+                const T x0 = b[0].re, xm = b[M].re;
+                b[0] = C<T>(x0 + xm, x0 - xm);
+            } else {
+                const cpx<T> Xk = b[k], Xm = b[m];
+                const cpx<T> Zk = (Xk + cj(Xm)) + mul_i((Xk - cj(Xm)) * wk);
+                if (m != k) b[m] = (Xm + cj(Xk)) + mul_i((Xm - cj(Xk)) * wm);
+                b[k] = Zk;
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft<T, EPC, NF>(rowb, rt.fstride, M, rt.t, g.TPR, twm, true);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = rt.t + g.TPR * e;
+            if (j < M) z[f][e] = rowb[f * rt.fstride + j];
+        }
     }
     __syncthreads();
 }
 
-// Forward row transform: real pairs z[e] -> H[kx][y] for kx = 0..M, each value
-// multiplied by `scale`.
-template <typename T, int EPC>
-__device__ __forceinline__ void row_forward(const RowGeom& g, const RowThread<T>& rt,
-                                            const cpx<T> (&z)[EPC], cpx<T>* __restrict__ H,
-                                            const cpx<T>* __restrict__ tw, T scale) {
+// Forward row transforms of NF fields: real pairs z[f][e] -> H_f[kx][y] for
+// kx = 0..M, each value multiplied by `scale`.
+template <typename T, int EPC, int NF>
+__device__ __forceinline__ void row_forward(const RowGeom& g, const RowThread<T>& rt, const cpx<T> (&z)[NF][EPC],
+                                            cpx<T>* const (&H)[NF], const cpx<T>* __restrict__ tw_all,
+                                            const cpx<T>* twm, T scale) {
     const int M = g.M, R = g.R, ny = g.ny;
+    cpx<T>* rowb = rt.lds + rt.r * (M + 1);
 #pragma unroll
-    for (int e = 0; e < EPC; ++e) {
-        const int j = rt.t + g.TPR * e;
-        if (j < M) rt.buf[j] = z[e];
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = rt.t + g.TPR * e;
+            if (j < M) rowb[f * rt.fstride + j] = z[f][e];
+        }
     }
     __syncthreads();
-    lds_fft<T, EPC>(rt.buf, M, rt.t, g.TPR, tw, false);
-    const int sh = TW_LOG - ilog2(2 * M);
+    lds_fft<T, EPC, NF>(rowb, rt.fstride, M, rt.t, g.TPR, twm, false);
+    const cpx<T>* tw2 = tw_size(tw_all, 2 * M);
     const T half = (T)0.5;
     for (int p = rt.t; p <= M / 2; p += g.TPR) {
-        cpx<T>* b = rt.buf;
-        if (p == 0) {
-            const cpx<T> Z0 = b[0];
-            b[0] = C<T>(Z0.re + Z0.im, 0);
-            b[M] = C<T>(Z0.re - Z0.im, 0);
-        } else {
-            const int k = p, m = M - p;
-            const cpx<T> Zk = b[k], Zm = b[m];
-            const cpx<T> wk = tw[k << sh];
-            const cpx<T> Xk = half * (Zk + cj(Zm)) - half * mul_i(wk * (Zk - cj(Zm)));
-            if (m != k) {
-                const cpx<T> wm = tw[m << sh];
-                const cpx<T> Xm = half * (Zm + cj(Zk)) - half * mul_i(wm * (Zm - cj(Zk)));
-                b[m] = Xm;
+        const int k = p, m = M - p;
+        const cpx<T> wk = tw2[k], wm = tw2[m < 2 * M ? m : 0];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cpx<T>* b = rowb + f * rt.fstride;
+            if (p == 0) {
+                const cpx<T> Z0 = b[0];
+                b[0] = C<T>(Z0.re + Z0.im, 0);
+                b[M] = C<T>(Z0.re - Z0.im, 0);
+            } else {
+                const cpx<T> Zk = b[k], Zm = b[m];
+                const cpx<T> Xk = half * (Zk + cj(Zm)) - half * mul_i(wk * (Zk - cj(Zm)));
+                if (m != k) b[m] = half * (Zm + cj(Zk)) - half * mul_i(wm * (Zm - cj(Zk)));
+                b[k] = Xk;
             }
-            b[k] = Xk;
         }
     }
     __syncthreads();
     const int total = R * (M + 1);
-    for (int i = threadIdx.x; i < total; i += blockDim.x) {
-        const int r = i & (R - 1);
-        const int kx = i / R;
-        const int y = rt.row0 + r;
-        if (y < ny) H[(size_t)kx * ny + y] = scale * rt.lds[r * (M + 1) + kx];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        for (int i = threadIdx.x; i < total; i += blockDim.x) {
+            const int r = i & (R - 1);
+            const int kx = i / R;
+            const int y = rt.row0 + r;
+            if (y < ny) H[f][(size_t)kx * ny + y] = scale * rt.lds[f * rt.fstride + r * (M + 1) + kx];
+        }
     }
     __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Column geometry: a block holds Cb columns (kx) of TPC threads each; column c
-// is kx = blockIdx.x * Cb + c.  Thread t owns modes j = t + TPC*e (e < EPC, j < ny).
+// is kx = blockIdx.x * Cb + c.  Thread t owns modes j = t + TPC*e (e < EPC,
+// j < ny).  LDS: NF fields x Cb columns of ny entries (field stride Cb ny), then
+// the twiddle table.
 // ---------------------------------------------------------------------------
 struct ColGeom {
     int nx, ny, nxh, TPC, Cb, nblocks;
@@ -281,8 +342,11 @@ template <typename T>
 struct ColThread {
     int c, t, kx;
     bool valid;
-    cpx<T>* buf;
+    cpx<T>* buf;  // field 0 of this column
+    int fstride;  // Cb ny
 };
+
+__host__ __device__ inline int col_lds_data(const ColGeom& g, int NF) { return NF * g.Cb * g.ny; }
 
 template <typename T>
 __device__ __forceinline__ ColThread<T> col_thread(const ColGeom& g, cpx<T>* lds) {
@@ -292,63 +356,80 @@ __device__ __forceinline__ ColThread<T> col_thread(const ColGeom& g, cpx<T>* lds
     ct.kx = blockIdx.x * g.Cb + ct.c;
     ct.valid = ct.kx < g.nxh;
     ct.buf = lds + ct.c * g.ny;
+    ct.fstride = g.Cb * g.ny;
     return ct;
 }
 
-// Load a column of H (or S) and optionally transform it along y.
-template <typename T, int EPC>
-__device__ __forceinline__ void col_load(const ColGeom& g, const ColThread<T>& ct,
-                                         const cpx<T>* __restrict__ H, bool fft,
-                                         const cpx<T>* __restrict__ tw, cpx<T> (&v)[EPC]) {
+// Load NF columns of H (or S) and optionally transform them along y.
+template <typename T, int EPC, int NF>
+__device__ __forceinline__ void col_load(const ColGeom& g, const ColThread<T>& ct, const cpx<T>* const (&H)[NF],
+                                         bool fft, const cpx<T>* twm, cpx<T> (&v)[NF][EPC]) {
     const int ny = g.ny;
 #pragma unroll
-    for (int e = 0; e < EPC; ++e) {
-        const int j = ct.t + g.TPC * e;
-        if (j < ny) v[e] = ct.valid ? H[(size_t)ct.kx * ny + j] : C<T>(0, 0);
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+            if (j < ny) v[f][e] = ct.valid ? H[f][(size_t)ct.kx * ny + j] : C<T>(0, 0);
+        }
     }
     if (fft && ny > 1) {
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            const int j = ct.t + g.TPC * e;
-            if (j < ny) ct.buf[j] = v[e];
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int j = ct.t + g.TPC * e;
+                if (j < ny) ct.buf[f * ct.fstride + j] = v[f][e];
+            }
         }
         __syncthreads();
-        lds_fft<T, EPC>(ct.buf, ny, ct.t, g.TPC, tw, false);
+        lds_fft<T, EPC, NF>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, false);
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            const int j = ct.t + g.TPC * e;
-            if (j < ny) v[e] = ct.buf[j];
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int j = ct.t + g.TPC * e;
+                if (j < ny) v[f][e] = ct.buf[f * ct.fstride + j];
+            }
         }
         __syncthreads();
     }
 }
 
-// Optionally inverse-transform along y, then store a column of H (or S).
-template <typename T, int EPC>
-__device__ __forceinline__ void col_store(const ColGeom& g, const ColThread<T>& ct,
-                                          cpx<T> (&v)[EPC], cpx<T>* __restrict__ H, bool ifft,
-                                          const cpx<T>* __restrict__ tw) {
+// Optionally inverse-transform NF columns along y, then store them to H (or S).
+template <typename T, int EPC, int NF>
+__device__ __forceinline__ void col_store(const ColGeom& g, const ColThread<T>& ct, cpx<T> (&v)[NF][EPC],
+                                          cpx<T>* const (&H)[NF], bool ifft, const cpx<T>* twm) {
     const int ny = g.ny;
     if (ifft && ny > 1) {
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            const int j = ct.t + g.TPC * e;
-            if (j < ny) ct.buf[j] = v[e];
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int j = ct.t + g.TPC * e;
+                if (j < ny) ct.buf[f * ct.fstride + j] = v[f][e];
+            }
         }
         __syncthreads();
-        lds_fft<T, EPC>(ct.buf, ny, ct.t, g.TPC, tw, true);
+        lds_fft<T, EPC, NF>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, true);
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            const int j = ct.t + g.TPC * e;
-            if (j < ny) v[e] = ct.buf[j];
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int j = ct.t + g.TPC * e;
+                if (j < ny) v[f][e] = ct.buf[f * ct.fstride + j];
+            }
         }
         __syncthreads();
     }
     if (ct.valid) {
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            const int j = ct.t + g.TPC * e;
-            if (j < ny) H[(size_t)ct.kx * ny + j] = v[e];
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int j = ct.t + g.TPC * e;
+                if (j < ny) H[f][(size_t)ct.kx * ny + j] = v[f][e];
+            }
         }
     }
 }

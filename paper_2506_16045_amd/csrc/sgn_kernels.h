@@ -76,48 +76,64 @@ __device__ __forceinline__ void precond_mode(T kx, T ky, T sig, T alp, const cpx
 // Generic FFT passes
 // ---------------------------------------------------------------------------
 
-// Forward row transforms of n physical fields (Tin = double or T) into H fields.
-template <typename T, typename Tin, int EPC>
+// Forward row transforms of n physical fields (Tin = double or T) into H fields,
+// NFG fields at a time in lockstep (the remainder one by one).
+template <typename T, typename Tin, int EPC, int NFG>
+__device__ __forceinline__ void rows_fwd_group(const RowGeom& g, const RowThread<T>& rt,
+                                               const PtrList<const Tin, MAXF>& src, const PtrList<cpx<T>, MAXF>& dst,
+                                               int f0, const cpx<T>* __restrict__ tw, const cpx<T>* twm, T scale) {
+    cpx<T> z[NFG][EPC];
+    cpx<T>* H[NFG];
+#pragma unroll
+    for (int f = 0; f < NFG; ++f) {
+        H[f] = dst.p[f0 + f];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = rt.t + g.TPR * e;
+            z[f][e] = C<T>(0, 0);
+            if (j < g.M && rt.valid) {
+                const size_t o = (size_t)rt.y * g.nx + 2 * j;
+                z[f][e] = C<T>((T)src.p[f0 + f][o], (T)src.p[f0 + f][o + 1]);
+            }
+        }
+    }
+    row_forward<T, EPC, NFG>(g, rt, z, H, tw, twm, scale);
+}
+
+template <typename T, typename Tin, int EPC, int NFG>
 __global__ void __launch_bounds__(1024) k_rows_fwd(RowGeom g, PtrList<const Tin, MAXF> src,
                                                    PtrList<cpx<T>, MAXF> dst,
                                                    const cpx<T>* __restrict__ tw, T scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* twm = twl_setup<T>(tw, g.M, lds + row_lds_data(g, NFG));
     const RowThread<T> rt = row_thread<T>(g, lds);
-    for (int f = 0; f < src.n; ++f) {
-        cpx<T> z[EPC];
-#pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            const int j = rt.t + g.TPR * e;
-            z[e] = C<T>(0, 0);
-            if (j < g.M && rt.valid) {
-                const size_t o = (size_t)rt.y * g.nx + 2 * j;
-                z[e] = C<T>((T)src.p[f][o], (T)src.p[f][o + 1]);
-            }
-        }
-        row_forward<T, EPC>(g, rt, z, dst.p[f], tw, scale);
-    }
+    int f = 0;
+    for (; f + NFG <= src.n; f += NFG) rows_fwd_group<T, Tin, EPC, NFG>(g, rt, src, dst, f, tw, twm, scale);
+    for (; f < src.n; ++f) rows_fwd_group<T, Tin, EPC, 1>(g, rt, src, dst, f, tw, twm, scale);
 }
 
 // Inverse row transforms of n H fields into physical fields (Tout):
 // dst = acc * dst + scale * value  (acc = 0 overwrites).
-template <typename T, typename Tout, int EPC>
-__global__ void __launch_bounds__(1024) k_rows_inv(RowGeom g, PtrList<const cpx<T>, MAXF> src,
-                                                   PtrList<Tout, MAXF> dst,
-                                                   const cpx<T>* __restrict__ tw, T scale, T acc) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-    const RowThread<T> rt = row_thread<T>(g, lds);
-    for (int f = 0; f < src.n; ++f) {
-        cpx<T> z[EPC];
-        row_inverse<T, EPC>(g, rt, src.p[f], tw, z);
+template <typename T, typename Tout, int EPC, int NFG>
+__device__ __forceinline__ void rows_inv_group(const RowGeom& g, const RowThread<T>& rt,
+                                               const PtrList<const cpx<T>, MAXF>& src, const PtrList<Tout, MAXF>& dst,
+                                               int f0, const cpx<T>* __restrict__ tw, const cpx<T>* twm, T scale,
+                                               T acc) {
+    cpx<T> z[NFG][EPC];
+    const cpx<T>* H[NFG];
+#pragma unroll
+    for (int f = 0; f < NFG; ++f) H[f] = src.p[f0 + f];
+    row_inverse<T, EPC, NFG>(g, rt, H, tw, twm, z);
+#pragma unroll
+    for (int f = 0; f < NFG; ++f) {
 #pragma unroll
         for (int e = 0; e < EPC; ++e) {
             const int j = rt.t + g.TPR * e;
             if (j < g.M && rt.valid) {
                 const size_t o = (size_t)rt.y * g.nx + 2 * j;
-                Tout* d = dst.p[f];
-                T v0 = scale * z[e].re, v1 = scale * z[e].im;
+                Tout* d = dst.p[f0 + f];
+                T v0 = scale * z[f][e].re, v1 = scale * z[f][e].im;
                 if (acc != (T)0) {
                     v0 += acc * (T)d[o];
                     v1 += acc * (T)d[o + 1];
@@ -127,6 +143,19 @@ __global__ void __launch_bounds__(1024) k_rows_inv(RowGeom g, PtrList<const cpx<
             }
         }
     }
+}
+
+template <typename T, typename Tout, int EPC, int NFG>
+__global__ void __launch_bounds__(1024) k_rows_inv(RowGeom g, PtrList<const cpx<T>, MAXF> src,
+                                                   PtrList<Tout, MAXF> dst,
+                                                   const cpx<T>* __restrict__ tw, T scale, T acc) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* twm = twl_setup<T>(tw, g.M, lds + row_lds_data(g, NFG));
+    const RowThread<T> rt = row_thread<T>(g, lds);
+    int f = 0;
+    for (; f + NFG <= src.n; f += NFG) rows_inv_group<T, Tout, EPC, NFG>(g, rt, src, dst, f, tw, twm, scale, acc);
+    for (; f < src.n; ++f) rows_inv_group<T, Tout, EPC, 1>(g, rt, src, dst, f, tw, twm, scale, acc);
 }
 
 // Linear spectral operators on columns: out_o = sum_i c(code[o][i], k) in_i, with
@@ -160,13 +189,16 @@ __global__ void __launch_bounds__(256) k_cols_lin(ColGeom g, PtrList<const cpx<T
                                                    T scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, NI));
     const ColThread<T> ct = col_thread<T>(g, lds);
     cpx<T> in[NI][EPC];
+    const cpx<T>* srcs[NI];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) col_load<T, EPC>(g, ct, src.p[i], true, tw, in[i]);
+    for (int i = 0; i < NI; ++i) srcs[i] = src.p[i];
+    col_load<T, EPC, NI>(g, ct, srcs, true, twm, in);
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
     for (int o = 0; o < lc.no; ++o) {
-        cpx<T> v[EPC];
+        cpx<T> v[1][EPC];
 #pragma unroll
         for (int e = 0; e < EPC; ++e) {
             const int j = ct.t + g.TPC * e;
@@ -174,9 +206,10 @@ __global__ void __launch_bounds__(256) k_cols_lin(ColGeom g, PtrList<const cpx<T
             cpx<T> s = C<T>(0, 0);
 #pragma unroll
             for (int i = 0; i < NI; ++i) s = s + lin_coef<T>(lc.code[o][i], kx, ky) * in[i][e];
-            v[e] = scale * s;
+            v[0][e] = scale * s;
         }
-        col_store<T, EPC>(g, ct, v, dst.p[o], true, tw);
+        cpx<T>* dsts[1] = {dst.p[o]};
+        col_store<T, EPC, 1>(g, ct, v, dsts, true, twm);
     }
 }
 
@@ -188,10 +221,17 @@ __global__ void __launch_bounds__(256) k_cols_precond(ColGeom g, PtrList<const c
                                                        T sig, T alp, T scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D));
     const ColThread<T> ct = col_thread<T>(g, lds);
     cpx<T> in[D][EPC];
+    const cpx<T>* srcs[D];
+    cpx<T>* dsts[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) col_load<T, EPC>(g, ct, src.p[c], true, tw, in[c]);
+    for (int c = 0; c < D; ++c) {
+        srcs[c] = src.p[c];
+        dsts[c] = dst.p[c];
+    }
+    col_load<T, EPC, D>(g, ct, srcs, true, twm, in);
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
     cpx<T> out[D][EPC];
 #pragma unroll
@@ -205,8 +245,7 @@ __global__ void __launch_bounds__(256) k_cols_precond(ColGeom g, PtrList<const c
 #pragma unroll
         for (int c = 0; c < D; ++c) out[c][e] = scale * z[c];
     }
-#pragma unroll
-    for (int c = 0; c < D; ++c) col_store<T, EPC>(g, ct, out[c], dst.p[c], true, tw);
+    col_store<T, EPC, D>(g, ct, out, dsts, true, twm);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,6 +319,7 @@ __global__ void __launch_bounds__(256) k_pcg_c1(ColGeom g, const cpx<T>* __restr
     if (MODE == C1_UPDATE) {
         if (pcg_iterate_state(sc, part, nb3, red, slot, beta_d)) return;
     }
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D + 1));
     const ColThread<T> ct = col_thread<T>(g, lds);
     const T beta = (T)beta_d, sig = (T)sc->sig, alp = (T)sc->alp, inv_n = (T)sc->inv_n;
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
@@ -316,8 +356,10 @@ __global__ void __launch_bounds__(256) k_pcg_c1(ColGeom g, const cpx<T>* __restr
             o[D][e] = inv_n * dv;
         }
     }
+    cpx<T>* dsts[D + 1];
 #pragma unroll
-    for (int c = 0; c <= D; ++c) col_store<T, EPC>(g, ct, o[c], H + c * NS, true, tw);
+    for (int c = 0; c <= D; ++c) dsts[c] = H + c * NS;
+    col_store<T, EPC, D + 1>(g, ct, o, dsts, true, twm);
 }
 
 // Stop test only (one block): closes a chunk of iterations so the host can
@@ -331,7 +373,7 @@ __global__ void __launch_bounds__(256) k_pcg_check(SolveScal* __restrict__ sc, c
     pcg_iterate_state(sc, part, nb3, red, slot, beta);
 }
 
-template <typename T, int EPC, int D>
+template <typename T, int EPC, int D, bool SEQ>
 __global__ void __launch_bounds__(1024) k_pcg_r1(RowGeom g, const cpx<T>* __restrict__ tw,
                                                  SolveScal* __restrict__ sc, cpx<T>* H, size_t NS,
                                                  const T* __restrict__ eta, const T* __restrict__ gh,
@@ -340,11 +382,26 @@ __global__ void __launch_bounds__(1024) k_pcg_r1(RowGeom g, const cpx<T>* __rest
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     __shared__ double red[16];
+    constexpr int NF = SEQ ? 1 : D + 1;
+    const cpx<T>* twm = twl_setup<T>(tw, g.M, lds + row_lds_data(g, NF));
     const RowThread<T> rt = row_thread<T>(g, lds);
     double acc[1] = {0.0};
     cpx<T> v[D + 1][EPC];
+    if (SEQ) {
 #pragma unroll
-    for (int c = 0; c <= D; ++c) row_inverse<T, EPC>(g, rt, H + c * NS, tw, v[c]);
+        for (int c = 0; c <= D; ++c) {
+            const cpx<T>* Hc[1] = {H + c * NS};
+            cpx<T> vc[1][EPC];
+            row_inverse<T, EPC, 1>(g, rt, Hc, tw, twm, vc);
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) v[c][e] = vc[0][e];
+        }
+    } else {
+        const cpx<T>* Hs[D + 1];
+#pragma unroll
+        for (int c = 0; c <= D; ++c) Hs[c] = H + c * NS;
+        row_inverse<T, EPC, D + 1>(g, rt, Hs, tw, twm, v);
+    }
     const size_t npts = (size_t)g.nx * g.ny;
     const T third = (T)1 / (T)3, half = (T)0.5;
 #pragma unroll
@@ -381,8 +438,21 @@ __global__ void __launch_bounds__(1024) k_pcg_r1(RowGeom g, const cpx<T>* __rest
             }
         }
     }
+    if (SEQ) {
 #pragma unroll
-    for (int c = 0; c <= D; ++c) row_forward<T, EPC>(g, rt, v[c], H + c * NS, tw, (T)1);
+        for (int c = 0; c <= D; ++c) {
+            cpx<T>* Hc[1] = {H + c * NS};
+            cpx<T> vc[1][EPC];
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) vc[0][e] = v[c][e];
+            row_forward<T, EPC, 1>(g, rt, vc, Hc, tw, twm, (T)1);
+        }
+    } else {
+        cpx<T>* Hs[D + 1];
+#pragma unroll
+        for (int c = 0; c <= D; ++c) Hs[c] = H + c * NS;
+        row_forward<T, EPC, D + 1>(g, rt, v, Hs, tw, twm, (T)1);
+    }
     if (part) {
         block_sum<1>(acc, red);
         if (threadIdx.x == 0) part[PART_C2 + blockIdx.x] = acc[0];
@@ -422,10 +492,13 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
             sc->first = 0;
         }
     }
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D + 1));
     const ColThread<T> ct = col_thread<T>(g, lds);
     cpx<T> in[D + 1][EPC];
+    const cpx<T>* srcs[D + 1];
 #pragma unroll
-    for (int c = 0; c <= D; ++c) col_load<T, EPC>(g, ct, H + c * NS, true, tw, in[c]);
+    for (int c = 0; c <= D; ++c) srcs[c] = H + c * NS;
+    col_load<T, EPC, D + 1>(g, ct, srcs, true, twm, in);
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
     const T sig = (T)sc->sig, alp = (T)sc->alp;
     const double w = ct.valid ? half_weight(ct.kx, g.nx) : 0.0;
@@ -525,21 +598,25 @@ __global__ void __launch_bounds__(256) k_setup_b(ColGeom g, const cpx<T>* __rest
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     __shared__ double red[16];
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D));
     const ColThread<T> ct = col_thread<T>(g, lds);
     const double w = ct.valid ? half_weight(ct.kx, g.nx) : 0.0;
     double acc[1] = {0.0};
+    cpx<T> v[D][EPC];
+    const cpx<T>* srcs[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) srcs[c] = H + c * NS;
+    col_load<T, EPC, D>(g, ct, srcs, true, twm, v);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-        cpx<T> v[EPC];
-        col_load<T, EPC>(g, ct, H + c * NS, true, tw, v);
 #pragma unroll
         for (int e = 0; e < EPC; ++e) {
             const int j = ct.t + g.TPC * e;
             if (ct.valid && j < g.ny) {
                 const size_t idx = (size_t)ct.kx * g.ny + j;
-                if (bh) bh[c * NS + idx] = v[e];
-                if (rh) rh[c * NS + idx] = v[e];
-                acc[0] += w * ((double)v[e].re * (double)v[e].re + (double)v[e].im * (double)v[e].im);
+                if (bh) bh[c * NS + idx] = v[c][e];
+                if (rh) rh[c * NS + idx] = v[c][e];
+                acc[0] += w * ((double)v[c][e].re * (double)v[c][e].re + (double)v[c][e].im * (double)v[c][e].im);
             }
         }
     }
@@ -569,13 +646,18 @@ __global__ void __launch_bounds__(256) k_cols_to_S(ColGeom g, const cpx<T>* __re
                                                     cpx<T>* __restrict__ Sdst) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D));
     const ColThread<T> ct = col_thread<T>(g, lds);
+    cpx<T> v[D][EPC];
+    const cpx<T>* srcs[D];
+    cpx<T>* dsts[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-        cpx<T> v[EPC];
-        col_load<T, EPC>(g, ct, H + c * NS, true, tw, v);
-        col_store<T, EPC>(g, ct, v, Sdst + c * NS, false, tw);
+        srcs[c] = H + c * NS;
+        dsts[c] = Sdst + c * NS;
     }
+    col_load<T, EPC, D>(g, ct, srcs, true, twm, v);
+    col_store<T, EPC, D>(g, ct, v, dsts, false, twm);
 }
 
 // Inverse y-FFT of D S fields (times scale) into H fields.
@@ -585,15 +667,22 @@ __global__ void __launch_bounds__(256) k_cols_from_S(ColGeom g, const cpx<T>* __
                                                       cpx<T>* __restrict__ H, T scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D));
     const ColThread<T> ct = col_thread<T>(g, lds);
+    cpx<T> v[D][EPC];
+    const cpx<T>* srcs[D];
+    cpx<T>* dsts[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-        cpx<T> v[EPC];
-        col_load<T, EPC>(g, ct, Ssrc + c * NS, false, tw, v);
-#pragma unroll
-        for (int e = 0; e < EPC; ++e) v[e] = scale * v[e];
-        col_store<T, EPC>(g, ct, v, H + c * NS, true, tw);
+        srcs[c] = Ssrc + c * NS;
+        dsts[c] = H + c * NS;
     }
+    col_load<T, EPC, D>(g, ct, srcs, false, twm, v);
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) v[c][e] = scale * v[c][e];
+    col_store<T, EPC, D>(g, ct, v, dsts, true, twm);
 }
 
 // Initialise the scalars of a solve on the device (no host round trip).  With

@@ -150,6 +150,19 @@ ColLaunch col_launch(int nx, int ny) {
     return L;
 }
 
+// LDS bytes of a row / column kernel transforming NF fields at a time (data,
+// then the staged twiddle table when the transform length allows it).
+inline int twl_entries(int M) { return (M <= TWL_MAX && M >= 4) ? M : 0; }
+template <typename T>
+size_t row_lds_bytes(const RowGeom& g, int NF) {
+    return (size_t)(row_lds_data(g, NF) + twl_entries(g.M)) * sizeof(cpx<T>);
+}
+template <typename T>
+size_t col_lds_bytes(const ColGeom& g, int NF) {
+    return (size_t)(col_lds_data(g, NF) + twl_entries(g.ny)) * sizeof(cpx<T>);
+}
+constexpr size_t LDS_MULTI_MAX = 96 * 1024;  // above this, row kernels transform fields one by one
+
 inline int flat_blocks(size_t n, int per = 256, int cap = 1024) {
     size_t b = (n + per - 1) / per;
     if (b < 1) b = 1;
@@ -210,17 +223,20 @@ sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, st
             s.p[i] = src[f0 + i];
             t.p[i] = dst[f0 + i];
         }
-        if (L.epc == 4) {
-            auto k = k_rows_fwd<T, Tin, 4>;
-            HIPCHK(ctx, allow_lds(k, L.lds));
-            hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, s, t,
-                               twiddles<T>(ctx), scale);
-        } else {
-            auto k = k_rows_fwd<T, Tin, 8>;
-            HIPCHK(ctx, allow_lds(k, L.lds));
-            hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, s, t,
-                               twiddles<T>(ctx), scale);
-        }
+        const bool multi = row_lds_bytes<T>(L.g, 3) <= LDS_MULTI_MAX;
+        const size_t lds = row_lds_bytes<T>(L.g, multi ? 3 : 1);
+        auto launch = [&](auto k) -> sgn_status {
+            HIPCHK(ctx, allow_lds(k, lds));
+            hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, s, t, twiddles<T>(ctx),
+                               scale);
+            return SGN_OK;
+        };
+        sgn_status st;
+        if (L.epc == 4)
+            st = multi ? launch(k_rows_fwd<T, Tin, 4, 3>) : launch(k_rows_fwd<T, Tin, 4, 1>);
+        else
+            st = multi ? launch(k_rows_fwd<T, Tin, 8, 3>) : launch(k_rows_fwd<T, Tin, 8, 1>);
+        if (st != SGN_OK) return st;
         CHECK_LAUNCH(ctx);
     }
     return SGN_OK;
@@ -239,17 +255,20 @@ sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src,
             s.p[i] = src[f0 + i];
             t.p[i] = dst[f0 + i];
         }
-        if (L.epc == 4) {
-            auto k = k_rows_inv<T, Tout, 4>;
-            HIPCHK(ctx, allow_lds(k, L.lds));
-            hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, s, t,
-                               twiddles<T>(ctx), scale, acc);
-        } else {
-            auto k = k_rows_inv<T, Tout, 8>;
-            HIPCHK(ctx, allow_lds(k, L.lds));
-            hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, s, t,
-                               twiddles<T>(ctx), scale, acc);
-        }
+        const bool multi = row_lds_bytes<T>(L.g, 3) <= LDS_MULTI_MAX;
+        const size_t lds = row_lds_bytes<T>(L.g, multi ? 3 : 1);
+        auto launch = [&](auto k) -> sgn_status {
+            HIPCHK(ctx, allow_lds(k, lds));
+            hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, s, t, twiddles<T>(ctx),
+                               scale, acc);
+            return SGN_OK;
+        };
+        sgn_status st;
+        if (L.epc == 4)
+            st = multi ? launch(k_rows_inv<T, Tout, 4, 3>) : launch(k_rows_inv<T, Tout, 4, 1>);
+        else
+            st = multi ? launch(k_rows_inv<T, Tout, 8, 3>) : launch(k_rows_inv<T, Tout, 8, 1>);
+        if (st != SGN_OK) return st;
         CHECK_LAUNCH(ctx);
     }
     return SGN_OK;
@@ -267,8 +286,9 @@ sgn_status cols_lin_n(sgn_ctx* ctx, const Dims& d, const std::vector<const cpx<T
     for (int i = 0; i < NI; ++i) s.p[i] = src[i];
     for (int i = 0; i < lc.no; ++i) t.p[i] = dst[i];
     auto k = k_cols_lin<T, 4, NI>;
-    HIPCHK(ctx, allow_lds(k, L.lds));
-    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, s, t, lc,
+    const size_t lds = col_lds_bytes<T>(L.g, NI);
+    HIPCHK(ctx, allow_lds(k, lds));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, s, t, lc,
                        twiddles<T>(ctx), (T)d.tpx, (T)d.tpy, scale);
     CHECK_LAUNCH(ctx);
     return SGN_OK;
@@ -398,18 +418,20 @@ struct PcgLaunch {
 
 template <typename T, int D>
 sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc) {
-    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C1);
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C1 + (sizeof(T) == 4 ? 6 : 0));
     auto& L = P.cl;
     if (mode == C1_COPY) {
         auto k = k_pcg_c1<T, 4, D, C1_COPY>;
-        HIPCHK(P.ctx, allow_lds(k, L.lds));
-        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
+        const size_t lds = col_lds_bytes<T>(L.g, D + 1);
+        HIPCHK(P.ctx, allow_lds(k, lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
                            P.sc, (const double*)P.partials, P.cl.g.nblocks, P.b.rh, P.b.ph, xsrc, P.b.H, P.d.NS,
                            (T)P.d.tpx, (T)P.d.tpy);
     } else {
         auto k = k_pcg_c1<T, 4, D, C1_UPDATE>;
-        HIPCHK(P.ctx, allow_lds(k, L.lds));
-        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
+        const size_t lds = col_lds_bytes<T>(L.g, D + 1);
+        HIPCHK(P.ctx, allow_lds(k, lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
                            P.sc, (const double*)P.partials, P.cl.g.nblocks, P.b.rh, P.b.ph, xsrc, P.b.H, P.d.NS,
                            (T)P.d.tpx, (T)P.d.tpy);
     }
@@ -419,20 +441,23 @@ sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc) {
 
 template <typename T, int D>
 sgn_status pcg_r1(PcgLaunch<T, D>& P, bool curvature = false) {
-    ProfScope ps(P.ctx, SGN_KERNEL_PCG_R1);
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_R1 + (sizeof(T) == 4 ? 6 : 0));
     double* part = curvature ? P.partials : nullptr;
     auto& L = P.rl;
-    if (L.epc == 4) {
-        auto k = k_pcg_r1<T, 4, D>;
-        HIPCHK(P.ctx, allow_lds(k, L.lds));
-        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, P.b.H, P.d.NS, P.eta, P.gh, part);
-    } else {
-        auto k = k_pcg_r1<T, 8, D>;
-        HIPCHK(P.ctx, allow_lds(k, L.lds));
-        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, P.b.H, P.d.NS, P.eta, P.gh, part);
-    }
+    const bool seq = row_lds_bytes<T>(L.g, D + 1) > LDS_MULTI_MAX;
+    const size_t lds = row_lds_bytes<T>(L.g, seq ? 1 : D + 1);
+    auto launch = [&](auto k) -> sgn_status {
+        HIPCHK(P.ctx, allow_lds(k, lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, L.g, twiddles<T>(P.ctx), P.sc,
+                           P.b.H, P.d.NS, P.eta, P.gh, part);
+        return SGN_OK;
+    };
+    sgn_status st;
+    if (L.epc == 4)
+        st = seq ? launch(k_pcg_r1<T, 4, D, true>) : launch(k_pcg_r1<T, 4, D, false>);
+    else
+        st = seq ? launch(k_pcg_r1<T, 8, D, true>) : launch(k_pcg_r1<T, 8, D, false>);
+    if (st != SGN_OK) return st;
     CHECK_LAUNCH(P.ctx);
     return SGN_OK;
 }
@@ -441,8 +466,9 @@ template <typename T, int D, int MODE>
 sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out) {
     auto& L = P.cl;
     auto k = k_pcg_c2<T, 4, D, MODE>;
-    HIPCHK(P.ctx, allow_lds(k, L.lds));
-    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, P.ctx->stream, L.g, twiddles<T>(P.ctx), P.sc,
+    const size_t lds = col_lds_bytes<T>(L.g, D + 1);
+    HIPCHK(P.ctx, allow_lds(k, lds));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, L.g, twiddles<T>(P.ctx), P.sc,
                        (const cpx<T>*)P.b.H, P.d.NS, P.b.qh, (const cpx<T>*)P.b.ph, P.b.xh, bh, rh_out, P.partials,
                        P.rl.g.nblocks, (T)P.d.tpx, (T)P.d.tpy);
     CHECK_LAUNCH(P.ctx);
@@ -451,7 +477,7 @@ sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out) {
 
 template <typename T, int D>
 sgn_status pcg_c2(PcgLaunch<T, D>& P, int mode, const cpx<T>* bh, cpx<T>* rh_out) {
-    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C2);
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C2 + (sizeof(T) == 4 ? 6 : 0));
     if (mode == C2_STORE) return pcg_c2_mode<T, D, C2_STORE>(P, bh, rh_out);
     if (mode == C2_RESID) return pcg_c2_mode<T, D, C2_RESID>(P, bh, rh_out);
     return pcg_c2_mode<T, D, C2_UPDATE>(P, nullptr, P.b.rh);
@@ -460,7 +486,7 @@ sgn_status pcg_c2(PcgLaunch<T, D>& P, int mode, const cpx<T>* bh, cpx<T>* rh_out
 // Initial residual pass: partials of r.z, r.r on the column grid.
 template <typename T, int D>
 sgn_status pcg_init(PcgLaunch<T, D>& P) {
-    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C3);
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_INIT + (sizeof(T) == 4 ? 6 : 0));
     hipLaunchKernelGGL((k_pcg_init<T, D>), dim3(P.cl.g.nblocks), dim3(256), 0, P.ctx->stream, P.d.nx, P.d.ny,
                        P.d.NS, P.sc, P.b.xh, P.b.rh, P.partials, (T)P.d.tpx, (T)P.d.tpy);
     CHECK_LAUNCH(P.ctx);
@@ -555,8 +581,8 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     if ((s = rows_fwd<double, double>(ctx, d, bsrc, hdst)) != SGN_OK) return s;
     {
         auto k = k_setup_b<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, P.cl.lds));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g,
+        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g,
                            ctx->tw64, (const cpx<double>*)P.b.H, d.NS, (cpx<double>*)nullptr, P.b.rh, P.partials);
         hipLaunchKernelGGL(k_finish_bb, dim3(1), dim3(256), 0, ctx->stream, P.sc, (const double*)P.partials,
                            P.cl.g.nblocks);
@@ -568,8 +594,8 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
         for (int c = 0; c < D; ++c) usrc.push_back(u + c * d.N);
         if ((s = rows_fwd<double, double>(ctx, d, usrc, hdst)) != SGN_OK) return s;
         auto k = k_cols_to_S<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, P.cl.lds));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g, ctx->tw64,
+        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
                            (const cpx<double>*)P.b.H, d.NS, P.b.xh);
         CHECK_LAUNCH(ctx);
         if ((s = pcg_c1<double, D>(P, C1_COPY, P.b.xh)) != SGN_OK) return s;
@@ -585,8 +611,8 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     // u = IFFT(x_hat)
     {
         auto k = k_cols_from_S<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, P.cl.lds));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g, ctx->tw64,
+        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
                            (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
         CHECK_LAUNCH(ctx);
         std::vector<const cpx<double>*> hs;
@@ -663,8 +689,8 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     if ((s = rows_fwd<double, double>(ctx, d, bsrc, hdst)) != SGN_OK) return s;
     {
         auto k = k_setup_b<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, P.cl.lds));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g,
+        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g,
                            ctx->tw64, (const cpx<double>*)P.b.H, d.NS, P.b.bh, P.b.rh, P.partials);
         hipLaunchKernelGGL(k_finish_bb, dim3(1), dim3(256), 0, ctx->stream, P.sc, (const double*)P.partials,
                            P.cl.g.nblocks);
@@ -675,8 +701,8 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
         for (int c = 0; c < D; ++c) usrc.push_back(u + c * d.N);
         if ((s = rows_fwd<double, double>(ctx, d, usrc, hdst)) != SGN_OK) return s;
         auto k = k_cols_to_S<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, P.cl.lds));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g, ctx->tw64,
+        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
                            (const cpx<double>*)P.b.H, d.NS, P.b.xh);
         CHECK_LAUNCH(ctx);
         if ((s = pcg_c1<double, D>(P, C1_COPY, P.b.xh)) != SGN_OK) return s;
@@ -721,8 +747,8 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
     {
         auto k = k_cols_from_S<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, P.cl.lds));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g, ctx->tw64,
+        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
                            (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
         CHECK_LAUNCH(ctx);
         std::vector<const cpx<double>*> hs;
@@ -795,8 +821,8 @@ sgn_status to_S_d(sgn_ctx* ctx, const Dims& d, const double* f, cpx<double>* H, 
     if ((s = rows_fwd<double, double>(ctx, d, src, hd)) != SGN_OK) return s;
     ColLaunch L = col_launch<double>(d.nx, d.ny);
     auto k = k_cols_to_S<double, 4, D>;
-    HIPCHK(ctx, allow_lds(k, L.lds));
-    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, ctx->tw64,
+    HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(L.g, D)));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), col_lds_bytes<double>(L.g, D), ctx->stream, L.g, ctx->tw64,
                        (const cpx<double>*)H, d.NS, Sd);
     CHECK_LAUNCH(ctx);
     return SGN_OK;
@@ -806,8 +832,8 @@ template <int D>
 sgn_status from_S_d(sgn_ctx* ctx, const Dims& d, const cpx<double>* Ssrc, cpx<double>* H, double* f) {
     ColLaunch L = col_launch<double>(d.nx, d.ny);
     auto k = k_cols_from_S<double, 4, D>;
-    HIPCHK(ctx, allow_lds(k, L.lds));
-    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, ctx->tw64, Ssrc, d.NS, H,
+    HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(L.g, D)));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), col_lds_bytes<double>(L.g, D), ctx->stream, L.g, ctx->tw64, Ssrc, d.NS, H,
                        d.inv_n);
     CHECK_LAUNCH(ctx);
     std::vector<const cpx<double>*> hs;
@@ -848,8 +874,8 @@ sgn_status apply_G(sgn_ctx* ctx, const Dims& d, const double* eta, const double*
     if ((s = rows_fwd<double, double>(ctx, d, usrc, hdst)) != SGN_OK) return s;
     {
         auto k = k_cols_to_S<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, P.cl.lds));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), P.cl.lds, ctx->stream, P.cl.g, ctx->tw64,
+        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
                            (const cpx<double>*)P.b.H, d.NS, P.b.xh);
         CHECK_LAUNCH(ctx);
     }
@@ -889,8 +915,8 @@ sgn_status precond_apply(sgn_ctx* ctx, const Dims& d, double sig, double alp, co
         b.p[c] = H + c * d.NS;
     }
     auto k = k_cols_precond<double, 4, D>;
-    HIPCHK(ctx, allow_lds(k, L.lds));
-    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), L.lds, ctx->stream, L.g, a, b, ctx->tw64, d.tpx, d.tpy,
+    HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(L.g, D)));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), col_lds_bytes<double>(L.g, D), ctx->stream, L.g, a, b, ctx->tw64, d.tpx, d.tpy,
                        sig, alp, d.inv_n);
     CHECK_LAUNCH(ctx);
     return rows_inv<double, double>(ctx, d, hs, od);
@@ -1342,22 +1368,25 @@ sgn_status sgn_create(sgn_ctx** out, int device, void* hip_stream) {
         delete ctx;
         return SGN_EDEVICE;
     }
-    // twiddle tables exp(-2 pi i k / TW), k < TW, from long double cos/sin
-    std::vector<cpx<double>> t64(TW_SIZE);
-    std::vector<cpx<float>> t32(TW_SIZE);
+    // twiddle tables: for every power of two L <= TW_SIZE the roots W_L^j =
+    // exp(-2 pi i j / L), j < L, at offset L - 1, from long double cos/sin
+    std::vector<cpx<double>> t64(TW_ALL);
+    std::vector<cpx<float>> t32(TW_ALL);
     const long double pi2 = 6.283185307179586476925286766559005768L;
-    for (int k = 0; k < TW_SIZE; ++k) {
-        const long double a = pi2 * (long double)k / (long double)TW_SIZE;
-        const long double c = cosl(a), sn = -sinl(a);
-        t64[k] = cpx<double>{(double)c, (double)sn};
-        t32[k] = cpx<float>{(float)c, (float)sn};
+    for (int L = 1; L <= TW_SIZE; L <<= 1) {
+        for (int j = 0; j < L; ++j) {
+            const long double a = pi2 * (long double)j / (long double)L;
+            const long double c = cosl(a), sn = -sinl(a);
+            t64[L - 1 + j] = cpx<double>{(double)c, (double)sn};
+            t32[L - 1 + j] = cpx<float>{(float)c, (float)sn};
+        }
     }
-    bool ok = hipMalloc(&ctx->tw64, TW_SIZE * sizeof(cpx<double>)) == hipSuccess &&
-              hipMalloc(&ctx->tw32, TW_SIZE * sizeof(cpx<float>)) == hipSuccess &&
+    bool ok = hipMalloc(&ctx->tw64, TW_ALL * sizeof(cpx<double>)) == hipSuccess &&
+              hipMalloc(&ctx->tw32, TW_ALL * sizeof(cpx<float>)) == hipSuccess &&
               hipHostMalloc((void**)&ctx->hscal, sizeof(SolveScal), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc((void**)&ctx->hflag, 64, hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipMemcpy(ctx->tw64, t64.data(), TW_SIZE * sizeof(cpx<double>), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(ctx->tw32, t32.data(), TW_SIZE * sizeof(cpx<float>), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(ctx->tw64, t64.data(), TW_ALL * sizeof(cpx<double>), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(ctx->tw32, t32.data(), TW_ALL * sizeof(cpx<float>), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
         sgn_destroy(ctx);
         return SGN_ENOMEM;

@@ -212,7 +212,8 @@ class Context:
         return ws
 
     # -- kernel timing ---------------------------------------------------------
-    KERNEL_KINDS = ("pcg_c1", "pcg_r1", "pcg_c2", "pcg_c3", "rows", "cols")
+    KERNEL_KINDS = ("pcg_c1", "pcg_r1", "pcg_c2", "pcg_init", "rows", "cols",
+                    "pcg_c1_f32", "pcg_r1_f32", "pcg_c2_f32", "pcg_init_f32")
 
     def profile_begin(self):
         self._sync_stream()
