@@ -27,6 +27,18 @@ struct sgn_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_next = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_marks;
+    // PCG iteration chunks captured as HIP graphs on a private stream and replayed
+    // on `stream`; keyed by everything the captured launches depend on
+    struct GraphEntry {
+        std::vector<const void*> key;
+        int chunk;
+        hipGraphExec_t exec;  // null: seen once (ran eagerly), capture on the next use
+    };
+    hipStream_t cap_stream = nullptr;
+    std::vector<GraphEntry> graphs;
+    bool use_graphs = true;
+    int last_iters[2] = {0, 0};   // iterations of the previous solve, FP64 / FP32 loops
+    bool stage = false;           // solving inside a stepper: skip the final scalar readback
 };
 
 namespace {
@@ -500,13 +512,6 @@ sgn_status read_scal(sgn_ctx* ctx, const SolveScal* sc) {
     return SGN_OK;
 }
 
-sgn_status read_done(sgn_ctx* ctx, const SolveScal* sc, int* done) {
-    HIPCHK(ctx, hipMemcpyAsync(ctx->hflag, &sc->done, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    *done = *ctx->hflag;
-    return SGN_OK;
-}
-
 // Initialise a SolveScal on the device (stream-ordered, no host round trip).
 sgn_status init_scal(sgn_ctx* ctx, SolveScal* sc, double tol, int max_iter, double inv_n,
                      const sgn_coeffs* co, int init_bb = 0) {
@@ -525,28 +530,107 @@ sgn_status pcg_check(PcgLaunch<T, D>& P) {
     return SGN_OK;
 }
 
-// Run PCG iterations until the device flag says done.  P.b holds x_hat, r_hat
-// (initialised), the scalars hold rho/bb (after the INIT C3).
+// One chunk of `chunk` PCG iterations followed by the stop test.
 template <typename T, int D>
-sgn_status pcg_loop(PcgLaunch<T, D>& P, int max_iter, int check_every) {
+sgn_status pcg_chunk_eager(PcgLaunch<T, D>& P, int chunk) {
+    for (int c = 0; c < chunk; ++c) {
+        sgn_status s;
+        if ((s = pcg_c1<T, D>(P, C1_UPDATE, nullptr)) != SGN_OK) return s;
+        if ((s = pcg_r1<T, D>(P, true)) != SGN_OK) return s;
+        if ((s = pcg_c2<T, D>(P, C2_UPDATE, nullptr, nullptr)) != SGN_OK) return s;
+    }
+    return pcg_check<T, D>(P);
+}
+
+// The same chunk replayed from a HIP graph (captured on the second use of a
+// configuration; the first use runs eagerly so every launch attribute is set).
+template <typename T, int D>
+sgn_status pcg_chunk(PcgLaunch<T, D>& P, int chunk) {
+    sgn_ctx* ctx = P.ctx;
+    if (!ctx->use_graphs || ctx->prof_on || ctx->cap_stream == nullptr) return pcg_chunk_eager<T, D>(P, chunk);
+    std::vector<const void*> key = {(const void*)(uintptr_t)sizeof(T), (const void*)(uintptr_t)D,
+                                    (const void*)(uintptr_t)P.d.nx, (const void*)(uintptr_t)P.d.ny,
+                                    (const void*)P.sc, (const void*)P.b.H, (const void*)P.b.xh,
+                                    (const void*)P.b.rh, (const void*)P.b.ph, (const void*)P.partials,
+                                    (const void*)P.eta, (const void*)P.gh, (const void*)twiddles<T>(ctx)};
+    for (auto& g : ctx->graphs) {
+        if (g.chunk == chunk && g.key == key) {
+            if (g.exec) {
+                HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
+                return SGN_OK;
+            }
+            // second use: capture
+            hipStream_t user = ctx->stream;
+            ctx->stream = ctx->cap_stream;
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+            sgn_status s = SGN_OK;
+            if (e == hipSuccess) {
+                s = pcg_chunk_eager<T, D>(P, chunk);
+                e = hipStreamEndCapture(ctx->cap_stream, &graph);
+            }
+            ctx->stream = user;
+            if (s != SGN_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return s;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                g.exec = nullptr;
+                ctx->use_graphs = false;   // fall back to eager launches for the context's life
+                return pcg_chunk_eager<T, D>(P, chunk);
+            }
+            HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
+            return SGN_OK;
+        }
+    }
+    if (ctx->graphs.size() >= 64) {
+        if (ctx->graphs.front().exec) (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back({key, chunk, nullptr});
+    return pcg_chunk_eager<T, D>(P, chunk);
+}
+
+// Integer state of a solve after its last readback.
+struct LoopOut {
+    int iter = 0, done = 0, converged = 0, status = 0;
+};
+
+// Read iter, max_iter, done, converged, flat, status of a solve (synchronises the stream).
+sgn_status read_loop(sgn_ctx* ctx, const SolveScal* sc, LoopOut* out) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->hflag, &sc->iter, 6 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    out->iter = ctx->hflag[0];
+    out->done = ctx->hflag[2];
+    out->converged = ctx->hflag[3];
+    out->status = ctx->hflag[5];
+    return SGN_OK;
+}
+
+// Run PCG iterations until the device flag says done.  The first chunk is sized
+// from the previous solve of the same precision (warm-started stage solves need
+// about as many iterations as the one before), later chunks are short, so a
+// solve usually needs one host readback and wastes at most a couple of
+// iterations (which return at once on the device).
+template <typename T, int D>
+sgn_status pcg_loop(PcgLaunch<T, D>& P, int max_iter, int check_every, LoopOut* out) {
     if (check_every < 1) check_every = 1;
+    int& last = P.ctx->last_iters[sizeof(T) == 4 ? 1 : 0];
+    int chunk = last > 0 ? last : check_every;
     int it = 0;
     while (it < max_iter) {
-        const int chunk = std::min(check_every, max_iter - it);
-        for (int c = 0; c < chunk; ++c) {
-            sgn_status s;
-            if ((s = pcg_c1<T, D>(P, C1_UPDATE, nullptr)) != SGN_OK) return s;
-            if ((s = pcg_r1<T, D>(P, true)) != SGN_OK) return s;
-            if ((s = pcg_c2<T, D>(P, C2_UPDATE, nullptr, nullptr)) != SGN_OK) return s;
-        }
+        chunk = std::max(1, std::min(chunk, max_iter - it));
+        sgn_status s = pcg_chunk<T, D>(P, chunk);
+        if (s != SGN_OK) return s;
         it += chunk;
-        int done = 0;
-        sgn_status s = pcg_check<T, D>(P);
-        if (s != SGN_OK) return s;
-        s = read_done(P.ctx, P.sc, &done);
-        if (s != SGN_OK) return s;
-        if (done) break;
+        if ((s = read_loop(P.ctx, P.sc, out)) != SGN_OK) return s;
+        if (out->done) break;
+        chunk = std::min(2, check_every);
     }
+    if (out->iter > 0) last = out->iter;
     return SGN_OK;
 }
 
@@ -607,7 +691,8 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
         CHECK_LAUNCH(ctx);
     }
     if ((s = pcg_init<double, D>(P)) != SGN_OK) return s;
-    if ((s = pcg_loop<double, D>(P, o.max_iter, o.check_every)) != SGN_OK) return s;
+    LoopOut lo;
+    if ((s = pcg_loop<double, D>(P, o.max_iter, o.check_every, &lo)) != SGN_OK) return s;
     // u = IFFT(x_hat)
     {
         auto k = k_cols_from_S<double, 4, D>;
@@ -622,6 +707,16 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
             ud.push_back(u + c * d.N);
         }
         if ((s = rows_inv<double, double>(ctx, d, hs, ud)) != SGN_OK) return s;
+    }
+    if (ctx->stage) {
+        // stepper: iterations and the outcome are known from the loop's readback
+        if (info) {
+            info->iters = lo.iter;
+            info->converged = lo.converged;
+        }
+        if (lo.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
+        if (!lo.converged) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
+        return SGN_OK;
     }
     if ((s = read_scal(ctx, P.sc)) != SGN_OK) return s;
     const SolveScal& h = *ctx->hscal;
@@ -718,11 +813,11 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     int total_inner = 0, outer = 0;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    LoopOut lo;
     for (; outer < max_outer; ++outer) {
-        int done = 0;
         if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
-        if ((s = read_done(ctx, P.sc, &done)) != SGN_OK) return s;
-        if (done) break;
+        if ((s = read_loop(ctx, P.sc, &lo)) != SGN_OK) return s;
+        if (lo.done) break;
         // inner FP32 solve of G dx = r from dx = 0; ||b_inner|| = ||r_outer||
         if ((s = init_scal(ctx, Q.sc, inner_tol, o.max_iter, d.inv_n, nullptr, 1)) != SGN_OK) return s;
         hipLaunchKernelGGL(k_copy_coeffs, dim3(1), dim3(64), 0, ctx->stream, P.sc, Q.sc);
@@ -732,9 +827,9 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
                            (void*)Q.b.xh);
         CHECK_LAUNCH(ctx);
         if ((s = pcg_init<float, D>(Q)) != SGN_OK) return s;
-        if ((s = pcg_loop<float, D>(Q, o.max_iter, o.check_every)) != SGN_OK) return s;
-        if ((s = read_scal(ctx, Q.sc)) != SGN_OK) return s;
-        total_inner += ctx->hscal->iter;
+        LoopOut li;
+        if ((s = pcg_loop<float, D>(Q, o.max_iter, o.check_every, &li)) != SGN_OK) return s;
+        total_inner += li.iter;
         // x_hat += dx_hat; r_hat = b_hat - G x_hat (FP64); stop test
         hipLaunchKernelGGL(k_S_accumulate, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream,
                            (size_t)D * d.NS, (const cpx<float>*)Q.b.xh, P.b.xh);
@@ -758,6 +853,16 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
             ud.push_back(u + c * d.N);
         }
         if ((s = rows_inv<double, double>(ctx, d, hs, ud)) != SGN_OK) return s;
+    }
+    if (ctx->stage && lo.done) {
+        if (info) {
+            info->iters = total_inner;
+            info->outer_iters = outer;
+            info->converged = lo.converged;
+        }
+        if (lo.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
+        if (!lo.converged) return fail(ctx, SGN_ENOCONV, "refinement did not reach the tolerance");
+        return SGN_OK;
     }
     if ((s = read_scal(ctx, P.sc)) != SGN_OK) return s;
     const SolveScal& h = *ctx->hscal;
@@ -1161,7 +1266,9 @@ sgn_status stage_solve(sgn_state* st, const double* eta, const double* U, double
     so.x0_is_guess = 1;
     sgn_solve_info si;
     std::memset(&si, 0, sizeof(si));
+    st->ctx->stage = true;
     sgn_status s = solve_dispatch(st->ctx, st->d, eta, st->gh, U, u, nullptr, st->flat, so, &si, st->ws);
+    st->ctx->stage = false;
     account(acc, si);
     return s;
 }
@@ -1391,6 +1498,9 @@ sgn_status sgn_create(sgn_ctx** out, int device, void* hip_stream) {
         sgn_destroy(ctx);
         return SGN_ENOMEM;
     }
+    if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) ctx->cap_stream = nullptr;
+    const char* ng = getenv("SGN_NO_GRAPHS");
+    if (ng && ng[0] && ng[0] != '0') ctx->use_graphs = false;
     *out = ctx;
     return SGN_OK;
 }
@@ -1403,6 +1513,9 @@ void sgn_destroy(sgn_ctx* ctx) {
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     if (ctx->hflag) (void)hipHostFree(ctx->hflag);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto& g : ctx->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 
