@@ -79,6 +79,18 @@ typedef enum sgn_coeff_kind {
     SGN_COEFF_OPTIMAL = 0,     /* Eq:Optcoeff */
     SGN_COEFF_REPLACEMENT = 1  /* sigma**, alpha** of Remark 4.2 */
 } sgn_coeff_kind;
+/* Initial guesses of the solves inside the steppers (the paper leaves them
+ * open).  Every such solve has a slot (RK4 stages 2, 3, 4, the final RK4
+ * solve, the Adams-Bashforth solve) and a base, the most recent velocity.
+ * PREVIOUS starts from the base.  EXTRAPOLATE records the slot's offset
+ * o_n = solution - base and starts from base + o_{n-1} (one recorded) or
+ * base + 2 o_{n-1} - o_{n-2}; the offsets are cleared when dt changes.  The
+ * guess moves the start of the iteration only: every solve still stops on
+ * its residual. */
+typedef enum sgn_guess {
+    SGN_GUESS_PREVIOUS = 0,
+    SGN_GUESS_EXTRAPOLATE = 1
+} sgn_guess;
 
 typedef struct sgn_solve_opts {
     int32_t method;        /* sgn_method */
@@ -91,6 +103,7 @@ typedef struct sgn_solve_opts {
     int32_t max_outer;     /* mixed mode: refinement steps */
     int32_t check_every;   /* convergence flag read back every this many iterations (>= 1) */
     int32_t coeff_kind;    /* sgn_coeff_kind, used when coefficients are computed */
+    int32_t guess;         /* sgn_guess, read by the steppers only */
 } sgn_solve_opts;
 
 typedef struct sgn_solve_info {
@@ -179,10 +192,11 @@ sgn_status sgn_precond_solve(sgn_ctx *ctx, const sgn_grid *grid, const sgn_coeff
                              const double *d_rhs, double *d_out, void *d_ws);
 
 /* Solve G_{eta,h} u = rhs by PCG preconditioned with A (section 3.2,
- * Eq:PCGLinSyst) or by right-preconditioned GMRES.  coeffs = NULL computes
- * the coefficients from eta (opts->coeff_kind).  On SGN_ENOCONV d_u_inout
- * holds the last iterate and *info is filled.  opts = NULL uses PCG, FP64,
- * tol 1e-12, max_iter 1000, zero initial guess. */
+ * Eq:PCGLinSyst).  method = SGN_GMRES returns SGN_EUNSUPPORTED (GMRES of
+ * section 3.2 is not built on the device).  coeffs = NULL computes the
+ * coefficients from eta (opts->coeff_kind).  On SGN_ENOCONV d_u_inout holds
+ * the last iterate and *info is filled.  opts = NULL uses PCG, FP64, tol
+ * 1e-12, max_iter 1000, zero initial guess. */
 sgn_status sgn_krylov_solve(sgn_ctx *ctx, const sgn_grid *grid, const double *d_eta,
                             const double *d_grad_h, const double *d_rhs, double *d_u_inout,
                             const sgn_coeffs *coeffs, const sgn_solve_opts *opts,
@@ -212,8 +226,9 @@ sgn_status sgn_state_create(sgn_ctx *ctx, const sgn_grid *grid, const double *d_
 void sgn_state_destroy(sgn_state *state);
 
 /* nsteps steps of classical RK4 (Eq:ERK) with one Krylov solve per stage
- * (4 per step).  Each solve starts from the most recent velocity and builds
- * A from the current eta. */
+ * (4 per step).  Each solve starts from the guess opts->guess selects (opts =
+ * NULL: SGN_GUESS_EXTRAPOLATE) and builds A from the current eta.  The guess
+ * history stays with the state across calls with the same dt. */
 sgn_status sgn_step_rk4(sgn_ctx *ctx, sgn_state *state, double dt, int32_t nsteps,
                         const sgn_solve_opts *opts, sgn_step_info *info);
 

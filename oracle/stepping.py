@@ -7,8 +7,10 @@ rk4_step  : classical RK4 (Eq:ERK) with one PCG solve per stage.  Readings of
             prints u_n), the stage constraint is G u^(i) = U^(i) (the text
             prints U^(j)), and the final update advances U (the text prints u),
             after which u_{n+1} is solved for.  Stage 1 reuses u_n, so a step
-            costs 4 solves.  Warm start (reading): each solve starts from the
-            most recent velocity.
+            costs 4 solves.  Initial guesses (reading: the paper leaves them
+            open) come from GuessHistory: the most recent velocity, or that
+            velocity plus the same solve's offset from earlier steps,
+            extrapolated in time.
 ab_step   : Adams-Bashforth of order s = 2, 3, 4 (Eq:AB, Table LMMCoeffs), one
             PCG solve per step; the first s-1 steps are RK4 steps with the same
             dt (reading: the paper does not state a start-up).
@@ -42,6 +44,54 @@ SBDF2_A = (0.5, -2.0, 1.5)
 SBDF2_B = (-1.0, 2.0)
 
 
+class GuessHistory:
+    """Initial guesses of the constraint solves inside the steppers.
+
+    Each solve has a slot (RK4 stages 2, 3, 4, the final RK4 solve, the
+    Adams-Bashforth solve) and a base: the most recent velocity when the solve
+    starts.  mode 'previous' starts every solve from its base (plain warm
+    start).  mode 'extrapolate' records the slot's offset o_n = solution - base
+    after every solve and starts the next solve of that slot from
+    base + o_{n-1} (one offset recorded) or base + 2 o_{n-1} - o_{n-2} (two or
+    more), the value at the next step of the polynomial through the recorded
+    offsets.  The offsets scale with the step, so a change of dt clears them.
+    A guess only changes where the Krylov iteration starts, not the solution
+    it converges to (the stop test is on the residual)."""
+
+    SLOTS = ("rk2", "rk3", "rk4", "rk_final", "ab")
+
+    def __init__(self, mode: str = "extrapolate"):
+        if mode not in ("previous", "extrapolate"):
+            raise ValueError("mode must be 'previous' or 'extrapolate'")
+        self.mode = mode
+        self.dt = None
+        self.offsets = {k: [] for k in self.SLOTS}
+
+    def prepare(self, dt):
+        if self.dt != dt:
+            self.clear()
+            self.dt = dt
+
+    def clear(self, slot=None):
+        for k in ([slot] if slot else self.SLOTS):
+            self.offsets[k] = []
+
+    def guess(self, slot, base):
+        o = self.offsets[slot]
+        if self.mode == "previous" or not o:
+            return base
+        if len(o) == 1:
+            return base + o[-1]
+        return base + (2.0 * o[-1] - o[-2])
+
+    def record(self, slot, base, solution):
+        if self.mode == "previous":
+            return
+        o = self.offsets[slot]
+        o.append(solution - base)
+        del o[:-2]
+
+
 @dataclass
 class Problem:
     g: object
@@ -51,11 +101,12 @@ class Problem:
     tol: float = 1e-12
     max_iter: int = 1000
     iters: list = field(default_factory=list)
+    hist: GuessHistory = field(default_factory=GuessHistory)
 
     @classmethod
-    def from_h(cls, g, h, tol=1e-12, max_iter=1000):
+    def from_h(cls, g, h, tol=1e-12, max_iter=1000, guess="extrapolate"):
         gh, fl = op.bathy_gradient(h, g)
-        return cls(g, np.asarray(h, dtype=np.float64), gh, fl, tol, max_iter)
+        return cls(g, np.asarray(h, dtype=np.float64), gh, fl, tol, max_iter, hist=GuessHistory(guess))
 
     def f(self, eta, u):
         return rhs(eta, u, self.h, self.grad_h, self.g)
@@ -74,8 +125,15 @@ class Problem:
         self.iters.append(it)
         return u
 
+    def stage_solve(self, slot, eta, U, base):
+        """Solve G u = U for one stepper slot, starting from the slot's guess."""
+        u = self.solve(eta, U, self.hist.guess(slot, base))
+        self.hist.record(slot, base, u)
+        return u
+
 
 def rk4_step(pb: Problem, eta, U, u, dt):
+    pb.hist.prepare(dt)
     fe, fU = [], []
     u_last = u
     for i in range(4):
@@ -88,14 +146,14 @@ def rk4_step(pb: Problem, eta, U, u, dt):
                 if aij != 0.0:
                     eta_i = eta_i + dt * aij * fe[j]
                     U_i = U_i + dt * aij * fU[j]
-            u_i = pb.solve(eta_i, U_i, u_last)
+            u_i = pb.stage_solve(GuessHistory.SLOTS[i - 1], eta_i, U_i, u_last)
             u_last = u_i
         e_t, U_t = pb.f(eta_i, u_i)
         fe.append(e_t)
         fU.append(U_t)
     eta_new = eta + dt * (RK4_B[0] * fe[0] + RK4_B[1] * fe[1] + RK4_B[2] * fe[2] + RK4_B[3] * fe[3])
     U_new = U + dt * (RK4_B[0] * fU[0] + RK4_B[1] * fU[1] + RK4_B[2] * fU[2] + RK4_B[3] * fU[3])
-    u_new = pb.solve(eta_new, U_new, u_last)
+    u_new = pb.stage_solve("rk_final", eta_new, U_new, u_last)
     return eta_new, U_new, u_new
 
 
@@ -108,6 +166,8 @@ def run_rk4(pb: Problem, eta, U, u, dt, nsteps):
 def run_ab(pb: Problem, order, eta, U, u, dt, nsteps):
     """AB_s for nsteps steps in total (the first s-1 are RK4 start-up steps)."""
     b = AB_B[order]
+    pb.hist.prepare(dt)
+    pb.hist.clear("ab")
     hist = []                                 # (f_eta, f_U) at levels n .. n+s-1
     done = 0
     while done < nsteps:
@@ -123,7 +183,7 @@ def run_ab(pb: Problem, order, eta, U, u, dt, nsteps):
         for j in range(order):
             eta_new = eta_new + dt * b[j] * hist[j][0]
             U_new = U_new + dt * b[j] * hist[j][1]
-        u = pb.solve(eta_new, U_new, u)
+        u = pb.stage_solve("ab", eta_new, U_new, u)
         eta, U = eta_new, U_new
         done += 1
     return eta, U, u

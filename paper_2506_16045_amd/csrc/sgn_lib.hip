@@ -11,6 +11,9 @@
 
 using namespace sgn;
 
+// Stepper solves that keep an initial-guess history (sgn_guess).
+enum { GUESS_RK2 = 0, GUESS_RK3, GUESS_RK4, GUESS_RK_FINAL, GUESS_AB, GUESS_SLOTS };
+
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
@@ -37,8 +40,11 @@ struct sgn_ctx {
     hipStream_t cap_stream = nullptr;
     std::vector<GraphEntry> graphs;
     bool use_graphs = true;
-    int last_iters[2] = {0, 0};   // iterations of the previous solve, FP64 / FP32 loops
+    // iterations of the previous solve per precision (FP64 / FP32 loop) and
+    // stepper slot (last entry: solves outside a stepper)
+    int last_iters[2][GUESS_SLOTS + 1] = {};
     bool stage = false;           // solving inside a stepper: skip the final scalar readback
+    int slot = GUESS_SLOTS;       // stepper slot of the running solve
 };
 
 namespace {
@@ -618,7 +624,7 @@ sgn_status read_loop(sgn_ctx* ctx, const SolveScal* sc, LoopOut* out) {
 template <typename T, int D>
 sgn_status pcg_loop(PcgLaunch<T, D>& P, int max_iter, int check_every, LoopOut* out) {
     if (check_every < 1) check_every = 1;
-    int& last = P.ctx->last_iters[sizeof(T) == 4 ? 1 : 0];
+    int& last = P.ctx->last_iters[sizeof(T) == 4 ? 1 : 0][P.ctx->slot];
     int chunk = last > 0 ? last : check_every;
     int it = 0;
     while (it < max_iter) {
@@ -894,6 +900,7 @@ sgn_solve_opts default_opts() {
     o.max_outer = 20;
     o.check_every = 8;
     o.coeff_kind = SGN_COEFF_OPTIMAL;
+    o.guess = SGN_GUESS_EXTRAPOLATE;
     return o;
 }
 
@@ -1180,6 +1187,8 @@ struct StateBufs {
     double *eta_s, *U_s, *u_s;              // RK4 stage values
     double *eta_prev, *U_prev, *fe_prev, *fU_prev, *tmp_e, *tmp_U;  // SBDF2 history
     cpx<double>*R_prev, *R_cur, *uh, *Uh, *Hs;                        // SBDF2 spectral
+    double* gx_off[GUESS_SLOTS][2];  // recorded offsets of each stepper slot (ring of two)
+    double* gx_base;                 // base velocity of the running solve
 };
 
 size_t carve_state(Carve& cv, const Dims& d, StateBufs* b) {
@@ -1205,6 +1214,9 @@ size_t carve_state(Carve& cv, const Dims& d, StateBufs* b) {
     t.uh = cv.take<cpx<double>>(DS);
     t.Uh = cv.take<cpx<double>>(DS);
     t.Hs = cv.take<cpx<double>>((size_t)(d.D + 1) * d.NS);
+    for (int k = 0; k < GUESS_SLOTS; ++k)
+        for (int l = 0; l < 2; ++l) t.gx_off[k][l] = cv.take<double>(DN);
+    t.gx_base = cv.take<double>(DN);
     if (b) *b = t;
     return cv.off;
 }
@@ -1229,6 +1241,11 @@ struct sgn_state {
     int ab_head;    // next ring slot
     double hist_dt;
     double sb_sig, sb_alp;
+    // initial-guess history: offsets recorded per slot, newest in gx_head
+    int gx_mode;
+    double gx_dt;
+    int gx_count[GUESS_SLOTS];
+    int gx_head[GUESS_SLOTS];
 };
 
 namespace {
@@ -1252,6 +1269,15 @@ sgn_status lincomb(sgn_ctx* ctx, size_t n, const double* base, double dt, std::v
     return SGN_OK;
 }
 
+// Start of a stepping call: the guess history holds offsets for this dt and mode.
+void guess_prepare(sgn_state* st, const sgn_solve_opts& o, double dt) {
+    if (st->gx_mode != o.guess || st->gx_dt != dt) {
+        st->gx_mode = o.guess;
+        st->gx_dt = dt;
+        for (int k = 0; k < GUESS_SLOTS; ++k) st->gx_count[k] = 0;
+    }
+}
+
 void account(sgn_step_info* acc, const sgn_solve_info& si) {
     acc->solves += 1;
     acc->iters += si.iters;
@@ -1259,18 +1285,47 @@ void account(sgn_step_info* acc, const sgn_solve_info& si) {
     if (!si.converged) acc->converged = 0;
 }
 
-// G_{eta,h} u = U from the guess in u; A built from the current eta.
-sgn_status stage_solve(sgn_state* st, const double* eta, const double* U, double* u, const sgn_solve_opts& o,
-                       sgn_step_info* acc) {
+// G_{eta,h} u = U for stepper slot `slot`; u holds the base velocity on entry.
+// With extrapolated guesses the solve starts from base + o_{n-1} or
+// base + 2 o_{n-1} - o_{n-2} and records o_n = u - base afterwards.  A is
+// built from the current eta.
+sgn_status stage_solve(sgn_state* st, int slot, const double* eta, const double* U, double* u,
+                       const sgn_solve_opts& o, sgn_step_info* acc) {
+    sgn_ctx* ctx = st->ctx;
+    StateBufs& b = st->b;
+    const size_t DN = (size_t)st->d.D * st->d.N;
+    const bool ex = o.guess == SGN_GUESS_EXTRAPOLATE;
+    sgn_status s;
+    int& cnt = st->gx_count[slot];
+    int& head = st->gx_head[slot];
+    if (ex) {
+        if ((s = copy_d(ctx, b.gx_base, u, DN)) != SGN_OK) return s;
+        if (cnt == 1) {
+            if ((s = lincomb(ctx, DN, b.gx_base, 1.0, {b.gx_off[slot][head]}, {1.0}, u)) != SGN_OK) return s;
+        } else if (cnt >= 2) {
+            if ((s = lincomb(ctx, DN, b.gx_base, 1.0, {b.gx_off[slot][head], b.gx_off[slot][head ^ 1]}, {2.0, -1.0},
+                             u)) != SGN_OK)
+                return s;
+        }
+    }
     sgn_solve_opts so = o;
     so.x0_is_guess = 1;
     sgn_solve_info si;
     std::memset(&si, 0, sizeof(si));
-    st->ctx->stage = true;
-    sgn_status s = solve_dispatch(st->ctx, st->d, eta, st->gh, U, u, nullptr, st->flat, so, &si, st->ws);
-    st->ctx->stage = false;
+    ctx->stage = true;
+    ctx->slot = slot;
+    s = solve_dispatch(ctx, st->d, eta, st->gh, U, u, nullptr, st->flat, so, &si, st->ws);
+    ctx->stage = false;
+    ctx->slot = GUESS_SLOTS;
     account(acc, si);
-    return s;
+    if (s != SGN_OK) return s;
+    if (ex) {
+        const int nh = cnt == 0 ? head : head ^ 1;
+        if ((s = lincomb(ctx, DN, u, 1.0, {b.gx_base}, {-1.0}, b.gx_off[slot][nh])) != SGN_OK) return s;
+        head = nh;
+        if (cnt < 2) cnt += 1;
+    }
+    return SGN_OK;
 }
 
 // One RK4 step (Eq:ERK): stage i uses eta_n + dt a_i f^(i-1), U_n + dt a_i f^(i-1),
@@ -1291,7 +1346,7 @@ sgn_status rk4_one(sgn_state* st, double dt, const sgn_solve_opts& o, sgn_step_i
     for (int i = 1; i < 4; ++i) {
         if ((s = lincomb(ctx, N, st->eta, dt, {b.rk_fe[i - 1]}, {a[i - 1]}, b.eta_s)) != SGN_OK) return s;
         if ((s = lincomb(ctx, DN, st->U, dt, {b.rk_fU[i - 1]}, {a[i - 1]}, b.U_s)) != SGN_OK) return s;
-        if ((s = stage_solve(st, b.eta_s, b.U_s, b.u_s, o, acc)) != SGN_OK) return s;
+        if ((s = stage_solve(st, GUESS_RK2 + i - 1, b.eta_s, b.U_s, b.u_s, o, acc)) != SGN_OK) return s;
         if ((s = rhs_dispatch(ctx, d, b.eta_s, st->gh, b.u_s, b.rk_fe[i], b.rk_fU[i], st->ws)) != SGN_OK) return s;
     }
     if ((s = lincomb(ctx, N, st->eta, dt, {b.rk_fe[0], b.rk_fe[1], b.rk_fe[2], b.rk_fe[3]}, {w[0], w[1], w[2], w[3]},
@@ -1301,7 +1356,7 @@ sgn_status rk4_one(sgn_state* st, double dt, const sgn_solve_opts& o, sgn_step_i
                      st->U)) != SGN_OK)
         return s;
     if ((s = copy_d(ctx, st->u, b.u_s, DN)) != SGN_OK) return s;
-    if ((s = stage_solve(st, st->eta, st->U, st->u, o, acc)) != SGN_OK) return s;
+    if ((s = stage_solve(st, GUESS_RK_FINAL, st->eta, st->U, st->u, o, acc)) != SGN_OK) return s;
     st->t += dt;
     st->steps += 1;
     return SGN_OK;
@@ -1709,6 +1764,8 @@ sgn_status sgn_state_create(sgn_ctx* ctx, const sgn_grid* grid, const double* h,
     st->t = 0.0;
     st->steps = 0;
     st->kind = 0;
+    st->gx_mode = -1;   // the first stepping call sets mode and dt and clears the history
+    st->gx_dt = 0.0;
     *out = st;
     return SGN_OK;
 }
@@ -1720,6 +1777,8 @@ sgn_status sgn_step_rk4(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nsteps, 
     if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
     if (nsteps < 0 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad step arguments");
     const sgn_solve_opts o = opts ? *opts : default_opts();
+    if (o.guess != SGN_GUESS_PREVIOUS && o.guess != SGN_GUESS_EXTRAPOLATE) return fail(ctx, SGN_EINVAL, "bad guess");
+    guess_prepare(st, o, dt);
     sgn_step_info acc;
     info_init(&acc);
     st->kind = 0;  // a multistep history does not survive other steps
@@ -1734,6 +1793,8 @@ sgn_status sgn_step_ab(sgn_ctx* ctx, sgn_state* st, int32_t order, double dt, in
     if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
     if (nsteps < 0 || order < 2 || order > 4 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad AB arguments");
     const sgn_solve_opts o = opts ? *opts : default_opts();
+    if (o.guess != SGN_GUESS_PREVIOUS && o.guess != SGN_GUESS_EXTRAPOLATE) return fail(ctx, SGN_EINVAL, "bad guess");
+    guess_prepare(st, o, dt);
     // b_j, j = 0 .. s-1 (Table LMMCoeffs)
     static const double B[5][4] = {{0, 0, 0, 0},
                                    {0, 0, 0, 0},
@@ -1748,6 +1809,7 @@ sgn_status sgn_step_ab(sgn_ctx* ctx, sgn_state* st, int32_t order, double dt, in
         st->hist_dt = dt;
         st->ab_count = 0;
         st->ab_head = 0;
+        st->gx_count[GUESS_AB] = 0;
     }
     const Dims& d = st->d;
     StateBufs& b = st->b;
@@ -1775,7 +1837,7 @@ sgn_status sgn_step_ab(sgn_ctx* ctx, sgn_state* st, int32_t order, double dt, in
         }
         if ((s = lincomb(ctx, N, st->eta, dt, fe, c, st->eta)) != SGN_OK) break;
         if ((s = lincomb(ctx, DN, st->U, dt, fU, c, st->U)) != SGN_OK) break;
-        if ((s = stage_solve(st, st->eta, st->U, st->u, o, &acc)) != SGN_OK) break;
+        if ((s = stage_solve(st, GUESS_AB, st->eta, st->U, st->u, o, &acc)) != SGN_OK) break;
         st->t += dt;
         st->steps += 1;
     }
@@ -1789,6 +1851,8 @@ sgn_status sgn_step_linimp(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nstep
     if (nsteps < 0 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad step arguments");
     if (fixed && !(fixed->sigma > 0.0 && fixed->alpha > 0.0)) return fail(ctx, SGN_EINVAL, "bad fixed coefficients");
     const sgn_solve_opts o = opts ? *opts : default_opts();
+    if (o.guess != SGN_GUESS_PREVIOUS && o.guess != SGN_GUESS_EXTRAPOLATE) return fail(ctx, SGN_EINVAL, "bad guess");
+    guess_prepare(st, o, dt);
     sgn_step_info acc;
     info_init(&acc);
     sgn_status s = st->d.D == 1 ? sbdf2_steps<1>(st, dt, nsteps, fixed, o, &acc)

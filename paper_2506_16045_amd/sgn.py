@@ -34,6 +34,7 @@ STATUS_NAMES = {0: "SGN_OK", -1: "SGN_EINVAL", -2: "SGN_EDOMAIN", -3: "SGN_ENOCO
 PCG, GMRES = 0, 1
 FP64, MIXED = 0, 1
 COEFF_OPTIMAL, COEFF_REPLACEMENT = 0, 1
+GUESS_PREVIOUS, GUESS_EXTRAPOLATE = 0, 1
 
 
 class SgnError(RuntimeError):
@@ -57,7 +58,7 @@ class SolveOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("x0_is_guess", ctypes.c_int32),
                 ("gmres_restart", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("coeff_kind", ctypes.c_int32)]
+                ("coeff_kind", ctypes.c_int32), ("guess", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -129,9 +130,13 @@ def state_workspace_bytes(g, precision: int = FP64) -> int:
 
 
 def solve_opts(tol=1e-12, max_iter=1000, precision=FP64, x0_is_guess=False, inner_tol=1e-5,
-               max_outer=20, check_every=8, coeff_kind=COEFF_OPTIMAL, method=PCG, gmres_restart=30):
+               max_outer=20, check_every=8, coeff_kind=COEFF_OPTIMAL, method=PCG, gmres_restart=30,
+               guess=GUESS_EXTRAPOLATE):
+    """Solver options; guess may also be given as 'previous' or 'extrapolate'."""
+    if isinstance(guess, str):
+        guess = {"previous": GUESS_PREVIOUS, "extrapolate": GUESS_EXTRAPOLATE}[guess]
     return SolveOpts(method, precision, tol, max_iter, int(bool(x0_is_guess)), gmres_restart,
-                     inner_tol, max_outer, check_every, coeff_kind)
+                     inner_tol, max_outer, check_every, coeff_kind, guess)
 
 
 def _ptr(t: torch.Tensor, shape, name: str):

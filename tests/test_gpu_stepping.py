@@ -1,6 +1,8 @@
 """GPU parity of the time steppers (section 5) against the oracle: RK4 (Eq:ERK),
 AB2-4 (Eq:AB) and the linearly implicit SBDF2 scheme (Eq:MM), in 1D and 2D,
-FP64 to 1e-10 relative L2 per field (zeta, u, U) and the mixed form to 1e-9.
+FP64 to 1e-10 relative L2 per field (zeta, u, U) and the mixed form to 1e-9,
+with both initial-guess rules of the stepper solves (the most recent velocity,
+or extrapolated per-slot offsets), the same rule on both sides.
 Also: Krylov iteration counts per solve agree, mass is conserved on the device."""
 import math
 
@@ -59,13 +61,13 @@ def case_2d_bump():
     return g, h, eta, u
 
 
-def _setup(ctx, g, h, eta, u, tol):
+def _setup(ctx, g, h, eta, u, tol, guess="extrapolate"):
     from paper_2506_16045_amd import sgn
     gh, flat = ctx.bathy_prepare(g, _t(h))
     e_d, u_d = _t(eta), _t(u)
     U_d = ctx.apply_constraint(g, e_d, gh, u_d)
     st = sgn.State(ctx, g, _t(h), gh, flat, e_d, U_d, u_d)
-    pb = ost.Problem.from_h(g, h, tol=tol)
+    pb = ost.Problem.from_h(g, h, tol=tol, guess=guess)
     U0 = pb.G(eta, u)
     return st, pb, U0
 
@@ -82,14 +84,15 @@ CASES = [("1d-flat", case_1d_flat, 0.05), ("1d-shelf", case_1d_shelf, 0.02), ("1
          ("2d-bump", case_2d_bump, 0.05)]
 
 
+@pytest.mark.parametrize("guess", ["previous", "extrapolate"])
 @pytest.mark.parametrize("cname,make,dt", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("scheme,nsteps", SCHEMES, ids=[s[0] for s in SCHEMES])
-def test_stepper_fp64_matches_oracle(ctx, cname, make, dt, scheme, nsteps):
+def test_stepper_fp64_matches_oracle(ctx, cname, make, dt, scheme, nsteps, guess):
     from paper_2506_16045_amd import sgn
     g, h, eta, u = make()
     tol = 1e-12
-    st, pb, U0 = _setup(ctx, g, h, eta, u, tol)
-    opts = sgn.solve_opts(tol=tol, check_every=4)
+    st, pb, U0 = _setup(ctx, g, h, eta, u, tol, guess)
+    opts = sgn.solve_opts(tol=tol, check_every=4, guess=guess)
     if scheme == "rk4":
         info = st.step_rk4(dt, nsteps, opts)
         ref = ost.run_rk4(pb, eta, U0, u, dt, nsteps)
@@ -110,12 +113,13 @@ def test_stepper_fp64_matches_oracle(ctx, cname, make, dt, scheme, nsteps):
     st.close()
 
 
+@pytest.mark.parametrize("guess", ["previous", "extrapolate"])
 @pytest.mark.parametrize("cname,make,dt", [CASES[2], CASES[3]], ids=["1d-bump", "2d-bump"])
-def test_rk4_mixed_matches_fp64_oracle(ctx, cname, make, dt):
+def test_rk4_mixed_matches_fp64_oracle(ctx, cname, make, dt, guess):
     from paper_2506_16045_amd import sgn
     g, h, eta, u = make()
-    st, pb, U0 = _setup(ctx, g, h, eta, u, 1e-13)
-    info = st.step_rk4(dt, 4, sgn.solve_opts(tol=1e-11, precision=sgn.MIXED, inner_tol=1e-4))
+    st, pb, U0 = _setup(ctx, g, h, eta, u, 1e-13, guess)
+    info = st.step_rk4(dt, 4, sgn.solve_opts(tol=1e-11, precision=sgn.MIXED, inner_tol=1e-4, guess=guess))
     ref = ost.run_rk4(pb, eta, U0, u, dt, 4)
     assert info.converged
     _compare(st, h, ref, 1e-9)
@@ -133,3 +137,33 @@ def test_sbdf2_fixed_coefficients_and_restart(ctx):
     st.step_linimp(0.05, 4, fixed)
     ref = ost.run_sbdf2(pb, eta, U0, u, 0.05, 7, coeffs=(1.2 * s, 1.2 * a))
     _compare(st, h, ref, 1e-10)
+
+
+def test_guess_history_persists_across_calls_and_resets_on_dt(ctx):
+    """Calls with the same dt continue the offset history (2 + 4 RK4 steps equal
+    6 oracle steps, iteration for iteration); a new dt clears it on both sides."""
+    from paper_2506_16045_amd import sgn
+    g, h, eta, u = case_2d_bump()
+    st, pb, U0 = _setup(ctx, g, h, eta, u, 1e-12)
+    opts = sgn.solve_opts(tol=1e-12, check_every=4)
+    i1 = st.step_rk4(0.05, 2, opts)
+    i2 = st.step_rk4(0.05, 4, opts)
+    i3 = st.step_rk4(0.04, 3, opts)
+    ref = ost.run_rk4(pb, eta, U0, u, 0.05, 6)
+    ref = ost.run_rk4(pb, *ref, 0.04, 3)
+    assert i1.solves + i2.solves + i3.solves == len(pb.iters) == 36
+    assert abs(i1.iters + i2.iters + i3.iters - sum(pb.iters)) <= len(pb.iters)
+    _compare(st, h, ref, 1e-10)
+    st.close()
+
+
+def test_bad_guess_rule_rejected(ctx):
+    from paper_2506_16045_amd import sgn
+    g, h, eta, u = case_1d_flat()
+    st, pb, U0 = _setup(ctx, g, h, eta, u, 1e-12)
+    opts = sgn.solve_opts(tol=1e-12)
+    opts.guess = 7
+    with pytest.raises(sgn.SgnError) as e:
+        st.step_rk4(0.05, 1, opts)
+    assert e.value.status == sgn.EINVAL
+    st.close()

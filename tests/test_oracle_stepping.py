@@ -85,3 +85,51 @@ def test_sbdf2_zero_stability_rate():
         errs[n] = np.linalg.norm(un.ravel() - u_star)
     measured = (errs[160] / errs[60]) ** (1.0 / 100)
     assert measured == pytest.approx(rho, rel=0.02)
+
+
+# ---------------------------------------------------------------------------
+# Initial guesses of the stepper solves (a reading: the paper does not fix them)
+# ---------------------------------------------------------------------------
+def test_guess_history_extrapolates_linear_offsets_exactly():
+    h = st.GuessHistory("extrapolate")
+    h.prepare(0.1)
+    base = np.array([3.0, -1.0])
+    assert np.array_equal(h.guess("rk2", base), base)           # nothing recorded: the base
+    a, b = np.array([0.5, 2.0]), np.array([-0.25, 0.125])
+    h.record("rk2", base, base + a)                                # o_0 = a
+    assert np.allclose(h.guess("rk2", base), base + a)             # one offset: held constant
+    h.record("rk2", base, base + a + b)                            # o_1 = a + b
+    assert np.allclose(h.guess("rk2", base), base + a + 2 * b)     # o_2 of the line, exactly
+    h.record("rk2", base, base + a + 2 * b)
+    assert np.allclose(h.guess("rk2", base), base + a + 3 * b)
+    assert np.array_equal(h.guess("rk3", base), base)              # slots are independent
+    h.prepare(0.05)                                                # a new step size clears
+    assert np.array_equal(h.guess("rk2", base), base)
+    p = st.GuessHistory("previous")
+    p.record("ab", base, base + a)
+    assert np.array_equal(p.guess("ab", base), base)
+    with pytest.raises(ValueError):
+        st.GuessHistory("linear")
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "ab3"])
+def test_guess_changes_iterations_not_solution(scheme):
+    """Both guesses converge to the same trajectory (to the solve tolerance);
+    the extrapolated one needs fewer PCG iterations once its history is built."""
+    g = I.grid1d(256, 80.0)
+    rng = np.random.default_rng(I.SEED_BASE + 71)
+    h = I.random_bumps1d(g, rng)
+    eta_s, u0 = I.solitary_wave(g, 1.0, 0.2, 30.0)
+    eta0 = h + (eta_s - 1.0)
+    out, iters = {}, {}
+    for mode in ("previous", "extrapolate"):
+        pb = st.Problem.from_h(g, h, tol=1e-12, guess=mode)
+        U0 = pb.G(eta0, u0)
+        if scheme == "rk4":
+            out[mode] = st.run_rk4(pb, eta0, U0, u0, 0.05, 12)
+        else:
+            out[mode] = st.run_ab(pb, 3, eta0, U0, u0, 0.05, 12)
+        iters[mode] = sum(pb.iters[-8:])
+    for a, b in zip(out["previous"], out["extrapolate"]):
+        assert np.max(np.abs(a - b)) <= 1e-9 * max(1.0, np.max(np.abs(a)))
+    assert iters["extrapolate"] < 0.85 * iters["previous"], iters
