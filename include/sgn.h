@@ -152,7 +152,8 @@ typedef enum sgn_kernel_kind {
     SGN_KERNEL_PCG_R1_F32 = 7,
     SGN_KERNEL_PCG_C2_F32 = 8,
     SGN_KERNEL_PCG_INIT_F32 = 9,
-    SGN_KERNEL_KINDS = 10
+    SGN_KERNEL_BATCH = 10,   /* batched 1D solves (one launch per call) */
+    SGN_KERNEL_KINDS = 11
 } sgn_kernel_kind;
 sgn_status sgn_profile_begin(sgn_ctx *ctx);
 sgn_status sgn_profile_end(sgn_ctx *ctx, int64_t *launches, double *total_ms, int32_t nkinds);
@@ -201,6 +202,36 @@ sgn_status sgn_krylov_solve(sgn_ctx *ctx, const sgn_grid *grid, const double *d_
                             const double *d_grad_h, const double *d_rhs, double *d_u_inout,
                             const sgn_coeffs *coeffs, const sgn_solve_opts *opts,
                             sgn_solve_info *info, void *d_ws);
+
+/* ---- batched independent 1D solves ----------------------------------------- */
+
+/* Bytes of device workspace sgn_batch_solve needs for nitems systems of sizes
+ * h_n[i] (host array) in the given precision; 0 if a size is unsupported. */
+size_t sgn_batch_workspace_bytes(int32_t nitems, const int32_t *h_n, int32_t precision);
+
+/* Solve nitems independent 1D systems G_{eta_i,h_i} u_i = rhs_i (Def:G in 1D)
+ * by PCG with the preconditioner A of Def:A built per system from eta_i
+ * (section 3.2, coefficients of section 4 by opts->coeff_kind, the flat
+ * formulas iff h_x is identically zero), all in one kernel launch: each
+ * workgroup takes whole systems, largest first, and iterates each to its own
+ * stop test ||r||_2 <= tol ||rhs||_2.  opts->precision = SGN_MIXED runs FP32
+ * inner solves to inner_tol inside an FP64 iterative refinement (residual,
+ * stop test and u in FP64); SGN_FP64 iterates in FP64.
+ *   h_n[i]   points of system i: a power of two in [2, 8192] (host array)
+ *   h_L[i]   its period (host array)
+ *   d_eta, d_grad_h (h_x), d_rhs, d_u_inout: device arrays packed in system
+ *            order, system i at offset sum_{j<i} h_n[j]; u is the initial
+ *            guess when opts->x0_is_guess (else 0) and the result on return
+ *   h_info   nitems results (host array, may be NULL)
+ *   d_ws     sgn_batch_workspace_bytes(...) bytes, 256-byte aligned
+ * Synchronises the stream.  Every system is solved even if another fails:
+ * SGN_EDOMAIN if a system had non-positive depth or non-finite data (its u
+ * is left unchanged, relres NaN), else SGN_ENOCONV if a system stopped at
+ * max_iter (inner) / max_outer, else SGN_OK.  opts = NULL: FP64, tol 1e-12. */
+sgn_status sgn_batch_solve(sgn_ctx *ctx, int32_t nitems, const int32_t *h_n, const double *h_L,
+                           const double *d_eta, const double *d_grad_h, const double *d_rhs,
+                           double *d_u_inout, const sgn_solve_opts *opts, sgn_solve_info *h_info,
+                           void *d_ws);
 
 /* Right-hand side of the constraint form (Eq:DSWEcf, Def:bigF, Eq:DAE_DSWE):
  * eta_t = -div(eta u), U_t = -eta grad(zeta) - div(eta u (x) u) + F with

@@ -1,0 +1,440 @@
+// Batched independent 1D constraint solves in one launch: each workgroup takes
+// whole systems G_{eta,h} u = b (Def:G in 1D) of its own size and runs the
+// preconditioned CG of section 3.2 on them to completion, every vector in the
+// half spectrum (modes 0..N/2) and every transform in LDS.  MODE_FP64 iterates
+// in FP64; MODE_MIXED runs FP32 inner PCG solves of G d = r inside an FP64
+// iterative refinement (outer residual r = b - G x, the stop test and x in
+// FP64).  Per-system convergence: a workgroup moves to its next system as soon
+// as the current one is done.
+#pragma once
+
+#include "sgn_kernels.h"
+
+namespace sgn {
+
+constexpr int BATCH_THREADS = 256;
+constexpr int BATCH_EPC = 16;                                  // M = N/2 <= BATCH_EPC * BATCH_THREADS
+constexpr int BATCH_NMAX = 2 * BATCH_EPC * BATCH_THREADS;     // 8192 points
+
+enum { BATCH_FP64 = 0, BATCH_MIXED = 1 };
+
+struct BatchItem {
+    int n;           // grid points, a power of two in [2, BATCH_NMAX]
+    int index;       // position of the system in the caller's order
+    double L;        // period
+    long long off;   // first point of the system in the packed field arrays
+    long long wso;   // first double of the system's workspace
+};
+
+struct BatchResult {
+    int iters;       // Krylov iterations (inner iterations in mixed mode)
+    int outer;       // refinement steps (mixed mode)
+    int converged;
+    int status;      // 0, or -2: non-positive depth or non-finite data
+    int flat;
+    int pad;
+    double relres, sig, alp, kap;
+};
+
+struct BatchParams {
+    double tol, inner_tol;
+    int max_iter, max_outer, x0_is_guess, coeff_kind, nitems, pad;
+};
+
+// Doubles of workspace one system of n points uses in the given mode.
+__host__ __device__ inline long long batch_item_doubles(int n, int mode) {
+    const long long M1 = n / 2 + 1;
+    long long w = 5 * 2 * M1 + n;            // FP64: b, x, r, p, a_hat (spectral) + physical scratch
+    if (mode == BATCH_MIXED) w += 4 * M1 + 3 * ((n + 1) / 2);   // FP32: d, r, p, a_hat + eta, h_x, scratch
+    return (w + 1) & ~1LL;
+}
+
+// Block-wide sums of NACC doubles, the result in every thread (fixed order).
+template <int NACC>
+__device__ __forceinline__ void blk_allsum(double (&v)[NACC], double* red) {
+    block_sum<NACC>(v, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) red[16 * NACC + a] = v[a];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) v[a] = red[16 * NACC + a];
+    __syncthreads();
+}
+
+// Block-wide maxima of NACC doubles, the result in every thread.
+template <int NACC>
+__device__ __forceinline__ void blk_allmax(double (&v)[NACC], double* red) {
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[a] = fmax(v[a], __shfl_xor(v[a], off, 64));
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) red[a * 16 + wave] = v[a];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) {
+        double m = red[a * 16];
+        for (int w = 1; w < nw; ++w) m = fmax(m, red[a * 16 + w]);
+        v[a] = m;
+    }
+    __syncthreads();
+}
+
+// Forward real transform of N = 2M points held as pairs buf[j] = (x_2j, x_2j+1),
+// j < M: on return buf[k] = X_k = sum_n x_n W_N^{kn} for k = 0..M.  Whole block.
+template <typename T>
+__device__ __forceinline__ void blk_rfft_fwd(cpx<T>* buf, int M, const cpx<T>* __restrict__ tw_all) {
+    __syncthreads();
+    lds_fft<T, BATCH_EPC, 1>(buf, 0, M, threadIdx.x, blockDim.x, tw_size(tw_all, M), false);
+    const cpx<T>* tw2 = tw_size(tw_all, 2 * M);
+    const T half = (T)0.5;
+    for (int p = threadIdx.x; p <= M / 2; p += blockDim.x) {
+        const int k = p, m = M - p;
+        if (p == 0) {
+            const cpx<T> Z0 = buf[0];
+            buf[0] = C<T>(Z0.re + Z0.im, 0);
+            buf[M] = C<T>(Z0.re - Z0.im, 0);
+        } else {
+            const cpx<T> wk = tw2[k], wm = tw2[m];
+            const cpx<T> Zk = buf[k], Zm = buf[m];
+            const cpx<T> Xk = half * (Zk + cj(Zm)) - half * mul_i(wk * (Zk - cj(Zm)));
+            if (m != k) buf[m] = half * (Zm + cj(Zk)) - half * mul_i(wm * (Zm - cj(Zk)));
+            buf[k] = Xk;
+        }
+    }
+    __syncthreads();
+}
+
+// Inverse of blk_rfft_fwd up to the factor N: buf[k] = X_k (k = 0..M; the
+// imaginary parts of X_0 and X_M are ignored) -> buf[j] = N (x_2j, x_2j+1).
+template <typename T>
+__device__ __forceinline__ void blk_rfft_inv(cpx<T>* buf, int M, const cpx<T>* __restrict__ tw_all) {
+    __syncthreads();
+    const cpx<T>* tw2 = tw_size(tw_all, 2 * M);
+    for (int p = threadIdx.x; p <= M / 2; p += blockDim.x) {
+        const int k = p, m = M - p;
+        if (p == 0) {
+            const T x0 = buf[0].re, xm = buf[M].re;
+            buf[0] = C<T>(x0 + xm, x0 - xm);
+        } else {
+            cpx<T> wk = tw2[k], wm = tw2[m];
+            wk.im = -wk.im;
+            wm.im = -wm.im;
+            const cpx<T> Xk = buf[k], Xm = buf[m];
+            const cpx<T> Zk = (Xk + cj(Xm)) + mul_i((Xk - cj(Xm)) * wk);
+            if (m != k) buf[m] = (Xm + cj(Xk)) + mul_i((Xm - cj(Xk)) * wm);
+            buf[k] = Zk;
+        }
+    }
+    __syncthreads();
+    lds_fft<T, BATCH_EPC, 1>(buf, 0, M, threadIdx.x, blockDim.x, tw_size(tw_all, M), true);
+}
+
+// One system's view for G applies in precision T.
+template <typename T>
+struct BatchOp {
+    int N, M;
+    T tp;                        // 2 pi / L
+    const T* eta;                // total depth, N points
+    const T* hx;                 // bathymetry slope, N points
+    T* scr;                      // N-point physical scratch
+    cpx<T>* ah;                  // M+1 spectral scratch
+    const cpx<T>* tw;
+};
+
+// q_hat = G v_hat (modes 0..M of the half spectrum).  The weak form of Def:G in
+// 1D: a = eta (1 + h_x^2) v + eta^2/2 h_x Dv, w = eta^3/3 Dv + eta^2/2 h_x v,
+// G v = a - D w.  The pointwise pass also sums v.Gv = sum (v a + Dv w), so the
+// curvature is known (pq, every thread) before q_hat is formed; `fin(k, kk,
+// q_k, pq)` then consumes q_hat mode by mode (kk the wavenumber) with the same
+// thread mapping as every other mode loop of the system.
+template <typename T, typename Fin>
+__device__ __forceinline__ void blk_apply(const BatchOp<T>& A, const cpx<T>* vh, cpx<T>* lds, double* red,
+                                          Fin&& fin) {
+    const int M = A.M, N = A.N;
+    const T invN = (T)1 / (T)N;
+    // D v into the physical scratch
+    for (int k = threadIdx.x; k <= M; k += blockDim.x) lds[k] = invN * ik(wavenumber<T>(k, N, A.tp), vh[k]);
+    blk_rfft_inv<T>(lds, M, A.tw);
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        A.scr[2 * j] = lds[j].re;
+        A.scr[2 * j + 1] = lds[j].im;
+    }
+    __syncthreads();
+    // v, then the pointwise products (a into LDS, w into the scratch)
+    for (int k = threadIdx.x; k <= M; k += blockDim.x) lds[k] = invN * vh[k];
+    blk_rfft_inv<T>(lds, M, A.tw);
+    const T third = (T)1 / (T)3, half = (T)0.5;
+    double acc[1] = {0.0};
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        cpx<T> pv = lds[j];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int i = 2 * j + s;
+            const T p = s ? pv.im : pv.re;
+            const T dl = A.scr[i], et = A.eta[i], h = A.hx[i];
+            const T bt = h * p, e2 = et * et;
+            const T w1 = third * e2 * et * dl + half * e2 * bt;
+            const T w2 = half * e2 * dl + et * bt;
+            const T a = et * p + h * w2;
+            acc[0] += (double)et * (double)p * (double)p + (double)dl * (double)w1 + (double)bt * (double)w2;
+            A.scr[i] = w1;
+            if (s) pv.im = a; else pv.re = a;
+        }
+        lds[j] = pv;
+    }
+    blk_allsum<1>(acc, red);
+    const double pq = acc[0];
+    // a_hat to the spectral scratch, then w_hat; q = a_hat - i k w_hat
+    blk_rfft_fwd<T>(lds, M, A.tw);
+    for (int k = threadIdx.x; k <= M; k += blockDim.x) A.ah[k] = lds[k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < M; j += blockDim.x) lds[j] = C<T>(A.scr[2 * j], A.scr[2 * j + 1]);
+    blk_rfft_fwd<T>(lds, M, A.tw);
+    for (int k = threadIdx.x; k <= M; k += blockDim.x) {
+        const T kk = wavenumber<T>(k, N, A.tp);
+        fin(k, kk, A.ah[k] - ik(kk, lds[k]), pq);
+    }
+    __syncthreads();
+}
+
+// z = A^{-1} r for one mode (Def:A in 1D).
+template <typename T>
+__device__ __forceinline__ cpx<T> batch_precond(T kk, T sig, T alp, cpx<T> r) {
+    return ((T)1 / (sig + alp * kk * kk)) * r;
+}
+
+// PCG of section 3.2 on G x = r0 in precision T from the state (x_hat, r_hat)
+// whose (r.z, r.r) are rz, rr; stops when r.r <= tol2 * bbref or after max_iter
+// iterations.  Returns the iterations; rr holds the last r.r.
+template <typename T>
+__device__ int blk_pcg(const BatchOp<T>& A, cpx<T>* xh, cpx<T>* rh, cpx<T>* ph, T sig, T alp, double tol2,
+                       double bbref, int max_iter, double& rz, double& rr, cpx<T>* lds, double* red) {
+    const int M = A.M, N = A.N;
+    const double invN = 1.0 / (double)N;
+    double rho_prev = 1.0;
+    int it = 0;
+    while (!(rr <= tol2 * bbref) && it < max_iter && rr == rr) {
+        const T beta = it == 0 ? (T)0 : (T)(rz / rho_prev);
+        for (int k = threadIdx.x; k <= M; k += blockDim.x) {
+            const cpx<T> z = batch_precond<T>(wavenumber<T>(k, N, A.tp), sig, alp, rh[k]);
+            ph[k] = it == 0 ? z : z + beta * ph[k];
+        }
+        const double rho = rz;
+        double acc[2] = {0.0, 0.0};
+        blk_apply<T>(A, ph, lds, red, [&](int k, T kk, cpx<T> q, double pq) {
+            const T alpha = (T)(rho / pq);
+            xh[k] = xh[k] + alpha * ph[k];
+            const cpx<T> r = rh[k] - alpha * q;
+            rh[k] = r;
+            const cpx<T> z = batch_precond<T>(kk, sig, alp, r);
+            const double w = half_weight(k, N) * invN;
+            acc[0] += w * ((double)r.re * (double)z.re + (double)r.im * (double)z.im);
+            acc[1] += w * ((double)r.re * (double)r.re + (double)r.im * (double)r.im);
+        });
+        blk_allsum<2>(acc, red);
+        rho_prev = rho;
+        rz = acc[0];
+        rr = acc[1];
+        ++it;
+    }
+    return it;
+}
+
+// r_hat = b_hat - G x_hat in FP64, with its (r.z, r.r).
+__device__ __forceinline__ void blk_residual(const BatchOp<double>& A, const cpx<double>* bh, const cpx<double>* xh,
+                                             cpx<double>* rh, double sig, double alp, double& rz, double& rr,
+                                             cpx<double>* lds, double* red) {
+    const double invN = 1.0 / (double)A.N;
+    double acc[2] = {0.0, 0.0};
+    blk_apply<double>(A, xh, lds, red, [&](int k, double kk, cpx<double> q, double) {
+        const cpx<double> r = bh[k] - q;
+        rh[k] = r;
+        const cpx<double> z = batch_precond<double>(kk, sig, alp, r);
+        const double w = half_weight(k, A.N) * invN;
+        acc[0] += w * (r.re * z.re + r.im * z.im);
+        acc[1] += w * (r.re * r.re + r.im * r.im);
+    });
+    blk_allsum<2>(acc, red);
+    rz = acc[0];
+    rr = acc[1];
+}
+
+// Transform N physical FP64 points into modes 0..M (dst), returning sum x^2.
+__device__ __forceinline__ void blk_to_spectral(const double* x, int N, cpx<double>* dst,
+                                                const cpx<double>* tw, cpx<double>* lds) {
+    const int M = N / 2;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) lds[j] = C<double>(x[2 * j], x[2 * j + 1]);
+    blk_rfft_fwd<double>(lds, M, tw);
+    for (int k = threadIdx.x; k <= M; k += blockDim.x) dst[k] = lds[k];
+    __syncthreads();
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(BATCH_THREADS) k_batch_solve(const BatchItem* __restrict__ items, int nitems,
+                                                               const double* __restrict__ eta_all,
+                                                               const double* __restrict__ hx_all,
+                                                               const double* __restrict__ b_all,
+                                                               double* __restrict__ u_all, double* __restrict__ ws,
+                                                               const cpx<double>* __restrict__ tw64,
+                                                               const cpx<float>* __restrict__ tw32, BatchParams prm,
+                                                               BatchResult* __restrict__ res) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<double>* lds64 = reinterpret_cast<cpx<double>*>(smem_raw);
+    cpx<float>* lds32 = reinterpret_cast<cpx<float>*>(smem_raw);
+    __shared__ double red[5 * 16 + 8];
+    for (int s = blockIdx.x; s < nitems; s += gridDim.x) {
+        const BatchItem it = items[s];
+        const int N = it.n, M = N / 2;
+        const double* eta = eta_all + it.off;
+        const double* hx = hx_all + it.off;
+        double* w = ws + it.wso;
+        cpx<double>* bh = reinterpret_cast<cpx<double>*>(w);
+        cpx<double>* xh = bh + (M + 1);
+        cpx<double>* rh = xh + (M + 1);
+        cpx<double>* ph = rh + (M + 1);
+        BatchOp<double> A64;
+        A64.N = N;
+        A64.M = M;
+        A64.tp = 6.283185307179586476925286766559 / it.L;
+        A64.eta = eta;
+        A64.hx = hx;
+        A64.ah = ph + (M + 1);
+        A64.scr = reinterpret_cast<double*>(A64.ah + (M + 1));
+        A64.tw = tw64;
+        BatchResult out{};
+        // coefficients of section 4 from the extremes of eta and h_x
+        const double lp = (4.0 + sqrt(13.0)) / 6.0;
+        double ex[5] = {-1.0e308, -1.0e308, -1.0e308, 0.0, 0.0};
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            const double e = eta[i], h = hx[i], g2 = h * h;
+            if (!isfinite(e) || !isfinite(g2) || !isfinite(b_all[it.off + i]) ||
+                (prm.x0_is_guess && !isfinite(u_all[it.off + i])))
+                ex[4] = 1.0;
+            ex[0] = fmax(ex[0], -e);
+            ex[1] = fmax(ex[1], e);
+            ex[2] = fmax(ex[2], e + lp * e * g2);
+            ex[3] = fmax(ex[3], g2);
+        }
+        blk_allmax<5>(ex, red);
+        const double emin = -ex[0];
+        if (ex[4] != 0.0 || !(emin > 0.0)) {
+            out.status = -2;
+            out.relres = __builtin_nan("");
+            if (threadIdx.x == 0) res[it.index] = out;
+            continue;
+        }
+        double sig, alp, kap;
+        int fl;
+        coeffs_formula(emin, ex[1], ex[2], ex[3], -1, prm.coeff_kind, sig, alp, kap, fl);
+        out.sig = sig;
+        out.alp = alp;
+        out.kap = kap;
+        out.flat = fl;
+        // b_hat, ||b||^2, and the initial x_hat, r_hat
+        blk_to_spectral(b_all + it.off, N, bh, tw64, lds64);
+        double bb = 0.0, rz = 0.0, rr = 0.0;
+        {
+            double acc[2] = {0.0, 0.0};
+            for (int k = threadIdx.x; k <= M; k += blockDim.x) {
+                const cpx<double> b = bh[k];
+                const double kk = wavenumber<double>(k, N, A64.tp);
+                const cpx<double> z = batch_precond<double>(kk, sig, alp, b);
+                const double wt = half_weight(k, N) / (double)N;
+                acc[0] += wt * (b.re * z.re + b.im * z.im);
+                acc[1] += wt * (b.re * b.re + b.im * b.im);
+            }
+            blk_allsum<2>(acc, red);
+            bb = acc[1];
+            rz = acc[0];
+            rr = acc[1];
+        }
+        const double tol2 = prm.tol * prm.tol;
+        if (prm.x0_is_guess && bb > 0.0) {
+            blk_to_spectral(u_all + it.off, N, xh, tw64, lds64);
+            blk_residual(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
+        } else {
+            for (int k = threadIdx.x; k <= M; k += blockDim.x) {
+                xh[k] = C<double>(0, 0);
+                rh[k] = bh[k];
+            }
+            __syncthreads();
+        }
+        if (MODE == BATCH_FP64) {
+            out.iters = blk_pcg<double>(A64, xh, rh, ph, sig, alp, tol2, bb, prm.max_iter, rz, rr, lds64, red);
+        } else {
+            // FP32 view of the same system
+            float* w32 = reinterpret_cast<float*>(A64.scr + N);
+            cpx<float>* dh = reinterpret_cast<cpx<float>*>(w32);
+            cpx<float>* r32 = dh + (M + 1);
+            cpx<float>* p32 = r32 + (M + 1);
+            BatchOp<float> A32;
+            A32.N = N;
+            A32.M = M;
+            A32.tp = (float)A64.tp;
+            A32.ah = p32 + (M + 1);
+            float* e32 = reinterpret_cast<float*>(A32.ah + (M + 1));
+            float* h32 = e32 + N;
+            A32.eta = e32;
+            A32.hx = h32;
+            A32.scr = h32 + N;
+            A32.tw = tw32;
+            for (int i = threadIdx.x; i < N; i += blockDim.x) {
+                e32[i] = (float)eta[i];
+                h32[i] = (float)hx[i];
+            }
+            const float sig32 = (float)sig, alp32 = (float)alp;
+            const double itol2 = prm.inner_tol * prm.inner_tol;
+            while (!(rr <= tol2 * bb) && rr == rr && out.outer < prm.max_outer && bb > 0.0) {
+                // inner: G d = r from d = 0 to inner_tol ||r||
+                double irz = 0.0, irr = 0.0;
+                {
+                    double acc[2] = {0.0, 0.0};
+                    for (int k = threadIdx.x; k <= M; k += blockDim.x) {
+                        const cpx<float> r = C<float>((float)rh[k].re, (float)rh[k].im);
+                        r32[k] = r;
+                        dh[k] = C<float>(0, 0);
+                        const cpx<float> z = batch_precond<float>(wavenumber<float>(k, N, A32.tp), sig32, alp32, r);
+                        const double wt = half_weight(k, N) / (double)N;
+                        acc[0] += wt * ((double)r.re * (double)z.re + (double)r.im * (double)z.im);
+                        acc[1] += wt * ((double)r.re * (double)r.re + (double)r.im * (double)r.im);
+                    }
+                    blk_allsum<2>(acc, red);
+                    irz = acc[0];
+                    irr = acc[1];
+                }
+                const double rr_outer = irr;
+                out.iters += blk_pcg<float>(A32, dh, r32, p32, sig32, alp32, itol2, rr_outer, prm.max_iter, irz, irr,
+                                            lds32, red);
+                // x += d; r = b - G x (FP64)
+                for (int k = threadIdx.x; k <= M; k += blockDim.x)
+                    xh[k] = xh[k] + C<double>((double)dh[k].re, (double)dh[k].im);
+                __syncthreads();
+                blk_residual(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
+                out.outer += 1;
+            }
+        }
+        out.converged = (bb == 0.0 || rr <= tol2 * bb) ? 1 : 0;
+        out.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+        if (!(rr == rr)) out.status = -2;
+        // u = x (physical)
+        const double invN = 1.0 / (double)N;
+        for (int k = threadIdx.x; k <= M; k += blockDim.x) lds64[k] = invN * xh[k];
+        blk_rfft_inv<double>(lds64, M, tw64);
+        double* u = u_all + it.off;
+        for (int j = threadIdx.x; j < M; j += blockDim.x) {
+            u[2 * j] = lds64[j].re;
+            u[2 * j + 1] = lds64[j].im;
+        }
+        if (threadIdx.x == 0) res[it.index] = out;
+        __syncthreads();
+    }
+}
+
+}  // namespace sgn

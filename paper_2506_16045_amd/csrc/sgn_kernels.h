@@ -765,17 +765,38 @@ __global__ void __launch_bounds__(256) k_coeffs(size_t npts, const double* __res
     }
 }
 
-// One block: (sigma*, alpha*, kappa_ub) of Eq:FlatbathCoeff, Eq:Optcoeff,
-// Eq:Optcoeffb (kind 0) or Remark 4.2 (kind 1).  flat < 0 selects the flat
-// formulas iff |grad h|_max = 0.
+// (sigma*, alpha*, kappa_ub) of Eq:FlatbathCoeff (flat), Eq:Optcoeff and
+// Eq:Optcoeffb (kind 0) or Remark 4.2 (kind 1) from min eta, max eta,
+// max(eta + lambda_+ eta |grad h|^2) and max |grad h|^2.  flat < 0 selects the
+// flat formulas iff |grad h|_max = 0; the choice is returned in fl.
+__host__ __device__ inline void coeffs_formula(double emin, double emax, double smx, double g2m, int flat, int kind,
+                                               double& sig, double& alp, double& kap, int& fl) {
+    const double lp = (4.0 + sqrt(13.0)) / 6.0;
+    const double lm = (4.0 - sqrt(13.0)) / 6.0;
+    const double ratio3 = (emax / emin) * (emax / emin) * (emax / emin);
+    fl = flat < 0 ? (g2m == 0.0 ? 1 : 0) : (flat != 0 ? 1 : 0);
+    if (fl) {
+        sig = emax;
+        alp = emax * emax * emax / 3.0;
+        kap = ratio3;
+    } else if (kind == 0) {
+        sig = smx;
+        alp = lp * emax * emax * emax;
+        kap = fmax(smx / emin, (lp / lm) * ratio3);
+    } else {
+        sig = emax * (1.0 + lp * g2m);
+        alp = lp * emax * emax * emax;
+        kap = fmax((emax / emin) * (1.0 + lp * g2m), (lp / lm) * ratio3);
+    }
+}
+
+// One block: the coefficients from the per-block extremes of k_coeffs.
 __global__ void __launch_bounds__(256) k_coeffs_finish(SolveScal* __restrict__ sc, const double* __restrict__ part,
                                                        int nb, int flat, int kind) {
     __shared__ double red[5 * 16];
     double r[5];
     final_max<5>(part + PART_GEN, nb, r, red);
     if (threadIdx.x != 0) return;
-    const double lp = (4.0 + sqrt(13.0)) / 6.0;
-    const double lm = (4.0 - sqrt(13.0)) / 6.0;
     const double emin = -r[0], emax = r[1], smx = r[2], g2m = r[3];
     sc->red[0] = emin;
     sc->red[1] = emax;
@@ -786,22 +807,13 @@ __global__ void __launch_bounds__(256) k_coeffs_finish(SolveScal* __restrict__ s
         sc->done = 1;
         return;
     }
-    const double ratio3 = (emax / emin) * (emax / emin) * (emax / emin);
-    const int fl = flat < 0 ? (g2m == 0.0 ? 1 : 0) : (flat != 0 ? 1 : 0);
+    double sig, alp, kap;
+    int fl;
+    coeffs_formula(emin, emax, smx, g2m, flat, kind, sig, alp, kap, fl);
     sc->flat = fl;
-    if (fl) {
-        sc->sig = emax;
-        sc->alp = emax * emax * emax / 3.0;
-        sc->kap = ratio3;
-    } else if (kind == 0) {
-        sc->sig = smx;
-        sc->alp = lp * emax * emax * emax;
-        sc->kap = fmax(smx / emin, (lp / lm) * ratio3);
-    } else {
-        sc->sig = emax * (1.0 + lp * g2m);
-        sc->alp = lp * emax * emax * emax;
-        sc->kap = fmax((emax / emin) * (1.0 + lp * g2m), (lp / lm) * ratio3);
-    }
+    sc->sig = sig;
+    sc->alp = alp;
+    sc->kap = kap;
 }
 
 // Per-block min and max of a physical field (the flat-bottom test).

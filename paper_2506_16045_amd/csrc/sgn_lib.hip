@@ -1,6 +1,7 @@
 // libsgn: C ABI entry points (include/sgn.h) and their host orchestration.
 #include "sgn.h"
 #include "sgn_kernels.h"
+#include "sgn_batch.h"
 
 #include <algorithm>
 #include <cmath>
@@ -44,6 +45,9 @@ struct sgn_ctx {
     // stepper slot (last entry: solves outside a stepper)
     int last_iters[2][GUESS_SLOTS + 1] = {};
     bool stage = false;           // solving inside a stepper: skip the final scalar readback
+    int cus = 256;                // compute units of the device
+    void* hbatch = nullptr;       // pinned staging of batch item tables and results
+    size_t hbatch_bytes = 0;
     int slot = GUESS_SLOTS;       // stepper slot of the running solve
 };
 
@@ -1554,6 +1558,9 @@ sgn_status sgn_create(sgn_ctx** out, int device, void* hip_stream) {
         return SGN_ENOMEM;
     }
     if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) ctx->cap_stream = nullptr;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        ctx->cus = cus;
     const char* ng = getenv("SGN_NO_GRAPHS");
     if (ng && ng[0] && ng[0] != '0') ctx->use_graphs = false;
     *out = ctx;
@@ -1571,6 +1578,7 @@ void sgn_destroy(sgn_ctx* ctx) {
     for (auto& g : ctx->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->hbatch) (void)hipHostFree(ctx->hbatch);
     delete ctx;
 }
 
@@ -1718,6 +1726,145 @@ sgn_status sgn_krylov_solve(sgn_ctx* ctx, const sgn_grid* grid, const double* et
         return fail(ctx, SGN_EINVAL, "bad coeff_kind");
     // without given coefficients the flat formulas apply iff |grad h|_max = 0
     return solve_dispatch(ctx, d, eta, grad_h, rhs, u, coeffs, coeffs ? coeffs->flat : -1, o, info, ws);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Layout of a batch workspace: item table, results, then each system's region.
+struct BatchLayout {
+    size_t items, results, data, total;
+};
+
+BatchLayout batch_layout(int nitems, const int32_t* n, int mode) {
+    BatchLayout l;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    l.items = 0;
+    l.results = up(sizeof(BatchItem) * (size_t)nitems);
+    l.data = l.results + up(sizeof(BatchResult) * (size_t)nitems);
+    size_t dbl = 0;
+    for (int i = 0; i < nitems; ++i) dbl += (size_t)batch_item_doubles(n[i], mode);
+    l.total = l.data + up(dbl * sizeof(double)) + 256;
+    return l;
+}
+
+bool batch_size_ok(int n) { return n >= 2 && n <= BATCH_NMAX && (n & (n - 1)) == 0; }
+
+sgn_status batch_staging(sgn_ctx* ctx, size_t bytes) {
+    if (ctx->hbatch_bytes >= bytes) return SGN_OK;
+    if (ctx->hbatch) (void)hipHostFree(ctx->hbatch);
+    ctx->hbatch = nullptr;
+    ctx->hbatch_bytes = 0;
+    if (hipHostMalloc(&ctx->hbatch, bytes, hipHostMallocDefault) != hipSuccess)
+        return fail(ctx, SGN_ENOMEM, "pinned staging allocation failed");
+    ctx->hbatch_bytes = bytes;
+    return SGN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sgn_batch_workspace_bytes(int32_t nitems, const int32_t* n, int32_t precision) {
+    if (nitems < 0 || (nitems > 0 && !n)) return 0;
+    if (precision != SGN_FP64 && precision != SGN_MIXED) return 0;
+    for (int i = 0; i < nitems; ++i)
+        if (!batch_size_ok(n[i])) return 0;
+    return batch_layout(nitems, n, precision == SGN_MIXED ? BATCH_MIXED : BATCH_FP64).total;
+}
+
+sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const double* L, const double* eta,
+                           const double* grad_h, const double* rhs, double* u, const sgn_solve_opts* opts,
+                           sgn_solve_info* info, void* ws) {
+    if (!ctx) return SGN_EINVAL;
+    if (nitems < 0) return fail(ctx, SGN_EINVAL, "nitems < 0");
+    if (nitems == 0) return SGN_OK;
+    if (!n || !L || !eta || !grad_h || !rhs || !u || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    const sgn_solve_opts o = opts ? *opts : default_opts();
+    if (o.method != SGN_PCG) return fail(ctx, SGN_EUNSUPPORTED, "only PCG is available");
+    if (o.precision != SGN_FP64 && o.precision != SGN_MIXED) return fail(ctx, SGN_EINVAL, "unknown precision");
+    if (!(o.tol > 0.0) || o.max_iter < 1) return fail(ctx, SGN_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (o.coeff_kind != SGN_COEFF_OPTIMAL && o.coeff_kind != SGN_COEFF_REPLACEMENT)
+        return fail(ctx, SGN_EINVAL, "bad coeff_kind");
+    int nmax = 0;
+    for (int i = 0; i < nitems; ++i) {
+        if (!batch_size_ok(n[i])) return fail(ctx, SGN_EUNSUPPORTED, "batch sizes must be powers of two in [2, 8192]");
+        if (!(L[i] > 0.0) || !std::isfinite(L[i])) return fail(ctx, SGN_EINVAL, "periods must be positive");
+        nmax = std::max(nmax, (int)n[i]);
+    }
+    const int mode = o.precision == SGN_MIXED ? BATCH_MIXED : BATCH_FP64;
+    const BatchLayout lay = batch_layout(nitems, n, mode);
+    sgn_status s;
+    if ((s = batch_staging(ctx, std::max(sizeof(BatchItem), sizeof(BatchResult)) * (size_t)nitems)) != SGN_OK)
+        return s;
+    // systems in the caller's order for offsets; the table is sorted by size
+    // (largest first) so that blocks take the long systems first
+    std::vector<long long> off(nitems), wso(nitems);
+    long long po = 0, pw = 0;
+    for (int i = 0; i < nitems; ++i) {
+        off[i] = po;
+        wso[i] = pw;
+        po += n[i];
+        pw += batch_item_doubles(n[i], mode);
+    }
+    std::vector<int> order(nitems);
+    for (int i = 0; i < nitems; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+    BatchItem* hit = static_cast<BatchItem*>(ctx->hbatch);
+    for (int s2 = 0; s2 < nitems; ++s2) {
+        const int i = order[s2];
+        hit[s2].n = n[i];
+        hit[s2].index = i;
+        hit[s2].L = L[i];
+        hit[s2].off = off[i];
+        hit[s2].wso = wso[i];
+    }
+    char* base = static_cast<char*>(ws);
+    BatchItem* d_items = reinterpret_cast<BatchItem*>(base + lay.items);
+    BatchResult* d_res = reinterpret_cast<BatchResult*>(base + lay.results);
+    double* d_data = reinterpret_cast<double*>(base + lay.data);
+    HIPCHK(ctx, hipMemcpyAsync(d_items, hit, sizeof(BatchItem) * (size_t)nitems, hipMemcpyHostToDevice, ctx->stream));
+    BatchParams prm{};
+    prm.tol = o.tol;
+    prm.inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    prm.max_iter = o.max_iter;
+    prm.max_outer = o.max_outer > 0 ? o.max_outer : 20;
+    prm.x0_is_guess = o.x0_is_guess ? 1 : 0;
+    prm.coeff_kind = o.coeff_kind;
+    prm.nitems = nitems;
+    const size_t lds = (size_t)(nmax / 2 + 1) * sizeof(cpx<double>);
+    const int grid = std::min(nitems, 2 * ctx->cus);
+    {
+        ProfScope ps(ctx, SGN_KERNEL_BATCH);
+        auto k = mode == BATCH_MIXED ? k_batch_solve<BATCH_MIXED> : k_batch_solve<BATCH_FP64>;
+        HIPCHK(ctx, allow_lds(k, lds));
+        hipLaunchKernelGGL(k, dim3(grid), dim3(BATCH_THREADS), lds, ctx->stream, (const BatchItem*)d_items, nitems,
+                           eta, grad_h, rhs, u, d_data, ctx->tw64, ctx->tw32, prm, d_res);
+        CHECK_LAUNCH(ctx);
+    }
+    BatchResult* hres = static_cast<BatchResult*>(ctx->hbatch);
+    HIPCHK(ctx, hipMemcpyAsync(hres, d_res, sizeof(BatchResult) * (size_t)nitems, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    bool bad = false, nc = false;
+    for (int i = 0; i < nitems; ++i) {
+        const BatchResult& r = hres[i];
+        if (info) {
+            info[i].iters = r.iters;
+            info[i].outer_iters = r.outer;
+            info[i].converged = r.converged;
+            info[i].relres = r.relres;
+            info[i].coeffs.sigma = r.sig;
+            info[i].coeffs.alpha = r.alp;
+            info[i].coeffs.kappa_ub = r.kap;
+            info[i].coeffs.flat = r.flat;
+        }
+        if (r.status == -2) bad = true;
+        else if (!r.converged) nc = true;
+    }
+    if (bad) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in a batched system");
+    if (nc) return fail(ctx, SGN_ENOCONV, "a batched system did not reach the tolerance");
+    return SGN_OK;
 }
 
 sgn_status sgn_rhs(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const double* h, const double* grad_h,

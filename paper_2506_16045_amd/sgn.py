@@ -91,6 +91,9 @@ _SIGS = {
     "sgn_krylov_solve": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, ctypes.POINTER(Coeffs),
                               ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
     "sgn_rhs": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P]),
+    "sgn_batch_workspace_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I]),
+    "sgn_batch_solve": (_S, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_D), _P, _P, _P, _P,
+                             ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
     "sgn_state_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
     "sgn_state_create": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _I, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "sgn_state_destroy": (None, [_P]),
@@ -123,6 +126,11 @@ def make_grid(g) -> Grid:
 
 def workspace_bytes(g, precision: int = FP64) -> int:
     return int(_lib.sgn_workspace_bytes(ctypes.byref(make_grid(g)), precision))
+
+
+def batch_workspace_bytes(sizes, precision: int = FP64) -> int:
+    n = (_I * len(sizes))(*[int(v) for v in sizes])
+    return int(_lib.sgn_batch_workspace_bytes(len(sizes), n, precision))
 
 
 def state_workspace_bytes(g, precision: int = FP64) -> int:
@@ -218,7 +226,7 @@ class Context:
 
     # -- kernel timing ---------------------------------------------------------
     KERNEL_KINDS = ("pcg_c1", "pcg_r1", "pcg_c2", "pcg_init", "rows", "cols",
-                    "pcg_c1_f32", "pcg_r1_f32", "pcg_c2_f32", "pcg_init_f32")
+                    "pcg_c1_f32", "pcg_r1_f32", "pcg_c2_f32", "pcg_init_f32", "batch")
 
     def profile_begin(self):
         self._sync_stream()
@@ -296,6 +304,38 @@ class Context:
             return u, res
         self._check(st)
         return u, res
+
+    def batch_solve(self, sizes, periods, eta, grad_h, rhs, u=None, opts: SolveOpts | None = None,
+                    raise_on_error: bool = True):
+        """Independent 1D solves in one launch (sgn_batch_solve).  The fields are
+        packed 1D float64 tensors (system i at offset sum(sizes[:i])).  Returns
+        (u, [SolveResult], status)."""
+        self._sync_stream()
+        nitems = len(sizes)
+        total = int(sum(int(v) for v in sizes))
+        if len(periods) != nitems:
+            raise ValueError("sizes and periods differ in length")
+        o = opts if opts is not None else solve_opts()
+        if u is None:
+            u = torch.zeros(total, dtype=torch.float64, device=self.device)
+        n = (_I * nitems)(*[int(v) for v in sizes])
+        L = (_D * nitems)(*[float(v) for v in periods])
+        infos = (SolveInfo * max(nitems, 1))()
+        nb = batch_workspace_bytes(sizes, o.precision)
+        if nitems and nb == 0:
+            raise SgnError(EUNSUPPORTED, "batch sizes must be powers of two in [2, 8192]")
+        ws = self._ws.get("batch")
+        if ws is None or ws.numel() < nb:
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+            self._ws["batch"] = ws
+        st = _lib.sgn_batch_solve(self._h, nitems, n, L, _ptr(eta, (total,), "eta"), _ptr(grad_h, (total,), "grad_h"),
+                                  _ptr(rhs, (total,), "rhs"), _ptr(u, (total,), "u"), ctypes.byref(o), infos,
+                                  _P(ws.data_ptr()))
+        res = [SolveResult(i.iters, i.outer_iters, bool(i.converged), i.relres, i.coeffs.sigma, i.coeffs.alpha,
+                           i.coeffs.kappa_ub, bool(i.coeffs.flat)) for i in list(infos)[:nitems]]
+        if raise_on_error:
+            self._check(st)
+        return u, res, st
 
     def rhs(self, g, eta, h, grad_h, u, eta_t=None, U_t=None):
         """(eta_t, U_t) = f(w, p) (sgn_rhs)."""
