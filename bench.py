@@ -19,6 +19,12 @@ over the timed region) and the CPU oracle timed on the host on one RK4 step of
 the same workload.
 
     python bench.py [--steps K] [--warmup W] [--precision mixed|fp64]
+
+--workload batch measures the batched-ensemble workload instead: 512
+independent 1D constraint solves G u = b with sizes drawn from
+{512, ..., 8192} on L = 400, random Gaussian bumps and random solitary waves,
+b = G u* formed on the device, all solved in one launch per step (a step is
+one batched solve of the whole ensemble from a zero guess, to 1e-10).
 """
 from __future__ import annotations
 
@@ -109,9 +115,154 @@ def cpu_baseline(cfg, steps: int = 1):
                       f"{np.mean(pb.iters):.1f})"}
 
 
+def batch_bytes(sizes, res, mixed: bool) -> float:
+    """Algorithmic HBM bytes of one batched launch: per system, the inputs eta,
+    h_x, b and the output u in FP64, 13 words per point for every PCG iteration
+    (x, r, p read and written, q and z formed on chip, eta and h_x read; the
+    transforms stay in LDS) in the working precision, and in mixed mode 7 FP64
+    words per point for each refinement step's residual."""
+    tot = 0.0
+    w = 4 if mixed else 8
+    for n, r in zip(sizes, res):
+        tot += n * (4 * 8 + r.iters * 13 * w + (r.outer_iters * 7 * 8 if mixed else 0))
+    return tot
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+
+    from paper_2506_16045_amd import inputs as I
+    from paper_2506_16045_amd import sgn
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    prec = sgn.MIXED if args.precision == "mixed" else sgn.FP64
+    tol = 1e-10
+    opts = sgn.solve_opts(tol=tol, precision=prec, inner_tol=args.inner_tol if prec == sgn.MIXED else 1e-5,
+                          max_iter=5000, max_outer=40)
+    systems = I.config_c4(args.count)
+    ctx = sgn.Context(0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    etas, ghs, bs, ustars, sizes, periods = [], [], [], [], [], []
+    for g, eta, h, u_star in systems:
+        gh, _ = ctx.bathy_prepare(g, to(h))
+        e = to(eta)
+        us = to(u_star)
+        bs.append(ctx.apply_constraint(g, e, gh, us).reshape(-1))
+        etas.append(e)
+        ghs.append(gh.reshape(-1))
+        ustars.append(us.reshape(-1))
+        sizes.append(g.nx)
+        periods.append(g.Lx)
+    eta_p, gh_p, b_p, us_p = (torch.cat(x) for x in (etas, ghs, bs, ustars))
+    npts = int(sum(sizes))
+    u = torch.zeros(npts, dtype=torch.float64, device=dev)
+    for _ in range(max(args.warmup, 1)):
+        u.zero_()
+        ctx.batch_solve(sizes, periods, eta_p, gh_p, b_p, u, opts)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        u.zero_()
+        _, res, _ = ctx.batch_solve(sizes, periods, eta_p, gh_p, b_p, u, opts)
+        lat.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {"batch": (0, 0.0)}
+    if not args.no_kernel_timing:
+        ctx.profile_begin()
+        for _ in range(args.timing_steps):
+            u.zero_()
+            ctx.batch_solve(sizes, periods, eta_p, gh_p, b_p, u, opts)
+        prof = ctx.profile_end()
+    # accuracy against the exact discrete solutions u* (b = G u*)
+    err = []
+    o = 0
+    for n in sizes:
+        d = torch.linalg.vector_norm(u[o:o + n] - us_p[o:o + n]) / torch.linalg.vector_norm(us_p[o:o + n])
+        err.append(float(d.item()))
+        o += n
+    iters = [r.iters for r in res]
+    roofline = None
+    nl, ms = prof["batch"]
+    if nl:
+        avg_us = 1e3 * ms / nl
+        nbytes = batch_bytes(sizes, res, prec == sgn.MIXED)
+        achieved = nbytes / (avg_us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "kernel": "k_batch_solve", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2),
+                    "timing": f"HIP events around {nl} launches"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_batch(systems, tol, args.cpu_sample)
+    out = {
+        "metric": "batched 1D SGN constraint solves/s (ragged N, per-system convergence); Krylov iters/solve; "
+                  "p50/p99 latency",
+        "value": len(sizes) * args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == sgn.MIXED else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{len(sizes)} independent 1D constraint solves in one launch, N from "
+                         f"{{512..8192}} on L=400, 1-3 random Gaussian bumps, random solitary waves, "
+                         f"b = G u*, tol {tol:g}, zero initial guess"),
+            "precision": args.precision, "systems": len(sizes), "points": npts, "tol": tol,
+            "parallelism": "single GPU",
+        },
+        "points_per_s": npts * args.steps / elapsed,
+        "krylov_iters_per_solve": float(np.mean(iters)),
+        "krylov_iters_max": int(max(iters)),
+        "outer_per_solve": float(np.mean([r.outer_iters for r in res])),
+        "batch_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)},
+        "checks": {"max_rel_err_vs_exact": max(err), "all_converged": all(r.converged for r in res)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+def cpu_baseline_batch(systems, tol, count):
+    """The oracle's PCG, as it stands, on the first `count` systems of the ensemble
+    (forming b = G u* is not timed)."""
+    from oracle import krylov
+    from oracle import operators as op
+    dt = 0.0
+    its = []
+    for g, eta, h, u_star in systems[:count]:
+        gh, _ = op.bathy_gradient(h, g)
+        fl = not gh.any()
+        b = op.apply_G(eta, gh, u_star, g)
+        sg, al, _ = op.coefficients(eta, gh, fl)
+        t1 = time.perf_counter()
+        _, it, ok, _ = krylov.pcg(lambda v: op.apply_G(eta, gh, v, g), lambda r: op.solve_A(sg, al, r, g), b,
+                                  tol=tol, max_iter=5000)
+        dt += time.perf_counter() - t1
+        its.append(it)
+    return {"value": count / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {count} systems of the ensemble, FP64 NumPy, single thread ({dt:.1f} s; "
+                      f"iterations/solve {sum(its) / max(len(its), 1):.1f})"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["rk4-2d", "batch"], default="rk4-2d")
+    ap.add_argument("--count", type=int, default=512, help="systems of the batched workload")
+    ap.add_argument("--cpu-sample", type=int, default=512, help="systems the CPU oracle solves for its baseline")
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
@@ -153,6 +304,9 @@ def main(argv=None):
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
               "(multi-GPU sharding is described in the design notes, not run)", file=sys.stderr)
         return 2
+
+    if args.workload == "batch":
+        return bench_batch(args)
 
     import numpy as np
     import torch

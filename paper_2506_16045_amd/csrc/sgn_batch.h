@@ -12,9 +12,11 @@
 
 namespace sgn {
 
-constexpr int BATCH_THREADS = 256;
-constexpr int BATCH_EPC = 16;                                  // M = N/2 <= BATCH_EPC * BATCH_THREADS
-constexpr int BATCH_NMAX = 2 * BATCH_EPC * BATCH_THREADS;     // 8192 points
+constexpr int BATCH_MMAX = 4096;                 // largest half length M = N/2
+constexpr int BATCH_NMAX = 2 * BATCH_MMAX;       // 8192 points
+// Complex points per thread and radix-4 pass for a workgroup of NT threads.
+template <int NT>
+constexpr int batch_epc() { return BATCH_MMAX / NT; }
 
 enum { BATCH_FP64 = 0, BATCH_MIXED = 1 };
 
@@ -45,7 +47,7 @@ struct BatchParams {
 __host__ __device__ inline long long batch_item_doubles(int n, int mode) {
     const long long M1 = n / 2 + 1;
     long long w = 5 * 2 * M1 + n;            // FP64: b, x, r, p, a_hat (spectral) + physical scratch
-    if (mode == BATCH_MIXED) w += 4 * M1 + 3 * ((n + 1) / 2);   // FP32: d, r, p, a_hat + eta, h_x, scratch
+    if (mode == BATCH_MIXED) w += n;         // FP32 eta and h_x
     return (w + 1) & ~1LL;
 }
 
@@ -86,54 +88,73 @@ __device__ __forceinline__ void blk_allmax(double (&v)[NACC], double* red) {
     __syncthreads();
 }
 
-// Forward real transform of N = 2M points held as pairs buf[j] = (x_2j, x_2j+1),
-// j < M: on return buf[k] = X_k = sum_n x_n W_N^{kn} for k = 0..M.  Whole block.
-template <typename T>
-__device__ __forceinline__ void blk_rfft_fwd(cpx<T>* buf, int M, const cpx<T>* __restrict__ tw_all) {
+// Forward real transforms of N = 2M points, NF fields at buf + f fstride held
+// as pairs buf[j] = (x_2j, x_2j+1), j < M: on return buf[k] = X_k =
+// sum_n x_n W_N^{kn} for k = 0..M.  Whole block; the fields in lockstep.
+template <typename T, int NT, int NF>
+__device__ __forceinline__ void blk_rfft_fwd_n(cpx<T>* buf, int fstride, int M, const cpx<T>* __restrict__ tw_all) {
     __syncthreads();
-    lds_fft<T, BATCH_EPC, 1>(buf, 0, M, threadIdx.x, blockDim.x, tw_size(tw_all, M), false);
+    lds_fft<T, batch_epc<NT>(), NF>(buf, fstride, M, threadIdx.x, blockDim.x, tw_size(tw_all, M), false);
     const cpx<T>* tw2 = tw_size(tw_all, 2 * M);
     const T half = (T)0.5;
     for (int p = threadIdx.x; p <= M / 2; p += blockDim.x) {
         const int k = p, m = M - p;
-        if (p == 0) {
-            const cpx<T> Z0 = buf[0];
-            buf[0] = C<T>(Z0.re + Z0.im, 0);
-            buf[M] = C<T>(Z0.re - Z0.im, 0);
-        } else {
-            const cpx<T> wk = tw2[k], wm = tw2[m];
-            const cpx<T> Zk = buf[k], Zm = buf[m];
-            const cpx<T> Xk = half * (Zk + cj(Zm)) - half * mul_i(wk * (Zk - cj(Zm)));
-            if (m != k) buf[m] = half * (Zm + cj(Zk)) - half * mul_i(wm * (Zm - cj(Zk)));
-            buf[k] = Xk;
+        const cpx<T> wk = tw2[k], wm = tw2[m];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cpx<T>* b = buf + f * fstride;
+            if (p == 0) {
+                const cpx<T> Z0 = b[0];
+                b[0] = C<T>(Z0.re + Z0.im, 0);
+                b[M] = C<T>(Z0.re - Z0.im, 0);
+            } else {
+                const cpx<T> Zk = b[k], Zm = b[m];
+                const cpx<T> Xk = half * (Zk + cj(Zm)) - half * mul_i(wk * (Zk - cj(Zm)));
+                if (m != k) b[m] = half * (Zm + cj(Zk)) - half * mul_i(wm * (Zm - cj(Zk)));
+                b[k] = Xk;
+            }
         }
     }
     __syncthreads();
 }
 
-// Inverse of blk_rfft_fwd up to the factor N: buf[k] = X_k (k = 0..M; the
+// Inverse of blk_rfft_fwd_n up to the factor N: buf[k] = X_k (k = 0..M; the
 // imaginary parts of X_0 and X_M are ignored) -> buf[j] = N (x_2j, x_2j+1).
-template <typename T>
-__device__ __forceinline__ void blk_rfft_inv(cpx<T>* buf, int M, const cpx<T>* __restrict__ tw_all) {
+template <typename T, int NT, int NF>
+__device__ __forceinline__ void blk_rfft_inv_n(cpx<T>* buf, int fstride, int M, const cpx<T>* __restrict__ tw_all) {
     __syncthreads();
     const cpx<T>* tw2 = tw_size(tw_all, 2 * M);
     for (int p = threadIdx.x; p <= M / 2; p += blockDim.x) {
         const int k = p, m = M - p;
-        if (p == 0) {
-            const T x0 = buf[0].re, xm = buf[M].re;
-            buf[0] = C<T>(x0 + xm, x0 - xm);
-        } else {
-            cpx<T> wk = tw2[k], wm = tw2[m];
-            wk.im = -wk.im;
-            wm.im = -wm.im;
-            const cpx<T> Xk = buf[k], Xm = buf[m];
-            const cpx<T> Zk = (Xk + cj(Xm)) + mul_i((Xk - cj(Xm)) * wk);
-            if (m != k) buf[m] = (Xm + cj(Xk)) + mul_i((Xm - cj(Xk)) * wm);
-            buf[k] = Zk;
+        cpx<T> wk = tw2[k], wm = tw2[m];
+        wk.im = -wk.im;
+        wm.im = -wm.im;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cpx<T>* b = buf + f * fstride;
+            if (p == 0) {
+                const T x0 = b[0].re, xm = b[M].re;
+                b[0] = C<T>(x0 + xm, x0 - xm);
+            } else {
+                const cpx<T> Xk = b[k], Xm = b[m];
+                const cpx<T> Zk = (Xk + cj(Xm)) + mul_i((Xk - cj(Xm)) * wk);
+                if (m != k) b[m] = (Xm + cj(Xk)) + mul_i((Xm - cj(Xk)) * wm);
+                b[k] = Zk;
+            }
         }
     }
     __syncthreads();
-    lds_fft<T, BATCH_EPC, 1>(buf, 0, M, threadIdx.x, blockDim.x, tw_size(tw_all, M), true);
+    lds_fft<T, batch_epc<NT>(), NF>(buf, fstride, M, threadIdx.x, blockDim.x, tw_size(tw_all, M), true);
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void blk_rfft_fwd(cpx<T>* buf, int M, const cpx<T>* __restrict__ tw_all) {
+    blk_rfft_fwd_n<T, NT, 1>(buf, 0, M, tw_all);
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void blk_rfft_inv(cpx<T>* buf, int M, const cpx<T>* __restrict__ tw_all) {
+    blk_rfft_inv_n<T, NT, 1>(buf, 0, M, tw_all);
 }
 
 // One system's view for G applies in precision T.
@@ -154,14 +175,14 @@ struct BatchOp {
 // curvature is known (pq, every thread) before q_hat is formed; `fin(k, kk,
 // q_k, pq)` then consumes q_hat mode by mode (kk the wavenumber) with the same
 // thread mapping as every other mode loop of the system.
-template <typename T, typename Fin>
+template <typename T, int NT, typename Fin>
 __device__ __forceinline__ void blk_apply(const BatchOp<T>& A, const cpx<T>* vh, cpx<T>* lds, double* red,
                                           Fin&& fin) {
     const int M = A.M, N = A.N;
     const T invN = (T)1 / (T)N;
     // D v into the physical scratch
     for (int k = threadIdx.x; k <= M; k += blockDim.x) lds[k] = invN * ik(wavenumber<T>(k, N, A.tp), vh[k]);
-    blk_rfft_inv<T>(lds, M, A.tw);
+    blk_rfft_inv<T, NT>(lds, M, A.tw);
     for (int j = threadIdx.x; j < M; j += blockDim.x) {
         A.scr[2 * j] = lds[j].re;
         A.scr[2 * j + 1] = lds[j].im;
@@ -169,7 +190,7 @@ __device__ __forceinline__ void blk_apply(const BatchOp<T>& A, const cpx<T>* vh,
     __syncthreads();
     // v, then the pointwise products (a into LDS, w into the scratch)
     for (int k = threadIdx.x; k <= M; k += blockDim.x) lds[k] = invN * vh[k];
-    blk_rfft_inv<T>(lds, M, A.tw);
+    blk_rfft_inv<T, NT>(lds, M, A.tw);
     const T third = (T)1 / (T)3, half = (T)0.5;
     double acc[1] = {0.0};
     for (int j = threadIdx.x; j < M; j += blockDim.x) {
@@ -192,11 +213,11 @@ __device__ __forceinline__ void blk_apply(const BatchOp<T>& A, const cpx<T>* vh,
     blk_allsum<1>(acc, red);
     const double pq = acc[0];
     // a_hat to the spectral scratch, then w_hat; q = a_hat - i k w_hat
-    blk_rfft_fwd<T>(lds, M, A.tw);
+    blk_rfft_fwd<T, NT>(lds, M, A.tw);
     for (int k = threadIdx.x; k <= M; k += blockDim.x) A.ah[k] = lds[k];
     __syncthreads();
     for (int j = threadIdx.x; j < M; j += blockDim.x) lds[j] = C<T>(A.scr[2 * j], A.scr[2 * j + 1]);
-    blk_rfft_fwd<T>(lds, M, A.tw);
+    blk_rfft_fwd<T, NT>(lds, M, A.tw);
     for (int k = threadIdx.x; k <= M; k += blockDim.x) {
         const T kk = wavenumber<T>(k, N, A.tp);
         fin(k, kk, A.ah[k] - ik(kk, lds[k]), pq);
@@ -210,50 +231,153 @@ __device__ __forceinline__ cpx<T> batch_precond(T kk, T sig, T alp, cpx<T> r) {
     return ((T)1 / (sig + alp * kk * kk)) * r;
 }
 
-// PCG of section 3.2 on G x = r0 in precision T from the state (x_hat, r_hat)
-// whose (r.z, r.r) are rz, rr; stops when r.r <= tol2 * bbref or after max_iter
-// iterations.  Returns the iterations; rr holds the last r.r.
-template <typename T>
-__device__ int blk_pcg(const BatchOp<T>& A, cpx<T>* xh, cpx<T>* rh, cpx<T>* ph, T sig, T alp, double tol2,
-                       double bbref, int max_iter, double& rz, double& rr, cpx<T>* lds, double* red) {
-    const int M = A.M, N = A.N;
-    const double invN = 1.0 / (double)N;
+template <typename T, typename U>
+__device__ __forceinline__ cpx<T> cvt(cpx<U> v) {
+    return C<T>((T)v.re, (T)v.im);
+}
+
+// PCG of section 3.2 on G d = r0 in precision T from d = 0, with the Krylov
+// vectors d, r, p in the registers of the workgroup (mode k of the half
+// spectrum in thread k mod NT, slot k / NT) and the transforms in two LDS
+// buffers (lds and lds + M + 1: p and D p inverse-transformed in lockstep, a and
+// w forward-transformed in lockstep), so the loop touches global memory for the
+// coefficient fields at most (REGCOEF: eta and h_x held in registers too).
+// r0 is read from r0h; on return xh += d (xh may hold a wider type).  Stops
+// when r.r <= tol2 * bbref or after max_iter iterations; returns the
+// iterations, rr the last r.r.
+template <typename T, int NT, bool REGCOEF, typename TX>
+__device__ int blk_pcg_reg(const BatchOp<T>& A, cpx<TX>* xh, const cpx<TX>* r0h, T sig, T alp, double tol2,
+                           double bbref, int max_iter, double& rr, cpx<T>* lds, double* red) {
+    constexpr int KPT = BATCH_MMAX / NT + 1;
+    constexpr int JPT = BATCH_MMAX / NT;
+    constexpr int JC = REGCOEF ? JPT : 1;
+    const int M = A.M, N = A.N, t = threadIdx.x;
+    const int fs = M + 1;
+    cpx<T>* la = lds;
+    cpx<T>* lb = lds + fs;
+    const T invN = (T)1 / (T)N;
+    const double dinvN = 1.0 / (double)N;
+    cpx<T> x[KPT], r[KPT], p[KPT];
+    T er[JC][2], hr[JC][2];
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < KPT; ++e) {
+        const int k = t + NT * e;
+        x[e] = C<T>(0, 0);
+        p[e] = C<T>(0, 0);
+        r[e] = C<T>(0, 0);
+        if (k <= M) {
+            r[e] = cvt<T>(r0h[k]);
+            const cpx<T> z = batch_precond<T>(wavenumber<T>(k, N, A.tp), sig, alp, r[e]);
+            const double w = half_weight(k, N) * dinvN;
+            acc[0] += w * ((double)r[e].re * (double)z.re + (double)r[e].im * (double)z.im);
+            acc[1] += w * ((double)r[e].re * (double)r[e].re + (double)r[e].im * (double)r[e].im);
+        }
+    }
+    if (REGCOEF) {
+#pragma unroll
+        for (int e = 0; e < JC; ++e) {
+            const int j = t + NT * e;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                er[e][s] = j < M ? A.eta[2 * j + s] : (T)0;
+                hr[e][s] = j < M ? A.hx[2 * j + s] : (T)0;
+            }
+        }
+    }
+    blk_allsum<2>(acc, red);
+    double rz = acc[0];
+    rr = acc[1];
     double rho_prev = 1.0;
     int it = 0;
+    const T third = (T)1 / (T)3, half = (T)0.5;
     while (!(rr <= tol2 * bbref) && it < max_iter && rr == rr) {
         const T beta = it == 0 ? (T)0 : (T)(rz / rho_prev);
-        for (int k = threadIdx.x; k <= M; k += blockDim.x) {
-            const cpx<T> z = batch_precond<T>(wavenumber<T>(k, N, A.tp), sig, alp, rh[k]);
-            ph[k] = it == 0 ? z : z + beta * ph[k];
+        // p = z + beta p; p / N and i k p / N into the two buffers
+#pragma unroll
+        for (int e = 0; e < KPT; ++e) {
+            const int k = t + NT * e;
+            const T kk = wavenumber<T>(k, N, A.tp);
+            const cpx<T> z = batch_precond<T>(kk, sig, alp, r[e]);
+            p[e] = it == 0 ? z : z + beta * p[e];
+            if (k <= M) {
+                la[k] = invN * p[e];
+                lb[k] = invN * ik(kk, p[e]);
+            }
         }
+        blk_rfft_inv_n<T, NT, 2>(lds, fs, M, A.tw);
+        // pointwise: a into buffer a, w into buffer b; curvature p.Gp
+        double pqa[1] = {0.0};
+#pragma unroll
+        for (int e = 0; e < JPT; ++e) {
+            const int j = t + NT * e;
+            if (j < M) {
+                cpx<T> pv = la[j], dv = lb[j];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const T pp = s ? pv.im : pv.re;
+                    const T dl = s ? dv.im : dv.re;
+                    const T et = REGCOEF ? er[REGCOEF ? e : 0][s] : A.eta[2 * j + s];
+                    const T h = REGCOEF ? hr[REGCOEF ? e : 0][s] : A.hx[2 * j + s];
+                    const T bt = h * pp, e2 = et * et;
+                    const T w1 = third * e2 * et * dl + half * e2 * bt;
+                    const T w2 = half * e2 * dl + et * bt;
+                    const T a = et * pp + h * w2;
+                    pqa[0] += (double)et * (double)pp * (double)pp + (double)dl * (double)w1 + (double)bt * (double)w2;
+                    if (s) {
+                        pv.im = a;
+                        dv.im = w1;
+                    } else {
+                        pv.re = a;
+                        dv.re = w1;
+                    }
+                }
+                la[j] = pv;
+                lb[j] = dv;
+            }
+        }
+        blk_allsum<1>(pqa, red);
         const double rho = rz;
-        double acc[2] = {0.0, 0.0};
-        blk_apply<T>(A, ph, lds, red, [&](int k, T kk, cpx<T> q, double pq) {
-            const T alpha = (T)(rho / pq);
-            xh[k] = xh[k] + alpha * ph[k];
-            const cpx<T> r = rh[k] - alpha * q;
-            rh[k] = r;
-            const cpx<T> z = batch_precond<T>(kk, sig, alp, r);
-            const double w = half_weight(k, N) * invN;
-            acc[0] += w * ((double)r.re * (double)z.re + (double)r.im * (double)z.im);
-            acc[1] += w * ((double)r.re * (double)r.re + (double)r.im * (double)r.im);
-        });
+        const T alpha = (T)(rho / pqa[0]);
+        blk_rfft_fwd_n<T, NT, 2>(lds, fs, M, A.tw);
+        acc[0] = acc[1] = 0.0;
+#pragma unroll
+        for (int e = 0; e < KPT; ++e) {
+            const int k = t + NT * e;
+            if (k <= M) {
+                const T kk = wavenumber<T>(k, N, A.tp);
+                const cpx<T> q = la[k] - ik(kk, lb[k]);
+                x[e] = x[e] + alpha * p[e];
+                r[e] = r[e] - alpha * q;
+                const cpx<T> z = batch_precond<T>(kk, sig, alp, r[e]);
+                const double w = half_weight(k, N) * dinvN;
+                acc[0] += w * ((double)r[e].re * (double)z.re + (double)r[e].im * (double)z.im);
+                acc[1] += w * ((double)r[e].re * (double)r[e].re + (double)r[e].im * (double)r[e].im);
+            }
+        }
         blk_allsum<2>(acc, red);
         rho_prev = rho;
         rz = acc[0];
         rr = acc[1];
         ++it;
     }
+#pragma unroll
+    for (int e = 0; e < KPT; ++e) {
+        const int k = t + NT * e;
+        if (k <= M) xh[k] = xh[k] + cvt<TX>(x[e]);
+    }
+    __syncthreads();
     return it;
 }
 
 // r_hat = b_hat - G x_hat in FP64, with its (r.z, r.r).
+template <int NT>
 __device__ __forceinline__ void blk_residual(const BatchOp<double>& A, const cpx<double>* bh, const cpx<double>* xh,
                                              cpx<double>* rh, double sig, double alp, double& rz, double& rr,
                                              cpx<double>* lds, double* red) {
     const double invN = 1.0 / (double)A.N;
     double acc[2] = {0.0, 0.0};
-    blk_apply<double>(A, xh, lds, red, [&](int k, double kk, cpx<double> q, double) {
+    blk_apply<double, NT>(A, xh, lds, red, [&](int k, double kk, cpx<double> q, double) {
         const cpx<double> r = bh[k] - q;
         rh[k] = r;
         const cpx<double> z = batch_precond<double>(kk, sig, alp, r);
@@ -267,17 +391,18 @@ __device__ __forceinline__ void blk_residual(const BatchOp<double>& A, const cpx
 }
 
 // Transform N physical FP64 points into modes 0..M (dst), returning sum x^2.
+template <int NT>
 __device__ __forceinline__ void blk_to_spectral(const double* x, int N, cpx<double>* dst,
                                                 const cpx<double>* tw, cpx<double>* lds) {
     const int M = N / 2;
     for (int j = threadIdx.x; j < M; j += blockDim.x) lds[j] = C<double>(x[2 * j], x[2 * j + 1]);
-    blk_rfft_fwd<double>(lds, M, tw);
+    blk_rfft_fwd<double, NT>(lds, M, tw);
     for (int k = threadIdx.x; k <= M; k += blockDim.x) dst[k] = lds[k];
     __syncthreads();
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(BATCH_THREADS) k_batch_solve(const BatchItem* __restrict__ items, int nitems,
+template <int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_batch_solve(const BatchItem* __restrict__ items, int nitems,
                                                                const double* __restrict__ eta_all,
                                                                const double* __restrict__ hx_all,
                                                                const double* __restrict__ b_all,
@@ -338,7 +463,7 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_solve(const BatchItem* 
         out.kap = kap;
         out.flat = fl;
         // b_hat, ||b||^2, and the initial x_hat, r_hat
-        blk_to_spectral(b_all + it.off, N, bh, tw64, lds64);
+        blk_to_spectral<NT>(b_all + it.off, N, bh, tw64, lds64);
         double bb = 0.0, rz = 0.0, rr = 0.0;
         {
             double acc[2] = {0.0, 0.0};
@@ -357,8 +482,8 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_solve(const BatchItem* 
         }
         const double tol2 = prm.tol * prm.tol;
         if (prm.x0_is_guess && bb > 0.0) {
-            blk_to_spectral(u_all + it.off, N, xh, tw64, lds64);
-            blk_residual(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
+            blk_to_spectral<NT>(u_all + it.off, N, xh, tw64, lds64);
+            blk_residual<NT>(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
         } else {
             for (int k = threadIdx.x; k <= M; k += blockDim.x) {
                 xh[k] = C<double>(0, 0);
@@ -367,56 +492,34 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_solve(const BatchItem* 
             __syncthreads();
         }
         if (MODE == BATCH_FP64) {
-            out.iters = blk_pcg<double>(A64, xh, rh, ph, sig, alp, tol2, bb, prm.max_iter, rz, rr, lds64, red);
+            out.iters = blk_pcg_reg<double, NT, false>(A64, xh, rh, sig, alp, tol2, bb, prm.max_iter, rr, lds64, red);
         } else {
-            // FP32 view of the same system
-            float* w32 = reinterpret_cast<float*>(A64.scr + N);
-            cpx<float>* dh = reinterpret_cast<cpx<float>*>(w32);
-            cpx<float>* r32 = dh + (M + 1);
-            cpx<float>* p32 = r32 + (M + 1);
+            // FP32 view of the same system: coefficient fields rounded once
+            float* e32 = reinterpret_cast<float*>(A64.scr + N);
+            float* h32 = e32 + N;
             BatchOp<float> A32;
             A32.N = N;
             A32.M = M;
             A32.tp = (float)A64.tp;
-            A32.ah = p32 + (M + 1);
-            float* e32 = reinterpret_cast<float*>(A32.ah + (M + 1));
-            float* h32 = e32 + N;
             A32.eta = e32;
             A32.hx = h32;
-            A32.scr = h32 + N;
+            A32.scr = nullptr;
+            A32.ah = nullptr;
             A32.tw = tw32;
             for (int i = threadIdx.x; i < N; i += blockDim.x) {
                 e32[i] = (float)eta[i];
                 h32[i] = (float)hx[i];
             }
+            __syncthreads();
             const float sig32 = (float)sig, alp32 = (float)alp;
             const double itol2 = prm.inner_tol * prm.inner_tol;
             while (!(rr <= tol2 * bb) && rr == rr && out.outer < prm.max_outer && bb > 0.0) {
-                // inner: G d = r from d = 0 to inner_tol ||r||
-                double irz = 0.0, irr = 0.0;
-                {
-                    double acc[2] = {0.0, 0.0};
-                    for (int k = threadIdx.x; k <= M; k += blockDim.x) {
-                        const cpx<float> r = C<float>((float)rh[k].re, (float)rh[k].im);
-                        r32[k] = r;
-                        dh[k] = C<float>(0, 0);
-                        const cpx<float> z = batch_precond<float>(wavenumber<float>(k, N, A32.tp), sig32, alp32, r);
-                        const double wt = half_weight(k, N) / (double)N;
-                        acc[0] += wt * ((double)r.re * (double)z.re + (double)r.im * (double)z.im);
-                        acc[1] += wt * ((double)r.re * (double)r.re + (double)r.im * (double)r.im);
-                    }
-                    blk_allsum<2>(acc, red);
-                    irz = acc[0];
-                    irr = acc[1];
-                }
-                const double rr_outer = irr;
-                out.iters += blk_pcg<float>(A32, dh, r32, p32, sig32, alp32, itol2, rr_outer, prm.max_iter, irz, irr,
-                                            lds32, red);
-                // x += d; r = b - G x (FP64)
-                for (int k = threadIdx.x; k <= M; k += blockDim.x)
-                    xh[k] = xh[k] + C<double>((double)dh[k].re, (double)dh[k].im);
-                __syncthreads();
-                blk_residual(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
+                // inner FP32 solve of G d = r to inner_tol ||r||, then x += d and
+                // the FP64 residual r = b - G x
+                double irr = 0.0;
+                out.iters += blk_pcg_reg<float, NT, true>(A32, xh, rh, sig32, alp32, itol2, rr, prm.max_iter, irr,
+                                                          lds32, red);
+                blk_residual<NT>(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
                 out.outer += 1;
             }
         }
@@ -426,7 +529,7 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_solve(const BatchItem* 
         // u = x (physical)
         const double invN = 1.0 / (double)N;
         for (int k = threadIdx.x; k <= M; k += blockDim.x) lds64[k] = invN * xh[k];
-        blk_rfft_inv<double>(lds64, M, tw64);
+        blk_rfft_inv<double, NT>(lds64, M, tw64);
         double* u = u_all + it.off;
         for (int j = threadIdx.x; j < M; j += blockDim.x) {
             u[2 * j] = lds64[j].re;

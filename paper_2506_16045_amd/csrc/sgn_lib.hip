@@ -46,6 +46,7 @@ struct sgn_ctx {
     int last_iters[2][GUESS_SLOTS + 1] = {};
     bool stage = false;           // solving inside a stepper: skip the final scalar readback
     int cus = 256;                // compute units of the device
+    int batch_threads = 512;      // workgroup size of the batched solver (SGN_BATCH_THREADS: 256, 512, 1024)
     void* hbatch = nullptr;       // pinned staging of batch item tables and results
     size_t hbatch_bytes = 0;
     int slot = GUESS_SLOTS;       // stepper slot of the running solve
@@ -1561,6 +1562,8 @@ sgn_status sgn_create(sgn_ctx** out, int device, void* hip_stream) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         ctx->cus = cus;
+    const char* bt = getenv("SGN_BATCH_THREADS");
+    if (bt) ctx->batch_threads = atoi(bt);
     const char* ng = getenv("SGN_NO_GRAPHS");
     if (ng && ng[0] && ng[0] != '0') ctx->use_graphs = false;
     *out = ctx;
@@ -1833,15 +1836,29 @@ sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const
     prm.x0_is_guess = o.x0_is_guess ? 1 : 0;
     prm.coeff_kind = o.coeff_kind;
     prm.nitems = nitems;
-    const size_t lds = (size_t)(nmax / 2 + 1) * sizeof(cpx<double>);
-    const int grid = std::min(nitems, 2 * ctx->cus);
+    // two transform buffers of M+1 modes: FP64 ones in FP64 mode; in mixed mode
+    // the FP32 pair or one FP64 buffer (the refinement residual), whichever is larger
+    const size_t lds = (size_t)(nmax / 2 + 1) * sizeof(cpx<double>) * (mode == BATCH_FP64 ? 2 : 1);
     {
         ProfScope ps(ctx, SGN_KERNEL_BATCH);
-        auto k = mode == BATCH_MIXED ? k_batch_solve<BATCH_MIXED> : k_batch_solve<BATCH_FP64>;
-        HIPCHK(ctx, allow_lds(k, lds));
-        hipLaunchKernelGGL(k, dim3(grid), dim3(BATCH_THREADS), lds, ctx->stream, (const BatchItem*)d_items, nitems,
-                           eta, grad_h, rhs, u, d_data, ctx->tw64, ctx->tw32, prm, d_res);
-        CHECK_LAUNCH(ctx);
+        auto launch = [&](auto k, int nt) -> sgn_status {
+            HIPCHK(ctx, allow_lds(k, lds));
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, nt, lds) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            const int grid = std::min(nitems, per_cu * ctx->cus);
+            hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, ctx->stream, (const BatchItem*)d_items, nitems, eta,
+                               grad_h, rhs, u, d_data, ctx->tw64, ctx->tw32, prm, d_res);
+            CHECK_LAUNCH(ctx);
+            return SGN_OK;
+        };
+        const bool mx = mode == BATCH_MIXED;
+        switch (ctx->batch_threads) {
+            case 1024: s = mx ? launch(k_batch_solve<BATCH_MIXED, 1024>, 1024) : launch(k_batch_solve<BATCH_FP64, 1024>, 1024); break;
+            case 512: s = mx ? launch(k_batch_solve<BATCH_MIXED, 512>, 512) : launch(k_batch_solve<BATCH_FP64, 512>, 512); break;
+            default: s = mx ? launch(k_batch_solve<BATCH_MIXED, 256>, 256) : launch(k_batch_solve<BATCH_FP64, 256>, 256); break;
+        }
+        if (s != SGN_OK) return s;
     }
     BatchResult* hres = static_cast<BatchResult*>(ctx->hbatch);
     HIPCHK(ctx, hipMemcpyAsync(hres, d_res, sizeof(BatchResult) * (size_t)nitems, hipMemcpyDeviceToHost, ctx->stream));
