@@ -278,6 +278,80 @@ sgn_status sgn_step_linimp(sgn_ctx *ctx, sgn_state *state, double dt, int32_t ns
                            const sgn_coeffs *fixed, const sgn_solve_opts *opts,
                            sgn_step_info *info);
 
+/* ---- served execution --------------------------------------------------
+ * A request server on one device.  Requests (constraint solves and RK4
+ * time-steps of 1D or 2D grids) are submitted from any host thread with host
+ * input arrays (copied at submission) and host output arrays (written when the
+ * request completes).  A request is admitted once its device footprint (its
+ * fields, Krylov workspace and stepping state) fits in the server's HBM budget
+ * beside the admitted ones; admitted requests keep their fields and Krylov
+ * state on the device until they complete, then release their memory.
+ * Continuous batching: admitted 1D solves with nx <= 8192 are gathered into
+ * one sgn_batch_solve launch whenever the batching lane is free, so requests
+ * that arrive while a batch runs join the next launch; every other request
+ * runs on one of the worker lanes (each its own context and HIP stream), so
+ * batches, solves and steps overlap on the device.  A request's result does
+ * not depend on what it was batched or overlapped with (the kernels reduce in
+ * a fixed order). */
+typedef struct sgn_server sgn_server;
+
+typedef struct sgn_server_opts {
+    size_t hbm_budget;      /* bytes; 0 = 80% of the device memory free at creation */
+    int32_t lanes;          /* worker lanes (>= 1; 0 = 3) */
+    int32_t max_batch;      /* most 1D solves per batched launch (0 = 1024) */
+} sgn_server_opts;
+
+typedef enum sgn_request_kind {
+    SGN_REQ_SOLVE = 0,      /* G_{eta,h} u = rhs (sgn_krylov_solve / sgn_batch_solve) */
+    SGN_REQ_STEP_RK4 = 1    /* nsteps RK4 steps of (eta, u) over bathymetry h (sgn_step_rk4) */
+} sgn_request_kind;
+
+typedef struct sgn_request {
+    int32_t kind;            /* sgn_request_kind */
+    sgn_grid grid;
+    sgn_solve_opts opts;     /* Krylov options of the solve or of every stage solve */
+    const double *h_eta;     /* [N] total depth (both kinds) */
+    const double *h_grad_h;  /* [d][N] bathymetry gradient (SOLVE) */
+    const double *h_rhs;     /* [d][N] right-hand side (SOLVE) */
+    const double *h_h;       /* [N] bathymetry (STEP) */
+    const double *h_u0;      /* [d][N] initial guess (SOLVE, read iff opts.x0_is_guess) or initial velocity (STEP) */
+    double dt;               /* STEP */
+    int32_t nsteps;          /* STEP */
+    double *h_eta_out;       /* [N] eta after the steps (STEP; may be NULL) */
+    double *h_u_out;         /* [d][N] solution (SOLVE) or velocity after the steps (STEP) */
+} sgn_request;
+
+typedef struct sgn_result {
+    int32_t done;            /* 1 once the outputs are written */
+    int32_t status;          /* sgn_status of the request */
+    int64_t iters;           /* Krylov iterations (summed over the solves of a STEP) */
+    int64_t solves;
+    double relres;           /* SOLVE: final relative residual */
+    double t_submit, t_admit, t_start, t_done;  /* seconds on the server's clock */
+    int32_t batched;         /* 1 if solved inside a batched launch */
+    int32_t batch_size;      /* systems in that launch */
+} sgn_result;
+
+/* Create a server on `device`.  opts = NULL: defaults.  Starts the lanes. */
+sgn_status sgn_server_create(sgn_server **server, int device, const sgn_server_opts *opts);
+/* Stop accepting requests, finish the admitted and queued ones, join the lanes
+ * and free every device buffer. */
+void sgn_server_destroy(sgn_server *server);
+/* Device bytes a request needs while admitted (0 if the request is invalid). */
+size_t sgn_request_footprint(const sgn_request *req);
+/* Queue a request; *id identifies it.  SGN_EINVAL for an invalid request,
+ * SGN_ENOMEM if its footprint exceeds the whole budget. */
+sgn_status sgn_server_submit(sgn_server *server, const sgn_request *req, uint64_t *id);
+/* Result of a request (done = 0 while it is queued or running); after a done
+ * result has been returned the request is forgotten. */
+sgn_status sgn_server_poll(sgn_server *server, uint64_t id, sgn_result *result);
+/* Block until the request is done (timeout_s < 0: no limit); on timeout
+ * returns SGN_OK with result->done = 0. */
+sgn_status sgn_server_wait(sgn_server *server, uint64_t id, double timeout_s, sgn_result *result);
+/* Requests queued, admitted and completed so far, and the admitted footprint. */
+sgn_status sgn_server_stats(sgn_server *server, int64_t *queued, int64_t *admitted, int64_t *completed,
+                            size_t *bytes_in_use, size_t *budget);
+
 #ifdef __cplusplus
 }
 #endif

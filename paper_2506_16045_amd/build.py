@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsgn.so")
-SOURCES = ["sgn_lib.hip"]
+SOURCES = ["sgn_lib.hip", "sgn_server.hip"]
 ARCH = os.environ.get("SGN_OFFLOAD_ARCH", "gfx950")
 
 

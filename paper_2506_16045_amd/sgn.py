@@ -71,6 +71,27 @@ class StepInfo(ctypes.Structure):
                 ("converged", ctypes.c_int32), ("t", ctypes.c_double), ("steps_done", ctypes.c_int64)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("lanes", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+REQ_SOLVE, REQ_STEP_RK4 = 0, 1
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("grid", Grid), ("opts", SolveOpts),
+                ("h_eta", ctypes.c_void_p), ("h_grad_h", ctypes.c_void_p), ("h_rhs", ctypes.c_void_p),
+                ("h_h", ctypes.c_void_p), ("h_u0", ctypes.c_void_p), ("dt", ctypes.c_double),
+                ("nsteps", ctypes.c_int32), ("h_eta_out", ctypes.c_void_p), ("h_u_out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("iters", ctypes.c_int64),
+                ("solves", ctypes.c_int64), ("relres", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("batched", ctypes.c_int32), ("batch_size", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
 _D = ctypes.c_double
@@ -92,6 +113,15 @@ _SIGS = {
                               ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
     "sgn_rhs": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P]),
     "sgn_batch_workspace_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I]),
+    "sgn_request_footprint": (ctypes.c_size_t, [ctypes.POINTER(Request)]),
+    "sgn_server_create": (_S, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ServerOpts)]),
+    "sgn_server_destroy": (None, [_P]),
+    "sgn_server_submit": (_S, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "sgn_server_poll": (_S, [_P, ctypes.c_uint64, ctypes.POINTER(Result)]),
+    "sgn_server_wait": (_S, [_P, ctypes.c_uint64, _D, ctypes.POINTER(Result)]),
+    "sgn_server_stats": (_S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t),
+                              ctypes.POINTER(ctypes.c_size_t)]),
     "sgn_batch_solve": (_S, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_D), _P, _P, _P, _P,
                              ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
     "sgn_state_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
@@ -405,3 +435,109 @@ class State:
                                              ctypes.byref(fixed) if fixed else None,
                                              ctypes.byref(opts) if opts else None, ctypes.byref(info)))
         return info
+
+
+# ---- served execution ------------------------------------------------------------
+class Server:
+    """Request server (sgn_server_*): host numpy inputs are copied at submission;
+    outputs are numpy arrays returned by wait()/poll() once the request is done."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, lanes: int = 3, max_batch: int = 1024):
+        import numpy as np  # noqa: F401  (inputs are numpy arrays)
+        self._h = _P()
+        opts = ServerOpts(int(hbm_budget), int(lanes), int(max_batch))
+        st = _lib.sgn_server_create(ctypes.byref(self._h), device, ctypes.byref(opts))
+        if st != OK:
+            raise SgnError(st, "sgn_server_create failed")
+        self._out = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.sgn_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _arr(a, shape, name):
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if tuple(a.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {a.shape}, expected {tuple(shape)}")
+        return a
+
+    def _request(self, kind, g, opts):
+        req = Request()
+        req.kind = kind
+        req.grid = make_grid(g)
+        req.opts = opts if opts is not None else solve_opts()
+        return req
+
+    def solve_request(self, g, eta, grad_h, rhs, u0=None, opts: SolveOpts | None = None):
+        import numpy as np
+        req = self._request(REQ_SOLVE, g, opts)
+        keep = [self._arr(eta, _scalar_shape(g), "eta"), self._arr(grad_h, _vector_shape(g), "grad_h"),
+                self._arr(rhs, _vector_shape(g), "rhs")]
+        req.h_eta, req.h_grad_h, req.h_rhs = (k.ctypes.data for k in keep)
+        if u0 is not None:
+            keep.append(self._arr(u0, _vector_shape(g), "u0"))
+            req.h_u0 = keep[-1].ctypes.data
+        u_out = np.zeros(_vector_shape(g))
+        req.h_u_out = u_out.ctypes.data
+        return req, keep, {"u": u_out}
+
+    def step_request(self, g, h, eta, u0, dt: float, nsteps: int, opts: SolveOpts | None = None):
+        import numpy as np
+        req = self._request(REQ_STEP_RK4, g, opts)
+        keep = [self._arr(h, _scalar_shape(g), "h"), self._arr(eta, _scalar_shape(g), "eta"),
+                self._arr(u0, _vector_shape(g), "u0")]
+        req.h_h, req.h_eta, req.h_u0 = (k.ctypes.data for k in keep)
+        req.dt = float(dt)
+        req.nsteps = int(nsteps)
+        out = {"eta": np.zeros(_scalar_shape(g)), "u": np.zeros(_vector_shape(g))}
+        req.h_eta_out = out["eta"].ctypes.data
+        req.h_u_out = out["u"].ctypes.data
+        return req, keep, out
+
+    @staticmethod
+    def footprint(req_tuple) -> int:
+        return int(_lib.sgn_request_footprint(ctypes.byref(req_tuple[0])))
+
+    def submit(self, req_tuple) -> int:
+        req, keep, out = req_tuple
+        rid = ctypes.c_uint64()
+        st = _lib.sgn_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid))
+        if st != OK:
+            raise SgnError(st, "request rejected")
+        self._out[rid.value] = out       # the output arrays stay alive until the result is read
+        return rid.value
+
+    def _finish(self, rid, res: Result):
+        out = self._out.pop(rid) if res.done else None
+        return res, out
+
+    def poll(self, rid: int):
+        res = Result()
+        st = _lib.sgn_server_poll(self._h, rid, ctypes.byref(res))
+        if st != OK:
+            raise SgnError(st, "unknown request")
+        return self._finish(rid, res)
+
+    def wait(self, rid: int, timeout: float = -1.0):
+        res = Result()
+        st = _lib.sgn_server_wait(self._h, rid, float(timeout), ctypes.byref(res))
+        if st != OK:
+            raise SgnError(st, "unknown request")
+        return self._finish(rid, res)
+
+    def stats(self):
+        q, a, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        used, budget = ctypes.c_size_t(), ctypes.c_size_t()
+        _lib.sgn_server_stats(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(c), ctypes.byref(used),
+                              ctypes.byref(budget))
+        return {"queued": q.value, "admitted": a.value, "completed": c.value, "bytes_in_use": used.value,
+                "budget": budget.value}
