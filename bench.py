@@ -25,6 +25,13 @@ independent 1D constraint solves G u = b with sizes drawn from
 {512, ..., 8192} on L = 400, random Gaussian bumps and random solitary waves,
 b = G u* formed on the device, all solved in one launch per step (a step is
 one batched solve of the whole ensemble from a zero guess, to 1e-10).
+
+--workload serve measures the request server: Poisson arrivals at each rate
+of --rates (requests per second), --serve-requests requests per rate, 70% 1D
+(N 1024..16384) and 30% 2D (128^2..1024^2) grids, half single constraint
+solves and half 10-step RK4 runs, admitted by HBM footprint; the line reports
+throughput and p50/p99 latency (submission to result on the host) per rate,
+for the FP64 and the mixed-precision path.
 """
 from __future__ import annotations
 
@@ -235,6 +242,129 @@ def bench_batch(args):
     return 0
 
 
+def bench_serve(args):
+    import numpy as np
+    import torch
+
+    from paper_2506_16045_amd import inputs as I
+    from paper_2506_16045_amd import sgn
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    rates = [float(r) for r in args.rates.split(",")]
+    nreq = args.serve_requests
+    rng = np.random.default_rng(I.SEED_BASE + 5)
+    ctx = sgn.Context(0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    # a few distinct payloads per (kind, dim, size), built before any timing;
+    # solve right-hand sides b = G u* and grad h are formed on the device
+    per = 3
+    pool = {}
+    for dim, sizes in ((1, I.C5_SIZES_1D), (2, I.C5_SIZES_2D)):
+        for n in sizes:
+            for kind in ("solve", "step"):
+                lst = []
+                for _ in range(per):
+                    r = I.config_c5_request(rng, kind=kind, dim=dim, n=n)
+                    g = r["grid"]
+                    gh, _ = ctx.bathy_prepare(g, to(r["h"]))
+                    if kind == "solve":
+                        b = ctx.apply_constraint(g, to(r["eta"]), gh, to(r["u"]))
+                        r["gh"] = gh.cpu().numpy()
+                        r["rhs"] = b.cpu().numpy()
+                    lst.append(r)
+                pool[(kind, dim, n)] = lst
+    ctx.close()
+    torch.cuda.synchronize()
+    # the request sequence (same for every precision and rate)
+    seq = []
+    for _ in range(nreq):
+        dim = 1 if rng.uniform() < 0.7 else 2
+        kind = "solve" if rng.uniform() < 0.5 else "step"
+        n = int(rng.choice(np.asarray(I.C5_SIZES_1D if dim == 1 else I.C5_SIZES_2D)))
+        seq.append((kind, dim, n, int(rng.integers(0, per))))
+
+    def make(srv, key, opts):
+        kind, dim, n, k = key
+        r = pool[(kind, dim, n)][k]
+        if kind == "solve":
+            return srv.solve_request(r["grid"], r["eta"], r["gh"], r["rhs"], opts=opts)
+        return srv.step_request(r["grid"], r["h"], r["eta"], r["u"], r["dt"], r["nsteps"], opts=opts)
+
+    precs = ["fp64", "mixed"] if args.precision_serve == "both" else [args.precision_serve]
+    results = {}
+    for pname in precs:
+        prec = sgn.MIXED if pname == "mixed" else sgn.FP64
+        opts = sgn.solve_opts(tol=1e-10, precision=prec, inner_tol=args.inner_tol, max_iter=5000, max_outer=40)
+        srv = sgn.Server(0, lanes=args.lanes)
+        for key in sorted({(k, d, n, 0) for (k, d, n, _) in seq}):
+            srv.wait(srv.submit(make(srv, key, opts)))          # warm-up: one request of each shape
+        rows = []
+        for rate in rates:
+            gaps = np.random.default_rng(I.SEED_BASE + int(rate)).exponential(1.0 / rate, nreq)
+            arrive = np.cumsum(gaps)
+            ids = []
+            t0 = time.perf_counter()
+            for key, ta in zip(seq, arrive):
+                dt = t0 + ta - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                ids.append((key, srv.submit(make(srv, key, opts))))
+            t_sub_end = time.perf_counter() - t0
+            res = []
+            for key, rid in ids:
+                r, _ = srv.wait(rid)
+                if r.status != sgn.OK:
+                    raise RuntimeError(f"request {key} failed with status {r.status}")
+                res.append((key, r))
+            lat = [1e3 * (r.t_done - r.t_submit) for _, r in res]
+            t_first = min(r.t_submit for _, r in res)
+            t_last = max(r.t_done for _, r in res)
+            span = t_last - t_first
+            pts = sum(pool[(k[0], k[1], k[2])][0]["grid"].npts * pool[(k[0], k[1], k[2])][0]["nsteps"]
+                      for k, _ in res if k[0] == "step")
+            row = {"rate": rate, "offered_req_s": nreq / max(t_sub_end, 1e-9), "throughput_req_s": nreq / span,
+                   "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99),
+                   "grid_pt_steps_s": pts / span,
+                   "batched_fraction": sum(1 for _, r in res if r.batched) / nreq,
+                   "mean_batch": float(np.mean([r.batch_size for _, r in res if r.batched] or [0]))}
+            for kind in ("solve", "step"):
+                lk = [1e3 * (r.t_done - r.t_submit) for k, r in res if k[0] == kind]
+                row[f"{kind}_p50_ms"] = percentile(lk, 0.5)
+                row[f"{kind}_p99_ms"] = percentile(lk, 0.99)
+            rows.append(row)
+            print(json.dumps({"serve_progress": pname, **{k: round(v, 3) for k, v in row.items()}}),
+                  file=sys.stderr, flush=True)
+        srv.close()
+        results[pname] = rows
+    best = max(results, key=lambda p: results[p][-1]["throughput_req_s"])
+    out = {
+        "metric": "served SGN requests: throughput and p50/p99 latency per Poisson arrival rate",
+        "value": results[best][-1]["throughput_req_s"],
+        "unit": "req/s",
+        "n_gpus": 1,
+        "steps": nreq,
+        "warmup": 1,
+        "ms_per_step": 1e3 / results[best][-1]["throughput_req_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if best == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"served stream: {nreq} requests per rate, 70% 1D N 1024..16384 / 30% 2D "
+                                "128^2..1024^2, half solves (tol 1e-10) and half 10-step RK4 runs, Poisson "
+                                f"arrivals at {args.rates} req/s, {args.lanes} worker lanes + a batching lane"),
+                   "rates": rates, "requests_per_rate": nreq, "parallelism": "single GPU"},
+        "value_precision": best,
+        "per_rate": results,
+        "roofline": None,
+        "cpu_baseline": None,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def cpu_baseline_batch(systems, tol, count):
     """The oracle's PCG, as it stands, on the first `count` systems of the ensemble
     (forming b = G u* is not timed)."""
@@ -260,7 +390,11 @@ def cpu_baseline_batch(systems, tol, count):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["rk4-2d", "batch"], default="rk4-2d")
+    ap.add_argument("--workload", choices=["rk4-2d", "batch", "serve"], default="rk4-2d")
+    ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="arrival rates of the serve workload")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests per rate (serve workload)")
+    ap.add_argument("--lanes", type=int, default=3, help="worker lanes of the server (serve workload)")
+    ap.add_argument("--precision-serve", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--count", type=int, default=512, help="systems of the batched workload")
     ap.add_argument("--cpu-sample", type=int, default=512, help="systems the CPU oracle solves for its baseline")
     ap.add_argument("--steps", type=int, default=40)
@@ -307,6 +441,8 @@ def main(argv=None):
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch

@@ -40,7 +40,11 @@ struct BatchResult {
 
 struct BatchParams {
     double tol, inner_tol;
-    int max_iter, max_outer, x0_is_guess, coeff_kind, nitems, pad;
+    int max_iter, max_outer, x0_is_guess, coeff_kind, nitems;
+    int flat;             // -1: flat formulas iff h_x == 0; 0 / 1: forced
+    int have_coeffs;      // 1: use sig, alp, kap (and flat) as given
+    int pad;
+    double sig, alp, kap;
 };
 
 // Doubles of workspace one system of n points uses in the given mode.
@@ -457,7 +461,14 @@ __global__ void __launch_bounds__(NT) k_batch_solve(const BatchItem* __restrict_
         }
         double sig, alp, kap;
         int fl;
-        coeffs_formula(emin, ex[1], ex[2], ex[3], -1, prm.coeff_kind, sig, alp, kap, fl);
+        if (prm.have_coeffs) {
+            sig = prm.sig;
+            alp = prm.alp;
+            kap = prm.kap;
+            fl = prm.flat;
+        } else {
+            coeffs_formula(emin, ex[1], ex[2], ex[3], prm.flat, prm.coeff_kind, sig, alp, kap, fl);
+        }
         out.sig = sig;
         out.alp = alp;
         out.kap = kap;

@@ -98,6 +98,7 @@ struct Dims {
     size_t N;   // physical points
     size_t NS;  // spectral modes (nx/2+1) * ny
     double tpx, tpy, inv_n;
+    double Lx;
 };
 
 sgn_status check_grid(sgn_ctx* ctx, const sgn_grid* g, Dims* d) {
@@ -119,6 +120,7 @@ sgn_status check_grid(sgn_ctx* ctx, const sgn_grid* g, Dims* d) {
     d->tpx = kTwoPi / g->Lx;
     d->tpy = g->dim == 2 ? kTwoPi / g->Ly : 0.0;
     d->inv_n = 1.0 / (double)d->N;
+    d->Lx = g->Lx;
     return SGN_OK;
 }
 
@@ -419,6 +421,8 @@ size_t workspace_bytes(const Dims& d, int precision) {
         carve_rhs(cv, d);
         best = std::max(best, cv.off);
     }
+    if (d.D == 1 && d.nx <= BATCH_NMAX)   // one-workgroup 1D solve: item, result, system region
+        best = std::max(best, (size_t)512 + (size_t)batch_item_doubles(d.nx, BATCH_MIXED) * sizeof(double));
     return best + 256;
 }
 
@@ -909,6 +913,10 @@ sgn_solve_opts default_opts() {
     return o;
 }
 
+sgn_status solve_1d_block(sgn_ctx* ctx, const Dims& d, double L, const double* eta, const double* gh,
+                          const double* rhs, double* u, const sgn_coeffs* coeffs, int flat, const sgn_solve_opts& o,
+                          sgn_solve_info* info, void* ws);
+
 sgn_status solve_dispatch(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* rhs,
                           double* u, const sgn_coeffs* coeffs, int flat, const sgn_solve_opts& o,
                           sgn_solve_info* info, void* ws) {
@@ -916,6 +924,9 @@ sgn_status solve_dispatch(sgn_ctx* ctx, const Dims& d, const double* eta, const 
     if (!(o.tol > 0.0) || o.max_iter < 1) return fail(ctx, SGN_EINVAL, "tol must be > 0 and max_iter >= 1");
     if (coeffs && !(coeffs->sigma > 0.0 && coeffs->alpha > 0.0))
         return fail(ctx, SGN_EINVAL, "coefficients must be positive");
+    // a 1D system that fits one workgroup is solved by it in one launch
+    if (d.D == 1 && d.nx <= BATCH_NMAX && (o.precision == SGN_FP64 || o.precision == SGN_MIXED))
+        return solve_1d_block(ctx, d, d.Lx, eta, gh, rhs, u, coeffs, flat, o, info, ws);
     if (o.precision == SGN_FP64)
         return d.D == 1 ? solve_fp64<1>(ctx, d, eta, gh, rhs, u, coeffs, flat, o, info, ws)
                         : solve_fp64<2>(ctx, d, eta, gh, rhs, u, coeffs, flat, o, info, ws);
@@ -923,6 +934,89 @@ sgn_status solve_dispatch(sgn_ctx* ctx, const Dims& d, const double* eta, const 
         return d.D == 1 ? solve_mixed<1>(ctx, d, eta, gh, rhs, u, coeffs, flat, o, info, ws)
                         : solve_mixed<2>(ctx, d, eta, gh, rhs, u, coeffs, flat, o, info, ws);
     return fail(ctx, SGN_EINVAL, "unknown precision");
+}
+
+// Pinned host staging of batch item tables and results (grows on demand).
+sgn_status batch_staging(sgn_ctx* ctx, size_t bytes) {
+    if (ctx->hbatch_bytes >= bytes) return SGN_OK;
+    if (ctx->hbatch) (void)hipHostFree(ctx->hbatch);
+    ctx->hbatch = nullptr;
+    ctx->hbatch_bytes = 0;
+    if (hipHostMalloc(&ctx->hbatch, bytes, hipHostMallocDefault) != hipSuccess)
+        return fail(ctx, SGN_ENOMEM, "pinned staging allocation failed");
+    ctx->hbatch_bytes = bytes;
+    return SGN_OK;
+}
+
+// A 1D system of nx <= BATCH_NMAX points solved by one workgroup in one launch
+// (the batched solver with a single system): workspace = item | result | region.
+sgn_status solve_1d_block(sgn_ctx* ctx, const Dims& d, double L, const double* eta, const double* gh,
+                          const double* rhs, double* u, const sgn_coeffs* coeffs, int flat, const sgn_solve_opts& o,
+                          sgn_solve_info* info, void* ws) {
+    sgn_status s;
+    if ((s = batch_staging(ctx, std::max(sizeof(BatchItem), sizeof(BatchResult)))) != SGN_OK) return s;
+    const int mode = o.precision == SGN_MIXED ? BATCH_MIXED : BATCH_FP64;
+    BatchItem* hit = static_cast<BatchItem*>(ctx->hbatch);
+    hit->n = d.nx;
+    hit->index = 0;
+    hit->L = L;
+    hit->off = 0;
+    hit->wso = 0;
+    char* base = static_cast<char*>(ws);
+    BatchItem* d_item = reinterpret_cast<BatchItem*>(base);
+    BatchResult* d_res = reinterpret_cast<BatchResult*>(base + 256);
+    double* d_data = reinterpret_cast<double*>(base + 512);
+    HIPCHK(ctx, hipMemcpyAsync(d_item, hit, sizeof(BatchItem), hipMemcpyHostToDevice, ctx->stream));
+    BatchParams prm{};
+    prm.tol = o.tol;
+    prm.inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    prm.max_iter = o.max_iter;
+    prm.max_outer = o.max_outer > 0 ? o.max_outer : 20;
+    prm.x0_is_guess = o.x0_is_guess ? 1 : 0;
+    prm.coeff_kind = o.coeff_kind;
+    prm.nitems = 1;
+    prm.flat = flat < 0 ? -1 : (flat ? 1 : 0);
+    if (coeffs) {
+        prm.have_coeffs = 1;
+        prm.sig = coeffs->sigma;
+        prm.alp = coeffs->alpha;
+        prm.kap = coeffs->kappa_ub;
+        prm.flat = coeffs->flat ? 1 : 0;
+    }
+    const size_t lds = (size_t)(d.nx / 2 + 1) * sizeof(cpx<double>) * (mode == BATCH_FP64 ? 2 : 1);
+    {
+        ProfScope ps(ctx, SGN_KERNEL_BATCH);
+        auto launch = [&](auto k, int nt) -> sgn_status {
+            HIPCHK(ctx, allow_lds(k, lds));
+            hipLaunchKernelGGL(k, dim3(1), dim3(nt), lds, ctx->stream, (const BatchItem*)d_item, 1, eta, gh, rhs, u,
+                               d_data, ctx->tw64, ctx->tw32, prm, d_res);
+            CHECK_LAUNCH(ctx);
+            return SGN_OK;
+        };
+        const bool mx = mode == BATCH_MIXED;
+        if (d.nx <= 2048)
+            s = mx ? launch(k_batch_solve<BATCH_MIXED, 256>, 256) : launch(k_batch_solve<BATCH_FP64, 256>, 256);
+        else
+            s = mx ? launch(k_batch_solve<BATCH_MIXED, 512>, 512) : launch(k_batch_solve<BATCH_FP64, 512>, 512);
+        if (s != SGN_OK) return s;
+    }
+    BatchResult* hres = static_cast<BatchResult*>(ctx->hbatch);
+    HIPCHK(ctx, hipMemcpyAsync(hres, d_res, sizeof(BatchResult), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const BatchResult r = *hres;
+    if (info) {
+        info->iters = r.iters;
+        info->outer_iters = r.outer;
+        info->converged = r.converged;
+        info->relres = r.relres;
+        info->coeffs.sigma = r.sig;
+        info->coeffs.alpha = r.alp;
+        info->coeffs.kappa_ub = r.kap;
+        info->coeffs.flat = r.flat;
+    }
+    if (r.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
+    if (!r.converged) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
+    return SGN_OK;
 }
 
 // physical D-vector field -> S layout (FP64)
@@ -1754,16 +1848,6 @@ BatchLayout batch_layout(int nitems, const int32_t* n, int mode) {
 
 bool batch_size_ok(int n) { return n >= 2 && n <= BATCH_NMAX && (n & (n - 1)) == 0; }
 
-sgn_status batch_staging(sgn_ctx* ctx, size_t bytes) {
-    if (ctx->hbatch_bytes >= bytes) return SGN_OK;
-    if (ctx->hbatch) (void)hipHostFree(ctx->hbatch);
-    ctx->hbatch = nullptr;
-    ctx->hbatch_bytes = 0;
-    if (hipHostMalloc(&ctx->hbatch, bytes, hipHostMallocDefault) != hipSuccess)
-        return fail(ctx, SGN_ENOMEM, "pinned staging allocation failed");
-    ctx->hbatch_bytes = bytes;
-    return SGN_OK;
-}
 
 }  // namespace
 
@@ -1836,6 +1920,7 @@ sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const
     prm.x0_is_guess = o.x0_is_guess ? 1 : 0;
     prm.coeff_kind = o.coeff_kind;
     prm.nitems = nitems;
+    prm.flat = -1;
     // two transform buffers of M+1 modes: FP64 ones in FP64 mode; in mixed mode
     // the FP32 pair or one FP64 buffer (the refinement residual), whichever is larger
     const size_t lds = (size_t)(nmax / 2 + 1) * sizeof(cpx<double>) * (mode == BATCH_FP64 ? 2 : 1);

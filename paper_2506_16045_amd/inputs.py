@@ -317,3 +317,40 @@ def config_c4_item(rng, L: float = 400.0, sizes=C4_SIZES):
 def config_c4(count: int = 512, seed_offset: int = 4, sizes=C4_SIZES):
     rng = np.random.default_rng(SEED_BASE + seed_offset)
     return [config_c4_item(rng, sizes=sizes) for _ in range(count)]
+
+
+# ---------------------------------------------------------------------------
+# Served request stream (reading: the sizes, mixes and step counts are
+# proposals; the paper prescribes no request workload)
+# ---------------------------------------------------------------------------
+C5_SIZES_1D = (1024, 2048, 4096, 8192, 16384)
+C5_SIZES_2D = (128, 256, 512, 1024)
+
+
+def config_c5_request(rng, kind: str | None = None, dim: int | None = None, n: int | None = None):
+    """One request of the served stream: 70% 1D (N in C5_SIZES_1D, L = 400, the
+    batched-ensemble recipe), 30% 2D (n x n in C5_SIZES_2D on 200 x 200, 1-3
+    random bumps, a line solitary wave in x); half "solve" (one constraint solve
+    G u = G u* to 1e-10 from a zero guess), half "step" (10 RK4 steps from
+    (eta, u), dt = min(0.02, dx / 2)).  Returns a dict with kind, grid, h, eta
+    and u (u* for a solve, the initial velocity for a step), dt, nsteps, tol."""
+    if dim is None:
+        dim = 1 if rng.uniform() < 0.7 else 2
+    if kind is None:
+        kind = "solve" if rng.uniform() < 0.5 else "step"
+    if dim == 1:
+        sizes = (n,) if n else C5_SIZES_1D
+        g, eta, h, u = config_c4_item(rng, sizes=sizes)
+    else:
+        nn = n if n else int(rng.choice(np.asarray(C5_SIZES_2D)))
+        g = grid2d(nn, nn, 200.0, 200.0)
+        h = random_bumps2d(g, rng)
+        a = rng.uniform(0.05, 0.4)
+        x0 = rng.uniform(0.0, 200.0)
+        c, gamma = solitary_speed_width(1.0, a)
+        X, _ = coords(g)
+        zeta = a / np.cosh(gamma * periodic_offset(X, x0, 200.0)) ** 2
+        eta = h + zeta
+        u = np.stack([c * zeta / eta, np.zeros_like(zeta)])
+    dx = g.Lx / g.nx
+    return dict(kind=kind, grid=g, h=h, eta=eta, u=u, dt=min(0.02, 0.5 * dx), nsteps=10, tol=1e-10)
