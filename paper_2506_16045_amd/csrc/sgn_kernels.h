@@ -189,13 +189,19 @@ __global__ void __launch_bounds__(256) k_cols_lin(ColGeom g, PtrList<const cpx<T
                                                    T scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, NI));
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, 1));
     const ColThread<T> ct = col_thread<T>(g, lds);
+    // inputs transformed one at a time through a single LDS column buffer (a
+    // small LDS footprint keeps several blocks resident per compute unit)
     cpx<T> in[NI][EPC];
-    const cpx<T>* srcs[NI];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) srcs[i] = src.p[i];
-    col_load<T, EPC, NI>(g, ct, srcs, true, twm, in);
+    for (int i = 0; i < NI; ++i) {
+        const cpx<T>* srcs[1] = {src.p[i]};
+        cpx<T> vi[1][EPC];
+        col_load<T, EPC, 1>(g, ct, srcs, true, twm, vi);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) in[i][e] = vi[0][e];
+    }
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
     for (int o = 0; o < lc.no; ++o) {
         cpx<T> v[1][EPC];

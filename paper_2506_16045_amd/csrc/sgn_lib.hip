@@ -311,7 +311,7 @@ sgn_status cols_lin_n(sgn_ctx* ctx, const Dims& d, const std::vector<const cpx<T
     for (int i = 0; i < NI; ++i) s.p[i] = src[i];
     for (int i = 0; i < lc.no; ++i) t.p[i] = dst[i];
     auto k = k_cols_lin<T, 4, NI>;
-    const size_t lds = col_lds_bytes<T>(L.g, NI);
+    const size_t lds = col_lds_bytes<T>(L.g, 1);
     HIPCHK(ctx, allow_lds(k, lds));
     hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, s, t, lc,
                        twiddles<T>(ctx), (T)d.tpx, (T)d.tpy, scale);
