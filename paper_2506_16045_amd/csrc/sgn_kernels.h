@@ -289,8 +289,9 @@ __device__ __forceinline__ bool pcg_iterate_state(SolveScal* __restrict__ sc, co
     const double rz = bcast(tot[0], slot) * sc->inv_n;
     const double rr = bcast(tot[1], slot + 1) * sc->inv_n;
     const int first = sc->first;
-    const double bb = (sc->init_bb && first && sc->iter == 0) ? rr : sc->bb;
-    const bool bad = !(rr == rr) || !(rz == rz);
+    // init_bb: ||b||^2 is the first r.r seen (r_0 = b); taken once, while bb is unset
+    const double bb = (sc->init_bb && first && sc->iter == 0 && sc->bb == 0.0) ? rr : sc->bb;
+    const bool bad = !(rr == rr) || !(rz == rz) || !(rr <= 1.0e300);
     const bool conv = !bad && (bb == 0.0 || rr <= sc->tol2 * bb);
     const bool done = bad || conv || sc->iter >= sc->max_iter;
     const double beta = first ? 0.0 : rz / sc->rho_prev;
@@ -465,11 +466,13 @@ __global__ void __launch_bounds__(1024) k_pcg_r1(RowGeom g, const cpx<T>* __rest
     }
 }
 
-enum { C2_RESID = 1, C2_STORE = 2, C2_UPDATE = 3 };
+enum { C2_RESID = 1, C2_STORE = 2, C2_UPDATE = 3, C2_RESID_INIT = 4 };
 
 // MODE C2_UPDATE: reduce p.Gp (row-pass partials, nb_r1 blocks) -> alpha;
 //   q = G p; x += alpha p; r -= alpha q; z = A^{-1} r; partial r.z, r.r.
 // MODE C2_RESID: r = b - G x -> rh.
+// MODE C2_RESID_INIT: reduce ||b||^2 (setup partials, nb_r1 blocks) -> bb;
+//   r = b - G x -> rh (x = r = 0 for a zero b); partial r.z, r.r of r_0.
 // MODE C2_STORE: q = G p -> qh.
 template <typename T, int EPC, int D, int MODE>
 __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restrict__ tw,
@@ -484,6 +487,22 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
     __shared__ double red[32];
     __shared__ double slot[1];
     T alpha = (T)0;
+    bool zero_x = false;
+    if (MODE == C2_RESID_INIT) {
+        double tot[1];
+        final_sum<1>(part + PART_GEN, nb_r1, tot, red);
+        const double bb = bcast(tot[0], slot) * sc->inv_n;
+        const bool bad = !(bb == bb) || bb > 1.0e300;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->bb = bb;
+            if (bad) {
+                sc->status = -2;
+                sc->done = 1;
+            }
+        }
+        if (bad) return;
+        zero_x = !sc->init_bb && bb == 0.0;
+    }
     if (MODE == C2_UPDATE) {
         double tot[1];
         final_sum<1>(part + PART_C2, nb_r1, tot, red);
@@ -525,13 +544,17 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
                     qh[c * NS + idx] = q;
                 } else if (MODE == C2_RESID) {
                     rh[c * NS + idx] = bh[c * NS + idx] - q;
+                } else if (MODE == C2_RESID_INIT) {
+                    r[c] = zero_x ? C<T>(0, 0) : bh[c * NS + idx] - q;
+                    rh[c * NS + idx] = r[c];
+                    if (zero_x) xh[c * NS + idx] = C<T>(0, 0);
                 } else {
                     xh[c * NS + idx] = xh[c * NS + idx] + alpha * ph[c * NS + idx];
                     r[c] = rh[c * NS + idx] - alpha * q;
                     rh[c * NS + idx] = r[c];
                 }
             }
-            if (MODE == C2_UPDATE) {
+            if (MODE == C2_UPDATE || MODE == C2_RESID_INIT) {
                 precond_mode<T, D>(kx, ky, sig, alp, r, z);
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
@@ -541,7 +564,106 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
             }
         }
     }
-    if (MODE == C2_UPDATE) {
+    if (MODE == C2_UPDATE || MODE == C2_RESID_INIT) {
+        block_sum<2>(acc, red);
+        if (threadIdx.x == 0) {
+            part[PART_C3 + 2 * blockIdx.x] = acc[0];
+            part[PART_C3 + 2 * blockIdx.x + 1] = acc[1];
+        }
+    }
+}
+
+// First column pass of a solve.  Hb holds the row transforms of b (D fields),
+// Hu those of the initial guess u0 (GUESS).  y-FFT of b -> b_hat into rh (and
+// bh).  GUESS: partial ||b||^2; y-FFT of u0 -> x_hat, and (x_hat, div x_hat)/N
+// y-inverse-transformed into H for the row pass of G x_0 (C2_RESID_INIT then
+// forms r_0).  Otherwise x_hat = 0, r_0 = b_hat and the partials r.z, r.r.
+template <typename T, int EPC, int D, bool GUESS>
+__global__ void __launch_bounds__(256) k_pcg_setup(ColGeom g, const cpx<T>* __restrict__ tw,
+                                                    const SolveScal* __restrict__ sc, const cpx<T>* Hb,
+                                                    const cpx<T>* __restrict__ Hu, size_t NS, cpx<T>* __restrict__ bh,
+                                                    cpx<T>* __restrict__ rh, cpx<T>* __restrict__ xh, cpx<T>* H,
+                                                    double* __restrict__ part, T tpx, T tpy) {
+    if (sc->done) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[32];
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D + 1));
+    const ColThread<T> ct = col_thread<T>(g, lds);
+    const double w = ct.valid ? half_weight(ct.kx, g.nx) : 0.0;
+    const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
+    const T sig = (T)sc->sig, alp = (T)sc->alp, inv_n = (T)sc->inv_n;
+    cpx<T> vb[D][EPC];
+    {
+        const cpx<T>* srcs[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) srcs[c] = Hb + c * NS;
+        col_load<T, EPC, D>(g, ct, srcs, true, twm, vb);
+    }
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int j = ct.t + g.TPC * e;
+        if (ct.valid && j < g.ny) {
+            const size_t idx = (size_t)ct.kx * g.ny + j;
+            cpx<T> r[D], z[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                r[c] = vb[c][e];
+                if (bh) bh[c * NS + idx] = r[c];
+                rh[c * NS + idx] = r[c];
+                if (!GUESS) xh[c * NS + idx] = C<T>(0, 0);
+            }
+            if (GUESS) {
+#pragma unroll
+                for (int c = 0; c < D; ++c)
+                    acc[0] += w * ((double)r[c].re * (double)r[c].re + (double)r[c].im * (double)r[c].im);
+            } else {
+                const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
+                precond_mode<T, D>(kx, ky, sig, alp, r, z);
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    acc[0] += w * ((double)r[c].re * (double)z[c].re + (double)r[c].im * (double)z[c].im);
+                    acc[1] += w * ((double)r[c].re * (double)r[c].re + (double)r[c].im * (double)r[c].im);
+                }
+            }
+        }
+    }
+    if (GUESS) {
+        cpx<T> vu[D][EPC];
+        {
+            const cpx<T>* srcs[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) srcs[c] = Hu + c * NS;
+            col_load<T, EPC, D>(g, ct, srcs, true, twm, vu);
+        }
+        cpx<T> o[D + 1][EPC];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+#pragma unroll
+            for (int c = 0; c <= D; ++c) o[c][e] = C<T>(0, 0);
+            if (ct.valid && j < g.ny) {
+                const size_t idx = (size_t)ct.kx * g.ny + j;
+                const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    xh[c * NS + idx] = vu[c][e];
+                    o[c][e] = inv_n * vu[c][e];
+                }
+                cpx<T> dv = ik(kx, vu[0][e]);
+                if (D == 2) dv = dv + ik(ky, vu[1 % D][e]);
+                o[D][e] = inv_n * dv;
+            }
+        }
+        cpx<T>* dsts[D + 1];
+#pragma unroll
+        for (int c = 0; c <= D; ++c) dsts[c] = H + c * NS;
+        col_store<T, EPC, D + 1>(g, ct, o, dsts, true, twm);
+        double bsum[1] = {acc[0]};
+        block_sum<1>(bsum, red);
+        if (threadIdx.x == 0) part[PART_GEN + blockIdx.x] = bsum[0];
+    } else {
         block_sum<2>(acc, red);
         if (threadIdx.x == 0) {
             part[PART_C3 + 2 * blockIdx.x] = acc[0];

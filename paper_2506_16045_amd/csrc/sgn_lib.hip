@@ -495,9 +495,11 @@ sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out) {
     auto k = k_pcg_c2<T, 4, D, MODE>;
     const size_t lds = col_lds_bytes<T>(L.g, D + 1);
     HIPCHK(P.ctx, allow_lds(k, lds));
+    // partials reduced at the start: p.Gp of the row pass, or ||b||^2 of the setup pass
+    const int nb_red = MODE == C2_RESID_INIT ? L.g.nblocks : P.rl.g.nblocks;
     hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, L.g, twiddles<T>(P.ctx), P.sc,
                        (const cpx<T>*)P.b.H, P.d.NS, P.b.qh, (const cpx<T>*)P.b.ph, P.b.xh, bh, rh_out, P.partials,
-                       P.rl.g.nblocks, (T)P.d.tpx, (T)P.d.tpy);
+                       nb_red, (T)P.d.tpx, (T)P.d.tpy);
     CHECK_LAUNCH(P.ctx);
     return SGN_OK;
 }
@@ -507,6 +509,7 @@ sgn_status pcg_c2(PcgLaunch<T, D>& P, int mode, const cpx<T>* bh, cpx<T>* rh_out
     ProfScope ps(P.ctx, SGN_KERNEL_PCG_C2 + (sizeof(T) == 4 ? 6 : 0));
     if (mode == C2_STORE) return pcg_c2_mode<T, D, C2_STORE>(P, bh, rh_out);
     if (mode == C2_RESID) return pcg_c2_mode<T, D, C2_RESID>(P, bh, rh_out);
+    if (mode == C2_RESID_INIT) return pcg_c2_mode<T, D, C2_RESID_INIT>(P, bh, rh_out);
     return pcg_c2_mode<T, D, C2_UPDATE>(P, nullptr, P.b.rh);
 }
 
@@ -517,6 +520,48 @@ sgn_status pcg_init(PcgLaunch<T, D>& P) {
     hipLaunchKernelGGL((k_pcg_init<T, D>), dim3(P.cl.g.nblocks), dim3(256), 0, P.ctx->stream, P.d.nx, P.d.ny,
                        P.d.NS, P.sc, P.b.xh, P.b.rh, P.partials, (T)P.d.tpx, (T)P.d.tpy);
     CHECK_LAUNCH(P.ctx);
+    return SGN_OK;
+}
+
+// First pass of a solve in FP64: b (and the guess u0) to the half spectrum in one
+// row launch, then k_pcg_setup; with a guess also G x_0 and r_0 = b - G x_0.
+// Afterwards the partials of (r.z, r.r) of r_0 wait for the first C1.
+template <int D>
+sgn_status pcg_start(PcgLaunch<double, D>& P, const double* rhs, const double* u0, bool guess, cpx<double>* bh) {
+    sgn_ctx* ctx = P.ctx;
+    const Dims& d = P.d;
+    std::vector<const double*> src;
+    std::vector<cpx<double>*> dst;
+    for (int c = 0; c < D; ++c) {
+        src.push_back(rhs + c * d.N);
+        dst.push_back(P.b.H + c * d.NS);
+    }
+    if (guess) {
+        for (int c = 0; c < D; ++c) {
+            src.push_back(u0 + c * d.N);
+            dst.push_back(P.b.qh + c * d.NS);
+        }
+    }
+    sgn_status s;
+    if ((s = rows_fwd<double, double>(ctx, d, src, dst)) != SGN_OK) return s;
+    {
+        ProfScope ps(ctx, SGN_KERNEL_PCG_INIT);
+        const size_t lds = col_lds_bytes<double>(P.cl.g, D + 1);
+        auto launch = [&](auto k) -> sgn_status {
+            HIPCHK(ctx, allow_lds(k, lds));
+            hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), lds, ctx->stream, P.cl.g, ctx->tw64,
+                               (const SolveScal*)P.sc, (const cpx<double>*)P.b.H, (const cpx<double>*)P.b.qh, d.NS,
+                               bh, P.b.rh, P.b.xh, P.b.H, P.partials, d.tpx, d.tpy);
+            CHECK_LAUNCH(ctx);
+            return SGN_OK;
+        };
+        s = guess ? launch(k_pcg_setup<double, 4, D, true>) : launch(k_pcg_setup<double, 4, D, false>);
+        if (s != SGN_OK) return s;
+    }
+    if (guess) {
+        if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
+        if ((s = pcg_c2<double, D>(P, C2_RESID_INIT, bh ? bh : P.b.rh, P.b.rh)) != SGN_OK) return s;
+    }
     return SGN_OK;
 }
 
@@ -666,46 +711,12 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     P.eta = eta;
     P.gh = gh;
     sgn_status s;
-    if ((s = init_scal(ctx, P.sc, o.tol, o.max_iter, d.inv_n, coeffs)) != SGN_OK) return s;
+    // without a guess r_0 = b, so ||b||^2 is the first r.r (init_bb)
+    if ((s = init_scal(ctx, P.sc, o.tol, o.max_iter, d.inv_n, coeffs, o.x0_is_guess ? 0 : 1)) != SGN_OK) return s;
     if (!coeffs) {
         if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials)) != SGN_OK) return s;
     }
-    // b_hat -> r_hat, ||b||^2
-    std::vector<const double*> bsrc;
-    std::vector<cpx<double>*> hdst;
-    for (int c = 0; c < D; ++c) {
-        bsrc.push_back(rhs + c * d.N);
-        hdst.push_back(P.b.H + c * d.NS);
-    }
-    if ((s = rows_fwd<double, double>(ctx, d, bsrc, hdst)) != SGN_OK) return s;
-    {
-        auto k = k_setup_b<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g,
-                           ctx->tw64, (const cpx<double>*)P.b.H, d.NS, (cpx<double>*)nullptr, P.b.rh, P.partials);
-        hipLaunchKernelGGL(k_finish_bb, dim3(1), dim3(256), 0, ctx->stream, P.sc, (const double*)P.partials,
-                           P.cl.g.nblocks);
-        CHECK_LAUNCH(ctx);
-    }
-    if (o.x0_is_guess) {
-        // x_hat = FFT(u0); r_hat = b_hat - G x_hat
-        std::vector<const double*> usrc;
-        for (int c = 0; c < D; ++c) usrc.push_back(u + c * d.N);
-        if ((s = rows_fwd<double, double>(ctx, d, usrc, hdst)) != SGN_OK) return s;
-        auto k = k_cols_to_S<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
-                           (const cpx<double>*)P.b.H, d.NS, P.b.xh);
-        CHECK_LAUNCH(ctx);
-        if ((s = pcg_c1<double, D>(P, C1_COPY, P.b.xh)) != SGN_OK) return s;
-        if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
-        if ((s = pcg_c2<double, D>(P, C2_RESID, P.b.rh, P.b.rh)) != SGN_OK) return s;
-    } else {
-        hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks(d.D * d.NS * 2)), dim3(256), 0, ctx->stream,
-                           (size_t)d.D * d.NS * 2, (void*)P.b.xh);
-        CHECK_LAUNCH(ctx);
-    }
-    if ((s = pcg_init<double, D>(P)) != SGN_OK) return s;
+    if ((s = pcg_start<D>(P, rhs, u, o.x0_is_guess != 0, nullptr)) != SGN_OK) return s;
     LoopOut lo;
     if ((s = pcg_loop<double, D>(P, o.max_iter, o.check_every, &lo)) != SGN_OK) return s;
     // u = IFFT(x_hat)
@@ -781,7 +792,7 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     Q.eta = eta32;
     Q.gh = eta32 + d.N;
     sgn_status s;
-    if ((s = init_scal(ctx, P.sc, o.tol, 1 << 30, d.inv_n, coeffs)) != SGN_OK) return s;
+    if ((s = init_scal(ctx, P.sc, o.tol, 1 << 30, d.inv_n, coeffs, o.x0_is_guess ? 0 : 1)) != SGN_OK) return s;
     if (!coeffs) {
         if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials)) != SGN_OK) return s;
     }
@@ -789,42 +800,8 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     hipLaunchKernelGGL((k_convert<float, double>), dim3(flat_blocks(d.D * d.N)), dim3(256), 0, ctx->stream,
                        (size_t)D * d.N, gh, eta32 + d.N);
     CHECK_LAUNCH(ctx);
-    // b_hat (kept) and r_hat = b_hat - G x_hat in FP64
-    std::vector<const double*> bsrc;
-    std::vector<cpx<double>*> hdst;
-    for (int c = 0; c < D; ++c) {
-        bsrc.push_back(rhs + c * d.N);
-        hdst.push_back(P.b.H + c * d.NS);
-    }
-    if ((s = rows_fwd<double, double>(ctx, d, bsrc, hdst)) != SGN_OK) return s;
-    {
-        auto k = k_setup_b<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g,
-                           ctx->tw64, (const cpx<double>*)P.b.H, d.NS, P.b.bh, P.b.rh, P.partials);
-        hipLaunchKernelGGL(k_finish_bb, dim3(1), dim3(256), 0, ctx->stream, P.sc, (const double*)P.partials,
-                           P.cl.g.nblocks);
-        CHECK_LAUNCH(ctx);
-    }
-    if (o.x0_is_guess) {
-        std::vector<const double*> usrc;
-        for (int c = 0; c < D; ++c) usrc.push_back(u + c * d.N);
-        if ((s = rows_fwd<double, double>(ctx, d, usrc, hdst)) != SGN_OK) return s;
-        auto k = k_cols_to_S<double, 4, D>;
-        HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
-                           (const cpx<double>*)P.b.H, d.NS, P.b.xh);
-        CHECK_LAUNCH(ctx);
-        if ((s = pcg_c1<double, D>(P, C1_COPY, P.b.xh)) != SGN_OK) return s;
-        if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
-        if ((s = pcg_c2<double, D>(P, C2_RESID, P.b.bh, P.b.rh)) != SGN_OK) return s;
-    } else {
-        hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks(d.D * d.NS * 2)), dim3(256), 0, ctx->stream,
-                           (size_t)d.D * d.NS * 2, (void*)P.b.xh);
-        CHECK_LAUNCH(ctx);
-    }
-    // FP64 residual norm and stop test (INIT C3 computes r.z and r.r)
-    if ((s = pcg_init<double, D>(P)) != SGN_OK) return s;
+    // b_hat (kept) and r_hat = b_hat - G x_hat in FP64, with the partials of r_0
+    if ((s = pcg_start<D>(P, rhs, u, o.x0_is_guess != 0, P.b.bh)) != SGN_OK) return s;
     int total_inner = 0, outer = 0;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
