@@ -66,7 +66,7 @@ __device__ __forceinline__ const cpx<T>* tw_size(const cpx<T>* __restrict__ tw_a
     return tw_all + (L - 1);
 }
 
-constexpr int TWL_MAX = 2048;  // largest FFT length whose twiddles are staged in LDS
+constexpr int TWL_MAX = 0;     // largest FFT length whose twiddles are staged in LDS (0: read from the global table)
 
 // Stage W_M^m (m < M) in LDS when M <= TWL_MAX; returns the table to use (LDS or
 // global).  Contains a block barrier; every thread must call it.
