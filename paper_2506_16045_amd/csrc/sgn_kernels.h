@@ -158,6 +158,195 @@ __global__ void __launch_bounds__(1024) k_rows_inv(RowGeom g, PtrList<const cpx<
     for (; f < src.n; ++f) rows_inv_group<T, Tout, EPC, 1>(g, rt, src, dst, f, tw, twm, scale, acc);
 }
 
+// ---------------------------------------------------------------------------
+// Right-hand side row passes (Eq:DSWEcf, Def:bigF, Eq:DAE_DSWE), fused with
+// their pointwise stages.
+// ---------------------------------------------------------------------------
+
+// Source field i of the right-hand side's forward transforms at one point:
+// [u_c (D), eta u_c (D), eta, eta u_a u_b (a <= b), beta = grad h . u].
+template <int D>
+__device__ __forceinline__ double rhs_source(int i, double e, const double (&uc)[D], const double (&hc)[D]) {
+    if (i < D) return uc[i];
+    if (i < 2 * D) return e * uc[i - D];
+    if (i == 2 * D) return e;
+    if (D == 1) {
+        if (i == 3) return e * uc[0] * uc[0];
+        return hc[0] * uc[0];
+    }
+    if (i == 5) return e * uc[0] * uc[0];
+    if (i == 6) return e * uc[0] * uc[1 % D];
+    if (i == 7) return e * uc[1 % D] * uc[1 % D];
+    double b = hc[0] * uc[0];
+    b += hc[1 % D] * uc[1 % D];
+    return b;
+}
+
+// Products and forward row transforms of the right-hand side's source fields
+// (rhs_source order) in groups of NFG fields; dst.p[i] receives field i.
+// MAXT bounds the workgroup size (256 lets the compiler use more registers).
+template <int D, int EPC, int NFG, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_rhs_rows_fwd(RowGeom g, const double* __restrict__ eta,
+                                                       const double* __restrict__ u, const double* __restrict__ gh,
+                                                       PtrList<cpx<double>, MAXF> dst,
+                                                       const cpx<double>* __restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<double>* lds = reinterpret_cast<cpx<double>*>(smem_raw);
+    const cpx<double>* twm = twl_setup<double>(tw, g.M, lds + row_lds_data(g, NFG));
+    const RowThread<double> rt = row_thread<double>(g, lds);
+    const size_t npts = (size_t)g.nx * g.ny;
+    constexpr int NFLD = 2 * D + 1 + (D == 2 ? 3 : 1) + 1;
+    for (int f0 = 0; f0 < NFLD; f0 += NFG) {
+        cpx<double> z[NFG][EPC];
+        cpx<double>* H[NFG];
+#pragma unroll
+        for (int k = 0; k < NFG; ++k) H[k] = (f0 + k < NFLD) ? dst.p[f0 + k] : dst.p[f0];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = rt.t + g.TPR * e;
+#pragma unroll
+            for (int k = 0; k < NFG; ++k) z[k][e] = C<double>(0, 0);
+            if (j < g.M && rt.valid) {
+                const size_t o = (size_t)rt.y * g.nx + 2 * j;
+                double v[NFG][2];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const double et = eta[o + s];
+                    double uc[D], hc[D];
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        uc[c] = u[c * npts + o + s];
+                        hc[c] = gh[c * npts + o + s];
+                    }
+#pragma unroll
+                    for (int k = 0; k < NFG; ++k) v[k][s] = rhs_source<D>(f0 + k, et, uc, hc);
+                }
+#pragma unroll
+                for (int k = 0; k < NFG; ++k) z[k][e] = C<double>(v[k][0], v[k][1]);
+            }
+        }
+        if (f0 + NFG <= NFLD) {
+            row_forward<double, EPC, NFG>(g, rt, z, H, tw, twm, 1.0);
+        } else {
+            // the last group holds fewer fields: transform them one by one
+            for (int k = 0; f0 + k < NFLD; ++k) {
+                cpx<double> z1[1][EPC];
+                cpx<double>* H1[1] = {H[k]};
+#pragma unroll
+                for (int e = 0; e < EPC; ++e) z1[0][e] = z[k][e];
+                row_forward<double, EPC, 1>(g, rt, z1, H1, tw, twm, 1.0);
+            }
+        }
+    }
+}
+
+// Inverse row transforms of the derivative fields Q (order: delta, d_c delta,
+// m = div(eta u), d_c eta, div_c(eta u (x) u), d_c beta) in groups of NFG,
+// consumed into the pointwise right-hand side as they arrive: eta_t = -m,
+// U_t = -eta grad(eta - h) - div(eta u (x) u) - T grad h, and S of Def:bigF,
+// whose forward row transform goes to Sdst (grad S is added to U_t later).
+// P = u.grad(delta) - delta^2, Q = u.grad(beta) (the reading u.grad(u.grad h)).
+template <int D, int EPC, int NFG, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_rhs_rows_inv(RowGeom g, PtrList<const cpx<double>, MAXF> src,
+                                                       const double* __restrict__ eta, const double* __restrict__ u,
+                                                       const double* __restrict__ gh, double* __restrict__ eta_t,
+                                                       double* __restrict__ U_t, cpx<double>* __restrict__ Sdst,
+                                                       const cpx<double>* __restrict__ tw, double scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<double>* lds = reinterpret_cast<cpx<double>*>(smem_raw);
+    const cpx<double>* twm = twl_setup<double>(tw, g.M, lds + row_lds_data(g, NFG));
+    const RowThread<double> rt = row_thread<double>(g, lds);
+    const size_t npts = (size_t)g.nx * g.ny;
+    constexpr int NQ = 4 * D + 2;
+    // running pointwise state at the thread's 2 EPC points
+    double dl[EPC][2], P[EPC][2], m[EPC][2], Q[EPC][2], Ut[D][EPC][2];
+    for (int f0 = 0; f0 < NQ; f0 += NFG) {
+        const int nf = NQ - f0 < NFG ? NQ - f0 : NFG;
+        cpx<double> z[NFG][EPC];
+        if (nf == NFG) {
+            const cpx<double>* Hs[NFG];
+#pragma unroll
+            for (int k = 0; k < NFG; ++k) Hs[k] = src.p[f0 + k];
+            row_inverse<double, EPC, NFG>(g, rt, Hs, tw, twm, z);
+        } else {
+            for (int k = 0; k < nf; ++k) {
+                const cpx<double>* H1[1] = {src.p[f0 + k]};
+                cpx<double> z1[1][EPC];
+                row_inverse<double, EPC, 1>(g, rt, H1, tw, twm, z1);
+#pragma unroll
+                for (int e = 0; e < EPC; ++e) z[k][e] = z1[0][e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = rt.t + g.TPR * e;
+            if (j < g.M && rt.valid) {
+                const size_t o = (size_t)rt.y * g.nx + 2 * j;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+#pragma unroll
+                    for (int k = 0; k < NFG; ++k) {
+                        const int i = f0 + k;
+                        if (k >= nf) continue;
+                        const double q = scale * (s ? z[k][e].im : z[k][e].re);
+                        if (i == 0) {
+                            dl[e][s] = q;
+                            P[e][s] = -q * q;
+                        } else if (i <= D) {
+                            P[e][s] += u[(i - 1) * npts + o + s] * q;
+                        } else if (i == 1 + D) {
+                            m[e][s] = q;
+                        } else if (i <= 1 + 2 * D) {
+                            const int c = i - 2 - D;
+                            Ut[c][e][s] = -eta[o + s] * (q - gh[c * npts + o + s]);
+                        } else if (i <= 1 + 3 * D) {
+                            const int c = i - 2 - 2 * D;
+                            Ut[c][e][s] = Ut[c][e][s] - q;
+                        } else {
+                            const int c = i - 2 - 3 * D;
+                            const double t = u[c * npts + o + s] * q;
+                            Q[e][s] = c == 0 ? t : Q[e][s] + t;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // S, T and the outputs; S forward-transformed
+    cpx<double> zs[1][EPC];
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int j = rt.t + g.TPR * e;
+        zs[0][e] = C<double>(0, 0);
+        if (j < g.M && rt.valid) {
+            const size_t o = (size_t)rt.y * g.nx + 2 * j;
+            double sv[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const double e0 = eta[o + s];
+                double hc[D], uc[D];
+                double bt = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    uc[c] = u[c * npts + o + s];
+                    hc[c] = gh[c * npts + o + s];
+                    bt += hc[c] * uc[c];
+                }
+                const double e2 = e0 * e0;
+                const double mm = m[e][s], d0 = dl[e][s], pp = P[e][s], qq = Q[e][s];
+                sv[s] = e2 * e0 / 3.0 * pp + e2 * mm * d0 + e2 / 2.0 * qq + e0 * mm * bt;
+                const double Tv = e2 / 2.0 * pp + e0 * mm * d0 + e0 * qq + mm * bt;
+                eta_t[o + s] = -mm;
+#pragma unroll
+                for (int c = 0; c < D; ++c) U_t[c * npts + o + s] = Ut[c][e][s] - hc[c] * Tv;
+            }
+            zs[0][e] = C<double>(sv[0], sv[1]);
+        }
+    }
+    cpx<double>* Hs1[1] = {Sdst};
+    row_forward<double, EPC, 1>(g, rt, zs, Hs1, tw, twm, 1.0);
+}
+
 // Linear spectral operators on columns: out_o = sum_i c(code[o][i], k) in_i, with
 // y-FFT of the inputs and y-IFFT of the outputs.  Codes: 0 none, 1 identity,
 // 2 i kx, 3 i ky, 4 (i kx)^2, 5 (i kx)(i ky), 6 (i ky)^2; every value is also

@@ -384,17 +384,14 @@ PcgBufs<T> carve_pcg(Carve& cv, const Dims& d, bool keep_b) {
 }
 
 struct RhsBufs {
-    double* P;          // physical temporaries
     cpx<double>* H;     // spectral temporaries
-    int nP, nH;
+    int nH;
 };
 RhsBufs carve_rhs(Carve& cv, const Dims& d) {
     RhsBufs b;
     const int D = d.D;
     const int nd2 = D == 2 ? 3 : 1;
-    b.nP = D + nd2 + 1 + (4 * D + 2) + 1;   // eta u, eta u u, beta, derivatives, S
     b.nH = (2 * D + 1) + (nd2 + 1) + (2 * D + 2) + (2 * D);
-    b.P = cv.take<double>((size_t)b.nP * d.N);
     b.H = cv.take<cpx<double>>((size_t)b.nH * d.NS);
     return b;
 }
@@ -1114,63 +1111,6 @@ sgn_status precond_apply(sgn_ctx* ctx, const Dims& d, double sig, double alp, co
 // Right-hand side f(w, p)  (FP64)
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_rhs_pre(size_t n, const double* __restrict__ eta, const double* __restrict__ u,
-                          const double* __restrict__ gh, double* __restrict__ eu, double* __restrict__ euu,
-                          double* __restrict__ beta) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double e = eta[i];
-        const double u0 = u[i];
-        const double u1 = D == 2 ? u[n + i] : 0.0;
-        eu[i] = e * u0;
-        euu[i] = e * u0 * u0;
-        double b = gh[i] * u0;
-        if (D == 2) {
-            eu[n + i] = e * u1;
-            euu[n + i] = e * u0 * u1;
-            euu[2 * n + i] = e * u1 * u1;
-            b += gh[n + i] * u1;
-        }
-        beta[i] = b;
-    }
-}
-
-// Q layout (physical derivative fields): delta, d_c delta (D), m, d_c eta (D),
-// div_c (D), d_c beta (D).
-template <int D>
-__global__ void k_rhs_point(size_t n, const double* __restrict__ eta, const double* __restrict__ u,
-                            const double* __restrict__ gh, const double* __restrict__ Qf,
-                            double* __restrict__ eta_t, double* __restrict__ U_t, double* __restrict__ S) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double e = eta[i];
-        double uc[D], hc[D], dd[D], de[D], dv[D], db[D];
-        const double dl = Qf[i];
-        const double m = Qf[(1 + D) * n + i];
-        for (int c = 0; c < D; ++c) {
-            uc[c] = u[c * n + i];
-            hc[c] = gh[c * n + i];
-            dd[c] = Qf[(1 + c) * n + i];
-            de[c] = Qf[(2 + D + c) * n + i];
-            dv[c] = Qf[(2 + 2 * D + c) * n + i];
-            db[c] = Qf[(2 + 3 * D + c) * n + i];
-        }
-        double bt = 0.0, P = -dl * dl, Q = 0.0;
-        for (int c = 0; c < D; ++c) {
-            bt += hc[c] * uc[c];
-            P += uc[c] * dd[c];
-            Q += uc[c] * db[c];
-        }
-        const double e2 = e * e;
-        const double Sv = e2 * e / 3.0 * P + e2 * m * dl + e2 / 2.0 * Q + e * m * bt;
-        const double Tv = e2 / 2.0 * P + e * m * dl + e * Q + m * bt;
-        eta_t[i] = -m;
-        for (int c = 0; c < D; ++c) U_t[c * n + i] = -e * (de[c] - hc[c]) - dv[c] - hc[c] * Tv;
-        S[i] = Sv;
-    }
-}
-
-template <int D>
 sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* u,
                     double* eta_t, double* U_t, void* ws) {
     Carve cv(ws);
@@ -1178,30 +1118,40 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     RhsBufs b = carve_rhs(cv, d);
     const size_t N = d.N, NS = d.NS;
     const int nd2 = D == 2 ? 3 : 1;
-    double* eu = b.P;
-    double* euu = eu + D * N;
-    double* beta = euu + nd2 * N;
-    double* Qf = beta + N;                    // 4D + 2 fields
-    double* S = Qf + (4 * D + 2) * N;
     cpx<double>* HA = b.H;                    // 2D + 1
     cpx<double>* HB = HA + (2 * D + 1) * NS;  // nd2 + 1
     cpx<double>* OA = HB + (nd2 + 1) * NS;    // 2D + 2
     cpx<double>* OB = OA + (2 * D + 2) * NS;  // 2D
     sgn_status s;
-    hipLaunchKernelGGL(k_rhs_pre<D>, dim3(flat_blocks(N)), dim3(256), 0, ctx->stream, N, eta, u, gh, eu, euu, beta);
-    CHECK_LAUNCH(ctx);
-    // forward transforms: group A = [u_c, eta u_c, eta], group B = [eta u_i u_j, beta]
-    std::vector<const double*> srcA, srcB;
+    // products and forward transforms: group A = [u_c, eta u_c, eta], group B = [eta u_i u_j, beta]
     std::vector<cpx<double>*> dA, dB;
-    for (int c = 0; c < D; ++c) srcA.push_back(u + c * N);
-    for (int c = 0; c < D; ++c) srcA.push_back(eu + c * N);
-    srcA.push_back(eta);
-    for (int c = 0; c < nd2; ++c) srcB.push_back(euu + c * N);
-    srcB.push_back(beta);
-    for (size_t i = 0; i < srcA.size(); ++i) dA.push_back(HA + i * NS);
-    for (size_t i = 0; i < srcB.size(); ++i) dB.push_back(HB + i * NS);
-    if ((s = rows_fwd<double, double>(ctx, d, srcA, dA)) != SGN_OK) return s;
-    if ((s = rows_fwd<double, double>(ctx, d, srcB, dB)) != SGN_OK) return s;
+    for (int i = 0; i < 2 * D + 1; ++i) dA.push_back(HA + i * NS);
+    for (int i = 0; i < nd2 + 1; ++i) dB.push_back(HB + i * NS);
+    // the fused right-hand-side row passes transform their fields one at a time
+    // (lockstep groups need more registers than the pointwise state leaves)
+    const RowLaunch RL = row_launch<double>(d.nx, d.ny);
+    const size_t rlds = row_lds_bytes<double>(RL.g, 1);
+    {
+        ProfScope ps(ctx, SGN_KERNEL_ROWS);
+        PtrList<cpx<double>, MAXF> t{};
+        t.n = 0;
+        for (auto p : dA) t.p[t.n++] = p;
+        for (auto p : dB) t.p[t.n++] = p;
+        auto launch = [&](auto k) -> sgn_status {
+            HIPCHK(ctx, allow_lds(k, rlds));
+            hipLaunchKernelGGL(k, dim3(RL.g.nblocks), dim3(RL.threads), rlds, ctx->stream, RL.g, eta, u, gh, t,
+                               ctx->tw64);
+            CHECK_LAUNCH(ctx);
+            return SGN_OK;
+        };
+        if (RL.epc == 4 && RL.threads <= 256)
+            s = launch(k_rhs_rows_fwd<D, 4, 1, 256>);
+        else if (RL.epc == 4)
+            s = launch(k_rhs_rows_fwd<D, 4, 1, 1024>);
+        else
+            s = launch(k_rhs_rows_fwd<D, 8, 1, 1024>);
+        if (s != SGN_OK) return s;
+    }
     std::vector<const cpx<double>*> cA(dA.begin(), dA.end()), cB(dB.begin(), dB.end());
     std::vector<cpx<double>*> oA, oB;
     for (int i = 0; i < 2 * D + 2; ++i) oA.push_back(OA + i * NS);
@@ -1222,17 +1172,30 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
             return s;
         if ((s = cols_lin<double>(ctx, d, cB, oB, {{2, 0}, {0, 2}}, d.inv_n)) != SGN_OK) return s;
     }
-    // back to physical: Q = [delta, d delta (D), m, d eta (D), div (D), d beta (D)]
-    std::vector<const cpx<double>*> hs;
-    std::vector<double*> qd;
-    for (int i = 0; i < 2 * D + 2; ++i) hs.push_back(OA + i * NS);
-    for (int i = 0; i < 2 * D; ++i) hs.push_back(OB + i * NS);
-    for (int i = 0; i < 4 * D + 2; ++i) qd.push_back(Qf + i * N);
-    if ((s = rows_inv<double, double>(ctx, d, hs, qd)) != SGN_OK) return s;
-    hipLaunchKernelGGL(k_rhs_point<D>, dim3(flat_blocks(N)), dim3(256), 0, ctx->stream, N, eta, u, gh, Qf, eta_t, U_t, S);
-    CHECK_LAUNCH(ctx);
+    // back to physical: Q = [delta, d delta (D), m, d eta (D), div (D), d beta (D)], consumed
+    // pointwise into eta_t, U_t (without grad S) and S, whose row transform goes to HA
+    {
+        ProfScope ps(ctx, SGN_KERNEL_ROWS);
+        PtrList<const cpx<double>, MAXF> q{};
+        q.n = 0;
+        for (int i = 0; i < 2 * D + 2; ++i) q.p[q.n++] = OA + i * NS;
+        for (int i = 0; i < 2 * D; ++i) q.p[q.n++] = OB + i * NS;
+        auto launch = [&](auto k) -> sgn_status {
+            HIPCHK(ctx, allow_lds(k, rlds));
+            hipLaunchKernelGGL(k, dim3(RL.g.nblocks), dim3(RL.threads), rlds, ctx->stream, RL.g, q, eta, u, gh, eta_t,
+                               U_t, HA, ctx->tw64, 1.0);
+            CHECK_LAUNCH(ctx);
+            return SGN_OK;
+        };
+        if (RL.epc == 4 && RL.threads <= 256)
+            s = launch(k_rhs_rows_inv<D, 4, 1, 256>);
+        else if (RL.epc == 4)
+            s = launch(k_rhs_rows_inv<D, 4, 1, 1024>);
+        else
+            s = launch(k_rhs_rows_inv<D, 8, 1, 1024>);
+        if (s != SGN_OK) return s;
+    }
     // U_t += grad S
-    if ((s = rows_fwd<double, double>(ctx, d, {S}, {HA})) != SGN_OK) return s;
     std::vector<cpx<double>*> gS;
     for (int c = 0; c < D; ++c) gS.push_back(HB + c * NS);
     if (D == 2) {
