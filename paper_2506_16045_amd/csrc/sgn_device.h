@@ -81,103 +81,127 @@ __device__ __forceinline__ const cpx<T>* twl_setup(const cpx<T>* __restrict__ tw
 
 // ---------------------------------------------------------------------------
 // Stockham FFT of length M (power of two) on NF buffers at buf + f * fstride,
-// transformed in lockstep by TPX cooperating threads (thread index t): radix-4
-// passes, then one radix-2 pass when log2 M is odd.  Every thread of the block
-// must call it (it contains block barriers); M <= EPC * TPX.  twm[m] = W_M^m.
+// transformed in lockstep by TPX cooperating threads (thread index t): radix-8
+// (few fields) or radix-4 (many fields) passes while they fit, then one
+// radix-4 or radix-2 pass for the remaining factor (mixed-radix Stockham: a pass of radix R over span Ns reads
+// x[j + r M/R], twiddles by W_{R Ns}^{k r} with k = j mod Ns, and writes the
+// R-point DFT to y[(j - k) R + k + q Ns]).  Every thread of the block must call
+// it (it contains block barriers); M <= EPC * TPX.  twm[m] = W_M^m.
 // Forward: exp(-i ...); inverse: exp(+i ...); unnormalised.
 // ---------------------------------------------------------------------------
+
+// In-register R-point DFTs (R = 2, 4, 8) of v[0..R).
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cpx<T> (&v)[R], bool inverse) {
+    if (R == 2) {
+        const cpx<T> a = v[0], b = v[1 % R];
+        v[0] = a + b;
+        v[1 % R] = a - b;
+    } else if (R == 4) {
+        const cpx<T> a0 = v[0] + v[2 % R], a1 = v[0] - v[2 % R];
+        const cpx<T> a2 = v[1 % R] + v[3 % R], d = v[1 % R] - v[3 % R];
+        const cpx<T> a3 = inverse ? mul_i(d) : mul_mi(d);
+        v[0] = a0 + a2;
+        v[1 % R] = a1 + a3;
+        v[2 % R] = a0 - a2;
+        v[3 % R] = a1 - a3;
+    } else {
+        // two 4-point DFTs (even and odd inputs), then W_8^q on the odd half
+        cpx<T> e[4], o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            e[q] = v[(2 * q) % R];
+            o[q] = v[(2 * q + 1) % R];
+        }
+        dft_small<T, 4>(e, inverse);
+        dft_small<T, 4>(o, inverse);
+        const T h = (T)0.70710678118654752440;
+        const T sg = inverse ? (T)1 : (T)-1;
+        const cpx<T> w1 = C<T>(h, sg * h), w3 = C<T>(-h, sg * h);
+        const cpx<T> t0 = o[0];
+        const cpx<T> t1 = w1 * o[1];
+        const cpx<T> t2 = inverse ? mul_i(o[2]) : mul_mi(o[2]);
+        const cpx<T> t3 = w3 * o[3];
+        v[0] = e[0] + t0;
+        v[4 % R] = e[0] - t0;
+        v[1 % R] = e[1] + t1;
+        v[5 % R] = e[1] - t1;
+        v[2 % R] = e[2] + t2;
+        v[6 % R] = e[2] - t2;
+        v[3 % R] = e[3] + t3;
+        v[7 % R] = e[3] - t3;
+    }
+}
+
+template <typename T, int R, int NB, int NF>
+__device__ __forceinline__ void fft_pass(cpx<T>* buf, int fstride, int M, int t, int TPX,
+                                         const cpx<T>* __restrict__ twm, bool inverse, int Ns, int sh) {
+    const int MR = M / R;
+    cpx<T> v[NB][NF][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = t + i * TPX;
+        if (j < MR) {
+            const int k = j & (Ns - 1);
+            cpx<T> w[R];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                w[r] = twm[(k * r) << sh];   // W_{R Ns}^{k r} = W_M^{k r M / (R Ns)}
+                if (inverse) w[r].im = -w[r].im;
+            }
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const cpx<T>* bf = buf + f * fstride;
+                v[i][f][0] = bf[j];
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][f][r] = bf[j + r * MR] * w[r];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = t + i * TPX;
+        if (j < MR) {
+            const int k = j & (Ns - 1);
+            const int o = (j - k) * R + k;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                dft_small<T, R>(v[i][f], inverse);
+                cpx<T>* bf = buf + f * fstride;
+#pragma unroll
+                for (int q = 0; q < R; ++q) bf[o + q * Ns] = v[i][f][q];
+            }
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, int EPC, int NF>
 __device__ __forceinline__ void lds_fft(cpx<T>* buf, int fstride, int M, int t, int TPX,
                                         const cpx<T>* __restrict__ twm, bool inverse) {
+    constexpr int NB8 = EPC / 8 > 0 ? EPC / 8 : 1;
     constexpr int NB4 = EPC / 4 > 0 ? EPC / 4 : 1;
     constexpr int NB2 = EPC / 2 > 0 ? EPC / 2 : 1;
-    const int M4 = M >> 2;
+    // radix-8 passes hold 8 NF values per butterfly in registers: used while that
+    // stays within 16 FP64 complex words (more fields in lockstep use radix 4)
+    constexpr bool R8 = NF * (int)sizeof(T) <= 16;
     const int logM = ilog2(M);
     int Ns = 1;
     int logNs = 0;
-    for (; Ns * 4 <= M; Ns <<= 2, logNs += 2) {
-        cpx<T> v[NB4][NF][4];
-        const int sh = logM - (logNs + 2);   // W_{4Ns}^{kr} = W_M^{kr M / 4Ns}
-#pragma unroll
-        for (int i = 0; i < NB4; ++i) {
-            const int j = t + i * TPX;
-            if (j < M4) {
-                const int k = j & (Ns - 1);
-                cpx<T> w[4];
-#pragma unroll
-                for (int r = 1; r < 4; ++r) {
-                    w[r] = twm[(k * r) << sh];
-                    if (inverse) w[r].im = -w[r].im;
-                }
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const cpx<T>* bf = buf + f * fstride;
-                    v[i][f][0] = bf[j];
-#pragma unroll
-                    for (int r = 1; r < 4; ++r) v[i][f][r] = bf[j + r * M4] * w[r];
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NB4; ++i) {
-            const int j = t + i * TPX;
-            if (j < M4) {
-                const int k = j & (Ns - 1);
-                const int o = ((j - k) << 2) + k;
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const cpx<T> a0 = v[i][f][0] + v[i][f][2];
-                    const cpx<T> a1 = v[i][f][0] - v[i][f][2];
-                    const cpx<T> a2 = v[i][f][1] + v[i][f][3];
-                    const cpx<T> d = v[i][f][1] - v[i][f][3];
-                    const cpx<T> a3 = inverse ? mul_i(d) : mul_mi(d);
-                    cpx<T>* bf = buf + f * fstride;
-                    bf[o] = a0 + a2;
-                    bf[o + Ns] = a1 + a3;
-                    bf[o + 2 * Ns] = a0 - a2;
-                    bf[o + 3 * Ns] = a1 - a3;
-                }
-            }
-        }
-        __syncthreads();
+    if (R8) {
+        for (; Ns * 8 <= M; Ns <<= 3, logNs += 3)
+            fft_pass<T, 8, NB8, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 3));
+    } else {
+        for (; Ns * 16 <= M; Ns <<= 2, logNs += 2)
+            fft_pass<T, 4, NB4, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 2));
     }
-    if (Ns < M) {  // one radix-2 pass remains (log2 M odd)
-        const int M2 = M >> 1;
-        const int sh = logM - (logNs + 1);
-        cpx<T> v[NB2][NF][2];
-#pragma unroll
-        for (int i = 0; i < NB2; ++i) {
-            const int j = t + i * TPX;
-            if (j < M2) {
-                const int k = j & (Ns - 1);
-                cpx<T> w = twm[k << sh];
-                if (inverse) w.im = -w.im;
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const cpx<T>* bf = buf + f * fstride;
-                    v[i][f][0] = bf[j];
-                    v[i][f][1] = bf[j + M2] * w;
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NB2; ++i) {
-            const int j = t + i * TPX;
-            if (j < M2) {
-                const int k = j & (Ns - 1);
-                const int o = ((j - k) << 1) + k;
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    cpx<T>* bf = buf + f * fstride;
-                    bf[o] = v[i][f][0] + v[i][f][1];
-                    bf[o + Ns] = v[i][f][0] - v[i][f][1];
-                }
-            }
-        }
-        __syncthreads();
+    if (Ns * 4 <= M) {
+        fft_pass<T, 4, NB4, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 2));
+        Ns <<= 2;
+        logNs += 2;
     }
+    if (Ns * 2 <= M) fft_pass<T, 2, NB2, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 1));
 }
 
 // ---------------------------------------------------------------------------

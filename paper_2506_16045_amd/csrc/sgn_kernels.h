@@ -100,8 +100,8 @@ __device__ __forceinline__ void rows_fwd_group(const RowGeom& g, const RowThread
     row_forward<T, EPC, NFG>(g, rt, z, H, tw, twm, scale);
 }
 
-template <typename T, typename Tin, int EPC, int NFG>
-__global__ void __launch_bounds__(1024) k_rows_fwd(RowGeom g, PtrList<const Tin, MAXF> src,
+template <typename T, typename Tin, int EPC, int NFG, int MAXT = 1024>
+__global__ void __launch_bounds__(MAXT) k_rows_fwd(RowGeom g, PtrList<const Tin, MAXF> src,
                                                    PtrList<cpx<T>, MAXF> dst,
                                                    const cpx<T>* __restrict__ tw, T scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -145,8 +145,8 @@ __device__ __forceinline__ void rows_inv_group(const RowGeom& g, const RowThread
     }
 }
 
-template <typename T, typename Tout, int EPC, int NFG>
-__global__ void __launch_bounds__(1024) k_rows_inv(RowGeom g, PtrList<const cpx<T>, MAXF> src,
+template <typename T, typename Tout, int EPC, int NFG, int MAXT = 1024>
+__global__ void __launch_bounds__(MAXT) k_rows_inv(RowGeom g, PtrList<const cpx<T>, MAXF> src,
                                                    PtrList<Tout, MAXF> dst,
                                                    const cpx<T>* __restrict__ tw, T scale, T acc) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -569,8 +569,8 @@ __global__ void __launch_bounds__(256) k_pcg_check(SolveScal* __restrict__ sc, c
     pcg_iterate_state(sc, part, nb3, red, slot, beta);
 }
 
-template <typename T, int EPC, int D, bool SEQ>
-__global__ void __launch_bounds__(1024) k_pcg_r1(RowGeom g, const cpx<T>* __restrict__ tw,
+template <typename T, int EPC, int D, bool SEQ, int MAXT = 1024>
+__global__ void __launch_bounds__(MAXT) k_pcg_r1(RowGeom g, const cpx<T>* __restrict__ tw,
                                                  SolveScal* __restrict__ sc, cpx<T>* H, size_t NS,
                                                  const T* __restrict__ eta, const T* __restrict__ gh,
                                                  double* __restrict__ part) {

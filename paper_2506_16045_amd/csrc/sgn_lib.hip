@@ -258,7 +258,9 @@ sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, st
         };
         sgn_status st;
         if (L.epc == 4)
-            st = multi ? launch(k_rows_fwd<T, Tin, 4, 3>) : launch(k_rows_fwd<T, Tin, 4, 1>);
+            st = L.threads <= 256
+                     ? (multi ? launch(k_rows_fwd<T, Tin, 4, 3, 256>) : launch(k_rows_fwd<T, Tin, 4, 1, 256>))
+                     : (multi ? launch(k_rows_fwd<T, Tin, 4, 3>) : launch(k_rows_fwd<T, Tin, 4, 1>));
         else
             st = multi ? launch(k_rows_fwd<T, Tin, 8, 3>) : launch(k_rows_fwd<T, Tin, 8, 1>);
         if (st != SGN_OK) return st;
@@ -290,7 +292,9 @@ sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src,
         };
         sgn_status st;
         if (L.epc == 4)
-            st = multi ? launch(k_rows_inv<T, Tout, 4, 3>) : launch(k_rows_inv<T, Tout, 4, 1>);
+            st = L.threads <= 256
+                     ? (multi ? launch(k_rows_inv<T, Tout, 4, 3, 256>) : launch(k_rows_inv<T, Tout, 4, 1, 256>))
+                     : (multi ? launch(k_rows_inv<T, Tout, 4, 3>) : launch(k_rows_inv<T, Tout, 4, 1>));
         else
             st = multi ? launch(k_rows_inv<T, Tout, 8, 3>) : launch(k_rows_inv<T, Tout, 8, 1>);
         if (st != SGN_OK) return st;
@@ -478,7 +482,9 @@ sgn_status pcg_r1(PcgLaunch<T, D>& P, bool curvature = false) {
     };
     sgn_status st;
     if (L.epc == 4)
-        st = seq ? launch(k_pcg_r1<T, 4, D, true>) : launch(k_pcg_r1<T, 4, D, false>);
+        st = L.threads <= 256
+                 ? (seq ? launch(k_pcg_r1<T, 4, D, true, 256>) : launch(k_pcg_r1<T, 4, D, false, 256>))
+                 : (seq ? launch(k_pcg_r1<T, 4, D, true>) : launch(k_pcg_r1<T, 4, D, false>));
     else
         st = seq ? launch(k_pcg_r1<T, 8, D, true>) : launch(k_pcg_r1<T, 8, D, false>);
     if (st != SGN_OK) return st;
