@@ -6,10 +6,11 @@ Workload (the 2D configuration the grid-point-steps metric is quoted on):
 still-water depth 1, bump height 0.5 and radius 10 at the centre, line
 solitary wave a = 0.2 travelling in x (crest at x = 50), classical RK4 with
 dt = 0.02, preconditioned Krylov (PCG with the constant-coefficient operator
-A) to a relative residual of 1e-10 at every stage.  Default precision: FP32
-operator/FFT/preconditioner inside FP64 iterative refinement (FP64 residual,
-dot products, right-hand side and state); --precision fp64 runs everything in
-FP64.
+A) to a relative residual of 1e-10 at every stage, stage solves started from
+extrapolated guesses.  Default precision FP64 (the faster form on this
+workload); the same run also times the mixed form (FP32
+operator/FFT/preconditioner inside FP64 iterative refinement) and reports it
+under other_precision (--precision mixed swaps the two).
 
 One step = one RK4 step of the whole hot path (4 right-hand sides, 4 Krylov
 solves, the stage combinations).  `value` = grid points x timed steps / wall
@@ -106,20 +107,28 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(cfg, steps: int = 1):
-    """The oracle, as it stands, on `steps` RK4 steps of the same workload."""
+def cpu_baseline(cfg, steps: int = 1, device_fields=None):
+    """The oracle, as it stands, on `steps` RK4 steps of the same workload from its
+    initial data.  device_fields = (eta, U, u) of the device after the same steps
+    adds the relative L2 difference per field (zeta = eta - h, U, u)."""
     import numpy as np
     from oracle import stepping as ost
     pb = ost.Problem.from_h(cfg["grid"], cfg["h"], tol=cfg["tol"])
     U0 = pb.G(cfg["eta"], cfg["u"])
     t0 = time.perf_counter()
-    ost.run_rk4(pb, cfg["eta"], U0, cfg["u"], cfg["dt"], steps)
+    e_r, U_r, u_r = ost.run_rk4(pb, cfg["eta"], U0, cfg["u"], cfg["dt"], steps)
     dt = time.perf_counter() - t0
     g = cfg["grid"]
-    return {"value": g.npts * steps / dt, "unit": "grid-pt-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} RK4 step(s) of the {g.nx}x{g.ny} workload from its initial data "
-                      f"({dt:.1f} s, FP64 NumPy, single thread; iterations/solve "
-                      f"{np.mean(pb.iters):.1f})"}
+    out = {"value": g.npts * steps / dt, "unit": "grid-pt-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{steps} RK4 step(s) of the {g.nx}x{g.ny} workload from its initial data "
+                     f"({dt:.1f} s, FP64 NumPy, single thread; iterations/solve "
+                     f"{np.mean(pb.iters):.1f})"}
+    if device_fields is not None:
+        e_d, U_d, u_d = device_fields
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        out["device_vs_oracle_rel_l2"] = {"zeta": rel(e_d - cfg["h"], e_r - cfg["h"]), "U": rel(U_d, U_r),
+                                          "u": rel(u_d, u_r), "steps": steps}
+    return out
 
 
 def batch_bytes(sizes, res, mixed: bool) -> float:
@@ -399,7 +408,8 @@ def main(argv=None):
     ap.add_argument("--cpu-sample", type=int, default=512, help="systems the CPU oracle solves for its baseline")
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="fp64")
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
     ap.add_argument("--n", type=int, default=1024, help="grid points per side (default 1024)")
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--inner-tol", type=float, default=1e-5)
@@ -454,18 +464,16 @@ def main(argv=None):
     dev = torch.device("cuda", 0)
     cfg = I.config_c3(args.n)
     g = cfg["grid"]
-    prec = sgn.MIXED if args.precision == "mixed" else sgn.FP64
-    opts = sgn.solve_opts(tol=cfg["tol"], precision=prec, check_every=args.check_every, inner_tol=args.inner_tol)
-
     ctx = sgn.Context(0)
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
     h = to(cfg["h"])
     gh, flat = ctx.bathy_prepare(g, h)
-    eta = to(cfg["eta"])
-    u = to(cfg["u"])
-    U = ctx.apply_constraint(g, eta, gh, u)
-    state = sgn.State(ctx, g, h, gh, flat, eta, U, u)
-    mass0 = float(torch.sum(eta - h).item())
+
+    def new_state():
+        eta = to(cfg["eta"])
+        u = to(cfg["u"])
+        U = ctx.apply_constraint(g, eta, gh, u)
+        return sgn.State(ctx, g, h, gh, flat, eta, U, u)
 
     if args.calib_copy_mib > 0:
         nel = args.calib_copy_mib * (1 << 20) // 8
@@ -475,44 +483,59 @@ def main(argv=None):
         dst_c.copy_(src_c)
         torch.cuda.synchronize()
         del src_c, dst_c
-    if args.warmup > 0:
-        state.step_rk4(cfg["dt"], args.warmup, opts)
-    torch.cuda.synchronize()
 
-    # timed region: K steps, no instrumentation
-    lat = []
-    solves = iters = 0
-    max_iters = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        info = state.step_rk4(cfg["dt"], 1, opts)
+    def run(precision: str, kernel_timing: bool):
+        prec = sgn.MIXED if precision == "mixed" else sgn.FP64
+        opts = sgn.solve_opts(tol=cfg["tol"], precision=prec, check_every=args.check_every,
+                              inner_tol=args.inner_tol)
+        state = new_state()
+        mass0 = float(torch.sum(state.eta - h).item())
+        if args.warmup > 0:
+            state.step_rk4(cfg["dt"], args.warmup, opts)
         torch.cuda.synchronize()
-        lat.append((time.perf_counter() - s0) * 1e3)
-        solves += info.solves
-        iters += info.iters
-        max_iters = max(max_iters, info.max_iters)
-        if not info.converged:
-            raise RuntimeError("a Krylov solve did not converge")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
+        # timed region: K steps, no instrumentation
+        lat = []
+        solves = iters = 0
+        max_iters = 0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s0 = time.perf_counter()
+            info = state.step_rk4(cfg["dt"], 1, opts)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - s0) * 1e3)
+            solves += info.solves
+            iters += info.iters
+            max_iters = max(max_iters, info.max_iters)
+            if not info.converged:
+                raise RuntimeError("a Krylov solve did not converge")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        # kernel timing: HIP events around every launch of each kernel family on the
+        # library's stream, over further steps of the same run (events between
+        # launches slow the step down, so they stay out of the timed region above)
+        prof = {k: (0, 0.0) for k in ctx.KERNEL_KINDS}
+        if kernel_timing and args.timing_steps > 0:
+            ctx.profile_begin()
+            state.step_rk4(cfg["dt"], args.timing_steps, opts)
+            prof = ctx.profile_end()
+        # device-side property checks of the final state (not part of the timed region)
+        Gu = ctx.apply_constraint(g, state.eta, gh, state.u)
+        relres = float((torch.linalg.vector_norm(Gu - state.U) / torch.linalg.vector_norm(state.U)).item())
+        drift = abs(float(torch.sum(state.eta - h).item()) - mass0) / max(abs(mass0), 1e-300)
+        state.close()
+        return {"precision": precision, "prec": prec, "elapsed": elapsed, "lat": lat, "solves": solves,
+                "iters": iters, "max_iters": max_iters, "prof": prof, "relres": relres, "drift": drift,
+                "value": g.npts * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps}
 
-    # kernel timing: HIP events around every launch of each kernel family on the
-    # library's stream, over further steps of the same run (events between
-    # launches slow the step down, so they stay out of the timed region above)
-    prof = {k: (0, 0.0) for k in ctx.KERNEL_KINDS}
-    if not args.no_kernel_timing and args.timing_steps > 0:
-        ctx.profile_begin()
-        state.step_rk4(cfg["dt"], args.timing_steps, opts)
-        prof = ctx.profile_end()
-
-    # device-side property checks of the final state (not part of the timed region)
-    Gu = ctx.apply_constraint(g, state.eta, gh, state.u)
-    constraint_relres = float((torch.linalg.vector_norm(Gu - state.U) / torch.linalg.vector_norm(state.U)).item())
-    mass_drift = abs(float(torch.sum(state.eta - h).item()) - mass0) / max(abs(mass0), 1e-300)
-
+    main_run = run(args.precision, not args.no_kernel_timing)
+    other = None
+    if not args.no_compare:
+        o = run("mixed" if args.precision == "fp64" else "fp64", False)
+        other = {"precision": o["precision"], "value": o["value"], "ms_per_step": o["ms_per_step"],
+                 "krylov_iters_per_solve": o["iters"] / max(o["solves"], 1),
+                 "checks": {"constraint_relres": o["relres"], "mass_rel_drift": o["drift"]}}
+    prec = main_run["prec"]
+    prof = main_run["prof"]
     word = 4 if prec == sgn.MIXED else 8
     kstats = {}
     kinds = ("pcg_c1_f32", "pcg_r1_f32", "pcg_c2_f32", "pcg_init_f32") if prec == sgn.MIXED else \
@@ -536,16 +559,23 @@ def main(argv=None):
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, 1)
+        # one device step from the initial data, compared with the oracle's step inside the baseline leg
+        st1 = new_state()
+        st1.step_rk4(cfg["dt"], 1, sgn.solve_opts(tol=cfg["tol"], precision=prec, check_every=args.check_every,
+                                                   inner_tol=args.inner_tol))
+        dev_fields = tuple(t.detach().cpu().numpy() for t in (st1.eta, st1.U, st1.u))
+        st1.close()
+        cpu = cpu_baseline(cfg, 1, dev_fields)
 
+    lat = main_run["lat"]
     out = {
         "metric": "2D SGN grid-pt-steps/s at 1e-9 rel err; Krylov iters/solve; p50/p99 latency",
-        "value": g.npts * args.steps / elapsed,
+        "value": main_run["value"],
         "unit": "grid-pt-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -556,20 +586,20 @@ def main(argv=None):
                          "h0=1, bump height 0.5 radius 10 at the centre, line solitary wave a=0.2 at x=50, "
                          f"dt={cfg['dt']}, Krylov tol {cfg['tol']:g}"),
             "scheme": "rk4", "precision": args.precision, "grid": [g.nx, g.ny], "dt": cfg["dt"],
-            "tol": cfg["tol"], "parallelism": "single GPU",
+            "tol": cfg["tol"], "initial_guess": "extrapolated per stage", "parallelism": "single GPU",
         },
-        "krylov_iters_per_solve": iters / max(solves, 1),
-        "krylov_max_iters": max_iters,
-        "solves": solves,
+        "krylov_iters_per_solve": main_run["iters"] / max(main_run["solves"], 1),
+        "krylov_max_iters": main_run["max_iters"],
+        "solves": main_run["solves"],
         "step_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)},
-        "checks": {"constraint_relres": constraint_relres, "mass_rel_drift": mass_drift},
+        "checks": {"constraint_relres": main_run["relres"], "mass_rel_drift": main_run["drift"]},
+        "other_precision": other,
         "kernels": kstats,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out), flush=True)
-    state.close()
     ctx.close()
     return 0
 
