@@ -200,3 +200,33 @@ def test_batch_invalid_inputs(ctx):
     # max_iter reached: ENOCONV with the last iterate
     _, res3, st3 = _run(ctx, good, sgn.solve_opts(tol=1e-14, max_iter=2))
     assert st3 == sgn.ENOCONV and all(r.iters == 2 and not r.converged for r in res3)
+
+
+def test_full_ensemble_512_systems(ctx):
+    """The batched workload at its full size (512 systems, N 512..8192) in one
+    launch, as the bench runs it: every system converges to the stop test,
+    matches the exact discrete solution u* (b = G u*) and the oracle's iteration
+    count within one (FP64), and the mixed form meets the same tolerance."""
+    from paper_2506_16045_amd import sgn
+    rng = np.random.default_rng(I.SEED_BASE + 4)
+    systems = []
+    for _ in range(512):
+        g, eta, h, u_star = I.config_c4_item(rng)
+        gh, _ = op.bathy_gradient(h, g)
+        systems.append(dict(g=g, eta=eta, gh=gh, fl=not np.any(gh), b=op.apply_G(eta, gh, u_star, g),
+                            u_star=u_star))
+    tol = 1e-10
+    u, res, st = _run(ctx, systems, sgn.solve_opts(tol=tol, max_iter=5000))
+    assert st == sgn.OK
+    for s, ui, ri in zip(systems, u, res):
+        assert ri.converged and ri.relres <= tol
+        assert np.linalg.norm(ui - s["u_star"]) <= 1e-6 * np.linalg.norm(s["u_star"])
+    for i in range(0, 512, 16):          # oracle iteration counts on a sample
+        _, it_ref, ok, _ = _oracle(systems[i], tol)
+        assert ok and abs(res[i].iters - it_ref) <= 1, (i, res[i].iters, it_ref)
+    u2, res2, st2 = _run(ctx, systems, sgn.solve_opts(tol=tol, precision=sgn.MIXED, inner_tol=1e-5, max_iter=5000,
+                                                      max_outer=40))
+    assert st2 == sgn.OK
+    for s, ui, ri in zip(systems, u2, res2):
+        assert ri.converged and ri.relres <= tol
+        assert np.linalg.norm(ui - s["u_star"]) <= 1e-6 * np.linalg.norm(s["u_star"])

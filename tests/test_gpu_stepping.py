@@ -167,3 +167,21 @@ def test_bad_guess_rule_rejected(ctx):
         st.step_rk4(0.05, 1, opts)
     assert e.value.status == sgn.EINVAL
     st.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_2d_rk4_step_matches_oracle(ctx, precision):
+    """The benchmarked 2D workload at its full size (1024 x 1024, tol 1e-10): one RK4
+    step from the initial data on the device against the oracle's, per field
+    (zeta, u, U) to 1e-9 relative L2, in the launch configuration the bench
+    times.  (The oracle step takes about 10 s on one core.)"""
+    from paper_2506_16045_amd import sgn
+    cfg = I.config_c3(1024)
+    g, h, eta, u = cfg["grid"], cfg["h"], cfg["eta"], cfg["u"]
+    st, pb, U0 = _setup(ctx, g, h, eta, u, cfg["tol"])
+    prec = sgn.FP64 if precision == "fp64" else sgn.MIXED
+    info = st.step_rk4(cfg["dt"], 1, sgn.solve_opts(tol=cfg["tol"], precision=prec, check_every=8))
+    assert info.converged and info.solves == 4
+    ref = ost.run_rk4(pb, eta, U0, u, cfg["dt"], 1)
+    _compare(st, h, ref, 1e-9)
+    st.close()
