@@ -552,3 +552,105 @@ __global__ void __launch_bounds__(NT) k_batch_solve(const BatchItem* __restrict_
 }
 
 }  // namespace sgn
+
+namespace sgn {
+
+// Right-hand side f(w, p) of a 1D system (Eq:DSWEcf, Def:bigF, Eq:DAE_DSWE) by
+// one workgroup: eta_t = -(eta u)_x, U_t = -eta (eta - h)_x - (eta u u)_x + F
+// with F = S_x - T h_x, S and T of Def:bigF, (u.grad)^2 h read as u (u h_x)_x.
+// All thirteen real transforms run in LDS; spec (5 (N/2+1) modes) and st (5 N
+// points) are global scratch the workgroup owns.  Each thread always handles the
+// same points and modes, so the scratch needs no barriers of its own.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_rhs_1d(int N, double L, const double* __restrict__ eta,
+                                               const double* __restrict__ hx, const double* __restrict__ u,
+                                               double* __restrict__ eta_t, double* __restrict__ U_t,
+                                               cpx<double>* __restrict__ spec, double* __restrict__ st,
+                                               const cpx<double>* __restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<double>* lds = reinterpret_cast<cpx<double>*>(smem_raw);
+    const int M = N / 2, M1 = M + 1;
+    const double tp = 6.283185307179586476925286766559 / L;
+    const double invN = 1.0 / (double)N;
+    double* s_dl = st;
+    double* s_P = st + N;
+    double* s_m = st + 2 * N;
+    double* s_Ut = st + 3 * N;
+    double* s_Q = st + 4 * N;
+    // forward transforms of u, eta u, eta, eta u u, beta = h_x u
+    for (int f = 0; f < 5; ++f) {
+        for (int j = threadIdx.x; j < M; j += NT) {
+            double v[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int i = 2 * j + s;
+                const double e = eta[i], uu = u[i], h = hx[i];
+                v[s] = f == 0 ? uu : f == 1 ? e * uu : f == 2 ? e : f == 3 ? e * uu * uu : h * uu;
+            }
+            lds[j] = C<double>(v[0], v[1]);
+        }
+        blk_rfft_fwd<double, NT>(lds, M, tw);
+        for (int k = threadIdx.x; k <= M; k += NT) spec[f * M1 + k] = lds[k];
+        __syncthreads();
+    }
+    // the derivative fields, consumed pointwise as they arrive:
+    // delta = u_x, delta_x = u_xx, m = (eta u)_x, eta_x, (eta u u)_x, beta_x
+    for (int q = 0; q < 6; ++q) {
+        const int src = q <= 1 ? 0 : q - 1;
+        for (int k = threadIdx.x; k <= M; k += NT) {
+            const double kk = wavenumber<double>(k, N, tp);
+            const cpx<double> X = spec[src * M1 + k];
+            lds[k] = invN * (q == 1 ? (-kk * kk) * X : ik(kk, X));
+        }
+        blk_rfft_inv<double, NT>(lds, M, tw);
+        for (int j = threadIdx.x; j < M; j += NT) {
+            const cpx<double> z = lds[j];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int i = 2 * j + s;
+                const double v = s ? z.im : z.re;
+                if (q == 0) {
+                    s_dl[i] = v;
+                    s_P[i] = -v * v;
+                } else if (q == 1) {
+                    s_P[i] += u[i] * v;
+                } else if (q == 2) {
+                    s_m[i] = v;
+                } else if (q == 3) {
+                    s_Ut[i] = -eta[i] * (v - hx[i]);
+                } else if (q == 4) {
+                    s_Ut[i] = s_Ut[i] - v;
+                } else {
+                    s_Q[i] = u[i] * v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // S, T, eta_t and U_t without S_x; then U_t += S_x
+    for (int j = threadIdx.x; j < M; j += NT) {
+        double sv[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int i = 2 * j + s;
+            const double e = eta[i], h = hx[i], uu = u[i];
+            const double bt = h * uu, e2 = e * e;
+            const double mm = s_m[i], d0 = s_dl[i], pp = s_P[i], qq = s_Q[i];
+            sv[s] = e2 * e / 3.0 * pp + e2 * mm * d0 + e2 / 2.0 * qq + e * mm * bt;
+            const double Tv = e2 / 2.0 * pp + e * mm * d0 + e * qq + mm * bt;
+            eta_t[i] = -mm;
+            U_t[i] = s_Ut[i] - h * Tv;
+        }
+        lds[j] = C<double>(sv[0], sv[1]);
+    }
+    blk_rfft_fwd<double, NT>(lds, M, tw);
+    for (int k = threadIdx.x; k <= M; k += NT) lds[k] = invN * ik(wavenumber<double>(k, N, tp), lds[k]);
+    blk_rfft_inv<double, NT>(lds, M, tw);
+    for (int j = threadIdx.x; j < M; j += NT) {
+        const cpx<double> z = lds[j];
+        U_t[2 * j] = z.re + U_t[2 * j];
+        U_t[2 * j + 1] = z.im + U_t[2 * j + 1];
+    }
+}
+
+}  // namespace sgn

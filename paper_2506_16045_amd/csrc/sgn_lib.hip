@@ -422,8 +422,14 @@ size_t workspace_bytes(const Dims& d, int precision) {
         carve_rhs(cv, d);
         best = std::max(best, cv.off);
     }
-    if (d.D == 1 && d.nx <= BATCH_NMAX)   // one-workgroup 1D solve: item, result, system region
+    if (d.D == 1 && d.nx <= BATCH_NMAX) {   // one-workgroup 1D solve and right-hand side
         best = std::max(best, (size_t)512 + (size_t)batch_item_doubles(d.nx, BATCH_MIXED) * sizeof(double));
+        Carve cv(nullptr);
+        carve_common(cv);
+        cv.take<cpx<double>>((size_t)5 * (d.nx / 2 + 1));
+        cv.take<double>((size_t)5 * d.nx);
+        best = std::max(best, cv.off);
+    }
     return best + 256;
 }
 
@@ -1215,8 +1221,29 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     return rows_inv<double, double>(ctx, d, gs2, ud, 1.0, 1.0);
 }
 
+// A 1D right-hand side of up to BATCH_NMAX points by one workgroup in one launch.
+sgn_status rhs_1d_block(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* u,
+                        double* eta_t, double* U_t, void* ws) {
+    Carve cv(ws);
+    carve_common(cv);
+    const int M1 = d.nx / 2 + 1;
+    cpx<double>* spec = cv.take<cpx<double>>((size_t)5 * M1);
+    double* st = cv.take<double>((size_t)5 * d.nx);
+    const size_t lds = (size_t)M1 * sizeof(cpx<double>);
+    ProfScope ps(ctx, SGN_KERNEL_ROWS);
+    auto launch = [&](auto k, int nt) -> sgn_status {
+        HIPCHK(ctx, allow_lds(k, lds));
+        hipLaunchKernelGGL(k, dim3(1), dim3(nt), lds, ctx->stream, d.nx, d.Lx, eta, gh, u, eta_t, U_t, spec, st,
+                           ctx->tw64);
+        CHECK_LAUNCH(ctx);
+        return SGN_OK;
+    };
+    return d.nx <= 2048 ? launch(k_rhs_1d<256>, 256) : launch(k_rhs_1d<512>, 512);
+}
+
 sgn_status rhs_dispatch(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* u,
                         double* eta_t, double* U_t, void* ws) {
+    if (d.D == 1 && d.nx <= BATCH_NMAX) return rhs_1d_block(ctx, d, eta, gh, u, eta_t, U_t, ws);
     return d.D == 1 ? rhs_impl<1>(ctx, d, eta, gh, u, eta_t, U_t, ws) : rhs_impl<2>(ctx, d, eta, gh, u, eta_t, U_t, ws);
 }
 
