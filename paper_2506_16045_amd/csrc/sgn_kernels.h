@@ -371,41 +371,75 @@ __device__ __forceinline__ cpx<T> lin_coef(int code, T kx, T ky) {
     }
 }
 
-template <typename T, int EPC, int NI>
+// Inputs loaded (and y-transformed) G fields at a time in lockstep; outputs
+// formed and inverse-transformed G at a time.
+template <typename T, int EPC, int G>
+__device__ __forceinline__ void cols_lin_load(const ColGeom& g, const ColThread<T>& ct,
+                                              const PtrList<const cpx<T>, MAXF>& src, int i0,
+                                              const cpx<T>* twm, cpx<T> (&vi)[G][EPC]) {
+    const cpx<T>* srcs[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) srcs[k] = src.p[i0 + k];
+    col_load<T, EPC, G>(g, ct, srcs, true, twm, vi);
+}
+
+template <typename T, int EPC, int G, int NI>
+__device__ __forceinline__ void cols_lin_store(const ColGeom& g, const ColThread<T>& ct,
+                                               const PtrList<cpx<T>, MAXF>& dst, const LinCodes& lc, int o0,
+                                               const cpx<T> (&in)[NI][EPC], T kx, T tpy, T scale,
+                                               const cpx<T>* twm) {
+    cpx<T> v[G][EPC];
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int j = ct.t + g.TPC * e;
+        const T ky = (g.ny > 1) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            cpx<T> s = C<T>(0, 0);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) s = s + lin_coef<T>(lc.code[o0 + k][i], kx, ky) * in[i][e];
+            v[k][e] = scale * s;
+        }
+    }
+    cpx<T>* dsts[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) dsts[k] = dst.p[o0 + k];
+    col_store<T, EPC, G>(g, ct, v, dsts, true, twm);
+}
+
+template <typename T, int EPC, int NI, int G>
 __global__ void __launch_bounds__(256) k_cols_lin(ColGeom g, PtrList<const cpx<T>, MAXF> src,
                                                    PtrList<cpx<T>, MAXF> dst, LinCodes lc,
                                                    const cpx<T>* __restrict__ tw, T tpx, T tpy,
                                                    T scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, 1));
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, G));
     const ColThread<T> ct = col_thread<T>(g, lds);
-    // inputs transformed one at a time through a single LDS column buffer (a
-    // small LDS footprint keeps several blocks resident per compute unit)
     cpx<T> in[NI][EPC];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const cpx<T>* srcs[1] = {src.p[i]};
-        cpx<T> vi[1][EPC];
-        col_load<T, EPC, 1>(g, ct, srcs, true, twm, vi);
+    for (int i0 = 0; i0 < NI; i0 += G) {
+        if (i0 + G <= NI) {
+            cpx<T> vi[G][EPC];
+            cols_lin_load<T, EPC, G>(g, ct, src, i0, twm, vi);
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) in[i][e] = vi[0][e];
+            for (int k = 0; k < G; ++k)
+#pragma unroll
+                for (int e = 0; e < EPC; ++e) in[(i0 + k) % NI][e] = vi[k][e];
+        } else {
+#pragma unroll
+            for (int i = i0; i < NI; ++i) {
+                cpx<T> vi[1][EPC];
+                cols_lin_load<T, EPC, 1>(g, ct, src, i, twm, vi);
+#pragma unroll
+                for (int e = 0; e < EPC; ++e) in[i][e] = vi[0][e];
+            }
+        }
     }
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
-    for (int o = 0; o < lc.no; ++o) {
-        cpx<T> v[1][EPC];
-#pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            const int j = ct.t + g.TPC * e;
-            const T ky = (g.ny > 1) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
-            cpx<T> s = C<T>(0, 0);
-#pragma unroll
-            for (int i = 0; i < NI; ++i) s = s + lin_coef<T>(lc.code[o][i], kx, ky) * in[i][e];
-            v[0][e] = scale * s;
-        }
-        cpx<T>* dsts[1] = {dst.p[o]};
-        col_store<T, EPC, 1>(g, ct, v, dsts, true, twm);
-    }
+    int o0 = 0;
+    for (; o0 + G <= lc.no; o0 += G) cols_lin_store<T, EPC, G, NI>(g, ct, dst, lc, o0, in, kx, tpy, scale, twm);
+    for (; o0 < lc.no; ++o0) cols_lin_store<T, EPC, 1, NI>(g, ct, dst, lc, o0, in, kx, tpy, scale, twm);
 }
 
 // A^{-1} on D spectral columns: y-FFT, per-mode A^{-1} (times scale), y-IFFT.

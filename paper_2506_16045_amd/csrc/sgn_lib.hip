@@ -314,11 +314,12 @@ sgn_status cols_lin_n(sgn_ctx* ctx, const Dims& d, const std::vector<const cpx<T
     t.n = lc.no;
     for (int i = 0; i < NI; ++i) s.p[i] = src[i];
     for (int i = 0; i < lc.no; ++i) t.p[i] = dst[i];
-    auto k = k_cols_lin<T, 4, NI>;
+    // one field at a time: lockstep groups cost more registers than they save barriers
+    auto k = k_cols_lin<T, 4, NI, 1>;
     const size_t lds = col_lds_bytes<T>(L.g, 1);
     HIPCHK(ctx, allow_lds(k, lds));
-    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, s, t, lc,
-                       twiddles<T>(ctx), (T)d.tpx, (T)d.tpy, scale);
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, s, t, lc, twiddles<T>(ctx),
+                       (T)d.tpx, (T)d.tpy, scale);
     CHECK_LAUNCH(ctx);
     return SGN_OK;
 }
@@ -1170,15 +1171,20 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     for (int i = 0; i < 2 * D; ++i) oB.push_back(OB + i * NS);
     // codes: 1 id, 2 ikx, 3 iky, 4 (ikx)^2, 5 (ikx)(iky), 6 (iky)^2
     if (D == 2) {
-        // A inputs [u, v, eu, ev, eta] -> [delta, dx delta, dy delta, m, dx eta, dy eta]
-        if ((s = cols_lin<double>(ctx, d, cA, oA,
-                                  {{2, 3, 0, 0, 0}, {4, 5, 0, 0, 0}, {5, 6, 0, 0, 0},
-                                   {0, 0, 2, 3, 0}, {0, 0, 0, 0, 2}, {0, 0, 0, 0, 3}}, d.inv_n)) != SGN_OK)
-            return s;
-        // B inputs [euu, euv, evv, beta] -> [div_x, div_y, dx beta, dy beta]
-        if ((s = cols_lin<double>(ctx, d, cB, oB, {{2, 3, 0, 0}, {0, 2, 3, 0}, {0, 0, 0, 2}, {0, 0, 0, 3}},
+        // the column operators, split by shared inputs so that each column kernel
+        // holds few transformed inputs in registers:
+        // [u, v] -> [delta, dx delta, dy delta]; [eu, ev, eta] -> [m, dx eta, dy eta];
+        // [euu, euv, evv] -> [div_x, div_y]; [beta] -> [dx beta, dy beta]
+        if ((s = cols_lin<double>(ctx, d, {cA[0], cA[1]}, {oA[0], oA[1], oA[2]}, {{2, 3}, {4, 5}, {5, 6}},
                                   d.inv_n)) != SGN_OK)
             return s;
+        if ((s = cols_lin<double>(ctx, d, {cA[2], cA[3], cA[4]}, {oA[3], oA[4], oA[5]},
+                                  {{2, 3, 0}, {0, 0, 2}, {0, 0, 3}}, d.inv_n)) != SGN_OK)
+            return s;
+        if ((s = cols_lin<double>(ctx, d, {cB[0], cB[1], cB[2]}, {oB[0], oB[1]}, {{2, 3, 0}, {0, 2, 3}},
+                                  d.inv_n)) != SGN_OK)
+            return s;
+        if ((s = cols_lin<double>(ctx, d, {cB[3]}, {oB[2], oB[3]}, {{2}, {3}}, d.inv_n)) != SGN_OK) return s;
     } else {
         if ((s = cols_lin<double>(ctx, d, cA, oA, {{2, 0, 0}, {4, 0, 0}, {0, 2, 0}, {0, 0, 2}}, d.inv_n)) != SGN_OK)
             return s;
