@@ -240,12 +240,15 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_fwd(RowGeom g, const double* 
     }
 }
 
-// Inverse row transforms of the derivative fields Q (order: delta, d_c delta,
-// m = div(eta u), d_c eta, div_c(eta u (x) u), d_c beta) in groups of NFG,
-// consumed into the pointwise right-hand side as they arrive: eta_t = -m,
-// U_t = -eta grad(eta - h) - div(eta u (x) u) - T grad h, and S of Def:bigF,
-// whose forward row transform goes to Sdst (grad S is added to U_t later).
-// P = u.grad(delta) - delta^2, Q = u.grad(beta) (the reading u.grad(u.grad h)).
+// Inverse row transforms of the derivative fields Q, in the order m =
+// div(eta u), delta = div u, d_c delta, d_c eta, div_c(eta u (x) u), d_c beta,
+// in groups of NFG, consumed into the pointwise right-hand side as they
+// arrive: eta_t = -m, U_t = -eta grad(eta - h) - div(eta u (x) u) - T grad h,
+// and S, T of Def:bigF accumulated as S = e^3/3 P + e^2 m delta + e m beta +
+// e^2/2 Q, T = e^2/2 P + e m delta + m beta + e Q with P = u.grad(delta) -
+// delta^2 and Q = u.grad(beta) (the reading u.grad(u.grad h)), so that at most
+// four values per point are live.  S's forward row transform goes to Sdst
+// (grad S is added to U_t later).
 template <int D, int EPC, int NFG, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_rhs_rows_inv(RowGeom g, PtrList<const cpx<double>, MAXF> src,
                                                        const double* __restrict__ eta, const double* __restrict__ u,
@@ -258,8 +261,9 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_inv(RowGeom g, PtrList<const 
     const RowThread<double> rt = row_thread<double>(g, lds);
     const size_t npts = (size_t)g.nx * g.ny;
     constexpr int NQ = 4 * D + 2;
-    // running pointwise state at the thread's 2 EPC points
-    double dl[EPC][2], P[EPC][2], m[EPC][2], Q[EPC][2], Ut[D][EPC][2];
+    // live state per point: (m, delta, P) while the first 2 + D fields arrive,
+    // then (S, T) and U_t (D)
+    double A0[EPC][2], A1[EPC][2], A2[EPC][2], Ut[D][EPC][2];
     for (int f0 = 0; f0 < NQ; f0 += NFG) {
         const int nf = NQ - f0 < NFG ? NQ - f0 : NFG;
         cpx<double> z[NFG][EPC];
@@ -289,30 +293,43 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_inv(RowGeom g, PtrList<const 
                         const int i = f0 + k;
                         if (k >= nf) continue;
                         const double q = scale * (s ? z[k][e].im : z[k][e].re);
-                        if (i == 0) {
-                            dl[e][s] = q;
-                            P[e][s] = -q * q;
-                        } else if (i <= D) {
-                            P[e][s] += u[(i - 1) * npts + o + s] * q;
-                        } else if (i == 1 + D) {
-                            m[e][s] = q;
-                        } else if (i <= 1 + 2 * D) {
+                        if (i == 0) {                       // m
+                            A0[e][s] = q;
+                            eta_t[o + s] = -q;
+                        } else if (i == 1) {                // delta
+                            A1[e][s] = q;
+                            A2[e][s] = -q * q;
+                        } else if (i <= 1 + D) {            // d_c delta: P += u_c d_c delta
+                            const int c = i - 2;
+                            A2[e][s] += u[c * npts + o + s] * q;
+                            if (c == D - 1) {               // P complete: fold into S, T
+                                const double e0 = eta[o + s];
+                                double bt = 0.0;
+#pragma unroll
+                                for (int cc = 0; cc < D; ++cc) bt += gh[cc * npts + o + s] * u[cc * npts + o + s];
+                                const double e2 = e0 * e0, mm = A0[e][s], d0 = A1[e][s], pp = A2[e][s];
+                                A0[e][s] = e2 * e0 / 3.0 * pp + e2 * mm * d0 + e0 * mm * bt;   // S
+                                A1[e][s] = e2 / 2.0 * pp + e0 * mm * d0 + mm * bt;            // T
+                            }
+                        } else if (i <= 1 + 2 * D) {        // d_c eta
                             const int c = i - 2 - D;
                             Ut[c][e][s] = -eta[o + s] * (q - gh[c * npts + o + s]);
-                        } else if (i <= 1 + 3 * D) {
+                        } else if (i <= 1 + 3 * D) {        // div_c(eta u (x) u)
                             const int c = i - 2 - 2 * D;
                             Ut[c][e][s] = Ut[c][e][s] - q;
-                        } else {
+                        } else {                            // d_c beta: Q += u_c d_c beta
                             const int c = i - 2 - 3 * D;
+                            const double e0 = eta[o + s];
                             const double t = u[c * npts + o + s] * q;
-                            Q[e][s] = c == 0 ? t : Q[e][s] + t;
+                            A0[e][s] += e0 * e0 / 2.0 * t;
+                            A1[e][s] += e0 * t;
                         }
                     }
                 }
             }
         }
     }
-    // S, T and the outputs; S forward-transformed
+    // U_t = U_t - T grad h; S forward-transformed
     cpx<double> zs[1][EPC];
 #pragma unroll
     for (int e = 0; e < EPC; ++e) {
@@ -320,27 +337,12 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_inv(RowGeom g, PtrList<const 
         zs[0][e] = C<double>(0, 0);
         if (j < g.M && rt.valid) {
             const size_t o = (size_t)rt.y * g.nx + 2 * j;
-            double sv[2];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const double e0 = eta[o + s];
-                double hc[D], uc[D];
-                double bt = 0.0;
 #pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    uc[c] = u[c * npts + o + s];
-                    hc[c] = gh[c * npts + o + s];
-                    bt += hc[c] * uc[c];
-                }
-                const double e2 = e0 * e0;
-                const double mm = m[e][s], d0 = dl[e][s], pp = P[e][s], qq = Q[e][s];
-                sv[s] = e2 * e0 / 3.0 * pp + e2 * mm * d0 + e2 / 2.0 * qq + e0 * mm * bt;
-                const double Tv = e2 / 2.0 * pp + e0 * mm * d0 + e0 * qq + mm * bt;
-                eta_t[o + s] = -mm;
-#pragma unroll
-                for (int c = 0; c < D; ++c) U_t[c * npts + o + s] = Ut[c][e][s] - hc[c] * Tv;
+                for (int c = 0; c < D; ++c) U_t[c * npts + o + s] = Ut[c][e][s] - gh[c * npts + o + s] * A1[e][s];
             }
-            zs[0][e] = C<double>(sv[0], sv[1]);
+            zs[0][e] = C<double>(A0[e][0], A0[e][1]);
         }
     }
     cpx<double>* Hs1[1] = {Sdst};

@@ -1157,7 +1157,15 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
             CHECK_LAUNCH(ctx);
             return SGN_OK;
         };
-        if (RL.epc == 4 && RL.threads <= 256)
+        // the forward pass holds no pointwise state: its fields go three at a time
+        const size_t l3 = row_lds_bytes<double>(RL.g, 3);
+        if (RL.epc == 4 && RL.threads <= 256 && l3 <= LDS_MULTI_MAX) {
+            HIPCHK(ctx, allow_lds(k_rhs_rows_fwd<D, 4, 3, 256>, l3));
+            hipLaunchKernelGGL((k_rhs_rows_fwd<D, 4, 3, 256>), dim3(RL.g.nblocks), dim3(RL.threads), l3,
+                               ctx->stream, RL.g, eta, u, gh, t, ctx->tw64);
+            CHECK_LAUNCH(ctx);
+            s = SGN_OK;
+        } else if (RL.epc == 4 && RL.threads <= 256)
             s = launch(k_rhs_rows_fwd<D, 4, 1, 256>);
         else if (RL.epc == 4)
             s = launch(k_rhs_rows_fwd<D, 4, 1, 1024>);
@@ -1196,7 +1204,11 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
         ProfScope ps(ctx, SGN_KERNEL_ROWS);
         PtrList<const cpx<double>, MAXF> q{};
         q.n = 0;
-        for (int i = 0; i < 2 * D + 2; ++i) q.p[q.n++] = OA + i * NS;
+        // OA = [delta, d delta (D), m, d eta (D)], OB = [div (D), d beta (D)]; consumed as
+        // m, delta, d delta, d eta, div, d beta
+        q.p[q.n++] = OA + (1 + D) * NS;
+        for (int i = 0; i <= D; ++i) q.p[q.n++] = OA + i * NS;
+        for (int i = 0; i < D; ++i) q.p[q.n++] = OA + (2 + D + i) * NS;
         for (int i = 0; i < 2 * D; ++i) q.p[q.n++] = OB + i * NS;
         auto launch = [&](auto k) -> sgn_status {
             HIPCHK(ctx, allow_lds(k, rlds));
