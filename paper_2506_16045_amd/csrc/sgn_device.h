@@ -249,38 +249,33 @@ __host__ __device__ inline int row_lds_data(const RowGeom& g, int NF) { return N
 // Inverse row transforms of NF fields: H_f[kx][y] (kx = 0..M) -> real pairs
 // z[f][e] = (x_2j, x_2j+1), unnormalised (nx times the inverse DFT).  The
 // imaginary parts of the kx = 0 and kx = nx/2 entries are ignored (real signal).
+// The even/odd recombination Z_k = (X_k + X*_{M-k}) + i (X_k - X*_{M-k}) W_nx^{-k}
+// is formed while the mirrored pair (k, M - k) is loaded from H, so it costs no
+// LDS pass of its own.
 template <typename T, int EPC, int NF>
 __device__ __forceinline__ void row_inverse(const RowGeom& g, const RowThread<T>& rt,
                                             const cpx<T>* const (&H)[NF],
                                             const cpx<T>* __restrict__ tw_all, const cpx<T>* twm,
                                             cpx<T> (&z)[NF][EPC]) {
     const int M = g.M, R = g.R, ny = g.ny;
-    const int total = R * (M + 1);
+    const int totalp = R * (M / 2 + 1);
+    const cpx<T>* tw2 = tw_size(tw_all, 2 * M);  // W_nx^k
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        for (int i = threadIdx.x; i < total; i += blockDim.x) {
+        for (int i = threadIdx.x; i < totalp; i += blockDim.x) {
             const int r = i & (R - 1);
-            const int kx = i / R;
+            const int p = i / R;
             const int y = rt.row0 + r;
-            rt.lds[f * rt.fstride + r * (M + 1) + kx] = (y < ny) ? H[f][(size_t)kx * ny + y] : C<T>(0, 0);
-        }
-    }
-    __syncthreads();
-    const cpx<T>* tw2 = tw_size(tw_all, 2 * M);  // W_nx^k
-    cpx<T>* rowb = rt.lds + rt.r * (M + 1);
-    for (int p = rt.t; p <= M / 2; p += g.TPR) {
-        const int k = p, m = M - p;
-        cpx<T> wk = tw2[k], wm = tw2[m < 2 * M ? m : 0];
-        wk.im = -wk.im;
-        wm.im = -wm.im;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            cpx<T>* b = rowb + f * rt.fstride;
+            const int k = p, m = M - p;
+            const cpx<T> Xk = (y < ny) ? H[f][(size_t)k * ny + y] : C<T>(0, 0);
+            const cpx<T> Xm = (y < ny) ? H[f][(size_t)m * ny + y] : C<T>(0, 0);
+            cpx<T>* b = rt.lds + f * rt.fstride + r * (M + 1);
             if (p == 0) {
-                const T x0 = b[0].re, xm = b[M].re;
-                b[0] = C<T>(x0 + xm, x0 - xm);
+                b[0] = C<T>(Xk.re + Xm.re, Xk.re - Xm.re);
             } else {
-                const cpx<T> Xk = b[k], Xm = b[m];
+                cpx<T> wk = tw2[k], wm = tw2[m];
+                wk.im = -wk.im;
+                wm.im = -wm.im;
                 const cpx<T> Zk = (Xk + cj(Xm)) + mul_i((Xk - cj(Xm)) * wk);
                 if (m != k) b[m] = (Xm + cj(Xk)) + mul_i((Xm - cj(Xk)) * wm);
                 b[k] = Zk;
@@ -288,6 +283,7 @@ __device__ __forceinline__ void row_inverse(const RowGeom& g, const RowThread<T>
         }
     }
     __syncthreads();
+    cpx<T>* rowb = rt.lds + rt.r * (M + 1);
     lds_fft<T, EPC, NF>(rowb, rt.fstride, M, rt.t, g.TPR, twm, true);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -301,7 +297,9 @@ __device__ __forceinline__ void row_inverse(const RowGeom& g, const RowThread<T>
 }
 
 // Forward row transforms of NF fields: real pairs z[f][e] -> H_f[kx][y] for
-// kx = 0..M, each value multiplied by `scale`.
+// kx = 0..M, each value multiplied by `scale`.  The recombination
+// X_k = (Z_k + Z*_{M-k})/2 - i W_nx^k (Z_k - Z*_{M-k})/2 is formed as each entry
+// is stored (no LDS pass of its own).
 template <typename T, int EPC, int NF>
 __device__ __forceinline__ void row_forward(const RowGeom& g, const RowThread<T>& rt, const cpx<T> (&z)[NF][EPC],
                                             cpx<T>* const (&H)[NF], const cpx<T>* __restrict__ tw_all,
@@ -320,25 +318,6 @@ __device__ __forceinline__ void row_forward(const RowGeom& g, const RowThread<T>
     lds_fft<T, EPC, NF>(rowb, rt.fstride, M, rt.t, g.TPR, twm, false);
     const cpx<T>* tw2 = tw_size(tw_all, 2 * M);
     const T half = (T)0.5;
-    for (int p = rt.t; p <= M / 2; p += g.TPR) {
-        const int k = p, m = M - p;
-        const cpx<T> wk = tw2[k], wm = tw2[m < 2 * M ? m : 0];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            cpx<T>* b = rowb + f * rt.fstride;
-            if (p == 0) {
-                const cpx<T> Z0 = b[0];
-                b[0] = C<T>(Z0.re + Z0.im, 0);
-                b[M] = C<T>(Z0.re - Z0.im, 0);
-            } else {
-                const cpx<T> Zk = b[k], Zm = b[m];
-                const cpx<T> Xk = half * (Zk + cj(Zm)) - half * mul_i(wk * (Zk - cj(Zm)));
-                if (m != k) b[m] = half * (Zm + cj(Zk)) - half * mul_i(wm * (Zm - cj(Zk)));
-                b[k] = Xk;
-            }
-        }
-    }
-    __syncthreads();
     const int total = R * (M + 1);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -346,7 +325,17 @@ __device__ __forceinline__ void row_forward(const RowGeom& g, const RowThread<T>
             const int r = i & (R - 1);
             const int kx = i / R;
             const int y = rt.row0 + r;
-            if (y < ny) H[f][(size_t)kx * ny + y] = scale * rt.lds[f * rt.fstride + r * (M + 1) + kx];
+            const cpx<T>* b = rt.lds + f * rt.fstride + r * (M + 1);
+            cpx<T> X;
+            if (kx == 0 || kx == M) {
+                const cpx<T> Z0 = b[0];
+                X = C<T>(kx == 0 ? Z0.re + Z0.im : Z0.re - Z0.im, 0);
+            } else {
+                const cpx<T> wk = tw2[kx];
+                const cpx<T> Zk = b[kx], Zm = b[M - kx];
+                X = half * (Zk + cj(Zm)) - half * mul_i(wk * (Zk - cj(Zm)));
+            }
+            if (y < ny) H[f][(size_t)kx * ny + y] = scale * X;
         }
     }
     __syncthreads();
