@@ -98,7 +98,7 @@ typedef struct sgn_solve_opts {
     double tol;            /* stop when ||r||_2 <= tol ||b||_2 */
     int32_t max_iter;      /* Krylov iterations (inner iterations in mixed mode) */
     int32_t x0_is_guess;   /* 1: u_inout is the initial guess; 0: start from 0 */
-    int32_t gmres_restart; /* GMRES restart length (<= 64) */
+    int32_t gmres_restart; /* GMRES restart length m, 1 <= m <= 256 */
     double inner_tol;      /* mixed mode: relative tolerance of each FP32 inner solve */
     int32_t max_outer;     /* mixed mode: refinement steps */
     int32_t check_every;   /* convergence flag read back every this many iterations (>= 1) */
@@ -192,16 +192,28 @@ sgn_status sgn_apply_constraint(sgn_ctx *ctx, const sgn_grid *grid, const double
 sgn_status sgn_precond_solve(sgn_ctx *ctx, const sgn_grid *grid, const sgn_coeffs *coeffs,
                              const double *d_rhs, double *d_out, void *d_ws);
 
-/* Solve G_{eta,h} u = rhs by PCG preconditioned with A (section 3.2,
- * Eq:PCGLinSyst).  method = SGN_GMRES returns SGN_EUNSUPPORTED (GMRES of
- * section 3.2 is not built on the device).  coeffs = NULL computes the
- * coefficients from eta (opts->coeff_kind).  On SGN_ENOCONV d_u_inout holds
- * the last iterate and *info is filled.  opts = NULL uses PCG, FP64, tol
- * 1e-12, max_iter 1000, zero initial guess. */
+/* Solve G_{eta,h} u = rhs by a Krylov method preconditioned with A (section
+ * 3.2, Eq:PCGLinSyst).  method = SGN_PCG: preconditioned conjugate gradients
+ * (FP64, or FP32 inner solves with FP64 refinement for SGN_MIXED).
+ * method = SGN_GMRES: right-preconditioned restarted GMRES(m) with
+ * m = opts->gmres_restart, FP64 only (SGN_EUNSUPPORTED otherwise); the stop
+ * test is the same, the residual estimate of the Arnoldi step ends a cycle and
+ * the true residual of each restart decides; info->iters counts operator
+ * applications inside Arnoldi steps.  GMRES needs the larger workspace of
+ * sgn_gmres_workspace_bytes(grid, m) (the size is not checked: d_ws must be
+ * at least that).  coeffs = NULL computes the coefficients from eta
+ * (opts->coeff_kind).  On SGN_ENOCONV d_u_inout holds the last iterate and
+ * *info is filled.  opts = NULL uses PCG, FP64, tol 1e-12, max_iter 1000, zero
+ * initial guess. */
 sgn_status sgn_krylov_solve(sgn_ctx *ctx, const sgn_grid *grid, const double *d_eta,
                             const double *d_grad_h, const double *d_rhs, double *d_u_inout,
                             const sgn_coeffs *coeffs, const sgn_solve_opts *opts,
                             sgn_solve_info *info, void *d_ws);
+
+/* Bytes of workspace sgn_krylov_solve needs with method = SGN_GMRES and
+ * restart length m (m + 1 basis vectors of the grid's half spectrum); 0 for an
+ * unsupported grid or m outside [1, 256]. */
+size_t sgn_gmres_workspace_bytes(const sgn_grid *grid, int32_t restart);
 
 /* ---- batched independent 1D solves ----------------------------------------- */
 

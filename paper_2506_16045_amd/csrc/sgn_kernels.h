@@ -1263,3 +1263,86 @@ __global__ void k_S_accumulate(size_t n, const cpx<float>* __restrict__ s, cpx<d
 }
 
 }  // namespace sgn
+
+namespace sgn {
+
+// ---------------------------------------------------------------------------
+// GMRES building blocks on D-vector fields in the S layout (modes [kx][ky],
+// kx = 0..nx/2), FP64.  Dot products are Parseval sums over the half spectrum
+// (weight 1 at kx = 0 and nx/2, 2 elsewhere) divided by nx ny.
+// ---------------------------------------------------------------------------
+
+// Per-block partials of <w, V_i> for i < nv (V_i = V + i * vstride):
+// part[block * nv + i].
+template <int D>
+__global__ void __launch_bounds__(256) k_S_multidot(int nx, int ny, size_t NS, const cpx<double>* __restrict__ w,
+                                                    const cpx<double>* __restrict__ V, size_t vstride, int nv,
+                                                    double* __restrict__ part) {
+    __shared__ double red[16 * 8];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (int i0 = 0; i0 < nv; i0 += 8) {
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const int nb = nv - i0 < 8 ? nv - i0 : 8;
+        for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < NS; idx += stride) {
+            const int kx = (int)(idx / ny);
+            const double wt = half_weight(kx, nx);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const cpx<double> a = w[c * NS + idx];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (k < nb) {
+                        const cpx<double> v = V[(size_t)(i0 + k) * vstride + c * NS + idx];
+                        acc[k] += wt * (a.re * v.re + a.im * v.im);
+                    }
+                }
+            }
+        }
+        block_sum<8>(acc, red);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < nb; ++k) part[(size_t)blockIdx.x * nv + i0 + k] = acc[k];
+    }
+}
+
+// out[i] = scale * sum over blocks of part[b * nv + i] (fixed order), one block.
+__global__ void __launch_bounds__(256) k_S_multidot_finish(const double* __restrict__ part, int nblocks, int nv,
+                                                           double scale, double* __restrict__ out) {
+    __shared__ double red[16];
+    for (int i = 0; i < nv; ++i) {
+        double v[1] = {0.0};
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v[0] += part[(size_t)b * nv + i];
+        block_sum<1>(v, red);
+        if (threadIdx.x == 0) out[i] = scale * v[0];
+    }
+}
+
+// w += sum_i coef[i] V_i (coef in device memory, nv <= 65), over n doubles.
+__global__ void k_S_multiaxpy(size_t n, double* __restrict__ w, const double* __restrict__ V, size_t vstride_d,
+                              int nv, const double* __restrict__ coef, double sign) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double s = 0.0;
+        for (int k = 0; k < nv; ++k) s += coef[k] * V[(size_t)k * vstride_d + i];
+        w[i] += sign * s;
+    }
+}
+
+// z = A^{-1} v on S fields (Def:A, section 6.1).
+template <int D>
+__global__ void k_S_precond(int nx, int ny, size_t NS, double tpx, double tpy, double sig, double alp,
+                            const cpx<double>* __restrict__ v, cpx<double>* __restrict__ z) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < NS; idx += stride) {
+        const int kxi = (int)(idx / ny), kyi = (int)(idx - (size_t)kxi * ny);
+        const double kx = wavenumber<double>(kxi, nx, tpx);
+        const double ky = D == 2 ? wavenumber<double>(kyi, ny, tpy) : 0.0;
+        cpx<double> r[D], zz[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) r[c] = v[c * NS + idx];
+        precond_mode<double, D>(kx, ky, sig, alp, r, zz);
+#pragma unroll
+        for (int c = 0; c < D; ++c) z[c * NS + idx] = zz[c];
+    }
+}
+
+}  // namespace sgn

@@ -883,6 +883,269 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     return SGN_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Right-preconditioned restarted GMRES(m) in FP64 (section 3.2 names GMRES
+// beside PCG for the constraint solve).  The Krylov basis lives in the S layout
+// (half spectrum, Parseval inner products), so G is applied by the same three
+// passes as in PCG and A^{-1} is a pointwise multiply.  Arnoldi uses classical
+// Gram-Schmidt with one reorthogonalisation (CGS2: two block dot products and
+// two block updates per step, all against the contiguous basis), which equals
+// modified Gram-Schmidt in exact arithmetic; the small Hessenberg least-squares
+// problem (Givens rotations, back substitution) runs on the host after one
+// readback of the step's coefficients.  Only V_0..V_m are stored: the update
+// x += A^{-1} (V y) uses the linearity of A^{-1} instead of keeping Z_j.
+// ---------------------------------------------------------------------------
+sgn_status batch_staging(sgn_ctx* ctx, size_t bytes);
+template <int D>
+sgn_status to_S_d(sgn_ctx* ctx, const Dims& d, const double* f, cpx<double>* H, cpx<double>* Sd);
+template <int D>
+sgn_status from_S_d(sgn_ctx* ctx, const Dims& d, const cpx<double>* Ssrc, cpx<double>* H, double* f);
+
+constexpr int GMRES_MAX_RESTART = 256;
+constexpr int GMRES_DOT_BLOCKS = 512;
+
+struct GmresBufs {
+    cpx<double>* bh;     // b in S
+    cpx<double>* V;      // (m + 1) basis vectors of D * NS modes
+    double* part;        // per-block partial dot products
+    double* coef;        // device coefficients: h (m + 1), h2 (m + 1), ||w||^2, y (m)
+};
+GmresBufs carve_gmres(Carve& cv, const Dims& d, int m) {
+    GmresBufs g;
+    g.bh = cv.take<cpx<double>>((size_t)d.D * d.NS);
+    g.V = cv.take<cpx<double>>((size_t)(m + 1) * d.D * d.NS);
+    g.part = cv.take<double>((size_t)GMRES_DOT_BLOCKS * (m + 1));
+    g.coef = cv.take<double>((size_t)3 * (m + 2));
+    return g;
+}
+
+size_t gmres_workspace_bytes(const Dims& d, int m) {
+    Carve cv(nullptr);
+    carve_common(cv);
+    carve_pcg<double>(cv, d, false);
+    carve_gmres(cv, d, m);
+    return std::max(cv.off + 256, workspace_bytes(d, SGN_FP64));
+}
+
+template <int D>
+struct Gmres {
+    PcgLaunch<double, D> P;
+    GmresBufs g;
+    int dot_blocks;
+    size_t nd;   // doubles per S vector
+
+    cpx<double>* Vi(int i) { return g.V + (size_t)i * D * P.d.NS; }
+
+    // coef[out .. out + nv) = <w, V_i> for i < nv
+    sgn_status dots(const cpx<double>* w, const cpx<double>* V, int nv, double* out) {
+        sgn_ctx* ctx = P.ctx;
+        hipLaunchKernelGGL(k_S_multidot<D>, dim3(dot_blocks), dim3(256), 0, ctx->stream, P.d.nx, P.d.ny, P.d.NS, w,
+                           V, (size_t)D * P.d.NS, nv, g.part);
+        hipLaunchKernelGGL(k_S_multidot_finish, dim3(1), dim3(256), 0, ctx->stream, (const double*)g.part,
+                           dot_blocks, nv, P.d.inv_n, out);
+        CHECK_LAUNCH(ctx);
+        return SGN_OK;
+    }
+    // w += sign * sum_i coef[i] V_i
+    sgn_status axpy(cpx<double>* w, int nv, const double* coef, double sign) {
+        hipLaunchKernelGGL(k_S_multiaxpy, dim3(flat_blocks(nd)), dim3(256), 0, P.ctx->stream, nd, (double*)w,
+                           (const double*)g.V, nd, nv, coef, sign);
+        CHECK_LAUNCH(P.ctx);
+        return SGN_OK;
+    }
+    // q_hat = G x for x in S (three passes of the PCG operator)
+    sgn_status apply(const cpx<double>* x) {
+        sgn_status s;
+        if ((s = pcg_c1<double, D>(P, C1_COPY, x)) != SGN_OK) return s;
+        if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
+        return pcg_c2<double, D>(P, C2_STORE, nullptr, nullptr);
+    }
+    sgn_status precond(const cpx<double>* v, cpx<double>* z, double sig, double alp) {
+        hipLaunchKernelGGL(k_S_precond<D>, dim3(flat_blocks(P.d.NS)), dim3(256), 0, P.ctx->stream, P.d.nx, P.d.ny,
+                           P.d.NS, P.d.tpx, P.d.tpy, sig, alp, v, z);
+        CHECK_LAUNCH(P.ctx);
+        return SGN_OK;
+    }
+    // y = a x + b y over one S vector
+    sgn_status axpby(double a, const cpx<double>* x, double b, cpx<double>* y) {
+        hipLaunchKernelGGL(k_axpby, dim3(flat_blocks(nd)), dim3(256), 0, P.ctx->stream, nd, a, (const double*)x, b,
+                           (double*)y);
+        CHECK_LAUNCH(P.ctx);
+        return SGN_OK;
+    }
+    sgn_status read(const double* dsrc, double* hdst, int n) {
+        HIPCHK(P.ctx, hipMemcpyAsync(hdst, dsrc, n * sizeof(double), hipMemcpyDeviceToHost, P.ctx->stream));
+        HIPCHK(P.ctx, hipStreamSynchronize(P.ctx->stream));
+        return SGN_OK;
+    }
+};
+
+template <int D>
+sgn_status solve_gmres(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* rhs,
+                       double* u, const sgn_coeffs* coeffs, int flat, const sgn_solve_opts& o,
+                       sgn_solve_info* info, void* ws) {
+    const int m = o.gmres_restart;
+    Carve cv(ws);
+    Common cm = carve_common(cv);
+    Gmres<D> G;
+    auto& P = G.P;
+    P.ctx = ctx;
+    P.d = d;
+    P.rl = row_launch<double>(d.nx, d.ny);
+    P.cl = col_launch<double>(d.nx, d.ny);
+    P.b = carve_pcg<double>(cv, d, false);
+    P.sc = cm.sc;
+    P.partials = cm.partials;
+    P.eta = eta;
+    P.gh = gh;
+    G.g = carve_gmres(cv, d, m);
+    G.dot_blocks = std::min(GMRES_DOT_BLOCKS, flat_blocks(d.NS));
+    G.nd = (size_t)2 * D * d.NS;
+    sgn_status s;
+    if ((s = batch_staging(ctx, (size_t)3 * (m + 2) * sizeof(double))) != SGN_OK) return s;
+    double* hc = static_cast<double*>(ctx->hbatch);
+    // coefficients of A (given or computed), read once: the basis loop is host driven
+    if ((s = init_scal(ctx, P.sc, o.tol, o.max_iter, d.inv_n, coeffs)) != SGN_OK) return s;
+    if (!coeffs) {
+        if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials)) != SGN_OK) return s;
+    }
+    if ((s = read_scal(ctx, P.sc)) != SGN_OK) return s;
+    const SolveScal sc0 = *ctx->hscal;
+    auto finish_info = [&](int iters, bool conv, double relres) {
+        if (!info) return;
+        info->iters = iters;
+        info->outer_iters = 0;
+        info->converged = conv ? 1 : 0;
+        info->relres = relres;
+        info->coeffs.sigma = sc0.sig;
+        info->coeffs.alpha = sc0.alp;
+        info->coeffs.kappa_ub = sc0.kap;
+        info->coeffs.flat = sc0.flat;
+    };
+    if (sc0.status != 0 || !(sc0.sig > 0.0) || !(sc0.alp > 0.0)) {
+        finish_info(0, false, std::nan(""));
+        return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
+    }
+    const double sig = sc0.sig, alp = sc0.alp;
+    cpx<double>* bh = G.g.bh;
+    cpx<double>* xh = P.b.xh;
+    cpx<double>* zh = P.b.ph;
+    cpx<double>* qh = P.b.qh;
+    if ((s = to_S_d<D>(ctx, d, rhs, P.b.H, bh)) != SGN_OK) return s;
+    if ((s = G.dots(bh, bh, 1, G.g.coef)) != SGN_OK) return s;
+    if ((s = G.read(G.g.coef, hc, 1)) != SGN_OK) return s;
+    const double bnorm = std::sqrt(std::max(hc[0], 0.0));
+    if (!std::isfinite(bnorm)) {
+        finish_info(0, false, std::nan(""));
+        return fail(ctx, SGN_EDOMAIN, "non-finite right-hand side");
+    }
+    if (bnorm == 0.0) {   // x = 0 solves it exactly, whatever the guess
+        hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks((size_t)D * d.N)), dim3(256), 0, ctx->stream,
+                           (size_t)D * d.N, (void*)u);
+        CHECK_LAUNCH(ctx);
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        finish_info(0, true, 0.0);
+        return SGN_OK;
+    }
+    const bool guess = o.x0_is_guess != 0;
+    if (guess) {
+        if ((s = to_S_d<D>(ctx, d, u, P.b.H, xh)) != SGN_OK) return s;
+    } else {
+        hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks(G.nd)), dim3(256), 0, ctx->stream, G.nd, (void*)xh);
+        CHECK_LAUNCH(ctx);
+    }
+    std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+    auto H = [&](int i, int j) -> double& { return Hm[(size_t)i * m + j]; };
+    const double thr = o.tol * bnorm;
+    int iters = 0;
+    bool conv = false;
+    double relres = 0.0;
+    for (;;) {
+        // true residual r = b - G x into V_0
+        if (guess || iters > 0) {
+            if ((s = G.apply(xh)) != SGN_OK) return s;
+            if ((s = G.axpby(1.0, bh, 0.0, G.Vi(0))) != SGN_OK) return s;
+            if ((s = G.axpby(-1.0, qh, 1.0, G.Vi(0))) != SGN_OK) return s;
+        } else {
+            if ((s = G.axpby(1.0, bh, 0.0, G.Vi(0))) != SGN_OK) return s;
+        }
+        if ((s = G.dots(G.Vi(0), G.Vi(0), 1, G.g.coef)) != SGN_OK) return s;
+        if ((s = G.read(G.g.coef, hc, 1)) != SGN_OK) return s;
+        const double beta = std::sqrt(std::max(hc[0], 0.0));
+        relres = beta / bnorm;
+        if (!std::isfinite(beta)) {
+            finish_info(iters, false, relres);
+            return fail(ctx, SGN_EDOMAIN, "non-finite residual in the solve");
+        }
+        if (beta <= thr) {
+            conv = true;
+            break;
+        }
+        if (iters >= o.max_iter) break;
+        if ((s = G.axpby(0.0, nullptr, 1.0 / beta, G.Vi(0))) != SGN_OK) return s;
+        std::fill(Hm.begin(), Hm.end(), 0.0);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int jd = 0;
+        for (int j = 0; j < m; ++j) {
+            if ((s = G.precond(G.Vi(j), zh, sig, alp)) != SGN_OK) return s;
+            if ((s = G.apply(zh)) != SGN_OK) return s;
+            ++iters;
+            double* h1 = G.g.coef;
+            double* h2 = G.g.coef + (m + 1);
+            double* ww = G.g.coef + 2 * (m + 1);
+            if ((s = G.dots(qh, G.g.V, j + 1, h1)) != SGN_OK) return s;
+            if ((s = G.axpy(qh, j + 1, h1, -1.0)) != SGN_OK) return s;
+            if ((s = G.dots(qh, G.g.V, j + 1, h2)) != SGN_OK) return s;
+            if ((s = G.axpy(qh, j + 1, h2, -1.0)) != SGN_OK) return s;
+            if ((s = G.dots(qh, qh, 1, ww)) != SGN_OK) return s;
+            if ((s = G.read(G.g.coef, hc, 2 * (m + 1) + 1)) != SGN_OK) return s;
+            for (int i = 0; i <= j; ++i) H(i, j) = hc[i] + hc[m + 1 + i];
+            const double hn = std::sqrt(std::max(hc[2 * (m + 1)], 0.0));
+            H(j + 1, j) = hn;
+            if (!std::isfinite(hn)) {
+                finish_info(iters, false, std::nan(""));
+                return fail(ctx, SGN_EDOMAIN, "non-finite data in the Arnoldi process");
+            }
+            if ((s = G.axpby(hn != 0.0 ? 1.0 / hn : 1.0, qh, 0.0, G.Vi(j + 1))) != SGN_OK) return s;
+            for (int i = 0; i < j; ++i) {   // earlier rotations
+                const double t = cs[i] * H(i, j) + sn[i] * H(i + 1, j);
+                H(i + 1, j) = -sn[i] * H(i, j) + cs[i] * H(i + 1, j);
+                H(i, j) = t;
+            }
+            const double den = std::hypot(H(j, j), H(j + 1, j));
+            cs[j] = H(j, j) / den;
+            sn[j] = H(j + 1, j) / den;
+            H(j, j) = den;
+            H(j + 1, j) = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            jd = j + 1;
+            if (std::fabs(gv[j + 1]) <= thr || iters >= o.max_iter) break;
+        }
+        // y = R^{-1} g, then x += A^{-1} (V y)
+        for (int i = jd - 1; i >= 0; --i) {
+            double t = gv[i];
+            for (int k = i + 1; k < jd; ++k) t -= H(i, k) * y[k];
+            y[i] = t / H(i, i);
+        }
+        for (int i = 0; i < jd; ++i) hc[i] = y[i];
+        double* yd = G.g.coef;
+        HIPCHK(ctx, hipMemcpyAsync(yd, hc, jd * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        if ((s = G.axpby(0.0, nullptr, 0.0, zh)) != SGN_OK) return s;
+        if ((s = G.axpy(zh, jd, yd, 1.0)) != SGN_OK) return s;
+        if ((s = G.precond(zh, qh, sig, alp)) != SGN_OK) return s;
+        if ((s = G.axpby(1.0, qh, 1.0, xh)) != SGN_OK) return s;
+        // the host copy of y must not be overwritten before the upload has run
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if ((s = from_S_d<D>(ctx, d, xh, P.b.H, u)) != SGN_OK) return s;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    finish_info(iters, conv, relres);
+    if (!conv) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
+    return SGN_OK;
+}
+
 sgn_solve_opts default_opts() {
     sgn_solve_opts o;
     std::memset(&o, 0, sizeof(o));
@@ -907,10 +1170,18 @@ sgn_status solve_1d_block(sgn_ctx* ctx, const Dims& d, double L, const double* e
 sgn_status solve_dispatch(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* rhs,
                           double* u, const sgn_coeffs* coeffs, int flat, const sgn_solve_opts& o,
                           sgn_solve_info* info, void* ws) {
-    if (o.method != SGN_PCG) return fail(ctx, SGN_EUNSUPPORTED, "only PCG is available");
+    if (o.method != SGN_PCG && o.method != SGN_GMRES) return fail(ctx, SGN_EINVAL, "unknown method");
     if (!(o.tol > 0.0) || o.max_iter < 1) return fail(ctx, SGN_EINVAL, "tol must be > 0 and max_iter >= 1");
     if (coeffs && !(coeffs->sigma > 0.0 && coeffs->alpha > 0.0))
         return fail(ctx, SGN_EINVAL, "coefficients must be positive");
+    if (o.method == SGN_GMRES) {
+        if (ctx->stage) return fail(ctx, SGN_EUNSUPPORTED, "stepper solves use PCG");
+        if (o.precision != SGN_FP64) return fail(ctx, SGN_EUNSUPPORTED, "GMRES runs in FP64 only");
+        if (o.gmres_restart < 1 || o.gmres_restart > GMRES_MAX_RESTART)
+            return fail(ctx, SGN_EINVAL, "gmres_restart must be in [1, 256]");
+        return d.D == 1 ? solve_gmres<1>(ctx, d, eta, gh, rhs, u, coeffs, flat, o, info, ws)
+                        : solve_gmres<2>(ctx, d, eta, gh, rhs, u, coeffs, flat, o, info, ws);
+    }
     // a 1D system that fits one workgroup is solved by it in one launch
     if (d.D == 1 && d.nx <= BATCH_NMAX && (o.precision == SGN_FP64 || o.precision == SGN_MIXED))
         return solve_1d_block(ctx, d, d.Lx, eta, gh, rhs, u, coeffs, flat, o, info, ws);
@@ -1712,6 +1983,13 @@ size_t sgn_workspace_bytes(const sgn_grid* grid, int32_t precision) {
     Dims d;
     if (check_grid(nullptr, grid, &d) != SGN_OK) return 0;
     return workspace_bytes(d, precision);
+}
+
+size_t sgn_gmres_workspace_bytes(const sgn_grid* grid, int32_t restart) {
+    Dims d;
+    if (check_grid(nullptr, grid, &d) != SGN_OK) return 0;
+    if (restart < 1 || restart > GMRES_MAX_RESTART) return 0;
+    return gmres_workspace_bytes(d, restart);
 }
 
 sgn_status sgn_bathy_prepare(sgn_ctx* ctx, const sgn_grid* grid, const double* h, double* grad_h, int32_t* flat,

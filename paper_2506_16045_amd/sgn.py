@@ -105,6 +105,7 @@ _SIGS = {
     "sgn_profile_begin": (_S, [_P]),
     "sgn_profile_end": (_S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), _I]),
     "sgn_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
+    "sgn_gmres_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
     "sgn_bathy_prepare": (_S, [_P, ctypes.POINTER(Grid), _P, _P, ctypes.POINTER(_I), _P]),
     "sgn_precond_coeffs": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _I, _I, ctypes.POINTER(Coeffs), _P]),
     "sgn_apply_constraint": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P]),
@@ -156,6 +157,10 @@ def make_grid(g) -> Grid:
 
 def workspace_bytes(g, precision: int = FP64) -> int:
     return int(_lib.sgn_workspace_bytes(ctypes.byref(make_grid(g)), precision))
+
+
+def gmres_workspace_bytes(g, restart: int = 30) -> int:
+    return int(_lib.sgn_gmres_workspace_bytes(ctypes.byref(make_grid(g)), int(restart)))
 
 
 def batch_workspace_bytes(sizes, precision: int = FP64) -> int:
@@ -225,6 +230,7 @@ class Context:
             raise SgnError(st, "sgn_create failed")
         self._h = h
         self._ws = {}
+        self._gmres_ws = {}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -324,10 +330,20 @@ class Context:
         if u is None:
             u = torch.zeros(_vector_shape(g), dtype=torch.float64, device=self.device)
         info = SolveInfo()
+        if o.method == GMRES:
+            # 0 for an unsupported grid or restart: the library then rejects the call before any work
+            nb = max(gmres_workspace_bytes(g, o.gmres_restart), 256)
+            ws = self._gmres_ws.get(nb)
+            if ws is None:
+                self._gmres_ws.clear()
+                ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+                self._gmres_ws[nb] = ws
+        else:
+            ws = self.workspace(g, o.precision)
         st = _lib.sgn_krylov_solve(self._h, ctypes.byref(grid), _ptr(eta, _scalar_shape(g), "eta"),
                                    _ptr(grad_h, _vector_shape(g), "grad_h"), _ptr(rhs, _vector_shape(g), "rhs"),
                                    _ptr(u, _vector_shape(g), "u"), ctypes.byref(coeffs) if coeffs else None,
-                                   ctypes.byref(o), ctypes.byref(info), _P(self.workspace(g, o.precision).data_ptr()))
+                                   ctypes.byref(o), ctypes.byref(info), _P(ws.data_ptr()))
         res = SolveResult(info.iters, info.outer_iters, bool(info.converged), info.relres, info.coeffs.sigma,
                           info.coeffs.alpha, info.coeffs.kappa_ub, bool(info.coeffs.flat))
         if st == ENOCONV and not raise_on_noconv:
