@@ -230,17 +230,23 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// Row thread of row block `blk` (blockIdx.x, or the block within one part of a
+// launch that runs several independent row jobs side by side).
 template <typename T>
-__device__ __forceinline__ RowThread<T> row_thread(const RowGeom& g, cpx<T>* lds) {
+__device__ __forceinline__ RowThread<T> row_thread_at(const RowGeom& g, cpx<T>* lds, int blk) {
     RowThread<T> rt;
     rt.r = threadIdx.x / g.TPR;
     rt.t = threadIdx.x - rt.r * g.TPR;
-    rt.row0 = xcd_remap(blockIdx.x, g.nblocks) * g.R;
+    rt.row0 = xcd_remap(blk, g.nblocks) * g.R;
     rt.y = rt.row0 + rt.r;
     rt.valid = rt.y < g.ny;
     rt.lds = lds;
     rt.fstride = g.R * (g.M + 1);
     return rt;
+}
+template <typename T>
+__device__ __forceinline__ RowThread<T> row_thread(const RowGeom& g, cpx<T>* lds) {
+    return row_thread_at<T>(g, lds, blockIdx.x);
 }
 
 // LDS entries a row kernel with NF fields needs before its twiddle table.

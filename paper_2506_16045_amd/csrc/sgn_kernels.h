@@ -183,7 +183,9 @@ __device__ __forceinline__ double rhs_source(int i, double e, const double (&uc)
 }
 
 // Products and forward row transforms of the right-hand side's source fields
-// (rhs_source order) in groups of NFG fields; dst.p[i] receives field i.
+// (rhs_source order) in groups of NFG fields; dst.p[i] receives field i.  Each
+// block does every group in turn (running the groups side by side in separate
+// blocks was measured slower: every group then reloads eta, u and grad h).
 // MAXT bounds the workgroup size (256 lets the compiler use more registers).
 template <int D, int EPC, int NFG, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_rhs_rows_fwd(RowGeom g, const double* __restrict__ eta,
@@ -442,6 +444,102 @@ __global__ void __launch_bounds__(256) k_cols_lin(ColGeom g, PtrList<const cpx<T
     int o0 = 0;
     for (; o0 + G <= lc.no; o0 += G) cols_lin_store<T, EPC, G, NI>(g, ct, dst, lc, o0, in, kx, tpy, scale, twm);
     for (; o0 < lc.no; ++o0) cols_lin_store<T, EPC, 1, NI>(g, ct, dst, lc, o0, in, kx, tpy, scale, twm);
+}
+
+// Several independent linear column operators in one launch: job k takes
+// blocks [k nblocks, (k+1) nblocks).  Each block first issues the loads of all
+// its inputs (so their latencies overlap), then transforms them along y one by
+// one, forms each output and inverse-transforms and stores it.  The jobs of the
+// 2D right-hand side run side by side this way instead of in four launches,
+// which keeps four times as many columns in flight.
+constexpr int LINJ_MAXI = 3;
+constexpr int LINJ_MAXO = 3;
+constexpr int LINJ_MAXJ = 4;
+template <typename T>
+struct LinJob {
+    const cpx<T>* src[LINJ_MAXI];
+    cpx<T>* dst[LINJ_MAXO];
+    int ni, no;
+    int code[LINJ_MAXO][LINJ_MAXI];
+};
+template <typename T>
+struct LinJobs {
+    LinJob<T> j[LINJ_MAXJ];
+    int n;
+};
+
+template <typename T, int EPC>
+__device__ __forceinline__ void col_fft_regs(const ColGeom& g, const ColThread<T>& ct, const cpx<T>* twm,
+                                             cpx<T> (&v)[EPC], bool inverse) {
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int j = ct.t + g.TPC * e;
+        if (j < g.ny) ct.buf[j] = v[e];
+    }
+    __syncthreads();
+    lds_fft<T, EPC, 1>(ct.buf, ct.fstride, g.ny, ct.t, g.TPC, twm, inverse);
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int j = ct.t + g.TPC * e;
+        if (j < g.ny) v[e] = ct.buf[j];
+    }
+    __syncthreads();
+}
+
+template <typename T, int EPC>
+__global__ void __launch_bounds__(256) k_cols_lin_jobs(ColGeom g, LinJobs<T> jobs, const cpx<T>* __restrict__ tw,
+                                                        T tpx, T tpy, T scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int jb = blockIdx.x / g.nblocks;
+    if (jb >= jobs.n) return;
+    const LinJob<T>& J = jobs.j[jb];
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, 1));
+    ColThread<T> ct;
+    ct.c = threadIdx.x / g.TPC;
+    ct.t = threadIdx.x - ct.c * g.TPC;
+    ct.kx = (blockIdx.x - jb * g.nblocks) * g.Cb + ct.c;
+    ct.valid = ct.kx < g.nxh;
+    ct.buf = lds + ct.c * g.ny;
+    ct.fstride = g.Cb * g.ny;
+    const int ny = g.ny;
+    cpx<T> in[LINJ_MAXI][EPC];
+#pragma unroll
+    for (int i = 0; i < LINJ_MAXI; ++i) {
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+            in[i][e] = (i < J.ni && ct.valid && j < ny) ? J.src[i][(size_t)ct.kx * ny + j] : C<T>(0, 0);
+        }
+    }
+    if (ny > 1) {
+#pragma unroll
+        for (int i = 0; i < LINJ_MAXI; ++i)
+            if (i < J.ni) col_fft_regs<T, EPC>(g, ct, twm, in[i], false);
+    }
+    const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
+#pragma unroll
+    for (int o = 0; o < LINJ_MAXO; ++o) {
+        if (o >= J.no) break;
+        cpx<T> v[EPC];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+            const T ky = (ny > 1) ? wavenumber<T>(j, ny, tpy) : (T)0;
+            cpx<T> s = C<T>(0, 0);
+#pragma unroll
+            for (int i = 0; i < LINJ_MAXI; ++i) s = s + lin_coef<T>(J.code[o][i], kx, ky) * in[i][e];
+            v[e] = scale * s;
+        }
+        if (ny > 1) col_fft_regs<T, EPC>(g, ct, twm, v, true);
+        if (ct.valid) {
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int j = ct.t + g.TPC * e;
+                if (j < ny) J.dst[o][(size_t)ct.kx * ny + j] = v[e];
+            }
+        }
+    }
 }
 
 // A^{-1} on D spectral columns: y-FFT, per-mode A^{-1} (times scale), y-IFFT.
@@ -1241,6 +1339,37 @@ __global__ void k_lincomb(size_t n, const double* __restrict__ base, double dt, 
         double s = 0.0;
         for (int k = 0; k < lc.n; ++k) s += lc.c[k] * lc.f[k][i];
         out[i] = (base ? base[i] : 0.0) + dt * s;
+    }
+}
+
+// Up to three independent linear combinations in one launch, each
+// out = base + dt * sum_k c_k f_k as in k_lincomb (same order of operations);
+// with `save` set, base is also copied there (out may alias base).
+struct LcJob {
+    double* out;
+    const double* base;
+    double* save;
+    const double* f[4];
+    double c[4];
+    double dt;
+    int nf;
+    size_t n;
+};
+struct LcJobs {
+    LcJob j[3];
+    int n;
+};
+__global__ void k_lincomb_jobs(LcJobs J) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (int k = 0; k < J.n; ++k) {
+        const LcJob& a = J.j[k];
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+            double s = 0.0;
+            for (int q = 0; q < a.nf; ++q) s += a.c[q] * a.f[q][i];
+            const double b = a.base ? a.base[i] : 0.0;
+            if (a.save) a.save[i] = b;
+            a.out[i] = b + a.dt * s;
+        }
     }
 }
 

@@ -342,6 +342,42 @@ sgn_status cols_lin(sgn_ctx* ctx, const Dims& d, const std::vector<const cpx<T>*
     }
 }
 
+// Independent linear column operators side by side in one launch (k_cols_lin_jobs).
+struct LinJobSpec {
+    std::vector<const cpx<double>*> src;
+    std::vector<cpx<double>*> dst;
+    std::vector<std::vector<int>> codes;
+};
+sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSpec>& spec, double scale) {
+    ProfScope ps(ctx, SGN_KERNEL_COLS);
+    if (spec.empty() || spec.size() > (size_t)LINJ_MAXJ) return fail(ctx, SGN_EINVAL, "cols_lin_jobs: job count");
+    LinJobs<double> J{};
+    J.n = (int)spec.size();
+    for (int k = 0; k < J.n; ++k) {
+        const LinJobSpec& s = spec[k];
+        LinJob<double>& j = J.j[k];
+        if (s.src.empty() || s.src.size() > (size_t)LINJ_MAXI || s.dst.empty() || s.dst.size() > (size_t)LINJ_MAXO ||
+            s.codes.size() != s.dst.size())
+            return fail(ctx, SGN_EINVAL, "cols_lin_jobs: bad job");
+        j.ni = (int)s.src.size();
+        j.no = (int)s.dst.size();
+        for (int i = 0; i < j.ni; ++i) j.src[i] = s.src[i];
+        for (int o = 0; o < j.no; ++o) {
+            j.dst[o] = s.dst[o];
+            if (s.codes[o].size() > (size_t)j.ni) return fail(ctx, SGN_EINVAL, "cols_lin_jobs: bad codes");
+            for (size_t i = 0; i < s.codes[o].size(); ++i) j.code[o][i] = s.codes[o][i];
+        }
+    }
+    ColLaunch L = col_launch<double>(d.nx, d.ny);
+    auto k = k_cols_lin_jobs<double, 4>;
+    const size_t lds = col_lds_bytes<double>(L.g, 1);
+    HIPCHK(ctx, allow_lds(k, lds));
+    hipLaunchKernelGGL(k, dim3(L.g.nblocks * J.n), dim3(L.threads), lds, ctx->stream, L.g, J, ctx->tw64, d.tpx, d.tpy,
+                       scale);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Coefficients (device) -> SolveScal
 // ---------------------------------------------------------------------------
@@ -1450,20 +1486,17 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     for (int i = 0; i < 2 * D; ++i) oB.push_back(OB + i * NS);
     // codes: 1 id, 2 ikx, 3 iky, 4 (ikx)^2, 5 (ikx)(iky), 6 (iky)^2
     if (D == 2) {
-        // the column operators, split by shared inputs so that each column kernel
-        // holds few transformed inputs in registers:
-        // [u, v] -> [delta, dx delta, dy delta]; [eu, ev, eta] -> [m, dx eta, dy eta];
-        // [euu, euv, evv] -> [div_x, div_y]; [beta] -> [dx beta, dy beta]
-        if ((s = cols_lin<double>(ctx, d, {cA[0], cA[1]}, {oA[0], oA[1], oA[2]}, {{2, 3}, {4, 5}, {5, 6}},
-                                  d.inv_n)) != SGN_OK)
-            return s;
-        if ((s = cols_lin<double>(ctx, d, {cA[2], cA[3], cA[4]}, {oA[3], oA[4], oA[5]},
-                                  {{2, 3, 0}, {0, 0, 2}, {0, 0, 3}}, d.inv_n)) != SGN_OK)
-            return s;
-        if ((s = cols_lin<double>(ctx, d, {cB[0], cB[1], cB[2]}, {oB[0], oB[1]}, {{2, 3, 0}, {0, 2, 3}},
-                                  d.inv_n)) != SGN_OK)
-            return s;
-        if ((s = cols_lin<double>(ctx, d, {cB[3]}, {oB[2], oB[3]}, {{2}, {3}}, d.inv_n)) != SGN_OK) return s;
+        // the column operators, split by shared inputs so that each block holds
+        // at most three transformed inputs in registers, run side by side in one
+        // launch: [u, v] -> [delta, dx delta, dy delta]; [eu, ev, eta] -> [m, dx eta,
+        // dy eta]; [euu, euv, evv] -> [div_x, div_y]; [beta] -> [dx beta, dy beta]
+        std::vector<LinJobSpec> jobs = {
+            {{cA[0], cA[1]}, {oA[0], oA[1], oA[2]}, {{2, 3}, {4, 5}, {5, 6}}},
+            {{cA[2], cA[3], cA[4]}, {oA[3], oA[4], oA[5]}, {{2, 3, 0}, {0, 0, 2}, {0, 0, 3}}},
+            {{cB[0], cB[1], cB[2]}, {oB[0], oB[1]}, {{2, 3, 0}, {0, 2, 3}}},
+            {{cB[3]}, {oB[2], oB[3]}, {{2}, {3}}},
+        };
+        if ((s = cols_lin_jobs(ctx, d, jobs, d.inv_n)) != SGN_OK) return s;
     } else {
         if ((s = cols_lin<double>(ctx, d, cA, oA, {{2, 0, 0}, {4, 0, 0}, {0, 2, 0}, {0, 0, 2}}, d.inv_n)) != SGN_OK)
             return s;
@@ -1630,6 +1663,42 @@ sgn_status lincomb(sgn_ctx* ctx, size_t n, const double* base, double dt, std::v
     return SGN_OK;
 }
 
+// Independent linear combinations in one launch (k_lincomb_jobs).
+struct LcSpec {
+    double* out;
+    const double* base;
+    double dt;
+    std::vector<const double*> f;
+    std::vector<double> c;
+    size_t n;
+    double* save;
+};
+sgn_status lincomb_jobs(sgn_ctx* ctx, const std::vector<LcSpec>& spec) {
+    LcJobs J{};
+    J.n = (int)spec.size();
+    if (J.n < 1 || J.n > 3) return fail(ctx, SGN_EINVAL, "lincomb_jobs: job count");
+    size_t nmax = 0;
+    for (int k = 0; k < J.n; ++k) {
+        const LcSpec& s = spec[k];
+        LcJob& j = J.j[k];
+        if (s.f.size() > 4 || s.f.size() != s.c.size()) return fail(ctx, SGN_EINVAL, "lincomb_jobs: terms");
+        j.out = s.out;
+        j.base = s.base;
+        j.save = s.save;
+        j.dt = s.dt;
+        j.nf = (int)s.f.size();
+        j.n = s.n;
+        for (int q = 0; q < j.nf; ++q) {
+            j.f[q] = s.f[q];
+            j.c[q] = s.c[q];
+        }
+        nmax = std::max(nmax, s.n);
+    }
+    hipLaunchKernelGGL(k_lincomb_jobs, dim3(flat_blocks(nmax)), dim3(256), 0, ctx->stream, J);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
 // Start of a stepping call: the guess history holds offsets for this dt and mode.
 void guess_prepare(sgn_state* st, const sgn_solve_opts& o, double dt) {
     if (st->gx_mode != o.guess || st->gx_dt != dt) {
@@ -1660,12 +1729,15 @@ sgn_status stage_solve(sgn_state* st, int slot, const double* eta, const double*
     int& cnt = st->gx_count[slot];
     int& head = st->gx_head[slot];
     if (ex) {
-        if ((s = copy_d(ctx, b.gx_base, u, DN)) != SGN_OK) return s;
-        if (cnt == 1) {
-            if ((s = lincomb(ctx, DN, b.gx_base, 1.0, {b.gx_off[slot][head]}, {1.0}, u)) != SGN_OK) return s;
-        } else if (cnt >= 2) {
-            if ((s = lincomb(ctx, DN, b.gx_base, 1.0, {b.gx_off[slot][head], b.gx_off[slot][head ^ 1]}, {2.0, -1.0},
-                             u)) != SGN_OK)
+        // keep the base and form the guess in place, in one pass
+        if (cnt == 0) {
+            if ((s = copy_d(ctx, b.gx_base, u, DN)) != SGN_OK) return s;
+        } else if (cnt == 1) {
+            if ((s = lincomb_jobs(ctx, {{u, u, 1.0, {b.gx_off[slot][head]}, {1.0}, DN, b.gx_base}})) != SGN_OK)
+                return s;
+        } else {
+            if ((s = lincomb_jobs(ctx, {{u, u, 1.0, {b.gx_off[slot][head], b.gx_off[slot][head ^ 1]}, {2.0, -1.0},
+                                         DN, b.gx_base}})) != SGN_OK)
                 return s;
         }
     }
@@ -1705,16 +1777,16 @@ sgn_status rk4_one(sgn_state* st, double dt, const sgn_solve_opts& o, sgn_step_i
         return s;
     if ((s = copy_d(ctx, b.u_s, st->u, DN)) != SGN_OK) return s;
     for (int i = 1; i < 4; ++i) {
-        if ((s = lincomb(ctx, N, st->eta, dt, {b.rk_fe[i - 1]}, {a[i - 1]}, b.eta_s)) != SGN_OK) return s;
-        if ((s = lincomb(ctx, DN, st->U, dt, {b.rk_fU[i - 1]}, {a[i - 1]}, b.U_s)) != SGN_OK) return s;
+        if ((s = lincomb_jobs(ctx, {{b.eta_s, st->eta, dt, {b.rk_fe[i - 1]}, {a[i - 1]}, N, nullptr},
+                                    {b.U_s, st->U, dt, {b.rk_fU[i - 1]}, {a[i - 1]}, DN, nullptr}})) != SGN_OK)
+            return s;
         if ((s = stage_solve(st, GUESS_RK2 + i - 1, b.eta_s, b.U_s, b.u_s, o, acc)) != SGN_OK) return s;
         if ((s = rhs_dispatch(ctx, d, b.eta_s, st->gh, b.u_s, b.rk_fe[i], b.rk_fU[i], st->ws)) != SGN_OK) return s;
     }
-    if ((s = lincomb(ctx, N, st->eta, dt, {b.rk_fe[0], b.rk_fe[1], b.rk_fe[2], b.rk_fe[3]}, {w[0], w[1], w[2], w[3]},
-                     st->eta)) != SGN_OK)
-        return s;
-    if ((s = lincomb(ctx, DN, st->U, dt, {b.rk_fU[0], b.rk_fU[1], b.rk_fU[2], b.rk_fU[3]}, {w[0], w[1], w[2], w[3]},
-                     st->U)) != SGN_OK)
+    if ((s = lincomb_jobs(ctx, {{st->eta, st->eta, dt, {b.rk_fe[0], b.rk_fe[1], b.rk_fe[2], b.rk_fe[3]},
+                                 {w[0], w[1], w[2], w[3]}, N, nullptr},
+                                {st->U, st->U, dt, {b.rk_fU[0], b.rk_fU[1], b.rk_fU[2], b.rk_fU[3]},
+                                 {w[0], w[1], w[2], w[3]}, DN, nullptr}})) != SGN_OK)
         return s;
     if ((s = copy_d(ctx, st->u, b.u_s, DN)) != SGN_OK) return s;
     if ((s = stage_solve(st, GUESS_RK_FINAL, st->eta, st->U, st->u, o, acc)) != SGN_OK) return s;
