@@ -99,7 +99,9 @@ typedef struct sgn_solve_opts {
     int32_t max_iter;      /* Krylov iterations (inner iterations in mixed mode) */
     int32_t x0_is_guess;   /* 1: u_inout is the initial guess; 0: start from 0 */
     int32_t gmres_restart; /* GMRES restart length m, 1 <= m <= 256 */
-    double inner_tol;      /* mixed mode: relative tolerance of each FP32 inner solve */
+    double inner_tol;      /* mixed mode: tightest relative tolerance of an FP32 inner solve;
+                              each inner solve stops at max(inner_tol, tol ||b|| / (2 ||r||))
+                              relative to the current outer residual r (at most 1/2) */
     int32_t max_outer;     /* mixed mode: refinement steps */
     int32_t check_every;   /* convergence flag read back every this many iterations (>= 1) */
     int32_t coeff_kind;    /* sgn_coeff_kind, used when coefficients are computed */
@@ -227,7 +229,7 @@ size_t sgn_batch_workspace_bytes(int32_t nitems, const int32_t *h_n, int32_t pre
  * formulas iff h_x is identically zero), all in one kernel launch: each
  * workgroup takes whole systems, largest first, and iterates each to its own
  * stop test ||r||_2 <= tol ||rhs||_2.  opts->precision = SGN_MIXED runs FP32
- * inner solves to inner_tol inside an FP64 iterative refinement (residual,
+ * inner solves (tolerance as for inner_tol above) inside an FP64 iterative refinement (residual,
  * stop test and u in FP64); SGN_FP64 iterates in FP64.
  *   h_n[i]   points of system i: a power of two in [2, 8192] (host array)
  *   h_L[i]   its period (host array)

@@ -525,10 +525,13 @@ __global__ void __launch_bounds__(NT) k_batch_solve(const BatchItem* __restrict_
             const float sig32 = (float)sig, alp32 = (float)alp;
             const double itol2 = prm.inner_tol * prm.inner_tol;
             while (!(rr <= tol2 * bb) && rr == rr && out.outer < prm.max_outer && bb > 0.0) {
-                // inner FP32 solve of G d = r to inner_tol ||r||, then x += d and
-                // the FP64 residual r = b - G x
+                // inner FP32 solve of G d = r to t ||r||, then x += d and the FP64
+                // residual r = b - G x; t = max(inner_tol, tol ||b|| / (2 ||r||)),
+                // capped at 1/2: no tighter than the outer target needs
+                double t2 = 0.25 * tol2 * (bb / rr);
+                t2 = t2 < itol2 ? itol2 : (t2 > 0.25 ? 0.25 : t2);
                 double irr = 0.0;
-                out.iters += blk_pcg_reg<float, NT, true>(A32, xh, rh, sig32, alp32, itol2, rr, prm.max_iter, irr,
+                out.iters += blk_pcg_reg<float, NT, true>(A32, xh, rh, sig32, alp32, t2, rr, prm.max_iter, irr,
                                                           lds32, red);
                 blk_residual<NT>(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
                 out.outer += 1;

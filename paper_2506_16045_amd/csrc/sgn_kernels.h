@@ -1161,12 +1161,22 @@ __global__ void k_init_scal(SolveScal* __restrict__ sc, double tol, int max_iter
 }
 
 // Inner solve of the refinement: coefficients from the outer solve.
-__global__ void k_copy_coeffs(const SolveScal* __restrict__ s, SolveScal* __restrict__ d) {
+// Inner solve of a refinement step: the coefficients of the outer solve, and an
+// inner tolerance no tighter than the outer target needs.  With outer residual
+// r, target tol ||b|| and inner stop ||r_in|| <= t ||r||, the inner tolerance is
+// t = max(t_min, c tol ||b|| / ||r||) (c2 = c^2): once r is within a few orders
+// of the target, the inner solve stops as soon as the corrected outer residual
+// will meet it, instead of always reducing by t_min.
+__global__ void k_inner_setup(const SolveScal* __restrict__ s, SolveScal* __restrict__ d, double c2) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         d->sig = s->sig;
         d->alp = s->alp;
         d->kap = s->kap;
         d->flat = s->flat;
+        if (s->rr > 0.0 && s->bb > 0.0) {
+            const double t2 = c2 * s->tol2 * (s->bb / s->rr);
+            if (t2 > d->tol2) d->tol2 = t2 < 0.25 ? t2 : 0.25;
+        }
     }
 }
 

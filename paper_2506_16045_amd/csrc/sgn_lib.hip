@@ -807,6 +807,10 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     return SGN_OK;
 }
 
+// Inner tolerance of refinement steps relative to the remaining gap to the
+// target: the inner solve aims at half the outer tolerance (c = 1/2).
+constexpr double INNER_SAFETY2 = 0.25;
+
 // Mixed precision: FP64 iterative refinement around FP32 PCG inner solves.  The
 // outer state (x_hat, r_hat = b_hat - G x_hat) and every dot product stay in
 // FP64; the inner operator, FFTs and preconditioner run in FP32.
@@ -858,7 +862,8 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
         if (lo.done) break;
         // inner FP32 solve of G dx = r from dx = 0; ||b_inner|| = ||r_outer||
         if ((s = init_scal(ctx, Q.sc, inner_tol, o.max_iter, d.inv_n, nullptr, 1)) != SGN_OK) return s;
-        hipLaunchKernelGGL(k_copy_coeffs, dim3(1), dim3(64), 0, ctx->stream, P.sc, Q.sc);
+        hipLaunchKernelGGL(k_inner_setup, dim3(1), dim3(64), 0, ctx->stream, (const SolveScal*)P.sc, Q.sc,
+                           INNER_SAFETY2);
         hipLaunchKernelGGL(k_S_demote, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream, (size_t)D * d.NS,
                            (const cpx<double>*)P.b.rh, Q.b.rh);
         hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream, (size_t)D * d.NS,
