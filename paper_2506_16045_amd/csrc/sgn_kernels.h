@@ -632,14 +632,18 @@ __device__ __forceinline__ bool pcg_iterate_state(SolveScal* __restrict__ sc, co
     return done;
 }
 
-enum { C1_UPDATE = 0, C1_COPY = 1 };
+// C1_UPDATE: the PCG step (p = z + beta p); C1_COPY: p = xsrc (apply G to a
+// given field); C1_ACCUM: x += dx (FP32 correction of a refinement step,
+// x in ph) and p = x, so the pass that starts the FP64 residual also applies
+// the correction.
+enum { C1_UPDATE = 0, C1_COPY = 1, C1_ACCUM = 2 };
 
 template <typename T, int EPC, int D, int MODE>
 __global__ void __launch_bounds__(256) k_pcg_c1(ColGeom g, const cpx<T>* __restrict__ tw,
                                                  SolveScal* __restrict__ sc, const double* __restrict__ part,
                                                  int nb3, const cpx<T>* __restrict__ rh, cpx<T>* __restrict__ ph,
                                                  const cpx<T>* __restrict__ xsrc, cpx<T>* __restrict__ H,
-                                                 size_t NS, T tpx, T tpy) {
+                                                 size_t NS, T tpx, T tpy, const cpx<float>* __restrict__ dx) {
     if (sc->done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -666,6 +670,14 @@ __global__ void __launch_bounds__(256) k_pcg_c1(ColGeom g, const cpx<T>* __restr
             if (MODE == C1_COPY) {
 #pragma unroll
                 for (int c = 0; c < D; ++c) p[c] = xsrc[c * NS + idx];
+            } else if (MODE == C1_ACCUM) {
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const cpx<T> x = ph[c * NS + idx];
+                    const cpx<float> e = dx[c * NS + idx];
+                    p[c] = cpx<T>{x.re + (T)e.re, x.im + (T)e.im};
+                    ph[c * NS + idx] = p[c];
+                }
             } else {
                 cpx<T> r[D], z[D];
 #pragma unroll
@@ -793,7 +805,7 @@ enum { C2_RESID = 1, C2_STORE = 2, C2_UPDATE = 3, C2_RESID_INIT = 4 };
 
 // MODE C2_UPDATE: reduce p.Gp (row-pass partials, nb_r1 blocks) -> alpha;
 //   q = G p; x += alpha p; r -= alpha q; z = A^{-1} r; partial r.z, r.r.
-// MODE C2_RESID: r = b - G x -> rh.
+// MODE C2_RESID: r = b - G x -> rh; partial r.z, r.r.
 // MODE C2_RESID_INIT: reduce ||b||^2 (setup partials, nb_r1 blocks) -> bb;
 //   r = b - G x -> rh (x = r = 0 for a zero b); partial r.z, r.r of r_0.
 // MODE C2_STORE: q = G p -> qh.
@@ -866,7 +878,8 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
                 if (MODE == C2_STORE) {
                     qh[c * NS + idx] = q;
                 } else if (MODE == C2_RESID) {
-                    rh[c * NS + idx] = bh[c * NS + idx] - q;
+                    r[c] = bh[c * NS + idx] - q;
+                    rh[c * NS + idx] = r[c];
                 } else if (MODE == C2_RESID_INIT) {
                     r[c] = zero_x ? C<T>(0, 0) : bh[c * NS + idx] - q;
                     rh[c * NS + idx] = r[c];
@@ -877,7 +890,7 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
                     rh[c * NS + idx] = r[c];
                 }
             }
-            if (MODE == C2_UPDATE || MODE == C2_RESID_INIT) {
+            if (MODE != C2_STORE) {
                 precond_mode<T, D>(kx, ky, sig, alp, r, z);
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
@@ -887,7 +900,7 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
             }
         }
     }
-    if (MODE == C2_UPDATE || MODE == C2_RESID_INIT) {
+    if (MODE != C2_STORE) {
         block_sum<2>(acc, red);
         if (threadIdx.x == 0) {
             part[PART_C3 + 2 * blockIdx.x] = acc[0];
@@ -995,100 +1008,6 @@ __global__ void __launch_bounds__(256) k_pcg_setup(ColGeom g, const cpx<T>* __re
     }
 }
 
-// Initial residual pass over the S modes (kx = idx / ny, ky index = idx % ny):
-// partials of r.z and r.r of r_0 for the first stop test.  Unless init_bb is
-// set, a zero right-hand side (bb == 0) gives x = 0 at once.
-template <typename T, int D>
-__global__ void __launch_bounds__(256) k_pcg_init(int nx, int ny, size_t NS, SolveScal* __restrict__ sc,
-                                                  cpx<T>* __restrict__ xh, cpx<T>* __restrict__ rh,
-                                                  double* __restrict__ part, T tpx, T tpy) {
-    if (sc->done) return;
-    __shared__ double red[32];
-    const bool zero_x = !sc->init_bb && sc->bb == 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->first = 1;
-    const T sig = (T)sc->sig, alp = (T)sc->alp;
-    double acc[2] = {0.0, 0.0};
-    const int nsi = (int)NS;
-    const int lny = ilog2(ny);
-    const int stride = gridDim.x * blockDim.x;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nsi; idx += stride) {
-        const int kxi = idx >> lny;
-        const int kyi = idx & (ny - 1);
-        const T kx = wavenumber<T>(kxi, nx, tpx);
-        const T ky = (D == 2) ? wavenumber<T>(kyi, ny, tpy) : (T)0;
-        cpx<T> r[D], z[D];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            r[c] = rh[c * NS + idx];
-            if (zero_x) {
-                xh[c * NS + idx] = C<T>(0, 0);
-                r[c] = C<T>(0, 0);
-            }
-        }
-        precond_mode<T, D>(kx, ky, sig, alp, r, z);
-        const double w = half_weight(kxi, nx);
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            acc[0] += w * ((double)r[c].re * (double)z[c].re + (double)r[c].im * (double)z[c].im);
-            acc[1] += w * ((double)r[c].re * (double)r[c].re + (double)r[c].im * (double)r[c].im);
-        }
-    }
-    block_sum<2>(acc, red);
-    if (threadIdx.x == 0) {
-        part[PART_C3 + 2 * blockIdx.x] = acc[0];
-        part[PART_C3 + 2 * blockIdx.x + 1] = acc[1];
-    }
-}
-
-// b_hat from the H layout: y-FFT, store to bh and/or rh, partial ||b||^2.
-template <typename T, int EPC, int D>
-__global__ void __launch_bounds__(256) k_setup_b(ColGeom g, const cpx<T>* __restrict__ tw,
-                                                  const cpx<T>* __restrict__ H, size_t NS,
-                                                  cpx<T>* __restrict__ bh, cpx<T>* __restrict__ rh,
-                                                  double* __restrict__ part) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[16];
-    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D));
-    const ColThread<T> ct = col_thread<T>(g, lds);
-    const double w = ct.valid ? half_weight(ct.kx, g.nx) : 0.0;
-    double acc[1] = {0.0};
-    cpx<T> v[D][EPC];
-    const cpx<T>* srcs[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) srcs[c] = H + c * NS;
-    col_load<T, EPC, D>(g, ct, srcs, true, twm, v);
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-#pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            const int j = ct.t + g.TPC * e;
-            if (ct.valid && j < g.ny) {
-                const size_t idx = (size_t)ct.kx * g.ny + j;
-                if (bh) bh[c * NS + idx] = v[c][e];
-                if (rh) rh[c * NS + idx] = v[c][e];
-                acc[0] += w * ((double)v[c][e].re * (double)v[c][e].re + (double)v[c][e].im * (double)v[c][e].im);
-            }
-        }
-    }
-    block_sum<1>(acc, red);
-    if (threadIdx.x == 0) part[PART_GEN + blockIdx.x] = acc[0];
-}
-
-// One block: ||b||^2 from the k_setup_b partials.
-__global__ void __launch_bounds__(256) k_finish_bb(SolveScal* __restrict__ sc, const double* __restrict__ part,
-                                                   int nb) {
-    __shared__ double red[16];
-    double tot[1];
-    final_sum<1>(part + PART_GEN, nb, tot, red);
-    if (threadIdx.x == 0) {
-        sc->bb = tot[0] * sc->inv_n;
-        if (!(sc->bb == sc->bb) || sc->bb > 1.0e300) {
-            sc->status = -2;
-            sc->done = 1;
-        }
-    }
-}
 
 // Forward y-FFT of D H fields into S fields (no reduction).
 template <typename T, int EPC, int D>
@@ -1188,7 +1107,8 @@ __global__ void k_inner_setup(const SolveScal* __restrict__ s, SolveScal* __rest
 // max(eta + lambda_+ eta |grad h|^2), max |grad h|^2 and a non-finite flag.
 template <int D>
 __global__ void __launch_bounds__(256) k_coeffs(size_t npts, const double* __restrict__ eta,
-                                                const double* __restrict__ gh, double* __restrict__ part) {
+                                                const double* __restrict__ gh, double* __restrict__ part,
+                                                float* __restrict__ eta32, float* __restrict__ gh32) {
     __shared__ double red[5 * 16];
     const double lp = (4.0 + sqrt(13.0)) / 6.0;
     double mn = 1.0e308, mx = -1.0e308, smax = -1.0e308, g2max = 0.0, bad = 0.0;
@@ -1200,7 +1120,9 @@ __global__ void __launch_bounds__(256) k_coeffs(size_t npts, const double* __res
         for (int c = 0; c < D; ++c) {
             const double h = gh[c * npts + i];
             g2 += h * h;
+            if (gh32) gh32[c * npts + i] = (float)h;
         }
+        if (eta32) eta32[i] = (float)e;
         if (!isfinite(e) || !isfinite(g2)) bad = 1.0;
         mn = fmin(mn, e);
         mx = fmax(mx, e);
@@ -1389,17 +1311,48 @@ __global__ void k_zero_c(size_t n, void* __restrict__ p) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = 0.0;
 }
 
-// Mixed precision glue in S: d32 = (float) s64 ; x64 += (double) x32
-__global__ void k_S_demote(size_t n, const cpx<double>* __restrict__ s, cpx<float>* __restrict__ d) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        d[i] = cpx<float>{(float)s[i].re, (float)s[i].im};
+// Start of an FP32 inner solve from the FP64 outer residual: r32 = (float) r,
+// x32 = 0, and the partials of r32.z, r32.r32, in one pass.
+template <int D>
+__global__ void __launch_bounds__(256) k_inner_start(int nx, int ny, size_t NS, SolveScal* __restrict__ sc,
+                                                     const cpx<double>* __restrict__ r64,
+                                                     cpx<float>* __restrict__ r32, cpx<float>* __restrict__ x32,
+                                                     double* __restrict__ part, float tpx, float tpy) {
+    __shared__ double red[32];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->first = 1;
+    const float sig = (float)sc->sig, alp = (float)sc->alp;
+    double acc[2] = {0.0, 0.0};
+    const int nsi = (int)NS;
+    const int lny = ilog2(ny);
+    const int stride = gridDim.x * blockDim.x;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nsi; idx += stride) {
+        const int kxi = idx >> lny;
+        const int kyi = idx & (ny - 1);
+        const float kx = wavenumber<float>(kxi, nx, tpx);
+        const float ky = (D == 2) ? wavenumber<float>(kyi, ny, tpy) : 0.0f;
+        cpx<float> r[D], z[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const cpx<double> v = r64[c * NS + idx];
+            r[c] = cpx<float>{(float)v.re, (float)v.im};
+            r32[c * NS + idx] = r[c];
+            x32[c * NS + idx] = C<float>(0, 0);
+        }
+        precond_mode<float, D>(kx, ky, sig, alp, r, z);
+        const double w = half_weight(kxi, nx);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            acc[0] += w * ((double)r[c].re * (double)z[c].re + (double)r[c].im * (double)z[c].im);
+            acc[1] += w * ((double)r[c].re * (double)r[c].re + (double)r[c].im * (double)r[c].im);
+        }
+    }
+    block_sum<2>(acc, red);
+    if (threadIdx.x == 0) {
+        part[PART_C3 + 2 * blockIdx.x] = acc[0];
+        part[PART_C3 + 2 * blockIdx.x + 1] = acc[1];
+    }
 }
-__global__ void k_S_accumulate(size_t n, const cpx<float>* __restrict__ s, cpx<double>* __restrict__ d) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        d[i] = cpx<double>{d[i].re + (double)s[i].re, d[i].im + (double)s[i].im};
-}
+
 
 }  // namespace sgn
 

@@ -381,13 +381,15 @@ sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSp
 // ---------------------------------------------------------------------------
 // Coefficients (device) -> SolveScal
 // ---------------------------------------------------------------------------
+// With eta32 / gh32 set, the same pass also writes FP32 copies of eta and grad h.
 sgn_status launch_coeffs(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, int flat,
-                         int kind, SolveScal* sc, double* partials) {
+                         int kind, SolveScal* sc, double* partials, float* eta32 = nullptr,
+                         float* gh32 = nullptr) {
     const int nb = flat_blocks(d.N, 256, 1024);
     if (d.D == 1)
-        hipLaunchKernelGGL(k_coeffs<1>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, partials);
+        hipLaunchKernelGGL(k_coeffs<1>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, partials, eta32, gh32);
     else
-        hipLaunchKernelGGL(k_coeffs<2>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, partials);
+        hipLaunchKernelGGL(k_coeffs<2>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, partials, eta32, gh32);
     hipLaunchKernelGGL(k_coeffs_finish, dim3(1), dim3(256), 0, ctx->stream, sc, (const double*)partials, nb, flat,
                        kind);
     CHECK_LAUNCH(ctx);
@@ -487,25 +489,29 @@ struct PcgLaunch {
     const T* gh;
 };
 
+// mode C1_ACCUM (T = double only): x_hat += dx (FP32) and G is applied to the
+// corrected x_hat.
 template <typename T, int D>
-sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc) {
+sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc, const cpx<float>* dx = nullptr) {
     ProfScope ps(P.ctx, SGN_KERNEL_PCG_C1 + (sizeof(T) == 4 ? 6 : 0));
     auto& L = P.cl;
-    if (mode == C1_COPY) {
-        auto k = k_pcg_c1<T, 4, D, C1_COPY>;
-        const size_t lds = col_lds_bytes<T>(L.g, D + 1);
+    const size_t lds = col_lds_bytes<T>(L.g, D + 1);
+    auto launch = [&](auto k, cpx<T>* ph) -> sgn_status {
         HIPCHK(P.ctx, allow_lds(k, lds));
         hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, (const double*)P.partials, P.cl.g.nblocks, P.b.rh, P.b.ph, xsrc, P.b.H, P.d.NS,
-                           (T)P.d.tpx, (T)P.d.tpy);
-    } else {
-        auto k = k_pcg_c1<T, 4, D, C1_UPDATE>;
-        const size_t lds = col_lds_bytes<T>(L.g, D + 1);
-        HIPCHK(P.ctx, allow_lds(k, lds));
-        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, (const double*)P.partials, P.cl.g.nblocks, P.b.rh, P.b.ph, xsrc, P.b.H, P.d.NS,
-                           (T)P.d.tpx, (T)P.d.tpy);
-    }
+                           P.sc, (const double*)P.partials, P.cl.g.nblocks, P.b.rh, ph, xsrc, P.b.H, P.d.NS,
+                           (T)P.d.tpx, (T)P.d.tpy, dx);
+        return SGN_OK;
+    };
+    sgn_status s;
+    if (mode == C1_COPY)
+        s = launch(k_pcg_c1<T, 4, D, C1_COPY>, P.b.ph);
+    else if (mode == C1_ACCUM) {
+        if (sizeof(T) != 8 || !dx) return fail(P.ctx, SGN_EINVAL, "pcg_c1: accumulate needs an FP64 solve");
+        s = launch(k_pcg_c1<T, 4, D, C1_ACCUM>, P.b.xh);
+    } else
+        s = launch(k_pcg_c1<T, 4, D, C1_UPDATE>, P.b.ph);
+    if (s != SGN_OK) return s;
     CHECK_LAUNCH(P.ctx);
     return SGN_OK;
 }
@@ -557,16 +563,6 @@ sgn_status pcg_c2(PcgLaunch<T, D>& P, int mode, const cpx<T>* bh, cpx<T>* rh_out
     if (mode == C2_RESID) return pcg_c2_mode<T, D, C2_RESID>(P, bh, rh_out);
     if (mode == C2_RESID_INIT) return pcg_c2_mode<T, D, C2_RESID_INIT>(P, bh, rh_out);
     return pcg_c2_mode<T, D, C2_UPDATE>(P, nullptr, P.b.rh);
-}
-
-// Initial residual pass: partials of r.z, r.r on the column grid.
-template <typename T, int D>
-sgn_status pcg_init(PcgLaunch<T, D>& P) {
-    ProfScope ps(P.ctx, SGN_KERNEL_PCG_INIT + (sizeof(T) == 4 ? 6 : 0));
-    hipLaunchKernelGGL((k_pcg_init<T, D>), dim3(P.cl.g.nblocks), dim3(256), 0, P.ctx->stream, P.d.nx, P.d.ny,
-                       P.d.NS, P.sc, P.b.xh, P.b.rh, P.partials, (T)P.d.tpx, (T)P.d.tpy);
-    CHECK_LAUNCH(P.ctx);
-    return SGN_OK;
 }
 
 // First pass of a solve in FP64: b (and the guess u0) to the half spectrum in one
@@ -844,12 +840,17 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     sgn_status s;
     if ((s = init_scal(ctx, P.sc, o.tol, 1 << 30, d.inv_n, coeffs, o.x0_is_guess ? 0 : 1)) != SGN_OK) return s;
     if (!coeffs) {
-        if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials)) != SGN_OK) return s;
+        // the coefficient pass also writes the FP32 copies of eta and grad h
+        if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials, eta32, eta32 + d.N)) !=
+            SGN_OK)
+            return s;
+    } else {
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(flat_blocks(d.N)), dim3(256), 0, ctx->stream, d.N, eta,
+                           eta32);
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(flat_blocks(d.D * d.N)), dim3(256), 0, ctx->stream,
+                           (size_t)D * d.N, gh, eta32 + d.N);
+        CHECK_LAUNCH(ctx);
     }
-    hipLaunchKernelGGL((k_convert<float, double>), dim3(flat_blocks(d.N)), dim3(256), 0, ctx->stream, d.N, eta, eta32);
-    hipLaunchKernelGGL((k_convert<float, double>), dim3(flat_blocks(d.D * d.N)), dim3(256), 0, ctx->stream,
-                       (size_t)D * d.N, gh, eta32 + d.N);
-    CHECK_LAUNCH(ctx);
     // b_hat (kept) and r_hat = b_hat - G x_hat in FP64, with the partials of r_0
     if ((s = pcg_start<D>(P, rhs, u, o.x0_is_guess != 0, P.b.bh)) != SGN_OK) return s;
     int total_inner = 0, outer = 0;
@@ -864,23 +865,22 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
         if ((s = init_scal(ctx, Q.sc, inner_tol, o.max_iter, d.inv_n, nullptr, 1)) != SGN_OK) return s;
         hipLaunchKernelGGL(k_inner_setup, dim3(1), dim3(64), 0, ctx->stream, (const SolveScal*)P.sc, Q.sc,
                            INNER_SAFETY2);
-        hipLaunchKernelGGL(k_S_demote, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream, (size_t)D * d.NS,
-                           (const cpx<double>*)P.b.rh, Q.b.rh);
-        hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream, (size_t)D * d.NS,
-                           (void*)Q.b.xh);
-        CHECK_LAUNCH(ctx);
-        if ((s = pcg_init<float, D>(Q)) != SGN_OK) return s;
+        {
+            ProfScope ps(ctx, SGN_KERNEL_PCG_INIT + 6);
+            // r32 = r, x32 = 0 and the inner solve's first partials, in one pass
+            hipLaunchKernelGGL((k_inner_start<D>), dim3(Q.cl.g.nblocks), dim3(256), 0, ctx->stream, d.nx, d.ny, d.NS,
+                               Q.sc, (const cpx<double>*)P.b.rh, Q.b.rh, Q.b.xh, Q.partials, (float)d.tpx,
+                               (float)d.tpy);
+            CHECK_LAUNCH(ctx);
+        }
         LoopOut li;
         if ((s = pcg_loop<float, D>(Q, o.max_iter, o.check_every, &li)) != SGN_OK) return s;
         total_inner += li.iter;
-        // x_hat += dx_hat; r_hat = b_hat - G x_hat (FP64); stop test
-        hipLaunchKernelGGL(k_S_accumulate, dim3(flat_blocks(D * d.NS)), dim3(256), 0, ctx->stream,
-                           (size_t)D * d.NS, (const cpx<float>*)Q.b.xh, P.b.xh);
-        CHECK_LAUNCH(ctx);
-        if ((s = pcg_c1<double, D>(P, C1_COPY, P.b.xh)) != SGN_OK) return s;
+        // x_hat += dx_hat inside the pass that starts G x_hat; r_hat = b_hat - G x_hat
+        // (FP64) with its dot products; stop test
+        if ((s = pcg_c1<double, D>(P, C1_ACCUM, nullptr, Q.b.xh)) != SGN_OK) return s;
         if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
         if ((s = pcg_c2<double, D>(P, C2_RESID, P.b.bh, P.b.rh)) != SGN_OK) return s;
-        if ((s = pcg_init<double, D>(P)) != SGN_OK) return s;
     }
     if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
     {
