@@ -164,19 +164,21 @@ __global__ void __launch_bounds__(MAXT) k_rows_inv(RowGeom g, PtrList<const cpx<
 // ---------------------------------------------------------------------------
 
 // Source field i of the right-hand side's forward transforms at one point:
-// [u_c (D), eta u_c (D), eta, eta u_a u_b (a <= b), beta = grad h . u].
+// [u_c (D), eta u_c (D), eta, -eta u_a u_b (a <= b), beta = grad h . u].  The
+// momentum flux enters negated: its divergence is later summed with grad S in
+// the spectral domain, so both reach U_t through one pair of inverse transforms.
 template <int D>
 __device__ __forceinline__ double rhs_source(int i, double e, const double (&uc)[D], const double (&hc)[D]) {
     if (i < D) return uc[i];
     if (i < 2 * D) return e * uc[i - D];
     if (i == 2 * D) return e;
     if (D == 1) {
-        if (i == 3) return e * uc[0] * uc[0];
+        if (i == 3) return -(e * uc[0] * uc[0]);
         return hc[0] * uc[0];
     }
-    if (i == 5) return e * uc[0] * uc[0];
-    if (i == 6) return e * uc[0] * uc[1 % D];
-    if (i == 7) return e * uc[1 % D] * uc[1 % D];
+    if (i == 5) return -(e * uc[0] * uc[0]);
+    if (i == 6) return -(e * uc[0] * uc[1 % D]);
+    if (i == 7) return -(e * uc[1 % D] * uc[1 % D]);
     double b = hc[0] * uc[0];
     b += hc[1 % D] * uc[1 % D];
     return b;
@@ -243,9 +245,9 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_fwd(RowGeom g, const double* 
 }
 
 // Inverse row transforms of the derivative fields Q, in the order m =
-// div(eta u), delta = div u, d_c delta, d_c eta, div_c(eta u (x) u), d_c beta,
-// in groups of NFG, consumed into the pointwise right-hand side as they
-// arrive: eta_t = -m, U_t = -eta grad(eta - h) - div(eta u (x) u) - T grad h,
+// div(eta u), delta = div u, d_c delta, d_c eta, d_c beta, in groups of NFG,
+// consumed into the pointwise right-hand side as they arrive: eta_t = -m,
+// U_t = -eta grad(eta - h) - T grad h (grad S - div(eta u (x) u) is added later),
 // and S, T of Def:bigF accumulated as S = e^3/3 P + e^2 m delta + e m beta +
 // e^2/2 Q, T = e^2/2 P + e m delta + m beta + e Q with P = u.grad(delta) -
 // delta^2 and Q = u.grad(beta) (the reading u.grad(u.grad h)), so that at most
@@ -262,7 +264,7 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_inv(RowGeom g, PtrList<const 
     const cpx<double>* twm = twl_setup<double>(tw, g.M, lds + row_lds_data(g, NFG));
     const RowThread<double> rt = row_thread<double>(g, lds);
     const size_t npts = (size_t)g.nx * g.ny;
-    constexpr int NQ = 4 * D + 2;
+    constexpr int NQ = 3 * D + 2;
     // live state per point: (m, delta, P) while the first 2 + D fields arrive,
     // then (S, T) and U_t (D)
     double A0[EPC][2], A1[EPC][2], A2[EPC][2], Ut[D][EPC][2];
@@ -316,11 +318,8 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_inv(RowGeom g, PtrList<const 
                         } else if (i <= 1 + 2 * D) {        // d_c eta
                             const int c = i - 2 - D;
                             Ut[c][e][s] = -eta[o + s] * (q - gh[c * npts + o + s]);
-                        } else if (i <= 1 + 3 * D) {        // div_c(eta u (x) u)
-                            const int c = i - 2 - 2 * D;
-                            Ut[c][e][s] = Ut[c][e][s] - q;
                         } else {                            // d_c beta: Q += u_c d_c beta
-                            const int c = i - 2 - 3 * D;
+                            const int c = i - 2 - 2 * D;
                             const double e0 = eta[o + s];
                             const double t = u[c * npts + o + s] * q;
                             A0[e][s] += e0 * e0 / 2.0 * t;
@@ -452,7 +451,7 @@ __global__ void __launch_bounds__(256) k_cols_lin(ColGeom g, PtrList<const cpx<T
 // one, forms each output and inverse-transforms and stores it.  The jobs of the
 // 2D right-hand side run side by side this way instead of in four launches,
 // which keeps four times as many columns in flight.
-constexpr int LINJ_MAXI = 3;
+constexpr int LINJ_MAXI = 4;
 constexpr int LINJ_MAXO = 3;
 constexpr int LINJ_MAXJ = 4;
 template <typename T>
@@ -486,7 +485,7 @@ __device__ __forceinline__ void col_fft_regs(const ColGeom& g, const ColThread<T
     __syncthreads();
 }
 
-template <typename T, int EPC>
+template <typename T, int EPC, int NI>
 __global__ void __launch_bounds__(256) k_cols_lin_jobs(ColGeom g, LinJobs<T> jobs, const cpx<T>* __restrict__ tw,
                                                         T tpx, T tpy, T scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -503,9 +502,9 @@ __global__ void __launch_bounds__(256) k_cols_lin_jobs(ColGeom g, LinJobs<T> job
     ct.buf = lds + ct.c * g.ny;
     ct.fstride = g.Cb * g.ny;
     const int ny = g.ny;
-    cpx<T> in[LINJ_MAXI][EPC];
+    cpx<T> in[NI][EPC];
 #pragma unroll
-    for (int i = 0; i < LINJ_MAXI; ++i) {
+    for (int i = 0; i < NI; ++i) {
 #pragma unroll
         for (int e = 0; e < EPC; ++e) {
             const int j = ct.t + g.TPC * e;
@@ -514,7 +513,7 @@ __global__ void __launch_bounds__(256) k_cols_lin_jobs(ColGeom g, LinJobs<T> job
     }
     if (ny > 1) {
 #pragma unroll
-        for (int i = 0; i < LINJ_MAXI; ++i)
+        for (int i = 0; i < NI; ++i)
             if (i < J.ni) col_fft_regs<T, EPC>(g, ct, twm, in[i], false);
     }
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
@@ -528,7 +527,7 @@ __global__ void __launch_bounds__(256) k_cols_lin_jobs(ColGeom g, LinJobs<T> job
             const T ky = (ny > 1) ? wavenumber<T>(j, ny, tpy) : (T)0;
             cpx<T> s = C<T>(0, 0);
 #pragma unroll
-            for (int i = 0; i < LINJ_MAXI; ++i) s = s + lin_coef<T>(J.code[o][i], kx, ky) * in[i][e];
+            for (int i = 0; i < NI; ++i) s = s + lin_coef<T>(J.code[o][i], kx, ky) * in[i][e];
             v[e] = scale * s;
         }
         if (ny > 1) col_fft_regs<T, EPC>(g, ct, twm, v, true);

@@ -2,6 +2,7 @@
 #include "sgn.h"
 #include "sgn_kernels.h"
 #include "sgn_batch.h"
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -216,19 +217,35 @@ hipEvent_t prof_event(sgn_ctx* ctx) {
     }
     return ctx->ev_pool[ctx->ev_next++];
 }
-// Scoped marker: records an event pair around the launches in its scope.
+// Scoped marker: records an event pair around the launches in its scope.  With
+// in_launch, the pair (a, b) is instead handed to the scope's single kernel
+// launch (hipExtLaunchKernelGGL records it at the kernel's own start and end, so
+// the time excludes the marker packets).
 struct ProfScope {
     sgn_ctx* ctx;
     int id;
-    hipEvent_t a = nullptr;
-    ProfScope(sgn_ctx* c, int kid) : ctx(c), id(kid) {
-        if (ctx->prof_on && (a = prof_event(ctx)) != nullptr) (void)hipEventRecord(a, ctx->stream);
+    hipEvent_t a = nullptr, b = nullptr;
+    bool in_launch = false;
+    ProfScope(sgn_ctx* c, int kid, bool in_launch_ = false) : ctx(c), id(kid) {
+        if (!ctx->prof_on || (a = prof_event(ctx)) == nullptr) return;
+        if (in_launch_) {
+            b = prof_event(ctx);
+            if (!b) {
+                a = nullptr;
+                return;
+            }
+            in_launch = true;
+        } else {
+            (void)hipEventRecord(a, ctx->stream);
+        }
     }
     ~ProfScope() {
         if (!a) return;
-        hipEvent_t b = prof_event(ctx);
-        if (!b) return;
-        (void)hipEventRecord(b, ctx->stream);
+        if (!in_launch) {
+            b = prof_event(ctx);
+            if (!b) return;
+            (void)hipEventRecord(b, ctx->stream);
+        }
         ctx->prof_marks.push_back({id, {a, b}});
     }
 };
@@ -368,14 +385,19 @@ sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSp
             for (size_t i = 0; i < s.codes[o].size(); ++i) j.code[o][i] = s.codes[o][i];
         }
     }
+    int maxi = 0;
+    for (int k = 0; k < J.n; ++k) maxi = std::max(maxi, J.j[k].ni);
     ColLaunch L = col_launch<double>(d.nx, d.ny);
-    auto k = k_cols_lin_jobs<double, 4>;
     const size_t lds = col_lds_bytes<double>(L.g, 1);
-    HIPCHK(ctx, allow_lds(k, lds));
-    hipLaunchKernelGGL(k, dim3(L.g.nblocks * J.n), dim3(L.threads), lds, ctx->stream, L.g, J, ctx->tw64, d.tpx, d.tpy,
-                       scale);
-    CHECK_LAUNCH(ctx);
-    return SGN_OK;
+    auto launch = [&](auto k) -> sgn_status {
+        HIPCHK(ctx, allow_lds(k, lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks * J.n), dim3(L.threads), lds, ctx->stream, L.g, J, ctx->tw64, d.tpx,
+                           d.tpy, scale);
+        CHECK_LAUNCH(ctx);
+        return SGN_OK;
+    };
+    // registers for the inputs are sized by the widest job
+    return maxi <= 3 ? launch(k_cols_lin_jobs<double, 4, 3>) : launch(k_cols_lin_jobs<double, 4, 4>);
 }
 
 // ---------------------------------------------------------------------------
@@ -493,14 +515,14 @@ struct PcgLaunch {
 // corrected x_hat.
 template <typename T, int D>
 sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc, const cpx<float>* dx = nullptr) {
-    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C1 + (sizeof(T) == 4 ? 6 : 0));
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C1 + (sizeof(T) == 4 ? 6 : 0), true);
     auto& L = P.cl;
     const size_t lds = col_lds_bytes<T>(L.g, D + 1);
     auto launch = [&](auto k, cpx<T>* ph) -> sgn_status {
         HIPCHK(P.ctx, allow_lds(k, lds));
-        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, L.g, twiddles<T>(P.ctx),
-                           P.sc, (const double*)P.partials, P.cl.g.nblocks, P.b.rh, ph, xsrc, P.b.H, P.d.NS,
-                           (T)P.d.tpx, (T)P.d.tpy, dx);
+        hipExtLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, ps.a, ps.b, 0, L.g,
+                              twiddles<T>(P.ctx), P.sc, (const double*)P.partials, P.cl.g.nblocks, P.b.rh, ph, xsrc,
+                              P.b.H, P.d.NS, (T)P.d.tpx, (T)P.d.tpy, dx);
         return SGN_OK;
     };
     sgn_status s;
@@ -518,15 +540,15 @@ sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc, const cpx<fl
 
 template <typename T, int D>
 sgn_status pcg_r1(PcgLaunch<T, D>& P, bool curvature = false) {
-    ProfScope ps(P.ctx, SGN_KERNEL_PCG_R1 + (sizeof(T) == 4 ? 6 : 0));
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_R1 + (sizeof(T) == 4 ? 6 : 0), true);
     double* part = curvature ? P.partials : nullptr;
     auto& L = P.rl;
     const bool seq = row_lds_bytes<T>(L.g, D + 1) > LDS_MULTI_MAX;
     const size_t lds = row_lds_bytes<T>(L.g, seq ? 1 : D + 1);
     auto launch = [&](auto k) -> sgn_status {
         HIPCHK(P.ctx, allow_lds(k, lds));
-        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, L.g, twiddles<T>(P.ctx), P.sc,
-                           P.b.H, P.d.NS, P.eta, P.gh, part);
+        hipExtLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, ps.a, ps.b, 0, L.g,
+                              twiddles<T>(P.ctx), P.sc, P.b.H, P.d.NS, P.eta, P.gh, part);
         return SGN_OK;
     };
     sgn_status st;
@@ -542,27 +564,27 @@ sgn_status pcg_r1(PcgLaunch<T, D>& P, bool curvature = false) {
 }
 
 template <typename T, int D, int MODE>
-sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out) {
+sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out, const ProfScope& ps) {
     auto& L = P.cl;
     auto k = k_pcg_c2<T, 4, D, MODE>;
     const size_t lds = col_lds_bytes<T>(L.g, D + 1);
     HIPCHK(P.ctx, allow_lds(k, lds));
     // partials reduced at the start: p.Gp of the row pass, or ||b||^2 of the setup pass
     const int nb_red = MODE == C2_RESID_INIT ? L.g.nblocks : P.rl.g.nblocks;
-    hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, L.g, twiddles<T>(P.ctx), P.sc,
-                       (const cpx<T>*)P.b.H, P.d.NS, P.b.qh, (const cpx<T>*)P.b.ph, P.b.xh, bh, rh_out, P.partials,
-                       nb_red, (T)P.d.tpx, (T)P.d.tpy);
+    hipExtLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, ps.a, ps.b, 0, L.g,
+                          twiddles<T>(P.ctx), P.sc, (const cpx<T>*)P.b.H, P.d.NS, P.b.qh, (const cpx<T>*)P.b.ph,
+                          P.b.xh, bh, rh_out, P.partials, nb_red, (T)P.d.tpx, (T)P.d.tpy);
     CHECK_LAUNCH(P.ctx);
     return SGN_OK;
 }
 
 template <typename T, int D>
 sgn_status pcg_c2(PcgLaunch<T, D>& P, int mode, const cpx<T>* bh, cpx<T>* rh_out) {
-    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C2 + (sizeof(T) == 4 ? 6 : 0));
-    if (mode == C2_STORE) return pcg_c2_mode<T, D, C2_STORE>(P, bh, rh_out);
-    if (mode == C2_RESID) return pcg_c2_mode<T, D, C2_RESID>(P, bh, rh_out);
-    if (mode == C2_RESID_INIT) return pcg_c2_mode<T, D, C2_RESID_INIT>(P, bh, rh_out);
-    return pcg_c2_mode<T, D, C2_UPDATE>(P, nullptr, P.b.rh);
+    ProfScope ps(P.ctx, SGN_KERNEL_PCG_C2 + (sizeof(T) == 4 ? 6 : 0), true);
+    if (mode == C2_STORE) return pcg_c2_mode<T, D, C2_STORE>(P, bh, rh_out, ps);
+    if (mode == C2_RESID) return pcg_c2_mode<T, D, C2_RESID>(P, bh, rh_out, ps);
+    if (mode == C2_RESID_INIT) return pcg_c2_mode<T, D, C2_RESID_INIT>(P, bh, rh_out, ps);
+    return pcg_c2_mode<T, D, C2_UPDATE>(P, nullptr, P.b.rh, ps);
 }
 
 // First pass of a solve in FP64: b (and the guess u0) to the half spectrum in one
@@ -1494,31 +1516,30 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
         // the column operators, split by shared inputs so that each block holds
         // at most three transformed inputs in registers, run side by side in one
         // launch: [u, v] -> [delta, dx delta, dy delta]; [eu, ev, eta] -> [m, dx eta,
-        // dy eta]; [euu, euv, evv] -> [div_x, div_y]; [beta] -> [dx beta, dy beta]
+        // dy eta]; [beta] -> [dx beta, dy beta]
         std::vector<LinJobSpec> jobs = {
             {{cA[0], cA[1]}, {oA[0], oA[1], oA[2]}, {{2, 3}, {4, 5}, {5, 6}}},
             {{cA[2], cA[3], cA[4]}, {oA[3], oA[4], oA[5]}, {{2, 3, 0}, {0, 0, 2}, {0, 0, 3}}},
-            {{cB[0], cB[1], cB[2]}, {oB[0], oB[1]}, {{2, 3, 0}, {0, 2, 3}}},
-            {{cB[3]}, {oB[2], oB[3]}, {{2}, {3}}},
+            {{cB[3]}, {oB[0], oB[1]}, {{2}, {3}}},
         };
         if ((s = cols_lin_jobs(ctx, d, jobs, d.inv_n)) != SGN_OK) return s;
     } else {
         if ((s = cols_lin<double>(ctx, d, cA, oA, {{2, 0, 0}, {4, 0, 0}, {0, 2, 0}, {0, 0, 2}}, d.inv_n)) != SGN_OK)
             return s;
-        if ((s = cols_lin<double>(ctx, d, cB, oB, {{2, 0}, {0, 2}}, d.inv_n)) != SGN_OK) return s;
+        if ((s = cols_lin<double>(ctx, d, {cB[1]}, {oB[0]}, {{2}}, d.inv_n)) != SGN_OK) return s;
     }
-    // back to physical: Q = [delta, d delta (D), m, d eta (D), div (D), d beta (D)], consumed
-    // pointwise into eta_t, U_t (without grad S) and S, whose row transform goes to HA
+    // back to physical: Q = [m, delta, d delta (D), d eta (D), d beta (D)], consumed
+    // pointwise into eta_t, U_t (without grad S - div(eta u (x) u)) and S, whose row
+    // transform goes to HA (slot 0)
     {
         ProfScope ps(ctx, SGN_KERNEL_ROWS);
         PtrList<const cpx<double>, MAXF> q{};
         q.n = 0;
-        // OA = [delta, d delta (D), m, d eta (D)], OB = [div (D), d beta (D)]; consumed as
-        // m, delta, d delta, d eta, div, d beta
+        // OA = [delta, d delta (D), m, d eta (D)], OB = [d beta (D)]
         q.p[q.n++] = OA + (1 + D) * NS;
         for (int i = 0; i <= D; ++i) q.p[q.n++] = OA + i * NS;
         for (int i = 0; i < D; ++i) q.p[q.n++] = OA + (2 + D + i) * NS;
-        for (int i = 0; i < 2 * D; ++i) q.p[q.n++] = OB + i * NS;
+        for (int i = 0; i < D; ++i) q.p[q.n++] = OB + i * NS;
         auto launch = [&](auto k) -> sgn_status {
             HIPCHK(ctx, allow_lds(k, rlds));
             hipLaunchKernelGGL(k, dim3(RL.g.nblocks), dim3(RL.threads), rlds, ctx->stream, RL.g, q, eta, u, gh, eta_t,
@@ -1534,19 +1555,25 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
             s = launch(k_rhs_rows_inv<D, 8, 1, 1024>);
         if (s != SGN_OK) return s;
     }
-    // U_t += grad S
+    // U_t += grad S - div(eta u (x) u), formed in the spectral domain from S and the
+    // (negated) row-transformed flux fields in HB, into OA (free again)
     std::vector<cpx<double>*> gS;
-    for (int c = 0; c < D; ++c) gS.push_back(HB + c * NS);
+    for (int c = 0; c < D; ++c) gS.push_back(OA + c * NS);
     if (D == 2) {
-        if ((s = cols_lin<double>(ctx, d, {HA}, gS, {{2}, {3}}, d.inv_n)) != SGN_OK) return s;
+        // one job per component, side by side (S and the mixed flux term are
+        // transformed by both; the shorter chain per block wins over the saved work)
+        std::vector<LinJobSpec> fj = {{{HA, cB[0], cB[1]}, {gS[0]}, {{2, 2, 3}}},
+                                      {{HA, cB[1], cB[2]}, {gS[1]}, {{3, 2, 3}}}};
+        if ((s = cols_lin_jobs(ctx, d, fj, d.inv_n)) != SGN_OK) return s;
     } else {
-        if ((s = cols_lin<double>(ctx, d, {HA}, gS, {{2}}, d.inv_n)) != SGN_OK) return s;
+        if ((s = cols_lin<double>(ctx, d, {HA, cB[0]}, gS, {{2, 2}}, d.inv_n)) != SGN_OK) return s;
     }
     std::vector<const cpx<double>*> gs2(gS.begin(), gS.end());
     std::vector<double*> ud;
     for (int c = 0; c < D; ++c) ud.push_back(U_t + c * N);
     return rows_inv<double, double>(ctx, d, gs2, ud, 1.0, 1.0);
 }
+
 
 // A 1D right-hand side of up to BATCH_NMAX points by one workgroup in one launch.
 sgn_status rhs_1d_block(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, const double* u,
