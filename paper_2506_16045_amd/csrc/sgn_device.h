@@ -367,16 +367,22 @@ struct ColThread {
 
 __host__ __device__ inline int col_lds_data(const ColGeom& g, int NF) { return NF * g.Cb * g.ny; }
 
+// Column thread of column block `blk` (blockIdx.x, or the block within one part
+// of a launch that runs several column jobs side by side).
 template <typename T>
-__device__ __forceinline__ ColThread<T> col_thread(const ColGeom& g, cpx<T>* lds) {
+__device__ __forceinline__ ColThread<T> col_thread_at(const ColGeom& g, cpx<T>* lds, int blk) {
     ColThread<T> ct;
     ct.c = threadIdx.x / g.TPC;
     ct.t = threadIdx.x - ct.c * g.TPC;
-    ct.kx = blockIdx.x * g.Cb + ct.c;
+    ct.kx = blk * g.Cb + ct.c;
     ct.valid = ct.kx < g.nxh;
     ct.buf = lds + ct.c * g.ny;
     ct.fstride = g.Cb * g.ny;
     return ct;
+}
+template <typename T>
+__device__ __forceinline__ ColThread<T> col_thread(const ColGeom& g, cpx<T>* lds) {
+    return col_thread_at<T>(g, lds, blockIdx.x);
 }
 
 // Load NF columns of H (or S) and optionally transform them along y.

@@ -76,24 +76,49 @@ __device__ __forceinline__ void precond_mode(T kx, T ky, T sig, T alp, const cpx
 // Generic FFT passes
 // ---------------------------------------------------------------------------
 
+// Fields f >= first of a forward row pass are read as src + (c1 a + c2 b): an
+// extrapolated initial guess formed from its base and two recorded offsets as
+// it is loaded (b may be null; first < 0: no field is combined).
+template <typename Tin>
+struct RowCombo {
+    const Tin* a[4];
+    const Tin* b[4];
+    double c1, c2;
+    int first;
+};
+
 // Forward row transforms of n physical fields (Tin = double or T) into H fields,
 // NFG fields at a time in lockstep (the remainder one by one).
 template <typename T, typename Tin, int EPC, int NFG>
 __device__ __forceinline__ void rows_fwd_group(const RowGeom& g, const RowThread<T>& rt,
                                                const PtrList<const Tin, MAXF>& src, const PtrList<cpx<T>, MAXF>& dst,
-                                               int f0, const cpx<T>* __restrict__ tw, const cpx<T>* twm, T scale) {
+                                               int f0, const cpx<T>* __restrict__ tw, const cpx<T>* twm, T scale,
+                                               const RowCombo<Tin>& cmb) {
     cpx<T> z[NFG][EPC];
     cpx<T>* H[NFG];
 #pragma unroll
     for (int f = 0; f < NFG; ++f) {
         H[f] = dst.p[f0 + f];
+        const int k = f0 + f - cmb.first;
+        const bool comb = cmb.first >= 0 && k >= 0;
 #pragma unroll
         for (int e = 0; e < EPC; ++e) {
             const int j = rt.t + g.TPR * e;
             z[f][e] = C<T>(0, 0);
             if (j < g.M && rt.valid) {
                 const size_t o = (size_t)rt.y * g.nx + 2 * j;
-                z[f][e] = C<T>((T)src.p[f0 + f][o], (T)src.p[f0 + f][o + 1]);
+                if (comb) {
+                    double v[2];
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        double t = cmb.c1 * (double)cmb.a[k][o + s];
+                        if (cmb.b[k]) t += cmb.c2 * (double)cmb.b[k][o + s];
+                        v[s] = (double)src.p[f0 + f][o + s] + t;
+                    }
+                    z[f][e] = C<T>((T)v[0], (T)v[1]);
+                } else {
+                    z[f][e] = C<T>((T)src.p[f0 + f][o], (T)src.p[f0 + f][o + 1]);
+                }
             }
         }
     }
@@ -103,23 +128,25 @@ __device__ __forceinline__ void rows_fwd_group(const RowGeom& g, const RowThread
 template <typename T, typename Tin, int EPC, int NFG, int MAXT = 1024>
 __global__ void __launch_bounds__(MAXT) k_rows_fwd(RowGeom g, PtrList<const Tin, MAXF> src,
                                                    PtrList<cpx<T>, MAXF> dst,
-                                                   const cpx<T>* __restrict__ tw, T scale) {
+                                                   const cpx<T>* __restrict__ tw, T scale, RowCombo<Tin> cmb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     const cpx<T>* twm = twl_setup<T>(tw, g.M, lds + row_lds_data(g, NFG));
     const RowThread<T> rt = row_thread<T>(g, lds);
     int f = 0;
-    for (; f + NFG <= src.n; f += NFG) rows_fwd_group<T, Tin, EPC, NFG>(g, rt, src, dst, f, tw, twm, scale);
-    for (; f < src.n; ++f) rows_fwd_group<T, Tin, EPC, 1>(g, rt, src, dst, f, tw, twm, scale);
+    for (; f + NFG <= src.n; f += NFG) rows_fwd_group<T, Tin, EPC, NFG>(g, rt, src, dst, f, tw, twm, scale, cmb);
+    for (; f < src.n; ++f) rows_fwd_group<T, Tin, EPC, 1>(g, rt, src, dst, f, tw, twm, scale, cmb);
 }
 
 // Inverse row transforms of n H fields into physical fields (Tout):
-// dst = acc * dst + scale * value  (acc = 0 overwrites).
+// dst = acc * dst + scale * value  (acc = 0 overwrites).  With offs.n > 0,
+// offs_f = new - old value of dst_f is written too (the offset of a solve's
+// result from its base, recorded for the next extrapolated guess).
 template <typename T, typename Tout, int EPC, int NFG>
 __device__ __forceinline__ void rows_inv_group(const RowGeom& g, const RowThread<T>& rt,
                                                const PtrList<const cpx<T>, MAXF>& src, const PtrList<Tout, MAXF>& dst,
                                                int f0, const cpx<T>* __restrict__ tw, const cpx<T>* twm, T scale,
-                                               T acc) {
+                                               T acc, const PtrList<Tout, MAXF>& offs) {
     cpx<T> z[NFG][EPC];
     const cpx<T>* H[NFG];
 #pragma unroll
@@ -138,6 +165,11 @@ __device__ __forceinline__ void rows_inv_group(const RowGeom& g, const RowThread
                     v0 += acc * (T)d[o];
                     v1 += acc * (T)d[o + 1];
                 }
+                if (offs.n > 0) {
+                    Tout* od = offs.p[f0 + f];
+                    od[o] = (Tout)v0 - d[o];
+                    od[o + 1] = (Tout)v1 - d[o + 1];
+                }
                 d[o] = (Tout)v0;
                 d[o + 1] = (Tout)v1;
             }
@@ -148,14 +180,16 @@ __device__ __forceinline__ void rows_inv_group(const RowGeom& g, const RowThread
 template <typename T, typename Tout, int EPC, int NFG, int MAXT = 1024>
 __global__ void __launch_bounds__(MAXT) k_rows_inv(RowGeom g, PtrList<const cpx<T>, MAXF> src,
                                                    PtrList<Tout, MAXF> dst,
-                                                   const cpx<T>* __restrict__ tw, T scale, T acc) {
+                                                   const cpx<T>* __restrict__ tw, T scale, T acc,
+                                                   PtrList<Tout, MAXF> offs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     const cpx<T>* twm = twl_setup<T>(tw, g.M, lds + row_lds_data(g, NFG));
     const RowThread<T> rt = row_thread<T>(g, lds);
     int f = 0;
-    for (; f + NFG <= src.n; f += NFG) rows_inv_group<T, Tout, EPC, NFG>(g, rt, src, dst, f, tw, twm, scale, acc);
-    for (; f < src.n; ++f) rows_inv_group<T, Tout, EPC, 1>(g, rt, src, dst, f, tw, twm, scale, acc);
+    for (; f + NFG <= src.n; f += NFG)
+        rows_inv_group<T, Tout, EPC, NFG>(g, rt, src, dst, f, tw, twm, scale, acc, offs);
+    for (; f < src.n; ++f) rows_inv_group<T, Tout, EPC, 1>(g, rt, src, dst, f, tw, twm, scale, acc, offs);
 }
 
 // ---------------------------------------------------------------------------
@@ -913,6 +947,8 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
 // bh).  GUESS: partial ||b||^2; y-FFT of u0 -> x_hat, and (x_hat, div x_hat)/N
 // y-inverse-transformed into H for the row pass of G x_0 (C2_RESID_INIT then
 // forms r_0).  Otherwise x_hat = 0, r_0 = b_hat and the partials r.z, r.r.
+// GUESS: the b part runs on blocks [0, nblocks) and the u0 part on blocks
+// [nblocks, 2 nblocks), side by side (H must not alias Hb then).
 template <typename T, int EPC, int D, bool GUESS>
 __global__ void __launch_bounds__(256) k_pcg_setup(ColGeom g, const cpx<T>* __restrict__ tw,
                                                     const SolveScal* __restrict__ sc, const cpx<T>* Hb,
@@ -924,10 +960,44 @@ __global__ void __launch_bounds__(256) k_pcg_setup(ColGeom g, const cpx<T>* __re
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     __shared__ double red[32];
     const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D + 1));
-    const ColThread<T> ct = col_thread<T>(g, lds);
+    const int job = GUESS ? (int)blockIdx.x / g.nblocks : 0;
+    const ColThread<T> ct = col_thread_at<T>(g, lds, (int)blockIdx.x - job * g.nblocks);
     const double w = ct.valid ? half_weight(ct.kx, g.nx) : 0.0;
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
     const T sig = (T)sc->sig, alp = (T)sc->alp, inv_n = (T)sc->inv_n;
+    if (GUESS && job == 1) {
+        cpx<T> vu[D][EPC];
+        {
+            const cpx<T>* srcs[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) srcs[c] = Hu + c * NS;
+            col_load<T, EPC, D>(g, ct, srcs, true, twm, vu);
+        }
+        cpx<T> o[D + 1][EPC];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+#pragma unroll
+            for (int c = 0; c <= D; ++c) o[c][e] = C<T>(0, 0);
+            if (ct.valid && j < g.ny) {
+                const size_t idx = (size_t)ct.kx * g.ny + j;
+                const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    xh[c * NS + idx] = vu[c][e];
+                    o[c][e] = inv_n * vu[c][e];
+                }
+                cpx<T> dv = ik(kx, vu[0][e]);
+                if (D == 2) dv = dv + ik(ky, vu[1 % D][e]);
+                o[D][e] = inv_n * dv;
+            }
+        }
+        cpx<T>* dsts[D + 1];
+#pragma unroll
+        for (int c = 0; c <= D; ++c) dsts[c] = H + c * NS;
+        col_store<T, EPC, D + 1>(g, ct, o, dsts, true, twm);
+        return;
+    }
     cpx<T> vb[D][EPC];
     {
         const cpx<T>* srcs[D];
@@ -965,36 +1035,6 @@ __global__ void __launch_bounds__(256) k_pcg_setup(ColGeom g, const cpx<T>* __re
         }
     }
     if (GUESS) {
-        cpx<T> vu[D][EPC];
-        {
-            const cpx<T>* srcs[D];
-#pragma unroll
-            for (int c = 0; c < D; ++c) srcs[c] = Hu + c * NS;
-            col_load<T, EPC, D>(g, ct, srcs, true, twm, vu);
-        }
-        cpx<T> o[D + 1][EPC];
-#pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            const int j = ct.t + g.TPC * e;
-#pragma unroll
-            for (int c = 0; c <= D; ++c) o[c][e] = C<T>(0, 0);
-            if (ct.valid && j < g.ny) {
-                const size_t idx = (size_t)ct.kx * g.ny + j;
-                const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    xh[c * NS + idx] = vu[c][e];
-                    o[c][e] = inv_n * vu[c][e];
-                }
-                cpx<T> dv = ik(kx, vu[0][e]);
-                if (D == 2) dv = dv + ik(ky, vu[1 % D][e]);
-                o[D][e] = inv_n * dv;
-            }
-        }
-        cpx<T>* dsts[D + 1];
-#pragma unroll
-        for (int c = 0; c <= D; ++c) dsts[c] = H + c * NS;
-        col_store<T, EPC, D + 1>(g, ct, o, dsts, true, twm);
         double bsum[1] = {acc[0]};
         block_sum<1>(bsum, red);
         if (threadIdx.x == 0) part[PART_GEN + blockIdx.x] = bsum[0];

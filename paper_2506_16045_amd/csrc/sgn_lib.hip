@@ -51,6 +51,13 @@ struct sgn_ctx {
     void* hbatch = nullptr;       // pinned staging of batch item tables and results
     size_t hbatch_bytes = 0;
     int slot = GUESS_SLOTS;       // stepper slot of the running solve
+    // extrapolated guess of a stepper solve on the FP64 row/column path: the solve
+    // reads u (the base) + (gx_c1 gx_a + gx_c2 gx_b) while transforming it, and
+    // writes its result's offset from the base to gx_off while storing it
+    const double* gx_a = nullptr;
+    const double* gx_b = nullptr;
+    double gx_c1 = 0.0, gx_c2 = 0.0;
+    double* gx_off = nullptr;
 };
 
 namespace {
@@ -252,11 +259,17 @@ struct ProfScope {
 
 // ---- generic passes --------------------------------------------------------
 
+// cmb (optional): fields from cmb->first on are read as src + (c1 a + c2 b)
+// (at most MAXF fields in that case).
 template <typename T, typename Tin>
 sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, std::vector<cpx<T>*> dst,
-                    T scale = (T)1) {
+                    T scale = (T)1, const RowCombo<Tin>* cmb = nullptr) {
     ProfScope ps(ctx, SGN_KERNEL_ROWS);
     RowLaunch L = row_launch<T>(d.nx, d.ny);
+    RowCombo<Tin> none{};
+    none.first = -1;
+    if (cmb && src.size() > (size_t)MAXF) return fail(ctx, SGN_EINVAL, "rows_fwd: combined sources exceed one pass");
+    const RowCombo<Tin>& cm = cmb ? *cmb : none;
     for (size_t f0 = 0; f0 < src.size(); f0 += MAXF) {
         PtrList<const Tin, MAXF> s{};
         PtrList<cpx<T>, MAXF> t{};
@@ -270,7 +283,7 @@ sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, st
         auto launch = [&](auto k) -> sgn_status {
             HIPCHK(ctx, allow_lds(k, lds));
             hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, s, t, twiddles<T>(ctx),
-                               scale);
+                               scale, cm);
             return SGN_OK;
         };
         sgn_status st;
@@ -286,25 +299,30 @@ sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, st
     return SGN_OK;
 }
 
+// offs (optional, one per field): also write new - old value of each dst field.
 template <typename T, typename Tout>
 sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src, std::vector<Tout*> dst,
-                    T scale = (T)1, T acc = (T)0) {
+                    T scale = (T)1, T acc = (T)0, const std::vector<Tout*>* offs = nullptr) {
     ProfScope ps(ctx, SGN_KERNEL_ROWS);
     RowLaunch L = row_launch<T>(d.nx, d.ny);
+    if (offs && offs->size() != src.size()) return fail(ctx, SGN_EINVAL, "rows_inv: offsets per field");
     for (size_t f0 = 0; f0 < src.size(); f0 += MAXF) {
         PtrList<const cpx<T>, MAXF> s{};
         PtrList<Tout, MAXF> t{};
+        PtrList<Tout, MAXF> of{};
         s.n = t.n = (int)std::min<size_t>(MAXF, src.size() - f0);
+        of.n = offs ? s.n : 0;
         for (int i = 0; i < s.n; ++i) {
             s.p[i] = src[f0 + i];
             t.p[i] = dst[f0 + i];
+            if (offs) of.p[i] = (*offs)[f0 + i];
         }
         const bool multi = row_lds_bytes<T>(L.g, 3) <= LDS_MULTI_MAX;
         const size_t lds = row_lds_bytes<T>(L.g, multi ? 3 : 1);
         auto launch = [&](auto k) -> sgn_status {
             HIPCHK(ctx, allow_lds(k, lds));
             hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, s, t, twiddles<T>(ctx),
-                               scale, acc);
+                               scale, acc, of);
             return SGN_OK;
         };
         sgn_status st;
@@ -594,28 +612,44 @@ template <int D>
 sgn_status pcg_start(PcgLaunch<double, D>& P, const double* rhs, const double* u0, bool guess, cpx<double>* bh) {
     sgn_ctx* ctx = P.ctx;
     const Dims& d = P.d;
+    // b's row transforms go to ph (unused until the first iteration) when a guess
+    // is transformed too: the setup's two column jobs then read b from ph while
+    // the guess job writes the row-pass fields of G x_0 to H
+    cpx<double>* Hb = guess ? P.b.ph : P.b.H;
     std::vector<const double*> src;
     std::vector<cpx<double>*> dst;
     for (int c = 0; c < D; ++c) {
         src.push_back(rhs + c * d.N);
-        dst.push_back(P.b.H + c * d.NS);
+        dst.push_back(Hb + c * d.NS);
     }
+    RowCombo<double> cmb{};
+    cmb.first = -1;
     if (guess) {
         for (int c = 0; c < D; ++c) {
             src.push_back(u0 + c * d.N);
             dst.push_back(P.b.qh + c * d.NS);
         }
+        if (ctx->gx_a) {   // stepper guess: base + offsets, formed while loading
+            cmb.first = D;
+            cmb.c1 = ctx->gx_c1;
+            cmb.c2 = ctx->gx_c2;
+            for (int c = 0; c < D; ++c) {
+                cmb.a[c] = ctx->gx_a + c * d.N;
+                cmb.b[c] = ctx->gx_b ? ctx->gx_b + c * d.N : nullptr;
+            }
+        }
     }
     sgn_status s;
-    if ((s = rows_fwd<double, double>(ctx, d, src, dst)) != SGN_OK) return s;
+    if ((s = rows_fwd<double, double>(ctx, d, src, dst, 1.0, &cmb)) != SGN_OK) return s;
     {
         ProfScope ps(ctx, SGN_KERNEL_PCG_INIT);
         const size_t lds = col_lds_bytes<double>(P.cl.g, D + 1);
         auto launch = [&](auto k) -> sgn_status {
             HIPCHK(ctx, allow_lds(k, lds));
-            hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), lds, ctx->stream, P.cl.g, ctx->tw64,
-                               (const SolveScal*)P.sc, (const cpx<double>*)P.b.H, (const cpx<double>*)P.b.qh, d.NS,
-                               bh, P.b.rh, P.b.xh, P.b.H, P.partials, d.tpx, d.tpy);
+            hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks * (guess ? 2 : 1)), dim3(P.cl.threads), lds, ctx->stream,
+                               P.cl.g, ctx->tw64, (const SolveScal*)P.sc, (const cpx<double>*)Hb,
+                               (const cpx<double>*)P.b.qh, d.NS, bh, P.b.rh, P.b.xh, P.b.H, P.partials, d.tpx,
+                               d.tpy);
             CHECK_LAUNCH(ctx);
             return SGN_OK;
         };
@@ -791,12 +825,13 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
                            (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
         CHECK_LAUNCH(ctx);
         std::vector<const cpx<double>*> hs;
-        std::vector<double*> ud;
+        std::vector<double*> ud, od;
         for (int c = 0; c < D; ++c) {
             hs.push_back(P.b.H + c * d.NS);
             ud.push_back(u + c * d.N);
+            if (ctx->gx_off) od.push_back(ctx->gx_off + c * d.N);
         }
-        if ((s = rows_inv<double, double>(ctx, d, hs, ud)) != SGN_OK) return s;
+        if ((s = rows_inv<double, double>(ctx, d, hs, ud, 1.0, 0.0, ctx->gx_off ? &od : nullptr)) != SGN_OK) return s;
     }
     if (ctx->stage) {
         // stepper: iterations and the outcome are known from the loop's readback
@@ -1757,10 +1792,21 @@ sgn_status stage_solve(sgn_state* st, int slot, const double* eta, const double*
     StateBufs& b = st->b;
     const size_t DN = (size_t)st->d.D * st->d.N;
     const bool ex = o.guess == SGN_GUESS_EXTRAPOLATE;
+    // FP64 PCG on the row/column path forms the guess and records the offset inside
+    // its first and last passes; the other paths do both with separate passes
+    const bool fused = ex && o.precision == SGN_FP64 && o.method == SGN_PCG &&
+                       !(st->d.D == 1 && st->d.nx <= BATCH_NMAX);
     sgn_status s;
     int& cnt = st->gx_count[slot];
     int& head = st->gx_head[slot];
-    if (ex) {
+    const int nh = cnt == 0 ? head : head ^ 1;
+    if (fused) {
+        ctx->gx_a = cnt >= 1 ? b.gx_off[slot][head] : nullptr;
+        ctx->gx_b = cnt >= 2 ? b.gx_off[slot][head ^ 1] : nullptr;
+        ctx->gx_c1 = cnt >= 2 ? 2.0 : 1.0;
+        ctx->gx_c2 = -1.0;
+        ctx->gx_off = b.gx_off[slot][nh];
+    } else if (ex) {
         // keep the base and form the guess in place, in one pass
         if (cnt == 0) {
             if ((s = copy_d(ctx, b.gx_base, u, DN)) != SGN_OK) return s;
@@ -1782,11 +1828,15 @@ sgn_status stage_solve(sgn_state* st, int slot, const double* eta, const double*
     s = solve_dispatch(ctx, st->d, eta, st->gh, U, u, nullptr, st->flat, so, &si, st->ws);
     ctx->stage = false;
     ctx->slot = GUESS_SLOTS;
+    ctx->gx_a = ctx->gx_b = nullptr;
+    ctx->gx_off = nullptr;
     account(acc, si);
-    if (s != SGN_OK) return s;
+    if (s != SGN_OK) {
+        if (fused) cnt = 0;   // the offset ring may hold a partial record
+        return s;
+    }
     if (ex) {
-        const int nh = cnt == 0 ? head : head ^ 1;
-        if ((s = lincomb(ctx, DN, u, 1.0, {b.gx_base}, {-1.0}, b.gx_off[slot][nh])) != SGN_OK) return s;
+        if (!fused && (s = lincomb(ctx, DN, u, 1.0, {b.gx_base}, {-1.0}, b.gx_off[slot][nh])) != SGN_OK) return s;
         head = nh;
         if (cnt < 2) cnt += 1;
     }
