@@ -55,6 +55,16 @@ __host__ __device__ inline long long batch_item_doubles(int n, int mode) {
     return (w + 1) & ~1LL;
 }
 
+// A value every lane of the wave holds alike, moved to scalar registers (the
+// block-wide results below are read from LDS, which the compiler cannot see
+// as uniform; in vector registers they would crowd the per-mode state).
+__device__ __forceinline__ double uniform_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Block-wide sums of NACC doubles, the result in every thread (fixed order).
 template <int NACC>
 __device__ __forceinline__ void blk_allsum(double (&v)[NACC], double* red) {
@@ -65,7 +75,7 @@ __device__ __forceinline__ void blk_allsum(double (&v)[NACC], double* red) {
     }
     __syncthreads();
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) v[a] = red[16 * NACC + a];
+    for (int a = 0; a < NACC; ++a) v[a] = uniform_d(red[16 * NACC + a]);
     __syncthreads();
 }
 
@@ -87,7 +97,7 @@ __device__ __forceinline__ void blk_allmax(double (&v)[NACC], double* red) {
     for (int a = 0; a < NACC; ++a) {
         double m = red[a * 16];
         for (int w = 1; w < nw; ++w) m = fmax(m, red[a * 16 + w]);
-        v[a] = m;
+        v[a] = uniform_d(m);
     }
     __syncthreads();
 }
@@ -261,13 +271,16 @@ __device__ int blk_pcg_reg(const BatchOp<T>& A, cpx<TX>* xh, const cpx<TX>* r0h,
     cpx<T>* lb = lds + fs;
     const T invN = (T)1 / (T)N;
     const double dinvN = 1.0 / (double)N;
-    cpx<T> x[KPT], r[KPT], p[KPT];
+    // FP32 inner solves accumulate their correction in registers; the FP64 solve,
+    // whose registers are fuller, adds each step to xh directly
+    constexpr bool XREG = sizeof(T) == 4;
+    cpx<T> x[XREG ? KPT : 1], r[KPT], p[KPT];
     T er[JC][2], hr[JC][2];
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < KPT; ++e) {
         const int k = t + NT * e;
-        x[e] = C<T>(0, 0);
+        if (XREG) x[XREG ? e : 0] = C<T>(0, 0);
         p[e] = C<T>(0, 0);
         r[e] = C<T>(0, 0);
         if (k <= M) {
@@ -296,6 +309,11 @@ __device__ int blk_pcg_reg(const BatchOp<T>& A, cpx<TX>* xh, const cpx<TX>* r0h,
     int it = 0;
     const T third = (T)1 / (T)3, half = (T)0.5;
     while (!(rr <= tol2 * bbref) && it < max_iter && rr == rr) {
+        // FP64: the thread index, opaque to the compiler inside the loop, so that
+        // per-mode indices, wavenumbers and weights are recomputed each iteration
+        // instead of being hoisted into registers that the Krylov vectors need
+        int t = threadIdx.x;
+        if (!XREG) asm volatile("" : "+v"(t));
         const T beta = it == 0 ? (T)0 : (T)(rz / rho_prev);
         // p = z + beta p; p / N and i k p / N into the two buffers
 #pragma unroll
@@ -312,7 +330,8 @@ __device__ int blk_pcg_reg(const BatchOp<T>& A, cpx<TX>* xh, const cpx<TX>* r0h,
         blk_rfft_inv_n<T, NT, 2>(lds, fs, M, A.tw);
         // pointwise: a into buffer a, w into buffer b; curvature p.Gp
         double pqa[1] = {0.0};
-#pragma unroll
+        constexpr int PU = REGCOEF ? JPT : 1;   // the FP64 loop reads eta, h_x from memory
+#pragma unroll PU
         for (int e = 0; e < JPT; ++e) {
             const int j = t + NT * e;
             if (j < M) {
@@ -351,7 +370,10 @@ __device__ int blk_pcg_reg(const BatchOp<T>& A, cpx<TX>* xh, const cpx<TX>* r0h,
             if (k <= M) {
                 const T kk = wavenumber<T>(k, N, A.tp);
                 const cpx<T> q = la[k] - ik(kk, lb[k]);
-                x[e] = x[e] + alpha * p[e];
+                if (XREG)
+                    x[XREG ? e : 0] = x[XREG ? e : 0] + alpha * p[e];
+                else
+                    xh[k] = xh[k] + cvt<TX>(alpha * p[e]);
                 r[e] = r[e] - alpha * q;
                 const cpx<T> z = batch_precond<T>(kk, sig, alp, r[e]);
                 const double w = half_weight(k, N) * dinvN;
@@ -365,10 +387,12 @@ __device__ int blk_pcg_reg(const BatchOp<T>& A, cpx<TX>* xh, const cpx<TX>* r0h,
         rr = acc[1];
         ++it;
     }
+    if (XREG) {
 #pragma unroll
-    for (int e = 0; e < KPT; ++e) {
-        const int k = t + NT * e;
-        if (k <= M) xh[k] = xh[k] + cvt<TX>(x[e]);
+        for (int e = 0; e < KPT; ++e) {
+            const int k = t + NT * e;
+            if (k <= M) xh[k] = xh[k] + cvt<TX>(x[XREG ? e : 0]);
+        }
     }
     __syncthreads();
     return it;
