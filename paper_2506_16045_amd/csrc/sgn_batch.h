@@ -65,6 +65,12 @@ __device__ __forceinline__ double uniform_d(double v) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Workgroup scratch for block reductions: blk_allsum<NACC> and blk_allmax<NACC>
+// use the first 17 NACC doubles; RED_PQ..RED_PQ+15 holds the wave partials of
+// the PCG curvature between the pointwise pass and the forward transform.
+constexpr int RED_PQ = 96;
+constexpr int RED_DOUBLES = RED_PQ + 16;
+
 // Block-wide sums of NACC doubles, the result in every thread (fixed order).
 template <int NACC>
 __device__ __forceinline__ void blk_allsum(double (&v)[NACC], double* red) {
@@ -359,10 +365,20 @@ __device__ int blk_pcg_reg(const BatchOp<T>& A, cpx<TX>* xh, const cpx<TX>* r0h,
                 lb[j] = dv;
             }
         }
-        blk_allsum<1>(pqa, red);
-        const double rho = rz;
-        const T alpha = (T)(rho / pqa[0]);
+        // p.Gp: wave sums now, the block sum (waves in order, as blk_allsum) after
+        // the forward transform, whose barriers publish the wave partials
+        {
+            double x = pqa[0];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+            if ((threadIdx.x & 63) == 0) red[RED_PQ + (threadIdx.x >> 6)] = x;
+        }
         blk_rfft_fwd_n<T, NT, 2>(lds, fs, M, A.tw);
+        double pq = 0.0;
+        for (int w = 0; w < NT / 64; ++w) pq += red[RED_PQ + w];
+        pq = uniform_d(pq);
+        const double rho = rz;
+        const T alpha = (T)(rho / pq);
         acc[0] = acc[1] = 0.0;
 #pragma unroll
         for (int e = 0; e < KPT; ++e) {
@@ -441,7 +457,7 @@ __global__ void __launch_bounds__(NT) k_batch_solve(const BatchItem* __restrict_
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<double>* lds64 = reinterpret_cast<cpx<double>*>(smem_raw);
     cpx<float>* lds32 = reinterpret_cast<cpx<float>*>(smem_raw);
-    __shared__ double red[5 * 16 + 8];
+    __shared__ double red[RED_DOUBLES];
     for (int s = blockIdx.x; s < nitems; s += gridDim.x) {
         const BatchItem it = items[s];
         const int N = it.n, M = N / 2;

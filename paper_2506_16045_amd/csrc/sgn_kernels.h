@@ -141,12 +141,13 @@ __global__ void __launch_bounds__(MAXT) k_rows_fwd(RowGeom g, PtrList<const Tin,
 // Inverse row transforms of n H fields into physical fields (Tout):
 // dst = acc * dst + scale * value  (acc = 0 overwrites).  With offs.n > 0,
 // offs_f = new - old value of dst_f is written too (the offset of a solve's
-// result from its base, recorded for the next extrapolated guess).
+// result from its base, recorded for the next extrapolated guess); with
+// oacc != 0 it is added to offs_f instead (a result stored a second time).
 template <typename T, typename Tout, int EPC, int NFG>
 __device__ __forceinline__ void rows_inv_group(const RowGeom& g, const RowThread<T>& rt,
                                                const PtrList<const cpx<T>, MAXF>& src, const PtrList<Tout, MAXF>& dst,
                                                int f0, const cpx<T>* __restrict__ tw, const cpx<T>* twm, T scale,
-                                               T acc, const PtrList<Tout, MAXF>& offs) {
+                                               T acc, const PtrList<Tout, MAXF>& offs, int oacc) {
     cpx<T> z[NFG][EPC];
     const cpx<T>* H[NFG];
 #pragma unroll
@@ -167,8 +168,9 @@ __device__ __forceinline__ void rows_inv_group(const RowGeom& g, const RowThread
                 }
                 if (offs.n > 0) {
                     Tout* od = offs.p[f0 + f];
-                    od[o] = (Tout)v0 - d[o];
-                    od[o + 1] = (Tout)v1 - d[o + 1];
+                    const Tout d0 = (Tout)v0 - d[o], d1 = (Tout)v1 - d[o + 1];
+                    od[o] = oacc ? od[o] + d0 : d0;
+                    od[o + 1] = oacc ? od[o + 1] + d1 : d1;
                 }
                 d[o] = (Tout)v0;
                 d[o + 1] = (Tout)v1;
@@ -181,15 +183,15 @@ template <typename T, typename Tout, int EPC, int NFG, int MAXT = 1024>
 __global__ void __launch_bounds__(MAXT) k_rows_inv(RowGeom g, PtrList<const cpx<T>, MAXF> src,
                                                    PtrList<Tout, MAXF> dst,
                                                    const cpx<T>* __restrict__ tw, T scale, T acc,
-                                                   PtrList<Tout, MAXF> offs) {
+                                                   PtrList<Tout, MAXF> offs, int oacc) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     const cpx<T>* twm = twl_setup<T>(tw, g.M, lds + row_lds_data(g, NFG));
     const RowThread<T> rt = row_thread<T>(g, lds);
     int f = 0;
     for (; f + NFG <= src.n; f += NFG)
-        rows_inv_group<T, Tout, EPC, NFG>(g, rt, src, dst, f, tw, twm, scale, acc, offs);
-    for (; f < src.n; ++f) rows_inv_group<T, Tout, EPC, 1>(g, rt, src, dst, f, tw, twm, scale, acc, offs);
+        rows_inv_group<T, Tout, EPC, NFG>(g, rt, src, dst, f, tw, twm, scale, acc, offs, oacc);
+    for (; f < src.n; ++f) rows_inv_group<T, Tout, EPC, 1>(g, rt, src, dst, f, tw, twm, scale, acc, offs, oacc);
 }
 
 // ---------------------------------------------------------------------------
@@ -746,6 +748,24 @@ __global__ void __launch_bounds__(256) k_pcg_check(SolveScal* __restrict__ sc, c
     __shared__ double slot[2];
     double beta;
     pcg_iterate_state(sc, part, nb3, red, slot, beta);
+}
+
+// Publish iter, max_iter, done, converged, flat, status of a solve into host
+// memory (d: device address of a host-coherent pinned buffer), then the
+// sequence number seq in d[6].  The stores are volatile and system-coherent:
+// each completes before the next is issued, so a host that sees seq also sees
+// the values (no cache-wide fence needed for one thread's ordered stores).
+__global__ void k_publish_flags(const SolveScal* __restrict__ sc, int* d, int seq) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        volatile int* v = d;
+        v[0] = sc->iter;
+        v[1] = sc->max_iter;
+        v[2] = sc->done;
+        v[3] = sc->converged;
+        v[4] = sc->flat;
+        v[5] = sc->status;
+        v[6] = seq;
+    }
 }
 
 template <typename T, int EPC, int D, bool SEQ, int MAXT = 1024>

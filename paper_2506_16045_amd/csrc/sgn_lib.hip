@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 using namespace sgn;
@@ -41,10 +42,11 @@ struct sgn_ctx {
     };
     hipStream_t cap_stream = nullptr;
     std::vector<GraphEntry> graphs;
-    bool use_graphs = true;
+    bool use_graphs = false;
     // iterations of the previous solve per precision (FP64 / FP32 loop) and
     // stepper slot (last entry: solves outside a stepper)
     int last_iters[2][GUESS_SLOTS + 1] = {};
+    int* stage_last = nullptr;    // the running stepper solve's counters (state-owned), if any
     bool stage = false;           // solving inside a stepper: skip the final scalar readback
     int cus = 256;                // compute units of the device
     int batch_threads = 512;      // workgroup size of the batched solver (SGN_BATCH_THREADS: 256, 512, 1024)
@@ -58,6 +60,16 @@ struct sgn_ctx {
     const double* gx_b = nullptr;
     double gx_c1 = 0.0, gx_c2 = 0.0;
     double* gx_off = nullptr;
+    // readbacks in the solve loops wait by polling this event: a blocking stream
+    // synchronisation wakes the host tens of microseconds after the GPU is done,
+    // and the GPU idles until the next launches arrive
+    hipEvent_t ev_sync = nullptr;
+    // the loop flags are published by a one-thread kernel straight into this
+    // host-coherent pinned buffer (hpub; dpub its device address), tagged with a
+    // sequence number; the host polls it (no device-to-host copy in the stream)
+    int* hpub = nullptr;
+    int* dpub = nullptr;
+    int pub_seq = 0;
 };
 
 namespace {
@@ -299,10 +311,11 @@ sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, st
     return SGN_OK;
 }
 
-// offs (optional, one per field): also write new - old value of each dst field.
+// offs (optional, one per field): also write new - old value of each dst field
+// (added to offs instead with offs_acc).
 template <typename T, typename Tout>
 sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src, std::vector<Tout*> dst,
-                    T scale = (T)1, T acc = (T)0, const std::vector<Tout*>* offs = nullptr) {
+                    T scale = (T)1, T acc = (T)0, const std::vector<Tout*>* offs = nullptr, bool offs_acc = false) {
     ProfScope ps(ctx, SGN_KERNEL_ROWS);
     RowLaunch L = row_launch<T>(d.nx, d.ny);
     if (offs && offs->size() != src.size()) return fail(ctx, SGN_EINVAL, "rows_inv: offsets per field");
@@ -322,7 +335,7 @@ sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src,
         auto launch = [&](auto k) -> sgn_status {
             HIPCHK(ctx, allow_lds(k, lds));
             hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, s, t, twiddles<T>(ctx),
-                               scale, acc, of);
+                               scale, acc, of, offs_acc ? 1 : 0);
             return SGN_OK;
         };
         sgn_status st;
@@ -663,11 +676,24 @@ sgn_status pcg_start(PcgLaunch<double, D>& P, const double* rhs, const double* u
     return SGN_OK;
 }
 
+// Wait until the stream has drained (polling an event when the context has one).
+sgn_status wait_stream(sgn_ctx* ctx) {
+    if (!ctx->ev_sync) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        return SGN_OK;
+    }
+    HIPCHK(ctx, hipEventRecord(ctx->ev_sync, ctx->stream));
+    for (;;) {
+        const hipError_t e = hipEventQuery(ctx->ev_sync);
+        if (e == hipSuccess) return SGN_OK;
+        if (e != hipErrorNotReady) return fail(ctx, SGN_EDEVICE, hipGetErrorString(e));
+    }
+}
+
 // Read the solve's device scalars into ctx->hscal (synchronises the stream).
 sgn_status read_scal(sgn_ctx* ctx, const SolveScal* sc) {
     HIPCHK(ctx, hipMemcpyAsync(ctx->hscal, sc, sizeof(SolveScal), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return SGN_OK;
+    return wait_stream(ctx);
 }
 
 // Initialise a SolveScal on the device (stream-ordered, no host round trip).
@@ -758,14 +784,58 @@ struct LoopOut {
 };
 
 // Read iter, max_iter, done, converged, flat, status of a solve (synchronises the stream).
-sgn_status read_loop(sgn_ctx* ctx, const SolveScal* sc, LoopOut* out) {
-    HIPCHK(ctx, hipMemcpyAsync(ctx->hflag, &sc->iter, 6 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    out->iter = ctx->hflag[0];
-    out->done = ctx->hflag[2];
-    out->converged = ctx->hflag[3];
-    out->status = ctx->hflag[5];
+// Enqueue the publication of iter, max_iter, done, converged, flat, status and
+// mark it.
+sgn_status issue_loop_readback(sgn_ctx* ctx, const SolveScal* sc) {
+    if (ctx->dpub) {
+        ctx->pub_seq = ctx->pub_seq == 0x7fffffff ? 1 : ctx->pub_seq + 1;
+        hipLaunchKernelGGL(k_publish_flags, dim3(1), dim3(64), 0, ctx->stream, sc, ctx->dpub, ctx->pub_seq);
+        CHECK_LAUNCH(ctx);
+    } else {
+        HIPCHK(ctx, hipMemcpyAsync(ctx->hflag, &sc->iter, 6 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    }
+    if (ctx->ev_sync) HIPCHK(ctx, hipEventRecord(ctx->ev_sync, ctx->stream));
     return SGN_OK;
+}
+// Wait for the flags enqueued by issue_loop_readback (work enqueued after them
+// may still run) and decode them.
+sgn_status wait_loop_readback(sgn_ctx* ctx, LoopOut* out) {
+    const int* f = ctx->hflag;
+    if (ctx->dpub) {
+        // poll the published sequence number; the event (recorded behind the
+        // publishing kernel) bounds the wait if the value is somehow not seen
+        int* h = ctx->hpub;
+        for (long spins = 0;; ++spins) {
+            if (__atomic_load_n(&h[6], __ATOMIC_ACQUIRE) == ctx->pub_seq) break;
+            if ((spins & 1023) == 1023) {
+                const hipError_t e = hipEventQuery(ctx->ev_sync);
+                if (e == hipSuccess) {
+                    if (__atomic_load_n(&h[6], __ATOMIC_ACQUIRE) == ctx->pub_seq) break;
+                    return fail(ctx, SGN_EDEVICE, "published solver flags not visible to the host");
+                }
+                if (e != hipErrorNotReady) return fail(ctx, SGN_EDEVICE, hipGetErrorString(e));
+            }
+        }
+        f = h;
+    } else if (!ctx->ev_sync) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    } else {
+        for (;;) {
+            const hipError_t e = hipEventQuery(ctx->ev_sync);
+            if (e == hipSuccess) break;
+            if (e != hipErrorNotReady) return fail(ctx, SGN_EDEVICE, hipGetErrorString(e));
+        }
+    }
+    out->iter = f[0];
+    out->done = f[2];
+    out->converged = f[3];
+    out->status = f[5];
+    return SGN_OK;
+}
+
+sgn_status read_loop(sgn_ctx* ctx, const SolveScal* sc, LoopOut* out) {
+    sgn_status s = issue_loop_readback(ctx, sc);
+    return s != SGN_OK ? s : wait_loop_readback(ctx, out);
 }
 
 // Run PCG iterations until the device flag says done.  The first chunk is sized
@@ -773,20 +843,41 @@ sgn_status read_loop(sgn_ctx* ctx, const SolveScal* sc, LoopOut* out) {
 // about as many iterations as the one before), later chunks are short, so a
 // solve usually needs one host readback and wastes at most a couple of
 // iterations (which return at once on the device).
-template <typename T, int D>
-sgn_status pcg_loop(PcgLaunch<T, D>& P, int max_iter, int check_every, LoopOut* out) {
+//
+// tail (optional): the work that follows the solve on the device (storing the
+// result).  It is enqueued right after the first readback, so the GPU runs it
+// while the host waits for the flag; if the solve needed more iterations, it is
+// enqueued again after them with redo = true.
+template <typename T, int D, typename Tail = std::nullptr_t>
+sgn_status pcg_loop(PcgLaunch<T, D>& P, int max_iter, int check_every, LoopOut* out, Tail tail = nullptr) {
     if (check_every < 1) check_every = 1;
-    int& last = P.ctx->last_iters[sizeof(T) == 4 ? 1 : 0][P.ctx->slot];
-    int chunk = last > 0 ? last : check_every;
+    const int prec = sizeof(T) == 4 ? 1 : 0;
+    int& last = P.ctx->stage_last ? P.ctx->stage_last[prec] : P.ctx->last_iters[prec][P.ctx->slot];
+    // one iteration of margin over the previous solve of the slot: a converged
+    // solve returns at once from the extra launches, a second readback costs more
+    int chunk = last > 0 ? last + 1 : check_every;
     int it = 0;
+    bool tail_done = false, rounds = false;
+    sgn_status s;
     while (it < max_iter) {
         chunk = std::max(1, std::min(chunk, max_iter - it));
-        sgn_status s = pcg_chunk<T, D>(P, chunk);
-        if (s != SGN_OK) return s;
+        if ((s = pcg_chunk<T, D>(P, chunk)) != SGN_OK) return s;
         it += chunk;
-        if ((s = read_loop(P.ctx, P.sc, out)) != SGN_OK) return s;
+        if ((s = issue_loop_readback(P.ctx, P.sc)) != SGN_OK) return s;
+        if constexpr (!std::is_same<Tail, std::nullptr_t>::value) {
+            if (!rounds) {
+                if ((s = tail(false)) != SGN_OK) return s;
+                tail_done = true;
+            }
+        }
+        if ((s = wait_loop_readback(P.ctx, out)) != SGN_OK) return s;
         if (out->done) break;
+        rounds = true;
         chunk = std::min(2, check_every);
+    }
+    if constexpr (!std::is_same<Tail, std::nullptr_t>::value) {
+        if (!tail_done || rounds)
+            if ((s = tail(tail_done)) != SGN_OK) return s;
     }
     if (out->iter > 0) last = out->iter;
     return SGN_OK;
@@ -815,14 +906,13 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
         if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials)) != SGN_OK) return s;
     }
     if ((s = pcg_start<D>(P, rhs, u, o.x0_is_guess != 0, nullptr)) != SGN_OK) return s;
-    LoopOut lo;
-    if ((s = pcg_loop<double, D>(P, o.max_iter, o.check_every, &lo)) != SGN_OK) return s;
-    // u = IFFT(x_hat)
-    {
+    // u = IFFT(x_hat) (and the stepper's offset record); stored a second time after
+    // further iterations, the offset accumulates the difference
+    auto store = [&](bool redo) -> sgn_status {
         auto k = k_cols_from_S<double, 4, D>;
         HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
-                           (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream,
+                           P.cl.g, ctx->tw64, (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
         CHECK_LAUNCH(ctx);
         std::vector<const cpx<double>*> hs;
         std::vector<double*> ud, od;
@@ -831,7 +921,16 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
             ud.push_back(u + c * d.N);
             if (ctx->gx_off) od.push_back(ctx->gx_off + c * d.N);
         }
-        if ((s = rows_inv<double, double>(ctx, d, hs, ud, 1.0, 0.0, ctx->gx_off ? &od : nullptr)) != SGN_OK) return s;
+        return rows_inv<double, double>(ctx, d, hs, ud, 1.0, 0.0, ctx->gx_off ? &od : nullptr, redo);
+    };
+    LoopOut lo;
+    if (ctx->stage) {
+        // stepper: the store is enqueued behind the first readback, so the GPU does
+        // it while the host waits for the convergence flag
+        if ((s = pcg_loop<double, D>(P, o.max_iter, o.check_every, &lo, store)) != SGN_OK) return s;
+    } else {
+        if ((s = pcg_loop<double, D>(P, o.max_iter, o.check_every, &lo)) != SGN_OK) return s;
+        if ((s = store(false)) != SGN_OK) return s;
     }
     if (ctx->stage) {
         // stepper: iterations and the outcome are known from the loop's readback
@@ -1073,8 +1172,7 @@ struct Gmres {
     }
     sgn_status read(const double* dsrc, double* hdst, int n) {
         HIPCHK(P.ctx, hipMemcpyAsync(hdst, dsrc, n * sizeof(double), hipMemcpyDeviceToHost, P.ctx->stream));
-        HIPCHK(P.ctx, hipStreamSynchronize(P.ctx->stream));
-        return SGN_OK;
+        return wait_stream(P.ctx);
     }
 };
 
@@ -1358,7 +1456,7 @@ sgn_status solve_1d_block(sgn_ctx* ctx, const Dims& d, double L, const double* e
     }
     BatchResult* hres = static_cast<BatchResult*>(ctx->hbatch);
     HIPCHK(ctx, hipMemcpyAsync(hres, d_res, sizeof(BatchResult), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if ((s = wait_stream(ctx)) != SGN_OK) return s;
     const BatchResult r = *hres;
     if (info) {
         info->iters = r.iters;
@@ -1707,6 +1805,10 @@ struct sgn_state {
     double gx_dt;
     int gx_count[GUESS_SLOTS];
     int gx_head[GUESS_SLOTS];
+    // iterations of the previous solve of each slot (FP64 / FP32 loop): the first
+    // chunk of the next one, kept with the state so that a run's launches (and with
+    // them its results) do not depend on what else its context solved before
+    int last_iters[GUESS_SLOTS][2] = {};
 };
 
 namespace {
@@ -1825,9 +1927,11 @@ sgn_status stage_solve(sgn_state* st, int slot, const double* eta, const double*
     std::memset(&si, 0, sizeof(si));
     ctx->stage = true;
     ctx->slot = slot;
+    ctx->stage_last = st->last_iters[slot];
     s = solve_dispatch(ctx, st->d, eta, st->gh, U, u, nullptr, st->flat, so, &si, st->ws);
     ctx->stage = false;
     ctx->slot = GUESS_SLOTS;
+    ctx->stage_last = nullptr;
     ctx->gx_a = ctx->gx_b = nullptr;
     ctx->gx_off = nullptr;
     account(acc, si);
@@ -2069,13 +2173,24 @@ sgn_status sgn_create(sgn_ctx** out, int device, void* hip_stream) {
         return SGN_ENOMEM;
     }
     if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) ctx->cap_stream = nullptr;
+    if (hipEventCreateWithFlags(&ctx->ev_sync, hipEventDisableTiming) != hipSuccess) ctx->ev_sync = nullptr;
+    if (ctx->ev_sync &&
+        hipHostMalloc((void**)&ctx->hpub, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess) {
+        std::memset(ctx->hpub, 0, 64);
+        if (hipHostGetDevicePointer((void**)&ctx->dpub, ctx->hpub, 0) != hipSuccess) ctx->dpub = nullptr;
+    } else {
+        ctx->hpub = nullptr;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         ctx->cus = cus;
     const char* bt = getenv("SGN_BATCH_THREADS");
     if (bt) ctx->batch_threads = atoi(bt);
-    const char* ng = getenv("SGN_NO_GRAPHS");
-    if (ng && ng[0] && ng[0] != '0') ctx->use_graphs = false;
+    // HIP graphs for the PCG chunks are opt-in: their host-side launch costs more
+    // than the eager launches of a chunk (measured: 1024^2 RK4 step 3.58 ms with
+    // graphs, 3.56 ms without)
+    const char* ug = getenv("SGN_GRAPHS");
+    ctx->use_graphs = ug && ug[0] && ug[0] != '0';
     *out = ctx;
     return SGN_OK;
 }
@@ -2088,6 +2203,8 @@ void sgn_destroy(sgn_ctx* ctx) {
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     if (ctx->hflag) (void)hipHostFree(ctx->hflag);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->ev_sync) (void)hipEventDestroy(ctx->ev_sync);
+    if (ctx->hpub) (void)hipHostFree(ctx->hpub);
     for (auto& g : ctx->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -2370,7 +2487,7 @@ sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const
     }
     BatchResult* hres = static_cast<BatchResult*>(ctx->hbatch);
     HIPCHK(ctx, hipMemcpyAsync(hres, d_res, sizeof(BatchResult) * (size_t)nitems, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if ((s = wait_stream(ctx)) != SGN_OK) return s;
     bool bad = false, nc = false;
     for (int i = 0; i < nitems; ++i) {
         const BatchResult& r = hres[i];
