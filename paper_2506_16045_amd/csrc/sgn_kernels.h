@@ -740,14 +740,28 @@ __global__ void __launch_bounds__(256) k_pcg_c1(ColGeom g, const cpx<T>* __restr
 }
 
 // Stop test only (one block): closes a chunk of iterations so the host can
-// read the done flag.  Idempotent with the C1 that follows.
+// read the done flag.  Idempotent with the C1 that follows.  With pub set,
+// thread 0 then publishes the loop flags as k_publish_flags does.
+__device__ __forceinline__ void publish_flags(const SolveScal* sc, int* d, int seq) {
+    volatile int* v = d;
+    v[0] = sc->iter;
+    v[1] = sc->max_iter;
+    v[2] = sc->done;
+    v[3] = sc->converged;
+    v[4] = sc->flat;
+    v[5] = sc->status;
+    v[6] = seq;
+}
 __global__ void __launch_bounds__(256) k_pcg_check(SolveScal* __restrict__ sc, const double* __restrict__ part,
-                                                   int nb3) {
-    if (sc->done) return;
-    __shared__ double red[32];
-    __shared__ double slot[2];
-    double beta;
-    pcg_iterate_state(sc, part, nb3, red, slot, beta);
+                                                   int nb3, int* pub, int seq) {
+    if (!sc->done) {
+        __shared__ double red[32];
+        __shared__ double slot[2];
+        double beta;
+        pcg_iterate_state(sc, part, nb3, red, slot, beta);
+    }
+    // block 0 thread 0 wrote the scalars above and reads them back here
+    if (pub && blockIdx.x == 0 && threadIdx.x == 0) publish_flags(sc, pub, seq);
 }
 
 // Publish iter, max_iter, done, converged, flat, status of a solve into host
@@ -756,16 +770,7 @@ __global__ void __launch_bounds__(256) k_pcg_check(SolveScal* __restrict__ sc, c
 // each completes before the next is issued, so a host that sees seq also sees
 // the values (no cache-wide fence needed for one thread's ordered stores).
 __global__ void k_publish_flags(const SolveScal* __restrict__ sc, int* d, int seq) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        volatile int* v = d;
-        v[0] = sc->iter;
-        v[1] = sc->max_iter;
-        v[2] = sc->done;
-        v[3] = sc->converged;
-        v[4] = sc->flat;
-        v[5] = sc->status;
-        v[6] = seq;
-    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) publish_flags(sc, d, seq);
 }
 
 template <typename T, int EPC, int D, bool SEQ, int MAXT = 1024>
@@ -1233,12 +1238,27 @@ __host__ __device__ inline void coeffs_formula(double emin, double emax, double 
 }
 
 // One block: the coefficients from the per-block extremes of k_coeffs.
+// With init set, the solve's scalars are initialised here too (as k_init_scal
+// with the given tol, max_iter, inv_n, init_bb), saving a launch per solve.
 __global__ void __launch_bounds__(256) k_coeffs_finish(SolveScal* __restrict__ sc, const double* __restrict__ part,
-                                                       int nb, int flat, int kind) {
+                                                       int nb, int flat, int kind, int init, double tol,
+                                                       int max_iter, double inv_n, int init_bb) {
     __shared__ double red[5 * 16];
     double r[5];
     final_max<5>(part + PART_GEN, nb, r, red);
     if (threadIdx.x != 0) return;
+    if (init) {
+        sc->rho = sc->rho_prev = sc->alpha = sc->beta = sc->bb = sc->rr = sc->pq = sc->relres = 0.0;
+        sc->tol2 = tol * tol;
+        sc->inv_n = inv_n;
+        sc->iter = 0;
+        sc->max_iter = max_iter;
+        sc->done = 0;
+        sc->converged = 0;
+        sc->status = 0;
+        sc->first = 1;
+        sc->init_bb = init_bb;
+    }
     const double emin = -r[0], emax = r[1], smx = r[2], g2m = r[3];
     sc->red[0] = emin;
     sc->red[1] = emax;

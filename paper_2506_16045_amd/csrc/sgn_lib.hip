@@ -434,17 +434,27 @@ sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSp
 // ---------------------------------------------------------------------------
 // Coefficients (device) -> SolveScal
 // ---------------------------------------------------------------------------
-// With eta32 / gh32 set, the same pass also writes FP32 copies of eta and grad h.
+// Initial values of a solve's scalars (see k_init_scal).
+struct ScalInit {
+    double tol;
+    int max_iter;
+    double inv_n;
+    int init_bb;
+};
+
+// With eta32 / gh32 set, the same pass also writes FP32 copies of eta and grad h;
+// with init set, the finishing kernel also initialises the solve's scalars.
 sgn_status launch_coeffs(sgn_ctx* ctx, const Dims& d, const double* eta, const double* gh, int flat,
                          int kind, SolveScal* sc, double* partials, float* eta32 = nullptr,
-                         float* gh32 = nullptr) {
+                         float* gh32 = nullptr, const ScalInit* init = nullptr) {
     const int nb = flat_blocks(d.N, 256, 1024);
     if (d.D == 1)
         hipLaunchKernelGGL(k_coeffs<1>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, partials, eta32, gh32);
     else
         hipLaunchKernelGGL(k_coeffs<2>, dim3(nb), dim3(256), 0, ctx->stream, d.N, eta, gh, partials, eta32, gh32);
     hipLaunchKernelGGL(k_coeffs_finish, dim3(1), dim3(256), 0, ctx->stream, sc, (const double*)partials, nb, flat,
-                       kind);
+                       kind, init ? 1 : 0, init ? init->tol : 0.0, init ? init->max_iter : 0,
+                       init ? init->inv_n : 0.0, init ? init->init_bb : 0);
     CHECK_LAUNCH(ctx);
     return SGN_OK;
 }
@@ -706,32 +716,40 @@ sgn_status init_scal(sgn_ctx* ctx, SolveScal* sc, double tol, int max_iter, doub
     return SGN_OK;
 }
 
+// Stop test; with pub set it also publishes the loop flags (sequence number seq).
 template <typename T, int D>
-sgn_status pcg_check(PcgLaunch<T, D>& P) {
+sgn_status pcg_check(PcgLaunch<T, D>& P, int* pub = nullptr, int seq = 0) {
     hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, P.ctx->stream, P.sc, (const double*)P.partials,
-                       P.cl.g.nblocks);
+                       P.cl.g.nblocks, pub, seq);
     CHECK_LAUNCH(P.ctx);
     return SGN_OK;
 }
 
-// One chunk of `chunk` PCG iterations followed by the stop test.
+// One chunk of `chunk` PCG iterations followed by the stop test (publishing the
+// flags with sequence number seq when pub is set).
 template <typename T, int D>
-sgn_status pcg_chunk_eager(PcgLaunch<T, D>& P, int chunk) {
+sgn_status pcg_chunk_eager(PcgLaunch<T, D>& P, int chunk, int* pub = nullptr, int seq = 0) {
     for (int c = 0; c < chunk; ++c) {
         sgn_status s;
         if ((s = pcg_c1<T, D>(P, C1_UPDATE, nullptr)) != SGN_OK) return s;
         if ((s = pcg_r1<T, D>(P, true)) != SGN_OK) return s;
         if ((s = pcg_c2<T, D>(P, C2_UPDATE, nullptr, nullptr)) != SGN_OK) return s;
     }
-    return pcg_check<T, D>(P);
+    return pcg_check<T, D>(P, pub, seq);
 }
 
 // The same chunk replayed from a HIP graph (captured on the second use of a
 // configuration; the first use runs eagerly so every launch attribute is set).
+// *published: whether the chunk's stop test already published the flags with
+// the context's current sequence number (eager launches do; graphs do not).
 template <typename T, int D>
-sgn_status pcg_chunk(PcgLaunch<T, D>& P, int chunk) {
+sgn_status pcg_chunk(PcgLaunch<T, D>& P, int chunk, bool* published) {
     sgn_ctx* ctx = P.ctx;
-    if (!ctx->use_graphs || ctx->prof_on || ctx->cap_stream == nullptr) return pcg_chunk_eager<T, D>(P, chunk);
+    *published = false;
+    if (!ctx->use_graphs || ctx->prof_on || ctx->cap_stream == nullptr) {
+        *published = ctx->dpub != nullptr;
+        return pcg_chunk_eager<T, D>(P, chunk, ctx->dpub, ctx->pub_seq);
+    }
     std::vector<const void*> key = {(const void*)(uintptr_t)sizeof(T), (const void*)(uintptr_t)D,
                                     (const void*)(uintptr_t)P.d.nx, (const void*)(uintptr_t)P.d.ny,
                                     (const void*)P.sc, (const void*)P.b.H, (const void*)P.b.xh,
@@ -764,7 +782,8 @@ sgn_status pcg_chunk(PcgLaunch<T, D>& P, int chunk) {
                 (void)hipGetLastError();
                 g.exec = nullptr;
                 ctx->use_graphs = false;   // fall back to eager launches for the context's life
-                return pcg_chunk_eager<T, D>(P, chunk);
+                *published = ctx->dpub != nullptr;
+                return pcg_chunk_eager<T, D>(P, chunk, ctx->dpub, ctx->pub_seq);
             }
             HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
             return SGN_OK;
@@ -775,7 +794,8 @@ sgn_status pcg_chunk(PcgLaunch<T, D>& P, int chunk) {
         ctx->graphs.erase(ctx->graphs.begin());
     }
     ctx->graphs.push_back({key, chunk, nullptr});
-    return pcg_chunk_eager<T, D>(P, chunk);
+    *published = ctx->dpub != nullptr;
+    return pcg_chunk_eager<T, D>(P, chunk, ctx->dpub, ctx->pub_seq);
 }
 
 // Integer state of a solve after its last readback.
@@ -784,16 +804,22 @@ struct LoopOut {
 };
 
 // Read iter, max_iter, done, converged, flat, status of a solve (synchronises the stream).
-// Enqueue the publication of iter, max_iter, done, converged, flat, status and
-// mark it.
-sgn_status issue_loop_readback(sgn_ctx* ctx, const SolveScal* sc) {
+// Next sequence number of the published loop flags.
+void next_pub_seq(sgn_ctx* ctx) { ctx->pub_seq = ctx->pub_seq == 0x7fffffff ? 1 : ctx->pub_seq + 1; }
+
+// Enqueue the publication of iter, max_iter, done, converged, flat, status
+// (unless the last stop test already published them under the current sequence
+// number) and mark it.
+sgn_status issue_loop_readback(sgn_ctx* ctx, const SolveScal* sc, bool published = false) {
     if (ctx->dpub) {
-        ctx->pub_seq = ctx->pub_seq == 0x7fffffff ? 1 : ctx->pub_seq + 1;
-        hipLaunchKernelGGL(k_publish_flags, dim3(1), dim3(64), 0, ctx->stream, sc, ctx->dpub, ctx->pub_seq);
-        CHECK_LAUNCH(ctx);
-    } else {
-        HIPCHK(ctx, hipMemcpyAsync(ctx->hflag, &sc->iter, 6 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        if (!published) {
+            next_pub_seq(ctx);
+            hipLaunchKernelGGL(k_publish_flags, dim3(1), dim3(64), 0, ctx->stream, sc, ctx->dpub, ctx->pub_seq);
+            CHECK_LAUNCH(ctx);
+        }
+        return SGN_OK;
     }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->hflag, &sc->iter, 6 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     if (ctx->ev_sync) HIPCHK(ctx, hipEventRecord(ctx->ev_sync, ctx->stream));
     return SGN_OK;
 }
@@ -802,13 +828,13 @@ sgn_status issue_loop_readback(sgn_ctx* ctx, const SolveScal* sc) {
 sgn_status wait_loop_readback(sgn_ctx* ctx, LoopOut* out) {
     const int* f = ctx->hflag;
     if (ctx->dpub) {
-        // poll the published sequence number; the event (recorded behind the
-        // publishing kernel) bounds the wait if the value is somehow not seen
+        // poll the published sequence number; a drained stream bounds the wait if
+        // the value is somehow not seen
         int* h = ctx->hpub;
         for (long spins = 0;; ++spins) {
             if (__atomic_load_n(&h[6], __ATOMIC_ACQUIRE) == ctx->pub_seq) break;
-            if ((spins & 1023) == 1023) {
-                const hipError_t e = hipEventQuery(ctx->ev_sync);
+            if ((spins & 4095) == 4095) {
+                const hipError_t e = hipStreamQuery(ctx->stream);
                 if (e == hipSuccess) {
                     if (__atomic_load_n(&h[6], __ATOMIC_ACQUIRE) == ctx->pub_seq) break;
                     return fail(ctx, SGN_EDEVICE, "published solver flags not visible to the host");
@@ -861,9 +887,11 @@ sgn_status pcg_loop(PcgLaunch<T, D>& P, int max_iter, int check_every, LoopOut* 
     sgn_status s;
     while (it < max_iter) {
         chunk = std::max(1, std::min(chunk, max_iter - it));
-        if ((s = pcg_chunk<T, D>(P, chunk)) != SGN_OK) return s;
+        if (P.ctx->dpub) next_pub_seq(P.ctx);
+        bool published = false;
+        if ((s = pcg_chunk<T, D>(P, chunk, &published)) != SGN_OK) return s;
         it += chunk;
-        if ((s = issue_loop_readback(P.ctx, P.sc)) != SGN_OK) return s;
+        if ((s = issue_loop_readback(P.ctx, P.sc, published)) != SGN_OK) return s;
         if constexpr (!std::is_same<Tail, std::nullptr_t>::value) {
             if (!rounds) {
                 if ((s = tail(false)) != SGN_OK) return s;
@@ -900,10 +928,15 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     P.eta = eta;
     P.gh = gh;
     sgn_status s;
-    // without a guess r_0 = b, so ||b||^2 is the first r.r (init_bb)
-    if ((s = init_scal(ctx, P.sc, o.tol, o.max_iter, d.inv_n, coeffs, o.x0_is_guess ? 0 : 1)) != SGN_OK) return s;
-    if (!coeffs) {
-        if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials)) != SGN_OK) return s;
+    // without a guess r_0 = b, so ||b||^2 is the first r.r (init_bb); computed
+    // coefficients initialise the scalars in their finishing kernel
+    if (coeffs) {
+        if ((s = init_scal(ctx, P.sc, o.tol, o.max_iter, d.inv_n, coeffs, o.x0_is_guess ? 0 : 1)) != SGN_OK) return s;
+    } else {
+        const ScalInit in{o.tol, o.max_iter, d.inv_n, o.x0_is_guess ? 0 : 1};
+        if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials, nullptr, nullptr, &in)) !=
+            SGN_OK)
+            return s;
     }
     if ((s = pcg_start<D>(P, rhs, u, o.x0_is_guess != 0, nullptr)) != SGN_OK) return s;
     // u = IFFT(x_hat) (and the stepper's offset record); stored a second time after
