@@ -15,7 +15,8 @@ Modules:
                (Eq:FlatbathCoeff, Eq:Optcoeff, Eq:Optcoeffb)
   krylov       textbook PCG (section 3.2) and restarted right-preconditioned GMRES
   rhs          the constraint-form right-hand side f(w, p) with forcing F
-               (Eq:DSWEcf, Def:bigF, Eq:DAE_DSWE)
+               (Eq:DSWEcf, Def:bigF, Eq:DAE_DSWE), and its de-aliased form
+               on a zero-padded grid (subsec:dswe_1d, remark on aliasing)
   stepping     RK4 (Eq:ERK), Adams-Bashforth 2-4 (Eq:AB, Table LMMCoeffs) and
                the linearly implicit SBDF2 scheme (Eq:MM)
   diagnostics  mass, energy (Remark 2.1), the G-norm error (def:discrete_Gerr)

@@ -18,6 +18,8 @@ u_t.grad h in F of Eq:defGF.  Every derivative is the spectral one
 """
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 
 from . import spectral as sp
@@ -97,3 +99,59 @@ def momentum_rhs(eta, u, h, grad_h, g):
     return (-eta[None] * adv - eta[None] * sp.grad(zeta, g)
             + sp.grad(eta ** 3 / 3.0 * P + eta ** 2 / 2.0 * Q, g)
             - (eta * (eta / 2.0 * P + Q))[None] * grad_h)
+
+
+# ---------------------------------------------------------------------------
+# De-aliased right-hand side (subsec:dswe_1d, remark on aliasing after Test 2:
+# zeros are padded onto the high wavenumbers before the nonlinear terms are
+# formed).  Reading: the inputs are interpolated onto a grid `factor` times as
+# fine per axis by zero-padding their spectra, f(w, p) is evaluated there with
+# the fine grid's spectral derivatives, and the result is truncated back to the
+# modes of the original grid.  On both transfers only the modes with
+# |m| < n/2 of the coarser grid are kept: its Nyquist modes, which the spectral
+# derivative already treats as carrying no wavenumber (section 6.1), are set
+# to zero.
+# ---------------------------------------------------------------------------
+
+def _axis_modes(n_src, n_dst):
+    """(source index, destination index) of the signed modes kept on one axis."""
+    n_min = min(n_src, n_dst)
+    if n_min == 1:
+        return np.array([0]), np.array([0])
+    m = np.arange(-(n_min // 2) + 1, n_min // 2)   # |m| < n_min / 2
+    return m % n_src, m % n_dst
+
+
+def resample(f, g_src, g_dst):
+    """Spectral interpolation (finer destination) or truncation (coarser) of a
+    real periodic scalar field between two grids of the same domain, keeping
+    the amplitude of every retained Fourier mode."""
+    F = np.fft.fftn(f) / f.size
+    if g_src.d == 1:
+        si, di = _axis_modes(g_src.nx, g_dst.nx)
+        G = np.zeros(g_dst.nx, dtype=complex)
+        G[di] = F[si]
+    else:
+        sx, dxi = _axis_modes(g_src.nx, g_dst.nx)
+        sy, dyi = _axis_modes(g_src.ny, g_dst.ny)
+        G = np.zeros((g_dst.ny, g_dst.nx), dtype=complex)
+        G[np.ix_(dyi, dxi)] = F[np.ix_(sy, sx)]
+    return np.real(np.fft.ifftn(G) * G.size)
+
+
+def fine_grid(g, factor=2):
+    """The same domain with `factor` times as many points per axis."""
+    if g.d == 1:
+        return dataclasses.replace(g, nx=g.nx * factor)
+    return dataclasses.replace(g, nx=g.nx * factor, ny=g.ny * factor)
+
+
+def rhs_dealiased(eta, u, h, g, factor=2):
+    """(eta_t, U_t) with the nonlinear terms formed on the padded grid."""
+    gf = fine_grid(g, factor)
+    eta_f = resample(eta, g, gf)
+    u_f = np.stack([resample(c, g, gf) for c in u])
+    h_f = resample(h, g, gf)
+    grad_h_f = sp.grad(h_f, gf)
+    e_t, U_t = rhs(eta_f, u_f, h_f, grad_h_f, gf)
+    return resample(e_t, gf, g), np.stack([resample(c, gf, g) for c in U_t])

@@ -28,7 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import krylov, operators as op
-from .rhs import rhs
+from .rhs import rhs, rhs_dealiased
 
 RK4_A = ((), (0.5,), (0.0, 0.5), (0.0, 0.0, 1.0))
 RK4_B = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
@@ -102,13 +102,17 @@ class Problem:
     max_iter: int = 1000
     iters: list = field(default_factory=list)
     hist: GuessHistory = field(default_factory=GuessHistory)
+    dealias: int = 1   # > 1: the right-hand side is the de-aliased one, padded by this factor
 
     @classmethod
-    def from_h(cls, g, h, tol=1e-12, max_iter=1000, guess="extrapolate"):
+    def from_h(cls, g, h, tol=1e-12, max_iter=1000, guess="extrapolate", dealias=1):
         gh, fl = op.bathy_gradient(h, g)
-        return cls(g, np.asarray(h, dtype=np.float64), gh, fl, tol, max_iter, hist=GuessHistory(guess))
+        return cls(g, np.asarray(h, dtype=np.float64), gh, fl, tol, max_iter, hist=GuessHistory(guess),
+                   dealias=dealias)
 
     def f(self, eta, u):
+        if self.dealias > 1:
+            return rhs_dealiased(eta, u, self.h, self.g, self.dealias)
         return rhs(eta, u, self.h, self.grad_h, self.g)
 
     def G(self, eta, u):
