@@ -292,6 +292,37 @@ sgn_status sgn_step_linimp(sgn_ctx *ctx, sgn_state *state, double dt, int32_t ns
                            const sgn_coeffs *fixed, const sgn_solve_opts *opts,
                            sgn_step_info *info);
 
+/* ---- de-aliased right-hand side ------------------------------------------
+ * The nonlinear terms of f(w, p) formed on a grid padded with zero modes
+ * (subsec:dswe_1d, the remark on aliasing after Test 2, which reports that
+ * padding the high wavenumbers with zeros helps long runs of large solitary
+ * waves).  eta, u and grad h are interpolated onto the grid twice as fine per
+ * axis (same domain) by zero-padding their spectra, f is evaluated there by the
+ * same kernels as sgn_rhs, and eta_t, U_t are truncated back to the modes of
+ * the original grid.  Both transfers keep the modes |m| < n/2 of the original
+ * axis and drop its Nyquist mode (which the spectral derivative already maps to
+ * zero).  Always FP64.  Grids: 1D nx <= 8192, 2D nx <= 2048 and ny <= 1024. */
+
+/* Bytes of device workspace for the two calls below (fields on the padded grid,
+ * the transfer spectra and the padded grid's right-hand-side workspace); 0 for
+ * a grid that is unsupported or too large to pad. */
+size_t sgn_dealias_workspace_bytes(const sgn_grid *grid);
+
+/* The de-aliased eta_t, U_t; arguments as sgn_rhs, with d_dws of
+ * sgn_dealias_workspace_bytes() bytes (contents not kept between calls).
+ * SGN_EUNSUPPORTED for a grid above the limits. */
+sgn_status sgn_rhs_dealiased(sgn_ctx *ctx, const sgn_grid *grid, const double *d_eta,
+                             const double *d_h, const double *d_grad_h, const double *d_u,
+                             double *d_eta_t, double *d_U_t, void *d_dws);
+
+/* Make every later step call of the state use the de-aliased right-hand side,
+ * with d_dws (sgn_dealias_workspace_bytes() bytes, owned by the caller) bound
+ * to the state until it is destroyed or this is called again; d_dws = NULL goes
+ * back to the plain form.  Either way a multistep (Adams-Bashforth or SBDF2)
+ * history is cleared, since it holds right-hand sides of the form used so far.
+ * The padded grad h is computed here, once. */
+sgn_status sgn_state_set_dealias(sgn_ctx *ctx, sgn_state *state, void *d_dws);
+
 /* ---- served execution --------------------------------------------------
  * A request server on one device.  Requests (constraint solves and RK4
  * time-steps of 1D or 2D grids) are submitted from any host thread with host

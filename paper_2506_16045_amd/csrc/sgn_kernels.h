@@ -1119,6 +1119,40 @@ __global__ void __launch_bounds__(256) k_cols_from_S(ColGeom g, const cpx<T>* __
     col_store<T, EPC, D>(g, ct, v, dsts, true, twm);
 }
 
+// Spectral resampling between two grids of one domain, column part (the
+// de-aliased right-hand side, subsec:dswe_1d): column kx of the destination
+// takes the source's S-layout modes (source column length ny_src) for
+// kx < kx_keep and signed ky mode |m| < m_keep, zero elsewhere, times scale,
+// then runs the inverse y-FFT of the destination length; the result is the
+// destination's H layout.  kx_keep and m_keep are half the smaller grid's
+// lengths (m_keep = 1 in 1D), so the smaller grid's Nyquist modes are dropped.
+template <typename T, int EPC, int NF>
+__global__ void __launch_bounds__(256) k_cols_resample(ColGeom g, const cpx<T>* __restrict__ tw,
+                                                        PtrList<const cpx<T>, MAXF> src, int ny_src,
+                                                        PtrList<cpx<T>, MAXF> dst, int kx_keep, int m_keep,
+                                                        T scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, NF));
+    const ColThread<T> ct = col_thread<T>(g, lds);
+    const bool col_kept = ct.valid && ct.kx < kx_keep;
+    cpx<T> v[NF][EPC];
+    cpx<T>* dsts[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        dsts[f] = dst.p[f];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+            const int m = (g.ny == 1) ? 0 : (j < g.ny / 2 ? j : j - g.ny);
+            const bool keep = col_kept && j < g.ny && m < m_keep && -m < m_keep;
+            const int js = m < 0 ? m + ny_src : m;
+            v[f][e] = keep ? scale * src.p[f][(size_t)ct.kx * ny_src + js] : C<T>(0, 0);
+        }
+    }
+    col_store<T, EPC, NF>(g, ct, v, dsts, true, twm);
+}
+
 // Initialise the scalars of a solve on the device (no host round trip).  With
 // have_coeffs the preconditioner coefficients are given; otherwise they are
 // filled later by k_coeffs_finish or copied from another solve.

@@ -179,14 +179,15 @@ struct ColLaunch {
     int threads;
     size_t lds;
 };
+// epc: column entries per thread (4; 8 for the columns of 2048 on a padded grid)
 template <typename T>
-ColLaunch col_launch(int nx, int ny) {
+ColLaunch col_launch(int nx, int ny, int epc = 4) {
     ColLaunch L;
     ColGeom& g = L.g;
     g.nx = nx;
     g.ny = ny;
     g.nxh = nx / 2 + 1;
-    g.TPC = ny / 4 > 0 ? ny / 4 : 1;
+    g.TPC = ny / epc > 0 ? ny / epc : 1;
     g.Cb = 256 / g.TPC > 0 ? 256 / g.TPC : 1;
     g.nblocks = (g.nxh + g.Cb - 1) / g.Cb;
     L.threads = g.Cb * g.TPC;
@@ -194,6 +195,10 @@ ColLaunch col_launch(int nx, int ny) {
     if (L.lds < 16) L.lds = 16;
     return L;
 }
+
+// Column entries per thread: columns up to 1024 use 4 (the grids the solvers
+// take); the padded grid of the de-aliased right-hand side has columns of 2048.
+inline int col_epc(int ny) { return ny > 1024 ? 8 : 4; }
 
 // LDS bytes of a row / column kernel transforming NF fields at a time (data,
 // then the staged twiddle table when the transform length allows it).
@@ -418,7 +423,8 @@ sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSp
     }
     int maxi = 0;
     for (int k = 0; k < J.n; ++k) maxi = std::max(maxi, J.j[k].ni);
-    ColLaunch L = col_launch<double>(d.nx, d.ny);
+    const int epc = col_epc(d.ny);
+    ColLaunch L = col_launch<double>(d.nx, d.ny, epc);
     const size_t lds = col_lds_bytes<double>(L.g, 1);
     auto launch = [&](auto k) -> sgn_status {
         HIPCHK(ctx, allow_lds(k, lds));
@@ -428,6 +434,10 @@ sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSp
         return SGN_OK;
     };
     // registers for the inputs are sized by the widest job
+    if (epc == 8) {
+        if (maxi > 3) return fail(ctx, SGN_EINVAL, "cols_lin_jobs: columns of 2048 take at most 3 inputs");
+        return launch(k_cols_lin_jobs<double, 8, 3>);
+    }
     return maxi <= 3 ? launch(k_cols_lin_jobs<double, 4, 3>) : launch(k_cols_lin_jobs<double, 4, 4>);
 }
 
@@ -1767,6 +1777,164 @@ sgn_status rhs_dispatch(sgn_ctx* ctx, const Dims& d, const double* eta, const do
     return d.D == 1 ? rhs_impl<1>(ctx, d, eta, gh, u, eta_t, U_t, ws) : rhs_impl<2>(ctx, d, eta, gh, u, eta_t, U_t, ws);
 }
 
+// ---------------------------------------------------------------------------
+// De-aliased right-hand side (subsec:dswe_1d, remark on aliasing after Test 2):
+// eta, u and grad h are interpolated onto the grid twice as fine per axis by
+// zero-padding their spectra, f(w, p) is formed there by the same kernels, and
+// eta_t, U_t are truncated back to the modes of the original grid.  Both
+// transfers keep the modes |m| < n/2 of the original grid (its Nyquist modes,
+// to which D gives no wavenumber, are dropped), so padding grad h equals
+// differentiating the padded h.
+// ---------------------------------------------------------------------------
+constexpr int DEALIAS_FACTOR = 2;
+constexpr int DEALIAS_MAX_1D = 8192;                       // padded: 16384
+constexpr int DEALIAS_MAX_NX = 2048, DEALIAS_MAX_NY = 1024; // padded: 4096 x 2048
+
+bool dealias_supported(const Dims& d) {
+    return d.D == 1 ? d.nx <= DEALIAS_MAX_1D : (d.nx <= DEALIAS_MAX_NX && d.ny <= DEALIAS_MAX_NY);
+}
+
+Dims fine_dims(const Dims& d) {
+    Dims f = d;
+    f.nx = d.nx * DEALIAS_FACTOR;
+    f.ny = d.D == 2 ? d.ny * DEALIAS_FACTOR : 1;
+    f.N = (size_t)f.nx * f.ny;
+    f.NS = (size_t)(f.nx / 2 + 1) * f.ny;
+    f.inv_n = 1.0 / (double)f.N;
+    return f;
+}
+
+size_t rhs_workspace_bytes(const Dims& d) {
+    Carve cv(nullptr);
+    carve_common(cv);
+    if (d.D == 1 && d.nx <= BATCH_NMAX) {
+        cv.take<cpx<double>>((size_t)5 * (d.nx / 2 + 1));
+        cv.take<double>((size_t)5 * d.nx);
+    } else {
+        carve_rhs(cv, d);
+    }
+    return cv.off + 256;
+}
+
+struct DealiasBufs {
+    double *eta_f, *u_f, *gh_f, *et_f, *Ut_f;  // fields on the padded grid
+    cpx<double>*Hf, *Sf, *Hc, *Sc;              // transfer spectra (1 + D fields each)
+    void* ws_f;                                 // the padded grid's right-hand-side workspace
+};
+size_t carve_dealias(Carve& cv, const Dims& d, DealiasBufs* b) {
+    const Dims f = fine_dims(d);
+    const size_t nf = (size_t)(1 + d.D);
+    DealiasBufs t;
+    t.eta_f = cv.take<double>(nf * f.N);   // eta_f, u_f adjacent (padded as one group)
+    t.u_f = t.eta_f ? t.eta_f + f.N : nullptr;
+    t.gh_f = cv.take<double>((size_t)d.D * f.N);
+    t.et_f = cv.take<double>(nf * f.N);    // et_f, Ut_f adjacent (truncated as one group)
+    t.Ut_f = t.et_f ? t.et_f + f.N : nullptr;
+    t.Hf = cv.take<cpx<double>>(nf * f.NS);
+    t.Sf = cv.take<cpx<double>>(nf * f.NS);
+    t.Hc = cv.take<cpx<double>>(nf * d.NS);
+    t.Sc = cv.take<cpx<double>>(nf * d.NS);
+    t.ws_f = cv.take<unsigned char>(rhs_workspace_bytes(f));
+    if (b) *b = t;
+    return cv.off;
+}
+
+// y-FFT of nf H fields (stride NS) into S fields, columns of the grid d.
+template <int NF>
+sgn_status cols_to_S_n(sgn_ctx* ctx, const Dims& d, const cpx<double>* H, cpx<double>* S) {
+    ProfScope ps(ctx, SGN_KERNEL_COLS);
+    const int epc = col_epc(d.ny);
+    const ColLaunch L = col_launch<double>(d.nx, d.ny, epc);
+    const size_t lds = col_lds_bytes<double>(L.g, NF);
+    auto launch = [&](auto k) -> sgn_status {
+        HIPCHK(ctx, allow_lds(k, lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, ctx->tw64, H, d.NS, S);
+        CHECK_LAUNCH(ctx);
+        return SGN_OK;
+    };
+    return epc == 8 ? launch(k_cols_to_S<double, 8, NF>) : launch(k_cols_to_S<double, 4, NF>);
+}
+
+template <int NF>
+sgn_status cols_resample_n(sgn_ctx* ctx, const Dims& s, const Dims& t, const cpx<double>* S, cpx<double>* Ht) {
+    ProfScope ps(ctx, SGN_KERNEL_COLS);
+    const int epc = col_epc(t.ny);
+    const ColLaunch L = col_launch<double>(t.nx, t.ny, epc);
+    const size_t lds = col_lds_bytes<double>(L.g, NF);
+    PtrList<const cpx<double>, MAXF> src{};
+    PtrList<cpx<double>, MAXF> dst{};
+    src.n = dst.n = NF;
+    for (int f = 0; f < NF; ++f) {
+        src.p[f] = S + f * s.NS;
+        dst.p[f] = Ht + f * t.NS;
+    }
+    const int kx_keep = std::min(s.nx, t.nx) / 2;
+    const int m_keep = s.D == 1 ? 1 : std::min(s.ny, t.ny) / 2;
+    auto launch = [&](auto k) -> sgn_status {
+        HIPCHK(ctx, allow_lds(k, lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, ctx->stream, L.g, ctx->tw64, src, s.ny, dst,
+                           kx_keep, m_keep, s.inv_n);
+        CHECK_LAUNCH(ctx);
+        return SGN_OK;
+    };
+    return epc == 8 ? launch(k_cols_resample<double, 8, NF>) : launch(k_cols_resample<double, 4, NF>);
+}
+
+// Spectral resampling of nf physical fields (stride s.N) from grid s to grid t
+// (same domain, same dimension): rows forward on s, y-FFT on s (2D), mode
+// transfer with the inverse y-FFT on t, rows inverse on t.
+sgn_status resample_fields(sgn_ctx* ctx, const Dims& s, const Dims& t, const double* src, int nf, double* dst,
+                           cpx<double>* Hs, cpx<double>* Ss, cpx<double>* Ht) {
+    if (nf < 1 || nf > 3) return fail(ctx, SGN_EINVAL, "resample: 1 to 3 fields");
+    std::vector<const double*> a;
+    std::vector<cpx<double>*> h;
+    std::vector<const cpx<double>*> ht;
+    std::vector<double*> o;
+    for (int f = 0; f < nf; ++f) {
+        a.push_back(src + f * s.N);
+        h.push_back(Hs + f * s.NS);
+        ht.push_back(Ht + f * t.NS);
+        o.push_back(dst + f * t.N);
+    }
+    sgn_status st;
+    if ((st = rows_fwd<double, double>(ctx, s, a, h)) != SGN_OK) return st;
+    const cpx<double>* S = Hs;   // 1D: the column transform is the identity
+    if (s.D == 2) {
+        st = nf == 1 ? cols_to_S_n<1>(ctx, s, Hs, Ss) : nf == 2 ? cols_to_S_n<2>(ctx, s, Hs, Ss)
+                                                           : cols_to_S_n<3>(ctx, s, Hs, Ss);
+        if (st != SGN_OK) return st;
+        S = Ss;
+    }
+    st = nf == 1 ? cols_resample_n<1>(ctx, s, t, S, Ht) : nf == 2 ? cols_resample_n<2>(ctx, s, t, S, Ht)
+                                                             : cols_resample_n<3>(ctx, s, t, S, Ht);
+    if (st != SGN_OK) return st;
+    return rows_inv<double, double>(ctx, t, ht, o);
+}
+
+// grad h on the padded grid (once per bathymetry).
+sgn_status dealias_pad_gh(sgn_ctx* ctx, const Dims& d, const double* gh, const DealiasBufs& b) {
+    return resample_fields(ctx, d, fine_dims(d), gh, d.D, b.gh_f, b.Hc, b.Sc, b.Hf);
+}
+
+// (eta_t, U_t) on grid d from eta, u on d and grad h already on the padded grid.
+sgn_status rhs_dealiased(sgn_ctx* ctx, const Dims& d, const double* eta, const double* u, double* eta_t,
+                         double* U_t, const DealiasBufs& b) {
+    const Dims f = fine_dims(d);
+    sgn_status s;
+    // eta and u are adjacent on the padded grid only: pad them as one group when
+    // they are adjacent on the original grid as well
+    if (u == eta + d.N) {
+        if ((s = resample_fields(ctx, d, f, eta, 1 + d.D, b.eta_f, b.Hc, b.Sc, b.Hf)) != SGN_OK) return s;
+    } else {
+        if ((s = resample_fields(ctx, d, f, eta, 1, b.eta_f, b.Hc, b.Sc, b.Hf)) != SGN_OK) return s;
+        if ((s = resample_fields(ctx, d, f, u, d.D, b.u_f, b.Hc, b.Sc, b.Hf)) != SGN_OK) return s;
+    }
+    if ((s = rhs_dispatch(ctx, f, b.eta_f, b.gh_f, b.u_f, b.et_f, b.Ut_f, b.ws_f)) != SGN_OK) return s;
+    if (U_t == eta_t + d.N) return resample_fields(ctx, f, d, b.et_f, 1 + d.D, eta_t, b.Hf, b.Sf, b.Hc);
+    if ((s = resample_fields(ctx, f, d, b.et_f, 1, eta_t, b.Hf, b.Sf, b.Hc)) != SGN_OK) return s;
+    return resample_fields(ctx, f, d, b.Ut_f, d.D, U_t, b.Hf, b.Sf, b.Hc);
+}
+
 
 // ---------------------------------------------------------------------------
 // Time-stepping state (section 5)
@@ -1842,9 +2010,18 @@ struct sgn_state {
     // chunk of the next one, kept with the state so that a run's launches (and with
     // them its results) do not depend on what else its context solved before
     int last_iters[GUESS_SLOTS][2] = {};
+    // de-aliased right-hand side (sgn_state_set_dealias): buffers in the caller's workspace
+    int dealias = 0;
+    DealiasBufs dl{};
 };
 
 namespace {
+
+// f(w, p) of a state: the plain or the de-aliased form.
+sgn_status state_rhs(sgn_state* st, const double* eta, const double* u, double* fe, double* fU) {
+    if (st->dealias) return rhs_dealiased(st->ctx, st->d, eta, u, fe, fU, st->dl);
+    return rhs_dispatch(st->ctx, st->d, eta, st->gh, u, fe, fU, st->ws);
+}
 
 sgn_status copy_d(sgn_ctx* ctx, double* dst, const double* src, size_t n) {
     HIPCHK(ctx, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
@@ -1992,7 +2169,7 @@ sgn_status rk4_one(sgn_state* st, double dt, const sgn_solve_opts& o, sgn_step_i
     static const double a[3] = {0.5, 0.5, 1.0};
     static const double w[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     sgn_status s;
-    if (!have_f1 && (s = rhs_dispatch(ctx, d, st->eta, st->gh, st->u, b.rk_fe[0], b.rk_fU[0], st->ws)) != SGN_OK)
+    if (!have_f1 && (s = state_rhs(st, st->eta, st->u, b.rk_fe[0], b.rk_fU[0])) != SGN_OK)
         return s;
     if ((s = copy_d(ctx, b.u_s, st->u, DN)) != SGN_OK) return s;
     for (int i = 1; i < 4; ++i) {
@@ -2000,7 +2177,7 @@ sgn_status rk4_one(sgn_state* st, double dt, const sgn_solve_opts& o, sgn_step_i
                                     {b.U_s, st->U, dt, {b.rk_fU[i - 1]}, {a[i - 1]}, DN, nullptr}})) != SGN_OK)
             return s;
         if ((s = stage_solve(st, GUESS_RK2 + i - 1, b.eta_s, b.U_s, b.u_s, o, acc)) != SGN_OK) return s;
-        if ((s = rhs_dispatch(ctx, d, b.eta_s, st->gh, b.u_s, b.rk_fe[i], b.rk_fU[i], st->ws)) != SGN_OK) return s;
+        if ((s = state_rhs(st, b.eta_s, b.u_s, b.rk_fe[i], b.rk_fU[i])) != SGN_OK) return s;
     }
     if ((s = lincomb_jobs(ctx, {{st->eta, st->eta, dt, {b.rk_fe[0], b.rk_fe[1], b.rk_fe[2], b.rk_fe[3]},
                                  {w[0], w[1], w[2], w[3]}, N, nullptr},
@@ -2114,7 +2291,7 @@ sgn_status sbdf2_steps(sgn_state* st, double dt, int nsteps, const sgn_coeffs* f
         }
         st->kind = 2;
         st->hist_dt = dt;
-        if ((s = rhs_dispatch(ctx, d, st->eta, st->gh, st->u, b.fe_prev, b.fU_prev, st->ws)) != SGN_OK) return s;
+        if ((s = state_rhs(st, st->eta, st->u, b.fe_prev, b.fU_prev)) != SGN_OK) return s;
         if ((s = to_S_d<D>(ctx, d, st->u, b.Hs, b.uh)) != SGN_OK) return s;
         if ((s = sbdf2_R<D>(st, b.R_prev)) != SGN_OK) return s;
         if ((s = copy_d(ctx, b.eta_prev, st->eta, N)) != SGN_OK) return s;
@@ -2125,7 +2302,7 @@ sgn_status sbdf2_steps(sgn_state* st, double dt, int nsteps, const sgn_coeffs* f
     }
     for (int n = 0; n < nsteps; ++n) {
         // level n+1 is the state: f_{n+1}, R_{n+1}
-        if ((s = rhs_dispatch(ctx, d, st->eta, st->gh, st->u, b.rk_fe[0], b.rk_fU[0], st->ws)) != SGN_OK) return s;
+        if ((s = state_rhs(st, st->eta, st->u, b.rk_fe[0], b.rk_fU[0])) != SGN_OK) return s;
         if ((s = sbdf2_R<D>(st, b.R_cur)) != SGN_OK) return s;
         // w_{n+2} = (-a0 w_n - a1 w_{n+1} + dt (b0 f_n + b1 f_{n+1})) / a2
         if ((s = lincomb(ctx, N, nullptr, 1.0, {b.eta_prev, st->eta, b.fe_prev, b.rk_fe[0]},
@@ -2552,6 +2729,44 @@ sgn_status sgn_rhs(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const 
     return rhs_dispatch(ctx, d, eta, grad_h, u, eta_t, U_t, ws);
 }
 
+size_t sgn_dealias_workspace_bytes(const sgn_grid* grid) {
+    Dims d;
+    if (check_grid(nullptr, grid, &d) != SGN_OK || !dealias_supported(d)) return 0;
+    Carve cv(nullptr);
+    return carve_dealias(cv, d, nullptr) + 256;
+}
+
+sgn_status sgn_rhs_dealiased(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const double* h,
+                             const double* grad_h, const double* u, double* eta_t, double* U_t, void* dws) {
+    if (!ctx) return SGN_EINVAL;
+    Dims d;
+    sgn_status s = check_grid(ctx, grid, &d);
+    if (s != SGN_OK) return s;
+    if (!dealias_supported(d)) return fail(ctx, SGN_EUNSUPPORTED, "de-aliasing: grid too large to pad");
+    if (!eta || !h || !grad_h || !u || !eta_t || !U_t || !dws) return fail(ctx, SGN_EINVAL, "null pointer");
+    DealiasBufs b;
+    Carve cv(dws);
+    carve_dealias(cv, d, &b);
+    if ((s = dealias_pad_gh(ctx, d, grad_h, b)) != SGN_OK) return s;
+    return rhs_dealiased(ctx, d, eta, u, eta_t, U_t, b);
+}
+
+sgn_status sgn_state_set_dealias(sgn_ctx* ctx, sgn_state* st, void* dws) {
+    if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (dws && !dealias_supported(st->d)) return fail(ctx, SGN_EUNSUPPORTED, "de-aliasing: grid too large to pad");
+    // a multistep history holds right-hand sides of the form used so far
+    st->kind = 0;
+    if (!dws) {
+        st->dealias = 0;
+        return SGN_OK;
+    }
+    Carve cv(dws);
+    carve_dealias(cv, st->d, &st->dl);
+    sgn_status s = dealias_pad_gh(ctx, st->d, st->gh, st->dl);
+    st->dealias = s == SGN_OK ? 1 : 0;
+    return s;
+}
+
 size_t sgn_state_workspace_bytes(const sgn_grid* grid, int32_t precision) {
     (void)precision;
     Dims d;
@@ -2639,7 +2854,7 @@ sgn_status sgn_step_ab(sgn_ctx* ctx, sgn_state* st, int32_t order, double dt, in
     sgn_status s = SGN_OK;
     for (int n = 0; n < nsteps; ++n) {
         const int slot = st->ab_head & 3;
-        if ((s = rhs_dispatch(ctx, d, st->eta, st->gh, st->u, b.ab_fe[slot], b.ab_fU[slot], st->ws)) != SGN_OK) break;
+        if ((s = state_rhs(st, st->eta, st->u, b.ab_fe[slot], b.ab_fU[slot])) != SGN_OK) break;
         st->ab_head += 1;
         if (st->ab_count < order) st->ab_count += 1;
         if (st->ab_count < order) {

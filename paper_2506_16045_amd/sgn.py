@@ -113,6 +113,9 @@ _SIGS = {
     "sgn_krylov_solve": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, ctypes.POINTER(Coeffs),
                               ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
     "sgn_rhs": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P]),
+    "sgn_dealias_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid)]),
+    "sgn_rhs_dealiased": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P]),
+    "sgn_state_set_dealias": (_S, [_P, _P, _P]),
     "sgn_batch_workspace_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I]),
     "sgn_request_footprint": (ctypes.c_size_t, [ctypes.POINTER(Request)]),
     "sgn_server_create": (_S, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ServerOpts)]),
@@ -166,6 +169,11 @@ def gmres_workspace_bytes(g, restart: int = 30) -> int:
 def batch_workspace_bytes(sizes, precision: int = FP64) -> int:
     n = (_I * len(sizes))(*[int(v) for v in sizes])
     return int(_lib.sgn_batch_workspace_bytes(len(sizes), n, precision))
+
+
+def dealias_workspace_bytes(g) -> int:
+    """Workspace of the de-aliased right-hand side; 0 if the grid is too large to pad."""
+    return int(_lib.sgn_dealias_workspace_bytes(ctypes.byref(make_grid(g))))
 
 
 def state_workspace_bytes(g, precision: int = FP64) -> int:
@@ -397,6 +405,22 @@ class Context:
                                  _ptr(U_t, _vector_shape(g), "U_t"), _P(self.workspace(g).data_ptr())))
         return eta_t, U_t
 
+    def rhs_dealiased(self, g, eta, h, grad_h, u, eta_t=None, U_t=None):
+        """(eta_t, U_t) = f(w, p) formed on the zero-padded grid (sgn_rhs_dealiased)."""
+        self._sync_stream()
+        grid = make_grid(g)
+        if eta_t is None:
+            eta_t = torch.empty(_scalar_shape(g), dtype=torch.float64, device=self.device)
+        if U_t is None:
+            U_t = torch.empty(_vector_shape(g), dtype=torch.float64, device=self.device)
+        # at least 256 bytes, so that an unsupported grid reaches the library's own check
+        ws = torch.empty(max(dealias_workspace_bytes(g), 256), dtype=torch.uint8, device=self.device)
+        self._check(_lib.sgn_rhs_dealiased(self._h, ctypes.byref(grid), _ptr(eta, _scalar_shape(g), "eta"),
+                                           _ptr(h, _scalar_shape(g), "h"), _ptr(grad_h, _vector_shape(g), "grad_h"),
+                                           _ptr(u, _vector_shape(g), "u"), _ptr(eta_t, _scalar_shape(g), "eta_t"),
+                                           _ptr(U_t, _vector_shape(g), "U_t"), _P(ws.data_ptr())))
+        return eta_t, U_t
+
 
 class State:
     """A time-stepping state (sgn_state) over caller-owned eta, U, u tensors."""
@@ -428,6 +452,17 @@ class State:
             self.close()
         except Exception:
             pass
+
+    def set_dealias(self, enable: bool = True):
+        """Use the de-aliased right-hand side in later steps (sgn_state_set_dealias)."""
+        self.ctx._sync_stream()
+        if enable:
+            self._dws = torch.empty(max(dealias_workspace_bytes(self.g), 256), dtype=torch.uint8,
+                                    device=self.ctx.device)
+            self.ctx._check(_lib.sgn_state_set_dealias(self.ctx._h, self._h, _P(self._dws.data_ptr())))
+        else:
+            self.ctx._check(_lib.sgn_state_set_dealias(self.ctx._h, self._h, None))
+            self._dws = None
 
     def step_rk4(self, dt: float, nsteps: int, opts: SolveOpts | None = None) -> StepInfo:
         self.ctx._sync_stream()
