@@ -107,13 +107,13 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(cfg, steps: int = 1, device_fields=None):
+def cpu_baseline(cfg, steps: int = 1, device_fields=None, dealias: bool = False):
     """The oracle, as it stands, on `steps` RK4 steps of the same workload from its
     initial data.  device_fields = (eta, U, u) of the device after the same steps
     adds the relative L2 difference per field (zeta = eta - h, U, u)."""
     import numpy as np
     from oracle import stepping as ost
-    pb = ost.Problem.from_h(cfg["grid"], cfg["h"], tol=cfg["tol"])
+    pb = ost.Problem.from_h(cfg["grid"], cfg["h"], tol=cfg["tol"], dealias=2 if dealias else 1)
     U0 = pb.G(cfg["eta"], cfg["u"])
     t0 = time.perf_counter()
     e_r, U_r, u_r = ost.run_rk4(pb, cfg["eta"], U0, cfg["u"], cfg["dt"], steps)
@@ -412,6 +412,8 @@ def main(argv=None):
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
     ap.add_argument("--n", type=int, default=1024, help="grid points per side (default 1024)")
     ap.add_argument("--check-every", type=int, default=8)
+    ap.add_argument("--dealias", action="store_true",
+                    help="rk4-2d with the de-aliased right-hand side (nonlinear terms on the 2x padded grid)")
     ap.add_argument("--inner-tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true", help="skip the per-kernel HIP-event timing pass")
@@ -424,6 +426,8 @@ def main(argv=None):
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="HBM bytes per launch of the PCG passes from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
                          "runs of this script with --calib-copy-mib (no GPU needed) and exit")
+    ap.add_argument("--traffic-pattern", help="with --summarize-traffic: bytes per dispatch of the kernels "
+                    "matching this regular expression, per launch shape, instead of the PCG loop families")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
     ap.add_argument("--out", help="summary output path")
     args = ap.parse_args(argv)
@@ -433,6 +437,11 @@ def main(argv=None):
         if args.summarize_kernels:
             text = profiling.kernel_summary_md(args.summarize_kernels, args.command,
                                                f"Kernel durations: {args.precision}, {args.n}x{args.n} RK4 workload")
+        elif args.traffic_pattern:
+            rec = profiling.traffic_by_kernel(args.summarize_traffic[0], args.summarize_traffic[1],
+                                              args.calib_copy_mib * (1 << 20), args.traffic_pattern)
+            rec.update({"n": args.n, "kernel_source_sha": kernel_source_hash(), "command": args.command})
+            text = json.dumps(rec, indent=1) + "\n"
         else:
             rec = profiling.traffic(args.summarize_traffic[0], args.summarize_traffic[1],
                                     args.calib_copy_mib * (1 << 20))
@@ -473,7 +482,10 @@ def main(argv=None):
         eta = to(cfg["eta"])
         u = to(cfg["u"])
         U = ctx.apply_constraint(g, eta, gh, u)
-        return sgn.State(ctx, g, h, gh, flat, eta, U, u)
+        st = sgn.State(ctx, g, h, gh, flat, eta, U, u)
+        if args.dealias:
+            st.set_dealias(True)
+        return st
 
     if args.calib_copy_mib > 0:
         nel = args.calib_copy_mib * (1 << 20) // 8
@@ -565,7 +577,7 @@ def main(argv=None):
                                                    inner_tol=args.inner_tol))
         dev_fields = tuple(t.detach().cpu().numpy() for t in (st1.eta, st1.U, st1.u))
         st1.close()
-        cpu = cpu_baseline(cfg, 1, dev_fields)
+        cpu = cpu_baseline(cfg, 1, dev_fields, args.dealias)
 
     lat = main_run["lat"]
     out = {
@@ -584,8 +596,9 @@ def main(argv=None):
         "config": {
             "workload": (f"2D SGN over a Gaussian bump, RK4: {g.nx}x{g.ny} grid on {g.Lx:g}x{g.Ly:g}, "
                          "h0=1, bump height 0.5 radius 10 at the centre, line solitary wave a=0.2 at x=50, "
-                         f"dt={cfg['dt']}, Krylov tol {cfg['tol']:g}"),
-            "scheme": "rk4", "precision": args.precision, "grid": [g.nx, g.ny], "dt": cfg["dt"],
+                         f"dt={cfg['dt']}, Krylov tol {cfg['tol']:g}"
+                         + (", de-aliased right-hand side (2x zero-padded grid)" if args.dealias else "")),
+            "scheme": "rk4", "rhs": "dealiased-2x" if args.dealias else "plain", "precision": args.precision, "grid": [g.nx, g.ny], "dt": cfg["dt"],
             "tol": cfg["tol"], "initial_guess": "extrapolated per stage", "parallelism": "single GPU",
         },
         "krylov_iters_per_solve": main_run["iters"] / max(main_run["solves"], 1),
@@ -595,6 +608,8 @@ def main(argv=None):
         "checks": {"constraint_relres": main_run["relres"], "mass_rel_drift": main_run["drift"]},
         "other_precision": other,
         "kernels": kstats,
+        "kernel_families_ms_per_step": {k: round(v[1] / max(args.timing_steps, 1), 4)
+                                         for k, v in prof.items() if v[0]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),

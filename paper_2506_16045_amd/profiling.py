@@ -120,3 +120,34 @@ def traffic(fetch_db: str, write_db: str, calib_bytes: int):
                                                     "hbm_bytes_per_launch": f + w,
                                                     "dispatches": len(fv)}
     return out
+
+
+def traffic_by_kernel(fetch_db: str, write_db: str, calib_bytes: int, pattern: str):
+    """HBM bytes per dispatch of every kernel whose demangled name matches
+    `pattern`, per launch shape (grid size), scaled by the reference copy as in
+    traffic()."""
+    fr = counter_means(fetch_db, "FETCH_SIZE")
+    wr = counter_means(write_db, "WRITE_SIZE")
+    kib = calib_bytes / 1024.0
+    cw = [v for n, v, g in wr if "copy" in n.lower()]
+    cf = [v for n, v, g in fr if "copy" in n.lower()]
+    if not cw or not cf:
+        raise RuntimeError("reference copy kernel not found in the counter runs")
+    scale_w = kib / min(cw, key=lambda v: abs(v - kib))
+    scale_f = kib / max(cf)
+    dem = demangle({n for n, _, _ in fr} | {n for n, _, _ in wr})
+    acc = collections.defaultdict(lambda: {"fetch": [], "write": []})
+    for rows, key in ((fr, "fetch"), (wr, "write")):
+        for n, v, g in rows:
+            nm = dem[n].split("(")[0]
+            if re.search(pattern, nm):
+                acc[(nm, g)][key].append(v)
+    out = {"scale_fetch": scale_f, "scale_write": scale_w, "reference_copy_bytes": calib_bytes, "kernels": []}
+    for (nm, g), d in sorted(acc.items()):
+        if not d["fetch"] or not d["write"]:
+            continue
+        f = sum(d["fetch"]) / len(d["fetch"]) * scale_f * 1024.0
+        w = sum(d["write"]) / len(d["write"]) * scale_w * 1024.0
+        out["kernels"].append({"kernel": nm, "grid_size": g, "dispatches": len(d["fetch"]),
+                               "fetch_bytes": f, "write_bytes": w, "hbm_bytes_per_launch": f + w})
+    return out
