@@ -144,6 +144,83 @@ def batch_bytes(sizes, res, mixed: bool) -> float:
     return tot
 
 
+COEFF_SWEEP = [(n, eta0) for n in (512, 16384) for eta0 in (1.0, 0.5, 0.2, 0.1, 0.05)]
+
+
+def cpu_baseline_coeffs():
+    """The oracle's PCG, as it stands, on every case of the coefficient sweep (both
+    coefficient kinds); its iteration counts are reported beside the device's."""
+    from oracle import krylov
+    from oracle import operators as op
+    from paper_2506_16045_amd import inputs as I
+    its, nsolves = {}, 0
+    t0 = time.perf_counter()
+    for n, eta0 in COEFF_SWEEP:
+        g, _, h, b = I.pcg_test_problem_1d(n, 1.0, 1.0)
+        gh, fl = op.bathy_gradient(h, g)
+        eta = I.square_wave_depth_1d(n, eta0, gh[0])
+        for kind in ("optimal", "replacement"):
+            s_, a_, _ = op.coefficients(eta, gh, fl, kind=kind)
+            _, it, ok, _ = krylov.pcg(lambda v: op.apply_G(eta, gh, v, g), lambda r: op.solve_A(s_, a_, r, g), b,
+                                      tol=1e-8, max_iter=20000)
+            its[f"{n}/{eta0}/{kind}"] = it if ok else None
+            nsolves += 1
+    dt = time.perf_counter() - t0
+    return {"value": nsolves / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"the {nsolves} solves of the sweep ({dt:.1f} s, FP64 NumPy, single thread)",
+            "iters": its}
+
+
+def bench_coeffs(args):
+    """Optimal (Eq:Optcoeff) against replacement (Remark 4.2) coefficients: PCG to
+    1e-8 on the square-wave depth of section 6.2 over a sweep of its contrast eta0
+    (the depth is small where the slope is large for eta0 < 1)."""
+    import numpy as np
+    import torch
+
+    from paper_2506_16045_amd import inputs as I
+    from paper_2506_16045_amd import sgn
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = sgn.Context(0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    rows = []
+    for n, eta0 in COEFF_SWEEP:
+        g, _, h, b = I.pcg_test_problem_1d(n, 1.0, 1.0)
+        gh_d, _ = ctx.bathy_prepare(g, to(h))
+        eta = I.square_wave_depth_1d(n, eta0, gh_d[0].cpu().numpy())
+        e_d, b_d = to(eta), to(b)
+        row = {"n": n, "eta0": eta0}
+        for kind, ck in (("optimal", sgn.COEFF_OPTIMAL), ("replacement", sgn.COEFF_REPLACEMENT)):
+            opts = sgn.solve_opts(tol=1e-8, max_iter=20000, check_every=8, coeff_kind=ck)
+            ctx.krylov_solve(g, e_d, gh_d, b_d, opts=opts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                _, res = ctx.krylov_solve(g, e_d, gh_d, b_d, opts=opts)
+            torch.cuda.synchronize()
+            row[kind] = {"iters": res.iters, "converged": res.converged, "relres": res.relres,
+                         "ms_per_solve": round(1e3 * (time.perf_counter() - t0) / reps, 3),
+                         "sigma": res.sigma, "alpha": res.alpha}
+        row["ratio"] = row["replacement"]["iters"] / max(row["optimal"]["iters"], 1)
+        print(f"n={n} eta0={eta0}: optimal {row['optimal']['iters']} / replacement "
+              f"{row['replacement']['iters']} iterations", file=sys.stderr, flush=True)
+        rows.append(row)
+    head = next(r for r in rows if r["n"] == 512 and r["eta0"] == 0.05)
+    out = {"metric": "PCG iterations to 1e-8 on the square-wave depth: replacement / optimal coefficients",
+           "value": head["ratio"], "unit": "iteration ratio (n=512, eta0=0.05)", "n_gpus": 1,
+           "steps": 5, "warmup": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "section 6.2 test problem (h0 = 1, b = cos 4 pi x on [0, 1]) with the square-wave "
+                                  "depth 0.1 / 0.1 eta0, tol 1e-8, zero initial guess"},
+           "sweep": rows, "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_coeffs(),
+           "device": torch.cuda.get_device_name(0)}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
 def bench_batch(args):
     import numpy as np
     import torch
@@ -399,7 +476,7 @@ def cpu_baseline_batch(systems, tol, count):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["rk4-2d", "batch", "serve"], default="rk4-2d")
+    ap.add_argument("--workload", choices=["rk4-2d", "batch", "serve", "coeffs"], default="rk4-2d")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="arrival rates of the serve workload")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per rate (serve workload)")
     ap.add_argument("--lanes", type=int, default=3, help="worker lanes of the server (serve workload)")
@@ -462,6 +539,8 @@ def main(argv=None):
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "coeffs":
+        return bench_coeffs(args)
 
     import numpy as np
     import torch
