@@ -17,6 +17,8 @@ Modules:
   rhs          the constraint-form right-hand side f(w, p) with forcing F
                (Eq:DSWEcf, Def:bigF, Eq:DAE_DSWE), and its de-aliased form
                on a zero-padded grid (subsec:dswe_1d, remark on aliasing)
+  walls        G, A^{-1} and PCG between walls (homogeneous Neumann, Subsec:DAEform,
+               Subsec:linop): cosine / sine series on a cell-centred grid
   stepping     RK4 (Eq:ERK), Adams-Bashforth 2-4 (Eq:AB, Table LMMCoeffs) and
                the linearly implicit SBDF2 scheme (Eq:MM)
   diagnostics  mass, energy (Remark 2.1), the G-norm error (def:discrete_Gerr)
@@ -24,4 +26,4 @@ Modules:
 Every function that has no independent pin says "parity unpinned" in its
 docstring; the pins live in tests/test_oracle_*.py.
 """
-from . import spectral, operators, krylov, rhs, stepping, diagnostics  # noqa: F401
+from . import spectral, operators, krylov, rhs, stepping, diagnostics, walls  # noqa: F401

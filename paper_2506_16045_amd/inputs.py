@@ -34,6 +34,7 @@ class Grid:
     ny: int = 1
     Lx: float = 1.0
     Ly: float = 1.0
+    bc: int = 0   # 0: periodic; 1: walls (homogeneous Neumann, cell-centred grid)
 
     @property
     def shape(self):
@@ -59,12 +60,24 @@ def grid2d(nx: int, ny: int, Lx: float, Ly: float) -> Grid:
     return Grid(2, nx, ny, float(Lx), float(Ly))
 
 
+def grid1d_walls(n: int, L: float) -> Grid:
+    """[0, L] between walls, cell-centred points x_j = (j + 1/2) L / n."""
+    return Grid(1, n, 1, float(L), 1.0, 1)
+
+
+def grid2d_walls(nx: int, ny: int, Lx: float, Ly: float) -> Grid:
+    """[0, Lx] x [0, Ly] closed by walls, cell-centred points."""
+    return Grid(2, nx, ny, float(Lx), float(Ly), 1)
+
+
 def coords(g: Grid):
-    """Grid coordinates; 1D returns x, 2D returns (X, Y) of shape (ny, nx)."""
-    x = np.arange(g.nx, dtype=np.float64) * (g.Lx / g.nx)
+    """Grid coordinates; 1D returns x, 2D returns (X, Y) of shape (ny, nx).  A grid
+    between walls has its points at the cell centres."""
+    off = 0.5 if g.bc == 1 else 0.0
+    x = (np.arange(g.nx, dtype=np.float64) + off) * (g.Lx / g.nx)
     if g.d == 1:
         return x
-    y = np.arange(g.ny, dtype=np.float64) * (g.Ly / g.ny)
+    y = (np.arange(g.ny, dtype=np.float64) + off) * (g.Ly / g.ny)
     X, Y = np.meshgrid(x, y, indexing="xy")
     return X, Y
 
