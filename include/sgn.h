@@ -49,13 +49,31 @@ typedef enum sgn_status {
 typedef struct sgn_ctx sgn_ctx;
 typedef struct sgn_state sgn_state;
 
-/* Grid (section 6.1): dim 1 or 2; ny and Ly are ignored when dim = 1. */
+/* Boundary conditions of a grid. */
+typedef enum sgn_bc {
+    SGN_BC_PERIODIC = 0,  /* periodic, points x_j = j L / n (section 6.1) */
+    SGN_BC_WALLS = 1      /* homogeneous Neumann n.u = 0 on the walls of [0, Lx] (x [0, Ly])
+                           * (Subsec:DAEform, Subsec:linop), points at the cell centres
+                           * x_j = (j + 1/2) L / n; scalar fields are cosine series, each
+                           * velocity component a sine series along its own axis.  Taken by
+                           * sgn_bathy_prepare, sgn_precond_coeffs, sgn_apply_constraint,
+                           * sgn_precond_solve and sgn_krylov_solve (and their workspace
+                           * queries); the right-hand side, the steppers, the batched solver
+                           * and the server return SGN_EUNSUPPORTED for it.  Sizes: 1D
+                           * nx <= 8192, 2D nx <= 2048 and ny <= 512.  Internally the fields
+                           * are reflected (even / odd) onto the periodic grid of twice the
+                           * length per axis, where every step of the periodic path runs. */
+} sgn_bc;
+
+/* Grid (section 6.1): dim 1 or 2; ny and Ly are ignored when dim = 1; bc takes
+ * a value of the enum above (periodic when the struct is zero-initialised). */
 typedef struct sgn_grid {
     int32_t dim;
     int32_t nx;
     int32_t ny;
     double Lx;
     double Ly;
+    int32_t bc;
 } sgn_grid;
 
 /* Coefficients of the preconditioner A = sigma I - alpha grad(div)  (Def:A),

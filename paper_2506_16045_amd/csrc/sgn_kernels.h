@@ -1153,6 +1153,44 @@ __global__ void __launch_bounds__(256) k_cols_resample(ColGeom g, const cpx<T>* 
     col_store<T, EPC, NF>(g, ct, v, dsts, true, twm);
 }
 
+// Grids between walls run on their periodic twin (twice the length per axis):
+// k_reflect writes the even / odd reflection of nf fields of the nx x ny wall
+// grid (field stride sstride) onto the twin (field stride dstride):
+// dst[Y][X] = sx sy src[ry][rx], r(X) = X below n and 2n - 1 - X above, with the
+// sign -1 on the reflected half of an axis along which field f is odd (bit f of
+// oddx / oddy).  k_restrict copies the twin's first quadrant back.
+__global__ void __launch_bounds__(256) k_reflect(int nx, int ny, int nye, const double* __restrict__ src,
+                                                  size_t sstride, double* __restrict__ dst, size_t dstride, int nf,
+                                                  unsigned oddx, unsigned oddy) {
+    const int nxe = 2 * nx;
+    const size_t ne = (size_t)nxe * nye;
+    const size_t total = ne * (size_t)nf;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int f = (int)(i / ne);
+        const size_t p = i - (size_t)f * ne;
+        const int Y = (int)(p / nxe), X = (int)(p - (size_t)Y * nxe);
+        const bool fx = X >= nx, fy = Y >= ny;
+        const int x = fx ? nxe - 1 - X : X;
+        const int y = fy ? 2 * ny - 1 - Y : Y;
+        double v = src[(size_t)f * sstride + (size_t)y * nx + x];
+        if (fx && ((oddx >> f) & 1u)) v = -v;
+        if (fy && ((oddy >> f) & 1u)) v = -v;
+        dst[(size_t)f * dstride + p] = v;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_restrict(int nx, int ny, const double* __restrict__ src, size_t sstride,
+                                                   double* __restrict__ dst, size_t dstride, int nf) {
+    const size_t n = (size_t)nx * ny;
+    const size_t total = n * (size_t)nf;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int f = (int)(i / n);
+        const size_t p = i - (size_t)f * n;
+        const int y = (int)(p / nx), x = (int)(p - (size_t)y * nx);
+        dst[(size_t)f * dstride + p] = src[(size_t)f * sstride + (size_t)y * (2 * nx) + x];
+    }
+}
+
 // Initialise the scalars of a solve on the device (no host round trip).  With
 // have_coeffs the preconditioner coefficients are given; otherwise they are
 // filled later by k_coeffs_finish or copied from another solve.

@@ -119,17 +119,22 @@ struct Dims {
     size_t NS;  // spectral modes (nx/2+1) * ny
     double tpx, tpy, inv_n;
     double Lx;
+    int bc = SGN_BC_PERIODIC;
+    double Ly = 1.0;
 };
 
 sgn_status check_grid(sgn_ctx* ctx, const sgn_grid* g, Dims* d) {
     if (!g) return fail(ctx, SGN_EINVAL, "grid is null");
     if (g->dim != 1 && g->dim != 2) return fail(ctx, SGN_EINVAL, "grid dim must be 1 or 2");
     const int ny = g->dim == 1 ? 1 : g->ny;
+    if (g->bc != SGN_BC_PERIODIC && g->bc != SGN_BC_WALLS) return fail(ctx, SGN_EINVAL, "bad boundary condition");
     if (!is_pow2(g->nx) || g->nx < 2 || !is_pow2(ny))
         return fail(ctx, SGN_EUNSUPPORTED, "grid sizes must be powers of two (nx >= 2)");
-    if (g->dim == 1 && g->nx > 16384) return fail(ctx, SGN_EUNSUPPORTED, "1D nx above 16384");
-    if (g->dim == 2 && (g->nx > 4096 || ny > 1024 || ny < 2))
-        return fail(ctx, SGN_EUNSUPPORTED, "2D sizes: nx in [2, 4096], ny in [2, 1024]");
+    // a grid between walls runs on its periodic twin, twice as long per axis
+    const int w = g->bc == SGN_BC_WALLS ? 2 : 1;
+    if (g->dim == 1 && g->nx * w > 16384) return fail(ctx, SGN_EUNSUPPORTED, "1D nx above 16384 (8192 with walls)");
+    if (g->dim == 2 && (g->nx * w > 4096 || ny * w > 1024 || ny < 2))
+        return fail(ctx, SGN_EUNSUPPORTED, "2D sizes: nx in [2, 4096], ny in [2, 1024] (half with walls)");
     if (!(g->Lx > 0.0) || (g->dim == 2 && !(g->Ly > 0.0)))
         return fail(ctx, SGN_EINVAL, "domain lengths must be positive");
     d->D = g->dim;
@@ -141,6 +146,30 @@ sgn_status check_grid(sgn_ctx* ctx, const sgn_grid* g, Dims* d) {
     d->tpy = g->dim == 2 ? kTwoPi / g->Ly : 0.0;
     d->inv_n = 1.0 / (double)d->N;
     d->Lx = g->Lx;
+    d->Ly = g->dim == 2 ? g->Ly : 1.0;
+    d->bc = g->bc;
+    return SGN_OK;
+}
+
+// The periodic grid of twice the length per axis on which a grid between walls runs.
+Dims twin_dims(const Dims& d) {
+    Dims t = d;
+    t.bc = SGN_BC_PERIODIC;
+    t.nx = 2 * d.nx;
+    t.ny = d.D == 2 ? 2 * d.ny : 1;
+    t.N = (size_t)t.nx * t.ny;
+    t.NS = (size_t)(t.nx / 2 + 1) * t.ny;
+    t.Lx = 2 * d.Lx;
+    t.Ly = d.D == 2 ? 2 * d.Ly : 1.0;
+    t.tpx = kTwoPi / t.Lx;
+    t.tpy = d.D == 2 ? kTwoPi / t.Ly : 0.0;
+    t.inv_n = 1.0 / (double)t.N;
+    return t;
+}
+
+sgn_status require_periodic(sgn_ctx* ctx, const Dims& d) {
+    if (d.bc != SGN_BC_PERIODIC)
+        return fail(ctx, SGN_EUNSUPPORTED, "grids between walls are taken by the constraint solve calls only");
     return SGN_OK;
 }
 
@@ -1937,6 +1966,50 @@ sgn_status rhs_dealiased(sgn_ctx* ctx, const Dims& d, const double* eta, const d
 
 
 // ---------------------------------------------------------------------------
+// Grids between walls (homogeneous Neumann, Subsec:DAEform): the cosine / sine
+// series of a cell-centred wall grid are the Fourier series of the fields
+// reflected evenly (scalars) or oddly (each velocity component along its own
+// axis) onto the periodic grid of twice the length per axis, and G, A^{-1} and
+// the Krylov iteration preserve that symmetry.  A call on a wall grid reflects
+// its inputs onto the twin, runs the periodic path there, and restricts the
+// result to the first quadrant.  Dot products over the twin are twice those
+// over the wall grid, so every ratio the iteration forms is unchanged.
+// ---------------------------------------------------------------------------
+struct WallBufs {
+    double *eta, *gh, *f, *u;  // on the twin: eta [N], grad h [D N], input [D N], result [D N]
+    void* ws;                  // the twin's own workspace
+};
+size_t carve_walls(Carve& cv, const Dims& t, WallBufs* b) {
+    WallBufs w;
+    w.eta = cv.take<double>(t.N);
+    w.gh = cv.take<double>((size_t)t.D * t.N);
+    w.f = cv.take<double>((size_t)t.D * t.N);
+    w.u = cv.take<double>((size_t)t.D * t.N);
+    cv.off = align_up(cv.off, 256);
+    w.ws = cv.base ? cv.base + cv.off : nullptr;
+    if (b) *b = w;
+    return cv.off;
+}
+
+sgn_status wall_reflect(sgn_ctx* ctx, const Dims& d, const double* src, double* dst, bool vector) {
+    const Dims t = twin_dims(d);
+    const int nf = vector ? d.D : 1;
+    const unsigned oddx = vector ? 1u : 0u, oddy = (vector && d.D == 2) ? 2u : 0u;
+    hipLaunchKernelGGL(k_reflect, dim3(flat_blocks(t.N * nf)), dim3(256), 0, ctx->stream, d.nx, d.ny, t.ny, src,
+                       d.N, dst, t.N, nf, oddx, oddy);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
+sgn_status wall_restrict(sgn_ctx* ctx, const Dims& d, const double* src, double* dst) {
+    const Dims t = twin_dims(d);
+    hipLaunchKernelGGL(k_restrict, dim3(flat_blocks(d.N * d.D)), dim3(256), 0, ctx->stream, d.nx, d.ny, src, t.N,
+                       dst, d.N, d.D);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Time-stepping state (section 5)
 // ---------------------------------------------------------------------------
 struct StateBufs {
@@ -2463,6 +2536,11 @@ const char* sgn_last_error(const sgn_ctx* ctx) { return ctx ? ctx->err.c_str() :
 size_t sgn_workspace_bytes(const sgn_grid* grid, int32_t precision) {
     Dims d;
     if (check_grid(nullptr, grid, &d) != SGN_OK) return 0;
+    if (d.bc == SGN_BC_WALLS) {
+        const Dims t = twin_dims(d);
+        Carve cv(nullptr);
+        return carve_walls(cv, t, nullptr) + workspace_bytes(t, precision);
+    }
     return workspace_bytes(d, precision);
 }
 
@@ -2470,16 +2548,19 @@ size_t sgn_gmres_workspace_bytes(const sgn_grid* grid, int32_t restart) {
     Dims d;
     if (check_grid(nullptr, grid, &d) != SGN_OK) return 0;
     if (restart < 1 || restart > GMRES_MAX_RESTART) return 0;
+    if (d.bc == SGN_BC_WALLS) {
+        const Dims t = twin_dims(d);
+        Carve cv(nullptr);
+        return carve_walls(cv, t, nullptr) + gmres_workspace_bytes(t, restart);
+    }
     return gmres_workspace_bytes(d, restart);
 }
 
-sgn_status sgn_bathy_prepare(sgn_ctx* ctx, const sgn_grid* grid, const double* h, double* grad_h, int32_t* flat,
-                             void* ws) {
-    if (!ctx) return SGN_EINVAL;
-    Dims d;
-    sgn_status s = check_grid(ctx, grid, &d);
-    if (s != SGN_OK) return s;
-    if (!h || !grad_h || !flat || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+}  // extern "C"
+
+namespace {
+sgn_status bathy_impl(sgn_ctx* ctx, const Dims& d, const double* h, double* grad_h, int32_t* flat, void* ws) {
+    sgn_status s;
     Carve cv(ws);
     Common cm = carve_common(cv);
     cpx<double>* H = cv.take<cpx<double>>((size_t)(1 + d.D) * d.NS);
@@ -2515,6 +2596,28 @@ sgn_status sgn_bathy_prepare(sgn_ctx* ctx, const sgn_grid* grid, const double* h
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return SGN_OK;
 }
+}  // namespace
+
+extern "C" {
+
+sgn_status sgn_bathy_prepare(sgn_ctx* ctx, const sgn_grid* grid, const double* h, double* grad_h, int32_t* flat,
+                             void* ws) {
+    if (!ctx) return SGN_EINVAL;
+    Dims d;
+    sgn_status s = check_grid(ctx, grid, &d);
+    if (s != SGN_OK) return s;
+    if (!h || !grad_h || !flat || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    if (d.bc != SGN_BC_WALLS) return bathy_impl(ctx, d, h, grad_h, flat, ws);
+    const Dims t = twin_dims(d);
+    WallBufs w;
+    Carve cv(ws);
+    carve_walls(cv, t, &w);
+    if ((s = wall_reflect(ctx, d, h, w.eta, false)) != SGN_OK) return s;
+    if ((s = bathy_impl(ctx, t, w.eta, w.gh, flat, w.ws)) != SGN_OK) return s;
+    if ((s = wall_restrict(ctx, d, w.gh, grad_h)) != SGN_OK) return s;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SGN_OK;
+}
 
 sgn_status sgn_precond_coeffs(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const double* grad_h,
                               int32_t flat, int32_t kind, sgn_coeffs* out, void* ws) {
@@ -2545,7 +2648,18 @@ sgn_status sgn_apply_constraint(sgn_ctx* ctx, const sgn_grid* grid, const double
     if (s != SGN_OK) return s;
     if (!eta || !grad_h || !u || !out || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
     if (out == u) return fail(ctx, SGN_EINVAL, "out may not alias u");
-    return d.D == 1 ? apply_G<1>(ctx, d, eta, grad_h, u, out, ws) : apply_G<2>(ctx, d, eta, grad_h, u, out, ws);
+    if (d.bc != SGN_BC_WALLS)
+        return d.D == 1 ? apply_G<1>(ctx, d, eta, grad_h, u, out, ws) : apply_G<2>(ctx, d, eta, grad_h, u, out, ws);
+    const Dims t = twin_dims(d);
+    WallBufs w;
+    Carve cv(ws);
+    carve_walls(cv, t, &w);
+    if ((s = wall_reflect(ctx, d, eta, w.eta, false)) != SGN_OK) return s;
+    if ((s = wall_reflect(ctx, d, grad_h, w.gh, true)) != SGN_OK) return s;
+    if ((s = wall_reflect(ctx, d, u, w.f, true)) != SGN_OK) return s;
+    s = d.D == 1 ? apply_G<1>(ctx, t, w.eta, w.gh, w.f, w.u, w.ws) : apply_G<2>(ctx, t, w.eta, w.gh, w.f, w.u, w.ws);
+    if (s != SGN_OK) return s;
+    return wall_restrict(ctx, d, w.u, out);
 }
 
 sgn_status sgn_precond_solve(sgn_ctx* ctx, const sgn_grid* grid, const sgn_coeffs* co, const double* rhs,
@@ -2556,8 +2670,18 @@ sgn_status sgn_precond_solve(sgn_ctx* ctx, const sgn_grid* grid, const sgn_coeff
     if (s != SGN_OK) return s;
     if (!co || !rhs || !out || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
     if (!(co->sigma > 0.0) || !(co->alpha > 0.0)) return fail(ctx, SGN_EINVAL, "sigma and alpha must be > 0");
-    return d.D == 1 ? precond_apply<1>(ctx, d, co->sigma, co->alpha, rhs, out, ws)
-                    : precond_apply<2>(ctx, d, co->sigma, co->alpha, rhs, out, ws);
+    if (d.bc != SGN_BC_WALLS)
+        return d.D == 1 ? precond_apply<1>(ctx, d, co->sigma, co->alpha, rhs, out, ws)
+                        : precond_apply<2>(ctx, d, co->sigma, co->alpha, rhs, out, ws);
+    const Dims t = twin_dims(d);
+    WallBufs w;
+    Carve cv(ws);
+    carve_walls(cv, t, &w);
+    if ((s = wall_reflect(ctx, d, rhs, w.f, true)) != SGN_OK) return s;
+    s = d.D == 1 ? precond_apply<1>(ctx, t, co->sigma, co->alpha, w.f, w.u, w.ws)
+                 : precond_apply<2>(ctx, t, co->sigma, co->alpha, w.f, w.u, w.ws);
+    if (s != SGN_OK) return s;
+    return wall_restrict(ctx, d, w.u, out);
 }
 
 sgn_status sgn_krylov_solve(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const double* grad_h,
@@ -2572,7 +2696,24 @@ sgn_status sgn_krylov_solve(sgn_ctx* ctx, const sgn_grid* grid, const double* et
     if (o.coeff_kind != SGN_COEFF_OPTIMAL && o.coeff_kind != SGN_COEFF_REPLACEMENT)
         return fail(ctx, SGN_EINVAL, "bad coeff_kind");
     // without given coefficients the flat formulas apply iff |grad h|_max = 0
-    return solve_dispatch(ctx, d, eta, grad_h, rhs, u, coeffs, coeffs ? coeffs->flat : -1, o, info, ws);
+    if (d.bc != SGN_BC_WALLS)
+        return solve_dispatch(ctx, d, eta, grad_h, rhs, u, coeffs, coeffs ? coeffs->flat : -1, o, info, ws);
+    const Dims t = twin_dims(d);
+    WallBufs w;
+    Carve cv(ws);
+    carve_walls(cv, t, &w);
+    if ((s = wall_reflect(ctx, d, eta, w.eta, false)) != SGN_OK) return s;
+    if ((s = wall_reflect(ctx, d, grad_h, w.gh, true)) != SGN_OK) return s;
+    if ((s = wall_reflect(ctx, d, rhs, w.f, true)) != SGN_OK) return s;
+    if (o.x0_is_guess && (s = wall_reflect(ctx, d, u, w.u, true)) != SGN_OK) return s;
+    s = solve_dispatch(ctx, t, w.eta, w.gh, w.f, w.u, coeffs, coeffs ? coeffs->flat : -1, o, info, w.ws);
+    // the iterate is returned as for a periodic grid: on success and when max_iter stops it
+    if (s == SGN_OK || s == SGN_ENOCONV) {
+        const sgn_status r = wall_restrict(ctx, d, w.u, u);
+        if (r != SGN_OK) return r;
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return s;
 }
 
 }  // extern "C"
@@ -2725,13 +2866,14 @@ sgn_status sgn_rhs(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const 
     Dims d;
     sgn_status s = check_grid(ctx, grid, &d);
     if (s != SGN_OK) return s;
+    if ((s = require_periodic(ctx, d)) != SGN_OK) return s;
     if (!eta || !h || !grad_h || !u || !eta_t || !U_t || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
     return rhs_dispatch(ctx, d, eta, grad_h, u, eta_t, U_t, ws);
 }
 
 size_t sgn_dealias_workspace_bytes(const sgn_grid* grid) {
     Dims d;
-    if (check_grid(nullptr, grid, &d) != SGN_OK || !dealias_supported(d)) return 0;
+    if (check_grid(nullptr, grid, &d) != SGN_OK || d.bc != SGN_BC_PERIODIC || !dealias_supported(d)) return 0;
     Carve cv(nullptr);
     return carve_dealias(cv, d, nullptr) + 256;
 }
@@ -2742,6 +2884,7 @@ sgn_status sgn_rhs_dealiased(sgn_ctx* ctx, const sgn_grid* grid, const double* e
     Dims d;
     sgn_status s = check_grid(ctx, grid, &d);
     if (s != SGN_OK) return s;
+    if ((s = require_periodic(ctx, d)) != SGN_OK) return s;
     if (!dealias_supported(d)) return fail(ctx, SGN_EUNSUPPORTED, "de-aliasing: grid too large to pad");
     if (!eta || !h || !grad_h || !u || !eta_t || !U_t || !dws) return fail(ctx, SGN_EINVAL, "null pointer");
     DealiasBufs b;
@@ -2770,7 +2913,7 @@ sgn_status sgn_state_set_dealias(sgn_ctx* ctx, sgn_state* st, void* dws) {
 size_t sgn_state_workspace_bytes(const sgn_grid* grid, int32_t precision) {
     (void)precision;
     Dims d;
-    if (check_grid(nullptr, grid, &d) != SGN_OK) return 0;
+    if (check_grid(nullptr, grid, &d) != SGN_OK || d.bc != SGN_BC_PERIODIC) return 0;
     Carve cv(nullptr);
     return carve_state(cv, d, nullptr) + 256;
 }
@@ -2783,6 +2926,7 @@ sgn_status sgn_state_create(sgn_ctx* ctx, const sgn_grid* grid, const double* h,
     Dims d;
     sgn_status s = check_grid(ctx, grid, &d);
     if (s != SGN_OK) return s;
+    if ((s = require_periodic(ctx, d)) != SGN_OK) return s;
     if (!h || !grad_h || !eta || !U || !u || !state_ws || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
     sgn_state* st = new (std::nothrow) sgn_state();
     if (!st) return fail(ctx, SGN_ENOMEM, "host allocation failed");

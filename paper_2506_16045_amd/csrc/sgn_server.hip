@@ -30,6 +30,7 @@ size_t up(size_t b) { return (b + ALIGN - 1) & ~(ALIGN - 1); }
 
 bool grid_ok(const sgn_grid& g) {
     auto pow2 = [](int v) { return v >= 2 && (v & (v - 1)) == 0; };
+    if (g.bc != SGN_BC_PERIODIC) return false;   // served requests: periodic grids
     if (g.dim == 1) return pow2(g.nx) && g.nx <= 16384 && g.Lx > 0.0 && std::isfinite(g.Lx);
     if (g.dim == 2)
         return pow2(g.nx) && pow2(g.ny) && g.nx <= 4096 && g.ny <= 1024 && g.Lx > 0.0 && g.Ly > 0.0 &&

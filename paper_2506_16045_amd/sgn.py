@@ -34,6 +34,7 @@ STATUS_NAMES = {0: "SGN_OK", -1: "SGN_EINVAL", -2: "SGN_EDOMAIN", -3: "SGN_ENOCO
 PCG, GMRES = 0, 1
 FP64, MIXED = 0, 1
 COEFF_OPTIMAL, COEFF_REPLACEMENT = 0, 1
+BC_PERIODIC, BC_WALLS = 0, 1
 GUESS_PREVIOUS, GUESS_EXTRAPOLATE = 0, 1
 
 
@@ -45,7 +46,7 @@ class SgnError(RuntimeError):
 
 class Grid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-                ("Lx", ctypes.c_double), ("Ly", ctypes.c_double)]
+                ("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("bc", ctypes.c_int32)]
 
 
 class Coeffs(ctypes.Structure):
@@ -155,7 +156,8 @@ def version() -> str:
 
 def make_grid(g) -> Grid:
     """Grid from an object with d, nx, ny, Lx, Ly (paper_2506_16045_amd.inputs.Grid)."""
-    return Grid(int(g.d), int(g.nx), int(g.ny if g.d == 2 else 1), float(g.Lx), float(g.Ly if g.d == 2 else 1.0))
+    return Grid(int(g.d), int(g.nx), int(g.ny if g.d == 2 else 1), float(g.Lx), float(g.Ly if g.d == 2 else 1.0),
+                int(getattr(g, "bc", BC_PERIODIC)))
 
 
 def workspace_bytes(g, precision: int = FP64) -> int:
@@ -260,7 +262,7 @@ class Context:
             raise SgnError(st, _lib.sgn_last_error(self._h).decode())
 
     def workspace(self, g, precision=FP64) -> torch.Tensor:
-        key = (g.d, g.nx, g.ny if g.d == 2 else 1, max(precision, MIXED))
+        key = (g.d, g.nx, g.ny if g.d == 2 else 1, int(getattr(g, "bc", BC_PERIODIC)), max(precision, MIXED))
         nb = workspace_bytes(g, MIXED)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < nb:

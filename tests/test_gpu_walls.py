@@ -1,0 +1,166 @@
+"""GPU parity of the constraint-solve entry points on grids between walls
+(homogeneous Neumann, Subsec:DAEform) against the oracle's cosine / sine series
+operators (oracle/walls.py), element by element on the same seeded inputs:
+grad h, G, A^{-1} and PCG (FP64 and mixed) and GMRES solves, on 1D and 2D wall
+grids from the smallest to the largest (whose periodic twins run on the
+one-workgroup 1D solver, the row-pass path and 2D columns of 1024), and the
+entry points that take periodic grids only rejecting walls."""
+import numpy as np
+import pytest
+
+from oracle import operators as op
+from oracle import walls as W
+from paper_2506_16045_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL_OP = 1e-12
+
+GRIDS = [
+    I.grid1d_walls(2, 1.0), I.grid1d_walls(256, 20.0), I.grid1d_walls(4096, 300.0), I.grid1d_walls(8192, 300.0),
+    I.grid2d_walls(2, 2, 1.0, 1.0), I.grid2d_walls(16, 8, 2.0, 1.0), I.grid2d_walls(64, 64, 5.0, 5.0),
+    I.grid2d_walls(32, 512, 1.0, 8.0), I.grid2d_walls(512, 512, 40.0, 40.0), I.grid2d_walls(2048, 256, 100.0, 12.5),
+]
+IDS = [f"{g.d}d-{g.nx}x{g.ny if g.d == 2 else 1}" for g in GRIDS]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2506_16045_amd import sgn
+    assert torch.cuda.is_available()
+    return sgn.Context(0)
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def _fields(g, seed):
+    rng = np.random.default_rng(seed)
+    eta = I.random_positive_depth(g, rng, 0.6, 1.6)
+    h = 1.0 + 0.2 * I.random_smooth_field(g, rng, modes=min(4, max(1, g.nx // 4)))
+    u = rng.normal(size=(g.d,) + g.shape)
+    return eta, h, u
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=IDS)
+def test_bathy_and_operators(ctx, g):
+    print(f"walls operators {g}", flush=True)
+    eta, h, u = _fields(g, 31)
+    gh_ref, fl_ref = W.bathy_gradient(h, g)
+    gh, fl = ctx.bathy_prepare(g, _t(h))
+    assert fl == fl_ref
+    assert rel(_n(gh), gh_ref) <= TOL_OP
+    Gu = ctx.apply_constraint(g, _t(eta), _t(gh_ref), _t(u))
+    assert rel(_n(Gu), W.apply_G(eta, gh_ref, u, g)) <= TOL_OP
+    for sig, alp in ((1.3, 0.7), (2.0, 40.0)):
+        z = ctx.precond_solve(g, sig, alp, _t(u))
+        assert rel(_n(z), W.solve_A(sig, alp, u, g)) <= TOL_OP
+    co = ctx.precond_coeffs(g, _t(eta), _t(gh_ref), fl_ref)
+    np.testing.assert_allclose([co.sigma, co.alpha, co.kappa_ub], op.coefficients(eta, gh_ref, fl_ref), rtol=1e-13)
+
+
+def test_flat_bathymetry_between_walls(ctx):
+    g = GRIDS[6]
+    gh, fl = ctx.bathy_prepare(g, _t(np.full(g.shape, 0.8)))
+    assert fl and not np.any(_n(gh))
+
+
+def _reflect(f, kinds):
+    out = f
+    for ax, k in enumerate(kinds):
+        out = np.concatenate([out, np.flip(out, axis=ax) * (1.0 if k == "c" else -1.0)], axis=ax)
+    return out
+
+
+def _twin_problem(g, eta, h, b):
+    """The periodic problem on the doubled domain that the library solves: the
+    even / odd reflections of the inputs (oracle's periodic operators)."""
+    g2 = I.grid1d(2 * g.nx, 2 * g.Lx) if g.d == 1 else I.grid2d(2 * g.nx, 2 * g.ny, 2 * g.Lx, 2 * g.Ly)
+    vk = W.VECTOR[g.d]
+    e2 = _reflect(eta, W.SCALAR[g.d])
+    gh2, fl2 = op.bathy_gradient(_reflect(h, W.SCALAR[g.d]), g2)
+    b2 = np.stack([_reflect(b[c], vk[c]) for c in range(g.d)])
+    return g2, e2, gh2, fl2, b2
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=IDS)
+def test_pcg_fp64_matches_oracle(ctx, g):
+    """Solutions equal the oracle's wall solve; the iteration count equals (+-1) the
+    oracle's periodic PCG on the reflected problem, the same computation, and is
+    within 12 % of the cosine / sine iteration: on the twin, rounding puts noise
+    into the wrong-parity subspace (the constant velocity mode lives only there),
+    which CG amplifies at low wavenumbers before it resolves it."""
+    from paper_2506_16045_amd import sgn
+    from oracle import krylov
+    print(f"walls pcg {g}", flush=True)
+    eta, h, b = _fields(g, 32)
+    gh, fl = W.bathy_gradient(h, g)
+    u_ref, it_ref, ok, co = W.pcg_solve(eta, gh, fl, b, g, tol=1e-12)
+    assert ok
+    g2, e2, gh2, fl2, b2 = _twin_problem(g, eta, h, b)
+    s2, a2, _ = op.coefficients(e2, gh2, fl2)
+    _, it_twin, ok2, _ = krylov.pcg(lambda v: op.apply_G(e2, gh2, v, g2), lambda r: op.solve_A(s2, a2, r, g2), b2,
+                                    tol=1e-12, max_iter=2000)
+    assert ok2
+    u, res = ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), opts=sgn.solve_opts(tol=1e-12, check_every=4))
+    assert res.converged and res.relres <= 1e-12
+    assert abs(res.iters - it_twin) <= 1, (res.iters, it_twin)
+    assert abs(res.iters - it_ref) <= max(2, 0.12 * it_ref), (res.iters, it_ref)
+    np.testing.assert_allclose([res.sigma, res.alpha, res.kappa_ub], co, rtol=1e-13)
+    assert rel(_n(u), u_ref) <= 1e-9
+    # the true residual with the oracle's wall operator is as small as the oracle's own
+    # (it floors near eps ||G|| ||u||, above the tolerance for stiff grids)
+    r = np.linalg.norm(b - W.apply_G(eta, gh, _n(u), g))
+    r_ref = np.linalg.norm(b - W.apply_G(eta, gh, u_ref, g))
+    assert r <= 2.0 * max(r_ref, 1e-12 * np.linalg.norm(b)), (r, r_ref)
+
+
+@pytest.mark.parametrize("g", [GRIDS[1], GRIDS[3], GRIDS[6], GRIDS[8]], ids=[IDS[1], IDS[3], IDS[6], IDS[8]])
+def test_mixed_and_gmres_and_warm_start(ctx, g):
+    from paper_2506_16045_amd import sgn
+    eta, h, b = _fields(g, 33)
+    gh, fl = W.bathy_gradient(h, g)
+    u_ref, _, ok, _ = W.pcg_solve(eta, gh, fl, b, g, tol=1e-13)
+    assert ok
+    bound = 2.0 * max(np.linalg.norm(b - W.apply_G(eta, gh, u_ref, g)), 1e-11 * np.linalg.norm(b))
+    u, res = ctx.krylov_solve(g, _t(eta), _t(gh), _t(b),
+                              opts=sgn.solve_opts(tol=1e-11, precision=sgn.MIXED, inner_tol=1e-4))
+    assert res.converged and res.outer_iters >= 1
+    assert np.linalg.norm(b - W.apply_G(eta, gh, _n(u), g)) <= bound
+    assert rel(_n(u), u_ref) <= 1e-9
+    u, res = ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), opts=sgn.solve_opts(tol=1e-11, method=sgn.GMRES))
+    assert res.converged and res.relres <= 1e-11
+    # GMRES stops right at the tolerance on the twin; the oracle's operator adds its own rounding
+    assert np.linalg.norm(b - W.apply_G(eta, gh, _n(u), g)) <= 2.0 * bound
+    # a warm start at the solution takes no iteration
+    u0 = _t(u_ref)
+    _, res = ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), u=u0, opts=sgn.solve_opts(tol=1e-11, x0_is_guess=True))
+    assert res.converged and res.iters == 0
+
+
+def test_periodic_only_entry_points_reject_walls(ctx):
+    import torch
+    from paper_2506_16045_amd import sgn
+    g = GRIDS[6]
+    x = torch.ones(g.shape, dtype=torch.float64, device="cuda")
+    v = torch.zeros((2,) + g.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(sgn.SgnError) as ei:
+        ctx.rhs(g, x, x, v, v)
+    assert ei.value.status == sgn.EUNSUPPORTED
+    assert sgn.state_workspace_bytes(g) == 0 and sgn.dealias_workspace_bytes(g) == 0
+    # too large to reflect: the twin would exceed the periodic limits
+    assert sgn.workspace_bytes(I.grid2d_walls(64, 1024, 1.0, 1.0)) == 0
+    assert sgn.workspace_bytes(I.grid1d_walls(16384, 1.0)) == 0
+    assert sgn.workspace_bytes(g) > sgn.workspace_bytes(I.grid2d(64, 64, 5.0, 5.0))
