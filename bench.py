@@ -221,6 +221,78 @@ def bench_coeffs(args):
     return 0
 
 
+def cpu_baseline_walls(cfg):
+    """The oracle's wall PCG (cosine / sine series), as it stands, on the same solve."""
+    from oracle import walls as W
+    g = cfg["grid"]
+    gh, fl = W.bathy_gradient(cfg["h"], g)
+    t0 = time.perf_counter()
+    _, it, ok, _ = W.pcg_solve(cfg["eta"], gh, fl, cfg["b"], g, tol=cfg["tol"])
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one solve ({dt:.1f} s, FP64 NumPy/SciPy DCT-DST, single thread; {it} iterations)"}
+
+
+def bench_walls(args):
+    """Constraint solves in a closed basin (walls): solves/s of the library's wall path
+    (reflection onto the periodic twin), FP64 and mixed, with the PCG kernels timed."""
+    import numpy as np
+    import torch
+
+    from paper_2506_16045_amd import inputs as I
+    from paper_2506_16045_amd import sgn
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = I.config_walls(args.n // 2 if args.n > 512 else args.n)
+    g = cfg["grid"]
+    ctx = sgn.Context(0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    gh, flat = ctx.bathy_prepare(g, to(cfg["h"]))
+    e_d, b_d = to(cfg["eta"]), to(cfg["b"])
+    res_by = {}
+    for prec_name, prec in (("fp64", sgn.FP64), ("mixed", sgn.MIXED)):
+        opts = sgn.solve_opts(tol=cfg["tol"], precision=prec, check_every=args.check_every, inner_tol=args.inner_tol)
+        for _ in range(max(args.warmup, 1)):
+            ctx.krylov_solve(g, e_d, gh, b_d, opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            u, res = ctx.krylov_solve(g, e_d, gh, b_d, opts=opts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.profile_begin()
+        ctx.krylov_solve(g, e_d, gh, b_d, opts=opts)
+        prof = ctx.profile_end()
+        res_by[prec_name] = {"solves_per_s": args.steps / el, "ms_per_solve": 1e3 * el / args.steps,
+                             "iters": res.iters, "outer_iters": res.outer_iters, "relres": res.relres,
+                             "converged": res.converged,
+                             "kernel_avg_us": {k: round(1e3 * v[1] / v[0], 2) for k, v in prof.items() if v[0]}}
+    main = res_by["fp64"]
+    kind = "pcg_r1"
+    twin = (2 * g.nx, 2 * g.ny)
+    nbytes = kernel_bytes(kind, 2, twin[0], twin[1], 8)
+    avg = main["kernel_avg_us"].get(kind)
+    roof = None
+    if avg:
+        ach = nbytes / (avg * 1e-6) / 1e9
+        roof = {"bound": "hbm", "kernel": kind, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes,
+                "avg_launch_us": avg, "timing": "HIP events around every launch of one further solve"}
+    out = {"metric": "constraint solves/s in a closed basin (walls)", "value": main["solves_per_s"],
+           "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": main["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"walls basin {g.nx}x{g.ny} cells on {g.Lx:g}x{g.Ly:g} (periodic twin "
+                                  f"{twin[0]}x{twin[1]}), Gaussian bump bathymetry, surface hump, tol {cfg['tol']:g}, "
+                                  "zero initial guess", "parallelism": "single GPU"},
+           "precisions": res_by, "roofline": roof,
+           "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_walls(cfg),
+           "device": torch.cuda.get_device_name(0)}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
 def bench_batch(args):
     import numpy as np
     import torch
@@ -476,7 +548,7 @@ def cpu_baseline_batch(systems, tol, count):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["rk4-2d", "batch", "serve", "coeffs"], default="rk4-2d")
+    ap.add_argument("--workload", choices=["rk4-2d", "batch", "serve", "coeffs", "walls"], default="rk4-2d")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="arrival rates of the serve workload")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per rate (serve workload)")
     ap.add_argument("--lanes", type=int, default=3, help="worker lanes of the server (serve workload)")
@@ -541,6 +613,8 @@ def main(argv=None):
         return bench_serve(args)
     if args.workload == "coeffs":
         return bench_coeffs(args)
+    if args.workload == "walls":
+        return bench_walls(args)
 
     import numpy as np
     import torch

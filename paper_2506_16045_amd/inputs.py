@@ -239,6 +239,25 @@ def elliptical_bump_2d(n: int, a: float, b: float, r0: float = 0.5):
     return g, eta, h, rhs
 
 
+def config_walls(n: int = 512, L: float = 200.0):
+    """A closed basin for the wall solve (reading: the paper runs no test with walls):
+    [0, L]^2 with walls, n x n cells, bathymetry of the 2D workload (h0 = 1, Gaussian
+    bump of height 0.5 and radius 10 at the centre), a Gaussian hump of height 0.2
+    and radius 15 at (L/4, L/2) on the surface, and the right-hand side U = b of
+    a velocity field that vanishes on the walls: u = 0.3 sin(pi x / L) cos(pi y / L)
+    * (1 + 0.2 sin(3 pi x / L)), v = 0.3 cos(pi x / L) sin(2 pi y / L), given as the
+    constraint's input b = eta u (the momentum without the dispersive terms)."""
+    g = grid2d_walls(n, n, L, L)
+    X, Y = coords(g)
+    h = 1.0 - 0.5 * np.exp(-((X - L / 2) ** 2 + (Y - L / 2) ** 2) / 10.0 ** 2)
+    zeta = 0.2 * np.exp(-((X - L / 4) ** 2 + (Y - L / 2) ** 2) / 15.0 ** 2)
+    eta = h + zeta
+    u = 0.3 * np.sin(np.pi * X / L) * np.cos(np.pi * Y / L) * (1.0 + 0.2 * np.sin(3 * np.pi * X / L))
+    v = 0.3 * np.cos(np.pi * X / L) * np.sin(2 * np.pi * Y / L)
+    b = np.stack([eta * u, eta * v])
+    return {"grid": g, "h": h, "eta": eta, "b": b, "tol": 1e-10}
+
+
 def random_smooth_field(g: Grid, rng, modes: int = 4, amp: float = 1.0):
     """A random band-limited periodic field (a few low Fourier modes)."""
     if g.d == 1:
