@@ -521,7 +521,43 @@ __device__ __forceinline__ void col_fft_regs(const ColGeom& g, const ColThread<T
     __syncthreads();
 }
 
-template <typename T, int EPC, int NI>
+// NF register columns of a block through one y-FFT in lockstep (shared barriers):
+// fields f < nf of v go to LDS (field stride ct.fstride), are transformed and
+// read back.
+template <typename T, int EPC, int NF>
+__device__ __forceinline__ void col_fft_group(const ColGeom& g, const ColThread<T>& ct, const cpx<T>* twm,
+                                              cpx<T> (*v)[EPC], bool inverse) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+            if (j < g.ny) ct.buf[f * ct.fstride + j] = v[f][e];
+        }
+    __syncthreads();
+    lds_fft<T, EPC, NF>(ct.buf, ct.fstride, g.ny, ct.t, g.TPC, twm, inverse);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+            if (j < g.ny) v[f][e] = ct.buf[f * ct.fstride + j];
+        }
+    __syncthreads();
+}
+
+// The first nf (1..3) register columns of v through one lockstep y-FFT.
+template <typename T, int EPC, int NMAX>
+__device__ __forceinline__ void col_fft_first(const ColGeom& g, const ColThread<T>& ct, const cpx<T>* twm,
+                                              cpx<T> (&v)[NMAX][EPC], int nf, bool inverse) {
+    if (nf == 1) col_fft_group<T, EPC, 1>(g, ct, twm, v, inverse);
+    else if (nf == 2 || NMAX < 3) col_fft_group<T, EPC, (NMAX < 2 ? NMAX : 2)>(g, ct, twm, v, inverse);
+    else col_fft_group<T, EPC, (NMAX < 3 ? NMAX : 3)>(g, ct, twm, v, inverse);
+}
+
+// LK: columns per lockstep transform, 3 (LDS holds three columns per block) or 1
+// (one at a time, for columns of 2048 where three would leave one block per CU).
+template <typename T, int EPC, int NI, int LK>
 __global__ void __launch_bounds__(256) k_cols_lin_jobs(ColGeom g, LinJobs<T> jobs, const cpx<T>* __restrict__ tw,
                                                         T tpx, T tpy, T scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -529,7 +565,8 @@ __global__ void __launch_bounds__(256) k_cols_lin_jobs(ColGeom g, LinJobs<T> job
     const int jb = blockIdx.x / g.nblocks;
     if (jb >= jobs.n) return;
     const LinJob<T>& J = jobs.j[jb];
-    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, 1));
+    constexpr int NL = LK == 1 ? 1 : (NI < 3 ? NI : 3);
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, NL));
     ColThread<T> ct;
     ct.c = threadIdx.x / g.TPC;
     ct.t = threadIdx.x - ct.c * g.TPC;
@@ -547,31 +584,50 @@ __global__ void __launch_bounds__(256) k_cols_lin_jobs(ColGeom g, LinJobs<T> job
             in[i][e] = (i < J.ni && ct.valid && j < ny) ? J.src[i][(size_t)ct.kx * ny + j] : C<T>(0, 0);
         }
     }
-    if (ny > 1) {
+    if (ny > 1 && LK == 1) {
 #pragma unroll
         for (int i = 0; i < NI; ++i)
-            if (i < J.ni) col_fft_regs<T, EPC>(g, ct, twm, in[i], false);
+            if (i < J.ni) col_fft_group<T, EPC, 1>(g, ct, twm, in + i, false);
+    } else if (ny > 1) {
+        // the inputs in groups of up to three sharing their transform's barriers
+        if (NI <= 3 || J.ni <= 3) {
+            col_fft_first<T, EPC, NI>(g, ct, twm, in, J.ni, false);
+        } else {
+            col_fft_first<T, EPC, NI>(g, ct, twm, in, 3, false);
+            col_fft_group<T, EPC, 1>(g, ct, twm, in + 3, false);
+        }
     }
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
+    cpx<T> out[LINJ_MAXO][EPC];
 #pragma unroll
     for (int o = 0; o < LINJ_MAXO; ++o) {
-        if (o >= J.no) break;
-        cpx<T> v[EPC];
 #pragma unroll
         for (int e = 0; e < EPC; ++e) {
             const int j = ct.t + g.TPC * e;
             const T ky = (ny > 1) ? wavenumber<T>(j, ny, tpy) : (T)0;
             cpx<T> s = C<T>(0, 0);
+            if (o < J.no) {
 #pragma unroll
-            for (int i = 0; i < NI; ++i) s = s + lin_coef<T>(J.code[o][i], kx, ky) * in[i][e];
-            v[e] = scale * s;
+                for (int i = 0; i < NI; ++i) s = s + lin_coef<T>(J.code[o][i], kx, ky) * in[i][e];
+            }
+            out[o][e] = scale * s;
         }
-        if (ny > 1) col_fft_regs<T, EPC>(g, ct, twm, v, true);
-        if (ct.valid) {
+    }
+    if (ny > 1 && LK == 1) {
+#pragma unroll
+        for (int o = 0; o < LINJ_MAXO; ++o)
+            if (o < J.no) col_fft_group<T, EPC, 1>(g, ct, twm, out + o, true);
+    } else if (ny > 1) {
+        col_fft_first<T, EPC, LINJ_MAXO>(g, ct, twm, out, J.no, true);
+    }
+    if (ct.valid) {
+#pragma unroll
+        for (int o = 0; o < LINJ_MAXO; ++o) {
+            if (o >= J.no) break;
 #pragma unroll
             for (int e = 0; e < EPC; ++e) {
                 const int j = ct.t + g.TPC * e;
-                if (j < ny) J.dst[o][(size_t)ct.kx * ny + j] = v[e];
+                if (j < ny) J.dst[o][(size_t)ct.kx * ny + j] = out[o][e];
             }
         }
     }

@@ -454,7 +454,9 @@ sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSp
     for (int k = 0; k < J.n; ++k) maxi = std::max(maxi, J.j[k].ni);
     const int epc = col_epc(d.ny);
     ColLaunch L = col_launch<double>(d.nx, d.ny, epc);
-    const size_t lds = col_lds_bytes<double>(L.g, 1);
+    // the inputs, then the outputs, are transformed up to three at a time in lockstep
+    // (one at a time for columns of 2048)
+    const size_t lds = col_lds_bytes<double>(L.g, epc == 8 ? 1 : 3);
     auto launch = [&](auto k) -> sgn_status {
         HIPCHK(ctx, allow_lds(k, lds));
         hipLaunchKernelGGL(k, dim3(L.g.nblocks * J.n), dim3(L.threads), lds, ctx->stream, L.g, J, ctx->tw64, d.tpx,
@@ -465,9 +467,9 @@ sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSp
     // registers for the inputs are sized by the widest job
     if (epc == 8) {
         if (maxi > 3) return fail(ctx, SGN_EINVAL, "cols_lin_jobs: columns of 2048 take at most 3 inputs");
-        return launch(k_cols_lin_jobs<double, 8, 3>);
+        return launch(k_cols_lin_jobs<double, 8, 3, 1>);
     }
-    return maxi <= 3 ? launch(k_cols_lin_jobs<double, 4, 3>) : launch(k_cols_lin_jobs<double, 4, 4>);
+    return maxi <= 3 ? launch(k_cols_lin_jobs<double, 4, 3, 3>) : launch(k_cols_lin_jobs<double, 4, 4, 3>);
 }
 
 // ---------------------------------------------------------------------------
