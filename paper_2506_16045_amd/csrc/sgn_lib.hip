@@ -182,17 +182,22 @@ struct RowLaunch {
     size_t lds;
     int epc;
 };
+// pcg: the row pass of the Krylov iteration on 2D rows of 512 to 1024 points
+// takes two entries per thread and 512-thread blocks of the same rows, so that
+// twice as many waves are resident to hide the transposed accesses' latency
+// (the grid has only ny / R blocks).
 template <typename T>
-RowLaunch row_launch(int nx, int ny) {
+RowLaunch row_launch(int nx, int ny, bool pcg = false) {
     RowLaunch L;
     const int M = nx / 2;
-    L.epc = (M > 4096) ? 8 : 4;
+    const bool two = pcg && ny > 1 && M >= 256 && M <= 512;
+    L.epc = two ? 2 : (M > 4096) ? 8 : 4;
     RowGeom& g = L.g;
     g.nx = nx;
     g.ny = ny;
     g.M = M;
     g.TPR = M / L.epc > 0 ? M / L.epc : 1;
-    int R = 256 / g.TPR;
+    int R = (two ? 512 : 256) / g.TPR;
     if (R < 1) R = 1;
     const int np = next_pow2(ny);
     if (R > np) R = np;
@@ -634,7 +639,9 @@ sgn_status pcg_r1(PcgLaunch<T, D>& P, bool curvature = false) {
         return SGN_OK;
     };
     sgn_status st;
-    if (L.epc == 4)
+    if (L.epc == 2)
+        st = seq ? launch(k_pcg_r1<T, 2, D, true, 512>) : launch(k_pcg_r1<T, 2, D, false, 512>);
+    else if (L.epc == 4)
         st = L.threads <= 256
                  ? (seq ? launch(k_pcg_r1<T, 4, D, true, 256>) : launch(k_pcg_r1<T, 4, D, false, 256>))
                  : (seq ? launch(k_pcg_r1<T, 4, D, true>) : launch(k_pcg_r1<T, 4, D, false>));
@@ -961,7 +968,7 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     PcgLaunch<double, D> P;
     P.ctx = ctx;
     P.d = d;
-    P.rl = row_launch<double>(d.nx, d.ny);
+    P.rl = row_launch<double>(d.nx, d.ny, true);
     P.cl = col_launch<double>(d.nx, d.ny);
     P.b = carve_pcg<double>(cv, d, false);
     P.sc = cm.sc;
@@ -1049,7 +1056,7 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     PcgLaunch<double, D> P;
     P.ctx = ctx;
     P.d = d;
-    P.rl = row_launch<double>(d.nx, d.ny);
+    P.rl = row_launch<double>(d.nx, d.ny, true);
     P.cl = col_launch<double>(d.nx, d.ny);
     P.b = carve_pcg<double>(cv, d, true);
     P.sc = cm.sc;
@@ -1059,7 +1066,7 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     PcgLaunch<float, D> Q;
     Q.ctx = ctx;
     Q.d = d;
-    Q.rl = row_launch<float>(d.nx, d.ny);
+    Q.rl = row_launch<float>(d.nx, d.ny, true);
     Q.cl = col_launch<float>(d.nx, d.ny);
     Q.b = carve_pcg<float>(cv, d, false);
     Q.sc = cm.sc + 1;
@@ -1261,7 +1268,7 @@ sgn_status solve_gmres(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     auto& P = G.P;
     P.ctx = ctx;
     P.d = d;
-    P.rl = row_launch<double>(d.nx, d.ny);
+    P.rl = row_launch<double>(d.nx, d.ny, true);
     P.cl = col_launch<double>(d.nx, d.ny);
     P.b = carve_pcg<double>(cv, d, false);
     P.sc = cm.sc;
@@ -1595,7 +1602,7 @@ sgn_status apply_G(sgn_ctx* ctx, const Dims& d, const double* eta, const double*
     PcgLaunch<double, D> P;
     P.ctx = ctx;
     P.d = d;
-    P.rl = row_launch<double>(d.nx, d.ny);
+    P.rl = row_launch<double>(d.nx, d.ny, true);
     P.cl = col_launch<double>(d.nx, d.ny);
     P.b = carve_pcg<double>(cv, d, false);
     P.sc = cm.sc;
@@ -2318,7 +2325,7 @@ sgn_status sbdf2_R(sgn_state* st, cpx<double>* Rout) {
     PcgLaunch<double, D> P;
     P.ctx = ctx;
     P.d = d;
-    P.rl = row_launch<double>(d.nx, d.ny);
+    P.rl = row_launch<double>(d.nx, d.ny, true);
     P.cl = col_launch<double>(d.nx, d.ny);
     P.b = carve_pcg<double>(cv, d, false);
     P.sc = cm.sc;
