@@ -494,14 +494,17 @@ __device__ __forceinline__ void block_sum(double (&v)[NACC], double* red /*LDS, 
 }
 
 // Sum of the per-block partials (layout partials[NACC*b + a]) by the whole
-// last block: thread t adds blocks t, t+blockDim, ... in order, then the fixed
-// block tree; the result is in thread 0.  Every thread of the block must call it.
+// last block: thread t < 256 adds blocks t, t+256, ... in order, then the fixed
+// block tree (further threads and waves add zeros); the result is in thread 0.
+// The order, and so the value, is the same in every kernel that reduces the same
+// partials, whatever its block size (at least 256 threads).  Every thread of the
+// block must call it.
 template <int NACC>
 __device__ __forceinline__ void final_sum(const double* __restrict__ partials, unsigned nblocks,
                                           double (&v)[NACC], double* red) {
 #pragma unroll
     for (int a = 0; a < NACC; ++a) v[a] = 0.0;
-    for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    for (unsigned b = threadIdx.x; threadIdx.x < 256 && b < nblocks; b += 256) {
 #pragma unroll
         for (int a = 0; a < NACC; ++a) v[a] += partials[(size_t)NACC * b + a];
     }
