@@ -182,15 +182,15 @@ struct RowLaunch {
     size_t lds;
     int epc;
 };
-// pcg: the row pass of the Krylov iteration on 2D rows of 512 to 1024 points
-// takes two entries per thread and 512-thread blocks of the same rows, so that
-// twice as many waves are resident to hide the transposed accesses' latency
-// (the grid has only ny / R blocks).
+// wide: on 2D rows of 512 to 1024 points, two entries per thread and
+// 512-thread blocks of the same rows, so that twice as many waves are resident
+// to hide the transposed accesses' latency (the grid has only ny / R blocks);
+// taken by the Krylov row pass and the plain row transforms.
 template <typename T>
-RowLaunch row_launch(int nx, int ny, bool pcg = false) {
+RowLaunch row_launch(int nx, int ny, bool wide = false) {
     RowLaunch L;
     const int M = nx / 2;
-    const bool two = pcg && ny > 1 && M >= 256 && M <= 512;
+    const bool two = wide && ny > 1 && M >= 256 && M <= 512;
     L.epc = two ? 2 : (M > 4096) ? 8 : 4;
     RowGeom& g = L.g;
     g.nx = nx;
@@ -316,7 +316,7 @@ template <typename T, typename Tin>
 sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, std::vector<cpx<T>*> dst,
                     T scale = (T)1, const RowCombo<Tin>* cmb = nullptr) {
     ProfScope ps(ctx, SGN_KERNEL_ROWS);
-    RowLaunch L = row_launch<T>(d.nx, d.ny);
+    RowLaunch L = row_launch<T>(d.nx, d.ny, true);
     RowCombo<Tin> none{};
     none.first = -1;
     if (cmb && src.size() > (size_t)MAXF) return fail(ctx, SGN_EINVAL, "rows_fwd: combined sources exceed one pass");
@@ -338,7 +338,9 @@ sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, st
             return SGN_OK;
         };
         sgn_status st;
-        if (L.epc == 4)
+        if (L.epc == 2)
+            st = multi ? launch(k_rows_fwd<T, Tin, 2, 3, 512>) : launch(k_rows_fwd<T, Tin, 2, 1, 512>);
+        else if (L.epc == 4)
             st = L.threads <= 256
                      ? (multi ? launch(k_rows_fwd<T, Tin, 4, 3, 256>) : launch(k_rows_fwd<T, Tin, 4, 1, 256>))
                      : (multi ? launch(k_rows_fwd<T, Tin, 4, 3>) : launch(k_rows_fwd<T, Tin, 4, 1>));
@@ -356,7 +358,7 @@ template <typename T, typename Tout>
 sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src, std::vector<Tout*> dst,
                     T scale = (T)1, T acc = (T)0, const std::vector<Tout*>* offs = nullptr, bool offs_acc = false) {
     ProfScope ps(ctx, SGN_KERNEL_ROWS);
-    RowLaunch L = row_launch<T>(d.nx, d.ny);
+    RowLaunch L = row_launch<T>(d.nx, d.ny, true);
     if (offs && offs->size() != src.size()) return fail(ctx, SGN_EINVAL, "rows_inv: offsets per field");
     for (size_t f0 = 0; f0 < src.size(); f0 += MAXF) {
         PtrList<const cpx<T>, MAXF> s{};
@@ -378,7 +380,9 @@ sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src,
             return SGN_OK;
         };
         sgn_status st;
-        if (L.epc == 4)
+        if (L.epc == 2)
+            st = multi ? launch(k_rows_inv<T, Tout, 2, 3, 512>) : launch(k_rows_inv<T, Tout, 2, 1, 512>);
+        else if (L.epc == 4)
             st = L.threads <= 256
                      ? (multi ? launch(k_rows_inv<T, Tout, 4, 3, 256>) : launch(k_rows_inv<T, Tout, 4, 1, 256>))
                      : (multi ? launch(k_rows_inv<T, Tout, 4, 3>) : launch(k_rows_inv<T, Tout, 4, 1>));
@@ -1690,6 +1694,8 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     for (int i = 0; i < nd2 + 1; ++i) dB.push_back(HB + i * NS);
     // the fused right-hand-side row passes transform their fields one at a time
     // (lockstep groups need more registers than the pointwise state leaves)
+    // (the fused right-hand-side row passes keep 256-thread blocks: their pointwise
+    // state makes the wide launch slower)
     const RowLaunch RL = row_launch<double>(d.nx, d.ny);
     const size_t rlds = row_lds_bytes<double>(RL.g, 1);
     {
