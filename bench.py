@@ -605,8 +605,8 @@ def main(argv=None):
         return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
-              "(multi-GPU sharding is described in the design notes, not run)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library's path is single-GPU "
+              "(how it would shard across GPUs is described in the design notes; it is not run)", file=sys.stderr)
         return 2
 
     if args.workload == "batch":
