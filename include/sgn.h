@@ -101,11 +101,8 @@ typedef enum sgn_coeff_kind {
  * open).  Every such solve has a slot (RK4 stages 2, 3, 4, the final RK4
  * solve, the Adams-Bashforth solve) and a base, the most recent velocity.
  * PREVIOUS starts from the base.  EXTRAPOLATE records the slot's offset
- * o_n = solution - base and starts from the next value of the polynomial
- * through the recorded offsets: base + o_{n-1} (one recorded),
- * base + 2 o_{n-1} - o_{n-2} (two), and in the RK4 stage slots
- * base + 3 o_{n-1} - 3 o_{n-2} + o_{n-3} (three; the final RK4 and the
- * Adams-Bashforth slots stay linear); the offsets are cleared when dt changes.  The
+ * o_n = solution - base and starts from base + o_{n-1} (one recorded) or
+ * base + 2 o_{n-1} - o_{n-2}; the offsets are cleared when dt changes.  The
  * guess moves the start of the iteration only: every solve still stops on
  * its residual. */
 typedef enum sgn_guess {

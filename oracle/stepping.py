@@ -51,18 +51,14 @@ class GuessHistory:
     Adams-Bashforth solve) and a base: the most recent velocity when the solve
     starts.  mode 'previous' starts every solve from its base (plain warm
     start).  mode 'extrapolate' records the slot's offset o_n = solution - base
-    after every solve and starts the next solve of that slot from the value at
-    the next step of the polynomial through the recorded offsets: base + o_{n-1}
-    (one offset recorded), base + 2 o_{n-1} - o_{n-2} (two), and for the RK4
-    stage slots base + 3 o_{n-1} - 3 o_{n-2} + o_{n-3} (three or more; the
-    final RK4 solve and the Adams-Bashforth solve stay linear: their offsets
-    are small and a quadratic extrapolation amplifies their noise).  The
-    offsets scale with the step, so a change of dt clears them.  A guess only
-    changes where the Krylov iteration starts, not the solution it converges
-    to (the stop test is on the residual)."""
+    after every solve and starts the next solve of that slot from
+    base + o_{n-1} (one offset recorded) or base + 2 o_{n-1} - o_{n-2} (two or
+    more), the value at the next step of the polynomial through the recorded
+    offsets.  The offsets scale with the step, so a change of dt clears them.
+    A guess only changes where the Krylov iteration starts, not the solution
+    it converges to (the stop test is on the residual)."""
 
     SLOTS = ("rk2", "rk3", "rk4", "rk_final", "ab")
-    QUADRATIC = ("rk2", "rk3", "rk4")
 
     def __init__(self, mode: str = "extrapolate"):
         if mode not in ("previous", "extrapolate"):
@@ -86,16 +82,14 @@ class GuessHistory:
             return base
         if len(o) == 1:
             return base + o[-1]
-        if len(o) == 2 or slot not in self.QUADRATIC:
-            return base + (2.0 * o[-1] - o[-2])
-        return base + (3.0 * o[-1] - 3.0 * o[-2] + o[-3])
+        return base + (2.0 * o[-1] - o[-2])
 
     def record(self, slot, base, solution):
         if self.mode == "previous":
             return
         o = self.offsets[slot]
         o.append(solution - base)
-        del o[:-3]
+        del o[:-2]
 
 
 @dataclass

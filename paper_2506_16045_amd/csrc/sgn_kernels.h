@@ -83,8 +83,7 @@ template <typename Tin>
 struct RowCombo {
     const Tin* a[4];
     const Tin* b[4];
-    const Tin* cc[4];
-    double c1, c2, c3;
+    double c1, c2;
     int first;
 };
 
@@ -114,7 +113,6 @@ __device__ __forceinline__ void rows_fwd_group(const RowGeom& g, const RowThread
                     for (int s = 0; s < 2; ++s) {
                         double t = cmb.c1 * (double)cmb.a[k][o + s];
                         if (cmb.b[k]) t += cmb.c2 * (double)cmb.b[k][o + s];
-                        if (cmb.cc[k]) t += cmb.c3 * (double)cmb.cc[k][o + s];
                         v[s] = (double)src.p[f0 + f][o + s] + t;
                     }
                     z[f][e] = C<T>((T)v[0], (T)v[1]);

@@ -54,12 +54,11 @@ struct sgn_ctx {
     size_t hbatch_bytes = 0;
     int slot = GUESS_SLOTS;       // stepper slot of the running solve
     // extrapolated guess of a stepper solve on the FP64 row/column path: the solve
-    // reads u (the base) + (gx_c1 gx_a + gx_c2 gx_b + gx_c3 gx_c) while transforming it, and
+    // reads u (the base) + (gx_c1 gx_a + gx_c2 gx_b) while transforming it, and
     // writes its result's offset from the base to gx_off while storing it
     const double* gx_a = nullptr;
     const double* gx_b = nullptr;
-    const double* gx_c = nullptr;
-    double gx_c1 = 0.0, gx_c2 = 0.0, gx_c3 = 0.0;
+    double gx_c1 = 0.0, gx_c2 = 0.0;
     double* gx_off = nullptr;
     // readbacks in the solve loops wait by polling this event: a blocking stream
     // synchronisation wakes the host tens of microseconds after the GPU is done,
@@ -709,11 +708,9 @@ sgn_status pcg_start(PcgLaunch<double, D>& P, const double* rhs, const double* u
             cmb.first = D;
             cmb.c1 = ctx->gx_c1;
             cmb.c2 = ctx->gx_c2;
-            cmb.c3 = ctx->gx_c3;
             for (int c = 0; c < D; ++c) {
                 cmb.a[c] = ctx->gx_a + c * d.N;
                 cmb.b[c] = ctx->gx_b ? ctx->gx_b + c * d.N : nullptr;
-                cmb.cc[c] = ctx->gx_c ? ctx->gx_c + c * d.N : nullptr;
             }
         }
     }
@@ -2038,7 +2035,7 @@ struct StateBufs {
     double *eta_s, *U_s, *u_s;              // RK4 stage values
     double *eta_prev, *U_prev, *fe_prev, *fU_prev, *tmp_e, *tmp_U;  // SBDF2 history
     cpx<double>*R_prev, *R_cur, *uh, *Uh, *Hs;                        // SBDF2 spectral
-    double* gx_off[GUESS_SLOTS][3];  // recorded offsets of each stepper slot (ring of three)
+    double* gx_off[GUESS_SLOTS][2];  // recorded offsets of each stepper slot (ring of two)
     double* gx_base;                 // base velocity of the running solve
 };
 
@@ -2066,7 +2063,7 @@ size_t carve_state(Carve& cv, const Dims& d, StateBufs* b) {
     t.Uh = cv.take<cpx<double>>(DS);
     t.Hs = cv.take<cpx<double>>((size_t)(d.D + 1) * d.NS);
     for (int k = 0; k < GUESS_SLOTS; ++k)
-        for (int l = 0; l < 3; ++l) t.gx_off[k][l] = cv.take<double>(DN);
+        for (int l = 0; l < 2; ++l) t.gx_off[k][l] = cv.take<double>(DN);
     t.gx_base = cv.take<double>(DN);
     if (b) *b = t;
     return cv.off;
@@ -2202,37 +2199,23 @@ sgn_status stage_solve(sgn_state* st, int slot, const double* eta, const double*
     sgn_status s;
     int& cnt = st->gx_count[slot];
     int& head = st->gx_head[slot];
-    // ring of three: newest at head, then (head + 2) % 3, then (head + 1) % 3, which
-    // the new offset replaces (it is read when the guess is formed, before the
-    // solve writes the new one, in stream order)
-    const int nh = cnt == 0 ? head : (head + 1) % 3;
-    const double* o1 = b.gx_off[slot][head];
-    const double* o2 = b.gx_off[slot][(head + 2) % 3];
-    const double* o3 = b.gx_off[slot][(head + 1) % 3];
-    // the polynomial through the recorded offsets: constant, line, or (RK4 stage
-    // slots) parabola
-    const bool quad = cnt >= 3 && slot <= GUESS_RK4;
-    const int nterms = quad ? 3 : std::min(cnt, 2);
-    const double c1 = quad ? 3.0 : (nterms == 2 ? 2.0 : 1.0);
-    const double c2 = quad ? -3.0 : -1.0;
+    const int nh = cnt == 0 ? head : head ^ 1;
     if (fused) {
-        ctx->gx_a = nterms >= 1 ? o1 : nullptr;
-        ctx->gx_b = nterms >= 2 ? o2 : nullptr;
-        ctx->gx_c = nterms >= 3 ? o3 : nullptr;
-        ctx->gx_c1 = c1;
-        ctx->gx_c2 = c2;
-        ctx->gx_c3 = 1.0;
+        ctx->gx_a = cnt >= 1 ? b.gx_off[slot][head] : nullptr;
+        ctx->gx_b = cnt >= 2 ? b.gx_off[slot][head ^ 1] : nullptr;
+        ctx->gx_c1 = cnt >= 2 ? 2.0 : 1.0;
+        ctx->gx_c2 = -1.0;
         ctx->gx_off = b.gx_off[slot][nh];
     } else if (ex) {
         // keep the base and form the guess in place, in one pass
-        if (nterms == 0) {
+        if (cnt == 0) {
             if ((s = copy_d(ctx, b.gx_base, u, DN)) != SGN_OK) return s;
-        } else if (nterms == 1) {
-            if ((s = lincomb_jobs(ctx, {{u, u, 1.0, {o1}, {1.0}, DN, b.gx_base}})) != SGN_OK) return s;
-        } else if (nterms == 2) {
-            if ((s = lincomb_jobs(ctx, {{u, u, 1.0, {o1, o2}, {c1, c2}, DN, b.gx_base}})) != SGN_OK) return s;
+        } else if (cnt == 1) {
+            if ((s = lincomb_jobs(ctx, {{u, u, 1.0, {b.gx_off[slot][head]}, {1.0}, DN, b.gx_base}})) != SGN_OK)
+                return s;
         } else {
-            if ((s = lincomb_jobs(ctx, {{u, u, 1.0, {o1, o2, o3}, {c1, c2, 1.0}, DN, b.gx_base}})) != SGN_OK)
+            if ((s = lincomb_jobs(ctx, {{u, u, 1.0, {b.gx_off[slot][head], b.gx_off[slot][head ^ 1]}, {2.0, -1.0},
+                                         DN, b.gx_base}})) != SGN_OK)
                 return s;
         }
     }
@@ -2247,7 +2230,7 @@ sgn_status stage_solve(sgn_state* st, int slot, const double* eta, const double*
     ctx->stage = false;
     ctx->slot = GUESS_SLOTS;
     ctx->stage_last = nullptr;
-    ctx->gx_a = ctx->gx_b = ctx->gx_c = nullptr;
+    ctx->gx_a = ctx->gx_b = nullptr;
     ctx->gx_off = nullptr;
     account(acc, si);
     if (s != SGN_OK) {
@@ -2257,7 +2240,7 @@ sgn_status stage_solve(sgn_state* st, int slot, const double* eta, const double*
     if (ex) {
         if (!fused && (s = lincomb(ctx, DN, u, 1.0, {b.gx_base}, {-1.0}, b.gx_off[slot][nh])) != SGN_OK) return s;
         head = nh;
-        if (cnt < 3) cnt += 1;
+        if (cnt < 2) cnt += 1;
     }
     return SGN_OK;
 }
