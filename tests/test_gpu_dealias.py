@@ -181,3 +181,17 @@ def test_dealiasing_switched_off_returns_to_plain_steps(ctx):
     ref = ost.run_rk4(pb, *ref, 0.05, 2)
     _compare(st, h, ref, 1e-10)
     st.close()
+
+
+def test_mixed_precision_steps_with_dealiasing(ctx):
+    """The right-hand side is FP64 whatever the solve precision: RK4 with the mixed
+    solve and the de-aliased right-hand side against the oracle (FP64 solves)."""
+    from paper_2506_16045_amd import sgn
+    g, h, eta, u = case_2d_bump()
+    st, pb, U0 = _state(ctx, g, h, eta, u, 1e-13)
+    st.set_dealias(True)
+    info = st.step_rk4(0.05, 4, sgn.solve_opts(tol=1e-11, precision=sgn.MIXED, inner_tol=1e-4))
+    assert info.converged
+    ref = ost.run_rk4(pb, eta, U0, u, 0.05, 4)
+    _compare(st, h, ref, 1e-9)
+    st.close()

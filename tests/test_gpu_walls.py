@@ -164,3 +164,19 @@ def test_periodic_only_entry_points_reject_walls(ctx):
     assert sgn.workspace_bytes(I.grid2d_walls(64, 1024, 1.0, 1.0)) == 0
     assert sgn.workspace_bytes(I.grid1d_walls(16384, 1.0)) == 0
     assert sgn.workspace_bytes(g) > sgn.workspace_bytes(I.grid2d(64, 64, 5.0, 5.0))
+
+
+def test_non_positive_depth_between_walls_is_rejected(ctx):
+    """A depth that is not strictly positive is a domain error on a wall grid as on a
+    periodic one (section 3.1 needs eta > 0); the output is left unchanged."""
+    import torch
+    from paper_2506_16045_amd import sgn
+    g = GRIDS[6]
+    eta, h, b = _fields(g, 34)
+    eta[3, 5] = -0.1
+    gh, _ = W.bathy_gradient(h, g)
+    u0 = torch.full((2,) + g.shape, 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(sgn.SgnError) as ei:
+        ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), u=u0, opts=sgn.solve_opts(tol=1e-10))
+    assert ei.value.status == sgn.EDOMAIN
+    assert torch.all(u0 == 7.0)
