@@ -328,7 +328,7 @@ size_t sgn_dealias_workspace_bytes(const sgn_grid *grid);
 
 /* The de-aliased eta_t, U_t; arguments as sgn_rhs, with d_dws of
  * sgn_dealias_workspace_bytes() bytes (contents not kept between calls).
- * SGN_EUNSUPPORTED for a grid above the limits. */
+ * SGN_EUNSUPPORTED for a grid above the limits or closed by walls. */
 sgn_status sgn_rhs_dealiased(sgn_ctx *ctx, const sgn_grid *grid, const double *d_eta,
                              const double *d_h, const double *d_grad_h, const double *d_u,
                              double *d_eta_t, double *d_U_t, void *d_dws);
@@ -338,7 +338,8 @@ sgn_status sgn_rhs_dealiased(sgn_ctx *ctx, const sgn_grid *grid, const double *d
  * to the state until it is destroyed or this is called again; d_dws = NULL goes
  * back to the plain form.  Either way a multistep (Adams-Bashforth or SBDF2)
  * history is cleared, since it holds right-hand sides of the form used so far.
- * The padded grad h is computed here, once. */
+ * The padded grad h is computed here, once.  SGN_EUNSUPPORTED (and the plain
+ * form kept) for a grid above the limits. */
 sgn_status sgn_state_set_dealias(sgn_ctx *ctx, sgn_state *state, void *d_dws);
 
 /* ---- served execution --------------------------------------------------
