@@ -118,11 +118,17 @@ class Problem:
     def G(self, eta, u):
         return op.apply_G(eta, self.grad_h, u, self.g)
 
+    def A(self, sigma, alpha, u):
+        return op.apply_A(sigma, alpha, u, self.g)
+
+    def A_inv(self, sigma, alpha, r):
+        return op.solve_A(sigma, alpha, r, self.g)
+
     def solve(self, eta, U, x0):
         """PCG solve of G_{eta,h} u = U, A built from the current eta."""
         s, a, _ = op.coefficients(eta, self.grad_h, self.flat)
         u, it, ok, _ = krylov.pcg(lambda v: self.G(eta, v),
-                                  lambda r: op.solve_A(s, a, r, self.g),
+                                  lambda r: self.A_inv(s, a, r),
                                   U, x0=x0, tol=self.tol, max_iter=self.max_iter)
         if not ok:
             raise RuntimeError("PCG did not converge")
@@ -205,10 +211,9 @@ def run_sbdf2(pb: Problem, eta, U, u, dt, nsteps, coeffs=None):
     A u_{n+2} = 2 R_{n+1} - R_n,  R_k = A u_k - G_{eta_k} u_k + U_k.
     """
     sig, alp = coeffs if coeffs is not None else sbdf2_coefficients(pb, eta)
-    g = pb.g
 
     def R(eta_k, U_k, u_k):
-        return op.apply_A(sig, alp, u_k, g) - pb.G(eta_k, u_k) + U_k
+        return pb.A(sig, alp, u_k) - pb.G(eta_k, u_k) + U_k
 
     if nsteps <= 0:
         return eta, U, u
@@ -224,7 +229,7 @@ def run_sbdf2(pb: Problem, eta, U, u, dt, nsteps, coeffs=None):
         b0, b1 = SBDF2_B
         eta2 = (-a0 * w0[0] - a1 * eta1 + dt * (b0 * f0[0] + b1 * f1[0])) / a2
         U2 = (-a0 * w0[1] - a1 * U1 + dt * (b0 * f0[1] + b1 * f1[1])) / a2
-        u2 = op.solve_A(sig, alp, b0 * R0 + b1 * R1, g)
+        u2 = pb.A_inv(sig, alp, b0 * R0 + b1 * R1)
         w0, f0, R0 = (eta1, U1), f1, R1
         eta1, U1, u1 = eta2, U2, u2
         done += 1

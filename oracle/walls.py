@@ -23,6 +23,7 @@ import scipy.fft as sf
 
 from . import krylov
 from . import operators as op
+from . import stepping
 
 
 # ---- transforms: samples <-> series amplitudes on one axis ------------------------
@@ -178,3 +179,59 @@ def pcg_solve(eta, grad_h, flat, b, g, tol=1e-12, max_iter=2000, x0=None, kind="
     u, it, ok, hist = krylov.pcg(lambda v: apply_G(eta, grad_h, v, g), lambda r: solve_A(s, a, r, g), b,
                                  x0=x0, tol=tol, max_iter=max_iter)
     return u, it, ok, (s, a, k)
+
+
+# ---- right-hand side between walls ---------------------------------------------
+def _dx(f, kinds, g):
+    return _deriv(f, kinds, f.ndim - 1, g.Lx)[0]
+
+
+def _dy(f, kinds, g):
+    return _deriv(f, kinds, 0, g.Ly)[0]
+
+
+def rhs(eta, u, h, grad_h, g):
+    """(eta_t, U_t) of the constraint form (Eq:DSWEcf, Def:bigF) between walls:
+    the terms of the periodic right-hand side with the wall derivatives.  Every
+    derivative acts on a product whose series kind follows from the parities:
+    scalars are cosine series, each velocity component a sine series along its
+    own axis, so eta u u_i is sine along axis i and eta u v sine along both."""
+    delta = div(u, g)
+    m = div(eta[None] * u, g)
+    beta = np.sum(grad_h * u, axis=0)
+    P = np.sum(u * grad(delta, g), axis=0) - delta ** 2
+    Q = np.sum(u * grad(beta, g), axis=0)
+    S = eta ** 3 / 3.0 * P + eta ** 2 * m * delta + eta ** 2 / 2.0 * Q + eta * m * beta
+    T = eta ** 2 / 2.0 * P + eta * m * delta + eta * Q + m * beta
+    F = grad(S, g) - grad_h * T[None]
+    if g.d == 1:
+        flux = _dx(eta * u[0] * u[0], "c", g)[None]
+    else:
+        flux = np.stack([
+            _dx(eta * u[0] * u[0], "cc", g) + _dy(eta * u[0] * u[1], "ss", g),
+            _dx(eta * u[0] * u[1], "ss", g) + _dy(eta * u[1] * u[1], "cc", g),
+        ])
+    return -m, -eta[None] * grad(eta - h, g) - flux + F
+
+
+class Problem(stepping.Problem):
+    """A stepping problem between walls: the steppers of oracle.stepping with the
+    wall right-hand side, G, A and A^{-1}."""
+
+    @classmethod
+    def from_h(cls, g, h, tol=1e-12, max_iter=1000, guess="extrapolate"):
+        gh, fl = bathy_gradient(h, g)
+        return cls(g, np.asarray(h, dtype=np.float64), gh, fl, tol, max_iter,
+                   hist=stepping.GuessHistory(guess))
+
+    def f(self, eta, u):
+        return rhs(eta, u, self.h, self.grad_h, self.g)
+
+    def G(self, eta, u):
+        return apply_G(eta, self.grad_h, u, self.g)
+
+    def A(self, sigma, alpha, u):
+        return apply_A(sigma, alpha, u, self.g)
+
+    def A_inv(self, sigma, alpha, r):
+        return solve_A(sigma, alpha, r, self.g)

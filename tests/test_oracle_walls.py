@@ -7,7 +7,10 @@
   fields and restricted back: a second construction of the same operator;
 * G symmetric positive definite and equal to A for constant depth and a flat
   bottom; the eigenvalue interval of Theorem 4.1, which Sec:BoundonG states for
-  walls as well; PCG reaching the tolerance on G u = b.
+  walls as well; PCG reaching the tolerance on G u = b;
+* the right-hand side between walls, and the RK4, Adams-Bashforth and SBDF2
+  steppers built on the wall operators, equal to the periodic ones on the
+  reflected fields (second construction again); the mass rate is zero.
 """
 import numpy as np
 import pytest
@@ -139,3 +142,49 @@ def test_pcg_with_walls_reaches_the_tolerance(g, rng):
     u, it, ok, _ = W.pcg_solve(eta, gh, fl, b, g, tol=1e-12)
     assert ok
     assert np.linalg.norm(b - W.apply_G(eta, gh, u, g)) <= 1e-12 * np.linalg.norm(b)
+
+
+def _state(g, rng):
+    eta, h, _ = _fields(g, rng)
+    u = 0.2 * np.stack([W.from_modes(W.to_modes(c, k), k) for c, k in
+                        zip(rng.normal(size=(g.d,) + g.shape), W.VECTOR[g.d])])
+    return eta, h, u
+
+
+@pytest.mark.parametrize("g", WALL_GRIDS, ids=IDS)
+def test_wall_rhs_equals_periodic_rhs_on_the_reflected_domain(g, rng):
+    from oracle import rhs as R
+    eta, h, u = _state(g, rng)
+    g2 = periodic_twin(g)
+    sc, vk = W.SCALAR[g.d], W.VECTOR[g.d]
+    E = lambda f: reflect(f, sc)  # noqa: E731
+    Ev = lambda v: np.stack([reflect(v[c], vk[c]) for c in range(g.d)])  # noqa: E731
+    gh, _ = W.bathy_gradient(h, g)
+    et, Ut = W.rhs(eta, u, h, gh, g)
+    gh2, _ = op.bathy_gradient(E(h), g2)
+    et2, Ut2 = R.rhs(E(eta), Ev(u), E(h), gh2, g2)
+    assert np.max(np.abs(restrict(et2, g) - et)) < 1e-10 * np.max(np.abs(et))
+    assert np.max(np.abs(restrict(Ut2, g) - Ut)) < 1e-10 * np.max(np.abs(Ut))
+    assert abs(np.sum(et)) < 1e-12 * np.sum(np.abs(et))      # mass rate zero
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "ab2", "sbdf2"])
+def test_wall_steppers_equal_periodic_steppers_on_the_reflected_domain(scheme, rng):
+    from oracle import stepping as ST
+    g = I.grid1d_walls(64, 20.0)
+    eta, h, u = _state(g, rng)
+    g2 = periodic_twin(g)
+    pw = W.Problem.from_h(g, h, tol=1e-13)
+    pp = ST.Problem.from_h(g2, reflect(h, "c"), tol=1e-13)
+    U = pw.G(eta, u)
+    U2 = pp.G(reflect(eta, "c"), np.stack([reflect(u[0], "s")]))
+    args_w = (eta, U, u)
+    args_p = (reflect(eta, "c"), U2, np.stack([reflect(u[0], "s")]))
+    if scheme == "rk4":
+        rw, rp = ST.run_rk4(pw, *args_w, 0.05, 3), ST.run_rk4(pp, *args_p, 0.05, 3)
+    elif scheme == "ab2":
+        rw, rp = ST.run_ab(pw, 2, *args_w, 0.05, 3), ST.run_ab(pp, 2, *args_p, 0.05, 3)
+    else:
+        rw, rp = ST.run_sbdf2(pw, *args_w, 0.05, 3), ST.run_sbdf2(pp, *args_p, 0.05, 3)
+    for a, b in zip(rw, rp):
+        assert np.max(np.abs(restrict(b, g) - a)) < 1e-9 * max(1.0, np.max(np.abs(a)))
