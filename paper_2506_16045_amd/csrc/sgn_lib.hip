@@ -2016,12 +2016,31 @@ sgn_status wall_reflect(sgn_ctx* ctx, const Dims& d, const double* src, double* 
     return SGN_OK;
 }
 
-sgn_status wall_restrict(sgn_ctx* ctx, const Dims& d, const double* src, double* dst) {
+// nf fields (default: the D components of a vector field)
+sgn_status wall_restrict(sgn_ctx* ctx, const Dims& d, const double* src, double* dst, int nf = 0) {
     const Dims t = twin_dims(d);
-    hipLaunchKernelGGL(k_restrict, dim3(flat_blocks(d.N * d.D)), dim3(256), 0, ctx->stream, d.nx, d.ny, src, t.N,
-                       dst, d.N, d.D);
+    if (nf <= 0) nf = d.D;
+    hipLaunchKernelGGL(k_restrict, dim3(flat_blocks(d.N * nf)), dim3(256), 0, ctx->stream, d.nx, d.ny, src, t.N,
+                       dst, d.N, nf);
     CHECK_LAUNCH(ctx);
     return SGN_OK;
+}
+
+// A stepping state between walls keeps its fields' reflections on the twin, and a
+// periodic state over them: h, grad h once; eta, U, u at every stepping call.
+struct WallStateBufs {
+    double *h, *gh, *eta, *U, *u;
+};
+size_t carve_wall_state(Carve& cv, const Dims& t, WallStateBufs* b) {
+    WallStateBufs w;
+    const size_t DN = (size_t)t.D * t.N;
+    w.h = cv.take<double>(t.N);
+    w.gh = cv.take<double>(DN);
+    w.eta = cv.take<double>(t.N);
+    w.U = cv.take<double>(DN);
+    w.u = cv.take<double>(DN);
+    if (b) *b = w;
+    return cv.off;
 }
 
 // ---------------------------------------------------------------------------
@@ -2101,6 +2120,10 @@ struct sgn_state {
     // de-aliased right-hand side (sgn_state_set_dealias): buffers in the caller's workspace
     int dealias = 0;
     DealiasBufs dl{};
+    // between walls: the periodic state on the twin that every stepping call runs
+    sgn_state* twin = nullptr;
+    WallStateBufs wb{};
+    ~sgn_state() { delete twin; }
 };
 
 namespace {
@@ -2886,6 +2909,34 @@ sgn_status sgn_rhs(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const 
     return rhs_dispatch(ctx, d, eta, grad_h, u, eta_t, U_t, ws);
 }
 
+}  // extern "C"
+
+namespace {
+// One stepping call of a state between walls: its fields reflected onto the twin,
+// the call run on the twin's periodic state, the fields restricted back (also
+// after a failed solve, as a periodic state leaves its fields).
+template <typename F>
+sgn_status wall_steps(sgn_state* st, F call) {
+    sgn_ctx* ctx = st->ctx;
+    const Dims& d = st->d;
+    sgn_state* tw = st->twin;
+    sgn_status s;
+    if ((s = wall_reflect(ctx, d, st->eta, tw->eta, false)) != SGN_OK) return s;
+    if ((s = wall_reflect(ctx, d, st->U, tw->U, true)) != SGN_OK) return s;
+    if ((s = wall_reflect(ctx, d, st->u, tw->u, true)) != SGN_OK) return s;
+    s = call(tw);
+    sgn_status r = wall_restrict(ctx, d, tw->eta, st->eta, 1);
+    if (r == SGN_OK) r = wall_restrict(ctx, d, tw->U, st->U);
+    if (r == SGN_OK) r = wall_restrict(ctx, d, tw->u, st->u);
+    st->t = tw->t;
+    st->steps = tw->steps;
+    return s != SGN_OK ? s : r;
+}
+
+}  // namespace
+
+extern "C" {
+
 size_t sgn_dealias_workspace_bytes(const sgn_grid* grid) {
     Dims d;
     if (check_grid(nullptr, grid, &d) != SGN_OK || d.bc != SGN_BC_PERIODIC || !dealias_supported(d)) return 0;
@@ -2911,6 +2962,7 @@ sgn_status sgn_rhs_dealiased(sgn_ctx* ctx, const sgn_grid* grid, const double* e
 
 sgn_status sgn_state_set_dealias(sgn_ctx* ctx, sgn_state* st, void* dws) {
     if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (st->twin) return fail(ctx, SGN_EUNSUPPORTED, "de-aliasing takes periodic grids only");
     if (dws && !dealias_supported(st->d)) return fail(ctx, SGN_EUNSUPPORTED, "de-aliasing: grid too large to pad");
     // a multistep history holds right-hand sides of the form used so far
     st->kind = 0;
@@ -2928,8 +2980,13 @@ sgn_status sgn_state_set_dealias(sgn_ctx* ctx, sgn_state* st, void* dws) {
 size_t sgn_state_workspace_bytes(const sgn_grid* grid, int32_t precision) {
     (void)precision;
     Dims d;
-    if (check_grid(nullptr, grid, &d) != SGN_OK || d.bc != SGN_BC_PERIODIC) return 0;
+    if (check_grid(nullptr, grid, &d) != SGN_OK) return 0;
     Carve cv(nullptr);
+    if (d.bc == SGN_BC_WALLS) {
+        const Dims t = twin_dims(d);
+        carve_wall_state(cv, t, nullptr);
+        return carve_state(cv, t, nullptr) + 256;
+    }
     return carve_state(cv, d, nullptr) + 256;
 }
 
@@ -2941,8 +2998,46 @@ sgn_status sgn_state_create(sgn_ctx* ctx, const sgn_grid* grid, const double* h,
     Dims d;
     sgn_status s = check_grid(ctx, grid, &d);
     if (s != SGN_OK) return s;
-    if ((s = require_periodic(ctx, d)) != SGN_OK) return s;
     if (!h || !grad_h || !eta || !U || !u || !state_ws || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    if (d.bc == SGN_BC_WALLS) {
+        // the twin's periodic state over the reflected fields; the caller's d_ws
+        // (sgn_workspace_bytes of the wall grid) is larger than the twin's own
+        const Dims t = twin_dims(d);
+        sgn_grid tg = *grid;
+        tg.bc = SGN_BC_PERIODIC;
+        tg.nx = t.nx;
+        tg.ny = t.ny;
+        tg.Lx = t.Lx;
+        tg.Ly = t.Ly;
+        Carve cv(state_ws);
+        WallStateBufs wb;
+        carve_wall_state(cv, t, &wb);
+        if ((s = wall_reflect(ctx, d, h, wb.h, false)) != SGN_OK) return s;
+        if ((s = wall_reflect(ctx, d, grad_h, wb.gh, true)) != SGN_OK) return s;
+        sgn_state* tw = nullptr;
+        void* tws = static_cast<char*>(state_ws) + align_up(cv.off, 256);
+        if ((s = sgn_state_create(ctx, &tg, wb.h, wb.gh, flat, wb.eta, wb.U, wb.u, tws, ws, &tw)) != SGN_OK)
+            return s;
+        sgn_state* st = new (std::nothrow) sgn_state();
+        if (!st) {
+            delete tw;
+            return fail(ctx, SGN_ENOMEM, "host allocation failed");
+        }
+        st->ctx = ctx;
+        st->grid = *grid;
+        st->d = d;
+        st->h = h;
+        st->gh = grad_h;
+        st->flat = flat ? 1 : 0;
+        st->eta = eta;
+        st->U = U;
+        st->u = u;
+        st->ws = ws;
+        st->twin = tw;
+        st->wb = wb;
+        *out = st;
+        return SGN_OK;
+    }
     sgn_state* st = new (std::nothrow) sgn_state();
     if (!st) return fail(ctx, SGN_ENOMEM, "host allocation failed");
     st->ctx = ctx;
@@ -2971,6 +3066,8 @@ void sgn_state_destroy(sgn_state* st) { delete st; }
 sgn_status sgn_step_rk4(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nsteps, const sgn_solve_opts* opts,
                         sgn_step_info* info) {
     if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (st->twin)
+        return wall_steps(st, [&](sgn_state* tw) { return sgn_step_rk4(ctx, tw, dt, nsteps, opts, info); });
     if (nsteps < 0 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad step arguments");
     const sgn_solve_opts o = opts ? *opts : default_opts();
     if (o.guess != SGN_GUESS_PREVIOUS && o.guess != SGN_GUESS_EXTRAPOLATE) return fail(ctx, SGN_EINVAL, "bad guess");
@@ -2987,6 +3084,8 @@ sgn_status sgn_step_rk4(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nsteps, 
 sgn_status sgn_step_ab(sgn_ctx* ctx, sgn_state* st, int32_t order, double dt, int32_t nsteps,
                        const sgn_solve_opts* opts, sgn_step_info* info) {
     if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (st->twin)
+        return wall_steps(st, [&](sgn_state* tw) { return sgn_step_ab(ctx, tw, order, dt, nsteps, opts, info); });
     if (nsteps < 0 || order < 2 || order > 4 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad AB arguments");
     const sgn_solve_opts o = opts ? *opts : default_opts();
     if (o.guess != SGN_GUESS_PREVIOUS && o.guess != SGN_GUESS_EXTRAPOLATE) return fail(ctx, SGN_EINVAL, "bad guess");
@@ -3044,6 +3143,8 @@ sgn_status sgn_step_ab(sgn_ctx* ctx, sgn_state* st, int32_t order, double dt, in
 sgn_status sgn_step_linimp(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nsteps, const sgn_coeffs* fixed,
                            const sgn_solve_opts* opts, sgn_step_info* info) {
     if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (st->twin)
+        return wall_steps(st, [&](sgn_state* tw) { return sgn_step_linimp(ctx, tw, dt, nsteps, fixed, opts, info); });
     if (nsteps < 0 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad step arguments");
     if (fixed && !(fixed->sigma > 0.0 && fixed->alpha > 0.0)) return fail(ctx, SGN_EINVAL, "bad fixed coefficients");
     const sgn_solve_opts o = opts ? *opts : default_opts();

@@ -159,7 +159,7 @@ def test_periodic_only_entry_points_reject_walls(ctx):
     with pytest.raises(sgn.SgnError) as ei:
         ctx.rhs(g, x, x, v, v)
     assert ei.value.status == sgn.EUNSUPPORTED
-    assert sgn.state_workspace_bytes(g) == 0 and sgn.dealias_workspace_bytes(g) == 0
+    assert sgn.dealias_workspace_bytes(g) == 0
     # too large to reflect: the twin would exceed the periodic limits
     assert sgn.workspace_bytes(I.grid2d_walls(64, 1024, 1.0, 1.0)) == 0
     assert sgn.workspace_bytes(I.grid1d_walls(16384, 1.0)) == 0
@@ -180,3 +180,71 @@ def test_non_positive_depth_between_walls_is_rejected(ctx):
         ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), u=u0, opts=sgn.solve_opts(tol=1e-10))
     assert ei.value.status == sgn.EDOMAIN
     assert torch.all(u0 == 7.0)
+
+
+def _wall_state(ctx, g, h, eta, u):
+    from paper_2506_16045_amd import sgn
+    gh, flat = ctx.bathy_prepare(g, _t(h))
+    e_d, u_d = _t(eta), _t(u)
+    U_d = ctx.apply_constraint(g, e_d, gh, u_d)
+    return sgn.State(ctx, g, _t(h), gh, flat, e_d, U_d, u_d)
+
+
+def _basin_1d():
+    g = I.grid1d_walls(256, 60.0)
+    x = I.coords(g)
+    h = 1.0 - 0.3 * np.exp(-((x - 40.0) / 5.0) ** 2)
+    eta = h + 0.15 * np.exp(-((x - 20.0) / 4.0) ** 2)
+    u = np.zeros((1,) + g.shape)
+    return g, h, eta, u
+
+
+def _basin_2d():
+    g = I.grid2d_walls(32, 32, 30.0, 30.0)
+    X, Y = I.coords(g)
+    h = 1.0 - 0.3 * np.exp(-((X - 20.0) ** 2 + (Y - 15.0) ** 2) / 16.0)
+    eta = h + 0.15 * np.exp(-((X - 10.0) ** 2 + (Y - 12.0) ** 2) / 9.0)
+    u = np.zeros((2,) + g.shape)
+    return g, h, eta, u
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "ab3", "sbdf2"])
+@pytest.mark.parametrize("make", [_basin_1d, _basin_2d], ids=["1d-basin", "2d-basin"])
+def test_steppers_between_walls_match_oracle(ctx, make, scheme):
+    """A hump of water released in a closed basin over a bump: RK4, AB3 and SBDF2
+    steps through the wall state against the oracle's wall steppers (cosine /
+    sine series), per field to 1e-10; the mass in the basin is conserved."""
+    from paper_2506_16045_amd import sgn
+    g, h, eta, u = make()
+    print(f"walls {scheme} {g}", flush=True)
+    st = _wall_state(ctx, g, h, eta, u)
+    pb = W.Problem.from_h(g, h, tol=1e-12)
+    U0 = pb.G(eta, u)
+    opts = sgn.solve_opts(tol=1e-12, check_every=4)
+    n, dt = 8, 0.05
+    if scheme == "rk4":
+        info = st.step_rk4(dt, n, opts)
+        ref = W.stepping.run_rk4(pb, eta, U0, u, dt, n)
+    elif scheme == "ab3":
+        info = st.step_ab(3, dt, n, opts)
+        ref = W.stepping.run_ab(pb, 3, eta, U0, u, dt, n)
+    else:
+        info = st.step_linimp(dt, n, None, opts)
+        ref = W.stepping.run_sbdf2(pb, eta, U0, u, dt, n)
+    assert info.converged and info.steps_done == n
+    assert abs(info.t - n * dt) < 1e-12
+    for a, b in zip((st.eta, st.U, st.u), ref):
+        assert rel(_n(a), b) <= 1e-10
+    assert abs(np.sum(_n(st.eta)) - np.sum(eta)) <= 1e-12 * np.sum(eta)
+    assert np.max(np.abs(_n(st.u))) > 1e-3          # the water moved
+    st.close()
+
+
+def test_wall_state_rejects_dealiasing(ctx):
+    from paper_2506_16045_amd import sgn
+    g, h, eta, u = _basin_2d()
+    st = _wall_state(ctx, g, h, eta, u)
+    with pytest.raises(sgn.SgnError) as ei:
+        st.set_dealias(True)
+    assert ei.value.status == sgn.EUNSUPPORTED
+    st.close()
