@@ -269,6 +269,22 @@ def bench_walls(args):
                              "iters": res.iters, "outer_iters": res.outer_iters, "relres": res.relres,
                              "converged": res.converged,
                              "kernel_avg_us": {k: round(1e3 * v[1] / v[0], 2) for k, v in prof.items() if v[0]}}
+    # RK4 steps of the basin (the hump released from rest) through a wall stepping state
+    h_d = to(cfg["h"])
+    u0 = torch.zeros((2,) + g.shape, dtype=torch.float64, device=e_d.device)
+    U0 = ctx.apply_constraint(g, e_d, gh, u0)
+    st = sgn.State(ctx, g, h_d, gh, flat, e_d.clone(), U0, u0)
+    sopts = sgn.solve_opts(tol=cfg["tol"], check_every=args.check_every)
+    st.step_rk4(0.05, max(args.warmup, 1), sopts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sinfo = st.step_rk4(0.05, args.steps, sopts)
+    torch.cuda.synchronize()
+    sel = time.perf_counter() - t0
+    stepping = {"scheme": "rk4", "dt": 0.05, "steps": args.steps, "ms_per_step": 1e3 * sel / args.steps,
+                "grid_pt_steps_per_s": g.npts * args.steps / sel, "krylov_iters_per_solve": sinfo.iters / max(sinfo.solves, 1),
+                "converged": bool(sinfo.converged)}
+    st.close()
     main = res_by["fp64"]
     kind = "pcg_r1"
     twin = (2 * g.nx, 2 * g.ny)
@@ -287,7 +303,7 @@ def bench_walls(args):
            "config": {"workload": f"walls basin {g.nx}x{g.ny} cells on {g.Lx:g}x{g.Ly:g} (periodic twin "
                                   f"{twin[0]}x{twin[1]}), Gaussian bump bathymetry, surface hump, tol {cfg['tol']:g}, "
                                   "zero initial guess", "parallelism": "single GPU"},
-           "precisions": res_by, "roofline": roof,
+           "precisions": res_by, "stepping": stepping, "roofline": roof,
            "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_walls(cfg),
            "device": torch.cuda.get_device_name(0)}
     print(json.dumps(out), flush=True)
