@@ -57,11 +57,11 @@ typedef enum sgn_bc {
                            * x_j = (j + 1/2) L / n; scalar fields are cosine series, each
                            * velocity component a sine series along its own axis.  Taken by
                            * sgn_bathy_prepare, sgn_precond_coeffs, sgn_apply_constraint,
-                           * sgn_precond_solve, sgn_krylov_solve and the stepping states
-                           * (sgn_state_create and the sgn_step_* calls; the state then keeps
-                           * the reflected fields and the stepping history of the twin), and
-                           * their workspace queries; sgn_rhs, the de-aliasing calls, the
-                           * batched solver and the server return SGN_EUNSUPPORTED.  Sizes: 1D
+                           * sgn_precond_solve, sgn_krylov_solve, sgn_rhs and the stepping
+                           * states (sgn_state_create and the sgn_step_* calls; the state then
+                           * keeps the reflected fields and the stepping history of the twin),
+                           * and their workspace queries; the de-aliasing calls, the batched
+                           * solver and the server return SGN_EUNSUPPORTED.  Sizes: 1D
                            * nx <= 8192, 2D nx <= 2048 and ny <= 512.  Internally the fields
                            * are reflected (even / odd) onto the periodic grid of twice the
                            * length per axis, where every step of the periodic path runs. */

@@ -1991,12 +1991,13 @@ sgn_status rhs_dealiased(sgn_ctx* ctx, const Dims& d, const double* eta, const d
 // over the wall grid, so every ratio the iteration forms is unchanged.
 // ---------------------------------------------------------------------------
 struct WallBufs {
-    double *eta, *gh, *f, *u;  // on the twin: eta [N], grad h [D N], input [D N], result [D N]
-    void* ws;                  // the twin's own workspace
+    double *eta, *et, *gh, *f, *u;  // on the twin: eta, eta_t [N], grad h [D N], input [D N], result [D N]
+    void* ws;                       // the twin's own workspace
 };
 size_t carve_walls(Carve& cv, const Dims& t, WallBufs* b) {
     WallBufs w;
     w.eta = cv.take<double>(t.N);
+    w.et = cv.take<double>(t.N);
     w.gh = cv.take<double>((size_t)t.D * t.N);
     w.f = cv.take<double>((size_t)t.D * t.N);
     w.u = cv.take<double>((size_t)t.D * t.N);
@@ -2904,9 +2905,19 @@ sgn_status sgn_rhs(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const 
     Dims d;
     sgn_status s = check_grid(ctx, grid, &d);
     if (s != SGN_OK) return s;
-    if ((s = require_periodic(ctx, d)) != SGN_OK) return s;
     if (!eta || !h || !grad_h || !u || !eta_t || !U_t || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
-    return rhs_dispatch(ctx, d, eta, grad_h, u, eta_t, U_t, ws);
+    if (d.bc != SGN_BC_WALLS) return rhs_dispatch(ctx, d, eta, grad_h, u, eta_t, U_t, ws);
+    // between walls: the periodic right-hand side of the reflected fields, restricted
+    const Dims t = twin_dims(d);
+    WallBufs w;
+    Carve cv(ws);
+    carve_walls(cv, t, &w);
+    if ((s = wall_reflect(ctx, d, eta, w.eta, false)) != SGN_OK) return s;
+    if ((s = wall_reflect(ctx, d, grad_h, w.gh, true)) != SGN_OK) return s;
+    if ((s = wall_reflect(ctx, d, u, w.f, true)) != SGN_OK) return s;
+    if ((s = rhs_dispatch(ctx, t, w.eta, w.gh, w.f, w.et, w.u, w.ws)) != SGN_OK) return s;
+    if ((s = wall_restrict(ctx, d, w.et, eta_t, 1)) != SGN_OK) return s;
+    return wall_restrict(ctx, d, w.u, U_t);
 }
 
 }  // extern "C"

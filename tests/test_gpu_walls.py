@@ -1,7 +1,8 @@
 """GPU parity of the constraint-solve entry points on grids between walls
 (homogeneous Neumann, Subsec:DAEform) against the oracle's cosine / sine series
 operators (oracle/walls.py), element by element on the same seeded inputs:
-grad h, G, A^{-1} and PCG (FP64 and mixed) and GMRES solves, on 1D and 2D wall
+grad h, G, A^{-1}, f(w, p), PCG (FP64 and mixed) and GMRES solves and the
+steppers, on 1D and 2D wall
 grids from the smallest to the largest (whose periodic twins run on the
 one-workgroup 1D solver, the row-pass path and 2D columns of 1024), and the
 entry points that take periodic grids only rejecting walls."""
@@ -95,6 +96,20 @@ def _twin_problem(g, eta, h, b):
     return g2, e2, gh2, fl2, b2
 
 
+@pytest.mark.parametrize("g", [GRIDS[1], GRIDS[3], GRIDS[5], GRIDS[7], GRIDS[8]],
+                         ids=[IDS[1], IDS[3], IDS[5], IDS[7], IDS[8]])
+def test_rhs_between_walls(ctx, g):
+    """f(w, p) between walls (sgn_rhs on a wall grid) against the oracle's wall
+    right-hand side, per field to 1e-11 relative L2."""
+    eta, h, u = _fields(g, 35)
+    u = 0.2 * np.stack([W.from_modes(W.to_modes(c, k), k) for c, k in zip(u, W.VECTOR[g.d])])
+    gh, _ = W.bathy_gradient(h, g)
+    et_ref, Ut_ref = W.rhs(eta, u, h, gh, g)
+    et, Ut = ctx.rhs(g, _t(eta), _t(h), _t(gh), _t(u))
+    assert rel(_n(et), et_ref) <= 1e-11
+    assert rel(_n(Ut), Ut_ref) <= 1e-11
+
+
 @pytest.mark.parametrize("g", GRIDS, ids=IDS)
 def test_pcg_fp64_matches_oracle(ctx, g):
     """Solutions equal the oracle's wall solve; the iteration count equals (+-1) the
@@ -157,7 +172,7 @@ def test_periodic_only_entry_points_reject_walls(ctx):
     x = torch.ones(g.shape, dtype=torch.float64, device="cuda")
     v = torch.zeros((2,) + g.shape, dtype=torch.float64, device="cuda")
     with pytest.raises(sgn.SgnError) as ei:
-        ctx.rhs(g, x, x, v, v)
+        ctx.rhs_dealiased(g, x, x, v, v)
     assert ei.value.status == sgn.EUNSUPPORTED
     assert sgn.dealias_workspace_bytes(g) == 0
     # too large to reflect: the twin would exceed the periodic limits
