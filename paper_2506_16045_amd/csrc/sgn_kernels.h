@@ -923,7 +923,56 @@ enum { C2_RESID = 1, C2_STORE = 2, C2_UPDATE = 3, C2_RESID_INIT = 4 };
 // MODE C2_RESID_INIT: reduce ||b||^2 (setup partials, nb_r1 blocks) -> bb;
 //   r = b - G x -> rh (x = r = 0 for a zero b); partial r.z, r.r of r_0.
 // MODE C2_STORE: q = G p -> qh.
-template <typename T, int EPC, int D, int MODE>
+// Projection of a residual mode onto the reflection-symmetric modes of a wall
+// grid's periodic twin (Nx x Ny points): velocity component c is odd along its
+// own axis and even along the other.  A field with E[N-1-X] = s E[X] along an
+// axis has E^[k] = s e^{2 pi i k / N} E^[-k]; in the half spectrum E^[ky][-kx] is
+// conj(E^[-ky][kx]), so both reflections pair the mode (kx, ky) with (kx, -ky) of
+// the same column.  a: the mode, b: its partner (kx, -ky).
+template <typename T, int D>
+__device__ __forceinline__ cpx<T> wall_project(int c, cpx<T> a, cpx<T> b, int kx, int nx, int ky, int ny) {
+    const T half = (T)0.5;
+    if (D == 2) {
+        const T sy = c == 1 ? (T)-1 : (T)1;
+        T sn, cs;
+        if (sizeof(T) == 8) {
+            double s2, c2;
+            sincospi(2.0 * (double)ky / (double)ny, &s2, &c2);
+            sn = (T)s2;
+            cs = (T)c2;
+        } else {
+            float s2, c2;
+            sincospif(2.0f * (float)ky / (float)ny, &s2, &c2);
+            sn = (T)s2;
+            cs = (T)c2;
+        }
+        const cpx<T> om = C<T>(sy * cs, sy * sn), omc = C<T>(sy * cs, -sy * sn);
+        const cpx<T> a2 = half * (a + om * b);
+        const cpx<T> b2 = half * (b + omc * a);
+        a = a2;
+        b = b2;
+    }
+    const T sx = c == 0 ? (T)-1 : (T)1;
+    T sn, cs;
+    if (sizeof(T) == 8) {
+        double s2, c2;
+        sincospi(2.0 * (double)kx / (double)nx, &s2, &c2);
+        sn = (T)s2;
+        cs = (T)c2;
+    } else {
+        float s2, c2;
+        sincospif(2.0f * (float)kx / (float)nx, &s2, &c2);
+        sn = (T)s2;
+        cs = (T)c2;
+    }
+    const cpx<T> ph = C<T>(sx * cs, sx * sn);
+    return half * (a + ph * cj(b));
+}
+
+// WALL: the solve runs on the periodic twin of a wall grid; the new residual is
+// projected onto the symmetric modes before it is used (rounding would otherwise
+// seed the other parity, which the iteration amplifies at low wavenumbers).
+template <typename T, int EPC, int D, int MODE, bool WALL = false>
 __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restrict__ tw,
                                                  SolveScal* __restrict__ sc, const cpx<T>* __restrict__ H,
                                                  size_t NS, cpx<T>* __restrict__ qh, const cpx<T>* __restrict__ ph,
@@ -977,6 +1026,64 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
     const T sig = (T)sc->sig, alp = (T)sc->alp;
     const double w = ct.valid ? half_weight(ct.kx, g.nx) : 0.0;
     double acc[2] = {0.0, 0.0};
+    if (WALL && MODE != C2_STORE) {
+        // the new residual of the whole column first, then its projection
+        cpx<T> rn[D][EPC];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+#pragma unroll
+            for (int c = 0; c < D; ++c) rn[c][e] = C<T>(0, 0);
+            if (ct.valid && j < g.ny) {
+                const size_t idx = (size_t)ct.kx * g.ny + j;
+                const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
+                const cpx<T> wv = in[D][e];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const T kc = (c == 0) ? kx : ky;
+                    const cpx<T> q = in[c][e] - ik(kc, wv);
+                    if (MODE == C2_RESID) {
+                        rn[c][e] = bh[c * NS + idx] - q;
+                    } else if (MODE == C2_RESID_INIT) {
+                        rn[c][e] = zero_x ? C<T>(0, 0) : bh[c * NS + idx] - q;
+                        if (zero_x) xh[c * NS + idx] = C<T>(0, 0);
+                    } else {
+                        xh[c * NS + idx] = xh[c * NS + idx] + alpha * ph[c * NS + idx];
+                        rn[c][e] = rh[c * NS + idx] - alpha * q;
+                    }
+                    ct.buf[c * ct.fstride + j] = rn[c][e];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = ct.t + g.TPC * e;
+            if (ct.valid && j < g.ny) {
+                const size_t idx = (size_t)ct.kx * g.ny + j;
+                const int jm = (g.ny - j) & (g.ny - 1);
+                const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
+                cpx<T> r[D], z[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    r[c] = wall_project<T, D>(c, rn[c][e], ct.buf[c * ct.fstride + jm], ct.kx, g.nx, j, g.ny);
+                    rh[c * NS + idx] = r[c];
+                }
+                precond_mode<T, D>(kx, ky, sig, alp, r, z);
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    acc[0] += w * ((double)r[c].re * (double)z[c].re + (double)r[c].im * (double)z[c].im);
+                    acc[1] += w * ((double)r[c].re * (double)r[c].re + (double)r[c].im * (double)r[c].im);
+                }
+            }
+        }
+        block_sum<2>(acc, red);
+        if (threadIdx.x == 0) {
+            part[PART_C3 + 2 * blockIdx.x] = acc[0];
+            part[PART_C3 + 2 * blockIdx.x + 1] = acc[1];
+        }
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < EPC; ++e) {
         const int j = ct.t + g.TPC * e;
@@ -1214,7 +1321,7 @@ __global__ void __launch_bounds__(256) k_cols_resample(ColGeom g, const cpx<T>* 
 // grid (field stride sstride) onto the twin (field stride dstride):
 // dst[Y][X] = sx sy src[ry][rx], r(X) = X below n and 2n - 1 - X above, with the
 // sign -1 on the reflected half of an axis along which field f is odd (bit f of
-// oddx / oddy).  k_restrict copies the twin's first quadrant back.
+// oddx / oddy).
 __global__ void __launch_bounds__(256) k_reflect(int nx, int ny, int nye, const double* __restrict__ src,
                                                   size_t sstride, double* __restrict__ dst, size_t dstride, int nf,
                                                   unsigned oddx, unsigned oddy) {
@@ -1235,15 +1342,32 @@ __global__ void __launch_bounds__(256) k_reflect(int nx, int ny, int nye, const 
     }
 }
 
-__global__ void __launch_bounds__(256) k_restrict(int nx, int ny, const double* __restrict__ src, size_t sstride,
-                                                   double* __restrict__ dst, size_t dstride, int nf) {
+// k_restrict returns the symmetric part: the mean of a point's images on the twin
+// (2 in 1D, 4 in 2D, signed as in k_reflect), which is the point itself for a
+// symmetric field and drops what rounding put into the other parities.
+__global__ void __launch_bounds__(256) k_restrict(int nx, int ny, int nye, const double* __restrict__ src,
+                                                   size_t sstride, double* __restrict__ dst, size_t dstride, int nf,
+                                                   unsigned oddx, unsigned oddy) {
     const size_t n = (size_t)nx * ny;
     const size_t total = n * (size_t)nf;
+    const int nxe = 2 * nx;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
         const int f = (int)(i / n);
         const size_t p = i - (size_t)f * n;
         const int y = (int)(p / nx), x = (int)(p - (size_t)y * nx);
-        dst[(size_t)f * dstride + p] = src[(size_t)f * sstride + (size_t)y * (2 * nx) + x];
+        const double* sf = src + (size_t)f * sstride;
+        const double sx = ((oddx >> f) & 1u) ? -1.0 : 1.0;
+        const int xm = nxe - 1 - x;
+        double v = sf[(size_t)y * nxe + x] + sx * sf[(size_t)y * nxe + xm];
+        if (nye > 1) {
+            const double sy = ((oddy >> f) & 1u) ? -1.0 : 1.0;
+            const int ym = nye - 1 - y;
+            v += sy * (sf[(size_t)ym * nxe + x] + sx * sf[(size_t)ym * nxe + xm]);
+            v *= 0.25;
+        } else {
+            v *= 0.5;
+        }
+        dst[(size_t)f * dstride + p] = v;
     }
 }
 

@@ -48,6 +48,7 @@ struct sgn_ctx {
     int last_iters[2][GUESS_SLOTS + 1] = {};
     int* stage_last = nullptr;    // the running stepper solve's counters (state-owned), if any
     bool stage = false;           // solving inside a stepper: skip the final scalar readback
+    bool wall_twin = false;       // solving on the periodic twin of a wall grid
     int cus = 256;                // compute units of the device
     int batch_threads = 512;      // workgroup size of the batched solver (SGN_BATCH_THREADS: 256, 512, 1024)
     void* hbatch = nullptr;       // pinned staging of batch item tables and results
@@ -600,6 +601,7 @@ struct PcgLaunch {
     double* partials;
     const T* eta;
     const T* gh;
+    bool wall = false;  // the grid is the periodic twin of a wall grid (residuals projected)
 };
 
 // mode C1_ACCUM (T = double only): x_hat += dx (FP32) and G is applied to the
@@ -659,16 +661,18 @@ sgn_status pcg_r1(PcgLaunch<T, D>& P, bool curvature = false) {
 template <typename T, int D, int MODE>
 sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out, const ProfScope& ps) {
     auto& L = P.cl;
-    auto k = k_pcg_c2<T, 4, D, MODE>;
     const size_t lds = col_lds_bytes<T>(L.g, D + 1);
-    HIPCHK(P.ctx, allow_lds(k, lds));
     // partials reduced at the start: p.Gp of the row pass, or ||b||^2 of the setup pass
     const int nb_red = MODE == C2_RESID_INIT ? L.g.nblocks : P.rl.g.nblocks;
-    hipExtLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, ps.a, ps.b, 0, L.g,
-                          twiddles<T>(P.ctx), P.sc, (const cpx<T>*)P.b.H, P.d.NS, P.b.qh, (const cpx<T>*)P.b.ph,
-                          P.b.xh, bh, rh_out, P.partials, nb_red, (T)P.d.tpx, (T)P.d.tpy);
-    CHECK_LAUNCH(P.ctx);
-    return SGN_OK;
+    auto launch = [&](auto k) -> sgn_status {
+        HIPCHK(P.ctx, allow_lds(k, lds));
+        hipExtLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, ps.a, ps.b, 0, L.g,
+                              twiddles<T>(P.ctx), P.sc, (const cpx<T>*)P.b.H, P.d.NS, P.b.qh, (const cpx<T>*)P.b.ph,
+                              P.b.xh, bh, rh_out, P.partials, nb_red, (T)P.d.tpx, (T)P.d.tpy);
+        CHECK_LAUNCH(P.ctx);
+        return SGN_OK;
+    };
+    return P.wall ? launch(k_pcg_c2<T, 4, D, MODE, true>) : launch(k_pcg_c2<T, 4, D, MODE>);
 }
 
 template <typename T, int D>
@@ -970,6 +974,7 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     Carve cv(ws);
     Common cm = carve_common(cv);
     PcgLaunch<double, D> P;
+    P.wall = ctx->wall_twin;
     P.ctx = ctx;
     P.d = d;
     P.rl = row_launch<double>(d.nx, d.ny, true);
@@ -1058,6 +1063,7 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     Carve cv(ws);
     Common cm = carve_common(cv);
     PcgLaunch<double, D> P;
+    P.wall = ctx->wall_twin;
     P.ctx = ctx;
     P.d = d;
     P.rl = row_launch<double>(d.nx, d.ny, true);
@@ -1068,6 +1074,7 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     P.eta = eta;
     P.gh = gh;
     PcgLaunch<float, D> Q;
+    Q.wall = ctx->wall_twin;
     Q.ctx = ctx;
     Q.d = d;
     Q.rl = row_launch<float>(d.nx, d.ny, true);
@@ -2017,12 +2024,14 @@ sgn_status wall_reflect(sgn_ctx* ctx, const Dims& d, const double* src, double* 
     return SGN_OK;
 }
 
-// nf fields (default: the D components of a vector field)
-sgn_status wall_restrict(sgn_ctx* ctx, const Dims& d, const double* src, double* dst, int nf = 0) {
+// The symmetric part of a twin field back on the wall grid: a scalar (vector =
+// false) or the D components of a vector field.
+sgn_status wall_restrict(sgn_ctx* ctx, const Dims& d, const double* src, double* dst, bool vector = true) {
     const Dims t = twin_dims(d);
-    if (nf <= 0) nf = d.D;
-    hipLaunchKernelGGL(k_restrict, dim3(flat_blocks(d.N * nf)), dim3(256), 0, ctx->stream, d.nx, d.ny, src, t.N,
-                       dst, d.N, nf);
+    const int nf = vector ? d.D : 1;
+    const unsigned oddx = vector ? 1u : 0u, oddy = (vector && d.D == 2) ? 2u : 0u;
+    hipLaunchKernelGGL(k_restrict, dim3(flat_blocks(d.N * nf)), dim3(256), 0, ctx->stream, d.nx, d.ny, t.ny, src,
+                       t.N, dst, d.N, nf, oddx, oddy);
     CHECK_LAUNCH(ctx);
     return SGN_OK;
 }
@@ -2745,7 +2754,9 @@ sgn_status sgn_krylov_solve(sgn_ctx* ctx, const sgn_grid* grid, const double* et
     if ((s = wall_reflect(ctx, d, grad_h, w.gh, true)) != SGN_OK) return s;
     if ((s = wall_reflect(ctx, d, rhs, w.f, true)) != SGN_OK) return s;
     if (o.x0_is_guess && (s = wall_reflect(ctx, d, u, w.u, true)) != SGN_OK) return s;
+    ctx->wall_twin = true;
     s = solve_dispatch(ctx, t, w.eta, w.gh, w.f, w.u, coeffs, coeffs ? coeffs->flat : -1, o, info, w.ws);
+    ctx->wall_twin = false;
     // the iterate is returned as for a periodic grid: on success and when max_iter stops it
     if (s == SGN_OK || s == SGN_ENOCONV) {
         const sgn_status r = wall_restrict(ctx, d, w.u, u);
@@ -2916,7 +2927,7 @@ sgn_status sgn_rhs(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const 
     if ((s = wall_reflect(ctx, d, grad_h, w.gh, true)) != SGN_OK) return s;
     if ((s = wall_reflect(ctx, d, u, w.f, true)) != SGN_OK) return s;
     if ((s = rhs_dispatch(ctx, t, w.eta, w.gh, w.f, w.et, w.u, w.ws)) != SGN_OK) return s;
-    if ((s = wall_restrict(ctx, d, w.et, eta_t, 1)) != SGN_OK) return s;
+    if ((s = wall_restrict(ctx, d, w.et, eta_t, false)) != SGN_OK) return s;
     return wall_restrict(ctx, d, w.u, U_t);
 }
 
@@ -2935,8 +2946,10 @@ sgn_status wall_steps(sgn_state* st, F call) {
     if ((s = wall_reflect(ctx, d, st->eta, tw->eta, false)) != SGN_OK) return s;
     if ((s = wall_reflect(ctx, d, st->U, tw->U, true)) != SGN_OK) return s;
     if ((s = wall_reflect(ctx, d, st->u, tw->u, true)) != SGN_OK) return s;
+    ctx->wall_twin = true;
     s = call(tw);
-    sgn_status r = wall_restrict(ctx, d, tw->eta, st->eta, 1);
+    ctx->wall_twin = false;
+    sgn_status r = wall_restrict(ctx, d, tw->eta, st->eta, false);
     if (r == SGN_OK) r = wall_restrict(ctx, d, tw->U, st->U);
     if (r == SGN_OK) r = wall_restrict(ctx, d, tw->u, st->u);
     st->t = tw->t;

