@@ -56,3 +56,33 @@ def test_unsupported_grids_report_zero_workspace(dim, nx, ny):
     from paper_2506_16045_amd import sgn
     g = sgn.Grid(dim, nx, ny, 1.0, 1.0)
     assert sgn._lib.sgn_workspace_bytes(ctypes.byref(g), 0) == 0
+
+
+def test_binding_refuses_to_load_without_the_library(tmp_path):
+    """No CPU fallback: with the library absent, importing the binding raises."""
+    import subprocess
+    import sys
+    env = dict(os.environ, SGN_LIB=str(tmp_path / "absent" / "libsgn.so"))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "try:\n    import paper_2506_16045_amd.sgn\nexcept ImportError as e:\n"
+            "    print('refused:', e); sys.exit(0)\nsys.exit(3)\n") % ROOT
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "no CPU fallback" in r.stdout
+
+
+def test_product_sources_never_reach_the_oracle():
+    """The package and the C sources neither import nor include anything under oracle/."""
+    pkg = os.path.join(ROOT, "paper_2506_16045_amd")
+    pat = re.compile(r"^\s*(from\s+oracle\b|import\s+oracle\b|from\s+\.\.oracle\b|#\s*include\s*[<\"][^>\"]*oracle)",
+                     re.M)
+    seen = 0
+    for base, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                seen += 1
+                text = open(os.path.join(base, f)).read()
+                assert not pat.search(text), os.path.join(base, f)
+                assert "importlib" not in text or "oracle" not in text, os.path.join(base, f)
+    assert seen >= 8
