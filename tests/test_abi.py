@@ -86,3 +86,30 @@ def test_product_sources_never_reach_the_oracle():
                 assert not pat.search(text), os.path.join(base, f)
                 assert "importlib" not in text or "oracle" not in text, os.path.join(base, f)
     assert seen >= 8
+
+
+def test_binding_constants_match_the_header():
+    """Every enumerator include/sgn.h gives a value has the same value in the binding
+    (SGN_X in the header is X in paper_2506_16045_amd.sgn)."""
+    import paper_2506_16045_amd.sgn as S
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    pairs = re.findall(r"\bSGN_([A-Z0-9_]+)\s*=\s*(-?\d+)", text)
+    assert len(pairs) >= 20
+    checked = 0
+    for name, val in pairs:
+        if hasattr(S, name):
+            assert getattr(S, name) == int(val), name
+            checked += 1
+    for name in ("OK", "EINVAL", "EDOMAIN", "ENOCONV", "ENOMEM", "EDEVICE", "EUNSUPPORTED",
+                 "PCG", "GMRES", "FP64", "MIXED", "BC_PERIODIC", "BC_WALLS",
+                 "COEFF_OPTIMAL", "COEFF_REPLACEMENT", "GUESS_PREVIOUS", "GUESS_EXTRAPOLATE"):
+        assert hasattr(S, name), name
+    assert checked >= 17
+    assert {v: k for k, v in S.STATUS_NAMES.items()} == {
+        "SGN_" + n: int(v) for n, v in pairs if n in ("OK", "EINVAL", "EDOMAIN", "ENOCONV", "ENOMEM",
+                                                      "EDEVICE", "EUNSUPPORTED")}
+    # the per-kernel timing families are reported in the order of sgn_kernel_kind
+    kinds = {n[len("KERNEL_"):].lower(): int(v) for n, v in pairs if n.startswith("KERNEL_")}
+    n_kinds = kinds.pop("kinds")
+    assert len(S.Context.KERNEL_KINDS) == n_kinds
+    assert {k: i for i, k in enumerate(S.Context.KERNEL_KINDS)} == kinds
