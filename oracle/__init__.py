@@ -21,9 +21,12 @@ Modules:
                Subsec:linop): cosine / sine series on a cell-centred grid
   stepping     RK4 (Eq:ERK), Adams-Bashforth 2-4 (Eq:AB, Table LMMCoeffs) and
                the linearly implicit SBDF2 scheme (Eq:MM)
+  linimp       linearly implicit schemes of up to three steps (Eq:IMEX_DAE), the
+               zero-stability checker of Eq:CharEq, and the third-order family
+               with the joint choice of A's scale (section 5.4)
   diagnostics  mass, energy (Remark 2.1), the G-norm error (def:discrete_Gerr)
 
 Every function that has no independent pin says "parity unpinned" in its
 docstring; the pins live in tests/test_oracle_*.py.
 """
-from . import spectral, operators, krylov, rhs, stepping, diagnostics, walls  # noqa: F401
+from . import spectral, operators, krylov, rhs, stepping, diagnostics, walls, linimp  # noqa: F401
