@@ -293,24 +293,53 @@ void sgn_state_destroy(sgn_state *state);
 /* nsteps steps of classical RK4 (Eq:ERK) with one Krylov solve per stage
  * (4 per step).  Each solve starts from the guess opts->guess selects (opts =
  * NULL: SGN_GUESS_EXTRAPOLATE) and builds A from the current eta.  The guess
- * history stays with the state across calls with the same dt. */
+ * history stays with the state across calls with the same dt.  A failed stage
+ * solve (SGN_ENOCONV, SGN_EDOMAIN) leaves the state at the last completed step;
+ * a failed final solve of a step still counts the step: eta and U hold the new
+ * level, u the last iterate of that solve, and t, steps_done describe them. */
 sgn_status sgn_step_rk4(sgn_ctx *ctx, sgn_state *state, double dt, int32_t nsteps,
                         const sgn_solve_opts *opts, sgn_step_info *info);
 
 /* nsteps steps of Adams-Bashforth of order 2..4 (Eq:AB, Table LMMCoeffs), one
  * Krylov solve per step.  Missing history is filled by RK4 steps with the
- * same dt; changing order or dt restarts the history. */
+ * same dt; changing order or dt restarts the history, and so does a failed
+ * solve (whose step counts, as in sgn_step_rk4). */
 sgn_status sgn_step_ab(sgn_ctx *ctx, sgn_state *state, int32_t order, double dt,
                        int32_t nsteps, const sgn_solve_opts *opts, sgn_step_info *info);
 
 /* nsteps steps of the linearly implicit SBDF2 scheme (Eq:MM): one A-solve per
  * step, no Krylov iteration.  fixed = NULL takes sigma*, alpha* from the
  * state's current eta (section 6.5 uses the initial data) and keeps them for
- * the life of the history.  The first step of a history is an RK4 step
- * (solver options opts). */
+ * the life of the history; fixed coefficients other than the history's, a
+ * new dt or a failed start-up step start a new history.  The first step of a
+ * history is an RK4 step (solver options opts). */
 sgn_status sgn_step_linimp(sgn_ctx *ctx, sgn_state *state, double dt, int32_t nsteps,
                            const sgn_coeffs *fixed, const sgn_solve_opts *opts,
                            sgn_step_info *info);
+
+/* Third-order linearly implicit steps (Eq:IMEX_DAE; section 5.4 on
+ * zero-stability): the one-parameter family
+ *     c(z) = (z - r)^3,  b(z) = c(z) - (z - 1)^3,  a(z) from the third-order
+ *     conditions sum_j a_j j^k = k sum_j c_j j^(k-1), k = 0..3
+ * (r = 0 is SBDF3), with A scaled to theta A.  Every step is one A-solve and no
+ * Krylov iteration; a history starts with the current level and two RK4 steps
+ * (solver options opts).  fixed = NULL takes sigma*, alpha* from the state's eta
+ * when a history starts (section 6.5) and keeps theta times them for its life;
+ * another r, theta, dt or fixed starts a new history.  The scheme is zero-stable
+ * (roots of Eq:CharEq inside the unit disk) for eigenvalues of (theta A)^{-1} G
+ * in (1/(1 + (1+r)^3), 1/(1 - ((1+r)/2)^3)); sgn_linimp3_choose gives (r, theta)
+ * covering Theorem 4.1's interval [1/kappa_ub, 1].  SGN_EINVAL unless
+ * 0 <= r < 1 and theta > 0. */
+sgn_status sgn_step_linimp3(sgn_ctx *ctx, sgn_state *state, double r, double theta, double dt,
+                            int32_t nsteps, const sgn_coeffs *fixed, const sgn_solve_opts *opts,
+                            sgn_step_info *info);
+
+/* Joint choice of the scheme and of A's scale for sgn_step_linimp3 (host only):
+ * the smallest r whose stable interval is at least kappa margin^2 wide, and theta
+ * placing [1/(theta kappa), 1/theta] (the eigenvalues of (theta A)^{-1} G when
+ * those of A^{-1} G lie in [1/kappa, 1]) at the interval's geometric centre, a
+ * factor of at least `margin` from either end.  kappa >= 1, margin >= 1. */
+sgn_status sgn_linimp3_choose(double kappa, double margin, double *r, double *theta);
 
 /* ---- de-aliased right-hand side ------------------------------------------
  * The nonlinear terms of f(w, p) formed on a grid padded with zero modes
@@ -403,7 +432,10 @@ sgn_status sgn_server_create(sgn_server **server, int device, const sgn_server_o
 /* Stop accepting requests, finish the admitted and queued ones, join the lanes
  * and free every device buffer. */
 void sgn_server_destroy(sgn_server *server);
-/* Device bytes a request needs while admitted (0 if the request is invalid). */
+/* Device bytes charged to a request while admitted (0 if the request is
+ * invalid): the pooled block a worker-lane request occupies (its fields, Krylov
+ * workspace and stepping state, rounded up to the pool's power-of-two size class),
+ * or the fields and one-system workspace of a batched 1D solve. */
 size_t sgn_request_footprint(const sgn_request *req);
 /* Queue a request; *id identifies it.  SGN_EINVAL for an invalid request,
  * SGN_ENOMEM if its footprint exceeds the whole budget. */
@@ -414,9 +446,13 @@ sgn_status sgn_server_poll(sgn_server *server, uint64_t id, sgn_result *result);
 /* Block until the request is done (timeout_s < 0: no limit); on timeout
  * returns SGN_OK with result->done = 0. */
 sgn_status sgn_server_wait(sgn_server *server, uint64_t id, double timeout_s, sgn_result *result);
-/* Requests queued, admitted and completed so far, and the admitted footprint. */
+/* Requests queued, admitted and completed so far; bytes_in_use: the footprints of
+ * the admitted requests not yet finished; bytes_held: the device memory the server
+ * holds (pooled blocks in use or cached for reuse, and the batching lane's buffer),
+ * never more than the budget (cached blocks are freed before an allocation would
+ * pass it).  Any output pointer may be NULL. */
 sgn_status sgn_server_stats(sgn_server *server, int64_t *queued, int64_t *admitted, int64_t *completed,
-                            size_t *bytes_in_use, size_t *budget);
+                            size_t *bytes_in_use, size_t *bytes_held, size_t *budget);
 
 #ifdef __cplusplus
 }

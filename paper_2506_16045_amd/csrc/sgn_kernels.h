@@ -1589,11 +1589,16 @@ __global__ void k_axpby(size_t n, double a, const double* __restrict__ x, double
     }
 }
 
-// out = base + dt * sum_k c_k f_k  (up to 4 terms, in the order given; base may be null)
+// out = (base + dt * sum_k c_k f_k) / div  (up to 6 terms, in the order given;
+// base may be null; div = 1 skips the division).  A multistep update divides by
+// its leading coefficient rather than multiplying by a rounded reciprocal, so
+// that coefficients summing to zero keep a constant field (and the mass) exact.
+constexpr int LINCOMB_MAX = 6;
 struct Lincomb4 {
-    const double* f[4];
-    double c[4];
+    const double* f[LINCOMB_MAX];
+    double c[LINCOMB_MAX];
     int n;
+    double div;
 };
 __global__ void k_lincomb(size_t n, const double* __restrict__ base, double dt, Lincomb4 lc,
                           double* __restrict__ out) {
@@ -1601,7 +1606,8 @@ __global__ void k_lincomb(size_t n, const double* __restrict__ base, double dt, 
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double s = 0.0;
         for (int k = 0; k < lc.n; ++k) s += lc.c[k] * lc.f[k][i];
-        out[i] = (base ? base[i] : 0.0) + dt * s;
+        const double v = (base ? base[i] : 0.0) + dt * s;
+        out[i] = lc.div == 1.0 ? v : v / lc.div;
     }
 }
 

@@ -2062,8 +2062,10 @@ struct StateBufs {
     double* ab_fe[4];   // Adams-Bashforth history ring
     double* ab_fU[4];
     double *eta_s, *U_s, *u_s;              // RK4 stage values
-    double *eta_prev, *U_prev, *fe_prev, *fU_prev, *tmp_e, *tmp_U;  // SBDF2 history
-    cpx<double>*R_prev, *R_cur, *uh, *Uh, *Hs;                        // SBDF2 spectral
+    // linearly implicit history: levels n .. n+s-2 (s <= 3) in a ring of two slots
+    double *lv_eta[2], *lv_U[2], *lv_fe[2], *lv_fU[2], *tmp_e, *tmp_U;
+    cpx<double>*lv_R[2], *lv_uh[2];
+    cpx<double>*R_cur, *uh, *Uh, *Hs;   // the current level's R and u (spectral), U and row scratch
     double* gx_off[GUESS_SLOTS][2];  // recorded offsets of each stepper slot (ring of two)
     double* gx_base;                 // base velocity of the running solve
 };
@@ -2080,13 +2082,16 @@ size_t carve_state(Carve& cv, const Dims& d, StateBufs* b) {
     t.eta_s = cv.take<double>(N);
     t.U_s = cv.take<double>(DN);
     t.u_s = cv.take<double>(DN);
-    t.eta_prev = cv.take<double>(N);
-    t.U_prev = cv.take<double>(DN);
-    t.fe_prev = cv.take<double>(N);
-    t.fU_prev = cv.take<double>(DN);
+    for (int k = 0; k < 2; ++k) {
+        t.lv_eta[k] = cv.take<double>(N);
+        t.lv_U[k] = cv.take<double>(DN);
+        t.lv_fe[k] = cv.take<double>(N);
+        t.lv_fU[k] = cv.take<double>(DN);
+        t.lv_R[k] = cv.take<cpx<double>>(DS);
+        t.lv_uh[k] = cv.take<cpx<double>>(DS);
+    }
     t.tmp_e = cv.take<double>(N);
     t.tmp_U = cv.take<double>(DN);
-    t.R_prev = cv.take<cpx<double>>(DS);
     t.R_cur = cv.take<cpx<double>>(DS);
     t.uh = cv.take<cpx<double>>(DS);
     t.Uh = cv.take<cpx<double>>(DS);
@@ -2112,12 +2117,20 @@ struct sgn_state {
     StateBufs b;
     double t;
     int64_t steps;
-    int kind;       // history held: 0 none, 1 Adams-Bashforth, 2 SBDF2
+    int kind;       // history held: 0 none, 1 Adams-Bashforth, 2 linearly implicit
     int ab_order;
     int ab_count;   // levels of f stored
     int ab_head;    // next ring slot
     double hist_dt;
+    // linearly implicit history: the scheme (steps and the parameter r of the
+    // third-order family; r < 0 for SBDF2), A = (sb_sig I - sb_alp grad div) with
+    // the scale theta already applied, the caller's fixed coefficients (0 if none),
+    // levels recorded in the ring and its oldest slot
+    int lm_s = 0;
+    double lm_r = -1.0, lm_theta = 1.0;
     double sb_sig, sb_alp;
+    double lm_fix_sig = 0.0, lm_fix_alp = 0.0;
+    int lm_count = 0, lm_head = 0;
     // initial-guess history: offsets recorded per slot, newest in gx_head
     int gx_mode;
     double gx_dt;
@@ -2149,10 +2162,12 @@ sgn_status copy_d(sgn_ctx* ctx, double* dst, const double* src, size_t n) {
     return SGN_OK;
 }
 
-// out = base + dt * sum_k c_k f_k (base may be null)
+// out = (base + dt * sum_k c_k f_k) / div (base may be null)
 sgn_status lincomb(sgn_ctx* ctx, size_t n, const double* base, double dt, std::vector<const double*> f,
-                   std::vector<double> c, double* out) {
+                   std::vector<double> c, double* out, double div = 1.0) {
     Lincomb4 lc{};
+    if (f.size() > (size_t)LINCOMB_MAX || f.size() != c.size()) return fail(ctx, SGN_EINVAL, "lincomb: terms");
+    lc.div = div;
     lc.n = (int)f.size();
     for (int k = 0; k < lc.n; ++k) {
         lc.f[k] = f[k];
@@ -2306,10 +2321,15 @@ sgn_status rk4_one(sgn_state* st, double dt, const sgn_solve_opts& o, sgn_step_i
                                  {w[0], w[1], w[2], w[3]}, DN, nullptr}})) != SGN_OK)
         return s;
     if ((s = copy_d(ctx, st->u, b.u_s, DN)) != SGN_OK) return s;
-    if ((s = stage_solve(st, GUESS_RK_FINAL, st->eta, st->U, st->u, o, acc)) != SGN_OK) return s;
-    st->t += dt;
-    st->steps += 1;
-    return SGN_OK;
+    // eta and U now hold level n+1: the step counts even if its final solve fails
+    // (u then holds that solve's last iterate), so that t and steps_done always
+    // describe eta and U and a retry does not advance them twice
+    s = stage_solve(st, GUESS_RK_FINAL, st->eta, st->U, st->u, o, acc);
+    if (s == SGN_OK || s == SGN_ENOCONV || s == SGN_EDOMAIN) {
+        st->t += dt;
+        st->steps += 1;
+    }
+    return s;
 }
 
 // R_hat = A u_hat - G_{eta,h} u_hat + U_hat at the state's level (u_hat in b.uh).
@@ -2334,24 +2354,51 @@ __global__ void k_sbdf2_R(int nx, int ny, size_t NS, double tpx, double tpy, dou
     }
 }
 
-// u_hat = A^{-1}(b0 R_prev + b1 R_cur) (Eq:MM with c = (0, 0, 1)); then R_prev <- R_cur.
+// Linearly implicit scheme of s <= 3 steps (Eq:IMEX_DAE): coefficients a_j,
+// c_j (j = 0..s) and b_j (j < s), lowest index first.
+struct LinimpScheme {
+    int s;
+    double a[4], b[3], c[4];
+};
+
+// Inputs of the constraint update: R_j and u_hat_j of the levels j < s.
+struct LinimpLevels {
+    const cpx<double>* R[3];
+    const cpx<double>* uh[3];
+    double b[3], c[3];
+    int s;
+};
+
+// u_hat_new = A^{-1} (sum_j b_j R_j - sum_{j<s} c_j A u_hat_j) / c_s per mode (the
+// constraint equation of Eq:IMEX_DAE; Eq:MM for SBDF2, where c_j = 0 for j < s).
+// out may alias an input (each mode is read before it is written).
 template <int D>
-__global__ void k_sbdf2_solve(int nx, int ny, size_t NS, double tpx, double tpy, double sig, double alp, double b0,
-                              double b1, cpx<double>* __restrict__ Rprev, const cpx<double>* __restrict__ Rcur,
-                              cpx<double>* __restrict__ uh) {
+__global__ void k_linimp_solve(int nx, int ny, size_t NS, double tpx, double tpy, double sig, double alp,
+                               double inv_cs, LinimpLevels L, cpx<double>* out) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < NS; idx += stride) {
         const int kxi = (int)(idx / ny), kyi = (int)(idx - (size_t)kxi * ny);
         const double kx = wavenumber<double>(kxi, nx, tpx);
         const double ky = D == 2 ? wavenumber<double>(kyi, ny, tpy) : 0.0;
         cpx<double> r[D], z[D];
-        for (int c = 0; c < D; ++c) {
-            const cpx<double> rn = Rcur[c * NS + idx];
-            r[c] = b0 * Rprev[c * NS + idx] + b1 * rn;
-            Rprev[c * NS + idx] = rn;
+        for (int c = 0; c < D; ++c) r[c] = C<double>(0.0, 0.0);
+        for (int j = 0; j < L.s; ++j) {
+            for (int c = 0; c < D; ++c) r[c] = r[c] + L.b[j] * L.R[j][c * NS + idx];
+            if (L.c[j] != 0.0) {
+                cpx<double> uu[D];
+                for (int c = 0; c < D; ++c) uu[c] = L.uh[j][c * NS + idx];
+                cpx<double> ku = kx * uu[0];
+                if (D == 2) ku = ku + ky * uu[1 % D];
+                for (int c = 0; c < D; ++c) {
+                    const double kc = c == 0 ? kx : ky;
+                    r[c] = r[c] - L.c[j] * (sig * uu[c] + (alp * kc) * ku);
+                }
+            }
         }
+        if (inv_cs != 1.0)
+            for (int c = 0; c < D; ++c) r[c] = inv_cs * r[c];
         precond_mode<double, D>(kx, ky, sig, alp, r, z);
-        for (int c = 0; c < D; ++c) uh[c * NS + idx] = z[c];
+        for (int c = 0; c < D; ++c) out[c * NS + idx] = z[c];
     }
 }
 
@@ -2384,21 +2431,48 @@ sgn_status sbdf2_R(sgn_state* st, cpx<double>* Rout) {
     return SGN_OK;
 }
 
+// Record the state's level (eta, U, f, R = A u - G u + U, u_hat) in ring slot k.
+// b.uh holds the state's u_hat on entry; afterwards b.uh is scratch.
 template <int D>
-sgn_status sbdf2_steps(sgn_state* st, double dt, int nsteps, const sgn_coeffs* fixed, const sgn_solve_opts& o,
-                       sgn_step_info* acc) {
+sgn_status linimp_record(sgn_state* st, int k) {
+    sgn_ctx* ctx = st->ctx;
+    StateBufs& b = st->b;
+    const size_t N = st->d.N, DN = (size_t)st->d.D * st->d.N;
+    sgn_status s;
+    if ((s = state_rhs(st, st->eta, st->u, b.lv_fe[k], b.lv_fU[k])) != SGN_OK) return s;
+    if ((s = sbdf2_R<D>(st, b.lv_R[k])) != SGN_OK) return s;
+    std::swap(b.lv_uh[k], b.uh);
+    if ((s = copy_d(ctx, b.lv_eta[k], st->eta, N)) != SGN_OK) return s;
+    return copy_d(ctx, b.lv_U[k], st->U, DN);
+}
+
+// nsteps steps of a linearly implicit scheme of s <= 3 steps with A = theta
+// (sigma I - alpha grad div): (sigma, alpha) fixed by the caller or taken from
+// the state's eta when a history starts (section 6.5), kept for its life.  A new
+// history records the current level and takes s-1 RK4 steps (opts), recording
+// each level; then every step forms
+//   w_{n+s}   = (-sum_{j<s} a_j w_{n+j} + dt sum_j b_j f_{n+j}) / a_s,
+//   A u_{n+s} = (sum_j b_j R_{n+j} - sum_{j<s} c_j A u_{n+j}) / c_s,
+// R = A u - G_{eta,h} u + U, with one A-solve and no Krylov iteration.
+template <int D>
+sgn_status linimp_steps(sgn_state* st, const LinimpScheme& sch, double scheme_r, double theta, double dt,
+                        int nsteps, const sgn_coeffs* fixed, const sgn_solve_opts& o, sgn_step_info* acc) {
     sgn_ctx* ctx = st->ctx;
     const Dims& d = st->d;
     StateBufs& b = st->b;
     const size_t N = d.N, DN = (size_t)d.D * d.N;
-    const double a0 = 0.5, a1 = -2.0, a2 = 1.5, b0 = -1.0, b1 = 2.0;  // SBDF2 of Table LMMCoeffs
+    const int S = sch.s;
     sgn_status s;
     if (nsteps <= 0) return SGN_OK;
-    if (st->kind != 2 || st->hist_dt != dt) {
-        // new history: fixed coefficients, f_0, R_0, w_0, then one RK4 step
+    // Eq:IMEX_DAE needs the same A on both sides of every step: another scheme,
+    // scale, dt or fixed coefficients start a new history
+    const double fs = fixed ? fixed->sigma : 0.0, fa = fixed ? fixed->alpha : 0.0;
+    const bool same = st->kind == 2 && st->hist_dt == dt && st->lm_s == S && st->lm_r == scheme_r &&
+                      st->lm_theta == theta && st->lm_fix_sig == fs && st->lm_fix_alp == fa;
+    if (!same) {
         if (fixed) {
-            st->sb_sig = fixed->sigma;
-            st->sb_alp = fixed->alpha;
+            st->sb_sig = theta * fixed->sigma;
+            st->sb_alp = theta * fixed->alpha;
         } else {
             Carve cv(st->ws);
             Common cm = carve_common(cv);
@@ -2407,47 +2481,137 @@ sgn_status sbdf2_steps(sgn_state* st, double dt, int nsteps, const sgn_coeffs* f
                 return s;
             if ((s = read_scal(ctx, cm.sc)) != SGN_OK) return s;
             if (ctx->hscal->status != 0) return fail(ctx, SGN_EDOMAIN, "total depth must be positive and finite");
-            st->sb_sig = ctx->hscal->sig;
-            st->sb_alp = ctx->hscal->alp;
+            st->sb_sig = theta * ctx->hscal->sig;
+            st->sb_alp = theta * ctx->hscal->alp;
         }
         st->kind = 2;
         st->hist_dt = dt;
-        if ((s = state_rhs(st, st->eta, st->u, b.fe_prev, b.fU_prev)) != SGN_OK) return s;
+        st->lm_s = S;
+        st->lm_r = scheme_r;
+        st->lm_theta = theta;
+        st->lm_fix_sig = fs;
+        st->lm_fix_alp = fa;
+        st->lm_count = 0;
+        st->lm_head = 0;
+    }
+    const int slots = S - 1;
+    auto slot = [&](int j) { return (st->lm_head + j) % slots; };   // j = 0: the oldest level
+    // start-up: record the level, then an RK4 step (its first stage reuses the f just formed)
+    while (st->lm_count < slots && nsteps > 0) {
+        const int k = slot(st->lm_count);
         if ((s = to_S_d<D>(ctx, d, st->u, b.Hs, b.uh)) != SGN_OK) return s;
-        if ((s = sbdf2_R<D>(st, b.R_prev)) != SGN_OK) return s;
-        if ((s = copy_d(ctx, b.eta_prev, st->eta, N)) != SGN_OK) return s;
-        if ((s = copy_d(ctx, b.U_prev, st->U, DN)) != SGN_OK) return s;
-        if ((s = rk4_one(st, dt, o, acc, false)) != SGN_OK) return s;
-        if ((s = to_S_d<D>(ctx, d, st->u, b.Hs, b.uh)) != SGN_OK) return s;
+        if ((s = linimp_record<D>(st, k)) != SGN_OK) return s;
+        if ((s = copy_d(ctx, b.rk_fe[0], b.lv_fe[k], N)) != SGN_OK) return s;
+        if ((s = copy_d(ctx, b.rk_fU[0], b.lv_fU[k], DN)) != SGN_OK) return s;
+        if ((s = rk4_one(st, dt, o, acc, true)) != SGN_OK) return s;
+        st->lm_count += 1;
         nsteps -= 1;
+        if (st->lm_count == slots && (s = to_S_d<D>(ctx, d, st->u, b.Hs, b.uh)) != SGN_OK) return s;
     }
     for (int n = 0; n < nsteps; ++n) {
-        // level n+1 is the state: f_{n+1}, R_{n+1}
+        // the current level n+s-1 is the state: f and R from eta, U and u_hat (b.uh)
         if ((s = state_rhs(st, st->eta, st->u, b.rk_fe[0], b.rk_fU[0])) != SGN_OK) return s;
         if ((s = sbdf2_R<D>(st, b.R_cur)) != SGN_OK) return s;
-        // w_{n+2} = (-a0 w_n - a1 w_{n+1} + dt (b0 f_n + b1 f_{n+1})) / a2
-        if ((s = lincomb(ctx, N, nullptr, 1.0, {b.eta_prev, st->eta, b.fe_prev, b.rk_fe[0]},
-                         {-a0 / a2, -a1 / a2, dt * b0 / a2, dt * b1 / a2}, b.tmp_e)) != SGN_OK)
-            return s;
-        if ((s = lincomb(ctx, DN, nullptr, 1.0, {b.U_prev, st->U, b.fU_prev, b.rk_fU[0]},
-                         {-a0 / a2, -a1 / a2, dt * b0 / a2, dt * b1 / a2}, b.tmp_U)) != SGN_OK)
-            return s;
-        // history shift, then the new level
-        if ((s = copy_d(ctx, b.eta_prev, st->eta, N)) != SGN_OK) return s;
-        if ((s = copy_d(ctx, b.U_prev, st->U, DN)) != SGN_OK) return s;
-        if ((s = copy_d(ctx, b.fe_prev, b.rk_fe[0], N)) != SGN_OK) return s;
-        if ((s = copy_d(ctx, b.fU_prev, b.rk_fU[0], DN)) != SGN_OK) return s;
+        std::vector<const double*> te, tU;
+        std::vector<double> cw;
+        for (int j = 0; j < S; ++j) {
+            te.push_back(j < slots ? b.lv_eta[slot(j)] : st->eta);
+            tU.push_back(j < slots ? b.lv_U[slot(j)] : st->U);
+            cw.push_back(-sch.a[j]);
+        }
+        for (int j = 0; j < S; ++j) {
+            te.push_back(j < slots ? b.lv_fe[slot(j)] : b.rk_fe[0]);
+            tU.push_back(j < slots ? b.lv_fU[slot(j)] : b.rk_fU[0]);
+            cw.push_back(dt * sch.b[j]);
+        }
+        if ((s = lincomb(ctx, N, nullptr, 1.0, te, cw, b.tmp_e, sch.a[S])) != SGN_OK) return s;
+        if ((s = lincomb(ctx, DN, nullptr, 1.0, tU, cw, b.tmp_U, sch.a[S])) != SGN_OK) return s;
+        // u_hat of level n+s into the oldest slot's u_hat buffer (read first per mode)
+        LinimpLevels lv{};
+        lv.s = S;
+        for (int j = 0; j < S; ++j) {
+            lv.R[j] = j < slots ? b.lv_R[slot(j)] : b.R_cur;
+            lv.uh[j] = j < slots ? b.lv_uh[slot(j)] : b.uh;
+            lv.b[j] = sch.b[j];
+            lv.c[j] = sch.c[j];
+        }
+        const int old = slot(0);
+        hipLaunchKernelGGL(k_linimp_solve<D>, dim3(flat_blocks(d.NS)), dim3(256), 0, ctx->stream, d.nx, d.ny, d.NS,
+                           d.tpx, d.tpy, st->sb_sig, st->sb_alp, 1.0 / sch.c[S], lv, b.lv_uh[old]);
+        CHECK_LAUNCH(ctx);
+        // ring shift: the oldest slot takes the current level; the new level becomes the state
+        if ((s = copy_d(ctx, b.lv_eta[old], st->eta, N)) != SGN_OK) return s;
+        if ((s = copy_d(ctx, b.lv_U[old], st->U, DN)) != SGN_OK) return s;
+        std::swap(b.lv_fe[old], b.rk_fe[0]);
+        std::swap(b.lv_fU[old], b.rk_fU[0]);
+        std::swap(b.lv_R[old], b.R_cur);
+        std::swap(b.lv_uh[old], b.uh);   // slot: the current u_hat; b.uh: the new one
+        st->lm_head = (st->lm_head + 1) % slots;
         if ((s = copy_d(ctx, st->eta, b.tmp_e, N)) != SGN_OK) return s;
         if ((s = copy_d(ctx, st->U, b.tmp_U, DN)) != SGN_OK) return s;
-        hipLaunchKernelGGL(k_sbdf2_solve<D>, dim3(flat_blocks(d.NS)), dim3(256), 0, ctx->stream, d.nx, d.ny, d.NS,
-                           d.tpx, d.tpy, st->sb_sig, st->sb_alp, b0, b1, b.R_prev, (const cpx<double>*)b.R_cur,
-                           b.uh);
-        CHECK_LAUNCH(ctx);
         if ((s = from_S_d<D>(ctx, d, b.uh, b.Hs, st->u)) != SGN_OK) return s;
         st->t += dt;
         st->steps += 1;
     }
     return SGN_OK;
+}
+
+// Coefficients of SBDF2 (Table LMMCoeffs).
+LinimpScheme scheme_sbdf2() {
+    LinimpScheme q{};
+    q.s = 2;
+    q.a[0] = 0.5;
+    q.a[1] = -2.0;
+    q.a[2] = 1.5;
+    q.b[0] = -1.0;
+    q.b[1] = 2.0;
+    q.c[2] = 1.0;
+    return q;
+}
+
+// The third-order family with c(z) = (z - r)^3 and b(z) = c(z) - (z - 1)^3 (so the
+// constraint recurrence has defect O(dt^3)); a(z) solves the third-order
+// conditions sum_j a_j j^k = k sum_j c_j j^(k-1), k = 0..3 (Gaussian elimination
+// of the 4 x 4 Vandermonde system).  r = 0 is SBDF3.
+LinimpScheme scheme_sbdf3r(double r) {
+    LinimpScheme q{};
+    q.s = 3;
+    q.c[0] = -r * r * r;
+    q.c[1] = 3.0 * r * r;
+    q.c[2] = -3.0 * r;
+    q.c[3] = 1.0;
+    const double cube[4] = {-1.0, 3.0, -3.0, 1.0};   // (z - 1)^3
+    for (int j = 0; j < 3; ++j) q.b[j] = q.c[j] - cube[j];
+    double M[4][5];
+    for (int k = 0; k < 4; ++k) {
+        double rhs = 0.0;
+        for (int j = 0; j < 4; ++j) {
+            M[k][j] = (k == 0) ? 1.0 : std::pow((double)j, k);
+            if (k >= 1) rhs += q.c[j] * (k == 1 ? 1.0 : std::pow((double)j, k - 1));
+        }
+        M[k][4] = k * rhs;
+    }
+    for (int col = 0; col < 4; ++col) {
+        int piv = col;
+        for (int r2 = col + 1; r2 < 4; ++r2)
+            if (std::fabs(M[r2][col]) > std::fabs(M[piv][col])) piv = r2;
+        for (int j = 0; j < 5; ++j) std::swap(M[col][j], M[piv][j]);
+        for (int r2 = 0; r2 < 4; ++r2) {
+            if (r2 == col) continue;
+            const double f = M[r2][col] / M[col][col];
+            for (int j = col; j < 5; ++j) M[r2][j] -= f * M[col][j];
+        }
+    }
+    for (int j = 0; j < 4; ++j) q.a[j] = M[j][4] / M[j][j];
+    return q;
+}
+
+// Real stable interval of the third-order family (roots of Eq:CharEq in |z| < 1):
+// (1 / (1 + (1 + r)^3), 1 / (1 - ((1 + r) / 2)^3)).
+void sbdf3r_interval(double r, double* lo, double* hi) {
+    *lo = 1.0 / (1.0 + (1.0 + r) * (1.0 + r) * (1.0 + r));
+    const double h = 0.5 * (1.0 + r);
+    *hi = 1.0 / (1.0 - h * h * h);
 }
 
 void info_init(sgn_step_info* acc) {
@@ -2515,6 +2679,7 @@ sgn_status sgn_create(sgn_ctx** out, int device, void* hip_stream) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         ctx->cus = cus;
+
     const char* bt = getenv("SGN_BATCH_THREADS");
     if (bt) ctx->batch_threads = atoi(bt);
     // HIP graphs for the PCG chunks are opt-in: their host-side launch costs more
@@ -3156,10 +3321,15 @@ sgn_status sgn_step_ab(sgn_ctx* ctx, sgn_state* st, int32_t order, double dt, in
         }
         if ((s = lincomb(ctx, N, st->eta, dt, fe, c, st->eta)) != SGN_OK) break;
         if ((s = lincomb(ctx, DN, st->U, dt, fU, c, st->U)) != SGN_OK) break;
-        if ((s = stage_solve(st, GUESS_AB, st->eta, st->U, st->u, o, &acc)) != SGN_OK) break;
-        st->t += dt;
-        st->steps += 1;
+        // as in RK4: the step counts even if its solve fails (u: the last iterate)
+        s = stage_solve(st, GUESS_AB, st->eta, st->U, st->u, o, &acc);
+        if (s == SGN_OK || s == SGN_ENOCONV || s == SGN_EDOMAIN) {
+            st->t += dt;
+            st->steps += 1;
+        }
+        if (s != SGN_OK) break;
     }
+    if (s != SGN_OK) st->kind = 0;   // the history no longer holds converged levels
     info_finish(st, &acc, info);
     return s;
 }
@@ -3176,8 +3346,64 @@ sgn_status sgn_step_linimp(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nstep
     guess_prepare(st, o, dt);
     sgn_step_info acc;
     info_init(&acc);
-    sgn_status s = st->d.D == 1 ? sbdf2_steps<1>(st, dt, nsteps, fixed, o, &acc)
-                                : sbdf2_steps<2>(st, dt, nsteps, fixed, o, &acc);
+    const LinimpScheme q = scheme_sbdf2();
+    sgn_status s = st->d.D == 1 ? linimp_steps<1>(st, q, -1.0, 1.0, dt, nsteps, fixed, o, &acc)
+                                : linimp_steps<2>(st, q, -1.0, 1.0, dt, nsteps, fixed, o, &acc);
+    if (s != SGN_OK) st->kind = 0;
+    if (s == SGN_OK) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    info_finish(st, &acc, info);
+    return s;
+}
+
+sgn_status sgn_linimp3_choose(double kappa, double margin, double* r, double* theta) {
+    if (!r || !theta || !(kappa >= 1.0) || !(margin >= 1.0) || !std::isfinite(kappa) || !std::isfinite(margin))
+        return SGN_EINVAL;
+    const double need = kappa * margin * margin;
+    auto ratio = [](double q) {
+        double lo, hi;
+        sbdf3r_interval(q, &lo, &hi);
+        return hi / lo;
+    };
+    double rr = 0.0;
+    if (ratio(0.0) < need) {
+        // the ratio grows monotonically from 16/7 at r = 0 without bound as r -> 1
+        double a = 0.0, b = 1.0 - 1e-15;
+        for (int it = 0; it < 200; ++it) {
+            const double m = 0.5 * (a + b);
+            if (ratio(m) >= need)
+                b = m;
+            else
+                a = m;
+        }
+        rr = b;
+    }
+    double lo, hi;
+    sbdf3r_interval(rr, &lo, &hi);
+    *r = rr;
+    *theta = 1.0 / std::sqrt(lo * hi * kappa);
+    return SGN_OK;
+}
+
+sgn_status sgn_step_linimp3(sgn_ctx* ctx, sgn_state* st, double r, double theta, double dt, int32_t nsteps,
+                            const sgn_coeffs* fixed, const sgn_solve_opts* opts, sgn_step_info* info) {
+    if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (st->twin)
+        return wall_steps(st, [&](sgn_state* tw) {
+            return sgn_step_linimp3(ctx, tw, r, theta, dt, nsteps, fixed, opts, info);
+        });
+    if (nsteps < 0 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad step arguments");
+    if (!(r >= 0.0 && r < 1.0) || !(theta > 0.0) || !std::isfinite(theta))
+        return fail(ctx, SGN_EINVAL, "r must lie in [0, 1) and theta be > 0");
+    if (fixed && !(fixed->sigma > 0.0 && fixed->alpha > 0.0)) return fail(ctx, SGN_EINVAL, "bad fixed coefficients");
+    const sgn_solve_opts o = opts ? *opts : default_opts();
+    if (o.guess != SGN_GUESS_PREVIOUS && o.guess != SGN_GUESS_EXTRAPOLATE) return fail(ctx, SGN_EINVAL, "bad guess");
+    guess_prepare(st, o, dt);
+    sgn_step_info acc;
+    info_init(&acc);
+    const LinimpScheme q = scheme_sbdf3r(r);
+    sgn_status s = st->d.D == 1 ? linimp_steps<1>(st, q, r, theta, dt, nsteps, fixed, o, &acc)
+                                : linimp_steps<2>(st, q, r, theta, dt, nsteps, fixed, o, &acc);
+    if (s != SGN_OK) st->kind = 0;
     if (s == SGN_OK) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     info_finish(st, &acc, info);
     return s;

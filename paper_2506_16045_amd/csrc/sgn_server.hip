@@ -78,12 +78,23 @@ LaneLayout lane_layout(const sgn_request& r) {
     return l;
 }
 
+// Size class of a pooled lane block: the power of two (at least 4 KiB) that
+// holds `b` bytes, which is what a lane request really occupies.
+size_t pool_class(size_t b) {
+    size_t c = 4096;
+    while (c < b) c <<= 1;
+    return c;
+}
+
+// Device bytes charged to an admitted request: its pooled block for a lane
+// request; for a batched 1D solve its fields and its share of the batching
+// lane's buffer (a group's buffer never exceeds the sum of its members' charges).
 size_t footprint(const sgn_request& r) {
     if (batchable(r)) {
         const int32_t n = r.grid.nx;
         return 4 * up((size_t)n * sizeof(double)) + sgn_batch_workspace_bytes(1, &n, r.opts.precision);
     }
-    return lane_layout(r).total;
+    return pool_class(lane_layout(r).total);
 }
 
 bool request_ok(const sgn_request& r) {
@@ -108,50 +119,106 @@ struct Req {
     std::vector<double> in;   // copied inputs: eta | grad_h | rhs | h | u0
     size_t fp = 0;
     bool batch = false;
-    sgn_result res{};
+    sgn_result res{};         // read and written under the server mutex only
+};
+
+// What a lane or the batching lane learned about a request; copied into the
+// request's result under the server mutex when it finishes.
+struct Outcome {
+    int64_t iters = 0, solves = 0;
+    double relres = 0.0;
+    int32_t batched = 0, batch_size = 0;
 };
 
 // Device memory kept in power-of-two size classes for reuse (hipFree would
-// synchronise the device under running lanes).
+// synchronise the device under running lanes).  Cached free blocks are given
+// back (trim) when an allocation would otherwise take the server's device
+// memory past its budget.
 class Pool {
    public:
-    void* get(size_t bytes) {
-        const size_t c = cls(bytes);
-        {
-            std::lock_guard<std::mutex> g(m_);
-            auto& v = free_[c];
-            if (!v.empty()) {
-                void* p = v.back();
-                v.pop_back();
-                return p;
-            }
-        }
-        void* p = nullptr;
-        if (hipMalloc(&p, c) != hipSuccess) return nullptr;
+    explicit Pool(size_t budget = 0) : budget_(budget) {}
+    void set_budget(size_t b) { budget_ = b; }
+
+    // A block of class c: a cached one, else a new allocation; if the new block
+    // would take the held bytes past the budget, the cached blocks are freed first.
+    void* get(size_t c) {
         std::lock_guard<std::mutex> g(m_);
-        all_.push_back(p);
+        auto& v = free_[c];
+        if (!v.empty()) {
+            void* p = v.back();
+            v.pop_back();
+            free_bytes_ -= c;
+            return p;
+        }
+        void* p = alloc_locked(c);
+        if (p) all_[p] = c;
         return p;
     }
-    void put(void* p, size_t bytes) {
+    // Replace the batching lane's buffer (`old`, old_bytes) by one of `need` bytes,
+    // under the same accounting.  Returns null (old freed) on failure.
+    void* regrow(void* old, size_t old_bytes, size_t need) {
         std::lock_guard<std::mutex> g(m_);
-        free_[cls(bytes)].push_back(p);
+        if (old) {
+            (void)hipFree(old);
+            held_ -= old_bytes;
+        }
+        return alloc_locked(need);
+    }
+    void free_extra(void* p, size_t bytes) {
+        std::lock_guard<std::mutex> g(m_);
+        if (p) {
+            (void)hipFree(p);
+            held_ -= bytes;
+        }
+    }
+    void put(void* p, size_t c) {
+        std::lock_guard<std::mutex> g(m_);
+        free_[c].push_back(p);
+        free_bytes_ += c;
+    }
+    // Device bytes held: pooled blocks (cached or in use) and the batch buffer.
+    size_t held() {
+        std::lock_guard<std::mutex> g(m_);
+        return held_;
     }
     void release() {
         std::lock_guard<std::mutex> g(m_);
-        for (void* p : all_) (void)hipFree(p);
+        for (auto& kv : all_) (void)hipFree(kv.first);
         all_.clear();
         free_.clear();
+        held_ = free_bytes_ = 0;
     }
 
    private:
-    static size_t cls(size_t b) {
-        size_t c = 4096;
-        while (c < b) c <<= 1;
-        return c;
+    void* alloc_locked(size_t bytes) {
+        if (held_ + bytes > budget_) trim_locked();
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            trim_locked();
+            if (hipMalloc(&p, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        held_ += bytes;
+        return p;
+    }
+    void trim_locked() {
+        for (auto& kv : free_) {
+            for (void* p : kv.second) {
+                (void)hipFree(p);
+                all_.erase(p);
+                held_ -= kv.first;
+            }
+            kv.second.clear();
+        }
+        free_bytes_ = 0;
     }
     std::mutex m_;
     std::map<size_t, std::vector<void*>> free_;
-    std::vector<void*> all_;
+    std::unordered_map<void*, size_t> all_;
+    size_t held_ = 0, free_bytes_ = 0, budget_ = 0;
 };
 
 struct Lane {
@@ -175,7 +242,14 @@ struct sgn_server {
     std::deque<Req*> batch_q;          // admitted, for the batching lane
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
     uint64_t next_id = 1;
-    size_t in_use = 0;
+    // Device memory accounting (under m).  lane_charged: pooled blocks of the
+    // admitted lane requests; batch_charged: footprints of the admitted batched
+    // solves.  The batching lane's grow-only buffer (d_batch_bytes) stays held
+    // after its group finishes, so the commitment is
+    //   lane_charged + max(batch_charged, d_batch_bytes) <= budget,
+    // and every block the server holds (pool blocks, cached or in use, and the
+    // batch buffer) is freed back to that bound before an allocation exceeds it.
+    size_t lane_charged = 0, batch_charged = 0;
     int64_t n_admitted = 0, n_completed = 0;
     int running = 0;                   // requests taken by a lane and not yet finished
     bool stopping = false;
@@ -195,9 +269,11 @@ struct sgn_server {
         bool any = false;
         while (!queued.empty()) {
             Req* q = queued.front();
-            if (in_use + q->fp > budget) break;
+            const size_t after = q->batch ? lane_charged + std::max(batch_charged + q->fp, d_batch_bytes)
+                                          : lane_charged + q->fp + std::max(batch_charged, d_batch_bytes);
+            if (after > budget) break;
             queued.pop_front();
-            in_use += q->fp;
+            (q->batch ? batch_charged : lane_charged) += q->fp;
             q->res.t_admit = now();
             ++n_admitted;
             (q->batch ? batch_q : lane_q).push_back(q);
@@ -206,12 +282,17 @@ struct sgn_server {
         if (any) cv_work.notify_all();
     }
 
-    void finish(Req* q, sgn_status st) {
+    void finish(Req* q, sgn_status st, const Outcome& oc) {
         std::lock_guard<std::mutex> g(m);
+        q->res.iters = oc.iters;
+        q->res.solves = oc.solves;
+        q->res.relres = oc.relres;
+        q->res.batched = oc.batched;
+        q->res.batch_size = oc.batch_size;
         q->res.status = st;
         q->res.t_done = now();
         q->res.done = 1;
-        in_use -= q->fp;
+        (q->batch ? batch_charged : lane_charged) -= q->fp;
         ++n_completed;
         --running;
         admit_locked();
@@ -219,17 +300,20 @@ struct sgn_server {
         cv_work.notify_all();
     }
 
+
+
     bool idle_locked() const { return queued.empty() && lane_q.empty() && batch_q.empty() && running == 0; }
 
     void lane_loop(Lane* L);
     void batch_loop();
-    sgn_status run_lane(Lane* L, Req* q);
+    sgn_status run_lane(Lane* L, Req* q, Outcome* oc);
 };
 
-sgn_status sgn_server::run_lane(Lane* L, Req* q) {
+sgn_status sgn_server::run_lane(Lane* L, Req* q, Outcome* oc) {
     const sgn_request& r = q->r;
     const LaneLayout lay = lane_layout(r);
-    char* base = static_cast<char*>(pool.get(lay.total));
+    const size_t cls = pool_class(lay.total);
+    char* base = static_cast<char*>(pool.get(cls));
     if (!base) return SGN_ENOMEM;
     const size_t N = npts(r.grid), dN = (size_t)r.grid.dim * N;
     auto D = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
@@ -254,9 +338,9 @@ sgn_status sgn_server::run_lane(Lane* L, Req* q) {
         if (st == SGN_OK)
             st = sgn_krylov_solve(L->ctx, &r.grid, D(lay.eta), D(lay.gh), D(lay.rhs), D(lay.u), nullptr, &r.opts,
                                   &info, base + lay.ws);
-        q->res.iters = info.iters;
-        q->res.solves = 1;
-        q->res.relres = info.relres;
+        oc->iters = info.iters;
+        oc->solves = 1;
+        oc->relres = info.relres;
         if ((st == SGN_OK || st == SGN_ENOCONV) && !(d2h(r.h_u_out, D(lay.u), dN))) st = SGN_EDEVICE;
     } else {
         ok = h2d(D(lay.h), r.h_h, N) && h2d(D(lay.eta), r.h_eta, N) && h2d(D(lay.u), r.h_u0, dN);
@@ -272,8 +356,8 @@ sgn_status sgn_server::run_lane(Lane* L, Req* q) {
         sgn_step_info info{};
         if (st == SGN_OK) st = sgn_step_rk4(L->ctx, state, r.dt, r.nsteps, &r.opts, &info);
         if (state) sgn_state_destroy(state);
-        q->res.iters = info.iters;
-        q->res.solves = info.solves;
+        oc->iters = info.iters;
+        oc->solves = info.solves;
         if (st == SGN_OK || st == SGN_ENOCONV) {
             ok = d2h(r.h_u_out, D(lay.u), dN);
             if (ok && r.h_eta_out) ok = d2h(r.h_eta_out, D(lay.eta), N);
@@ -281,7 +365,7 @@ sgn_status sgn_server::run_lane(Lane* L, Req* q) {
         }
     }
     if (hipStreamSynchronize(L->stream) != hipSuccess && st == SGN_OK) st = SGN_EDEVICE;
-    pool.put(base, lay.total);
+    pool.put(base, cls);
     return st;
 }
 
@@ -298,7 +382,9 @@ void sgn_server::lane_loop(Lane* L) {
             ++running;
             q->res.t_start = now();
         }
-        finish(q, run_lane(L, q));
+        Outcome oc;
+        const sgn_status st = run_lane(L, q, &oc);
+        finish(q, st, oc);
     }
 }
 
@@ -346,13 +432,13 @@ void sgn_server::batch_loop() {
         const size_t need = 4 * up(tot * sizeof(double)) + up(wsb);
         sgn_status st = SGN_OK;
         if (need > d_batch_bytes) {
-            if (d_batch) (void)hipFree(d_batch);
-            d_batch = nullptr;
-            d_batch_bytes = 0;
-            if (hipMalloc(&d_batch, need) == hipSuccess)
-                d_batch_bytes = need;
-            else
-                st = SGN_ENOMEM;
+            // the group's charges cover `need` (each member was charged its fields and
+            // a one-system workspace, at least its share of the group's)
+            void* nb = pool.regrow(d_batch, d_batch_bytes, need);
+            std::lock_guard<std::mutex> g(m);
+            d_batch = nb;
+            d_batch_bytes = nb ? need : 0;
+            if (!nb) st = SGN_ENOMEM;
         }
         if (st == SGN_OK && 4 * tot > h_stage_doubles) {
             if (h_stage) (void)hipHostFree(h_stage);
@@ -412,20 +498,20 @@ void sgn_server::batch_loop() {
             }
         }
         for (int i = 0; i < n; ++i) {
-            Req* q = group[i];
-            q->res.batched = 1;
-            q->res.batch_size = n;
+            Outcome oc;
+            oc.batched = 1;
+            oc.batch_size = n;
             sgn_status qs = st;
             if (st == SGN_OK) {
-                q->res.iters = info[i].iters;
-                q->res.solves = 1;
-                q->res.relres = info[i].relres;
+                oc.iters = info[i].iters;
+                oc.solves = 1;
+                oc.relres = info[i].relres;
                 if (!(info[i].relres == info[i].relres))
                     qs = SGN_EDOMAIN;
                 else if (!info[i].converged)
                     qs = SGN_ENOCONV;
             }
-            finish(q, qs);
+            finish(group[i], qs, oc);
         }
     }
 }
@@ -448,6 +534,7 @@ sgn_status sgn_server_create(sgn_server** out, int device, const sgn_server_opts
     size_t fr = 0, total = 0;
     if (hipMemGetInfo(&fr, &total) != hipSuccess) return SGN_EDEVICE;
     s->budget = (opts && opts->hbm_budget) ? opts->hbm_budget : (size_t)(0.8 * (double)fr);
+    s->pool.set_budget(s->budget);
     const int nl = (opts && opts->lanes > 0) ? opts->lanes : 3;
     s->max_batch = (opts && opts->max_batch > 0) ? opts->max_batch : 1024;
     auto make_lane = [&](Lane& L) -> bool {
@@ -489,7 +576,7 @@ void sgn_server_destroy(sgn_server* s) {
     }
     sgn_destroy(s->blane.ctx);
     (void)hipStreamDestroy(s->blane.stream);
-    if (s->d_batch) (void)hipFree(s->d_batch);
+    s->pool.free_extra(s->d_batch, s->d_batch_bytes);
     if (s->h_stage) (void)hipHostFree(s->h_stage);
     s->pool.release();
     delete s;
@@ -569,13 +656,15 @@ sgn_status sgn_server_wait(sgn_server* s, uint64_t id, double timeout_s, sgn_res
 }
 
 sgn_status sgn_server_stats(sgn_server* s, int64_t* queued, int64_t* admitted, int64_t* completed,
-                            size_t* bytes_in_use, size_t* budget) {
+                            size_t* bytes_in_use, size_t* bytes_held, size_t* budget) {
     if (!s) return SGN_EINVAL;
+    const size_t pool_held = s->pool.held();
     std::lock_guard<std::mutex> g(s->m);
     if (queued) *queued = (int64_t)s->queued.size();
     if (admitted) *admitted = s->n_admitted;
     if (completed) *completed = s->n_completed;
-    if (bytes_in_use) *bytes_in_use = s->in_use;
+    if (bytes_in_use) *bytes_in_use = s->lane_charged + s->batch_charged;
+    if (bytes_held) *bytes_held = pool_held;
     if (budget) *budget = s->budget;
     return SGN_OK;
 }

@@ -126,7 +126,7 @@ _SIGS = {
     "sgn_server_wait": (_S, [_P, ctypes.c_uint64, _D, ctypes.POINTER(Result)]),
     "sgn_server_stats": (_S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t),
-                              ctypes.POINTER(ctypes.c_size_t)]),
+                              ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "sgn_batch_solve": (_S, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_D), _P, _P, _P, _P,
                              ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
     "sgn_state_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
@@ -136,6 +136,9 @@ _SIGS = {
     "sgn_step_ab": (_S, [_P, _P, _I, _D, _I, ctypes.POINTER(SolveOpts), ctypes.POINTER(StepInfo)]),
     "sgn_step_linimp": (_S, [_P, _P, _D, _I, ctypes.POINTER(Coeffs), ctypes.POINTER(SolveOpts),
                              ctypes.POINTER(StepInfo)]),
+    "sgn_step_linimp3": (_S, [_P, _P, _D, _D, _D, _I, ctypes.POINTER(Coeffs), ctypes.POINTER(SolveOpts),
+                              ctypes.POINTER(StepInfo)]),
+    "sgn_linimp3_choose": (_S, [_D, _D, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -480,6 +483,15 @@ class State:
                                          ctypes.byref(opts) if opts else None, ctypes.byref(info)))
         return info
 
+    def step_linimp3(self, r: float, theta: float, dt: float, nsteps: int, fixed: Coeffs | None = None,
+                     opts: SolveOpts | None = None) -> StepInfo:
+        self.ctx._sync_stream()
+        info = StepInfo()
+        self.ctx._check(_lib.sgn_step_linimp3(self.ctx._h, self._h, r, theta, dt, nsteps,
+                                              ctypes.byref(fixed) if fixed else None,
+                                              ctypes.byref(opts) if opts else None, ctypes.byref(info)))
+        return info
+
     def step_linimp(self, dt: float, nsteps: int, fixed: Coeffs | None = None,
                     opts: SolveOpts | None = None) -> StepInfo:
         self.ctx._sync_stream()
@@ -488,6 +500,16 @@ class State:
                                              ctypes.byref(fixed) if fixed else None,
                                              ctypes.byref(opts) if opts else None, ctypes.byref(info)))
         return info
+
+
+def linimp3_choose(kappa: float, margin: float = 1.1):
+    """(r, theta) of the third-order linearly implicit scheme for eigenvalues of
+    A^{-1} G in [1/kappa, 1] (sgn_linimp3_choose, host only)."""
+    r, th = _D(), _D()
+    st = _lib.sgn_linimp3_choose(float(kappa), float(margin), ctypes.byref(r), ctypes.byref(th))
+    if st != OK:
+        raise SgnError(st, "kappa >= 1 and margin >= 1 required")
+    return r.value, th.value
 
 
 # ---- served execution ------------------------------------------------------------
@@ -589,8 +611,8 @@ class Server:
 
     def stats(self):
         q, a, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        used, budget = ctypes.c_size_t(), ctypes.c_size_t()
+        used, held, budget = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
         _lib.sgn_server_stats(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(c), ctypes.byref(used),
-                              ctypes.byref(budget))
+                              ctypes.byref(held), ctypes.byref(budget))
         return {"queued": q.value, "admitted": a.value, "completed": c.value, "bytes_in_use": used.value,
-                "budget": budget.value}
+                "bytes_held": held.value, "budget": budget.value}

@@ -113,3 +113,17 @@ def test_binding_constants_match_the_header():
     n_kinds = kinds.pop("kinds")
     assert len(S.Context.KERNEL_KINDS) == n_kinds
     assert {k: i for i, k in enumerate(S.Context.KERNEL_KINDS)} == kinds
+
+
+def test_linimp3_choice_equals_the_oracles():
+    """The library's joint choice of (r, theta) for the third-order linearly
+    implicit scheme (host only) equals the oracle's, written independently."""
+    from oracle import linimp as L
+    from paper_2506_16045_amd import sgn
+    for kappa in (1.0, 1.728, 5.0, 17.6, 266.5, 338.9, 1e4):
+        for margin in (1.0, 1.1, 1.5):
+            r, th = sgn.linimp3_choose(kappa, margin)
+            r_o, th_o = L.choose_sbdf3r(kappa, margin)
+            assert abs(r - r_o) <= 1e-12 and abs(th - th_o) <= 1e-12 * th_o, (kappa, margin)
+    with pytest.raises(sgn.SgnError):
+        sgn.linimp3_choose(0.5)

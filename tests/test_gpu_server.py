@@ -83,14 +83,21 @@ def test_results_same_alone_and_in_the_mix(precision):
     srv.close()
 
 
-def test_results_match_the_oracle():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_results_match_the_oracle(precision):
+    """Every served result against the FP64 oracle, the error stated per result:
+    solves by relative L2 distance to the oracle's PCG solution and by true
+    residual, RK4 runs per field (zeta, u, U); 1e-10 for the FP64 path, 1e-9 for
+    the mixed one (FP32 inner solves inside FP64 refinement)."""
     from paper_2506_16045_amd import sgn
     cases = _cases()
     tol = 1e-11
-    opts = sgn.solve_opts(tol=tol, max_iter=3000)
+    prec = sgn.FP64 if precision == "fp64" else sgn.MIXED
+    gate = 1e-10 if precision == "fp64" else 1e-9
+    opts = sgn.solve_opts(tol=tol, max_iter=3000, precision=prec, inner_tol=1e-4)
     srv = sgn.Server(0)
     ids = [srv.submit(_req(srv, c, opts)) for c in cases]
-    for c, rid in zip(cases, ids):
+    for i, (c, rid) in enumerate(zip(cases, ids)):
         res, out = srv.wait(rid)
         assert res.status == sgn.OK
         g = c["g"]
@@ -103,14 +110,21 @@ def test_results_match_the_oracle():
             bn = np.linalg.norm(b)
             r = np.linalg.norm(b - op.apply_G(eta, gh, u, g))
             r_ref = np.linalg.norm(b - op.apply_G(eta, gh, u_ref, g))
+            err = dg.rel_l2(u, u_ref)
+            print(f"  result {i}: solve {g.d}D n={g.nx} {precision} error vs oracle {err:.2e} "
+                  f"relres {r / bn:.2e}", flush=True)
             assert r <= 2.0 * max(r_ref, tol * bn)
-            assert abs(res.iters - it) <= 1
+            assert err <= gate, err
+            if precision == "fp64":
+                assert abs(res.iters - it) <= 1
         else:
             pb = ost.Problem.from_h(g, c["h"], tol=tol)
             U0 = pb.G(c["eta"], c["u"])
             e_r, U_r, u_r = ost.run_rk4(pb, c["eta"], U0, c["u"], c["dt"], c["nsteps"])
             err = dg.field_errors(out["eta"], pb.G(out["eta"], out["u"]), out["u"], e_r, U_r, u_r, c["h"])
-            assert max(err.values()) <= 1e-10, err
+            print(f"  result {i}: {c['nsteps']} RK4 steps {g.d}D n={g.nx} {precision} error vs oracle "
+                  f"{max(err.values()):.2e}", flush=True)
+            assert max(err.values()) <= gate, err
             assert res.solves == 4 * c["nsteps"]
     srv.close()
 
@@ -126,13 +140,20 @@ def test_admission_by_footprint():
     budget = int(1.2 * max(fps))
     srv = sgn.Server(0, hbm_budget=budget, lanes=2)
     ids = [srv.submit(_req(srv, c, opts)) for c in cases]
-    starts = []
-    for rid in ids:
+    spans = []
+    for rid, fp in zip(ids, fps):
         res, out = srv.wait(rid)
         assert res.status == sgn.OK and res.t_submit <= res.t_admit <= res.t_start <= res.t_done
-        starts.append((res.t_admit, res.t_done))
+        spans.append((res.t_admit, res.t_done, fp, res.t_submit))
+    # at no time did the admitted requests' footprints exceed the budget
+    for t0, _, _, _ in spans:
+        live = sum(fp for a, d, fp, _ in spans if a <= t0 < d)
+        assert live <= budget, (live, budget)
+    # the budget held requests back: at least one waited for admission
+    assert any(a > s for a, _, _, s in spans)
     st = srv.stats()
     assert st["budget"] == budget and st["bytes_in_use"] == 0 and st["completed"] == len(cases)
+    assert 0 < st["bytes_held"] <= budget
     # a request larger than the whole budget is refused at submission
     big = dict(cases[6])
     g = I.grid2d(1024, 1024, 200.0, 200.0)
