@@ -142,13 +142,20 @@ def test_pcg_fp64_matches_oracle(ctx, g):
         assert abs(res.iters - it_twin) <= 1, (res.iters, it_twin)
     assert abs(res.iters - it_ref) <= max(2, 0.12 * it_ref), (res.iters, it_ref)
     np.testing.assert_allclose([res.sigma, res.alpha, res.kappa_ub], co, rtol=1e-13)
-    assert rel(_n(u), u_ref) <= 1e-9
+    err = rel(_n(u), u_ref)
     # the true residual with the oracle's wall operator is of the size of the oracle's
-    # own: both floor near eps ||G|| ||u|| (above the tolerance for stiff grids such as
-    # 32 x 512 on 1 x 8), where the two FFT implementations' rounding differs by a few
+    # own.  On stiff grids (32 x 512 on 1 x 8: kappa(G) ~ 1e4) both residuals stop at
+    # the rounding floor of an FFT-based apply, about eps * ||G|| ||u|| * log2(N),
+    # above tol ||b||; the library's floor is set by its own transforms (the twin has
+    # 4x the points and other rounding than the oracle's cosine / sine transforms),
+    # so the bound is 2x the larger of the oracle's residual and that floor
     r = np.linalg.norm(b - W.apply_G(eta, gh, _n(u), g))
     r_ref = np.linalg.norm(b - W.apply_G(eta, gh, u_ref, g))
-    assert r <= 5.0 * max(r_ref, 1e-12 * np.linalg.norm(b)), (r, r_ref)
+    Gu_abs = np.linalg.norm(W.apply_G(eta, gh, np.abs(u_ref), g))
+    floor = np.finfo(float).eps * Gu_abs * np.log2(4.0 * g.npts)
+    print(f"  err {err:.2e} residual {r:.3e} oracle {r_ref:.3e} floor {floor:.3e}", flush=True)
+    assert err <= 1e-10, err
+    assert r <= 2.0 * max(r_ref, 1e-12 * np.linalg.norm(b), floor), (r, r_ref, floor)
 
 
 @pytest.mark.parametrize("g", [GRIDS[1], GRIDS[3], GRIDS[6], GRIDS[8]], ids=[IDS[1], IDS[3], IDS[6], IDS[8]])
