@@ -156,6 +156,9 @@ def sbdf3r(r: float) -> Scheme:
     for k in range(1, 4):
         rhs[k] = k * sum(c[j] * (float(j) ** (k - 1) if (j or k - 1) else 1.0) for j in range(4))
     a = np.linalg.solve(M, rhs)
+    # consistency a(1) = 0 held exactly in floating point, in the order the update
+    # sums its terms, so that a constant level (and the mass, Remark 2.1) is kept
+    a[3] = -((a[0] + a[1]) + a[2])
     return Scheme(f"SBDF3(r={r:g})", tuple(a), tuple(b), tuple(c))
 
 

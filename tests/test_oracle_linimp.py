@@ -199,6 +199,24 @@ def test_sbdf3r_converges_at_third_order_on_the_exact_solitary_wave(member):
     assert all(2.8 < q < 3.3 for q in rates), (errs, rates)
 
 
+@pytest.mark.parametrize("r", [0.0, 0.6, 0.9])
+def test_sbdf3r_conserves_mass_to_rounding(r):
+    """Remark 2.1: the mass integral of zeta is conserved; the update keeps it to
+    rounding over many steps (its coefficients satisfy a(1) = 0 exactly)."""
+    g = I.grid1d(512, 80.0)
+    x = I.coords(g)
+    h = 1.0 - 0.4 * np.exp(-((x - 45.0) / 6.0) ** 2)
+    es, u = I.solitary_wave(g, 1.0, 0.3, 35.0)
+    eta = h + es - 1.0
+    pb = ost.Problem.from_h(g, h, tol=1e-12)
+    lo, hi = L.sbdf3r_interval(r)
+    _, _, kap = op.coefficients(eta, pb.grad_h, pb.flat)
+    th = 1.0 / math.sqrt(lo * hi * min(kap, 0.8 * hi / lo))
+    e, _, _ = L.run_linimp(pb, L.sbdf3r(r), eta, pb.G(eta, u), u, 0.05, 60, theta=th)
+    m0 = dg.mass(eta, h, g)
+    assert abs(dg.mass(e, h, g) - m0) <= 1e-12
+
+
 @pytest.mark.slow
 def test_plain_sbdf3_blows_up_over_the_shelf_while_the_joint_choice_does_not():
     c = I.config_c2()
