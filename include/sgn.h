@@ -232,6 +232,23 @@ sgn_status sgn_krylov_solve(sgn_ctx *ctx, const sgn_grid *grid, const double *d_
                             const sgn_coeffs *coeffs, const sgn_solve_opts *opts,
                             sgn_solve_info *info, void *d_ws);
 
+/* sgn_krylov_solve without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The call allocates nothing: its workspace
+ * is a static device array of 48 MiB (50331648 bytes) that the library holds on
+ * every device it runs on until the process ends (its device address is looked up
+ * once per device by sgn_create).  Arguments, results and errors are those of
+ * sgn_krylov_solve; in addition SGN_EINVAL if the workspace the call needs
+ * (sgn_workspace_bytes, or sgn_gmres_workspace_bytes for GMRES) exceeds 48 MiB:
+ * every 1D grid fits, and 2D grids up to 512 x 512.  Iteration chunks run
+ * eagerly (no graph capture).  All calls on one device share the array, which
+ * keeps the last call's contents (nothing in it needs to start at zero): calls
+ * that overlap in time on one device race and must not be issued. */
+sgn_status sgn_krylov_solve_noalloc(sgn_ctx *ctx, const sgn_grid *grid, const double *d_eta,
+                                    const double *d_grad_h, const double *d_rhs, double *d_u_inout,
+                                    const sgn_coeffs *coeffs, const sgn_solve_opts *opts,
+                                    sgn_solve_info *info);
+
 /* Bytes of workspace sgn_krylov_solve needs with method = SGN_GMRES and
  * restart length m (m + 1 basis vectors of the grid's half spectrum); 0 for an
  * unsupported grid or m outside [1, 256]. */

@@ -5,6 +5,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -71,7 +72,40 @@ struct sgn_ctx {
     int* hpub = nullptr;
     int* dpub = nullptr;
     int pub_seq = 0;
+    // device address of this device's copy of the allocation-free solve's scratch
+    void* scratch = nullptr;
 };
+
+// Workspace of sgn_krylov_solve_noalloc: a static device array, so that the call
+// allocates nothing.  Every device the library runs on holds its own copy of it
+// (at its own address) until the process ends.  In host code the array's name is
+// only a host-side stand-in: host code uses the address hipGetSymbolAddress
+// returns for the current device, looked up once per device at context creation.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)48 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of `scratch` on `device` (which must be current); null on failure.
+void* scratch_address(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -2679,7 +2713,14 @@ sgn_status sgn_create(sgn_ctx** out, int device, void* hip_stream) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         ctx->cus = cus;
-
+    // pinned staging of one batch item and result and of the GMRES(m <= 256)
+    // coefficients, allocated here so that a single solve (sgn_krylov_solve_noalloc
+    // included) allocates nothing
+    if (batch_staging(ctx, 8192) != SGN_OK) {
+        sgn_destroy(ctx);
+        return SGN_ENOMEM;
+    }
+    ctx->scratch = scratch_address(device);
     const char* bt = getenv("SGN_BATCH_THREADS");
     if (bt) ctx->batch_threads = atoi(bt);
     // HIP graphs for the PCG chunks are opt-in: their host-side launch costs more
@@ -2928,6 +2969,29 @@ sgn_status sgn_krylov_solve(sgn_ctx* ctx, const sgn_grid* grid, const double* et
         if (r != SGN_OK) return r;
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     }
+    return s;
+}
+
+sgn_status sgn_krylov_solve_noalloc(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const double* grad_h,
+                                    const double* rhs, double* u, const sgn_coeffs* coeffs,
+                                    const sgn_solve_opts* opts, sgn_solve_info* info) {
+    if (!ctx) return SGN_EINVAL;
+    if (!ctx->scratch) return fail(ctx, SGN_EDEVICE, "the no-alloc scratch has no device address");
+    Dims d;
+    sgn_status s = check_grid(ctx, grid, &d);
+    if (s != SGN_OK) return s;
+    const sgn_solve_opts o = opts ? *opts : default_opts();
+    const size_t need = o.method == SGN_GMRES ? sgn_gmres_workspace_bytes(grid, o.gmres_restart)
+                                              : sgn_workspace_bytes(grid, o.precision);
+    if (need == 0) return fail(ctx, SGN_EINVAL, "bad solver options for this grid");
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, SGN_EINVAL, "workspace of " + std::to_string(need) + " bytes exceeds the " +
+                                         std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte no-alloc scratch");
+    // graph capture allocates: the iteration chunks run eagerly here
+    const bool graphs = ctx->use_graphs;
+    ctx->use_graphs = false;
+    s = sgn_krylov_solve(ctx, grid, eta, grad_h, rhs, u, coeffs, opts, info, ctx->scratch);
+    ctx->use_graphs = graphs;
     return s;
 }
 

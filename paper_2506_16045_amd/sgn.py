@@ -113,6 +113,8 @@ _SIGS = {
     "sgn_precond_solve": (_S, [_P, ctypes.POINTER(Grid), ctypes.POINTER(Coeffs), _P, _P, _P]),
     "sgn_krylov_solve": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, ctypes.POINTER(Coeffs),
                               ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
+    "sgn_krylov_solve_noalloc": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, ctypes.POINTER(Coeffs),
+                                      ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
     "sgn_rhs": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P]),
     "sgn_dealias_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid)]),
     "sgn_rhs_dealiased": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P]),
@@ -357,6 +359,28 @@ class Context:
                                    _ptr(grad_h, _vector_shape(g), "grad_h"), _ptr(rhs, _vector_shape(g), "rhs"),
                                    _ptr(u, _vector_shape(g), "u"), ctypes.byref(coeffs) if coeffs else None,
                                    ctypes.byref(o), ctypes.byref(info), _P(ws.data_ptr()))
+        res = SolveResult(info.iters, info.outer_iters, bool(info.converged), info.relres, info.coeffs.sigma,
+                          info.coeffs.alpha, info.coeffs.kappa_ub, bool(info.coeffs.flat))
+        if st == ENOCONV and not raise_on_noconv:
+            return u, res
+        self._check(st)
+        return u, res
+
+    def krylov_solve_noalloc(self, g, eta, grad_h, rhs, u=None, coeffs: Coeffs | None = None,
+                             opts: SolveOpts | None = None, raise_on_noconv: bool = True):
+        """Solve G u = rhs with the library's static scratch as workspace
+        (sgn_krylov_solve_noalloc).  Returns (u, SolveResult)."""
+        self._sync_stream()
+        grid = make_grid(g)
+        o = opts if opts is not None else solve_opts()
+        if u is None:
+            u = torch.zeros(_vector_shape(g), dtype=torch.float64, device=self.device)
+        info = SolveInfo()
+        st = _lib.sgn_krylov_solve_noalloc(self._h, ctypes.byref(grid), _ptr(eta, _scalar_shape(g), "eta"),
+                                           _ptr(grad_h, _vector_shape(g), "grad_h"),
+                                           _ptr(rhs, _vector_shape(g), "rhs"), _ptr(u, _vector_shape(g), "u"),
+                                           ctypes.byref(coeffs) if coeffs else None, ctypes.byref(o),
+                                           ctypes.byref(info))
         res = SolveResult(info.iters, info.outer_iters, bool(info.converged), info.relres, info.coeffs.sigma,
                           info.coeffs.alpha, info.coeffs.kappa_ub, bool(info.coeffs.flat))
         if st == ENOCONV and not raise_on_noconv:
