@@ -2637,6 +2637,9 @@ LinimpScheme scheme_sbdf3r(double r) {
         }
     }
     for (int j = 0; j < 4; ++j) q.a[j] = M[j][4] / M[j][j];
+    // a(1) = 0 exactly in floating point, in the order k_lincomb sums the terms, so
+    // that the update keeps a constant level (and the mass) to rounding
+    q.a[3] = -((q.a[0] + q.a[1]) + q.a[2]);
     return q;
 }
 
