@@ -27,6 +27,17 @@ independent 1D constraint solves G u = b with sizes drawn from
 b = G u* formed on the device, all solved in one launch per step (a step is
 one batched solve of the whole ensemble from a zero guess, to 1e-10).
 
+--workload c1 runs the 1D flat-bottom solitary wave (N = 256 on L = 80, a = 0.2
+at x = 20, RK4 dt = 0.01, PCG tol 1e-12) for its stated 500 steps (--steps
+overrides), FP64; the oracle runs the same 500 steps on the host and both are
+compared with each other and with the exact travelling wave.
+
+--workload c2 runs the 1D shelf (N = 4096 on L = 400, a = 0.3 at x = 100,
+dt = 0.02, tol 1e-12) for its stated 2000 steps per leg: the linearly implicit
+SBDF2 (one constant-coefficient FFT solve per step), AB3+PCG and RK4+PCG, each
+in FP64 and mixed precision; the oracle runs the first 200 steps of each leg,
+against a device run of the same length.
+
 --workload serve measures the request server: Poisson arrivals at each rate
 of --rates (requests per second), --serve-requests requests per rate, 70% 1D
 (N 1024..16384) and 30% 2D (128^2..1024^2) grids, half single constraint
@@ -72,6 +83,16 @@ def kernel_bytes(kind: str, d: int, nx: int, ny: int, word: int) -> float:
         return ((d + 1) + 3 * d + 2 * d) * ns * cw
     if base == "pcg_init":    # read r hat (d)
         return d * ns * cw
+    # 2D right-hand side (word = 8): the passes of one evaluation of f(w, p)
+    nd2 = 3 if d == 2 else 1
+    if base == "rhs_rows_fwd":  # read eta, u (d), grad h (d); write [u, eta u, eta, eta u u (nd2), beta] spectra
+        return (1 + 2 * d) * n * word + ((2 * d + 1) + (nd2 + 1)) * ns * cw
+    if base == "rhs_cols":      # read u, eta u, eta, beta spectra; write delta, grad delta, m, grad eta, grad beta
+        return ((2 * d + 1) + 1) * ns * cw + ((2 * d + 2) + d) * ns * cw
+    if base == "rhs_rows_inv":  # read those 3d + 2 spectra and eta, u, grad h; write eta_t, U_t and S's spectrum
+        return (3 * d + 2) * ns * cw + (1 + 2 * d) * n * word + (1 + d) * n * word + ns * cw
+    if base == "rhs_flux":      # read S and the nd2 flux spectra; write grad S - div(flux) (d)
+        return (1 + nd2) * ns * cw + d * ns * cw
     raise ValueError(kind)
 
 
@@ -410,6 +431,7 @@ def bench_batch(args):
         "batch_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)},
         "checks": {"max_rel_err_vs_exact": max(err), "all_converged": all(r.converged for r in res)},
         "roofline": roofline,
+        "rooflines": rooflines,
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
     }
@@ -541,6 +563,167 @@ def bench_serve(args):
     return 0
 
 
+def _state_1d(ctx, cfg, to):
+    from paper_2506_16045_amd import sgn
+    g = cfg["grid"]
+    h = to(cfg["h"])
+    gh, flat = ctx.bathy_prepare(g, h)
+    eta, u = to(cfg["eta"]), to(cfg["u"])
+    U = ctx.apply_constraint(g, eta, gh, u)
+    return sgn.State(ctx, g, h, gh, flat, eta, U, u)
+
+
+def _leg_step(st, leg, dt, n, opts):
+    if leg == "rk4":
+        return st.step_rk4(dt, n, opts)
+    if leg == "ab3":
+        return st.step_ab(3, dt, n, opts)
+    return st.step_linimp(dt, n, None, opts)
+
+
+def _oracle_leg(cfg, leg, steps):
+    from oracle import stepping as ost
+    pb = ost.Problem.from_h(cfg["grid"], cfg["h"], tol=cfg["tol"])
+    U0 = pb.G(cfg["eta"], cfg["u"])
+    t0 = time.perf_counter()
+    if leg == "rk4":
+        out = ost.run_rk4(pb, cfg["eta"], U0, cfg["u"], cfg["dt"], steps)
+    elif leg == "ab3":
+        out = ost.run_ab(pb, 3, cfg["eta"], U0, cfg["u"], cfg["dt"], steps)
+    else:
+        out = ost.run_sbdf2(pb, cfg["eta"], U0, cfg["u"], cfg["dt"], steps)
+    return out, time.perf_counter() - t0, pb.iters
+
+
+def _rel_fields(dev, ref, h):
+    import numpy as np
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return {"zeta": rel(dev[0] - h, ref[0] - h), "U": rel(dev[1], ref[1]), "u": rel(dev[2], ref[2])}
+
+
+def bench_c1(args):
+    """1D flat solitary wave, RK4, the stated 500 steps (section 6, ExSleta/ExSlu)."""
+    import numpy as np
+    import torch
+    from paper_2506_16045_amd import inputs as I
+    from paper_2506_16045_amd import sgn
+    dev = torch.device("cuda", 0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    cfg = I.config_c1()
+    g = cfg["grid"]
+    steps = args.steps if args.steps is not None else cfg["steps"]
+    ctx = sgn.Context(0)
+    opts = sgn.solve_opts(tol=cfg["tol"], check_every=args.check_every)
+    for _ in range(max(args.warmup, 0)):
+        st = _state_1d(ctx, cfg, to)
+        st.step_rk4(cfg["dt"], steps, opts)
+        st.close()
+    st = _state_1d(ctx, cfg, to)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = st.step_rk4(cfg["dt"], steps, opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if not info.converged:
+        raise RuntimeError("a Krylov solve did not converge")
+    fields = tuple(t.detach().cpu().numpy() for t in (st.eta, st.U, st.u))
+    st.close()
+    T = cfg["dt"] * steps
+    e_x, u_x = I.solitary_wave(g, cfg["h0"], cfg["a"], cfg["x0"], t=T)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    cpu = None
+    if not args.no_cpu_baseline:
+        ref, sec, iters = _oracle_leg(cfg, "rk4", steps)
+        cpu = {"value": g.npts * steps / sec, "unit": "grid-pt-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole run, {steps} RK4 steps ({sec:.1f} s, FP64 NumPy, single thread; "
+                         f"iterations/solve {np.mean(iters):.2f})",
+               "device_vs_oracle_rel_l2": _rel_fields(fields, ref, cfg["h"])}
+    out = {"metric": "1D SGN grid-pt-steps/s at 1e-10 rel err; Krylov iters/solve",
+           "value": g.npts * steps / el, "unit": "grid-pt-steps/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "1D flat solitary wave: N=256 on L=80, h0=1, a=0.2 at x=20, RK4 dt=0.01, "
+                                  f"{steps} steps, PCG tol 1e-12", "scheme": "rk4"},
+           "krylov_iters_per_solve": info.iters / max(info.solves, 1), "solves": info.solves,
+           "vs_exact_solitary_wave": {"zeta": rel(fields[0] - 1.0, e_x - 1.0), "u": rel(fields[2], u_x),
+                                      "t": T},
+           "cpu_baseline": cpu, "device": torch.cuda.get_device_name(0)}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+def bench_c2(args):
+    """1D shelf: SBDF2 (Eq:MM), AB3+PCG (Eq:AB), RK4+PCG (Eq:ERK), FP64 and mixed,
+    the stated 2000 steps per leg."""
+    import numpy as np
+    import torch
+    from paper_2506_16045_amd import inputs as I
+    from paper_2506_16045_amd import sgn
+    dev = torch.device("cuda", 0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    cfg = I.config_c2()
+    g = cfg["grid"]
+    steps = args.steps if args.steps is not None else cfg["steps"]
+    ctx = sgn.Context(0)
+    legs = {}
+    for leg in ("sbdf2", "ab3", "rk4"):
+        for precision in ("fp64", "mixed"):
+            prec = sgn.FP64 if precision == "fp64" else sgn.MIXED
+            opts = sgn.solve_opts(tol=cfg["tol"], precision=prec, check_every=args.check_every,
+                                  inner_tol=args.inner_tol)
+            if args.warmup > 0:
+                st = _state_1d(ctx, cfg, to)
+                _leg_step(st, leg, cfg["dt"], min(args.warmup, steps), opts)
+                st.close()
+            st = _state_1d(ctx, cfg, to)
+            m0 = float(torch.sum(st.eta - st._keep[0]).item())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = _leg_step(st, leg, cfg["dt"], steps, opts)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            m1 = float(torch.sum(st.eta - st._keep[0]).item())
+            st.close()
+            legs[f"{leg}-{precision}"] = {"value": g.npts * steps / el, "ms_per_step": 1e3 * el / steps,
+                                          "solves": info.solves,
+                                          "krylov_iters_per_solve": info.iters / max(info.solves, 1),
+                                          "mass_rel_drift": abs(m1 - m0) / abs(m0)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        sample = min(200, steps)
+        cpu = {"unit": "grid-pt-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {sample} steps of each leg (FP64 NumPy, single thread), against a device "
+                         f"run of the same length", "legs": {}}
+        tot_sec = 0.0
+        for leg in ("sbdf2", "ab3", "rk4"):
+            ref, sec, _ = _oracle_leg(cfg, leg, sample)
+            tot_sec += sec
+            rec = {"value": g.npts * sample / sec}
+            for precision in ("fp64", "mixed"):
+                prec = sgn.FP64 if precision == "fp64" else sgn.MIXED
+                st = _state_1d(ctx, cfg, to)
+                _leg_step(st, leg, cfg["dt"], sample, sgn.solve_opts(tol=cfg["tol"], precision=prec,
+                                                                     inner_tol=args.inner_tol))
+                fields = tuple(t.detach().cpu().numpy() for t in (st.eta, st.U, st.u))
+                st.close()
+                rec[f"device_{precision}_vs_oracle_rel_l2"] = _rel_fields(fields, ref, cfg["h"])
+            cpu["legs"][leg] = rec
+        cpu["value"] = g.npts * 3 * sample / tot_sec
+    main = legs["sbdf2-fp64"]
+    out = {"metric": "1D SGN grid-pt-steps/s at 1e-10 rel err; Krylov iters/solve",
+           "value": main["value"], "unit": "grid-pt-steps/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": main["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "1D shelf: N=4096 on L=400, depth 1 -> 0.5 (tanh steps), solitary wave a=0.3 "
+                                  f"at x=100, dt=0.02, {steps} steps per leg, PCG tol 1e-12; value: the linearly "
+                                  "implicit SBDF2 leg in FP64", "scheme": "sbdf2 | ab3 | rk4"},
+           "legs": legs, "cpu_baseline": cpu, "device": torch.cuda.get_device_name(0)}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
 def cpu_baseline_batch(systems, tol, count):
     """The oracle's PCG, as it stands, on the first `count` systems of the ensemble
     (forming b = G u* is not timed)."""
@@ -566,14 +749,16 @@ def cpu_baseline_batch(systems, tol, count):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["rk4-2d", "batch", "serve", "coeffs", "walls"], default="rk4-2d")
+    ap.add_argument("--workload", choices=["rk4-2d", "c1", "c2", "batch", "serve", "coeffs", "walls"],
+                    default="rk4-2d")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="arrival rates of the serve workload")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per rate (serve workload)")
     ap.add_argument("--lanes", type=int, default=3, help="worker lanes of the server (serve workload)")
     ap.add_argument("--precision-serve", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--count", type=int, default=512, help="systems of the batched workload")
     ap.add_argument("--cpu-sample", type=int, default=512, help="systems the CPU oracle solves for its baseline")
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 40; the stated run length for c1 and c2)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="fp64")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision")
@@ -611,7 +796,7 @@ def main(argv=None):
             text = json.dumps(rec, indent=1) + "\n"
         else:
             rec = profiling.traffic(args.summarize_traffic[0], args.summarize_traffic[1],
-                                    args.calib_copy_mib * (1 << 20))
+                                    args.calib_copy_mib * (1 << 20), args.n)
             rec.update({"n": args.n, "kernel_source_sha": kernel_source_hash(), "command": args.command})
             text = json.dumps(rec, indent=1) + "\n"
         if args.out:
@@ -625,6 +810,12 @@ def main(argv=None):
               "(how it would shard across GPUs is described in the design notes; it is not run)", file=sys.stderr)
         return 2
 
+    if args.workload == "c1":
+        return bench_c1(args)
+    if args.workload == "c2":
+        return bench_c2(args)
+    if args.steps is None:
+        args.steps = 40
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "serve":
@@ -723,22 +914,32 @@ def main(argv=None):
     kstats = {}
     kinds = ("pcg_c1_f32", "pcg_r1_f32", "pcg_c2_f32", "pcg_init_f32") if prec == sgn.MIXED else \
         ("pcg_c1", "pcg_r1", "pcg_c2", "pcg_init")
-    for kind in kinds:
+    rhs_kinds = ("rhs_rows_fwd", "rhs_cols", "rhs_rows_inv", "rhs_flux") if not args.dealias else ()
+    for kind in kinds + rhs_kinds:
         n_launch, ms = prof[kind]
         if n_launch:
             kstats[kind] = {"launches": n_launch, "avg_us": 1e3 * ms / n_launch, "total_ms": ms}
-    # the roofline is quoted for the dominant family of the working precision
-    # (FP32 inner passes in mixed mode; the FP64 residual passes are separate families)
+    # every timed family against the HBM roofline (algorithmic bytes per launch over its
+    # event-timed average); `roofline` is the family with the largest total time
+    # (FP32 inner passes in mixed mode; the FP64 residual passes are separate families;
+    # the right-hand side is FP64 in both precisions)
+    rooflines = {}
+    for kind, st_ in kstats.items():
+        if kind.startswith("pcg_init"):
+            continue
+        w_k = 8 if kind.startswith("rhs_") else word
+        nbytes = kernel_bytes(kind, g.d, g.nx, g.ny, w_k)
+        achieved = nbytes / (st_["avg_us"] * 1e-6) / 1e9
+        rooflines[kind] = {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": measured_traffic(kind, args.n), "bytes_per_launch": nbytes,
+                           "avg_launch_us": round(st_["avg_us"], 2), "total_ms": round(st_["total_ms"], 4)}
     roofline = None
-    if kstats:
-        dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
-        nbytes = kernel_bytes(dom, g.d, g.nx, g.ny, word)
-        achieved = nbytes / (kstats[dom]["avg_us"] * 1e-6) / 1e9
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(dom, args.n),
-                    "bytes_per_launch": nbytes, "avg_launch_us": round(kstats[dom]["avg_us"], 2),
-                    "timing": f"HIP events around every launch over {args.timing_steps} further steps"}
+    if rooflines:
+        dom = max(rooflines, key=lambda k: rooflines[k]["total_ms"])
+        roofline = dict(rooflines[dom])
+        roofline["timing"] = f"HIP events around every launch over {args.timing_steps} further steps"
+        del roofline["total_ms"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -782,6 +983,7 @@ def main(argv=None):
         "kernel_families_ms_per_step": {k: round(v[1] / max(args.timing_steps, 1), 4)
                                          for k, v in prof.items() if v[0]},
         "roofline": roofline,
+        "rooflines": rooflines,
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
     }

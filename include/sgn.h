@@ -175,7 +175,11 @@ typedef enum sgn_kernel_kind {
     SGN_KERNEL_PCG_C2_F32 = 8,
     SGN_KERNEL_PCG_INIT_F32 = 9,
     SGN_KERNEL_BATCH = 10,   /* batched 1D solves (one launch per call) */
-    SGN_KERNEL_KINDS = 11
+    SGN_KERNEL_RHS_ROWS_FWD = 11,  /* 2D right-hand side: products and their row transforms */
+    SGN_KERNEL_RHS_COLS = 12,      /* 2D right-hand side: derivative column operators */
+    SGN_KERNEL_RHS_ROWS_INV = 13,  /* 2D right-hand side: inverse row transforms, pointwise eta_t, U_t, S */
+    SGN_KERNEL_RHS_FLUX = 14,      /* 2D right-hand side: grad S - div(eta u (x) u) column operators */
+    SGN_KERNEL_KINDS = 15
 } sgn_kernel_kind;
 sgn_status sgn_profile_begin(sgn_ctx *ctx);
 sgn_status sgn_profile_end(sgn_ctx *ctx, int64_t *launches, double *total_ms, int32_t nkinds);

@@ -302,6 +302,70 @@ __device__ __forceinline__ void row_inverse(const RowGeom& g, const RowThread<T>
     __syncthreads();
 }
 
+// row_inverse with every transposed load of the block issued before the first
+// LDS store: each thread keeps its mirrored pairs (k, M - k) of all NF fields in
+// registers (EPC/2 + 1 pairs per field), so the loads of all fields are in
+// flight together.  For the short rows of the Krylov row pass, whose launch
+// leaves few waves per CU to hide the latency of the transposed accesses.
+template <typename T, int EPC, int NF>
+__device__ __forceinline__ void row_inverse_batched(const RowGeom& g, const RowThread<T>& rt,
+                                                    const cpx<T>* const (&H)[NF],
+                                                    const cpx<T>* __restrict__ tw_all, const cpx<T>* twm,
+                                                    cpx<T> (&z)[NF][EPC]) {
+    const int M = g.M, R = g.R, ny = g.ny;
+    // R (M/2 + 1) pairs over R M / EPC threads: EPC/2 pairs each, R more for the first threads
+    constexpr int Q = EPC / 2 + 1;
+    const int totalp = R * (M / 2 + 1);
+    const cpx<T>* tw2 = tw_size(tw_all, 2 * M);
+    cpx<T> Xk[Q][NF], Xm[Q][NF];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = threadIdx.x + q * blockDim.x;
+        const int y = rt.row0 + (i & (R - 1));
+        const int p = i / R;
+        const bool ok = i < totalp && y < ny;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            Xk[q][f] = ok ? H[f][(size_t)p * ny + y] : C<T>(0, 0);
+            Xm[q][f] = ok ? H[f][(size_t)(M - p) * ny + y] : C<T>(0, 0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = threadIdx.x + q * blockDim.x;
+        if (i >= totalp) continue;
+        const int r = i & (R - 1);
+        const int k = i / R, m = M - k;
+        cpx<T> wk = tw2[k], wm = tw2[m];
+        wk.im = -wk.im;
+        wm.im = -wm.im;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cpx<T>* b = rt.lds + f * rt.fstride + r * (M + 1);
+            const cpx<T> xk = Xk[q][f], xm = Xm[q][f];
+            if (k == 0) {
+                b[0] = C<T>(xk.re + xm.re, xk.re - xm.re);
+            } else {
+                const cpx<T> Zk = (xk + cj(xm)) + mul_i((xk - cj(xm)) * wk);
+                if (m != k) b[m] = (xm + cj(xk)) + mul_i((xm - cj(xk)) * wm);
+                b[k] = Zk;
+            }
+        }
+    }
+    __syncthreads();
+    cpx<T>* rowb = rt.lds + rt.r * (M + 1);
+    lds_fft<T, EPC, NF>(rowb, rt.fstride, M, rt.t, g.TPR, twm, true);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const int j = rt.t + g.TPR * e;
+            if (j < M) z[f][e] = rowb[f * rt.fstride + j];
+        }
+    }
+    __syncthreads();
+}
+
 // Forward row transforms of NF fields: real pairs z[f][e] -> H_f[kx][y] for
 // kx = 0..M, each value multiplied by `scale`.  The recombination
 // X_k = (Z_k + Z*_{M-k})/2 - i W_nx^k (Z_k - Z*_{M-k})/2 is formed as each entry

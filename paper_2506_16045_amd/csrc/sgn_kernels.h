@@ -856,7 +856,10 @@ __global__ void __launch_bounds__(MAXT) k_pcg_r1(RowGeom g, const cpx<T>* __rest
         const cpx<T>* Hs[D + 1];
 #pragma unroll
         for (int c = 0; c <= D; ++c) Hs[c] = H + c * NS;
-        row_inverse<T, EPC, D + 1>(g, rt, Hs, tw, twm, v);
+        if (EPC <= 2)
+            row_inverse_batched<T, EPC, D + 1>(g, rt, Hs, tw, twm, v);
+        else
+            row_inverse<T, EPC, D + 1>(g, rt, Hs, tw, twm, v);
     }
     const size_t npts = (size_t)g.nx * g.ny;
     const T third = (T)1 / (T)3, half = (T)0.5;

@@ -474,8 +474,9 @@ struct LinJobSpec {
     std::vector<cpx<double>*> dst;
     std::vector<std::vector<int>> codes;
 };
-sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSpec>& spec, double scale) {
-    ProfScope ps(ctx, SGN_KERNEL_COLS);
+sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSpec>& spec, double scale,
+                         int kind = SGN_KERNEL_COLS) {
+    ProfScope ps(ctx, kind);
     if (spec.empty() || spec.size() > (size_t)LINJ_MAXJ) return fail(ctx, SGN_EINVAL, "cols_lin_jobs: job count");
     LinJobs<double> J{};
     J.n = (int)spec.size();
@@ -1740,7 +1741,7 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     const RowLaunch RL = row_launch<double>(d.nx, d.ny);
     const size_t rlds = row_lds_bytes<double>(RL.g, 1);
     {
-        ProfScope ps(ctx, SGN_KERNEL_ROWS);
+        ProfScope ps(ctx, D == 2 ? SGN_KERNEL_RHS_ROWS_FWD : SGN_KERNEL_ROWS);
         PtrList<cpx<double>, MAXF> t{};
         t.n = 0;
         for (auto p : dA) t.p[t.n++] = p;
@@ -1783,7 +1784,7 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
             {{cA[2], cA[3], cA[4]}, {oA[3], oA[4], oA[5]}, {{2, 3, 0}, {0, 0, 2}, {0, 0, 3}}},
             {{cB[3]}, {oB[0], oB[1]}, {{2}, {3}}},
         };
-        if ((s = cols_lin_jobs(ctx, d, jobs, d.inv_n)) != SGN_OK) return s;
+        if ((s = cols_lin_jobs(ctx, d, jobs, d.inv_n, SGN_KERNEL_RHS_COLS)) != SGN_OK) return s;
     } else {
         if ((s = cols_lin<double>(ctx, d, cA, oA, {{2, 0, 0}, {4, 0, 0}, {0, 2, 0}, {0, 0, 2}}, d.inv_n)) != SGN_OK)
             return s;
@@ -1793,7 +1794,7 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     // pointwise into eta_t, U_t (without grad S - div(eta u (x) u)) and S, whose row
     // transform goes to HA (slot 0)
     {
-        ProfScope ps(ctx, SGN_KERNEL_ROWS);
+        ProfScope ps(ctx, D == 2 ? SGN_KERNEL_RHS_ROWS_INV : SGN_KERNEL_ROWS);
         PtrList<const cpx<double>, MAXF> q{};
         q.n = 0;
         // OA = [delta, d delta (D), m, d eta (D)], OB = [d beta (D)]
@@ -1825,7 +1826,7 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
         // transformed by both; the shorter chain per block wins over the saved work)
         std::vector<LinJobSpec> fj = {{{HA, cB[0], cB[1]}, {gS[0]}, {{2, 2, 3}}},
                                       {{HA, cB[1], cB[2]}, {gS[1]}, {{3, 2, 3}}}};
-        if ((s = cols_lin_jobs(ctx, d, fj, d.inv_n)) != SGN_OK) return s;
+        if ((s = cols_lin_jobs(ctx, d, fj, d.inv_n, SGN_KERNEL_RHS_FLUX)) != SGN_OK) return s;
     } else {
         if ((s = cols_lin<double>(ctx, d, {HA, cB[0]}, gS, {{2, 2}}, d.inv_n)) != SGN_OK) return s;
     }

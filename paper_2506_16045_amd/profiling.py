@@ -26,8 +26,18 @@ def demangle(names):
     return {n: n for n in names}
 
 
-def kernel_family(demangled: str):
-    """(family, precision) of a PCG kernel name, e.g. ('pcg_r1', 'f32'), else None."""
+def kernel_family(demangled: str, grid_size: int = 0, n: int = 0):
+    """(family, precision) of a PCG loop or 2D right-hand-side kernel name, e.g.
+    ('pcg_r1', 'f32') or ('rhs_rows_inv', 'f64'), else None.  The right-hand side's
+    two column launches share one kernel; they are told apart by their job count
+    (grid_size work-items over 256-thread blocks of n/2 + 1 columns per job)."""
+    if re.search(r"k_rhs_rows_fwd<2,", demangled):
+        return "rhs_rows_fwd", "f64"
+    if re.search(r"k_rhs_rows_inv<2,", demangled):
+        return "rhs_rows_inv", "f64"
+    if re.search(r"k_cols_lin_jobs<double, 4, [34], 3>", demangled) and n:
+        jobs = round(grid_size / (256 * (n // 2 + 1)))
+        return ("rhs_cols", "f64") if jobs == 3 else ("rhs_flux", "f64") if jobs == 2 else None
     m = re.search(r"k_pcg_(c1|r1|c2|init)<(double|float)(?:, (\d+))?(?:, (\d+))?(?:, (\d+|true|false))?", demangled)
     if not m:
         return None
@@ -76,9 +86,10 @@ def counter_means(db_path: str, counter: str):
     return rows
 
 
-def traffic(fetch_db: str, write_db: str, calib_bytes: int):
-    """HBM bytes per launch of each PCG loop family and precision, from FETCH_SIZE
-    and WRITE_SIZE (KiB per dispatch) scaled so that the reference copy of
+def traffic(fetch_db: str, write_db: str, calib_bytes: int, n: int = 0):
+    """HBM bytes per launch of each PCG loop family and precision (and of the 2D
+    right-hand-side passes when n, the grid side, is given), from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) scaled so that the reference copy of
     calib_bytes reads and writes exactly calib_bytes."""
     fr = counter_means(fetch_db, "FETCH_SIZE")
     wr = counter_means(write_db, "WRITE_SIZE")
@@ -94,12 +105,12 @@ def traffic(fetch_db: str, write_db: str, calib_bytes: int):
     scale_f = kib / f_ref
     dem = demangle({n for n, _, _ in fr} | {n for n, _, _ in wr})
     acc = collections.defaultdict(lambda: {"fetch": [], "write": []})
-    for n, v, g in fr:
-        fam = kernel_family(dem[n])
+    for nm, v, g in fr:
+        fam = kernel_family(dem[nm], g, n)
         if fam:
             acc[fam]["fetch"].append(v)
-    for n, v, g in wr:
-        fam = kernel_family(dem[n])
+    for nm, v, g in wr:
+        fam = kernel_family(dem[nm], g, n)
         if fam:
             acc[fam]["write"].append(v)
     out = {"scale_fetch": scale_f, "scale_write": scale_w, "reference_copy_bytes": calib_bytes,
