@@ -431,7 +431,6 @@ def bench_batch(args):
         "batch_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)},
         "checks": {"max_rel_err_vs_exact": max(err), "all_converged": all(r.converged for r in res)},
         "roofline": roofline,
-        "rooflines": rooflines,
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
     }

@@ -179,7 +179,8 @@ typedef enum sgn_kernel_kind {
     SGN_KERNEL_RHS_COLS = 12,      /* 2D right-hand side: derivative column operators */
     SGN_KERNEL_RHS_ROWS_INV = 13,  /* 2D right-hand side: inverse row transforms, pointwise eta_t, U_t, S */
     SGN_KERNEL_RHS_FLUX = 14,      /* 2D right-hand side: grad S - div(eta u (x) u) column operators */
-    SGN_KERNEL_KINDS = 15
+    SGN_KERNEL_BATCH_STEP = 15,    /* whole 1D RK4 runs, one workgroup per state (one launch per call) */
+    SGN_KERNEL_KINDS = 16
 } sgn_kernel_kind;
 sgn_status sgn_profile_begin(sgn_ctx *ctx);
 sgn_status sgn_profile_end(sgn_ctx *ctx, int64_t *launches, double *total_ms, int32_t nkinds);
@@ -287,6 +288,45 @@ sgn_status sgn_batch_solve(sgn_ctx *ctx, int32_t nitems, const int32_t *h_n, con
                            const double *d_eta, const double *d_grad_h, const double *d_rhs,
                            double *d_u_inout, const sgn_solve_opts *opts, sgn_solve_info *h_info,
                            void *d_ws);
+
+/* Bytes of device workspace sgn_batch_step_rk4 needs for nitems states of
+ * sizes h_n[i] (host array) in the given precision (each state's h_x, U, stage
+ * values, right-hand sides, guess offsets and solve scratch, about 40 h_n[i]
+ * doubles); 0 if a size is unsupported. */
+size_t sgn_batch_step_workspace_bytes(int32_t nitems, const int32_t *h_n, int32_t precision);
+
+/* Advance nitems independent periodic 1D states by RK4 (Eq:ERK, with the
+ * constraint solve of section 3.2 for the velocity of every stage and of the
+ * new level), all in one kernel launch: each workgroup takes whole runs,
+ * largest first, and carries its state through all of its steps.  State i
+ * starts from (eta_i, u_i) over bathymetry h_i: h_x = D h (zero, and the flat
+ * coefficient formulas, iff h_i is constant) and U = G_{eta,h} u are formed
+ * first, and every solve starts from the guess opts->guess selects, its history
+ * starting empty.  The steps are those of sgn_step_rk4 (which runs a 1D state of
+ * up to 8192 points through the same kernel), and a state's result is the same,
+ * bit for bit, whatever else shares the launch.
+ *   h_n[i]      points of state i: a power of two in [2, 8192] (host array)
+ *   h_L[i], h_dt[i], h_nsteps[i] (>= 0): its period, step and step count (host)
+ *   d_h         bathymetry, device, packed in state order (state i at offset
+ *               sum_{j<i} h_n[j]), read only
+ *   d_eta, d_u  total depth and velocity, device, packed the same way: the
+ *               initial state on entry, the state after the run on return
+ *   h_info      nitems results (host array, may be NULL): solves, iterations,
+ *               t = the simulated time advanced, steps_done = steps taken
+ *   h_status    nitems statuses (host array, may be NULL): SGN_OK, SGN_EDOMAIN
+ *               (non-positive depth or non-finite data; the run stops there)
+ *               or SGN_ENOCONV (a solve missed tol; the run stops after it)
+ *   d_ws        sgn_batch_step_workspace_bytes(...) bytes, 256-byte aligned
+ * Synchronises the stream.  Every run proceeds even if another fails; a run
+ * that stops leaves the state it reached (a failed last solve counts its step,
+ * as sgn_step_rk4 does).  Returns SGN_EDOMAIN if a run met bad data, else
+ * SGN_ENOCONV if a solve missed tol, else SGN_OK.  opts = NULL: FP64, tol
+ * 1e-12, extrapolated guesses; method must be SGN_PCG, precision SGN_FP64 or
+ * SGN_MIXED. */
+sgn_status sgn_batch_step_rk4(sgn_ctx *ctx, int32_t nitems, const int32_t *h_n, const double *h_L,
+                              const double *h_dt, const int32_t *h_nsteps, const double *d_h,
+                              double *d_eta, double *d_u, const sgn_solve_opts *opts,
+                              sgn_step_info *h_info, sgn_status *h_status, void *d_ws);
 
 /* Right-hand side of the constraint form (Eq:DSWEcf, Def:bigF, Eq:DAE_DSWE):
  * eta_t = -div(eta u), U_t = -eta grad(zeta) - div(eta u (x) u) + F with
@@ -403,18 +443,21 @@ sgn_status sgn_state_set_dealias(sgn_ctx *ctx, sgn_state *state, void *d_dws);
  * beside the admitted ones; admitted requests keep their fields and Krylov
  * state on the device until they complete, then release their memory.
  * Continuous batching: admitted 1D solves with nx <= 8192 are gathered into
- * one sgn_batch_solve launch whenever the batching lane is free, so requests
- * that arrive while a batch runs join the next launch; every other request
- * runs on one of the worker lanes (each its own context and HIP stream), so
- * batches, solves and steps overlap on the device.  A request's result does
- * not depend on what it was batched or overlapped with (the kernels reduce in
- * a fixed order). */
+ * one sgn_batch_solve launch whenever their batching lane is free, and admitted
+ * 1D RK4 requests with nx <= 8192 into one sgn_batch_step_rk4 launch on a
+ * second batching lane, so requests that arrive while a batch runs join the
+ * next launch (a group shares its options; dt and nsteps may differ); every
+ * other request runs on one of the worker lanes (each its own context and HIP
+ * stream), so batches, solves and steps overlap on the device.  A request's
+ * result does not depend on what it was batched or overlapped with (one
+ * workgroup carries each batched request, and the kernels reduce in a fixed
+ * order). */
 typedef struct sgn_server sgn_server;
 
 typedef struct sgn_server_opts {
     size_t hbm_budget;      /* bytes; 0 = 80% of the device memory free at creation */
     int32_t lanes;          /* worker lanes (>= 1; 0 = 3) */
-    int32_t max_batch;      /* most 1D solves per batched launch (0 = 1024) */
+    int32_t max_batch;      /* most requests per batched launch (0 = 1024) */
 } sgn_server_opts;
 
 typedef enum sgn_request_kind {
@@ -456,7 +499,7 @@ void sgn_server_destroy(sgn_server *server);
 /* Device bytes charged to a request while admitted (0 if the request is
  * invalid): the pooled block a worker-lane request occupies (its fields, Krylov
  * workspace and stepping state, rounded up to the pool's power-of-two size class),
- * or the fields and one-system workspace of a batched 1D solve. */
+ * or the fields and one-system workspace of a batched 1D solve or RK4 run. */
 size_t sgn_request_footprint(const sgn_request *req);
 /* Queue a request; *id identifies it.  SGN_EINVAL for an invalid request,
  * SGN_ENOMEM if its footprint exceeds the whole budget. */

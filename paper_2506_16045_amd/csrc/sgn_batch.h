@@ -445,6 +445,158 @@ __device__ __forceinline__ void blk_to_spectral(const double* x, int N, cpx<doub
     __syncthreads();
 }
 
+// Next system of a block.  queue = null: a static stride over the table.
+// Otherwise a work queue: the first round takes the block's own index, later
+// systems come from a global counter (zero at launch) in table order, so a block
+// that finishes early takes the next largest system.  Every thread of the block
+// calls it; the result is the same in all of them.
+__device__ __forceinline__ int batch_next(int* queue, int cur, int* slot) {
+    if (!queue) return cur + gridDim.x;
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = (int)gridDim.x + atomicAdd(queue, 1);
+    __syncthreads();
+    return *slot;
+}
+
+// One system's solve G u = b (section 3.2, Def:G in 1D) by the whole block:
+// coefficients of section 4 from eta and h_x, b_hat, the initial residual
+// (from u when `guess`, else from 0), PCG (FP64) or FP32 inner PCG inside FP64
+// refinement (MIXED), and u (physical) on return; w is the system's workspace
+// (batch_item_doubles).  Every thread of the block calls it.
+template <int MODE, int NT>
+__device__ BatchResult blk_solve_system(const BatchItem& it, const double* __restrict__ eta,
+                                        const double* __restrict__ hx, const double* __restrict__ b, double* u,
+                                        bool guess, double* w, const cpx<double>* __restrict__ tw64,
+                                        const cpx<float>* __restrict__ tw32, const BatchParams& prm,
+                                        cpx<double>* lds64, cpx<float>* lds32, double* red) {
+    const int N = it.n, M = N / 2;
+    cpx<double>* bh = reinterpret_cast<cpx<double>*>(w);
+    cpx<double>* xh = bh + (M + 1);
+    cpx<double>* rh = xh + (M + 1);
+    cpx<double>* ph = rh + (M + 1);
+    BatchOp<double> A64;
+    A64.N = N;
+    A64.M = M;
+    A64.tp = 6.283185307179586476925286766559 / it.L;
+    A64.eta = eta;
+    A64.hx = hx;
+    A64.ah = ph + (M + 1);
+    A64.scr = reinterpret_cast<double*>(A64.ah + (M + 1));
+    A64.tw = tw64;
+    BatchResult out{};
+    // coefficients of section 4 from the extremes of eta and h_x
+    const double lp = (4.0 + sqrt(13.0)) / 6.0;
+    double ex[5] = {-1.0e308, -1.0e308, -1.0e308, 0.0, 0.0};
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const double e = eta[i], h = hx[i], g2 = h * h;
+        if (!isfinite(e) || !isfinite(g2) || !isfinite(b[i]) ||
+            (guess && !isfinite(u[i])))
+            ex[4] = 1.0;
+        ex[0] = fmax(ex[0], -e);
+        ex[1] = fmax(ex[1], e);
+        ex[2] = fmax(ex[2], e + lp * e * g2);
+        ex[3] = fmax(ex[3], g2);
+    }
+    blk_allmax<5>(ex, red);
+    const double emin = -ex[0];
+    if (ex[4] != 0.0 || !(emin > 0.0)) {
+        out.status = -2;
+        out.relres = __builtin_nan("");
+        return out;
+    }
+    double sig, alp, kap;
+    int fl;
+    if (prm.have_coeffs) {
+        sig = prm.sig;
+        alp = prm.alp;
+        kap = prm.kap;
+        fl = prm.flat;
+    } else {
+        coeffs_formula(emin, ex[1], ex[2], ex[3], prm.flat, prm.coeff_kind, sig, alp, kap, fl);
+    }
+    out.sig = sig;
+    out.alp = alp;
+    out.kap = kap;
+    out.flat = fl;
+    // b_hat, ||b||^2, and the initial x_hat, r_hat
+    blk_to_spectral<NT>(b, N, bh, tw64, lds64);
+    double bb = 0.0, rz = 0.0, rr = 0.0;
+    {
+        double acc[2] = {0.0, 0.0};
+        for (int k = threadIdx.x; k <= M; k += blockDim.x) {
+            const cpx<double> b = bh[k];
+            const double kk = wavenumber<double>(k, N, A64.tp);
+            const cpx<double> z = batch_precond<double>(kk, sig, alp, b);
+            const double wt = half_weight(k, N) / (double)N;
+            acc[0] += wt * (b.re * z.re + b.im * z.im);
+            acc[1] += wt * (b.re * b.re + b.im * b.im);
+        }
+        blk_allsum<2>(acc, red);
+        bb = acc[1];
+        rz = acc[0];
+        rr = acc[1];
+    }
+    const double tol2 = prm.tol * prm.tol;
+    if (guess && bb > 0.0) {
+        blk_to_spectral<NT>(u, N, xh, tw64, lds64);
+        blk_residual<NT>(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
+    } else {
+        for (int k = threadIdx.x; k <= M; k += blockDim.x) {
+            xh[k] = C<double>(0, 0);
+            rh[k] = bh[k];
+        }
+        __syncthreads();
+    }
+    if (MODE == BATCH_FP64) {
+        out.iters = blk_pcg_reg<double, NT, false>(A64, xh, rh, sig, alp, tol2, bb, prm.max_iter, rr, lds64, red);
+    } else {
+        // FP32 view of the same system: coefficient fields rounded once
+        float* e32 = reinterpret_cast<float*>(A64.scr + N);
+        float* h32 = e32 + N;
+        BatchOp<float> A32;
+        A32.N = N;
+        A32.M = M;
+        A32.tp = (float)A64.tp;
+        A32.eta = e32;
+        A32.hx = h32;
+        A32.scr = nullptr;
+        A32.ah = nullptr;
+        A32.tw = tw32;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            e32[i] = (float)eta[i];
+            h32[i] = (float)hx[i];
+        }
+        __syncthreads();
+        const float sig32 = (float)sig, alp32 = (float)alp;
+        const double itol2 = prm.inner_tol * prm.inner_tol;
+        while (!(rr <= tol2 * bb) && rr == rr && out.outer < prm.max_outer && bb > 0.0) {
+            // inner FP32 solve of G d = r to t ||r||, then x += d and the FP64
+            // residual r = b - G x; t = max(inner_tol, tol ||b|| / (2 ||r||)),
+            // capped at 1/2: no tighter than the outer target needs
+            double t2 = 0.25 * tol2 * (bb / rr);
+            t2 = t2 < itol2 ? itol2 : (t2 > 0.25 ? 0.25 : t2);
+            double irr = 0.0;
+            out.iters += blk_pcg_reg<float, NT, true>(A32, xh, rh, sig32, alp32, t2, rr, prm.max_iter, irr,
+                                                      lds32, red);
+            blk_residual<NT>(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
+            out.outer += 1;
+        }
+    }
+    out.converged = (bb == 0.0 || rr <= tol2 * bb) ? 1 : 0;
+    out.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    if (!(rr == rr)) out.status = -2;
+    // u = x (physical)
+    const double invN = 1.0 / (double)N;
+    for (int k = threadIdx.x; k <= M; k += blockDim.x) lds64[k] = invN * xh[k];
+    blk_rfft_inv<double, NT>(lds64, M, tw64);
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        u[2 * j] = lds64[j].re;
+        u[2 * j + 1] = lds64[j].im;
+    }
+    __syncthreads();
+    return out;
+}
+
 template <int MODE, int NT>
 __global__ void __launch_bounds__(NT) k_batch_solve(const BatchItem* __restrict__ items, int nitems,
                                                                const double* __restrict__ eta_all,
@@ -453,142 +605,17 @@ __global__ void __launch_bounds__(NT) k_batch_solve(const BatchItem* __restrict_
                                                                double* __restrict__ u_all, double* __restrict__ ws,
                                                                const cpx<double>* __restrict__ tw64,
                                                                const cpx<float>* __restrict__ tw32, BatchParams prm,
-                                                               BatchResult* __restrict__ res) {
+                                                               BatchResult* __restrict__ res, int* queue) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<double>* lds64 = reinterpret_cast<cpx<double>*>(smem_raw);
     cpx<float>* lds32 = reinterpret_cast<cpx<float>*>(smem_raw);
     __shared__ double red[RED_DOUBLES];
-    for (int s = blockIdx.x; s < nitems; s += gridDim.x) {
+    __shared__ int next_slot;
+    for (int s = blockIdx.x; s < nitems; s = batch_next(queue, s, &next_slot)) {
         const BatchItem it = items[s];
-        const int N = it.n, M = N / 2;
-        const double* eta = eta_all + it.off;
-        const double* hx = hx_all + it.off;
-        double* w = ws + it.wso;
-        cpx<double>* bh = reinterpret_cast<cpx<double>*>(w);
-        cpx<double>* xh = bh + (M + 1);
-        cpx<double>* rh = xh + (M + 1);
-        cpx<double>* ph = rh + (M + 1);
-        BatchOp<double> A64;
-        A64.N = N;
-        A64.M = M;
-        A64.tp = 6.283185307179586476925286766559 / it.L;
-        A64.eta = eta;
-        A64.hx = hx;
-        A64.ah = ph + (M + 1);
-        A64.scr = reinterpret_cast<double*>(A64.ah + (M + 1));
-        A64.tw = tw64;
-        BatchResult out{};
-        // coefficients of section 4 from the extremes of eta and h_x
-        const double lp = (4.0 + sqrt(13.0)) / 6.0;
-        double ex[5] = {-1.0e308, -1.0e308, -1.0e308, 0.0, 0.0};
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
-            const double e = eta[i], h = hx[i], g2 = h * h;
-            if (!isfinite(e) || !isfinite(g2) || !isfinite(b_all[it.off + i]) ||
-                (prm.x0_is_guess && !isfinite(u_all[it.off + i])))
-                ex[4] = 1.0;
-            ex[0] = fmax(ex[0], -e);
-            ex[1] = fmax(ex[1], e);
-            ex[2] = fmax(ex[2], e + lp * e * g2);
-            ex[3] = fmax(ex[3], g2);
-        }
-        blk_allmax<5>(ex, red);
-        const double emin = -ex[0];
-        if (ex[4] != 0.0 || !(emin > 0.0)) {
-            out.status = -2;
-            out.relres = __builtin_nan("");
-            if (threadIdx.x == 0) res[it.index] = out;
-            continue;
-        }
-        double sig, alp, kap;
-        int fl;
-        if (prm.have_coeffs) {
-            sig = prm.sig;
-            alp = prm.alp;
-            kap = prm.kap;
-            fl = prm.flat;
-        } else {
-            coeffs_formula(emin, ex[1], ex[2], ex[3], prm.flat, prm.coeff_kind, sig, alp, kap, fl);
-        }
-        out.sig = sig;
-        out.alp = alp;
-        out.kap = kap;
-        out.flat = fl;
-        // b_hat, ||b||^2, and the initial x_hat, r_hat
-        blk_to_spectral<NT>(b_all + it.off, N, bh, tw64, lds64);
-        double bb = 0.0, rz = 0.0, rr = 0.0;
-        {
-            double acc[2] = {0.0, 0.0};
-            for (int k = threadIdx.x; k <= M; k += blockDim.x) {
-                const cpx<double> b = bh[k];
-                const double kk = wavenumber<double>(k, N, A64.tp);
-                const cpx<double> z = batch_precond<double>(kk, sig, alp, b);
-                const double wt = half_weight(k, N) / (double)N;
-                acc[0] += wt * (b.re * z.re + b.im * z.im);
-                acc[1] += wt * (b.re * b.re + b.im * b.im);
-            }
-            blk_allsum<2>(acc, red);
-            bb = acc[1];
-            rz = acc[0];
-            rr = acc[1];
-        }
-        const double tol2 = prm.tol * prm.tol;
-        if (prm.x0_is_guess && bb > 0.0) {
-            blk_to_spectral<NT>(u_all + it.off, N, xh, tw64, lds64);
-            blk_residual<NT>(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
-        } else {
-            for (int k = threadIdx.x; k <= M; k += blockDim.x) {
-                xh[k] = C<double>(0, 0);
-                rh[k] = bh[k];
-            }
-            __syncthreads();
-        }
-        if (MODE == BATCH_FP64) {
-            out.iters = blk_pcg_reg<double, NT, false>(A64, xh, rh, sig, alp, tol2, bb, prm.max_iter, rr, lds64, red);
-        } else {
-            // FP32 view of the same system: coefficient fields rounded once
-            float* e32 = reinterpret_cast<float*>(A64.scr + N);
-            float* h32 = e32 + N;
-            BatchOp<float> A32;
-            A32.N = N;
-            A32.M = M;
-            A32.tp = (float)A64.tp;
-            A32.eta = e32;
-            A32.hx = h32;
-            A32.scr = nullptr;
-            A32.ah = nullptr;
-            A32.tw = tw32;
-            for (int i = threadIdx.x; i < N; i += blockDim.x) {
-                e32[i] = (float)eta[i];
-                h32[i] = (float)hx[i];
-            }
-            __syncthreads();
-            const float sig32 = (float)sig, alp32 = (float)alp;
-            const double itol2 = prm.inner_tol * prm.inner_tol;
-            while (!(rr <= tol2 * bb) && rr == rr && out.outer < prm.max_outer && bb > 0.0) {
-                // inner FP32 solve of G d = r to t ||r||, then x += d and the FP64
-                // residual r = b - G x; t = max(inner_tol, tol ||b|| / (2 ||r||)),
-                // capped at 1/2: no tighter than the outer target needs
-                double t2 = 0.25 * tol2 * (bb / rr);
-                t2 = t2 < itol2 ? itol2 : (t2 > 0.25 ? 0.25 : t2);
-                double irr = 0.0;
-                out.iters += blk_pcg_reg<float, NT, true>(A32, xh, rh, sig32, alp32, t2, rr, prm.max_iter, irr,
-                                                          lds32, red);
-                blk_residual<NT>(A64, bh, xh, rh, sig, alp, rz, rr, lds64, red);
-                out.outer += 1;
-            }
-        }
-        out.converged = (bb == 0.0 || rr <= tol2 * bb) ? 1 : 0;
-        out.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-        if (!(rr == rr)) out.status = -2;
-        // u = x (physical)
-        const double invN = 1.0 / (double)N;
-        for (int k = threadIdx.x; k <= M; k += blockDim.x) lds64[k] = invN * xh[k];
-        blk_rfft_inv<double, NT>(lds64, M, tw64);
-        double* u = u_all + it.off;
-        for (int j = threadIdx.x; j < M; j += blockDim.x) {
-            u[2 * j] = lds64[j].re;
-            u[2 * j + 1] = lds64[j].im;
-        }
+        const BatchResult out =
+            blk_solve_system<MODE, NT>(it, eta_all + it.off, hx_all + it.off, b_all + it.off, u_all + it.off,
+                                       prm.x0_is_guess != 0, ws + it.wso, tw64, tw32, prm, lds64, lds32, red);
         if (threadIdx.x == 0) res[it.index] = out;
         __syncthreads();
     }
@@ -599,19 +626,16 @@ __global__ void __launch_bounds__(NT) k_batch_solve(const BatchItem* __restrict_
 namespace sgn {
 
 // Right-hand side f(w, p) of a 1D system (Eq:DSWEcf, Def:bigF, Eq:DAE_DSWE) by
-// one workgroup: eta_t = -(eta u)_x, U_t = -eta (eta - h)_x - (eta u u)_x + F
+// the whole workgroup: eta_t = -(eta u)_x, U_t = -eta (eta - h)_x - (eta u u)_x + F
 // with F = S_x - T h_x, S and T of Def:bigF, (u.grad)^2 h read as u (u h_x)_x.
 // All thirteen real transforms run in LDS; spec (5 (N/2+1) modes) and st (5 N
 // points) are global scratch the workgroup owns.  Each thread always handles the
 // same points and modes, so the scratch needs no barriers of its own.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_rhs_1d(int N, double L, const double* __restrict__ eta,
-                                               const double* __restrict__ hx, const double* __restrict__ u,
-                                               double* __restrict__ eta_t, double* __restrict__ U_t,
-                                               cpx<double>* __restrict__ spec, double* __restrict__ st,
-                                               const cpx<double>* __restrict__ tw) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cpx<double>* lds = reinterpret_cast<cpx<double>*>(smem_raw);
+__device__ void blk_rhs_1d(int N, double L, const double* __restrict__ eta, const double* __restrict__ hx,
+                           const double* __restrict__ u, double* __restrict__ eta_t, double* __restrict__ U_t,
+                           cpx<double>* __restrict__ spec, double* __restrict__ st,
+                           const cpx<double>* __restrict__ tw, cpx<double>* lds) {
     const int M = N / 2, M1 = M + 1;
     const double tp = 6.283185307179586476925286766559 / L;
     const double invN = 1.0 / (double)N;
@@ -693,6 +717,272 @@ __global__ void __launch_bounds__(NT) k_rhs_1d(int N, double L, const double* __
         const cpx<double> z = lds[j];
         U_t[2 * j] = z.re + U_t[2 * j];
         U_t[2 * j + 1] = z.im + U_t[2 * j + 1];
+    }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_rhs_1d(int N, double L, const double* __restrict__ eta,
+                                               const double* __restrict__ hx, const double* __restrict__ u,
+                                               double* __restrict__ eta_t, double* __restrict__ U_t,
+                                               cpx<double>* __restrict__ spec, double* __restrict__ st,
+                                               const cpx<double>* __restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    blk_rhs_1d<NT>(N, L, eta, hx, u, eta_t, U_t, spec, st, tw, reinterpret_cast<cpx<double>*>(smem_raw));
+}
+
+// ---- batched RK4 stepping --------------------------------------------------
+// Whole RK4 runs (Eq:ERK) of independent 1D states of up to BATCH_NMAX points,
+// one workgroup per state: every right-hand side (blk_rhs_1d), stage
+// combination and constraint solve (blk_solve_system) of every step runs inside
+// the workgroup, so a run of any length is one launch.  The arithmetic of each
+// step is that of the library's one-state stepper: the same stage values, the
+// same initial guesses (the previous stage's velocity, or that plus the
+// extrapolated offsets of the slot's last two solves) and the same sums.
+
+constexpr int STEP_SLOTS = 4;   // solves of stages 2, 3, 4 and of the new level
+
+struct StepItem {
+    double *eta, *U, *u;           // state (in / out): total depth, U = G u, velocity
+    double* hx;                    // bathymetry slope (written from h when h is set)
+    const double* h;               // bathymetry, or null when hx and U are given
+    double *fe[4], *fU[4];         // stage right-hand sides
+    double *eta_s, *U_s, *u_s;     // stage values
+    double* base;                  // velocity a solve started from
+    double* off[STEP_SLOTS][2];    // offsets recorded by each slot's solves (ring of two)
+    double* scr;                   // step_scratch_doubles(n, mode) doubles
+    double L, dt;
+    int n, index, nsteps, flat;    // flat: 0 / 1 (ignored when h is set)
+    int cnt[STEP_SLOTS], head[STEP_SLOTS];
+};
+
+struct StepResult {
+    long long iters, solves;
+    int max_iters, converged, steps, status;   // status 0, -2 (domain) or -3 (a solve missed tol)
+    int flat, pad;
+    int cnt[STEP_SLOTS], head[STEP_SLOTS];
+};
+
+// Doubles of per-state scratch: the right-hand side's (5 (N/2+1) modes and 5 N
+// points) or one solve's workspace, whichever is larger.
+__host__ __device__ inline long long step_scratch_doubles(int n, int mode) {
+    const long long rhs = 10LL * (n / 2 + 1) + 5LL * n;
+    const long long sol = batch_item_doubles(n, mode);
+    return rhs > sol ? rhs : sol;
+}
+
+// h_x = D h (zero when h is constant: the flat formulas apply) and U = G_{eta,h} u
+// for a state given by eta, h and u.  False for non-finite h.
+template <int NT>
+__device__ bool blk_step_prepare(const StepItem& it, int& flat, const cpx<double>* __restrict__ tw,
+                                 cpx<double>* lds, double* red) {
+    const int N = it.n, M = N / 2;
+    const double invN = 1.0 / (double)N, tp = 6.283185307179586476925286766559 / it.L;
+    double ex[3] = {-1.0e308, -1.0e308, 0.0};
+    for (int i = threadIdx.x; i < N; i += NT) {
+        const double v = it.h[i];
+        if (!isfinite(v)) ex[2] = 1.0;
+        ex[0] = fmax(ex[0], -v);
+        ex[1] = fmax(ex[1], v);
+    }
+    blk_allmax<3>(ex, red);
+    if (ex[2] != 0.0) return false;
+    flat = (-ex[0] == ex[1]) ? 1 : 0;
+    if (flat) {
+        for (int i = threadIdx.x; i < N; i += NT) it.hx[i] = 0.0;
+    } else {
+        for (int j = threadIdx.x; j < M; j += NT) lds[j] = C<double>(it.h[2 * j], it.h[2 * j + 1]);
+        blk_rfft_fwd<double, NT>(lds, M, tw);
+        for (int k = threadIdx.x; k <= M; k += NT) lds[k] = invN * ik(wavenumber<double>(k, N, tp), lds[k]);
+        blk_rfft_inv<double, NT>(lds, M, tw);
+        for (int j = threadIdx.x; j < M; j += NT) {
+            it.hx[2 * j] = lds[j].re;
+            it.hx[2 * j + 1] = lds[j].im;
+        }
+    }
+    __syncthreads();
+    // U = G u: u_hat, then q_hat = G u_hat (blk_apply) back to physical space
+    cpx<double>* uh = reinterpret_cast<cpx<double>*>(it.scr);
+    BatchOp<double> A;
+    A.N = N;
+    A.M = M;
+    A.tp = tp;
+    A.eta = it.eta;
+    A.hx = it.hx;
+    A.ah = uh + (M + 1);
+    A.scr = reinterpret_cast<double*>(A.ah + (M + 1));
+    A.tw = tw;
+    blk_to_spectral<NT>(it.u, N, uh, tw, lds);
+    blk_apply<double, NT>(A, uh, lds, red, [&](int k, double, cpx<double> q, double) { uh[k] = invN * q; });
+    for (int k = threadIdx.x; k <= M; k += NT) lds[k] = uh[k];
+    blk_rfft_inv<double, NT>(lds, M, tw);
+    for (int j = threadIdx.x; j < M; j += NT) {
+        it.U[2 * j] = lds[j].re;
+        it.U[2 * j + 1] = lds[j].im;
+    }
+    __syncthreads();
+    return true;
+}
+
+// G_{eta,h} u = U for stepper slot `slot`, u holding the base velocity on entry.
+// With extrapolation the solve starts from base + o_1 (one recorded offset) or
+// base + (2 o_1 - o_2) (two), and records u - base afterwards.  0, -2 or -3.
+template <int MODE, int NT>
+__device__ int blk_step_solve(const StepItem& it, StepResult& out, int slot, bool extrapolate, const double* eta,
+                              const double* U, double* u, const cpx<double>* __restrict__ tw64,
+                              const cpx<float>* __restrict__ tw32, const BatchParams& prm, cpx<double>* lds64,
+                              cpx<float>* lds32, double* red) {
+    const int N = it.n;
+    int& cnt = out.cnt[slot];
+    int& head = out.head[slot];
+    const int nh = cnt == 0 ? head : head ^ 1;
+    if (extrapolate) {
+        const double* o1 = it.off[slot][head];
+        const double* o2 = it.off[slot][head ^ 1];
+        for (int i = threadIdx.x; i < N; i += NT) {
+            const double b = u[i];
+            it.base[i] = b;
+            if (cnt == 1) {
+                double s = 0.0;
+                s += 1.0 * o1[i];
+                u[i] = b + 1.0 * s;
+            } else if (cnt >= 2) {
+                double s = 0.0;
+                s += 2.0 * o1[i];
+                s += -1.0 * o2[i];
+                u[i] = b + 1.0 * s;
+            }
+        }
+        __syncthreads();
+    }
+    BatchItem bi;
+    bi.n = N;
+    bi.index = it.index;
+    bi.L = it.L;
+    bi.off = 0;
+    bi.wso = 0;
+    const BatchResult r = blk_solve_system<MODE, NT>(bi, eta, it.hx, U, u, true, it.scr, tw64, tw32, prm, lds64,
+                                                     lds32, red);
+    out.solves += 1;
+    out.iters += r.iters;
+    if (r.iters > out.max_iters) out.max_iters = r.iters;
+    if (!r.converged) out.converged = 0;
+    if (r.status != 0) return -2;
+    if (!r.converged) return -3;
+    if (extrapolate) {
+        double* o = it.off[slot][nh];
+        for (int i = threadIdx.x; i < N; i += NT) {
+            double s = 0.0;
+            s += -1.0 * it.base[i];
+            o[i] = u[i] + 1.0 * s;
+        }
+        __syncthreads();
+        head = nh;
+        if (cnt < 2) cnt += 1;
+    }
+    return 0;
+}
+
+// RK4 steps of one state by the whole workgroup (Eq:ERK): stage i takes
+// eta_n + dt a_i f^(i-1) and U_n + dt a_i f^(i-1) and solves G u^(i) = U^(i) from
+// u^(i-1); the weighted sum advances eta and U, and u_{n+1} is solved from u^(4).
+// A step counts once eta and U have advanced, even if its last solve fails.
+template <int MODE, int NT>
+__device__ StepResult blk_rk4_run(const StepItem& it, bool extrapolate, const cpx<double>* __restrict__ tw64,
+                                  const cpx<float>* __restrict__ tw32, BatchParams prm, cpx<double>* lds64,
+                                  cpx<float>* lds32, double* red) {
+    StepResult out{};
+    out.converged = 1;
+#pragma unroll
+    for (int k = 0; k < STEP_SLOTS; ++k) {
+        out.cnt[k] = it.cnt[k];
+        out.head[k] = it.head[k];
+    }
+    const int N = it.n;
+    int flat = it.flat;
+    if (it.h && !blk_step_prepare<NT>(it, flat, tw64, lds64, red)) {
+        out.status = -2;
+        return out;
+    }
+    out.flat = flat;
+    prm.flat = flat ? 1 : 0;
+    prm.have_coeffs = 0;
+    prm.x0_is_guess = 1;
+    cpx<double>* spec = reinterpret_cast<cpx<double>*>(it.scr);
+    double* st = it.scr + 10LL * (N / 2 + 1);
+    const double a[3] = {0.5, 0.5, 1.0};
+    const double w[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const double dt = it.dt;
+    // phase k of a step: k > 0 forms stage k + 1's values (the new level for
+    // k = 4) and solves for its velocity; k < 4 then evaluates f^(k) there.  One
+    // call site for the solve and one for the right-hand side keep the kernel's
+    // code (and register allocation) to a single copy of each.
+    for (int n = 0; n < it.nsteps; ++n) {
+        for (int k = 0; k <= 4; ++k) {
+            if (k > 0) {
+                const bool last = k == 4;
+                for (int i = threadIdx.x; i < N; i += NT) {
+                    if (!last) {
+                        double s = 0.0;
+                        s += a[k - 1] * it.fe[k - 1][i];
+                        it.eta_s[i] = it.eta[i] + dt * s;
+                        double q = 0.0;
+                        q += a[k - 1] * it.fU[k - 1][i];
+                        it.U_s[i] = it.U[i] + dt * q;
+                    } else {
+                        double s = 0.0, q = 0.0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            s += w[j] * it.fe[j][i];
+                            q += w[j] * it.fU[j][i];
+                        }
+                        it.eta[i] = it.eta[i] + dt * s;
+                        it.U[i] = it.U[i] + dt * q;
+                        it.u[i] = it.u_s[i];
+                    }
+                }
+                __syncthreads();
+                const int rc = blk_step_solve<MODE, NT>(it, out, k - 1, extrapolate, last ? it.eta : it.eta_s,
+                                                        last ? it.U : it.U_s, last ? it.u : it.u_s, tw64, tw32, prm,
+                                                        lds64, lds32, red);
+                if (last) out.steps += 1;
+                if (rc != 0) {
+                    out.status = rc;
+                    return out;
+                }
+            }
+            if (k < 4) {
+                blk_rhs_1d<NT>(N, it.L, k ? it.eta_s : it.eta, it.hx, k ? it.u_s : it.u, it.fe[k], it.fU[k], spec,
+                               st, tw64, lds64);
+                __syncthreads();
+                if (k == 0) {
+                    for (int i = threadIdx.x; i < N; i += NT) it.u_s[i] = it.u[i];
+                    __syncthreads();
+                }
+            }
+        }
+    }
+    return out;
+}
+
+// Batched RK4 runs: workgroups take states from the table (a work queue when
+// queue is set, its counter zero at launch) until none is left.  LDS: two FP64
+// transform buffers of the largest state's N/2 + 1 modes.
+template <int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_batch_rk4(const StepItem* __restrict__ items, int nitems,
+                                                  const cpx<double>* __restrict__ tw64,
+                                                  const cpx<float>* __restrict__ tw32, BatchParams prm,
+                                                  int extrapolate, StepResult* __restrict__ res, int* queue) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<double>* lds64 = reinterpret_cast<cpx<double>*>(smem_raw);
+    cpx<float>* lds32 = reinterpret_cast<cpx<float>*>(smem_raw);
+    __shared__ double red[RED_DOUBLES];
+    __shared__ int next_slot;
+    for (int s = blockIdx.x; s < nitems; s = batch_next(queue, s, &next_slot)) {
+        // the table entry stays in memory and is read where used (uniform loads)
+        const StepItem& it = items[__builtin_amdgcn_readfirstlane(s)];
+        const StepResult out = blk_rk4_run<MODE, NT>(it, extrapolate != 0, tw64, tw32, prm, lds64, lds32, red);
+        if (threadIdx.x == 0) res[it.index] = out;
+        __syncthreads();
     }
 }
 

@@ -42,6 +42,10 @@ struct sgn_ctx {
         hipGraphExec_t exec;  // null: seen once (ran eagerly), capture on the next use
     };
     hipStream_t cap_stream = nullptr;
+    // second stream of batched RK4 launches (created on first use, default
+    // priority): the size classes of one call run side by side
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<GraphEntry> graphs;
     bool use_graphs = false;
     // iterations of the previous solve per precision (FP64 / FP32 loop) and
@@ -610,8 +614,9 @@ size_t workspace_bytes(const Dims& d, int precision) {
         carve_rhs(cv, d);
         best = std::max(best, cv.off);
     }
-    if (d.D == 1 && d.nx <= BATCH_NMAX) {   // one-workgroup 1D solve and right-hand side
+    if (d.D == 1 && d.nx <= BATCH_NMAX) {   // one-workgroup 1D solve, right-hand side and RK4 run
         best = std::max(best, (size_t)512 + (size_t)batch_item_doubles(d.nx, BATCH_MIXED) * sizeof(double));
+        best = std::max(best, (size_t)1024 + (size_t)step_scratch_doubles(d.nx, BATCH_MIXED) * sizeof(double));
         Carve cv(nullptr);
         carve_common(cv);
         cv.take<cpx<double>>((size_t)5 * (d.nx / 2 + 1));
@@ -1570,7 +1575,7 @@ sgn_status solve_1d_block(sgn_ctx* ctx, const Dims& d, double L, const double* e
         auto launch = [&](auto k, int nt) -> sgn_status {
             HIPCHK(ctx, allow_lds(k, lds));
             hipLaunchKernelGGL(k, dim3(1), dim3(nt), lds, ctx->stream, (const BatchItem*)d_item, 1, eta, gh, rhs, u,
-                               d_data, ctx->tw64, ctx->tw32, prm, d_res);
+                               d_data, ctx->tw64, ctx->tw32, prm, d_res, (int*)nullptr);
             CHECK_LAUNCH(ctx);
             return SGN_OK;
         };
@@ -2749,6 +2754,9 @@ void sgn_destroy(sgn_ctx* ctx) {
     for (auto& g : ctx->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->hbatch) (void)hipHostFree(ctx->hbatch);
     delete ctx;
 }
@@ -3003,16 +3011,19 @@ sgn_status sgn_krylov_solve_noalloc(sgn_ctx* ctx, const sgn_grid* grid, const do
 
 namespace {
 
-// Layout of a batch workspace: item table, results, then each system's region.
+// Layout of a batch workspace: the work-queue counter, the item table, results,
+// then each system's region.
 struct BatchLayout {
-    size_t items, results, data, total;
+    size_t queue, items, results, data, total;
 };
+constexpr size_t BATCH_HEAD = 256;   // bytes before the item table (the counter, padded)
 
 BatchLayout batch_layout(int nitems, const int32_t* n, int mode) {
     BatchLayout l;
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    l.items = 0;
-    l.results = up(sizeof(BatchItem) * (size_t)nitems);
+    l.queue = 0;
+    l.items = BATCH_HEAD;
+    l.results = l.items + up(sizeof(BatchItem) * (size_t)nitems);
     l.data = l.results + up(sizeof(BatchResult) * (size_t)nitems);
     size_t dbl = 0;
     for (int i = 0; i < nitems; ++i) dbl += (size_t)batch_item_doubles(n[i], mode);
@@ -3021,6 +3032,153 @@ BatchLayout batch_layout(int nitems, const int32_t* n, int mode) {
 }
 
 bool batch_size_ok(int n) { return n >= 2 && n <= BATCH_NMAX && (n & (n - 1)) == 0; }
+
+// ---- batched RK4 runs (k_batch_rk4) ----------------------------------------
+
+// One state's arrays in a batched run, each 256-byte aligned: h_x, U, the four
+// stage right-hand sides of eta and of U, eta_s, U_s, u_s, the solve base, the
+// two recorded offsets of each guess slot; then the scratch.
+constexpr int STEP_ARRAYS = 2 + 8 + 4 + 2 * STEP_SLOTS;
+long long step_align(long long d) { return (d + 31) & ~31LL; }
+long long step_item_doubles(int n, int mode) {
+    return STEP_ARRAYS * step_align(n) + step_align(step_scratch_doubles(n, mode));
+}
+
+struct StepLayout {
+    size_t items, results, data, total;
+};
+StepLayout step_layout(int nitems, const int32_t* n, int mode) {
+    StepLayout l;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    l.items = BATCH_HEAD;
+    l.results = l.items + up(sizeof(StepItem) * (size_t)nitems);
+    l.data = l.results + up(sizeof(StepResult) * (size_t)nitems);
+    size_t dbl = 0;
+    for (int i = 0; i < nitems; ++i) dbl += (size_t)step_item_doubles(n[i], mode);
+    l.total = l.data + dbl * sizeof(double) + 256;
+    return l;
+}
+
+// Solve parameters of every stage solve of a run.
+BatchParams step_params(const sgn_solve_opts& o, int nitems) {
+    BatchParams prm{};
+    prm.tol = o.tol;
+    prm.inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    prm.max_iter = o.max_iter;
+    prm.max_outer = o.max_outer > 0 ? o.max_outer : 20;
+    prm.x0_is_guess = 1;
+    prm.coeff_kind = o.coeff_kind;
+    prm.nitems = nitems;
+    prm.flat = -1;
+    return prm;
+}
+
+// Workgroup size of a state's runs: fixed by its own size, so that its
+// reductions (and with them its results) do not depend on what shares a launch.
+int step_threads(int n) { return n <= 2048 ? 256 : 512; }
+
+// k_batch_rk4 over nitems table entries of one size class (workgroups of nt
+// threads) on `stream`; grid = 0: as many workgroups as fit the device (at most
+// nitems), which then share the work queue d_queue (zero at launch).
+sgn_status launch_batch_rk4(sgn_ctx* ctx, hipStream_t stream, int nt, const StepItem* d_items, int nitems, int nmax,
+                            int mode, int grid, const BatchParams& prm, bool extrapolate, StepResult* d_res,
+                            int* d_queue) {
+    const size_t lds = (size_t)(nmax / 2 + 1) * sizeof(cpx<double>) * (mode == BATCH_FP64 ? 2 : 1);
+    auto launch = [&](auto k) -> sgn_status {
+        HIPCHK(ctx, allow_lds(k, lds));
+        int g = grid;
+        if (g <= 0) {
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, nt, lds) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            g = std::min(nitems, per_cu * ctx->cus);
+        }
+        hipLaunchKernelGGL(k, dim3(g), dim3(nt), lds, stream, d_items, nitems, ctx->tw64, ctx->tw32, prm,
+                           extrapolate ? 1 : 0, d_res, d_queue);
+        CHECK_LAUNCH(ctx);
+        return SGN_OK;
+    };
+    const bool mx = mode == BATCH_MIXED;
+    if (nt == 256) return mx ? launch(k_batch_rk4<BATCH_MIXED, 256>) : launch(k_batch_rk4<BATCH_FP64, 256>);
+    return mx ? launch(k_batch_rk4<BATCH_MIXED, 512>) : launch(k_batch_rk4<BATCH_FP64, 512>);
+}
+
+static_assert(sizeof(StepItem) <= 512 && sizeof(StepResult) <= 512, "step table entries");
+
+// RK4 steps of a periodic 1D state of up to BATCH_NMAX points in one launch:
+// k_batch_rk4 with the single state, its own buffers and guess history.  The
+// table entry, its result and the scratch sit at the start of the state's solve
+// workspace (item | result | scratch from byte 1024).
+sgn_status rk4_block(sgn_state* st, double dt, int nsteps, const sgn_solve_opts& o, sgn_step_info* acc) {
+    sgn_ctx* ctx = st->ctx;
+    StateBufs& b = st->b;
+    sgn_status s;
+    if ((s = batch_staging(ctx, 1024)) != SGN_OK) return s;
+    const int mode = o.precision == SGN_MIXED ? BATCH_MIXED : BATCH_FP64;
+    StepItem* hit = static_cast<StepItem*>(ctx->hbatch);
+    std::memset(hit, 0, sizeof(StepItem));
+    hit->eta = st->eta;
+    hit->U = st->U;
+    hit->u = st->u;
+    hit->hx = const_cast<double*>(st->gh);   // read only: h is null
+    hit->h = nullptr;
+    for (int k = 0; k < 4; ++k) {
+        hit->fe[k] = b.rk_fe[k];
+        hit->fU[k] = b.rk_fU[k];
+    }
+    hit->eta_s = b.eta_s;
+    hit->U_s = b.U_s;
+    hit->u_s = b.u_s;
+    hit->base = b.gx_base;
+    static_assert(GUESS_RK2 == 0 && GUESS_RK_FINAL == STEP_SLOTS - 1, "stepper slots");
+    for (int k = 0; k < STEP_SLOTS; ++k) {
+        hit->off[k][0] = b.gx_off[k][0];
+        hit->off[k][1] = b.gx_off[k][1];
+        hit->cnt[k] = st->gx_count[k];
+        hit->head[k] = st->gx_head[k];
+    }
+    char* base = static_cast<char*>(st->ws);
+    hit->scr = reinterpret_cast<double*>(base + 1024);
+    hit->L = st->d.Lx;
+    hit->dt = dt;
+    hit->n = st->d.nx;
+    hit->index = 0;
+    hit->nsteps = nsteps;
+    hit->flat = st->flat ? 1 : 0;
+    StepItem* d_item = reinterpret_cast<StepItem*>(base);
+    StepResult* d_res = reinterpret_cast<StepResult*>(base + 512);
+    HIPCHK(ctx, hipMemcpyAsync(d_item, hit, sizeof(StepItem), hipMemcpyHostToDevice, ctx->stream));
+    {
+        ProfScope ps(ctx, SGN_KERNEL_BATCH_STEP);
+        if ((s = launch_batch_rk4(ctx, ctx->stream, step_threads(st->d.nx), d_item, 1, st->d.nx, mode, 1,
+                                  step_params(o, 1), o.guess == SGN_GUESS_EXTRAPOLATE, d_res, nullptr)) != SGN_OK)
+            return s;
+    }
+    StepResult* hres = reinterpret_cast<StepResult*>(static_cast<char*>(ctx->hbatch) + 512);
+    HIPCHK(ctx, hipMemcpyAsync(hres, d_res, sizeof(StepResult), hipMemcpyDeviceToHost, ctx->stream));
+    if ((s = wait_stream(ctx)) != SGN_OK) return s;
+    const StepResult r = *hres;
+    acc->solves += r.solves;
+    acc->iters += r.iters;
+    if (r.max_iters > acc->max_iters) acc->max_iters = r.max_iters;
+    if (!r.converged) acc->converged = 0;
+    for (int k = 0; k < r.steps; ++k) st->t += dt;
+    st->steps += r.steps;
+    for (int k = 0; k < STEP_SLOTS; ++k) {
+        st->gx_count[k] = r.cnt[k];
+        st->gx_head[k] = r.head[k];
+    }
+    if (r.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
+    if (r.status == -3) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
+    return SGN_OK;
+}
+
+// The state's RK4 steps run in one launch: a periodic 1D grid of up to
+// BATCH_NMAX points, the plain right-hand side, PCG in FP64 or mixed precision.
+bool rk4_block_ok(const sgn_state* st, const sgn_solve_opts& o) {
+    return st->d.D == 1 && st->d.nx <= BATCH_NMAX && !st->dealias && o.method == SGN_PCG &&
+           (o.precision == SGN_FP64 || o.precision == SGN_MIXED);
+}
 
 
 }  // namespace
@@ -3057,7 +3215,8 @@ sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const
     const int mode = o.precision == SGN_MIXED ? BATCH_MIXED : BATCH_FP64;
     const BatchLayout lay = batch_layout(nitems, n, mode);
     sgn_status s;
-    if ((s = batch_staging(ctx, std::max(sizeof(BatchItem), sizeof(BatchResult)) * (size_t)nitems)) != SGN_OK)
+    if ((s = batch_staging(ctx, BATCH_HEAD + std::max(sizeof(BatchItem), sizeof(BatchResult)) * (size_t)nitems)) !=
+        SGN_OK)
         return s;
     // systems in the caller's order for offsets; the table is sorted by size
     // (largest first) so that blocks take the long systems first
@@ -3072,7 +3231,9 @@ sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const
     std::vector<int> order(nitems);
     for (int i = 0; i < nitems; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
-    BatchItem* hit = static_cast<BatchItem*>(ctx->hbatch);
+    // staging: the queue counter (0), then the item table, copied in one transfer
+    std::memset(ctx->hbatch, 0, BATCH_HEAD);
+    BatchItem* hit = reinterpret_cast<BatchItem*>(static_cast<char*>(ctx->hbatch) + BATCH_HEAD);
     for (int s2 = 0; s2 < nitems; ++s2) {
         const int i = order[s2];
         hit[s2].n = n[i];
@@ -3082,10 +3243,12 @@ sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const
         hit[s2].wso = wso[i];
     }
     char* base = static_cast<char*>(ws);
+    int* d_queue = reinterpret_cast<int*>(base + lay.queue);
     BatchItem* d_items = reinterpret_cast<BatchItem*>(base + lay.items);
     BatchResult* d_res = reinterpret_cast<BatchResult*>(base + lay.results);
     double* d_data = reinterpret_cast<double*>(base + lay.data);
-    HIPCHK(ctx, hipMemcpyAsync(d_items, hit, sizeof(BatchItem) * (size_t)nitems, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(base, ctx->hbatch, BATCH_HEAD + sizeof(BatchItem) * (size_t)nitems,
+                               hipMemcpyHostToDevice, ctx->stream));
     BatchParams prm{};
     prm.tol = o.tol;
     prm.inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
@@ -3107,7 +3270,7 @@ sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const
                 per_cu = 1;
             const int grid = std::min(nitems, per_cu * ctx->cus);
             hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, ctx->stream, (const BatchItem*)d_items, nitems, eta,
-                               grad_h, rhs, u, d_data, ctx->tw64, ctx->tw32, prm, d_res);
+                               grad_h, rhs, u, d_data, ctx->tw64, ctx->tw32, prm, d_res, d_queue);
             CHECK_LAUNCH(ctx);
             return SGN_OK;
         };
@@ -3140,6 +3303,169 @@ sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const
     }
     if (bad) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in a batched system");
     if (nc) return fail(ctx, SGN_ENOCONV, "a batched system did not reach the tolerance");
+    return SGN_OK;
+}
+
+size_t sgn_batch_step_workspace_bytes(int32_t nitems, const int32_t* n, int32_t precision) {
+    if (nitems < 0 || (nitems > 0 && !n)) return 0;
+    if (precision != SGN_FP64 && precision != SGN_MIXED) return 0;
+    for (int i = 0; i < nitems; ++i)
+        if (!batch_size_ok(n[i])) return 0;
+    return step_layout(nitems, n, precision == SGN_MIXED ? BATCH_MIXED : BATCH_FP64).total;
+}
+
+sgn_status sgn_batch_step_rk4(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const double* L, const double* dt,
+                              const int32_t* nsteps, const double* h, double* eta, double* u,
+                              const sgn_solve_opts* opts, sgn_step_info* info, sgn_status* status, void* ws) {
+    if (!ctx) return SGN_EINVAL;
+    if (nitems < 0) return fail(ctx, SGN_EINVAL, "nitems < 0");
+    if (nitems == 0) return SGN_OK;
+    if (!n || !L || !dt || !nsteps || !h || !eta || !u || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
+    const sgn_solve_opts o = opts ? *opts : default_opts();
+    if (o.method != SGN_PCG) return fail(ctx, SGN_EUNSUPPORTED, "stepper solves use PCG");
+    if (o.precision != SGN_FP64 && o.precision != SGN_MIXED) return fail(ctx, SGN_EINVAL, "unknown precision");
+    if (!(o.tol > 0.0) || o.max_iter < 1) return fail(ctx, SGN_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (o.coeff_kind != SGN_COEFF_OPTIMAL && o.coeff_kind != SGN_COEFF_REPLACEMENT)
+        return fail(ctx, SGN_EINVAL, "bad coeff_kind");
+    if (o.guess != SGN_GUESS_PREVIOUS && o.guess != SGN_GUESS_EXTRAPOLATE) return fail(ctx, SGN_EINVAL, "bad guess");
+    int nmax = 0;
+    for (int i = 0; i < nitems; ++i) {
+        if (!batch_size_ok(n[i])) return fail(ctx, SGN_EUNSUPPORTED, "batch sizes must be powers of two in [2, 8192]");
+        if (!(L[i] > 0.0) || !std::isfinite(L[i])) return fail(ctx, SGN_EINVAL, "periods must be positive");
+        if (!std::isfinite(dt[i]) || nsteps[i] < 0) return fail(ctx, SGN_EINVAL, "bad step arguments");
+        nmax = std::max(nmax, (int)n[i]);
+    }
+    const int mode = o.precision == SGN_MIXED ? BATCH_MIXED : BATCH_FP64;
+    const StepLayout lay = step_layout(nitems, n, mode);
+    sgn_status s;
+    if ((s = batch_staging(ctx, BATCH_HEAD + std::max(sizeof(StepItem), sizeof(StepResult)) * (size_t)nitems)) !=
+        SGN_OK)
+        return s;
+    char* base = static_cast<char*>(ws);
+    double* data = reinterpret_cast<double*>(base + lay.data);
+    // states in the caller's order for offsets; the table runs longest first
+    // (points times steps) so that workgroups take the long runs first
+    std::vector<long long> off(nitems), dso(nitems);
+    long long po = 0, pd = 0;
+    for (int i = 0; i < nitems; ++i) {
+        off[i] = po;
+        dso[i] = pd;
+        po += n[i];
+        pd += step_item_doubles(n[i], mode);
+    }
+    // the table: the 512-thread class (n > 2048) first, then the 256-thread one,
+    // each longest run (points times steps) first
+    std::vector<int> order(nitems);
+    for (int i = 0; i < nitems; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int ta = step_threads(n[a]), tb = step_threads(n[b]);
+        if (ta != tb) return ta > tb;
+        return (long long)n[a] * nsteps[a] > (long long)n[b] * nsteps[b];
+    });
+    int n_big = 0, nmax_small = 0;
+    for (int i = 0; i < nitems; ++i) {
+        if (step_threads(n[i]) == 512)
+            ++n_big;
+        else
+            nmax_small = std::max(nmax_small, (int)n[i]);
+    }
+    std::memset(ctx->hbatch, 0, BATCH_HEAD);   // the two classes' queue counters
+    StepItem* hit = reinterpret_cast<StepItem*>(static_cast<char*>(ctx->hbatch) + BATCH_HEAD);
+    for (int q = 0; q < nitems; ++q) {
+        const int i = order[q];
+        StepItem& it = hit[q];
+        std::memset(&it, 0, sizeof(it));
+        const long long a = step_align(n[i]);
+        double* p = data + dso[i];
+        auto take = [&]() {
+            double* r = p;
+            p += a;
+            return r;
+        };
+        it.eta = eta + off[i];
+        it.u = u + off[i];
+        it.h = h + off[i];
+        it.hx = take();
+        it.U = take();
+        for (int k = 0; k < 4; ++k) {
+            it.fe[k] = take();
+            it.fU[k] = take();
+        }
+        it.eta_s = take();
+        it.U_s = take();
+        it.u_s = take();
+        it.base = take();
+        for (int k = 0; k < STEP_SLOTS; ++k) {
+            it.off[k][0] = take();
+            it.off[k][1] = take();
+        }
+        it.scr = p;
+        it.L = L[i];
+        it.dt = dt[i];
+        it.n = n[i];
+        it.index = i;
+        it.nsteps = nsteps[i];
+    }
+    HIPCHK(ctx, hipMemcpyAsync(base, ctx->hbatch, BATCH_HEAD + sizeof(StepItem) * (size_t)nitems,
+                               hipMemcpyHostToDevice, ctx->stream));
+    const StepItem* d_items = reinterpret_cast<const StepItem*>(base + lay.items);
+    StepResult* d_res = reinterpret_cast<StepResult*>(base + lay.results);
+    int* d_queue = reinterpret_cast<int*>(base);   // counters at bytes 0 and 128
+    const BatchParams prm = step_params(o, nitems);
+    const bool ex = o.guess == SGN_GUESS_EXTRAPOLATE;
+    const int n_small = nitems - n_big;
+    {
+        ProfScope ps(ctx, SGN_KERNEL_BATCH_STEP);
+        if (n_big > 0 && n_small > 0) {
+            // the large class on the second stream, the small one beside it
+            if (!ctx->aux_stream) {
+                HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
+                HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+                HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+            }
+            HIPCHK(ctx, hipEventRecord(ctx->ev_fork, ctx->stream));
+            HIPCHK(ctx, hipStreamWaitEvent(ctx->aux_stream, ctx->ev_fork, 0));
+            if ((s = launch_batch_rk4(ctx, ctx->aux_stream, 512, d_items, n_big, nmax, mode, 0, prm, ex, d_res,
+                                      d_queue)) != SGN_OK)
+                return s;
+            HIPCHK(ctx, hipEventRecord(ctx->ev_join, ctx->aux_stream));
+            s = launch_batch_rk4(ctx, ctx->stream, 256, d_items + n_big, n_small, nmax_small, mode, 0, prm, ex, d_res,
+                                 d_queue + 32);
+            HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
+            if (s != SGN_OK) return s;
+        } else {
+            const int nt = n_big > 0 ? 512 : 256;
+            if ((s = launch_batch_rk4(ctx, ctx->stream, nt, d_items, nitems, nmax, mode, 0, prm, ex, d_res,
+                                      d_queue)) != SGN_OK)
+                return s;
+        }
+    }
+    StepResult* hres = static_cast<StepResult*>(ctx->hbatch);
+    HIPCHK(ctx, hipMemcpyAsync(hres, base + lay.results, sizeof(StepResult) * (size_t)nitems, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    if ((s = wait_stream(ctx)) != SGN_OK) return s;
+    bool bad = false, nc = false;
+    for (int i = 0; i < nitems; ++i) {
+        const StepResult& r = hres[i];
+        if (info) {
+            sgn_step_info& f = info[i];
+            std::memset(&f, 0, sizeof(f));
+            f.solves = r.solves;
+            f.iters = r.iters;
+            f.max_iters = r.max_iters;
+            f.converged = r.converged;
+            double t = 0.0;
+            for (int k = 0; k < r.steps; ++k) t += dt[i];
+            f.t = t;
+            f.steps_done = r.steps;
+        }
+        const sgn_status si = r.status == -2 ? SGN_EDOMAIN : r.status == -3 ? SGN_ENOCONV : SGN_OK;
+        if (status) status[i] = si;
+        bad = bad || si == SGN_EDOMAIN;
+        nc = nc || si == SGN_ENOCONV;
+    }
+    if (bad) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in a batched run");
+    if (nc) return fail(ctx, SGN_ENOCONV, "a batched run's solve did not reach the tolerance");
     return SGN_OK;
 }
 
@@ -3333,7 +3659,11 @@ sgn_status sgn_step_rk4(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nsteps, 
     info_init(&acc);
     st->kind = 0;  // a multistep history does not survive other steps
     sgn_status s = SGN_OK;
-    for (int n = 0; n < nsteps && s == SGN_OK; ++n) s = rk4_one(st, dt, o, &acc, false);
+    if (rk4_block_ok(st, o)) {
+        if (nsteps > 0) s = rk4_block(st, dt, nsteps, o, &acc);
+    } else {
+        for (int n = 0; n < nsteps && s == SGN_OK; ++n) s = rk4_one(st, dt, o, &acc, false);
+    }
     info_finish(st, &acc, info);
     return s;
 }

@@ -1,7 +1,8 @@
 // libsgn request server: HBM-footprint admission, continuous batching of small
-// 1D solves into sgn_batch_solve launches, and worker lanes (one context and
-// HIP stream each) for 2D and large 1D solves and RK4 time-steps.  A client of
-// the C ABI in sgn.h.
+// 1D solves into sgn_batch_solve launches and of small 1D RK4 runs into
+// sgn_batch_step_rk4 launches (a batching lane for each), and worker lanes (one
+// context and HIP stream each) for 2D and large 1D solves and steps.  A client
+// of the C ABI in sgn.h.
 #include "sgn.h"
 
 #include <hip/hip_runtime.h>
@@ -23,7 +24,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr int BATCH_N_MAX = 8192;      // largest 1D size the batched solver takes
+constexpr int BATCH_N_MAX = 8192;      // largest 1D size the batched solver and stepper take
+enum { BATCH_SOLVES = 0, BATCH_STEPS = 1, BATCH_LANES = 2 };
 constexpr size_t ALIGN = 256;
 
 size_t up(size_t b) { return (b + ALIGN - 1) & ~(ALIGN - 1); }
@@ -40,8 +42,10 @@ bool grid_ok(const sgn_grid& g) {
 
 size_t npts(const sgn_grid& g) { return (size_t)g.nx * (g.dim == 2 ? (size_t)g.ny : 1); }
 
-bool batchable(const sgn_request& r) {
-    return r.kind == SGN_REQ_SOLVE && r.grid.dim == 1 && r.grid.nx <= BATCH_N_MAX;
+// Batching lane of a request (BATCH_SOLVES, BATCH_STEPS), or -1: a worker lane.
+int batch_lane_of(const sgn_request& r) {
+    if (r.grid.dim != 1 || r.grid.nx > BATCH_N_MAX) return -1;
+    return r.kind == SGN_REQ_SOLVE ? BATCH_SOLVES : BATCH_STEPS;
 }
 
 // Device layout of a lane request: fields, then the Krylov workspace, then the
@@ -86,13 +90,24 @@ size_t pool_class(size_t b) {
     return c;
 }
 
+// Device bytes a batched group of the lane's kind needs for its fields and
+// workspace: eta | h_x | rhs | u then the batched solver's workspace, or h |
+// eta | u then the batched stepper's.
+size_t batch_group_bytes(int lane, size_t tot, int n, const int32_t* sizes, int32_t precision) {
+    if (lane == BATCH_SOLVES) return 4 * up(tot * sizeof(double)) + up(sgn_batch_workspace_bytes(n, sizes, precision));
+    return 3 * up(tot * sizeof(double)) + up(sgn_batch_step_workspace_bytes(n, sizes, precision));
+}
+
 // Device bytes charged to an admitted request: its pooled block for a lane
-// request; for a batched 1D solve its fields and its share of the batching
-// lane's buffer (a group's buffer never exceeds the sum of its members' charges).
+// request; for a batched 1D solve or run its fields and its share of the
+// batching lane's buffer (a group's buffer never exceeds the sum of its
+// members' charges: every per-system term of the group's layout is in one
+// member's charge, and each member's charge holds the fixed terms once).
 size_t footprint(const sgn_request& r) {
-    if (batchable(r)) {
+    const int bl = batch_lane_of(r);
+    if (bl >= 0) {
         const int32_t n = r.grid.nx;
-        return 4 * up((size_t)n * sizeof(double)) + sgn_batch_workspace_bytes(1, &n, r.opts.precision);
+        return batch_group_bytes(bl, (size_t)n, 1, &n, r.opts.precision);
     }
     return pool_class(lane_layout(r).total);
 }
@@ -118,7 +133,7 @@ struct Req {
     sgn_request r{};
     std::vector<double> in;   // copied inputs: eta | grad_h | rhs | h | u0
     size_t fp = 0;
-    bool batch = false;
+    int batch = -1;           // batching lane, or -1: a worker lane
     sgn_result res{};         // read and written under the server mutex only
 };
 
@@ -227,6 +242,18 @@ struct Lane {
     std::thread th;
 };
 
+// A batching lane: its admitted requests, their charges, and its grow-only
+// device buffer and pinned staging (held until the server is destroyed).
+struct BatchLane {
+    Lane lane;
+    std::deque<Req*> q;
+    size_t charged = 0;
+    void* d_buf = nullptr;
+    size_t d_bytes = 0;
+    double* h_stage = nullptr;
+    size_t h_doubles = 0;
+};
+
 }  // namespace
 
 struct sgn_server {
@@ -239,44 +266,43 @@ struct sgn_server {
     std::condition_variable cv_done;   // waiters
     std::deque<Req*> queued;           // submitted, not yet admitted
     std::deque<Req*> lane_q;           // admitted, for the worker lanes
-    std::deque<Req*> batch_q;          // admitted, for the batching lane
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
     uint64_t next_id = 1;
     // Device memory accounting (under m).  lane_charged: pooled blocks of the
-    // admitted lane requests; batch_charged: footprints of the admitted batched
-    // solves.  The batching lane's grow-only buffer (d_batch_bytes) stays held
+    // admitted lane requests; a batching lane's `charged`: footprints of its
+    // admitted requests.  A batching lane's grow-only buffer (d_bytes) stays held
     // after its group finishes, so the commitment is
-    //   lane_charged + max(batch_charged, d_batch_bytes) <= budget,
+    //   lane_charged + sum over batching lanes of max(charged, d_bytes) <= budget,
     // and every block the server holds (pool blocks, cached or in use, and the
-    // batch buffer) is freed back to that bound before an allocation exceeds it.
-    size_t lane_charged = 0, batch_charged = 0;
+    // batch buffers) is freed back to that bound before an allocation exceeds it.
+    size_t lane_charged = 0;
     int64_t n_admitted = 0, n_completed = 0;
     int running = 0;                   // requests taken by a lane and not yet finished
     bool stopping = false;
     std::vector<Lane> lanes;
-    Lane blane;
+    BatchLane bl[BATCH_LANES];
     Pool pool;
-    // batching lane buffers (grow only)
-    void* d_batch = nullptr;
-    size_t d_batch_bytes = 0;
-    double* h_stage = nullptr;
-    size_t h_stage_doubles = 0;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+    // Device bytes committed with `add` more charged to lane `to` (-1: worker lanes).
+    size_t committed_locked(int to, size_t add) const {
+        size_t c = lane_charged + (to < 0 ? add : 0);
+        for (int b = 0; b < BATCH_LANES; ++b) c += std::max(bl[b].charged + (to == b ? add : 0), bl[b].d_bytes);
+        return c;
+    }
 
     // Admit queued requests in arrival order while they fit (caller holds m).
     void admit_locked() {
         bool any = false;
         while (!queued.empty()) {
             Req* q = queued.front();
-            const size_t after = q->batch ? lane_charged + std::max(batch_charged + q->fp, d_batch_bytes)
-                                          : lane_charged + q->fp + std::max(batch_charged, d_batch_bytes);
-            if (after > budget) break;
+            if (committed_locked(q->batch, q->fp) > budget) break;
             queued.pop_front();
-            (q->batch ? batch_charged : lane_charged) += q->fp;
+            (q->batch >= 0 ? bl[q->batch].charged : lane_charged) += q->fp;
             q->res.t_admit = now();
             ++n_admitted;
-            (q->batch ? batch_q : lane_q).push_back(q);
+            (q->batch >= 0 ? bl[q->batch].q : lane_q).push_back(q);
             any = true;
         }
         if (any) cv_work.notify_all();
@@ -292,7 +318,7 @@ struct sgn_server {
         q->res.status = st;
         q->res.t_done = now();
         q->res.done = 1;
-        (q->batch ? batch_charged : lane_charged) -= q->fp;
+        (q->batch >= 0 ? bl[q->batch].charged : lane_charged) -= q->fp;
         ++n_completed;
         --running;
         admit_locked();
@@ -302,10 +328,14 @@ struct sgn_server {
 
 
 
-    bool idle_locked() const { return queued.empty() && lane_q.empty() && batch_q.empty() && running == 0; }
+    bool idle_locked() const {
+        return queued.empty() && lane_q.empty() && bl[0].q.empty() && bl[1].q.empty() && running == 0;
+    }
 
     void lane_loop(Lane* L);
-    void batch_loop();
+    void batch_loop(int b);
+    sgn_status run_batch(int b, const std::vector<Req*>& group, std::vector<Outcome>& oc,
+                         std::vector<sgn_status>& qs);
     sgn_status run_lane(Lane* L, Req* q, Outcome* oc);
 };
 
@@ -392,24 +422,137 @@ namespace {
 bool same_batch_opts(const sgn_solve_opts& a, const sgn_solve_opts& b) {
     return a.precision == b.precision && a.tol == b.tol && a.max_iter == b.max_iter &&
            a.x0_is_guess == b.x0_is_guess && a.inner_tol == b.inner_tol && a.max_outer == b.max_outer &&
-           a.coeff_kind == b.coeff_kind;
+           a.coeff_kind == b.coeff_kind && a.guess == b.guess;
 }
 }  // namespace
 
-void sgn_server::batch_loop() {
+// One batched launch over `group` (all of lane b's kind, with the same options):
+// inputs packed in pinned memory and copied in at once, the batched call, the
+// outputs copied back at once.  Fills each member's outcome and status; returns
+// a status that applies to the whole group (staging or device failures).
+sgn_status sgn_server::run_batch(int b, const std::vector<Req*>& group, std::vector<Outcome>& oc,
+                                 std::vector<sgn_status>& qs) {
+    BatchLane& B = bl[b];
+    const int n = (int)group.size();
+    const bool steps = b == BATCH_STEPS;
+    std::vector<int32_t> sizes(n), nsteps(n);
+    std::vector<double> periods(n), dts(n);
+    size_t tot = 0;
+    for (int i = 0; i < n; ++i) {
+        const sgn_request& r = group[i]->r;
+        sizes[i] = r.grid.nx;
+        periods[i] = r.grid.Lx;
+        dts[i] = r.dt;
+        nsteps[i] = r.nsteps;
+        tot += (size_t)sizes[i];
+    }
+    const sgn_solve_opts opts = group[0]->r.opts;
+    const size_t need = batch_group_bytes(b, tot, n, sizes.data(), opts.precision);
+    if (need > B.d_bytes) {
+        // the group's charges cover `need` (each member was charged its fields and
+        // a one-system workspace, at least its share of the group's)
+        void* nb = pool.regrow(B.d_buf, B.d_bytes, need);
+        std::lock_guard<std::mutex> g(m);
+        B.d_buf = nb;
+        B.d_bytes = nb ? need : 0;
+        if (!nb) return SGN_ENOMEM;
+    }
+    const int nf = steps ? 3 : 4;   // staged fields: h | eta | u, or eta | h_x | rhs | u
+    if (nf * tot > B.h_doubles) {
+        if (B.h_stage) (void)hipHostFree(B.h_stage);
+        B.h_stage = nullptr;
+        B.h_doubles = 0;
+        if (hipHostMalloc((void**)&B.h_stage, nf * tot * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return SGN_ENOMEM;
+        B.h_doubles = nf * tot;
+    }
+    double* hs[4];
+    for (int f = 0; f < nf; ++f) hs[f] = B.h_stage + f * tot;
+    size_t o = 0;
+    for (int i = 0; i < n; ++i) {
+        const sgn_request& r = group[i]->r;
+        const size_t ni = (size_t)sizes[i], nb = ni * sizeof(double);
+        if (steps) {
+            std::memcpy(hs[0] + o, r.h_h, nb);
+            std::memcpy(hs[1] + o, r.h_eta, nb);
+            std::memcpy(hs[2] + o, r.h_u0, nb);
+        } else {
+            std::memcpy(hs[0] + o, r.h_eta, nb);
+            std::memcpy(hs[1] + o, r.h_grad_h, nb);
+            std::memcpy(hs[2] + o, r.h_rhs, nb);
+            if (opts.x0_is_guess)
+                std::memcpy(hs[3] + o, r.h_u0, nb);
+            else
+                std::memset(hs[3] + o, 0, nb);
+        }
+        o += ni;
+    }
+    double* d = static_cast<double*>(B.d_buf);
+    const size_t stride = up(tot * sizeof(double)) / sizeof(double);
+    double* ds[4];
+    for (int f = 0; f < nf; ++f) ds[f] = d + f * stride;
+    void* dws = d + nf * stride;
+    hipStream_t stream = B.lane.stream;
+    bool ok = true;
+    for (int f = 0; f < nf && ok; ++f)
+        ok = hipMemcpyAsync(ds[f], hs[f], tot * sizeof(double), hipMemcpyHostToDevice, stream) == hipSuccess;
+    if (!ok) return SGN_EDEVICE;
+    sgn_status bst;
+    std::vector<sgn_solve_info> info(steps ? 0 : n);
+    std::vector<sgn_step_info> sinfo(steps ? n : 0);
+    std::vector<sgn_status> sst(steps ? n : 0);
+    if (steps)
+        bst = sgn_batch_step_rk4(B.lane.ctx, n, sizes.data(), periods.data(), dts.data(), nsteps.data(), ds[0], ds[1],
+                                 ds[2], &opts, sinfo.data(), sst.data(), dws);
+    else
+        bst = sgn_batch_solve(B.lane.ctx, n, sizes.data(), periods.data(), ds[0], ds[1], ds[2], ds[3], &opts,
+                              info.data(), dws);
+    if (bst != SGN_OK && bst != SGN_ENOCONV && bst != SGN_EDOMAIN) return bst;
+    // outputs: u (solves); eta and u (runs)
+    for (int f = steps ? 1 : 3; f < nf && ok; ++f)
+        ok = hipMemcpyAsync(hs[f], ds[f], tot * sizeof(double), hipMemcpyDeviceToHost, stream) == hipSuccess;
+    if (!ok || hipStreamSynchronize(stream) != hipSuccess) return SGN_EDEVICE;
+    o = 0;
+    for (int i = 0; i < n; ++i) {
+        const sgn_request& r = group[i]->r;
+        const size_t nb = (size_t)sizes[i] * sizeof(double);
+        oc[i].batched = 1;
+        oc[i].batch_size = n;
+        if (steps) {
+            oc[i].iters = sinfo[i].iters;
+            oc[i].solves = sinfo[i].solves;
+            qs[i] = sst[i];
+            if (sst[i] != SGN_EDOMAIN) {
+                std::memcpy(r.h_u_out, hs[2] + o, nb);
+                if (r.h_eta_out) std::memcpy(r.h_eta_out, hs[1] + o, nb);
+            }
+        } else {
+            oc[i].iters = info[i].iters;
+            oc[i].solves = 1;
+            oc[i].relres = info[i].relres;
+            qs[i] = !(info[i].relres == info[i].relres) ? SGN_EDOMAIN : !info[i].converged ? SGN_ENOCONV : SGN_OK;
+            std::memcpy(r.h_u_out, hs[3] + o, nb);
+        }
+        o += (size_t)sizes[i];
+    }
+    return SGN_OK;
+}
+
+void sgn_server::batch_loop(int b) {
     (void)hipSetDevice(device);
+    BatchLane& B = bl[b];
     for (;;) {
         std::vector<Req*> group;
         {
             std::unique_lock<std::mutex> g(m);
-            cv_work.wait(g, [&] { return !batch_q.empty() || (stopping && idle_locked()); });
-            if (batch_q.empty()) return;
-            // every admitted 1D solve with the options of the oldest one joins this launch
-            const sgn_solve_opts key = batch_q.front()->r.opts;
-            for (auto it = batch_q.begin(); it != batch_q.end() && (int)group.size() < max_batch;) {
+            cv_work.wait(g, [&] { return !B.q.empty() || (stopping && idle_locked()); });
+            if (B.q.empty()) return;
+            // every admitted request of the lane with the options of the oldest one joins this launch
+            const sgn_solve_opts key = B.q.front()->r.opts;
+            for (auto it = B.q.begin(); it != B.q.end() && (int)group.size() < max_batch;) {
                 if (same_batch_opts((*it)->r.opts, key)) {
                     group.push_back(*it);
-                    it = batch_q.erase(it);
+                    it = B.q.erase(it);
                 } else {
                     ++it;
                 }
@@ -418,101 +561,10 @@ void sgn_server::batch_loop() {
             for (Req* q : group) q->res.t_start = ts;
             running += (int)group.size();
         }
-        const int n = (int)group.size();
-        std::vector<int32_t> sizes(n);
-        std::vector<double> periods(n);
-        size_t tot = 0;
-        for (int i = 0; i < n; ++i) {
-            sizes[i] = group[i]->r.grid.nx;
-            periods[i] = group[i]->r.grid.Lx;
-            tot += (size_t)sizes[i];
-        }
-        const sgn_solve_opts opts = group[0]->r.opts;
-        const size_t wsb = sgn_batch_workspace_bytes(n, sizes.data(), opts.precision);
-        const size_t need = 4 * up(tot * sizeof(double)) + up(wsb);
-        sgn_status st = SGN_OK;
-        if (need > d_batch_bytes) {
-            // the group's charges cover `need` (each member was charged its fields and
-            // a one-system workspace, at least its share of the group's)
-            void* nb = pool.regrow(d_batch, d_batch_bytes, need);
-            std::lock_guard<std::mutex> g(m);
-            d_batch = nb;
-            d_batch_bytes = nb ? need : 0;
-            if (!nb) st = SGN_ENOMEM;
-        }
-        if (st == SGN_OK && 4 * tot > h_stage_doubles) {
-            if (h_stage) (void)hipHostFree(h_stage);
-            h_stage = nullptr;
-            h_stage_doubles = 0;
-            if (hipHostMalloc((void**)&h_stage, 4 * tot * sizeof(double), hipHostMallocDefault) == hipSuccess)
-                h_stage_doubles = 4 * tot;
-            else
-                st = SGN_ENOMEM;
-        }
-        std::vector<sgn_solve_info> info(n);
-        sgn_status bst = SGN_OK;
-        if (st == SGN_OK) {
-            // pack eta | h_x | rhs | u0 in pinned memory, one copy in, one copy out
-            double* he = h_stage;
-            double* hg = he + tot;
-            double* hb = hg + tot;
-            double* hu = hb + tot;
-            size_t o = 0;
-            for (int i = 0; i < n; ++i) {
-                const sgn_request& r = group[i]->r;
-                const size_t ni = (size_t)sizes[i];
-                std::memcpy(he + o, r.h_eta, ni * sizeof(double));
-                std::memcpy(hg + o, r.h_grad_h, ni * sizeof(double));
-                std::memcpy(hb + o, r.h_rhs, ni * sizeof(double));
-                if (opts.x0_is_guess)
-                    std::memcpy(hu + o, r.h_u0, ni * sizeof(double));
-                else
-                    std::memset(hu + o, 0, ni * sizeof(double));
-                o += ni;
-            }
-            double* d = static_cast<double*>(d_batch);
-            const size_t stride = up(tot * sizeof(double)) / sizeof(double);
-            double *de = d, *dg = d + stride, *db = d + 2 * stride, *du = d + 3 * stride;
-            void* dws = d + 4 * stride;
-            bool ok = hipMemcpyAsync(de, he, tot * sizeof(double), hipMemcpyHostToDevice, blane.stream) == hipSuccess &&
-                      hipMemcpyAsync(dg, hg, tot * sizeof(double), hipMemcpyHostToDevice, blane.stream) == hipSuccess &&
-                      hipMemcpyAsync(db, hb, tot * sizeof(double), hipMemcpyHostToDevice, blane.stream) == hipSuccess &&
-                      hipMemcpyAsync(du, hu, tot * sizeof(double), hipMemcpyHostToDevice, blane.stream) == hipSuccess;
-            if (!ok) st = SGN_EDEVICE;
-            if (st == SGN_OK) {
-                bst = sgn_batch_solve(blane.ctx, n, sizes.data(), periods.data(), de, dg, db, du, &opts, info.data(),
-                                      dws);
-                if (bst != SGN_OK && bst != SGN_ENOCONV && bst != SGN_EDOMAIN) st = bst;
-            }
-            if (st == SGN_OK) {
-                if (hipMemcpyAsync(hu, du, tot * sizeof(double), hipMemcpyDeviceToHost, blane.stream) != hipSuccess ||
-                    hipStreamSynchronize(blane.stream) != hipSuccess)
-                    st = SGN_EDEVICE;
-            }
-            if (st == SGN_OK) {
-                o = 0;
-                for (int i = 0; i < n; ++i) {
-                    std::memcpy(group[i]->r.h_u_out, hu + o, (size_t)sizes[i] * sizeof(double));
-                    o += (size_t)sizes[i];
-                }
-            }
-        }
-        for (int i = 0; i < n; ++i) {
-            Outcome oc;
-            oc.batched = 1;
-            oc.batch_size = n;
-            sgn_status qs = st;
-            if (st == SGN_OK) {
-                oc.iters = info[i].iters;
-                oc.solves = 1;
-                oc.relres = info[i].relres;
-                if (!(info[i].relres == info[i].relres))
-                    qs = SGN_EDOMAIN;
-                else if (!info[i].converged)
-                    qs = SGN_ENOCONV;
-            }
-            finish(group[i], qs, oc);
-        }
+        std::vector<Outcome> oc(group.size());
+        std::vector<sgn_status> qs(group.size(), SGN_OK);
+        const sgn_status st = run_batch(b, group, oc, qs);
+        for (size_t i = 0; i < group.size(); ++i) finish(group[i], st == SGN_OK ? qs[i] : st, oc[i]);
     }
 }
 
@@ -542,20 +594,21 @@ sgn_status sgn_server_create(sgn_server** out, int device, const sgn_server_opts
         return sgn_create(&L.ctx, device, L.stream) == SGN_OK;
     };
     s->lanes.resize(nl);
-    bool ok = make_lane(s->blane);
+    bool ok = true;
+    for (auto& B : s->bl) ok = ok && make_lane(B.lane);
     for (auto& L : s->lanes) ok = ok && make_lane(L);
     if (!ok) {
-        for (auto& L : s->lanes) {
+        auto drop = [](Lane& L) {
             if (L.ctx) sgn_destroy(L.ctx);
             if (L.stream) (void)hipStreamDestroy(L.stream);
-        }
-        if (s->blane.ctx) sgn_destroy(s->blane.ctx);
-        if (s->blane.stream) (void)hipStreamDestroy(s->blane.stream);
+        };
+        for (auto& L : s->lanes) drop(L);
+        for (auto& B : s->bl) drop(B.lane);
         return SGN_EDEVICE;
     }
     sgn_server* sp = s.get();
     for (auto& L : s->lanes) L.th = std::thread([sp, &L] { sp->lane_loop(&L); });
-    s->blane.th = std::thread([sp] { sp->batch_loop(); });
+    for (int b = 0; b < BATCH_LANES; ++b) s->bl[b].lane.th = std::thread([sp, b] { sp->batch_loop(b); });
     *out = s.release();
     return SGN_OK;
 }
@@ -569,15 +622,18 @@ void sgn_server_destroy(sgn_server* s) {
     }
     for (auto& L : s->lanes)
         if (L.th.joinable()) L.th.join();
-    if (s->blane.th.joinable()) s->blane.th.join();
+    for (auto& B : s->bl)
+        if (B.lane.th.joinable()) B.lane.th.join();
     for (auto& L : s->lanes) {
         sgn_destroy(L.ctx);
         (void)hipStreamDestroy(L.stream);
     }
-    sgn_destroy(s->blane.ctx);
-    (void)hipStreamDestroy(s->blane.stream);
-    s->pool.free_extra(s->d_batch, s->d_batch_bytes);
-    if (s->h_stage) (void)hipHostFree(s->h_stage);
+    for (auto& B : s->bl) {
+        sgn_destroy(B.lane.ctx);
+        (void)hipStreamDestroy(B.lane.stream);
+        s->pool.free_extra(B.d_buf, B.d_bytes);
+        if (B.h_stage) (void)hipHostFree(B.h_stage);
+    }
     s->pool.release();
     delete s;
 }
@@ -590,7 +646,7 @@ sgn_status sgn_server_submit(sgn_server* s, const sgn_request* req, uint64_t* id
     q->r = *req;
     q->fp = footprint(*req);
     if (q->fp > s->budget) return SGN_ENOMEM;
-    q->batch = batchable(*req);
+    q->batch = batch_lane_of(*req);
     // copy the inputs so the caller may reuse its arrays at once
     const sgn_grid& g = req->grid;
     const size_t N = npts(g), dN = (size_t)g.dim * N;
@@ -663,7 +719,7 @@ sgn_status sgn_server_stats(sgn_server* s, int64_t* queued, int64_t* admitted, i
     if (queued) *queued = (int64_t)s->queued.size();
     if (admitted) *admitted = s->n_admitted;
     if (completed) *completed = s->n_completed;
-    if (bytes_in_use) *bytes_in_use = s->lane_charged + s->batch_charged;
+    if (bytes_in_use) *bytes_in_use = s->lane_charged + s->bl[0].charged + s->bl[1].charged;
     if (bytes_held) *bytes_held = pool_held;
     if (budget) *budget = s->budget;
     return SGN_OK;

@@ -131,6 +131,10 @@ _SIGS = {
                               ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "sgn_batch_solve": (_S, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_D), _P, _P, _P, _P,
                              ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
+    "sgn_batch_step_workspace_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I]),
+    "sgn_batch_step_rk4": (_S, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                ctypes.POINTER(_I), _P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(StepInfo),
+                                ctypes.POINTER(_S), _P]),
     "sgn_state_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
     "sgn_state_create": (_S, [_P, ctypes.POINTER(Grid), _P, _P, _I, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "sgn_state_destroy": (None, [_P]),
@@ -231,6 +235,31 @@ class SolveResult:
     flat: bool
 
 
+class _BatchResults:
+    """Per-system results of a batched solve, converted from the C records when read."""
+
+    def __init__(self, infos, n):
+        self._infos = infos
+        self._n = n
+
+    def __len__(self):
+        return self._n
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[k] for k in range(*i.indices(self._n))]
+        if i < 0:
+            i += self._n
+        if not 0 <= i < self._n:
+            raise IndexError(i)
+        r = self._infos[i]
+        return SolveResult(r.iters, r.outer_iters, bool(r.converged), r.relres, r.coeffs.sigma, r.coeffs.alpha,
+                           r.coeffs.kappa_ub, bool(r.coeffs.flat))
+
+    def __iter__(self):
+        return (self[k] for k in range(self._n))
+
+
 class Context:
     """An sgn_ctx bound to a GPU and to the PyTorch stream current at each call."""
 
@@ -278,7 +307,7 @@ class Context:
     # -- kernel timing ---------------------------------------------------------
     KERNEL_KINDS = ("pcg_c1", "pcg_r1", "pcg_c2", "pcg_init", "rows", "cols",
                     "pcg_c1_f32", "pcg_r1_f32", "pcg_c2_f32", "pcg_init_f32", "batch",
-                    "rhs_rows_fwd", "rhs_cols", "rhs_rows_inv", "rhs_flux")
+                    "rhs_rows_fwd", "rhs_cols", "rhs_rows_inv", "rhs_flux", "batch_step")
 
     def profile_begin(self):
         self._sync_stream()
@@ -393,19 +422,23 @@ class Context:
                     raise_on_error: bool = True):
         """Independent 1D solves in one launch (sgn_batch_solve).  The fields are
         packed 1D float64 tensors (system i at offset sum(sizes[:i])).  Returns
-        (u, [SolveResult], status)."""
+        (u, results, status); results is a sequence of SolveResult, one per system,
+        each built when it is read."""
+        import numpy as np
         self._sync_stream()
-        nitems = len(sizes)
-        total = int(sum(int(v) for v in sizes))
-        if len(periods) != nitems:
+        n_np = np.ascontiguousarray(sizes, dtype=np.int32)
+        L_np = np.ascontiguousarray(periods, dtype=np.float64)
+        nitems = int(n_np.shape[0])
+        total = int(n_np.sum())
+        if L_np.shape[0] != nitems:
             raise ValueError("sizes and periods differ in length")
         o = opts if opts is not None else solve_opts()
         if u is None:
             u = torch.zeros(total, dtype=torch.float64, device=self.device)
-        n = (_I * nitems)(*[int(v) for v in sizes])
-        L = (_D * nitems)(*[float(v) for v in periods])
+        n = n_np.ctypes.data_as(ctypes.POINTER(_I))
+        L = L_np.ctypes.data_as(ctypes.POINTER(_D))
         infos = (SolveInfo * max(nitems, 1))()
-        nb = batch_workspace_bytes(sizes, o.precision)
+        nb = int(_lib.sgn_batch_workspace_bytes(nitems, n, o.precision))
         if nitems and nb == 0:
             raise SgnError(EUNSUPPORTED, "batch sizes must be powers of two in [2, 8192]")
         ws = self._ws.get("batch")
@@ -415,11 +448,44 @@ class Context:
         st = _lib.sgn_batch_solve(self._h, nitems, n, L, _ptr(eta, (total,), "eta"), _ptr(grad_h, (total,), "grad_h"),
                                   _ptr(rhs, (total,), "rhs"), _ptr(u, (total,), "u"), ctypes.byref(o), infos,
                                   _P(ws.data_ptr()))
-        res = [SolveResult(i.iters, i.outer_iters, bool(i.converged), i.relres, i.coeffs.sigma, i.coeffs.alpha,
-                           i.coeffs.kappa_ub, bool(i.coeffs.flat)) for i in list(infos)[:nitems]]
         if raise_on_error:
             self._check(st)
-        return u, res, st
+        return u, _BatchResults(infos, nitems), st
+
+    def batch_step_rk4(self, sizes, periods, dts, nsteps, h, eta, u, opts: SolveOpts | None = None,
+                       raise_on_error: bool = True):
+        """Independent 1D RK4 runs in one launch (sgn_batch_step_rk4).  h, eta and
+        u are packed 1D float64 tensors (state i at offset sum(sizes[:i])); eta
+        and u are advanced in place.  dts and nsteps: one per state.  Returns
+        (infos, statuses, status): a StepInfo and an sgn_status per state."""
+        import numpy as np
+        self._sync_stream()
+        n_np = np.ascontiguousarray(sizes, dtype=np.int32)
+        nitems = int(n_np.shape[0])
+        L_np = np.ascontiguousarray(periods, dtype=np.float64)
+        dt_np = np.ascontiguousarray(np.broadcast_to(np.asarray(dts, dtype=np.float64), (nitems,)))
+        ns_np = np.ascontiguousarray(np.broadcast_to(np.asarray(nsteps, dtype=np.int32), (nitems,)))
+        if L_np.shape[0] != nitems:
+            raise ValueError("sizes and periods differ in length")
+        total = int(n_np.sum())
+        o = opts if opts is not None else solve_opts()
+        n = n_np.ctypes.data_as(ctypes.POINTER(_I))
+        infos = (StepInfo * max(nitems, 1))()
+        stats = (_S * max(nitems, 1))()
+        nb = int(_lib.sgn_batch_step_workspace_bytes(nitems, n, o.precision))
+        if nitems and nb == 0:
+            raise SgnError(EUNSUPPORTED, "batch sizes must be powers of two in [2, 8192]")
+        ws = self._ws.get("batch_step")
+        if ws is None or ws.numel() < nb:
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+            self._ws["batch_step"] = ws
+        st = _lib.sgn_batch_step_rk4(self._h, nitems, n, L_np.ctypes.data_as(ctypes.POINTER(_D)),
+                                     dt_np.ctypes.data_as(ctypes.POINTER(_D)), ns_np.ctypes.data_as(ctypes.POINTER(_I)),
+                                     _ptr(h, (total,), "h"), _ptr(eta, (total,), "eta"), _ptr(u, (total,), "u"),
+                                     ctypes.byref(o), infos, stats, _P(ws.data_ptr()))
+        if raise_on_error:
+            self._check(st)
+        return list(infos)[:nitems], [int(x) for x in stats[:nitems]], st
 
     def rhs(self, g, eta, h, grad_h, u, eta_t=None, U_t=None):
         """(eta_t, U_t) = f(w, p) (sgn_rhs)."""

@@ -51,6 +51,22 @@ def test_version_and_workspace_sizes(lib):
     assert 100e6 < big < 1e9
 
 
+def test_batch_workspace_sizes(lib):
+    """Batched solves and RK4 runs: a workspace grows with the systems it holds
+    (a run holds about 40 doubles per point), and an unsupported size gives 0."""
+    from paper_2506_16045_amd import sgn
+    for fn in (sgn._lib.sgn_batch_workspace_bytes, sgn._lib.sgn_batch_step_workspace_bytes):
+        for prec in (sgn.FP64, sgn.MIXED):
+            one = (ctypes.c_int32 * 1)(8192)
+            many = (ctypes.c_int32 * 3)(256, 8192, 2)
+            a, b = fn(1, one, prec), fn(3, many, prec)
+            assert 0 < a < b
+            assert fn(1, (ctypes.c_int32 * 1)(16384), prec) == 0
+            assert fn(1, (ctypes.c_int32 * 1)(384), prec) == 0
+    step = sgn._lib.sgn_batch_step_workspace_bytes(1, (ctypes.c_int32 * 1)(8192), sgn.MIXED)
+    assert 30 * 8 * 8192 < step < 50 * 8 * 8192
+
+
 @pytest.mark.parametrize("dim,nx,ny", [(1, 3, 1), (1, 32768, 1), (2, 64, 1), (2, 8192, 8), (2, 64, 2048), (3, 8, 8), (1, 0, 1)])
 def test_unsupported_grids_report_zero_workspace(dim, nx, ny):
     from paper_2506_16045_amd import sgn
