@@ -144,6 +144,31 @@ def test_solve_A_split_form_matches_assembled_symbol_solve(rng):
     assert np.max(np.abs(z1 - z2)) < 1e-13 * np.max(np.abs(z1)) * 50
 
 
+@pytest.mark.parametrize("sigma,alpha", [(1e-4, 1.0), (1e-6, 3.0), (2.0, 1e-3)])
+def test_solve_A_plane_waves_in_the_stiff_regime(sigma, alpha):
+    """A = sigma I - alpha grad div (Def:A) maps a plane wave a cos(k.x) to
+    (sigma + alpha |k|^2) a cos(k.x) when a is along k and to sigma a cos(k.x)
+    when a is across k.  Plane waves written out in closed form (no FFT) pin
+    A^{-1} mode by mode where alpha |k|^2 / sigma reaches 1e10.  Rounding of the
+    input of size eps |r| in any direction is amplified by 1/sigma (the
+    conditioning), which the bound allows; across k the solution itself is r /
+    sigma, so there the bound is 1e-12 relative, which a solve of the assembled
+    2x2 symbol misses by orders of magnitude (it loses the digits of sigma)."""
+    g = I.grid2d(32, 64, 3.0, 5.0)
+    X, Y = I.coords(g)
+    for mx, my in ((1, 0), (0, 3), (7, -5), (15, 31), (-11, 20)):
+        kx, ky = 2 * math.pi * mx / g.Lx, 2 * math.pi * my / g.Ly
+        c = np.cos(kx * X + ky * Y)
+        kk = math.hypot(kx, ky)
+        along, across = np.array([kx, ky]) / kk, np.array([-ky, kx]) / kk
+        for a, lam in ((along, sigma + alpha * kk * kk), (across, sigma)):
+            r = np.stack([a[0] * c, a[1] * c])
+            z = op.solve_A(sigma, alpha, r, g)
+            exact = r / lam
+            bound = 1e-12 * np.max(np.abs(exact)) + 1000 * np.finfo(float).eps * np.max(np.abs(r)) / sigma
+            assert np.max(np.abs(z - exact)) <= bound, (mx, my, lam)
+
+
 @pytest.mark.parametrize("g", [I.grid1d(32, 2.0), I.grid2d(8, 8, 1.0, 1.0)], ids=["1d", "2d"])
 @pytest.mark.parametrize("flat", [True, False])
 def test_theorem_4_1_eigenvalue_interval(g, flat, rng):
