@@ -1704,12 +1704,18 @@ namespace sgn {
 // (weight 1 at kx = 0 and nx/2, 2 elsewhere) divided by nx ny.
 // ---------------------------------------------------------------------------
 
+// The kernels below take an optional stop flag (the done flag of the solve's
+// scalars): when it is set they return at once, so a host that issues several
+// Arnoldi steps ahead pays little for the steps after the cycle has ended.
+__device__ __forceinline__ bool gmres_stopped(const SolveScal* stop) { return stop && stop->done; }
+
 // Per-block partials of <w, V_i> for i < nv (V_i = V + i * vstride):
 // part[block * nv + i].
 template <int D>
 __global__ void __launch_bounds__(256) k_S_multidot(int nx, int ny, size_t NS, const cpx<double>* __restrict__ w,
                                                     const cpx<double>* __restrict__ V, size_t vstride, int nv,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, const SolveScal* stop) {
+    if (gmres_stopped(stop)) return;
     __shared__ double red[16 * 8];
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (int i0 = 0; i0 < nv; i0 += 8) {
@@ -1738,7 +1744,9 @@ __global__ void __launch_bounds__(256) k_S_multidot(int nx, int ny, size_t NS, c
 
 // out[i] = scale * sum over blocks of part[b * nv + i] (fixed order), one block.
 __global__ void __launch_bounds__(256) k_S_multidot_finish(const double* __restrict__ part, int nblocks, int nv,
-                                                           double scale, double* __restrict__ out) {
+                                                           double scale, double* __restrict__ out,
+                                                           const SolveScal* stop) {
+    if (gmres_stopped(stop)) return;
     __shared__ double red[16];
     for (int i = 0; i < nv; ++i) {
         double v[1] = {0.0};
@@ -1748,9 +1756,13 @@ __global__ void __launch_bounds__(256) k_S_multidot_finish(const double* __restr
     }
 }
 
-// w += sum_i coef[i] V_i (coef in device memory, nv <= 65), over n doubles.
+// w += sign sum_i coef[i] V_i (coef in device memory), over n doubles; nv_dev,
+// when set, gives the count in device memory instead of nv.
 __global__ void k_S_multiaxpy(size_t n, double* __restrict__ w, const double* __restrict__ V, size_t vstride_d,
-                              int nv, const double* __restrict__ coef, double sign) {
+                              int nv, const double* __restrict__ coef, double sign, const SolveScal* stop,
+                              const int* nv_dev) {
+    if (gmres_stopped(stop)) return;
+    if (nv_dev) nv = *nv_dev;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double s = 0.0;
@@ -1762,7 +1774,8 @@ __global__ void k_S_multiaxpy(size_t n, double* __restrict__ w, const double* __
 // z = A^{-1} v on S fields (Def:A, section 6.1).
 template <int D>
 __global__ void k_S_precond(int nx, int ny, size_t NS, double tpx, double tpy, double sig, double alp,
-                            const cpx<double>* __restrict__ v, cpx<double>* __restrict__ z) {
+                            const cpx<double>* __restrict__ v, cpx<double>* __restrict__ z, const SolveScal* stop) {
+    if (gmres_stopped(stop)) return;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < NS; idx += stride) {
         const int kxi = (int)(idx / ny), kyi = (int)(idx - (size_t)kxi * ny);
@@ -1774,6 +1787,143 @@ __global__ void k_S_precond(int nx, int ny, size_t NS, double tpx, double tpy, d
         precond_mode<double, D>(kx, ky, sig, alp, r, zz);
 #pragma unroll
         for (int c = 0; c < D; ++c) z[c * NS + idx] = zz[c];
+    }
+}
+
+// y = scale[0] x over n doubles (the scale in device memory).
+__global__ void k_S_scale(size_t n, const double* __restrict__ scale, const double* __restrict__ x,
+                          double* __restrict__ y, const SolveScal* stop) {
+    if (gmres_stopped(stop)) return;
+    const double a = *scale;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = a * x[i];
+}
+
+// State of a restarted GMRES(m) solve kept on the device: the Hessenberg
+// matrix of the running cycle reduced by Givens rotations, and the stop logic,
+// so that the host reads it back once per few Arnoldi steps.
+struct GmresCtl {
+    double thr;       // tol ||b||
+    double bnorm;
+    double beta;      // ||r|| at the start of the running cycle
+    double relres;    // beta / ||b||
+    double scale;     // normalisation of the next basis vector (1 / beta, then 1 / h_{j+1,j})
+    int jd;           // columns of the running cycle
+    int iters, max_iter;
+    int final_;       // 1: no further cycle (converged, max_iter reached or bad data)
+    int conv, status; // status -2: non-finite data
+};
+
+// Hessenberg storage of a cycle of m steps: H (m + 1) x m by rows, cs, sn (m),
+// g (m + 1), y (m) in one array.
+__host__ __device__ inline size_t gmres_hess_doubles(int m) {
+    return (size_t)(m + 1) * m + 2 * (size_t)m + (size_t)(m + 1) + (size_t)m;
+}
+
+__global__ void k_gmres_init(GmresCtl* ctl, double thr, double bnorm, int max_iter) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    ctl->thr = thr;
+    ctl->bnorm = bnorm;
+    ctl->beta = 0.0;
+    ctl->relres = 0.0;
+    ctl->scale = 1.0;
+    ctl->jd = 0;
+    ctl->iters = 0;
+    ctl->max_iter = max_iter;
+    ctl->final_ = 0;
+    ctl->conv = 0;
+    ctl->status = 0;
+}
+
+// Open a cycle: the operator passes run again (done = 0) unless the solve is over.
+__global__ void k_gmres_open(const GmresCtl* ctl, SolveScal* sc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) sc->done = ctl->final_ ? 1 : 0;
+}
+
+// Start of a cycle from rr = ||r||^2 of the true residual (in V_0): the stop
+// tests of the restart (||r|| <= thr: converged; max_iter reached; non-finite),
+// else g = (beta, 0, ...) and V_0 is scaled by 1 / beta.
+__global__ void k_gmres_begin(GmresCtl* ctl, SolveScal* sc, const double* __restrict__ rr, double* __restrict__ hs,
+                              int m) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double beta = sqrt(fmax(*rr, 0.0));
+    ctl->beta = beta;
+    ctl->relres = beta / ctl->bnorm;
+    ctl->jd = 0;
+    bool stop = false;
+    if (!isfinite(beta)) {
+        ctl->status = -2;
+        stop = true;
+    } else if (beta <= ctl->thr) {
+        ctl->conv = 1;
+        stop = true;
+    } else if (ctl->iters >= ctl->max_iter) {
+        stop = true;
+    }
+    if (stop) {
+        ctl->final_ = 1;
+        sc->done = 1;
+        return;
+    }
+    double* g = hs + (size_t)(m + 1) * m + 2 * (size_t)m;
+    for (int i = 0; i <= m; ++i) g[i] = 0.0;
+    g[0] = beta;
+    ctl->scale = 1.0 / beta;
+    sc->done = 0;
+}
+
+// Arnoldi step j: column j of H from the two Gram-Schmidt passes (h1 + h2) and
+// h_{j+1,j} = ||w||, the earlier rotations applied to it, the new rotation
+// that zeroes h_{j+1,j}, and the residual estimate |g_{j+1}|; the cycle ends
+// (done) when that estimate reaches thr, at max_iter, or after step m - 1.
+__global__ void k_gmres_givens(int j, int m, const double* __restrict__ coef, double* __restrict__ hs,
+                               GmresCtl* ctl, SolveScal* sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || sc->done) return;
+    double* H = hs;
+    double* cs = hs + (size_t)(m + 1) * m;
+    double* sn = cs + m;
+    double* g = sn + m;
+    const double* h1 = coef;
+    const double* h2 = coef + (m + 1);
+    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h1[i] + h2[i];
+    const double hn = sqrt(fmax(coef[2 * (m + 1)], 0.0));
+    ctl->iters += 1;
+    if (!isfinite(hn)) {
+        ctl->status = -2;
+        ctl->final_ = 1;
+        sc->done = 1;
+        return;
+    }
+    H[(size_t)(j + 1) * m + j] = hn;
+    ctl->scale = hn != 0.0 ? 1.0 / hn : 1.0;
+    for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+    }
+    const double hjj = H[(size_t)j * m + j];
+    const double den = hypot(hjj, hn);
+    cs[j] = hjj / den;
+    sn[j] = hn / den;
+    H[(size_t)j * m + j] = den;
+    H[(size_t)(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    ctl->jd = j + 1;
+    if (fabs(g[j + 1]) <= ctl->thr || ctl->iters >= ctl->max_iter || j + 1 >= m) sc->done = 1;
+}
+
+// y = R^{-1} g over the cycle's jd columns (back substitution).
+__global__ void k_gmres_backsolve(int m, const GmresCtl* ctl, double* __restrict__ hs) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double* H = hs;
+    const double* g = hs + (size_t)(m + 1) * m + 2 * (size_t)m;
+    double* y = hs + (size_t)(m + 1) * m + 2 * (size_t)m + (m + 1);
+    const int jd = ctl->status == 0 ? ctl->jd : 0;
+    for (int i = jd - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k = i + 1; k < jd; ++k) t -= H[(size_t)i * m + k] * y[k];
+        y[i] = t / H[(size_t)i * m + i];
     }
 }
 

@@ -1220,9 +1220,12 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
 // Gram-Schmidt with one reorthogonalisation (CGS2: two block dot products and
 // two block updates per step, all against the contiguous basis), which equals
 // modified Gram-Schmidt in exact arithmetic; the small Hessenberg least-squares
-// problem (Givens rotations, back substitution) runs on the host after one
-// readback of the step's coefficients.  Only V_0..V_m are stored: the update
-// x += A^{-1} (V y) uses the linearity of A^{-1} instead of keeping Z_j.
+// problem (Givens rotations, back substitution) and the stop tests run in
+// one-thread kernels on device-resident state, so the host issues Arnoldi steps
+// in chunks and reads the state back once per chunk (check_every steps), not
+// once per step; the steps issued after a cycle has ended return at once.
+// Only V_0..V_m are stored: the update x += A^{-1} (V y) uses the linearity of
+// A^{-1} instead of keeping Z_j.
 // ---------------------------------------------------------------------------
 sgn_status batch_staging(sgn_ctx* ctx, size_t bytes);
 template <int D>
@@ -1231,13 +1234,16 @@ template <int D>
 sgn_status from_S_d(sgn_ctx* ctx, const Dims& d, const cpx<double>* Ssrc, cpx<double>* H, double* f);
 
 constexpr int GMRES_MAX_RESTART = 256;
+static_assert(sizeof(GmresCtl) <= 512, "GMRES state readback");
 constexpr int GMRES_DOT_BLOCKS = 512;
 
 struct GmresBufs {
     cpx<double>* bh;     // b in S
     cpx<double>* V;      // (m + 1) basis vectors of D * NS modes
     double* part;        // per-block partial dot products
-    double* coef;        // device coefficients: h (m + 1), h2 (m + 1), ||w||^2, y (m)
+    double* coef;        // device coefficients: h (m + 1), h2 (m + 1), ||w||^2
+    double* hs;          // Hessenberg matrix, rotations, g and y of a cycle (gmres_hess_doubles)
+    GmresCtl* ctl;
 };
 GmresBufs carve_gmres(Carve& cv, const Dims& d, int m) {
     GmresBufs g;
@@ -1245,6 +1251,8 @@ GmresBufs carve_gmres(Carve& cv, const Dims& d, int m) {
     g.V = cv.take<cpx<double>>((size_t)(m + 1) * d.D * d.NS);
     g.part = cv.take<double>((size_t)GMRES_DOT_BLOCKS * (m + 1));
     g.coef = cv.take<double>((size_t)3 * (m + 2));
+    g.hs = cv.take<double>(gmres_hess_doubles(m));
+    g.ctl = cv.take<GmresCtl>(1);
     return g;
 }
 
@@ -1265,20 +1273,28 @@ struct Gmres {
 
     cpx<double>* Vi(int i) { return g.V + (size_t)i * D * P.d.NS; }
 
-    // coef[out .. out + nv) = <w, V_i> for i < nv
-    sgn_status dots(const cpx<double>* w, const cpx<double>* V, int nv, double* out) {
+    // coef[out .. out + nv) = <w, V_i> for i < nv; stop: the gate (null: always run)
+    sgn_status dots(const cpx<double>* w, const cpx<double>* V, int nv, double* out, const SolveScal* stop) {
         sgn_ctx* ctx = P.ctx;
         hipLaunchKernelGGL(k_S_multidot<D>, dim3(dot_blocks), dim3(256), 0, ctx->stream, P.d.nx, P.d.ny, P.d.NS, w,
-                           V, (size_t)D * P.d.NS, nv, g.part);
+                           V, (size_t)D * P.d.NS, nv, g.part, stop);
         hipLaunchKernelGGL(k_S_multidot_finish, dim3(1), dim3(256), 0, ctx->stream, (const double*)g.part,
-                           dot_blocks, nv, P.d.inv_n, out);
+                           dot_blocks, nv, P.d.inv_n, out, stop);
         CHECK_LAUNCH(ctx);
         return SGN_OK;
     }
-    // w += sign * sum_i coef[i] V_i
-    sgn_status axpy(cpx<double>* w, int nv, const double* coef, double sign) {
+    // w += sign * sum_i coef[i] V_i (i < nv, or i < *nv_dev when set)
+    sgn_status axpy(cpx<double>* w, int nv, const double* coef, double sign, const SolveScal* stop,
+                    const int* nv_dev = nullptr) {
         hipLaunchKernelGGL(k_S_multiaxpy, dim3(flat_blocks(nd)), dim3(256), 0, P.ctx->stream, nd, (double*)w,
-                           (const double*)g.V, nd, nv, coef, sign);
+                           (const double*)g.V, nd, nv, coef, sign, stop, nv_dev);
+        CHECK_LAUNCH(P.ctx);
+        return SGN_OK;
+    }
+    // y = scale[0] x (scale in device memory)
+    sgn_status scale(const double* sc_dev, const cpx<double>* x, cpx<double>* y, const SolveScal* stop) {
+        hipLaunchKernelGGL(k_S_scale, dim3(flat_blocks(nd)), dim3(256), 0, P.ctx->stream, nd, sc_dev,
+                           (const double*)x, (double*)y, stop);
         CHECK_LAUNCH(P.ctx);
         return SGN_OK;
     }
@@ -1289,9 +1305,9 @@ struct Gmres {
         if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
         return pcg_c2<double, D>(P, C2_STORE, nullptr, nullptr);
     }
-    sgn_status precond(const cpx<double>* v, cpx<double>* z, double sig, double alp) {
+    sgn_status precond(const cpx<double>* v, cpx<double>* z, double sig, double alp, const SolveScal* stop) {
         hipLaunchKernelGGL(k_S_precond<D>, dim3(flat_blocks(P.d.NS)), dim3(256), 0, P.ctx->stream, P.d.nx, P.d.ny,
-                           P.d.NS, P.d.tpx, P.d.tpy, sig, alp, v, z);
+                           P.d.NS, P.d.tpx, P.d.tpy, sig, alp, v, z, stop);
         CHECK_LAUNCH(P.ctx);
         return SGN_OK;
     }
@@ -1330,7 +1346,8 @@ sgn_status solve_gmres(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     G.dot_blocks = std::min(GMRES_DOT_BLOCKS, flat_blocks(d.NS));
     G.nd = (size_t)2 * D * d.NS;
     sgn_status s;
-    if ((s = batch_staging(ctx, (size_t)3 * (m + 2) * sizeof(double))) != SGN_OK) return s;
+    // pinned readback: ||b||^2, then the cycle state and the stop flag (at byte 512)
+    if ((s = batch_staging(ctx, 1024)) != SGN_OK) return s;
     double* hc = static_cast<double*>(ctx->hbatch);
     // coefficients of A (given or computed), read once: the basis loop is host driven
     if ((s = init_scal(ctx, P.sc, o.tol, o.max_iter, d.inv_n, coeffs)) != SGN_OK) return s;
@@ -1360,7 +1377,7 @@ sgn_status solve_gmres(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     cpx<double>* zh = P.b.ph;
     cpx<double>* qh = P.b.qh;
     if ((s = to_S_d<D>(ctx, d, rhs, P.b.H, bh)) != SGN_OK) return s;
-    if ((s = G.dots(bh, bh, 1, G.g.coef)) != SGN_OK) return s;
+    if ((s = G.dots(bh, bh, 1, G.g.coef, nullptr)) != SGN_OK) return s;
     if ((s = G.read(G.g.coef, hc, 1)) != SGN_OK) return s;
     const double bnorm = std::sqrt(std::max(hc[0], 0.0));
     if (!std::isfinite(bnorm)) {
@@ -1382,95 +1399,71 @@ sgn_status solve_gmres(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
         hipLaunchKernelGGL(k_zero_c, dim3(flat_blocks(G.nd)), dim3(256), 0, ctx->stream, G.nd, (void*)xh);
         CHECK_LAUNCH(ctx);
     }
-    std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
-    auto H = [&](int i, int j) -> double& { return Hm[(size_t)i * m + j]; };
-    const double thr = o.tol * bnorm;
-    int iters = 0;
-    bool conv = false;
-    double relres = 0.0;
-    for (;;) {
-        // true residual r = b - G x into V_0
-        if (guess || iters > 0) {
+    GmresCtl* ctl = G.g.ctl;
+    SolveScal* gate = P.sc;   // its done flag gates the Arnoldi kernels and the operator passes
+    double* y = G.g.hs + (size_t)(m + 1) * m + 2 * (size_t)m + (m + 1);
+    hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(64), 0, ctx->stream, ctl, o.tol * bnorm, bnorm, o.max_iter);
+    CHECK_LAUNCH(ctx);
+    const int chunk = std::max(1, o.check_every);
+    GmresCtl* hctl = reinterpret_cast<GmresCtl*>(hc);
+    for (int cycle = 0;; ++cycle) {
+        // true residual r = b - G x into V_0 (x = 0 on the first cycle without a guess)
+        hipLaunchKernelGGL(k_gmres_open, dim3(1), dim3(64), 0, ctx->stream, (const GmresCtl*)ctl, gate);
+        CHECK_LAUNCH(ctx);
+        if (guess || cycle > 0) {
             if ((s = G.apply(xh)) != SGN_OK) return s;
             if ((s = G.axpby(1.0, bh, 0.0, G.Vi(0))) != SGN_OK) return s;
             if ((s = G.axpby(-1.0, qh, 1.0, G.Vi(0))) != SGN_OK) return s;
         } else {
             if ((s = G.axpby(1.0, bh, 0.0, G.Vi(0))) != SGN_OK) return s;
         }
-        if ((s = G.dots(G.Vi(0), G.Vi(0), 1, G.g.coef)) != SGN_OK) return s;
-        if ((s = G.read(G.g.coef, hc, 1)) != SGN_OK) return s;
-        const double beta = std::sqrt(std::max(hc[0], 0.0));
-        relres = beta / bnorm;
-        if (!std::isfinite(beta)) {
-            finish_info(iters, false, relres);
-            return fail(ctx, SGN_EDOMAIN, "non-finite residual in the solve");
-        }
-        if (beta <= thr) {
-            conv = true;
-            break;
-        }
-        if (iters >= o.max_iter) break;
-        if ((s = G.axpby(0.0, nullptr, 1.0 / beta, G.Vi(0))) != SGN_OK) return s;
-        std::fill(Hm.begin(), Hm.end(), 0.0);
-        std::fill(gv.begin(), gv.end(), 0.0);
-        gv[0] = beta;
-        int jd = 0;
-        for (int j = 0; j < m; ++j) {
-            if ((s = G.precond(G.Vi(j), zh, sig, alp)) != SGN_OK) return s;
-            if ((s = G.apply(zh)) != SGN_OK) return s;
-            ++iters;
-            double* h1 = G.g.coef;
-            double* h2 = G.g.coef + (m + 1);
-            double* ww = G.g.coef + 2 * (m + 1);
-            if ((s = G.dots(qh, G.g.V, j + 1, h1)) != SGN_OK) return s;
-            if ((s = G.axpy(qh, j + 1, h1, -1.0)) != SGN_OK) return s;
-            if ((s = G.dots(qh, G.g.V, j + 1, h2)) != SGN_OK) return s;
-            if ((s = G.axpy(qh, j + 1, h2, -1.0)) != SGN_OK) return s;
-            if ((s = G.dots(qh, qh, 1, ww)) != SGN_OK) return s;
-            if ((s = G.read(G.g.coef, hc, 2 * (m + 1) + 1)) != SGN_OK) return s;
-            for (int i = 0; i <= j; ++i) H(i, j) = hc[i] + hc[m + 1 + i];
-            const double hn = std::sqrt(std::max(hc[2 * (m + 1)], 0.0));
-            H(j + 1, j) = hn;
-            if (!std::isfinite(hn)) {
-                finish_info(iters, false, std::nan(""));
-                return fail(ctx, SGN_EDOMAIN, "non-finite data in the Arnoldi process");
+        if ((s = G.dots(G.Vi(0), G.Vi(0), 1, G.g.coef, nullptr)) != SGN_OK) return s;
+        hipLaunchKernelGGL(k_gmres_begin, dim3(1), dim3(64), 0, ctx->stream, ctl, gate, (const double*)G.g.coef,
+                           G.g.hs, m);
+        CHECK_LAUNCH(ctx);
+        if ((s = G.scale(&ctl->scale, G.Vi(0), G.Vi(0), gate)) != SGN_OK) return s;
+        // Arnoldi steps, issued check_every at a time; the state is read after each chunk
+        for (int j0 = 0; j0 < m; j0 += chunk) {
+            for (int j = j0; j < std::min(m, j0 + chunk); ++j) {
+                if ((s = G.precond(G.Vi(j), zh, sig, alp, gate)) != SGN_OK) return s;
+                if ((s = G.apply(zh)) != SGN_OK) return s;
+                double* h1 = G.g.coef;
+                double* h2 = G.g.coef + (m + 1);
+                double* ww = G.g.coef + 2 * (m + 1);
+                if ((s = G.dots(qh, G.g.V, j + 1, h1, gate)) != SGN_OK) return s;
+                if ((s = G.axpy(qh, j + 1, h1, -1.0, gate)) != SGN_OK) return s;
+                if ((s = G.dots(qh, G.g.V, j + 1, h2, gate)) != SGN_OK) return s;
+                if ((s = G.axpy(qh, j + 1, h2, -1.0, gate)) != SGN_OK) return s;
+                if ((s = G.dots(qh, qh, 1, ww, gate)) != SGN_OK) return s;
+                hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, ctx->stream, j, m,
+                                   (const double*)G.g.coef, G.g.hs, ctl, gate);
+                CHECK_LAUNCH(ctx);
+                if ((s = G.scale(&ctl->scale, qh, G.Vi(j + 1), gate)) != SGN_OK) return s;
             }
-            if ((s = G.axpby(hn != 0.0 ? 1.0 / hn : 1.0, qh, 0.0, G.Vi(j + 1))) != SGN_OK) return s;
-            for (int i = 0; i < j; ++i) {   // earlier rotations
-                const double t = cs[i] * H(i, j) + sn[i] * H(i + 1, j);
-                H(i + 1, j) = -sn[i] * H(i, j) + cs[i] * H(i + 1, j);
-                H(i, j) = t;
-            }
-            const double den = std::hypot(H(j, j), H(j + 1, j));
-            cs[j] = H(j, j) / den;
-            sn[j] = H(j + 1, j) / den;
-            H(j, j) = den;
-            H(j + 1, j) = 0.0;
-            gv[j + 1] = -sn[j] * gv[j];
-            gv[j] = cs[j] * gv[j];
-            jd = j + 1;
-            if (std::fabs(gv[j + 1]) <= thr || iters >= o.max_iter) break;
+            HIPCHK(ctx, hipMemcpyAsync(hctl, ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(hc + 64, &gate->done, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            if ((s = wait_stream(ctx)) != SGN_OK) return s;
+            if (*reinterpret_cast<const int*>(hc + 64)) break;
         }
-        // y = R^{-1} g, then x += A^{-1} (V y)
-        for (int i = jd - 1; i >= 0; --i) {
-            double t = gv[i];
-            for (int k = i + 1; k < jd; ++k) t -= H(i, k) * y[k];
-            y[i] = t / H(i, i);
+        const GmresCtl c = *hctl;
+        if (c.status == -2) {
+            finish_info(c.iters, false, std::nan(""));
+            return fail(ctx, SGN_EDOMAIN, "non-finite data in the residual or the Arnoldi process");
         }
-        for (int i = 0; i < jd; ++i) hc[i] = y[i];
-        double* yd = G.g.coef;
-        HIPCHK(ctx, hipMemcpyAsync(yd, hc, jd * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        if (c.final_) break;
+        // y = R^{-1} g, then x += A^{-1} (V y), over the cycle's columns
+        hipLaunchKernelGGL(k_gmres_backsolve, dim3(1), dim3(64), 0, ctx->stream, m, (const GmresCtl*)ctl, G.g.hs);
+        CHECK_LAUNCH(ctx);
         if ((s = G.axpby(0.0, nullptr, 0.0, zh)) != SGN_OK) return s;
-        if ((s = G.axpy(zh, jd, yd, 1.0)) != SGN_OK) return s;
-        if ((s = G.precond(zh, qh, sig, alp)) != SGN_OK) return s;
+        if ((s = G.axpy(zh, m, y, 1.0, nullptr, &ctl->jd)) != SGN_OK) return s;
+        if ((s = G.precond(zh, qh, sig, alp, nullptr)) != SGN_OK) return s;
         if ((s = G.axpby(1.0, qh, 1.0, xh)) != SGN_OK) return s;
-        // the host copy of y must not be overwritten before the upload has run
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     }
+    const GmresCtl c = *hctl;
     if ((s = from_S_d<D>(ctx, d, xh, P.b.H, u)) != SGN_OK) return s;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    finish_info(iters, conv, relres);
-    if (!conv) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
+    finish_info(c.iters, c.conv != 0, c.relres);
+    if (!c.conv) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
     return SGN_OK;
 }
 

@@ -259,6 +259,14 @@ class _BatchResults:
     def __iter__(self):
         return (self[k] for k in range(self._n))
 
+    def __eq__(self, other):
+        if isinstance(other, (list, tuple, _BatchResults)):
+            return list(self) == list(other)
+        return NotImplemented
+
+    def __repr__(self):
+        return repr(list(self))
+
 
 class Context:
     """An sgn_ctx bound to a GPU and to the PyTorch stream current at each call."""
