@@ -490,6 +490,7 @@ def bench_serve(args):
 
     precs = ["fp64", "mixed"] if args.precision_serve == "both" else [args.precision_serve]
     results = {}
+    served = {}   # (precision, payload key) -> output of its first served result
     for pname in precs:
         prec = sgn.MIXED if pname == "mixed" else sgn.FP64
         opts = sgn.solve_opts(tol=1e-10, precision=prec, inner_tol=args.inner_tol, max_iter=5000, max_outer=40)
@@ -510,7 +511,8 @@ def bench_serve(args):
             t_sub_end = time.perf_counter() - t0
             res = []
             for key, rid in ids:
-                r, _ = srv.wait(rid)
+                r, out = srv.wait(rid)
+                served.setdefault((pname, key), out)
                 if r.status != sgn.OK:
                     raise RuntimeError(f"request {key} failed with status {r.status}")
                 res.append((key, r))
@@ -529,8 +531,21 @@ def bench_serve(args):
                 lk = [1e3 * (r.t_done - r.t_submit) for k, r in res if k[0] == kind]
                 row[f"{kind}_p50_ms"] = percentile(lk, 0.5)
                 row[f"{kind}_p99_ms"] = percentile(lk, 0.99)
+            # per request shape: count, mean time on a lane or in a batched launch
+            # (start to done), the share of the summed service time, mean batch
+            shapes = {}
+            for k, r in res:
+                e = shapes.setdefault(f"{k[0]}-{k[1]}d-{k[2]}", {"count": 0, "service_ms": 0.0, "batch": 0.0})
+                e["count"] += 1
+                e["service_ms"] += 1e3 * (r.t_done - r.t_start)
+                e["batch"] += r.batch_size if r.batched else 1
+            tot_service = sum(e["service_ms"] for e in shapes.values())
+            row["per_shape"] = {name: {"count": e["count"], "mean_service_ms": round(e["service_ms"] / e["count"], 3),
+                                       "service_share": round(e["service_ms"] / max(tot_service, 1e-9), 3),
+                                       "mean_batch": round(e["batch"] / e["count"], 2)}
+                                for name, e in sorted(shapes.items())}
             rows.append(row)
-            print(json.dumps({"serve_progress": pname, **{k: round(v, 3) for k, v in row.items()}}),
+            print(json.dumps({"serve_progress": pname, **{k: round(v, 3) for k, v in row.items() if k != "per_shape"}}),
                   file=sys.stderr, flush=True)
         srv.close()
         results[pname] = rows
@@ -550,16 +565,66 @@ def bench_serve(args):
         "data": "synthetic",
         "config": {"workload": (f"served stream: {nreq} requests per rate, 70% 1D N 1024..16384 / 30% 2D "
                                 "128^2..1024^2, half solves (tol 1e-10) and half 10-step RK4 runs, Poisson "
-                                f"arrivals at {args.rates} req/s, {args.lanes} worker lanes + a batching lane"),
-                   "rates": rates, "requests_per_rate": nreq, "parallelism": "single GPU"},
+                                f"arrivals at {args.rates} req/s, {args.lanes} worker lanes + 2 batching lanes (1D solves, 1D RK4 runs)"),
+                   "rates": rates, "requests_per_rate": nreq, "parallelism": "single GPU",
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "value_precision": best,
         "per_rate": results,
         "roofline": None,
-        "cpu_baseline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else serve_cpu_baseline(pool, served, precs),
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def serve_cpu_baseline(pool, served, precs):
+    """The FP64 oracle on a bounded sample of the served payloads (every 1D
+    payload, the 2D 128^2 ones and the first 2D 256^2 one of each kind), timed
+    on the host, and the error of each sampled served result against it.  Every
+    request of a payload returned the same result bit for bit (alone or in the
+    mix, tested), so the error of a payload is that of each of its requests.
+    The oracle forms its own inputs from the seeded fields (h, eta and u* for a
+    solve, h, eta and u for a run) and solves to tol 1e-12."""
+    import numpy as np
+    from oracle import diagnostics as dg
+    from oracle import krylov
+    from oracle import operators as op
+    from oracle import stepping as ost
+    keys = sorted({k for _, k in served})
+    sample = [k for k in keys if k[1] == 1 or k[2] == 128 or (k[2] == 256 and k[3] == 0)]
+    errs = {}
+    t0 = time.perf_counter()
+    for key in sample:
+        kind, dim, n, i = key
+        r = pool[(kind, dim, n)][i]
+        g = r["grid"]
+        name = f"{kind}-{dim}d-{n}-#{i}"
+        if kind == "solve":
+            gh, fl = op.bathy_gradient(r["h"], g)
+            b = op.apply_G(r["eta"], gh, r["u"], g)
+            sg, al, _ = op.coefficients(r["eta"], gh, fl)
+            u_ref, _, _, _ = krylov.pcg(lambda v: op.apply_G(r["eta"], gh, v, g),
+                                        lambda q: op.solve_A(sg, al, q, g), b, tol=1e-12, max_iter=5000)
+            for p in precs:
+                if (p, key) in served:
+                    u = served[(p, key)]["u"].reshape(u_ref.shape)
+                    errs.setdefault(name, {})[p] = float(dg.rel_l2(u, u_ref))
+        else:
+            pb = ost.Problem.from_h(g, r["h"], tol=1e-12)
+            e_r, U_r, u_r = ost.run_rk4(pb, r["eta"], pb.G(r["eta"], r["u"]), r["u"], r["dt"], r["nsteps"])
+            for p in precs:
+                if (p, key) in served:
+                    o = served[(p, key)]
+                    e, u = o["eta"].reshape(e_r.shape), o["u"].reshape(u_r.shape)
+                    fe = dg.field_errors(e, pb.G(e, u), u, e_r, U_r, u_r, r["h"])
+                    errs.setdefault(name, {})[p] = float(max(fe.values()))
+    dt = time.perf_counter() - t0
+    worst = {p: max((v[p] for v in errs.values() if p in v), default=None) for p in precs}
+    return {"value": len(sample) / dt, "unit": "req/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{len(sample)} distinct served payloads (all 1D, 2D 128^2, one 2D 256^2 per kind), "
+                       f"FP64 NumPy, single thread, {dt:.1f} s"),
+            "per_result_error_vs_oracle": errs, "max_error_vs_oracle": worst}
 
 
 def _state_1d(ctx, cfg, to):
@@ -751,7 +816,7 @@ def main(argv=None):
     ap.add_argument("--workload", choices=["rk4-2d", "c1", "c2", "batch", "serve", "coeffs", "walls"],
                     default="rk4-2d")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="arrival rates of the serve workload")
-    ap.add_argument("--serve-requests", type=int, default=200, help="requests per rate (serve workload)")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate (serve workload)")
     ap.add_argument("--lanes", type=int, default=3, help="worker lanes of the server (serve workload)")
     ap.add_argument("--precision-serve", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--count", type=int, default=512, help="systems of the batched workload")
@@ -818,6 +883,10 @@ def main(argv=None):
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "serve":
+        # the server's lanes overlap on the device only with a hardware queue
+        # each; HIP's default of 4 queues per process makes 2 batching lanes and
+        # 3 worker lanes share them.  Read when the HIP runtime starts, so set here.
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
         return bench_serve(args)
     if args.workload == "coeffs":
         return bench_coeffs(args)

@@ -451,7 +451,9 @@ sgn_status sgn_state_set_dealias(sgn_ctx *ctx, sgn_state *state, void *d_dws);
  * stream), so batches, solves and steps overlap on the device.  A request's
  * result does not depend on what it was batched or overlapped with (one
  * workgroup carries each batched request, and the kernels reduce in a fixed
- * order). */
+ * order).  The lanes overlap on the device only if the process has a hardware
+ * queue for each of them (lanes + 2); HIP gives a process 4 unless
+ * GPU_MAX_HW_QUEUES, read when the HIP runtime starts, says otherwise. */
 typedef struct sgn_server sgn_server;
 
 typedef struct sgn_server_opts {

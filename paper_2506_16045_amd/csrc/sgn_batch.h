@@ -14,9 +14,23 @@ namespace sgn {
 
 constexpr int BATCH_MMAX = 4096;                 // largest half length M = N/2
 constexpr int BATCH_NMAX = 2 * BATCH_MMAX;       // 8192 points
-// Complex points per thread and radix-4 pass for a workgroup of NT threads.
+// Size classes: a system of n <= 2048 points runs on 256 threads whose
+// per-mode registers and transform tiling cover M <= 1024; a larger one on 512
+// threads covering M <= 4096.  The class is a function of n alone, so a
+// system's reductions, and its results, do not depend on what shares a launch.
+__host__ __device__ constexpr int batch_threads_for(int n) { return n <= 2048 ? 256 : 512; }
 template <int NT>
-constexpr int batch_epc() { return BATCH_MMAX / NT; }
+constexpr int batch_mmax() { return NT <= 256 ? 1024 : BATCH_MMAX; }
+// Complex points per thread of one transform pass for a workgroup of NT threads.
+template <int NT>
+constexpr int batch_epc() { return batch_mmax<NT>() / NT; }
+#ifndef SGN_BATCH_WAVES_SMALL
+#define SGN_BATCH_WAVES_SMALL 2
+#endif
+// Waves per SIMD the compiler must leave room for (register budget): the small
+// class keeps several workgroups resident per CU.
+template <int NT>
+constexpr int batch_waves() { return NT <= 256 ? SGN_BATCH_WAVES_SMALL : 1; }
 
 enum { BATCH_FP64 = 0, BATCH_MIXED = 1 };
 
@@ -268,8 +282,8 @@ __device__ __forceinline__ cpx<T> cvt(cpx<U> v) {
 template <typename T, int NT, bool REGCOEF, typename TX>
 __device__ int blk_pcg_reg(const BatchOp<T>& A, cpx<TX>* xh, const cpx<TX>* r0h, T sig, T alp, double tol2,
                            double bbref, int max_iter, double& rr, cpx<T>* lds, double* red) {
-    constexpr int KPT = BATCH_MMAX / NT + 1;
-    constexpr int JPT = BATCH_MMAX / NT;
+    constexpr int KPT = batch_mmax<NT>() / NT + 1;
+    constexpr int JPT = batch_mmax<NT>() / NT;
     constexpr int JC = REGCOEF ? JPT : 1;
     const int M = A.M, N = A.N, t = threadIdx.x;
     const int fs = M + 1;
@@ -464,7 +478,7 @@ __device__ __forceinline__ int batch_next(int* queue, int cur, int* slot) {
 // refinement (MIXED), and u (physical) on return; w is the system's workspace
 // (batch_item_doubles).  Every thread of the block calls it.
 template <int MODE, int NT>
-__device__ BatchResult blk_solve_system(const BatchItem& it, const double* __restrict__ eta,
+__device__ __forceinline__ BatchResult blk_solve_system(const BatchItem& it, const double* __restrict__ eta,
                                         const double* __restrict__ hx, const double* __restrict__ b, double* u,
                                         bool guess, double* w, const cpx<double>* __restrict__ tw64,
                                         const cpx<float>* __restrict__ tw32, const BatchParams& prm,
@@ -598,7 +612,7 @@ __device__ BatchResult blk_solve_system(const BatchItem& it, const double* __res
 }
 
 template <int MODE, int NT>
-__global__ void __launch_bounds__(NT) k_batch_solve(const BatchItem* __restrict__ items, int nitems,
+__global__ void __launch_bounds__(NT, batch_waves<NT>()) k_batch_solve(const BatchItem* __restrict__ items, int nitems,
                                                                const double* __restrict__ eta_all,
                                                                const double* __restrict__ hx_all,
                                                                const double* __restrict__ b_all,
@@ -968,7 +982,7 @@ __device__ StepResult blk_rk4_run(const StepItem& it, bool extrapolate, const cp
 // queue is set, its counter zero at launch) until none is left.  LDS: two FP64
 // transform buffers of the largest state's N/2 + 1 modes.
 template <int MODE, int NT>
-__global__ void __launch_bounds__(NT) k_batch_rk4(const StepItem* __restrict__ items, int nitems,
+__global__ void __launch_bounds__(NT, batch_waves<NT>()) k_batch_rk4(const StepItem* __restrict__ items, int nitems,
                                                   const cpx<double>* __restrict__ tw64,
                                                   const cpx<float>* __restrict__ tw32, BatchParams prm,
                                                   int extrapolate, StepResult* __restrict__ res, int* queue) {

@@ -42,10 +42,6 @@ struct sgn_ctx {
         hipGraphExec_t exec;  // null: seen once (ran eagerly), capture on the next use
     };
     hipStream_t cap_stream = nullptr;
-    // second stream of batched RK4 launches (created on first use, default
-    // priority): the size classes of one call run side by side
-    hipStream_t aux_stream = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<GraphEntry> graphs;
     bool use_graphs = false;
     // iterations of the previous solve per precision (FP64 / FP32 loop) and
@@ -55,7 +51,6 @@ struct sgn_ctx {
     bool stage = false;           // solving inside a stepper: skip the final scalar readback
     bool wall_twin = false;       // solving on the periodic twin of a wall grid
     int cus = 256;                // compute units of the device
-    int batch_threads = 512;      // workgroup size of the batched solver (SGN_BATCH_THREADS: 256, 512, 1024)
     void* hbatch = nullptr;       // pinned staging of batch item tables and results
     size_t hbatch_bytes = 0;
     int slot = GUESS_SLOTS;       // stepper slot of the running solve
@@ -2723,8 +2718,6 @@ sgn_status sgn_create(sgn_ctx** out, int device, void* hip_stream) {
         return SGN_ENOMEM;
     }
     ctx->scratch = scratch_address(device);
-    const char* bt = getenv("SGN_BATCH_THREADS");
-    if (bt) ctx->batch_threads = atoi(bt);
     // HIP graphs for the PCG chunks are opt-in: their host-side launch costs more
     // than the eager launches of a chunk (measured: 1024^2 RK4 step 3.58 ms with
     // graphs, 3.56 ms without)
@@ -2747,9 +2740,6 @@ void sgn_destroy(sgn_ctx* ctx) {
     for (auto& g : ctx->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
-    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->hbatch) (void)hipHostFree(ctx->hbatch);
     delete ctx;
 }
@@ -3026,6 +3016,38 @@ BatchLayout batch_layout(int nitems, const int32_t* n, int mode) {
 
 bool batch_size_ok(int n) { return n >= 2 && n <= BATCH_NMAX && (n & (n - 1)) == 0; }
 
+// Workgroup size of every system of a batched call (sgn_batch_solve,
+// sgn_batch_step_rk4); the one-system paths take the size class of their n.
+constexpr int BATCH_CALL_THREADS = 512;
+
+// k_batch_solve over nitems table entries (workgroups of nt threads) on
+// `stream`.  LDS: two transform buffers of the largest system's M + 1 modes (FP64
+// ones in FP64 mode; in mixed mode the FP32 pair or one FP64 buffer, the
+// refinement residual, whichever is larger).  grid = 0: as many workgroups as fit
+// the device (at most nitems), sharing the work queue d_queue.
+sgn_status launch_batch_solve(sgn_ctx* ctx, hipStream_t stream, int nt, const BatchItem* d_items, int nitems,
+                              int nmax, int mode, int grid, const double* eta, const double* gh, const double* rhs,
+                              double* u, double* d_data, const BatchParams& prm, BatchResult* d_res, int* d_queue) {
+    const size_t lds = (size_t)(nmax / 2 + 1) * sizeof(cpx<double>) * (mode == BATCH_FP64 ? 2 : 1);
+    auto launch = [&](auto k) -> sgn_status {
+        HIPCHK(ctx, allow_lds(k, lds));
+        int g = grid;
+        if (g <= 0) {
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, nt, lds) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            g = std::min(nitems, per_cu * ctx->cus);
+        }
+        hipLaunchKernelGGL(k, dim3(g), dim3(nt), lds, stream, d_items, nitems, eta, gh, rhs, u, d_data, ctx->tw64,
+                           ctx->tw32, prm, d_res, d_queue);
+        CHECK_LAUNCH(ctx);
+        return SGN_OK;
+    };
+    const bool mx = mode == BATCH_MIXED;
+    if (nt == 256) return mx ? launch(k_batch_solve<BATCH_MIXED, 256>) : launch(k_batch_solve<BATCH_FP64, 256>);
+    return mx ? launch(k_batch_solve<BATCH_MIXED, 512>) : launch(k_batch_solve<BATCH_FP64, 512>);
+}
+
 // ---- batched RK4 runs (k_batch_rk4) ----------------------------------------
 
 // One state's arrays in a batched run, each 256-byte aligned: h_x, U, the four
@@ -3068,9 +3090,9 @@ BatchParams step_params(const sgn_solve_opts& o, int nitems) {
 
 // Workgroup size of a state's runs: fixed by its own size, so that its
 // reductions (and with them its results) do not depend on what shares a launch.
-int step_threads(int n) { return n <= 2048 ? 256 : 512; }
+int step_threads(int n) { return batch_threads_for(n); }
 
-// k_batch_rk4 over nitems table entries of one size class (workgroups of nt
+// k_batch_rk4 over nitems table entries (workgroups of nt
 // threads) on `stream`; grid = 0: as many workgroups as fit the device (at most
 // nitems), which then share the work queue d_queue (zero at launch).
 sgn_status launch_batch_rk4(sgn_ctx* ctx, hipStream_t stream, int nt, const StepItem* d_items, int nitems, int nmax,
@@ -3221,6 +3243,8 @@ sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const
         po += n[i];
         pw += batch_item_doubles(n[i], mode);
     }
+    // systems in the caller's order for offsets; the table is sorted by size
+    // (largest first) so that workgroups take the long systems first
     std::vector<int> order(nitems);
     for (int i = 0; i < nitems; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
@@ -3251,29 +3275,13 @@ sgn_status sgn_batch_solve(sgn_ctx* ctx, int32_t nitems, const int32_t* n, const
     prm.coeff_kind = o.coeff_kind;
     prm.nitems = nitems;
     prm.flat = -1;
-    // two transform buffers of M+1 modes: FP64 ones in FP64 mode; in mixed mode
-    // the FP32 pair or one FP64 buffer (the refinement residual), whichever is larger
-    const size_t lds = (size_t)(nmax / 2 + 1) * sizeof(cpx<double>) * (mode == BATCH_FP64 ? 2 : 1);
     {
         ProfScope ps(ctx, SGN_KERNEL_BATCH);
-        auto launch = [&](auto k, int nt) -> sgn_status {
-            HIPCHK(ctx, allow_lds(k, lds));
-            int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, nt, lds) != hipSuccess || per_cu < 1)
-                per_cu = 1;
-            const int grid = std::min(nitems, per_cu * ctx->cus);
-            hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, ctx->stream, (const BatchItem*)d_items, nitems, eta,
-                               grad_h, rhs, u, d_data, ctx->tw64, ctx->tw32, prm, d_res, d_queue);
-            CHECK_LAUNCH(ctx);
-            return SGN_OK;
-        };
-        const bool mx = mode == BATCH_MIXED;
-        switch (ctx->batch_threads) {
-            case 1024: s = mx ? launch(k_batch_solve<BATCH_MIXED, 1024>, 1024) : launch(k_batch_solve<BATCH_FP64, 1024>, 1024); break;
-            case 512: s = mx ? launch(k_batch_solve<BATCH_MIXED, 512>, 512) : launch(k_batch_solve<BATCH_FP64, 512>, 512); break;
-            default: s = mx ? launch(k_batch_solve<BATCH_MIXED, 256>, 256) : launch(k_batch_solve<BATCH_FP64, 256>, 256); break;
-        }
-        if (s != SGN_OK) return s;
+        // every system of a batched call on 512 threads, whatever its size: a
+        // system's reductions, and so its result, do not depend on the batch
+        if ((s = launch_batch_solve(ctx, ctx->stream, BATCH_CALL_THREADS, d_items, nitems, nmax, mode, 0, eta, grad_h,
+                                    rhs, u, d_data, prm, d_res, d_queue)) != SGN_OK)
+            return s;
     }
     BatchResult* hres = static_cast<BatchResult*>(ctx->hbatch);
     HIPCHK(ctx, hipMemcpyAsync(hres, d_res, sizeof(BatchResult) * (size_t)nitems, hipMemcpyDeviceToHost, ctx->stream));
@@ -3346,23 +3354,14 @@ sgn_status sgn_batch_step_rk4(sgn_ctx* ctx, int32_t nitems, const int32_t* n, co
         po += n[i];
         pd += step_item_doubles(n[i], mode);
     }
-    // the table: the 512-thread class (n > 2048) first, then the 256-thread one,
-    // each longest run (points times steps) first
+    // the table runs longest first (points times steps) so that workgroups take
+    // the long runs first
     std::vector<int> order(nitems);
     for (int i = 0; i < nitems; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const int ta = step_threads(n[a]), tb = step_threads(n[b]);
-        if (ta != tb) return ta > tb;
         return (long long)n[a] * nsteps[a] > (long long)n[b] * nsteps[b];
     });
-    int n_big = 0, nmax_small = 0;
-    for (int i = 0; i < nitems; ++i) {
-        if (step_threads(n[i]) == 512)
-            ++n_big;
-        else
-            nmax_small = std::max(nmax_small, (int)n[i]);
-    }
-    std::memset(ctx->hbatch, 0, BATCH_HEAD);   // the two classes' queue counters
+    std::memset(ctx->hbatch, 0, BATCH_HEAD);   // the queue counter
     StepItem* hit = reinterpret_cast<StepItem*>(static_cast<char*>(ctx->hbatch) + BATCH_HEAD);
     for (int q = 0; q < nitems; ++q) {
         const int i = order[q];
@@ -3406,32 +3405,13 @@ sgn_status sgn_batch_step_rk4(sgn_ctx* ctx, int32_t nitems, const int32_t* n, co
     int* d_queue = reinterpret_cast<int*>(base);   // counters at bytes 0 and 128
     const BatchParams prm = step_params(o, nitems);
     const bool ex = o.guess == SGN_GUESS_EXTRAPOLATE;
-    const int n_small = nitems - n_big;
     {
+        // every run of a batched call on 512 threads, whatever its size: a run's
+        // reductions, and so its result, do not depend on the batch
         ProfScope ps(ctx, SGN_KERNEL_BATCH_STEP);
-        if (n_big > 0 && n_small > 0) {
-            // the large class on the second stream, the small one beside it
-            if (!ctx->aux_stream) {
-                HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
-                HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
-                HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
-            }
-            HIPCHK(ctx, hipEventRecord(ctx->ev_fork, ctx->stream));
-            HIPCHK(ctx, hipStreamWaitEvent(ctx->aux_stream, ctx->ev_fork, 0));
-            if ((s = launch_batch_rk4(ctx, ctx->aux_stream, 512, d_items, n_big, nmax, mode, 0, prm, ex, d_res,
-                                      d_queue)) != SGN_OK)
-                return s;
-            HIPCHK(ctx, hipEventRecord(ctx->ev_join, ctx->aux_stream));
-            s = launch_batch_rk4(ctx, ctx->stream, 256, d_items + n_big, n_small, nmax_small, mode, 0, prm, ex, d_res,
-                                 d_queue + 32);
-            HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
-            if (s != SGN_OK) return s;
-        } else {
-            const int nt = n_big > 0 ? 512 : 256;
-            if ((s = launch_batch_rk4(ctx, ctx->stream, nt, d_items, nitems, nmax, mode, 0, prm, ex, d_res,
-                                      d_queue)) != SGN_OK)
-                return s;
-        }
+        if ((s = launch_batch_rk4(ctx, ctx->stream, BATCH_CALL_THREADS, d_items, nitems, nmax, mode, 0, prm, ex, d_res,
+                                  d_queue)) != SGN_OK)
+            return s;
     }
     StepResult* hres = static_cast<StepResult*>(ctx->hbatch);
     HIPCHK(ctx, hipMemcpyAsync(hres, base + lay.results, sizeof(StepResult) * (size_t)nitems, hipMemcpyDeviceToHost,
