@@ -817,7 +817,7 @@ def main(argv=None):
                     default="rk4-2d")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="arrival rates of the serve workload")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate (serve workload)")
-    ap.add_argument("--lanes", type=int, default=3, help="worker lanes of the server (serve workload)")
+    ap.add_argument("--lanes", type=int, default=6, help="worker lanes of the server (serve workload)")
     ap.add_argument("--precision-serve", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--count", type=int, default=512, help="systems of the batched workload")
     ap.add_argument("--cpu-sample", type=int, default=512, help="systems the CPU oracle solves for its baseline")
@@ -885,8 +885,8 @@ def main(argv=None):
     if args.workload == "serve":
         # the server's lanes overlap on the device only with a hardware queue
         # each; HIP's default of 4 queues per process makes 2 batching lanes and
-        # 3 worker lanes share them.  Read when the HIP runtime starts, so set here.
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+        # the worker lanes share them.  Read when the HIP runtime starts, so set here.
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(args.lanes + 2))
         return bench_serve(args)
     if args.workload == "coeffs":
         return bench_coeffs(args)

@@ -223,7 +223,10 @@ __device__ __forceinline__ double rhs_source(int i, double e, const double (&uc)
 // Products and forward row transforms of the right-hand side's source fields
 // (rhs_source order) in groups of NFG fields; dst.p[i] receives field i.  Each
 // block does every group in turn (running the groups side by side in separate
-// blocks was measured slower: every group then reloads eta, u and grad h).
+// blocks was measured slower: every group then reloads its inputs).  With
+// 256-thread blocks eta, u and beta = grad h . u are read once per point into
+// registers before the first group, so each input crosses HBM once; larger
+// blocks, whose register budget is smaller, read them again for every group.
 // MAXT bounds the workgroup size (256 lets the compiler use more registers).
 template <int D, int EPC, int NFG, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_rhs_rows_fwd(RowGeom g, const double* __restrict__ eta,
@@ -236,6 +239,35 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_fwd(RowGeom g, const double* 
     const RowThread<double> rt = row_thread<double>(g, lds);
     const size_t npts = (size_t)g.nx * g.ny;
     constexpr int NFLD = 2 * D + 1 + (D == 2 ? 3 : 1) + 1;
+    // the inputs of this thread's points: eta, u_c and beta (the last field)
+    constexpr bool KEEP = MAXT <= 256;
+    constexpr int EK = KEEP ? EPC : 1;
+    double ie[EK][2], iu[D][EK][2], ib[EK][2];
+    auto load = [&](int e, int s, double& et, double (&uc)[D], double (&hc)[D]) {
+        const int j = rt.t + g.TPR * e;
+        const bool ok = j < g.M && rt.valid;
+        const size_t o = ok ? (size_t)rt.y * g.nx + 2 * j : 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            uc[c] = ok ? u[c * npts + o + s] : 0.0;
+            hc[c] = ok ? gh[c * npts + o + s] : 0.0;
+        }
+        et = ok ? eta[o + s] : 0.0;
+    };
+    if (KEEP) {
+#pragma unroll
+        for (int e = 0; e < EK; ++e) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                double uc[D], hc[D];
+                load(e, s, ie[e][s], uc, hc);
+#pragma unroll
+                for (int c = 0; c < D; ++c) iu[c][e][s] = uc[c];
+                ib[e][s] = rhs_source<D>(NFLD - 1, ie[e][s], uc, hc);
+            }
+        }
+    }
+#pragma unroll
     for (int f0 = 0; f0 < NFLD; f0 += NFG) {
         cpx<double> z[NFG][EPC];
         cpx<double>* H[NFG];
@@ -247,19 +279,24 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_fwd(RowGeom g, const double* 
 #pragma unroll
             for (int k = 0; k < NFG; ++k) z[k][e] = C<double>(0, 0);
             if (j < g.M && rt.valid) {
-                const size_t o = (size_t)rt.y * g.nx + 2 * j;
                 double v[NFG][2];
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    const double et = eta[o + s];
-                    double uc[D], hc[D];
+                    double et, uc[D], hc[D];
+                    if (KEEP) {
+                        const int ek = KEEP ? e : 0;
+                        et = ie[ek][s];
 #pragma unroll
-                    for (int c = 0; c < D; ++c) {
-                        uc[c] = u[c * npts + o + s];
-                        hc[c] = gh[c * npts + o + s];
+                        for (int c = 0; c < D; ++c) {
+                            uc[c] = iu[c][ek][s];
+                            hc[c] = 0.0;
+                        }
+                    } else {
+                        load(e, s, et, uc, hc);
                     }
 #pragma unroll
-                    for (int k = 0; k < NFG; ++k) v[k][s] = rhs_source<D>(f0 + k, et, uc, hc);
+                    for (int k = 0; k < NFG; ++k)
+                        v[k][s] = KEEP && f0 + k == NFLD - 1 ? ib[KEEP ? e : 0][s] : rhs_source<D>(f0 + k, et, uc, hc);
                 }
 #pragma unroll
                 for (int k = 0; k < NFG; ++k) z[k][e] = C<double>(v[k][0], v[k][1]);
