@@ -886,7 +886,13 @@ def main(argv=None):
         # the server's lanes overlap on the device only with a hardware queue
         # each; HIP's default of 4 queues per process makes 2 batching lanes and
         # the worker lanes share them.  Read when the HIP runtime starts, so set here.
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(args.lanes + 2))
+        need = args.lanes + 2
+        try:
+            have = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+        except ValueError:
+            have = 4
+        if have < need:
+            os.environ["GPU_MAX_HW_QUEUES"] = str(need)
         return bench_serve(args)
     if args.workload == "coeffs":
         return bench_coeffs(args)
