@@ -7,8 +7,10 @@ pcg   : textbook preconditioned conjugate gradient, preconditioner solves only
         routine the paper's computations used.
 gmres : restarted, right-preconditioned GMRES with the same stop rule on the
         (unpreconditioned) residual.  The paper itself uses PCG only; GMRES is
-        an option of the device library.  parity unpinned beyond the checks
-        that it solves manufactured systems.
+        an option of the device library.  Pinned by manufactured systems and by
+        its definition: every iterate (with and without restarts) and the
+        iteration count equal a brute-force minimisation of the residual over
+        each cycle's Krylov space on a dense tiny problem.
 """
 from __future__ import annotations
 

@@ -1,6 +1,8 @@
 """Pins of the oracle's PCG/GMRES: manufactured solutions, the dense direct
 solve, one-step convergence when G = A, the CG error bound Eq:pcg_upperbound
-with the epsilon of def:discrete_Gerr, monotone epsilon, mesh independence."""
+with the epsilon of def:discrete_Gerr, monotone epsilon, mesh independence, and
+restarted GMRES(m) against its defining minimisation (every iterate and the
+iteration count, by brute force on a dense tiny problem)."""
 import math
 
 import numpy as np
@@ -114,3 +116,58 @@ def test_replacement_coefficients_are_no_better():
         assert ok
         its[kind] = it
     assert its["replacement"] >= its["optimal"], its
+
+
+def _gmres_brute(G, Minv, b, x0, tol, max_iter, m):
+    """Restarted right-preconditioned GMRES(m) from its definition: each cycle
+    takes x = x_c + Minv V y with y minimising ||b - G (x_c + Minv V y)||_2 over
+    the Krylov space K_j(G Minv, r_c) (an orthonormal basis of the explicit
+    power basis, a dense least-squares solve), one application of G per step;
+    the cycle stops at the first j whose minimal residual reaches tol ||b||, or
+    after m steps, and the next cycle restarts from the true residual.  Returns
+    (x, iters, converged)."""
+    x = x0.copy()
+    bn = np.linalg.norm(b)
+    iters = 0
+    K = G @ Minv
+    while True:
+        r = b - G @ x
+        if np.linalg.norm(r) <= tol * bn:
+            return x, iters, True
+        if iters >= max_iter:
+            return x, iters, False
+        basis = [r / np.linalg.norm(r)]
+        best = None
+        for j in range(1, m + 1):
+            Q, _ = np.linalg.qr(np.stack(basis, axis=1))
+            y, *_ = np.linalg.lstsq(K @ Q, r, rcond=None)
+            best = x + Minv @ (Q @ y)
+            iters += 1
+            if np.linalg.norm(r - K @ (Q @ y)) <= tol * bn or iters >= max_iter:
+                break
+            v = K @ basis[-1]
+            basis.append(v / np.linalg.norm(v))
+        x = best
+
+
+@pytest.mark.parametrize("restart,max_iter", [(30, 3), (30, 5), (2, 5), (3, 30)])
+def test_gmres_iterates_and_counts_equal_the_defining_minimisation(restart, max_iter, rng):
+    """Each iterate of restarted GMRES(m) is the minimiser of the residual over its
+    cycle's Krylov space; checked against a brute-force minimisation on a dense
+    problem of 16 unknowns, after a fixed number of steps (with and without
+    restarts) and at convergence (iterate and iteration count)."""
+    g = I.grid1d(16, 3.0)
+    eta = I.random_positive_depth(g, rng, 0.6, 1.6)
+    h = 1.0 + 0.3 * I.random_smooth_field(g, rng, modes=3)
+    gh, fl = op.bathy_gradient(h, g)
+    s, a, _ = op.coefficients(eta, gh, fl)
+    G = op.dense_G(eta, gh, g)
+    Minv = np.linalg.inv(op.dense_A(s, a, g))
+    b = rng.normal(size=(1,) + g.shape)
+    x0 = 0.1 * rng.normal(size=b.shape)
+    tol = 1e-10
+    x, it, ok, _ = krylov.gmres(lambda v: op.apply_G(eta, gh, v, g), lambda r: op.solve_A(s, a, r, g), b, x0=x0,
+                                tol=tol, max_iter=max_iter, restart=restart)
+    xr, itr, okr = _gmres_brute(G, Minv, b.ravel(), x0.ravel(), tol, max_iter, restart)
+    assert it == itr and ok == okr
+    assert np.max(np.abs(x.ravel() - xr)) <= 1e-8 * np.max(np.abs(xr))
