@@ -357,7 +357,11 @@ void sgn_state_destroy(sgn_state *state);
  * history stays with the state across calls with the same dt.  A failed stage
  * solve (SGN_ENOCONV, SGN_EDOMAIN) leaves the state at the last completed step;
  * a failed final solve of a step still counts the step: eta and U hold the new
- * level, u the last iterate of that solve, and t, steps_done describe them. */
+ * level, u the last iterate of that solve, and t, steps_done describe them.
+ * On a periodic 1D grid of up to 8192 points (plain right-hand side, PCG in
+ * FP64 or mixed precision) the whole call runs in one workgroup of one kernel
+ * launch (the kernel of sgn_batch_step_rk4, on this state's buffers and guess
+ * history). */
 sgn_status sgn_step_rk4(sgn_ctx *ctx, sgn_state *state, double dt, int32_t nsteps,
                         const sgn_solve_opts *opts, sgn_step_info *info);
 

@@ -175,3 +175,26 @@ def test_one_state_rk4_runs_in_one_launch_and_matches_the_oracle(ctx, precision)
                           st.u.cpu().numpy().reshape(u_r.shape), e_r, U_r, u_r, h)
     print(f"  one-state RK4 n=2048 {precision}: error vs oracle {max(err.values()):.2e}", flush=True)
     assert max(err.values()) <= (1e-10 if precision == "fp64" else 1e-9), err
+
+
+def test_smallest_sizes_match_the_oracle(ctx):
+    """States of 2, 4 and 8 points (the degenerate transform lengths) beside a
+    larger one: each run matches the oracle's RK4 run."""
+    from paper_2506_16045_amd import sgn
+    rng = np.random.default_rng(I.SEED_BASE + 71)
+    states = []
+    for n in (2, 4, 8, 64):
+        g = I.grid1d(n, 5.0)
+        x = I.coords(g)
+        h = 1.0 - 0.2 * np.cos(2 * np.pi * x / g.Lx)
+        eta = h + 0.1 * (1.0 + np.sin(2 * np.pi * x / g.Lx + rng.uniform(0, 1)))
+        u = 0.05 * np.cos(2 * np.pi * x / g.Lx)
+        states.append(dict(g=g, h=h, eta=eta, u=u, dt=0.01, nsteps=3))
+    opts = sgn.solve_opts(tol=1e-12, max_iter=500)
+    outs, infos, stats, st = _run(ctx, states, opts)
+    assert st == sgn.OK and all(x == sgn.OK for x in stats)
+    for s, (e, u), inf in zip(states, outs, infos):
+        pb, e_r, U_r, u_r = _oracle(s, 1e-12, "extrapolate")
+        err = dg.field_errors(e, pb.G(e, u[None, :]), u[None, :], e_r, U_r, u_r, s["h"])
+        assert max(err.values()) <= 1e-10, (s["g"].nx, err)
+        assert inf.steps_done == 3
