@@ -257,8 +257,9 @@ def cpu_baseline_walls(cfg):
 
 
 def bench_walls(args):
-    """Constraint solves in a closed basin (walls): solves/s of the library's wall path
-    (reflection onto the periodic twin), FP64 and mixed, with the PCG kernels timed."""
+    """Constraint solves in a closed basin (walls): solves/s of the library's wall path,
+    FP64 (PCG on the basin's own points in cosine / sine amplitudes) and mixed
+    (reflection onto the periodic twin), with the PCG kernels timed."""
     import numpy as np
     import torch
 
@@ -309,7 +310,7 @@ def bench_walls(args):
     main = res_by["fp64"]
     kind = "pcg_r1"
     twin = (2 * g.nx, 2 * g.ny)
-    nbytes = kernel_bytes(kind, 2, twin[0], twin[1], 8)
+    nbytes = kernel_bytes(kind, 2, g.nx, g.ny, 8)   # the FP64 row pass runs on the basin's own points
     avg = main["kernel_avg_us"].get(kind)
     roof = None
     if avg:
@@ -321,9 +322,10 @@ def bench_walls(args):
            "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": main["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"walls basin {g.nx}x{g.ny} cells on {g.Lx:g}x{g.Ly:g} (periodic twin "
-                                  f"{twin[0]}x{twin[1]}), Gaussian bump bathymetry, surface hump, tol {cfg['tol']:g}, "
-                                  "zero initial guess", "parallelism": "single GPU"},
+           "config": {"workload": f"walls basin {g.nx}x{g.ny} cells on {g.Lx:g}x{g.Ly:g} (FP64 PCG on the "
+                                  f"cells in cosine / sine amplitudes; mixed precision and the RK4 state on the "
+                                  f"periodic twin {twin[0]}x{twin[1]}), Gaussian bump bathymetry, surface hump, "
+                                  f"tol {cfg['tol']:g}, zero initial guess", "parallelism": "single GPU"},
            "precisions": res_by, "stepping": stepping, "roofline": roof,
            "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_walls(cfg),
            "device": torch.cuda.get_device_name(0)}

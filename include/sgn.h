@@ -180,7 +180,8 @@ typedef enum sgn_kernel_kind {
     SGN_KERNEL_RHS_ROWS_INV = 13,  /* 2D right-hand side: inverse row transforms, pointwise eta_t, U_t, S */
     SGN_KERNEL_RHS_FLUX = 14,      /* 2D right-hand side: grad S - div(eta u (x) u) column operators */
     SGN_KERNEL_BATCH_STEP = 15,    /* whole 1D RK4 runs, one workgroup per state (one launch per call) */
-    SGN_KERNEL_KINDS = 16
+    SGN_KERNEL_WALL_ORDER = 16,    /* 2D fields between walls to and from the cosine / sine transform order */
+    SGN_KERNEL_KINDS = 17
 } sgn_kernel_kind;
 sgn_status sgn_profile_begin(sgn_ctx *ctx);
 sgn_status sgn_profile_end(sgn_ctx *ctx, int64_t *launches, double *total_ms, int32_t nkinds);

@@ -2,6 +2,7 @@
 #include "sgn.h"
 #include "sgn_kernels.h"
 #include "sgn_batch.h"
+#include "sgn_wall.h"
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -637,6 +638,7 @@ struct PcgLaunch {
     const T* eta;
     const T* gh;
     bool wall = false;  // the grid is the periodic twin of a wall grid (residuals projected)
+    bool native = false;  // a 2D grid between walls on its own points (the wall column passes)
 };
 
 // mode C1_ACCUM (T = double only): x_hat += dx (FP32) and G is applied to the
@@ -646,6 +648,16 @@ sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc, const cpx<fl
     ProfScope ps(P.ctx, SGN_KERNEL_PCG_C1 + (sizeof(T) == 4 ? 6 : 0), true);
     auto& L = P.cl;
     const size_t lds = col_lds_bytes<T>(L.g, D + 1);
+    if (P.native) {
+        if (D != 2 || mode != C1_UPDATE) return fail(P.ctx, SGN_EINVAL, "pcg_c1: wall column pass takes updates only");
+        auto k = k_wall_c1<T, 4>;
+        HIPCHK(P.ctx, allow_lds(k, lds));
+        hipExtLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, ps.a, ps.b, 0, L.g,
+                              twiddles<T>(P.ctx), P.sc, (const double*)P.partials, P.cl.g.nblocks,
+                              (const cpx<T>*)P.b.rh, P.b.ph, P.b.H, P.d.NS, (T)P.d.tpx, (T)P.d.tpy);
+        CHECK_LAUNCH(P.ctx);
+        return SGN_OK;
+    }
     auto launch = [&](auto k, cpx<T>* ph) -> sgn_status {
         HIPCHK(P.ctx, allow_lds(k, lds));
         hipExtLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, ps.a, ps.b, 0, L.g,
@@ -707,6 +719,19 @@ sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out, con
         CHECK_LAUNCH(P.ctx);
         return SGN_OK;
     };
+    if (P.native) {
+        if constexpr (D == 2 && (MODE == C2_UPDATE || MODE == C2_RESID_INIT)) {
+            auto k = k_wall_c2<T, 4, MODE>;
+            HIPCHK(P.ctx, allow_lds(k, lds));
+            hipExtLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, ps.a, ps.b, 0, L.g,
+                                  twiddles<T>(P.ctx), P.sc, (const cpx<T>*)P.b.H, P.d.NS, (const cpx<T>*)P.b.ph,
+                                  P.b.xh, bh, rh_out, P.partials, nb_red, (T)P.d.tpx, (T)P.d.tpy);
+            CHECK_LAUNCH(P.ctx);
+            return SGN_OK;
+        } else {
+            return fail(P.ctx, SGN_EINVAL, "pcg_c2: wall column pass takes updates and the initial residual only");
+        }
+    }
     return P.wall ? launch(k_pcg_c2<T, 4, D, MODE, true>) : launch(k_pcg_c2<T, 4, D, MODE>);
 }
 
@@ -767,7 +792,10 @@ sgn_status pcg_start(PcgLaunch<double, D>& P, const double* rhs, const double* u
             CHECK_LAUNCH(ctx);
             return SGN_OK;
         };
-        s = guess ? launch(k_pcg_setup<double, 4, D, true>) : launch(k_pcg_setup<double, 4, D, false>);
+        if (P.native)
+            s = guess ? launch(k_wall_setup<double, 4, true>) : launch(k_wall_setup<double, 4, false>);
+        else
+            s = guess ? launch(k_pcg_setup<double, 4, D, true>) : launch(k_pcg_setup<double, 4, D, false>);
         if (s != SGN_OK) return s;
     }
     if (guess) {
@@ -842,6 +870,7 @@ sgn_status pcg_chunk(PcgLaunch<T, D>& P, int chunk, bool* published) {
         return pcg_chunk_eager<T, D>(P, chunk, ctx->dpub, ctx->pub_seq);
     }
     std::vector<const void*> key = {(const void*)(uintptr_t)sizeof(T), (const void*)(uintptr_t)D,
+                                    (const void*)(uintptr_t)(P.wall ? 1 : 0), (const void*)(uintptr_t)(P.native ? 1 : 0),
                                     (const void*)(uintptr_t)P.d.nx, (const void*)(uintptr_t)P.d.ny,
                                     (const void*)P.sc, (const void*)P.b.H, (const void*)P.b.xh,
                                     (const void*)P.b.rh, (const void*)P.b.ph, (const void*)P.partials,
@@ -1080,6 +1109,114 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
         info->coeffs.flat = h.flat;
     }
     if (h.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
+    if (!h.converged) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
+    return SGN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 PCG on a 2D grid between walls on the grid's own points: eta, grad h, b
+// (and the guess) are put in transform order (sgn_wall.h), the iteration runs
+// the periodic row pass between the wall column passes, and the result goes
+// back to grid order.  No periodic twin is formed.
+// ---------------------------------------------------------------------------
+struct WallOrderBufs {
+    double *eta, *gh, *b, *u;
+};
+void carve_wall_order(Carve& cv, const Dims& d, WallOrderBufs* w) {
+    w->eta = cv.take<double>(d.N);
+    w->gh = cv.take<double>(2 * d.N);
+    w->b = cv.take<double>(2 * d.N);
+    w->u = cv.take<double>(2 * d.N);
+}
+
+// A scalar or a 2D vector field (u sine along x, v sine along y) between grid
+// order and transform order.
+sgn_status wall_order(sgn_ctx* ctx, const Dims& d, const double* src, double* dst, bool vector, bool to_order) {
+    ProfScope ps(ctx, SGN_KERNEL_WALL_ORDER);
+    const int nf = vector ? 2 : 1;
+    const unsigned sx = vector ? 1u : 0u, sy = vector ? 2u : 0u;
+    hipLaunchKernelGGL(k_wall_order, dim3(flat_blocks(d.N * nf)), dim3(256), 0, ctx->stream, d.nx, d.ny, nf, sx, sy,
+                       to_order ? 1 : 0, src, dst);
+    CHECK_LAUNCH(ctx);
+    return SGN_OK;
+}
+
+// Solves between walls that run on the grid's own points; the others (1D,
+// mixed precision, GMRES) run on the periodic twin.
+bool wall_native(const Dims& d, const sgn_solve_opts& o) {
+    return d.D == 2 && d.bc == SGN_BC_WALLS && o.method == SGN_PCG && o.precision == SGN_FP64 &&
+           4 * d.nx <= TW_SIZE && 4 * d.ny <= TW_SIZE;
+}
+
+sgn_status solve_wall_native(sgn_ctx* ctx, const Dims& dw, const double* eta, const double* gh, const double* rhs,
+                             double* u, const sgn_coeffs* coeffs, int flat, const sgn_solve_opts& o,
+                             sgn_solve_info* info, void* ws) {
+    if (o.method != SGN_PCG || o.precision != SGN_FP64) return fail(ctx, SGN_EINVAL, "wall solve: FP64 PCG only");
+    if (!(o.tol > 0.0) || o.max_iter < 1) return fail(ctx, SGN_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (coeffs && !(coeffs->sigma > 0.0 && coeffs->alpha > 0.0))
+        return fail(ctx, SGN_EINVAL, "coefficients must be positive");
+    // wavenumbers of the slots: s pi / L
+    Dims d = dw;
+    d.tpx = 0.5 * kTwoPi / d.Lx;
+    d.tpy = 0.5 * kTwoPi / d.Ly;
+    Carve cv(ws);
+    WallOrderBufs w;
+    carve_wall_order(cv, d, &w);
+    Common cm = carve_common(cv);
+    PcgLaunch<double, 2> P;
+    P.native = true;
+    P.ctx = ctx;
+    P.d = d;
+    P.rl = row_launch<double>(d.nx, d.ny, true);
+    P.cl = col_launch<double>(d.nx, d.ny);
+    P.b = carve_pcg<double>(cv, d, false);
+    P.sc = cm.sc;
+    P.partials = cm.partials;
+    P.eta = w.eta;
+    P.gh = w.gh;
+    const bool guess = o.x0_is_guess != 0;
+    sgn_status s;
+    if ((s = wall_order(ctx, d, eta, w.eta, false, true)) != SGN_OK) return s;
+    if ((s = wall_order(ctx, d, gh, w.gh, true, true)) != SGN_OK) return s;
+    if ((s = wall_order(ctx, d, rhs, w.b, true, true)) != SGN_OK) return s;
+    if (guess && (s = wall_order(ctx, d, u, w.u, true, true)) != SGN_OK) return s;
+    // the coefficients are pointwise extrema: taken on the grid-order fields
+    if (coeffs) {
+        if ((s = init_scal(ctx, P.sc, o.tol, o.max_iter, d.inv_n, coeffs, guess ? 0 : 1)) != SGN_OK) return s;
+    } else {
+        const ScalInit in{o.tol, o.max_iter, d.inv_n, guess ? 0 : 1};
+        if ((s = launch_coeffs(ctx, d, eta, gh, flat, o.coeff_kind, P.sc, P.partials, nullptr, nullptr, &in)) !=
+            SGN_OK)
+            return s;
+    }
+    if ((s = pcg_start<2>(P, w.b, w.u, guess, nullptr)) != SGN_OK) return s;
+    LoopOut lo;
+    if ((s = pcg_loop<double, 2>(P, o.max_iter, o.check_every, &lo)) != SGN_OK) return s;
+    if ((s = read_scal(ctx, P.sc)) != SGN_OK) return s;
+    const SolveScal& h = *ctx->hscal;
+    if (h.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
+    // the iterate is returned on success and when max_iter stops the solve
+    {
+        auto k = k_wall_from_S<double, 4>;
+        const size_t lds = col_lds_bytes<double>(P.cl.g, 2);
+        HIPCHK(ctx, allow_lds(k, lds));
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), lds, ctx->stream, P.cl.g, ctx->tw64,
+                           (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
+        CHECK_LAUNCH(ctx);
+    }
+    if ((s = rows_inv<double, double>(ctx, d, {P.b.H, P.b.H + d.NS}, {w.u, w.u + d.N})) != SGN_OK) return s;
+    if ((s = wall_order(ctx, d, w.u, u, true, false)) != SGN_OK) return s;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (info) {
+        info->iters = h.iter;
+        info->outer_iters = 0;
+        info->converged = h.converged;
+        info->relres = h.relres;
+        info->coeffs.sigma = h.sig;
+        info->coeffs.alpha = h.alp;
+        info->coeffs.kappa_ub = h.kap;
+        info->coeffs.flat = h.flat;
+    }
     if (!h.converged) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
     return SGN_OK;
 }
@@ -2947,6 +3084,9 @@ sgn_status sgn_krylov_solve(sgn_ctx* ctx, const sgn_grid* grid, const double* et
     // without given coefficients the flat formulas apply iff |grad h|_max = 0
     if (d.bc != SGN_BC_WALLS)
         return solve_dispatch(ctx, d, eta, grad_h, rhs, u, coeffs, coeffs ? coeffs->flat : -1, o, info, ws);
+    if (wall_native(d, o)) {
+        return solve_wall_native(ctx, d, eta, grad_h, rhs, u, coeffs, coeffs ? coeffs->flat : -1, o, info, ws);
+    }
     const Dims t = twin_dims(d);
     WallBufs w;
     Carve cv(ws);

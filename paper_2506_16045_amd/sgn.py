@@ -315,7 +315,7 @@ class Context:
     # -- kernel timing ---------------------------------------------------------
     KERNEL_KINDS = ("pcg_c1", "pcg_r1", "pcg_c2", "pcg_init", "rows", "cols",
                     "pcg_c1_f32", "pcg_r1_f32", "pcg_c2_f32", "pcg_init_f32", "batch",
-                    "rhs_rows_fwd", "rhs_cols", "rhs_rows_inv", "rhs_flux", "batch_step")
+                    "rhs_rows_fwd", "rhs_cols", "rhs_rows_inv", "rhs_flux", "batch_step", "wall_order")
 
     def profile_begin(self):
         self._sync_stream()

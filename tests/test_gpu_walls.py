@@ -112,10 +112,11 @@ def test_rhs_between_walls(ctx, g):
 
 @pytest.mark.parametrize("g", GRIDS, ids=IDS)
 def test_pcg_fp64_matches_oracle(ctx, g):
-    """Solutions equal the oracle's wall solve.  On the row/column path the new
-    residual of every iteration is projected onto the reflection-symmetric modes,
-    so the iteration is the cosine / sine one and its count equals the wall
-    oracle's (+-1).  Twins of up to 8192 points run on the one-workgroup 1D solver
+    """Solutions equal the oracle's wall solve.  2D grids run on their own points
+    in cosine / sine amplitudes, and 1D twins on the row/column path project the
+    new residual of every iteration onto the reflection-symmetric modes, so the
+    iteration is the cosine / sine one and its count equals the wall oracle's
+    (+-1).  Twins of up to 8192 points run on the one-workgroup 1D solver
     without that projection: rounding there seeds the wrong-parity subspace (the
     constant velocity mode lives only there), which CG amplifies at low
     wavenumbers before it resolves it, so the count equals (+-1) the oracle's
@@ -179,6 +180,70 @@ def test_mixed_and_gmres_and_warm_start(ctx, g):
     u0 = _t(u_ref)
     _, res = ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), u=u0, opts=sgn.solve_opts(tol=1e-11, x0_is_guess=True))
     assert res.converged and res.iters == 0
+
+
+@pytest.mark.parametrize("g", [GRIDS[4], GRIDS[5], GRIDS[6], GRIDS[8]], ids=[IDS[4], IDS[5], IDS[6], IDS[8]])
+def test_2d_fp64_pcg_runs_on_the_wall_grid(ctx, g):
+    """A 2D FP64 PCG solve between walls runs on the grid's own points: the
+    fields are put in the cosine / sine transform order and back (four order
+    passes: eta, grad h, b, the result; five with a guess), no twin is formed,
+    and the iterate after a fixed number of iterations equals the oracle's
+    (section 3.2: the same iteration on the same amplitudes).  A guess near the
+    solution is taken as x_0.  Mixed-precision solves run on the twin (no order
+    pass)."""
+    from paper_2506_16045_amd import sgn
+    from oracle import krylov
+    print(f"walls native {g}", flush=True)
+    eta, h, b = _fields(g, 36)
+    gh, fl = W.bathy_gradient(h, g)
+    ctx.profile_begin()
+    u, res = ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), opts=sgn.solve_opts(tol=1e-12))
+    prof = ctx.profile_end()
+    assert res.converged and prof["wall_order"][0] == 4
+    u_ref, it_ref, ok, co = W.pcg_solve(eta, gh, fl, b, g, tol=1e-12)
+    assert ok and rel(_n(u), u_ref) <= 1e-10 and abs(res.iters - it_ref) <= 1
+    s_, a_, _ = co
+    if g.npts >= 128:   # tiny systems converge within a few iterations
+        for k in (1, 3):
+            u_k, _, _, _ = krylov.pcg(lambda v: W.apply_G(eta, gh, v, g), lambda r: W.solve_A(s_, a_, r, g), b,
+                                      tol=1e-300, max_iter=k)
+            v_k, r_k = ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), opts=sgn.solve_opts(tol=1e-300, max_iter=k),
+                                        raise_on_noconv=False)
+            assert not r_k.converged and r_k.iters == k
+            assert rel(_n(v_k), u_k) <= 1e-11, k
+    rng = np.random.default_rng(37)
+    u0 = u_ref + 1e-3 * rng.normal(size=u_ref.shape) * np.abs(u_ref).max()
+    ctx.profile_begin()
+    v, rg = ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), u=_t(u0), opts=sgn.solve_opts(tol=1e-12, x0_is_guess=True))
+    prof = ctx.profile_end()
+    assert rg.converged and prof["wall_order"][0] == 5
+    v_ref, it_g, okg, _ = W.pcg_solve(eta, gh, fl, b, g, tol=1e-12, x0=u0)
+    assert okg and abs(rg.iters - it_g) <= 1 and rel(_n(v), v_ref) <= 1e-10
+    ctx.profile_begin()
+    ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), opts=sgn.solve_opts(tol=1e-11, precision=sgn.MIXED, inner_tol=1e-4))
+    prof = ctx.profile_end()
+    assert prof["wall_order"][0] == 0
+
+
+def test_2d_wall_solve_of_zero_rhs_and_fixed_coefficients(ctx):
+    """b = 0 gives u = 0 at once; caller-given (sigma, alpha) are used as given
+    (the iteration count equals the oracle PCG's with that A)."""
+    import torch
+    from paper_2506_16045_amd import sgn
+    from oracle import krylov
+    g = GRIDS[6]
+    eta, h, b = _fields(g, 38)
+    gh, fl = W.bathy_gradient(h, g)
+    u0 = torch.full((2,) + g.shape, 3.0, dtype=torch.float64, device="cuda")
+    u, res = ctx.krylov_solve(g, _t(eta), _t(gh), _t(np.zeros_like(b)), u=u0, opts=sgn.solve_opts(tol=1e-12))
+    assert res.converged and res.iters == 0 and not torch.any(u)
+    s_, a_ = 1.7, 0.9
+    u, res = ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), coeffs=sgn.Coeffs(s_, a_, 0.0, 0),
+                              opts=sgn.solve_opts(tol=1e-12))
+    u_ref, it_ref, ok, _ = krylov.pcg(lambda v: W.apply_G(eta, gh, v, g), lambda r: W.solve_A(s_, a_, r, g), b,
+                                      tol=1e-12, max_iter=2000)
+    assert ok and res.converged and abs(res.iters - it_ref) <= 1 and rel(_n(u), u_ref) <= 1e-10
+    assert res.sigma == s_ and res.alpha == a_
 
 
 def test_periodic_only_entry_points_reject_walls(ctx):
