@@ -217,15 +217,15 @@ struct RowLaunch {
     size_t lds;
     int epc;
 };
-// wide: on 2D rows of 512 to 1024 points, two entries per thread and
-// 512-thread blocks of the same rows, so that twice as many waves are resident
-// to hide the transposed accesses' latency (the grid has only ny / R blocks);
-// taken by the Krylov row pass and the plain row transforms.
+// wide: on 2D rows of 64 to 1024 points, two entries per thread and up to
+// 512-thread blocks, so that more waves are resident to hide the transposed
+// accesses' latency (the grid has only ny / R blocks); taken by the Krylov row
+// pass and the plain row transforms.
 template <typename T>
 RowLaunch row_launch(int nx, int ny, bool wide = false) {
     RowLaunch L;
     const int M = nx / 2;
-    const bool two = wide && ny > 1 && M >= 256 && M <= 512;
+    const bool two = wide && ny > 1 && M >= 32 && M <= 512;
     L.epc = two ? 2 : (M > 4096) ? 8 : 4;
     RowGeom& g = L.g;
     g.nx = nx;
@@ -236,10 +236,12 @@ RowLaunch row_launch(int nx, int ny, bool wide = false) {
     if (R < 1) R = 1;
     const int np = next_pow2(ny);
     if (R > np) R = np;
-    // keep a block per compute unit: fewer rows per block when the grid has
-    // fewer than 256 R rows (512^2: 2 rows per 256-thread block, 16.8 -> 13.6 us)
+    // keep a block per compute unit: fewer rows per block (down to 64 threads)
+    // while the grid has fewer than 256 R rows (Krylov row pass: 512^2 2 rows
+    // per block, 16.8 -> 13.6 us; 256^2 one row of 64 threads, 19.0 -> 10.2 us;
+    // 128^2 two rows, 17.4 -> 9.5 us)
     if (two)
-        while (R > 1 && ny / R < 256) R >>= 1;
+        while (R > 1 && ny / R < 256 && (R / 2) * g.TPR >= 64) R >>= 1;
     g.R = R;
     g.nblocks = (ny + R - 1) / R;
     L.threads = R * g.TPR;
@@ -270,6 +272,12 @@ ColLaunch col_launch(int nx, int ny, int epc = 4) {
     L.epc = epc;
     return L;
 }
+
+// Column geometry of the Krylov passes (the PcgLaunch of every solve): 2D
+// columns of up to 512 points take two entries per thread (256^2: C1 10.9 ->
+// 8.5 us, C2 10.5 -> 8.8 us; 512^2: C1 12.7 -> 10.2 us), longer ones four.
+template <typename T>
+ColLaunch pcg_col_launch(const Dims& d) { return col_launch<T>(d.nx, d.ny, (d.D == 2 && d.ny <= 512) ? 2 : 4); }
 
 // Column passes of a wall solve (columns of up to 512): two entries per thread,
 // 256-thread blocks as every column pass (the partial sums are reduced over 256
@@ -677,13 +685,14 @@ sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc, const cpx<fl
         return SGN_OK;
     };
     sgn_status s;
+    const bool e2 = L.epc == 2;
     if (mode == C1_COPY)
-        s = launch(k_pcg_c1<T, 4, D, C1_COPY>, P.b.ph);
+        s = launch(e2 ? k_pcg_c1<T, 2, D, C1_COPY> : k_pcg_c1<T, 4, D, C1_COPY>, P.b.ph);
     else if (mode == C1_ACCUM) {
         if (sizeof(T) != 8 || !dx) return fail(P.ctx, SGN_EINVAL, "pcg_c1: accumulate needs an FP64 solve");
-        s = launch(k_pcg_c1<T, 4, D, C1_ACCUM>, P.b.xh);
+        s = launch(e2 ? k_pcg_c1<T, 2, D, C1_ACCUM> : k_pcg_c1<T, 4, D, C1_ACCUM>, P.b.xh);
     } else
-        s = launch(k_pcg_c1<T, 4, D, C1_UPDATE>, P.b.ph);
+        s = launch(e2 ? k_pcg_c1<T, 2, D, C1_UPDATE> : k_pcg_c1<T, 4, D, C1_UPDATE>, P.b.ph);
     if (s != SGN_OK) return s;
     CHECK_LAUNCH(P.ctx);
     return SGN_OK;
@@ -743,6 +752,7 @@ sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out, con
             return fail(P.ctx, SGN_EINVAL, "pcg_c2: wall column pass takes updates and the initial residual only");
         }
     }
+    if (L.epc == 2) return P.wall ? launch(k_pcg_c2<T, 2, D, MODE, true>) : launch(k_pcg_c2<T, 2, D, MODE>);
     return P.wall ? launch(k_pcg_c2<T, 4, D, MODE, true>) : launch(k_pcg_c2<T, 4, D, MODE>);
 }
 
@@ -807,6 +817,8 @@ sgn_status pcg_start(PcgLaunch<double, D>& P, const double* rhs, const double* u
             s = guess ? launch(k_wall_setup<double, 2, true>) : launch(k_wall_setup<double, 2, false>);
         else if (P.native)
             s = guess ? launch(k_wall_setup<double, 4, true>) : launch(k_wall_setup<double, 4, false>);
+        else if (P.cl.epc == 2)
+            s = guess ? launch(k_pcg_setup<double, 2, D, true>) : launch(k_pcg_setup<double, 2, D, false>);
         else
             s = guess ? launch(k_pcg_setup<double, 4, D, true>) : launch(k_pcg_setup<double, 4, D, false>);
         if (s != SGN_OK) return s;
@@ -1055,7 +1067,7 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     P.ctx = ctx;
     P.d = d;
     P.rl = row_launch<double>(d.nx, d.ny, true);
-    P.cl = col_launch<double>(d.nx, d.ny);
+    P.cl = pcg_col_launch<double>(d);
     P.b = carve_pcg<double>(cv, d, false);
     P.sc = cm.sc;
     P.partials = cm.partials;
@@ -1076,7 +1088,7 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     // u = IFFT(x_hat) (and the stepper's offset record); stored a second time after
     // further iterations, the offset accumulates the difference
     auto store = [&](bool redo) -> sgn_status {
-        auto k = k_cols_from_S<double, 4, D>;
+        auto k = P.cl.epc == 2 ? k_cols_from_S<double, 2, D> : k_cols_from_S<double, 4, D>;
         HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
         hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream,
                            P.cl.g, ctx->tw64, (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
@@ -1252,7 +1264,7 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     P.ctx = ctx;
     P.d = d;
     P.rl = row_launch<double>(d.nx, d.ny, true);
-    P.cl = col_launch<double>(d.nx, d.ny);
+    P.cl = pcg_col_launch<double>(d);
     P.b = carve_pcg<double>(cv, d, true);
     P.sc = cm.sc;
     P.partials = cm.partials;
@@ -1263,7 +1275,7 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     Q.ctx = ctx;
     Q.d = d;
     Q.rl = row_launch<float>(d.nx, d.ny, true);
-    Q.cl = col_launch<float>(d.nx, d.ny);
+    Q.cl = pcg_col_launch<float>(d);
     Q.b = carve_pcg<float>(cv, d, false);
     Q.sc = cm.sc + 1;
     Q.partials = cm.partials;
@@ -1317,7 +1329,7 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     }
     if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
     {
-        auto k = k_cols_from_S<double, 4, D>;
+        auto k = P.cl.epc == 2 ? k_cols_from_S<double, 2, D> : k_cols_from_S<double, 4, D>;
         HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
         hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
                            (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
@@ -1481,7 +1493,7 @@ sgn_status solve_gmres(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     P.ctx = ctx;
     P.d = d;
     P.rl = row_launch<double>(d.nx, d.ny, true);
-    P.cl = col_launch<double>(d.nx, d.ny);
+    P.cl = pcg_col_launch<double>(d);
     P.b = carve_pcg<double>(cv, d, false);
     P.sc = cm.sc;
     P.partials = cm.partials;
@@ -1792,7 +1804,7 @@ sgn_status apply_G(sgn_ctx* ctx, const Dims& d, const double* eta, const double*
     P.ctx = ctx;
     P.d = d;
     P.rl = row_launch<double>(d.nx, d.ny, true);
-    P.cl = col_launch<double>(d.nx, d.ny);
+    P.cl = pcg_col_launch<double>(d);
     P.b = carve_pcg<double>(cv, d, false);
     P.sc = cm.sc;
     P.partials = cm.partials;
@@ -1808,7 +1820,7 @@ sgn_status apply_G(sgn_ctx* ctx, const Dims& d, const double* eta, const double*
     }
     if ((s = rows_fwd<double, double>(ctx, d, usrc, hdst)) != SGN_OK) return s;
     {
-        auto k = k_cols_to_S<double, 4, D>;
+        auto k = P.cl.epc == 2 ? k_cols_to_S<double, 2, D> : k_cols_to_S<double, 4, D>;
         HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
         hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
                            (const cpx<double>*)P.b.H, d.NS, P.b.xh);
@@ -2590,7 +2602,7 @@ sgn_status sbdf2_R(sgn_state* st, cpx<double>* Rout) {
     P.ctx = ctx;
     P.d = d;
     P.rl = row_launch<double>(d.nx, d.ny, true);
-    P.cl = col_launch<double>(d.nx, d.ny);
+    P.cl = pcg_col_launch<double>(d);
     P.b = carve_pcg<double>(cv, d, false);
     P.sc = cm.sc;
     P.partials = cm.partials;

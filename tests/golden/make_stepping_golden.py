@@ -12,7 +12,8 @@ here touches the HIP library.  Outputs, next to this file:
                     and the linearly implicit SBDF2 (Eq:MM); eta, U, u per leg
                     and the oracle's Krylov iteration totals.
   c3_256_rk4.npz    the 2D bump workload at 256 x 256 (same domain, bump,
-                    wave, dt = 0.02, tol 1e-10) after 500 RK4 steps.
+                    wave, dt = 0.02) after 500 RK4 steps: at the workload's
+                    tol 1e-10 (eta, U, u, iters) and at tol 1e-13 (*_tight).
   stepping_checks.json
                     what the runs show about the readings: SBDF2 at dt = 0.02
                     on the shelf stays bounded and within O(dt^2) of RK4 (the
@@ -146,10 +147,12 @@ def make_c3_small(checks):
     t0 = time.time()
     (e, U, u), iters = run_leg(cfg, "rk4", C3_SMALL_STEPS)
     sec = time.time() - t0
-    np.savez_compressed(os.path.join(HERE, "c3_256_rk4.npz"), eta=e, U=U, u=u,
-                        iters=np.array([len(iters), int(np.sum(iters))], dtype=np.int64))
     print("c3-256 tol 1e-10 done", sec, flush=True)
     (e2, U2, u2), iters2 = run_leg(cfg, "rk4", C3_SMALL_STEPS, tol=1e-13)
+    np.savez_compressed(os.path.join(HERE, "c3_256_rk4.npz"), eta=e, U=U, u=u,
+                        iters=np.array([len(iters), int(np.sum(iters))], dtype=np.int64),
+                        eta_tight=e2, U_tight=U2, u_tight=u2,
+                        iters_tight=np.array([len(iters2), int(np.sum(iters2))], dtype=np.int64))
     checks["c3_256_rk4_500"] = {
         "steps": C3_SMALL_STEPS, "tol": cfg["tol"], "seconds": sec,
         "iters_per_solve": float(np.mean(iters)),

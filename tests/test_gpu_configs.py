@@ -10,10 +10,16 @@
   (tests/golden/c2_legs.npz, written by tests/golden/make_stepping_golden.py,
   which calls only the oracle).
 * 2D bump, RK4 dt = 0.02, tol 1e-10: 500 steps at 256 x 256 against the stored
-  oracle run, and 5 steps of the full 1024 x 1024 workload against the oracle
+  oracle runs, and 5 steps of the full 1024 x 1024 workload against the oracle
   run here (~50 s on one core).
 Gates: 1e-10 relative L2 per field (zeta, u, U) for FP64, 1e-9 for the mixed
-form.  Each test prints its case before the device work starts."""
+form.  Over the 500 steps at 256 x 256 the solver tolerance itself moves the
+trajectory: the oracle at the workload's tol 1e-10 ends 8.8e-11 (u) from its own
+run at tol 1e-13, so two correct solvers at tol 1e-10 can end up to twice that
+apart.  The FP64 gate is therefore applied to a device run at tol 1e-12 against
+the oracle's tol-1e-13 trajectory, and the run at the workload's tolerance is
+held to twice the oracle's own drift against the oracle's run at that
+tolerance.  Each test prints its case before the device work starts."""
 import os
 
 import numpy as np
@@ -136,6 +142,10 @@ def test_shelf_2000_steps_per_leg(ctx, c2_golden, leg, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_bump_256_500_rk4_steps(ctx, precision):
+    """The 500 steps at the workload's tolerance 1e-10.  FP64: the oracle's solve
+    count, iterations within one per solve, and the fields within twice the
+    oracle's own tolerance drift (its tol-1e-10 run against its tol-1e-13 run) of
+    the oracle's tol-1e-10 run; mixed: within the mixed gate."""
     cfg = I.config_c3(256)
     print(f"c3 256x256 rk4 500 steps {precision}", flush=True)
     st = _state(ctx, cfg)
@@ -143,12 +153,35 @@ def test_bump_256_500_rk4_steps(ctx, precision):
     assert info.converged and info.steps_done == 500
     with np.load(os.path.join(GOLDEN, "c3_256_rk4.npz")) as z:
         ref = (z["eta"], z["U"], z["u"])
+        tight = (z["eta_tight"], z["U_tight"], z["u_tight"])
         solves, iters = (int(v) for v in z["iters"])
     assert info.solves == solves
+    err = _errors(st, cfg["h"], ref)
+    print(f"  error vs the oracle at tol 1e-10: {err}", flush=True)
     if precision == "fp64":
         assert abs(info.iters - iters) <= solves
-    err = _errors(st, cfg["h"], ref)
-    assert max(err.values()) <= _gate(precision), err
+        drift = dg.field_errors(*ref, *tight, cfg["h"])
+        for k in err:
+            assert err[k] <= 2.0 * drift[k], (k, err, drift)
+    else:
+        assert max(err.values()) <= MIXED_GATE, err
+    st.close()
+
+
+def test_bump_256_500_rk4_steps_fp64_gate(ctx):
+    """FP64 parity over the 500 steps with the tolerance drift taken out: the device
+    at tol 1e-12 against the oracle's trajectory at tol 1e-13, to 1e-10."""
+    from paper_2506_16045_amd import sgn
+    cfg = I.config_c3(256)
+    print("c3 256x256 rk4 500 steps fp64 tol 1e-12", flush=True)
+    st = _state(ctx, cfg)
+    info = st.step_rk4(cfg["dt"], 500, sgn.solve_opts(tol=1e-12, check_every=8))
+    assert info.converged and info.steps_done == 500
+    with np.load(os.path.join(GOLDEN, "c3_256_rk4.npz")) as z:
+        tight = (z["eta_tight"], z["U_tight"], z["u_tight"])
+    err = _errors(st, cfg["h"], tight)
+    print(f"  error vs the oracle at tol 1e-13: {err}", flush=True)
+    assert max(err.values()) <= FP64_GATE, err
     st.close()
 
 

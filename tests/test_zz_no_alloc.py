@@ -83,7 +83,11 @@ def test_noalloc_matches_oracle_and_reuses_scratch():
         s, a, _ = op.coefficients(eta, gh, fl)
         u_ref, it, ok, _ = krylov.pcg(lambda v: op.apply_G(eta, gh, v, g), lambda q: op.solve_A(s, a, q, g), b,
                                       tol=1e-12, max_iter=3000)
-        assert ok and abs(r.iters - it) <= 1
+        # CG in floating point: over the ~300 iterations these problems take at tol
+        # 1e-12 the count depends on the rounding order of the dot products (64 x 64:
+        # 323 on the device, 321 in the oracle, solutions equal to 9e-14), so the
+        # counts agree to 1 %
+        assert ok and abs(r.iters - it) <= max(1, it // 100), (r.iters, it)
         err = np.linalg.norm(_n(u) - u_ref) / np.linalg.norm(u_ref)
         assert err <= 1e-10, err
     ctx.close()
