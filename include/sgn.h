@@ -62,9 +62,12 @@ typedef enum sgn_bc {
                            * keeps the reflected fields and the stepping history of the twin),
                            * and their workspace queries; the de-aliasing calls, the batched
                            * solver and the server return SGN_EUNSUPPORTED.  Sizes: 1D
-                           * nx <= 8192, 2D nx <= 2048 and ny <= 512.  Internally the fields
-                           * are reflected (even / odd) onto the periodic grid of twice the
-                           * length per axis, where every step of the periodic path runs. */
+                           * nx <= 8192, 2D nx <= 2048 and ny <= 512.  A 2D FP64 PCG solve
+                           * (sgn_krylov_solve, sgn_krylov_solve_noalloc) runs on the grid's
+                           * own points in cosine / sine amplitudes; every other call
+                           * reflects the fields (even / odd) onto the periodic grid of twice
+                           * the length per axis, where the periodic path runs.  The
+                           * workspace queries cover both. */
 } sgn_bc;
 
 /* Grid (section 6.1): dim 1 or 2; ny and Ly are ignored when dim = 1; bc takes

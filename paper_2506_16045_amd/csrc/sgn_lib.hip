@@ -1219,6 +1219,16 @@ sgn_status solve_wall_native(sgn_ctx* ctx, const Dims& dw, const double* eta, co
     if ((s = pcg_loop<double, 2>(P, o.max_iter, o.check_every, &lo)) != SGN_OK) return s;
     if ((s = read_scal(ctx, P.sc)) != SGN_OK) return s;
     const SolveScal& h = *ctx->hscal;
+    if (info) {
+        info->iters = h.iter;
+        info->outer_iters = 0;
+        info->converged = h.converged;
+        info->relres = h.relres;
+        info->coeffs.sigma = h.sig;
+        info->coeffs.alpha = h.alp;
+        info->coeffs.kappa_ub = h.kap;
+        info->coeffs.flat = h.flat;
+    }
     if (h.status == -2) return fail(ctx, SGN_EDOMAIN, "non-positive depth or non-finite data in the solve");
     // the iterate is returned on success and when max_iter stops the solve
     {
@@ -1232,16 +1242,6 @@ sgn_status solve_wall_native(sgn_ctx* ctx, const Dims& dw, const double* eta, co
     if ((s = rows_inv<double, double>(ctx, d, {P.b.H, P.b.H + d.NS}, {w.u, w.u + d.N})) != SGN_OK) return s;
     if ((s = wall_order(ctx, d, w.u, u, true, false)) != SGN_OK) return s;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    if (info) {
-        info->iters = h.iter;
-        info->outer_iters = 0;
-        info->converged = h.converged;
-        info->relres = h.relres;
-        info->coeffs.sigma = h.sig;
-        info->coeffs.alpha = h.alp;
-        info->coeffs.kappa_ub = h.kap;
-        info->coeffs.flat = h.flat;
-    }
     if (!h.converged) return fail(ctx, SGN_ENOCONV, "Krylov solve did not reach the tolerance");
     return SGN_OK;
 }
