@@ -533,6 +533,7 @@ struct LinJob {
     cpx<T>* dst[LINJ_MAXO];
     int ni, no;
     int code[LINJ_MAXO][LINJ_MAXI];
+    int kin[LINJ_MAXI], kout[LINJ_MAXO];   // series kinds of a wall job (bit 0: sine along x, bit 1: along y)
 };
 template <typename T>
 struct LinJobs {

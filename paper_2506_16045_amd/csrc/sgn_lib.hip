@@ -51,6 +51,7 @@ struct sgn_ctx {
     int* stage_last = nullptr;    // the running stepper solve's counters (state-owned), if any
     bool stage = false;           // solving inside a stepper: skip the final scalar readback
     bool wall_twin = false;       // solving on the periodic twin of a wall grid
+    bool wall_native = false;     // stepping a 2D wall grid on its own points (fields in transform order)
     int cus = 256;                // compute units of the device
     void* hbatch = nullptr;       // pinned staging of batch item tables and results
     size_t hbatch_bytes = 0;
@@ -492,9 +493,10 @@ struct LinJobSpec {
     std::vector<const cpx<double>*> src;
     std::vector<cpx<double>*> dst;
     std::vector<std::vector<int>> codes;
+    std::vector<int> kin, kout;   // wall jobs: series kinds of the inputs and outputs
 };
 sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSpec>& spec, double scale,
-                         int kind = SGN_KERNEL_COLS) {
+                         int kind = SGN_KERNEL_COLS, bool wall = false) {
     ProfScope ps(ctx, kind);
     if (spec.empty() || spec.size() > (size_t)LINJ_MAXJ) return fail(ctx, SGN_EINVAL, "cols_lin_jobs: job count");
     LinJobs<double> J{};
@@ -516,6 +518,25 @@ sgn_status cols_lin_jobs(sgn_ctx* ctx, const Dims& d, const std::vector<LinJobSp
     }
     int maxi = 0;
     for (int k = 0; k < J.n; ++k) maxi = std::max(maxi, J.j[k].ni);
+    if (wall) {
+        // a 2D wall grid on its own points: the slot coefficients of each job's kinds
+        for (int k = 0; k < J.n; ++k) {
+            const LinJobSpec& sp = spec[k];
+            LinJob<double>& j = J.j[k];
+            if (j.ni > 3 || j.no > 3 || sp.kin.size() != (size_t)j.ni || sp.kout.size() != (size_t)j.no)
+                return fail(ctx, SGN_EINVAL, "cols_lin_jobs: a wall job takes up to three inputs and outputs, kinds given");
+            for (int i = 0; i < j.ni; ++i) j.kin[i] = sp.kin[i];
+            for (int o = 0; o < j.no; ++o) j.kout[o] = sp.kout[o];
+        }
+        const ColLaunch L = wall_col_launch(d.nx, d.ny);
+        const size_t lds = col_lds_bytes<double>(L.g, 3);
+        auto k = L.epc == 2 ? k_wall_cols_jobs<double, 2> : k_wall_cols_jobs<double, 4>;
+        HIPCHK(ctx, allow_lds(k, lds));
+        hipLaunchKernelGGL(k, dim3(L.g.nblocks * J.n), dim3(L.threads), lds, ctx->stream, L.g, J, ctx->tw64, d.tpx,
+                           d.tpy, scale);
+        CHECK_LAUNCH(ctx);
+        return SGN_OK;
+    }
     const int epc = col_epc(d.ny);
     ColLaunch L = col_launch<double>(d.nx, d.ny, epc);
     // the inputs, then the outputs, are transformed up to three at a time in lockstep
@@ -1064,10 +1085,11 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     Common cm = carve_common(cv);
     PcgLaunch<double, D> P;
     P.wall = ctx->wall_twin;
+    P.native = D == 2 && ctx->wall_native;
     P.ctx = ctx;
     P.d = d;
     P.rl = row_launch<double>(d.nx, d.ny, true);
-    P.cl = pcg_col_launch<double>(d);
+    P.cl = P.native ? wall_col_launch(d.nx, d.ny) : pcg_col_launch<double>(d);
     P.b = carve_pcg<double>(cv, d, false);
     P.sc = cm.sc;
     P.partials = cm.partials;
@@ -1088,7 +1110,8 @@ sgn_status solve_fp64(sgn_ctx* ctx, const Dims& d, const double* eta, const doub
     // u = IFFT(x_hat) (and the stepper's offset record); stored a second time after
     // further iterations, the offset accumulates the difference
     auto store = [&](bool redo) -> sgn_status {
-        auto k = P.cl.epc == 2 ? k_cols_from_S<double, 2, D> : k_cols_from_S<double, 4, D>;
+        auto k = P.native ? (P.cl.epc == 2 ? k_wall_from_S<double, 2> : k_wall_from_S<double, 4>)
+                          : (P.cl.epc == 2 ? k_cols_from_S<double, 2, D> : k_cols_from_S<double, 4, D>);
         HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
         hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream,
                            P.cl.g, ctx->tw64, (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
@@ -1650,6 +1673,8 @@ sgn_status solve_dispatch(sgn_ctx* ctx, const Dims& d, const double* eta, const 
                           sgn_solve_info* info, void* ws) {
     if (o.method != SGN_PCG && o.method != SGN_GMRES) return fail(ctx, SGN_EINVAL, "unknown method");
     if (!(o.tol > 0.0) || o.max_iter < 1) return fail(ctx, SGN_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (ctx->wall_native && !(d.D == 2 && o.method == SGN_PCG && o.precision == SGN_FP64))
+        return fail(ctx, SGN_EUNSUPPORTED, "a wall grid on its own points takes FP64 PCG only");
     if (coeffs && !(coeffs->sigma > 0.0 && coeffs->alpha > 0.0))
         return fail(ctx, SGN_EINVAL, "coefficients must be positive");
     if (o.method == SGN_GMRES) {
@@ -1880,6 +1905,9 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     RhsBufs b = carve_rhs(cv, d);
     const size_t N = d.N, NS = d.NS;
     const int nd2 = D == 2 ? 3 : 1;
+    // a 2D grid between walls on its own points: eta, grad h, u (and the results)
+    // in transform order; only the column operators differ
+    const bool wall = D == 2 && ctx->wall_native;
     cpx<double>* HA = b.H;                    // 2D + 1
     cpx<double>* HB = HA + (2 * D + 1) * NS;  // nd2 + 1
     cpx<double>* OA = HB + (nd2 + 1) * NS;    // 2D + 2
@@ -1934,12 +1962,14 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
         // at most three transformed inputs in registers, run side by side in one
         // launch: [u, v] -> [delta, dx delta, dy delta]; [eu, ev, eta] -> [m, dx eta,
         // dy eta]; [beta] -> [dx beta, dy beta]
+        // between walls (fields in transform order) the kinds: u sine along x (1),
+        // v sine along y (2), scalars cosine (0), u v sine along both (3)
         std::vector<LinJobSpec> jobs = {
-            {{cA[0], cA[1]}, {oA[0], oA[1], oA[2]}, {{2, 3}, {4, 5}, {5, 6}}},
-            {{cA[2], cA[3], cA[4]}, {oA[3], oA[4], oA[5]}, {{2, 3, 0}, {0, 0, 2}, {0, 0, 3}}},
-            {{cB[3]}, {oB[0], oB[1]}, {{2}, {3}}},
+            {{cA[0], cA[1]}, {oA[0], oA[1], oA[2]}, {{2, 3}, {4, 5}, {5, 6}}, {1, 2}, {0, 1, 2}},
+            {{cA[2], cA[3], cA[4]}, {oA[3], oA[4], oA[5]}, {{2, 3, 0}, {0, 0, 2}, {0, 0, 3}}, {1, 2, 0}, {0, 1, 2}},
+            {{cB[3]}, {oB[0], oB[1]}, {{2}, {3}}, {0}, {1, 2}},
         };
-        if ((s = cols_lin_jobs(ctx, d, jobs, d.inv_n, SGN_KERNEL_RHS_COLS)) != SGN_OK) return s;
+        if ((s = cols_lin_jobs(ctx, d, jobs, d.inv_n, SGN_KERNEL_RHS_COLS, wall)) != SGN_OK) return s;
     } else {
         if ((s = cols_lin<double>(ctx, d, cA, oA, {{2, 0, 0}, {4, 0, 0}, {0, 2, 0}, {0, 0, 2}}, d.inv_n)) != SGN_OK)
             return s;
@@ -1979,9 +2009,9 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     if (D == 2) {
         // one job per component, side by side (S and the mixed flux term are
         // transformed by both; the shorter chain per block wins over the saved work)
-        std::vector<LinJobSpec> fj = {{{HA, cB[0], cB[1]}, {gS[0]}, {{2, 2, 3}}},
-                                      {{HA, cB[1], cB[2]}, {gS[1]}, {{3, 2, 3}}}};
-        if ((s = cols_lin_jobs(ctx, d, fj, d.inv_n, SGN_KERNEL_RHS_FLUX)) != SGN_OK) return s;
+        std::vector<LinJobSpec> fj = {{{HA, cB[0], cB[1]}, {gS[0]}, {{2, 2, 3}}, {0, 0, 3}, {1}},
+                                      {{HA, cB[1], cB[2]}, {gS[1]}, {{3, 2, 3}}, {0, 3, 0}, {2}}};
+        if ((s = cols_lin_jobs(ctx, d, fj, d.inv_n, SGN_KERNEL_RHS_FLUX, wall)) != SGN_OK) return s;
     } else {
         if ((s = cols_lin<double>(ctx, d, {HA, cB[0]}, gS, {{2, 2}}, d.inv_n)) != SGN_OK) return s;
     }
@@ -2333,10 +2363,19 @@ struct sgn_state {
     // de-aliased right-hand side (sgn_state_set_dealias): buffers in the caller's workspace
     int dealias = 0;
     DealiasBufs dl{};
-    // between walls: the periodic state on the twin that every stepping call runs
+    // between walls: the periodic state on the twin, and (2D) the state on the
+    // grid's own points with its fields in transform order, which FP64 PCG calls
+    // of RK4 and Adams-Bashforth take; path: the sub-state of the last call (0
+    // none, 1 twin, 2 own points)
     sgn_state* twin = nullptr;
     WallStateBufs wb{};
-    ~sgn_state() { delete twin; }
+    sgn_state* nat = nullptr;
+    WallStateBufs nb{};
+    int path = 0;
+    ~sgn_state() {
+        delete twin;
+        delete nat;
+    }
 };
 
 namespace {
@@ -3615,6 +3654,27 @@ sgn_status sgn_rhs(sgn_ctx* ctx, const sgn_grid* grid, const double* eta, const 
     if (s != SGN_OK) return s;
     if (!eta || !h || !grad_h || !u || !eta_t || !U_t || !ws) return fail(ctx, SGN_EINVAL, "null pointer");
     if (d.bc != SGN_BC_WALLS) return rhs_dispatch(ctx, d, eta, grad_h, u, eta_t, U_t, ws);
+    if (d.D == 2) {
+        // a 2D grid between walls on its own points: the fields in transform order
+        // through the periodic row passes and the wall column operators
+        Dims n = d;
+        n.bc = SGN_BC_PERIODIC;
+        n.tpx = 0.5 * kTwoPi / d.Lx;
+        n.tpy = 0.5 * kTwoPi / d.Ly;
+        Carve cv(ws);
+        WallStateBufs o;
+        carve_wall_state(cv, d, &o);   // h unused; gh, eta, u in order, U (the U_t result)
+        double* et = o.h;
+        if ((s = wall_order(ctx, d, eta, o.eta, false, true)) != SGN_OK) return s;
+        if ((s = wall_order(ctx, d, grad_h, o.gh, true, true)) != SGN_OK) return s;
+        if ((s = wall_order(ctx, d, u, o.u, true, true)) != SGN_OK) return s;
+        ctx->wall_native = true;
+        s = rhs_dispatch(ctx, n, o.eta, o.gh, o.u, et, o.U, static_cast<char*>(ws) + align_up(cv.off, 256));
+        ctx->wall_native = false;
+        if (s != SGN_OK) return s;
+        if ((s = wall_order(ctx, d, et, eta_t, false, false)) != SGN_OK) return s;
+        return wall_order(ctx, d, o.U, U_t, true, false);
+    }
     // between walls: the periodic right-hand side of the reflected fields, restricted
     const Dims t = twin_dims(d);
     WallBufs w;
@@ -3640,6 +3700,13 @@ sgn_status wall_steps(sgn_state* st, F call) {
     const Dims& d = st->d;
     sgn_state* tw = st->twin;
     sgn_status s;
+    if (st->path != 1) {   // the other sub-state ran last: its histories are not this one's
+        tw->t = st->t;
+        tw->steps = st->steps;
+        tw->kind = 0;
+        tw->gx_mode = -1;
+        st->path = 1;
+    }
     if ((s = wall_reflect(ctx, d, st->eta, tw->eta, false)) != SGN_OK) return s;
     if ((s = wall_reflect(ctx, d, st->U, tw->U, true)) != SGN_OK) return s;
     if ((s = wall_reflect(ctx, d, st->u, tw->u, true)) != SGN_OK) return s;
@@ -3652,6 +3719,42 @@ sgn_status wall_steps(sgn_state* st, F call) {
     st->t = tw->t;
     st->steps = tw->steps;
     return s != SGN_OK ? s : r;
+}
+
+// A stepping call of a 2D wall state on the grid's own points: eta, U, u go to
+// transform order, the periodic stepper runs with the wall column passes
+// (ctx->wall_native) and the fields come back to grid order.
+template <typename F>
+sgn_status wall_native_steps(sgn_state* st, F call) {
+    sgn_ctx* ctx = st->ctx;
+    const Dims& d = st->d;
+    sgn_state* nt = st->nat;
+    sgn_status s;
+    if (st->path != 2) {
+        nt->t = st->t;
+        nt->steps = st->steps;
+        nt->kind = 0;
+        nt->gx_mode = -1;
+        st->path = 2;
+    }
+    if ((s = wall_order(ctx, d, st->eta, nt->eta, false, true)) != SGN_OK) return s;
+    if ((s = wall_order(ctx, d, st->U, nt->U, true, true)) != SGN_OK) return s;
+    if ((s = wall_order(ctx, d, st->u, nt->u, true, true)) != SGN_OK) return s;
+    ctx->wall_native = true;
+    s = call(nt);
+    ctx->wall_native = false;
+    sgn_status r = wall_order(ctx, d, nt->eta, st->eta, false, false);
+    if (r == SGN_OK) r = wall_order(ctx, d, nt->U, st->U, true, false);
+    if (r == SGN_OK) r = wall_order(ctx, d, nt->u, st->u, true, false);
+    st->t = nt->t;
+    st->steps = nt->steps;
+    return s != SGN_OK ? s : r;
+}
+
+// Whether a stepping call of a wall state runs on the grid's own points.
+bool wall_native_call(const sgn_state* st, const sgn_solve_opts* opts) {
+    const sgn_solve_opts o = opts ? *opts : default_opts();
+    return st->nat && o.method == SGN_PCG && o.precision == SGN_FP64;
 }
 
 }  // namespace
@@ -3704,9 +3807,13 @@ size_t sgn_state_workspace_bytes(const sgn_grid* grid, int32_t precision) {
     if (check_grid(nullptr, grid, &d) != SGN_OK) return 0;
     Carve cv(nullptr);
     if (d.bc == SGN_BC_WALLS) {
+        // the layout of sgn_state_create: the twin's reflected fields, the twin's
+        // state, and in 2D the fields in transform order and their state
         const Dims t = twin_dims(d);
-        carve_wall_state(cv, t, nullptr);
-        return carve_state(cv, t, nullptr) + 256;
+        Carve c1(nullptr), c2(nullptr), c3(nullptr), c4(nullptr);
+        size_t n = align_up(carve_wall_state(c1, t, nullptr), 256) + align_up(carve_state(c2, t, nullptr), 256);
+        if (d.D == 2) n += align_up(carve_wall_state(c3, d, nullptr), 256) + carve_state(c4, d, nullptr);
+        return n + 256;
     }
     return carve_state(cv, d, nullptr) + 256;
 }
@@ -3756,6 +3863,33 @@ sgn_status sgn_state_create(sgn_ctx* ctx, const sgn_grid* grid, const double* h,
         st->ws = ws;
         st->twin = tw;
         st->wb = wb;
+        if (d.D == 2) {
+            // the state on the grid's own points: h and grad h in transform order
+            // once, its own stepping buffers after the twin's
+            Carve ct(nullptr);
+            const size_t tsz = align_up(carve_state(ct, t, nullptr), 256);
+            char* nbase = static_cast<char*>(tws) + tsz;
+            Carve cn(nbase);
+            WallStateBufs nb;
+            carve_wall_state(cn, d, &nb);
+            if ((s = wall_order(ctx, d, h, nb.h, false, true)) != SGN_OK || (s = wall_order(ctx, d, grad_h, nb.gh, true, true)) != SGN_OK) {
+                delete st;
+                return s;
+            }
+            sgn_grid ng = *grid;
+            ng.bc = SGN_BC_PERIODIC;
+            sgn_state* nt = nullptr;
+            if ((s = sgn_state_create(ctx, &ng, nb.h, nb.gh, flat, nb.eta, nb.U, nb.u, nbase + align_up(cn.off, 256),
+                                      ws, &nt)) != SGN_OK) {
+                delete st;
+                return s;
+            }
+            // wavenumbers of the slots: s pi / L
+            nt->d.tpx = 0.5 * kTwoPi / d.Lx;
+            nt->d.tpy = 0.5 * kTwoPi / d.Ly;
+            st->nat = nt;
+            st->nb = nb;
+        }
         *out = st;
         return SGN_OK;
     }
@@ -3787,6 +3921,8 @@ void sgn_state_destroy(sgn_state* st) { delete st; }
 sgn_status sgn_step_rk4(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nsteps, const sgn_solve_opts* opts,
                         sgn_step_info* info) {
     if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (st->twin && wall_native_call(st, opts))
+        return wall_native_steps(st, [&](sgn_state* nt) { return sgn_step_rk4(ctx, nt, dt, nsteps, opts, info); });
     if (st->twin)
         return wall_steps(st, [&](sgn_state* tw) { return sgn_step_rk4(ctx, tw, dt, nsteps, opts, info); });
     if (nsteps < 0 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad step arguments");
@@ -3809,6 +3945,9 @@ sgn_status sgn_step_rk4(sgn_ctx* ctx, sgn_state* st, double dt, int32_t nsteps, 
 sgn_status sgn_step_ab(sgn_ctx* ctx, sgn_state* st, int32_t order, double dt, int32_t nsteps,
                        const sgn_solve_opts* opts, sgn_step_info* info) {
     if (!ctx || !st || st->ctx != ctx) return SGN_EINVAL;
+    if (st->twin && wall_native_call(st, opts))
+        return wall_native_steps(st,
+                                 [&](sgn_state* nt) { return sgn_step_ab(ctx, nt, order, dt, nsteps, opts, info); });
     if (st->twin)
         return wall_steps(st, [&](sgn_state* tw) { return sgn_step_ab(ctx, tw, order, dt, nsteps, opts, info); });
     if (nsteps < 0 || order < 2 || order > 4 || !std::isfinite(dt)) return fail(ctx, SGN_EINVAL, "bad AB arguments");

@@ -578,4 +578,131 @@ __global__ void __launch_bounds__(256) k_wall_from_S(ColGeom g, const cpx<T>* __
     wall_col_emit<T, EPC, 2>(g, ct, dsts, twm);
 }
 
+// Coefficient of derivative code c (1 identity, 2 d/dx, 3 d/dy, 4 d2/dx2,
+// 5 d2/dxdy, 6 d2/dy2) on the slot of wavenumbers (kx, ky), for an input of
+// series kind `kind` (bit 0: sine along x, bit 1: sine along y): d/dx takes a
+// cosine amplitude to the sine one times -kx and a sine amplitude to the cosine
+// one times +kx; a second derivative along one axis is -k^2 either way.
+template <typename T>
+__device__ __forceinline__ T wall_coef(int code, T kx, T ky, int kind) {
+    const T dx = (kind & 1) ? kx : -kx;
+    const T dy = (kind & 2) ? ky : -ky;
+    switch (code) {
+        case 1: return (T)1;
+        case 2: return dx;
+        case 3: return dy;
+        case 4: return -kx * kx;
+        case 5: return dx * dy;
+        case 6: return -ky * ky;
+        default: return (T)0;
+    }
+}
+
+// Linear column operators of a 2D wall grid (the k_cols_lin_jobs of the
+// right-hand side): job jb of the launch takes blocks [jb nblocks, (jb + 1)
+// nblocks); its ni inputs (H columns of fields in transform order, kinds kin)
+// are y-transformed together in LDS, turned into slot amplitudes pair by pair,
+// combined into the no outputs (kinds kout) with the slot coefficients, turned
+// back and inverse-transformed together.  At most three inputs and three
+// outputs per job (the LDS holds three columns per block column).
+template <typename T, int EPC>
+__global__ void __launch_bounds__(256) k_wall_cols_jobs(ColGeom g, LinJobs<T> jobs, const cpx<T>* __restrict__ tw,
+                                                         T pix, T piy, T scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int jb = blockIdx.x / g.nblocks;
+    if (jb >= jobs.n) return;
+    const LinJob<T>& J = jobs.j[jb];
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, 3));
+    const ColThread<T> ct = col_thread_at<T>(g, lds, (int)blockIdx.x - jb * g.nblocks);
+    const WallColumn<T> wc = wall_column<T>(g, ct, tw, pix);
+    const cpx<T>* twy = tw_size(tw, 4 * g.ny);
+    const int ny = g.ny;
+    {
+        cpx<T> v[3][EPC];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int j = ct.t + g.TPC * e;
+                v[i][e] = (i < J.ni && ct.valid && j < ny) ? J.src[i][(size_t)ct.kx * ny + j] : C<T>(0, 0);
+            }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int j = ct.t + g.TPC * e;
+                if (j < ny) ct.buf[i * ct.fstride + j] = v[i][e];
+            }
+    }
+    __syncthreads();
+    if (J.ni == 1)
+        lds_fft<T, EPC, 1>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, false);
+    else if (J.ni == 2)
+        lds_fft<T, EPC, 2>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, false);
+    else
+        lds_fft<T, EPC, 3>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, false);
+#pragma unroll
+    for (int e_ = 0; e_ <= EPC / 2; ++e_) {
+        const int q = ct.t + g.TPC * e_;
+        if (q > ny / 2) continue;
+        const int m = (ny - q) & (ny - 1);
+        const bool self = q == m;
+        const cpx<T> wy = twy[q];
+        cpx<T> a[3][2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            a[i][0] = a[i][1] = C<T>(0, 0);
+            if (i < J.ni)
+                wall_to_slots<T>(ct.buf[i * ct.fstride + q], ct.buf[i * ct.fstride + m], wc.wx, wy, wc.k0, q == 0,
+                                 (J.kin[i] & 1) != 0, (J.kin[i] & 2) != 0, a[i][0], a[i][1]);
+        }
+        cpx<T> o[3][2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const T ky = (T)(s ? m : q) * piy;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                T re = (T)0, im = (T)0;
+                if (k < J.no) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        if (i >= J.ni) continue;
+                        re += wall_coef<T>(J.code[k][i], wc.kre, ky, J.kin[i]) * a[i][s].re;
+                        im += wall_coef<T>(J.code[k][i], wc.kim, ky, J.kin[i]) * a[i][s].im;
+                    }
+                }
+                o[k][s] = C<T>(scale * re, scale * im);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k >= J.no) continue;
+            cpx<T> F1, F2;
+            wall_from_slots<T>(o[k][0], self ? o[k][0] : o[k][1], wc.wx, wy, wc.k0, q == 0, (J.kout[k] & 1) != 0,
+                               (J.kout[k] & 2) != 0, F1, F2);
+            ct.buf[k * ct.fstride + q] = F1;
+            if (!self) ct.buf[k * ct.fstride + m] = F2;
+        }
+    }
+    __syncthreads();
+    if (J.no == 1)
+        lds_fft<T, EPC, 1>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, true);
+    else if (J.no == 2)
+        lds_fft<T, EPC, 2>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, true);
+    else
+        lds_fft<T, EPC, 3>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, true);
+    if (ct.valid) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k >= J.no) break;
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int j = ct.t + g.TPC * e;
+                if (j < ny) J.dst[k][(size_t)ct.kx * ny + j] = ct.buf[k * ct.fstride + j];
+            }
+        }
+    }
+}
+
 }  // namespace sgn

@@ -336,6 +336,68 @@ def test_steppers_between_walls_match_oracle(ctx, make, scheme):
     st.close()
 
 
+def test_2d_wall_steps_run_on_the_grid_points(ctx):
+    """RK4 and AB3 steps of a 2D wall state in FP64 PCG run on the basin's own
+    points (the fields go to the cosine / sine transform order and back once per
+    call: six order passes, none in between); a mixed-precision call runs on the
+    twin (no order pass).  Calls that switch between the two continue the same
+    run: against the oracle's RK4 run of all the steps, to the mixed gate (the
+    guess history restarts at a switch, which moves the result by no more than
+    the solver tolerance)."""
+    from paper_2506_16045_amd import sgn
+    g, h, eta, u = _basin_2d()
+    print(f"walls native steps {g}", flush=True)
+    st = _wall_state(ctx, g, h, eta, u)
+    pb = W.Problem.from_h(g, h, tol=1e-12)
+    U0 = pb.G(eta, u)
+    fp64 = sgn.solve_opts(tol=1e-12, check_every=4)
+    mixed = sgn.solve_opts(tol=1e-12, precision=sgn.MIXED, inner_tol=1e-4, check_every=4)
+    dt = 0.05
+    ctx.profile_begin()
+    i1 = st.step_rk4(dt, 3, fp64)
+    prof = ctx.profile_end()
+    assert i1.converged and prof["wall_order"][0] == 6
+    ctx.profile_begin()
+    i2 = st.step_rk4(dt, 2, mixed)
+    prof = ctx.profile_end()
+    assert i2.converged and prof["wall_order"][0] == 0
+    i3 = st.step_rk4(dt, 3, fp64)
+    assert i3.converged and i3.steps_done == 8 and abs(i3.t - 8 * dt) < 1e-12
+    ref = W.stepping.run_rk4(pb, eta, U0, u, dt, 8)
+    for a, b in zip((st.eta, st.U, st.u), ref):
+        assert rel(_n(a), b) <= 1e-9
+    assert abs(np.sum(_n(st.eta)) - np.sum(eta)) <= 1e-12 * np.sum(eta)
+    st.close()
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "ab3"])
+def test_2d_wall_steps_of_a_larger_basin(ctx, scheme):
+    """The same on a 128 x 64 basin with an uneven aspect (RK4 and AB3 on the
+    grid's points, 6 steps) against the oracle's wall steppers, per field to 1e-10."""
+    from paper_2506_16045_amd import sgn
+    g = I.grid2d_walls(128, 64, 40.0, 20.0)
+    X, Y = I.coords(g)
+    h = 1.0 - 0.3 * np.exp(-((X - 25.0) ** 2 + (Y - 8.0) ** 2) / 20.0)
+    eta = h + 0.12 * np.exp(-((X - 12.0) ** 2 + (Y - 11.0) ** 2) / 10.0)
+    u = np.zeros((2,) + g.shape)
+    print(f"walls native {scheme} {g}", flush=True)
+    st = _wall_state(ctx, g, h, eta, u)
+    pb = W.Problem.from_h(g, h, tol=1e-12)
+    U0 = pb.G(eta, u)
+    opts = sgn.solve_opts(tol=1e-12, check_every=4)
+    n, dt = 6, 0.05
+    if scheme == "rk4":
+        info = st.step_rk4(dt, n, opts)
+        ref = W.stepping.run_rk4(pb, eta, U0, u, dt, n)
+    else:
+        info = st.step_ab(3, dt, n, opts)
+        ref = W.stepping.run_ab(pb, 3, eta, U0, u, dt, n)
+    assert info.converged and info.steps_done == n
+    for a, b in zip((st.eta, st.U, st.u), ref):
+        assert rel(_n(a), b) <= 1e-10
+    st.close()
+
+
 def test_wall_state_rejects_dealiasing(ctx):
     from paper_2506_16045_amd import sgn
     g, h, eta, u = _basin_2d()
