@@ -62,12 +62,17 @@ typedef enum sgn_bc {
                            * keeps the reflected fields and the stepping history of the twin),
                            * and their workspace queries; the de-aliasing calls, the batched
                            * solver and the server return SGN_EUNSUPPORTED.  Sizes: 1D
-                           * nx <= 8192, 2D nx <= 2048 and ny <= 512.  A 2D FP64 PCG solve
-                           * (sgn_krylov_solve, sgn_krylov_solve_noalloc) runs on the grid's
-                           * own points in cosine / sine amplitudes; every other call
-                           * reflects the fields (even / odd) onto the periodic grid of twice
-                           * the length per axis, where the periodic path runs.  The
-                           * workspace queries cover both. */
+                           * nx <= 8192, 2D nx <= 2048 and ny <= 512.  On 2D grids the FP64
+                           * PCG solve (sgn_krylov_solve, sgn_krylov_solve_noalloc), sgn_rhs
+                           * and the FP64 PCG calls of sgn_step_rk4 and sgn_step_ab run on
+                           * the grid's own points in cosine / sine amplitudes; every other
+                           * call (1D, mixed precision, GMRES, sgn_apply_constraint,
+                           * sgn_precond_solve, the linearly implicit steps) reflects the
+                           * fields (even / odd) onto the periodic grid of twice the length
+                           * per axis, where the periodic path runs.  A stepping state holds
+                           * both forms; a call that uses the other form than the call before
+                           * restarts the initial-guess history.  The workspace queries cover
+                           * both. */
 } sgn_bc;
 
 /* Grid (section 6.1): dim 1 or 2; ny and Ly are ignored when dim = 1; bc takes
