@@ -259,7 +259,8 @@ def cpu_baseline_walls(cfg):
 def bench_walls(args):
     """Constraint solves in a closed basin (walls): solves/s of the library's wall path,
     FP64 (PCG on the basin's own points in cosine / sine amplitudes) and mixed
-    (reflection onto the periodic twin), with the PCG kernels timed."""
+    (reflection onto the periodic twin), with the PCG kernels timed; then FP64 RK4
+    steps of the basin through a wall stepping state (on the basin's points)."""
     import numpy as np
     import torch
 
@@ -322,8 +323,8 @@ def bench_walls(args):
            "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": main["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"walls basin {g.nx}x{g.ny} cells on {g.Lx:g}x{g.Ly:g} (FP64 PCG on the "
-                                  f"cells in cosine / sine amplitudes; mixed precision and the RK4 state on the "
+           "config": {"workload": f"walls basin {g.nx}x{g.ny} cells on {g.Lx:g}x{g.Ly:g} (FP64 PCG solves and "
+                                  f"FP64 RK4 steps on the cells in cosine / sine amplitudes; mixed precision on the "
                                   f"periodic twin {twin[0]}x{twin[1]}), Gaussian bump bathymetry, surface hump, "
                                   f"tol {cfg['tol']:g}, zero initial guess", "parallelism": "single GPU"},
            "precisions": res_by, "stepping": stepping, "roofline": roof,
