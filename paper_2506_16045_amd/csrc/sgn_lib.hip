@@ -3,6 +3,7 @@
 #include "sgn_kernels.h"
 #include "sgn_batch.h"
 #include "sgn_wall.h"
+#include "sgn_wave.h"
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -719,10 +720,33 @@ sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc, const cpx<fl
     return SGN_OK;
 }
 
+// The Krylov row pass on 2D rows of 1024 points runs as wave-private transforms
+// (k_pcg_r1w, one block per row); SGN_WAVE_ROWS=0 selects the block-wide pass.
+inline bool wave_rows_enabled() {
+    static const bool on = [] {
+        const char* e = getenv("SGN_WAVE_ROWS");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+template <typename T, int D>
+bool r1_wave(const PcgLaunch<T, D>& P) {
+    return D == 2 && P.d.nx == WROW_NX && P.d.ny <= PARTIALS_MAX && !P.native && wave_rows_enabled();
+}
+// Blocks of the row pass, i.e. the p.Gp partials the next column pass reduces.
+template <typename T, int D>
+int r1_blocks(const PcgLaunch<T, D>& P) { return r1_wave(P) ? P.d.ny : P.rl.g.nblocks; }
+
 template <typename T, int D>
 sgn_status pcg_r1(PcgLaunch<T, D>& P, bool curvature = false) {
     ProfScope ps(P.ctx, SGN_KERNEL_PCG_R1 + (sizeof(T) == 4 ? 6 : 0), true);
     double* part = curvature ? P.partials : nullptr;
+    if (r1_wave(P)) {
+        hipExtLaunchKernelGGL(k_pcg_r1w<T>, dim3(P.d.ny), dim3(192), 0, P.ctx->stream, ps.a, ps.b, 0, P.d.ny,
+                              twiddles<T>(P.ctx), P.sc, P.b.H, P.d.NS, P.eta, P.gh, part, PART_C2);
+        CHECK_LAUNCH(P.ctx);
+        return SGN_OK;
+    }
     auto& L = P.rl;
     const bool seq = row_lds_bytes<T>(L.g, D + 1) > LDS_MULTI_MAX;
     const size_t lds = row_lds_bytes<T>(L.g, seq ? 1 : D + 1);
@@ -751,7 +775,7 @@ sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out, con
     auto& L = P.cl;
     const size_t lds = col_lds_bytes<T>(L.g, D + 1);
     // partials reduced at the start: p.Gp of the row pass, or ||b||^2 of the setup pass
-    const int nb_red = MODE == C2_RESID_INIT ? L.g.nblocks : P.rl.g.nblocks;
+    const int nb_red = MODE == C2_RESID_INIT ? L.g.nblocks : r1_blocks(P);
     auto launch = [&](auto k) -> sgn_status {
         HIPCHK(P.ctx, allow_lds(k, lds));
         hipExtLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, ps.a, ps.b, 0, L.g,

@@ -1,0 +1,258 @@
+// Wave-private row transforms for 2D rows of nx = 1024 points (M = 512
+// complex points per real row), and the Krylov row pass built on them.
+//
+// The block-wide Stockham engine of sgn_device.h spreads one row over several
+// waves and pays two block barriers per radix pass.  Here one wave (64 lanes,
+// eight complex entries per lane) owns one field of one row: the 512-point
+// transform is three radix-8 stages in registers with two exchanges through a
+// wave-private LDS region, so no block barrier sits inside a transform and the
+// waves of a CU drift apart, overlapping one wave's loads with another's
+// arithmetic.  Stage decomposition (n = l + 64 m, k = k1 + 8 j1 + 64 j2,
+// l = l1 + 8 l2):
+//   X[k1 + 8 j1 + 64 j2] = sum_l1 W8^{l1 j2} W64^{l1 j1}
+//                          sum_l2 W8^{l2 j1} W512^{l k1} sum_m W8^{m k1} x[l + 64 m].
+// Input and output both sit in the natural layout: lane l holds index l + 64 s
+// in slot s.  The real-to-complex split of section 6.1's transforms (a real row
+// of nx points as M complex points) pairs index k with M - k, which another lane
+// holds; the pair is exchanged through the same LDS region.
+#pragma once
+#include "sgn_device.h"
+#include "sgn_kernels.h"
+
+namespace sgn {
+
+constexpr int WROW_NX = 1024;   // real row length taken by the wave row pass
+constexpr int WROW_M = 512;     // complex transform length
+constexpr int WROW_BUF = 584;   // LDS entries per field wave (padded exchange layouts)
+constexpr int WROW_S1 = 72;     // first exchange: row stride of the (k1, l) layout
+constexpr int WROW_S2 = 73;     // second exchange: row stride of the (j1, lambda) layout
+
+// Orders this wave's LDS accesses around a cross-lane exchange: LDS performs
+// one wave's accesses in issue order, so only the compiler needs fencing.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+
+// t[k] = a^k for k = 0..7 from a, a^2, a^4 (at most three factors per power).
+template <typename T>
+__device__ __forceinline__ void wave_pow7(cpx<T> a1, cpx<T> a2, cpx<T> a4, cpx<T> (&t)[8]) {
+    t[0] = C<T>(1, 0);
+    t[1] = a1;
+    t[2] = a2;
+    t[3] = a1 * a2;
+    t[4] = a4;
+    t[5] = a1 * a4;
+    t[6] = a2 * a4;
+    t[7] = t[3] * a4;
+}
+
+// W16^j, j = 0..7: W1024^{lane + 64 j} = W1024^{lane} W16^j.
+template <typename T>
+__device__ __forceinline__ cpx<T> w16(int j) {
+    const T c = (T)0.92387953251128675613, s = (T)0.38268343236508977173, r = (T)0.70710678118654752440;
+    switch (j & 7) {
+        case 0: return C<T>(1, 0);
+        case 1: return C<T>(c, -s);
+        case 2: return C<T>(r, -r);
+        case 3: return C<T>(s, -c);
+        case 4: return C<T>(0, -1);
+        case 5: return C<T>(-s, -c);
+        case 6: return C<T>(-r, -r);
+        default: return C<T>(-c, -s);
+    }
+}
+
+// 512-point FFT of one field held by one wave.  In: v[s] = x[lane + 64 s];
+// out: v[s] = X[lane + 64 s] (forward: exp(-i), inverse: exp(+i), unnormalised).
+// buf: this wave's WROW_BUF entries of LDS.
+// Twiddles come from the global table (W_L^j = exp(-2 pi i j / L) at tw_size(L)):
+// per stage three bases a, a^2, a^4, the other powers by products.
+template <typename T>
+__device__ __forceinline__ void wave_fft512(cpx<T> (&v)[8], cpx<T>* buf, const cpx<T>* __restrict__ tw_all,
+                                            int lane, bool inverse) {
+    const cpx<T>* t512 = tw_size(tw_all, WROW_M);
+    cpx<T> t[8];
+    // first stage: 8-point DFT over m, twiddle W512^{l k1}; lane l holds k1 = 0..7
+    dft_small<T, 8>(v, inverse);
+    wave_pow7(t512[lane], t512[2 * lane], t512[4 * lane], t);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) v[k] = v[k] * (inverse ? cj(t[k]) : t[k]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) buf[k * WROW_S1 + lane] = v[k];
+    wave_lds_sync();
+    // second stage: lane = l1 + 8 k1 takes l2 = 0..7 of l = l1 + 8 l2
+    {
+        const int l1 = lane & 7, k1 = lane >> 3;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = buf[k1 * WROW_S1 + l1 + 8 * q];
+    }
+    wave_lds_sync();
+    dft_small<T, 8>(v, inverse);
+    {
+        const int l1 = lane & 7;   // W64^{l1 j1} = W512^{8 l1 j1}
+        wave_pow7(t512[8 * l1], t512[16 * l1], t512[32 * l1], t);
+    }
+#pragma unroll
+    for (int k = 1; k < 8; ++k) v[k] = v[k] * (inverse ? cj(t[k]) : t[k]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) buf[j * WROW_S2 + lane + (lane >> 3)] = v[j];
+    wave_lds_sync();
+    // third stage: lane = k1 + 8 j1 takes l1 = 0..7 (written by lane l1 + 8 k1)
+    {
+        const int k1 = lane & 7, j1 = lane >> 3;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = buf[j1 * WROW_S2 + q + 9 * k1];
+    }
+    wave_lds_sync();
+    dft_small<T, 8>(v, inverse);
+}
+
+// Half spectrum of one real row (H layout: entry kx at Hrow[kx * ny], kx = 0..M)
+// to the complex input of the inverse transform, Z_k = (X_k + X*_{M-k}) +
+// i (X_k - X*_{M-k}) W1024^{-k}, Z_0 = (X_0 + X_M) + i (X_0 - X_M) on the real
+// parts.  X: the loaded entries X[lane + 64 s]; XM: X[M] (lane 0).
+// The loaded entries go to LDS and are read back with their mirrors, so they
+// do not stay live in registers across the exchange.
+template <typename T>
+__device__ __forceinline__ void wave_c2r_split(cpx<T> (&v)[8], const cpx<T> (&X)[8], cpx<T> XM, cpx<T>* buf,
+                                               cpx<T> r1, int lane) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = X[s];
+    const T x0 = X[0].re;
+    wave_lds_sync();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const cpx<T> wk = cj(r1 * w16<T>(s));
+        const cpx<T> xk = buf[lane + 64 * s];
+        const cpx<T> xm = buf[(WROW_M - lane - 64 * s) & (WROW_M - 1)];
+        v[s] = (xk + cj(xm)) + mul_i((xk - cj(xm)) * wk);
+    }
+    wave_lds_sync();
+    if (lane == 0) v[0] = C<T>(x0 + XM.re, x0 - XM.re);
+}
+
+// Forward transform output Z[lane + 64 s] (v) to the half spectrum,
+// X_k = (Z_k + Z*_{M-k})/2 - i W1024^k (Z_k - Z*_{M-k})/2, X_0 and X_M from Z_0,
+// each multiplied by scale and stored at Hrow[kx * ny].
+template <typename T>
+__device__ __forceinline__ void wave_r2c_store(const cpx<T> (&v)[8], cpx<T>* buf, cpx<T> r1, int lane,
+                                               cpx<T>* Hrow, int ny, T scale) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
+    const cpx<T> z0 = v[0];
+    wave_lds_sync();
+    const T half = (T)0.5;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int k = lane + 64 * s;
+        const cpx<T> wk = r1 * w16<T>(s);
+        const cpx<T> zk = buf[k], zm = buf[(WROW_M - lane - 64 * s) & (WROW_M - 1)];
+        cpx<T> X = half * (zk + cj(zm)) - half * mul_i(wk * (zk - cj(zm)));
+        if (k == 0) X = C<T>(zk.re + zk.im, 0);
+        Hrow[(size_t)k * ny] = scale * X;
+    }
+    if (lane == 0) Hrow[(size_t)WROW_M * ny] = scale * C<T>(z0.re - z0.im, 0);
+}
+
+// Krylov row pass (the G apply's x-direction work, Def:G) on rows of 1024
+// points: one block per row, one wave per field (p_x, p_y, div p).  Each wave
+// loads its field's half-spectrum row, splits and inverse-transforms it, and
+// leaves the real row in its LDS region; after a block barrier wave f forms the
+// pointwise products of the slots [3f, 3f + 3) of all three fields
+//   a = eta p + grad h (eta^2/2 div p + eta beta),  w = eta^3/3 div p + eta^2/2 beta,
+// beta = grad h . p, and the B-density eta|p|^2 + div p w + beta (eta^2/2 div p +
+// eta beta) of the curvature p.Gp (section 3.1); after a second barrier each wave
+// forward-transforms its field of (a, w) and stores it.  Launch: ny blocks of
+// 192 threads; part[part_base + block] receives the block's curvature sum.
+// Three waves per SIMD: at 1024 rows the whole grid (12 waves per CU) is then
+// resident at once.  eta and grad h are read in the pointwise phase: holding
+// them from the start costs 36 more registers per lane, which spilled at three
+// waves per SIMD and was slower (24.5 against 20.7 us at 1024^2, FP64).
+template <typename T>
+__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) k_pcg_r1w(int ny, const cpx<T>* __restrict__ tw,
+                                                 SolveScal* __restrict__ sc, cpx<T>* H, size_t NS,
+                                                 const T* __restrict__ eta, const T* __restrict__ gh,
+                                                 double* __restrict__ part, int part_base) {
+    if (sc->done) return;
+    __shared__ cpx<T> lds[3][WROW_BUF];
+    __shared__ double red[16];
+    const int f = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int y = xcd_remap(blockIdx.x, gridDim.x);
+    cpx<T>* Hrow = H + (size_t)f * NS + y;
+    cpx<T>* buf = lds[f];
+    // every global load of the wave is issued before the first LDS access
+    cpx<T> X[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) X[s] = Hrow[(size_t)(lane + 64 * s) * ny];
+    const cpx<T> XM = lane == 0 ? Hrow[(size_t)WROW_M * ny] : C<T>(0, 0);
+    const cpx<T> r1 = tw_size(tw, WROW_NX)[lane];
+    cpx<T> v[8];
+    wave_c2r_split<T>(v, X, XM, buf, r1, lane);
+    const size_t npts = (size_t)WROW_NX * ny;
+    const int m0 = 3 * f;
+    const int ms = f == 2 ? 2 : 3;
+    const cpx<T>* er = reinterpret_cast<const cpx<T>*>(eta + (size_t)y * WROW_NX);
+    const cpx<T>* gxr = reinterpret_cast<const cpx<T>*>(gh + (size_t)y * WROW_NX);
+    const cpx<T>* gyr = reinterpret_cast<const cpx<T>*>(gh + npts + (size_t)y * WROW_NX);
+    wave_fft512<T>(v, buf, tw, lane, true);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
+    __syncthreads();
+
+    cpx<T> pe[3], px[3], py[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (i < ms) {
+            const int n = lane + 64 * (m0 + i);
+            pe[i] = er[n];
+            px[i] = gxr[n];
+            py[i] = gyr[n];
+        }
+    }
+    double acc = 0.0;
+    const T third = (T)1 / (T)3, half = (T)0.5;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (i < ms) {
+            const int n = lane + 64 * (m0 + i);
+            cpx<T> p0 = lds[0][n], p1 = lds[1][n], dv = lds[2][n];
+            const T et2[2] = {pe[i].re, pe[i].im};
+            const T hx2[2] = {px[i].re, px[i].im};
+            const T hy2[2] = {py[i].re, py[i].im};
+            T a0[2], a1[2], ww[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const T et = et2[s];
+                const T pxs = s ? p0.im : p0.re, pys = s ? p1.im : p1.re, dl = s ? dv.im : dv.re;
+                const T bt = hx2[s] * pxs + hy2[s] * pys;
+                const T e2 = et * et;
+                const T w1 = third * e2 * et * dl + half * e2 * bt;
+                const T w2 = half * e2 * dl + et * bt;
+                const double pp = (double)pxs * (double)pxs + (double)pys * (double)pys;
+                acc += (double)et * pp + (double)dl * (double)w1 + (double)bt * (double)w2;
+                a0[s] = et * pxs + hx2[s] * w2;
+                a1[s] = et * pys + hy2[s] * w2;
+                ww[s] = w1;
+            }
+            lds[0][n] = C<T>(a0[0], a0[1]);
+            lds[1][n] = C<T>(a1[0], a1[1]);
+            lds[2][n] = C<T>(ww[0], ww[1]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = buf[lane + 64 * s];
+    wave_lds_sync();
+    wave_fft512<T>(v, buf, tw, lane, false);
+    wave_r2c_store<T>(v, buf, r1, lane, Hrow, ny, (T)1);
+    if (part) {
+        double a[1] = {acc};
+        block_sum<1>(a, red);
+        if (threadIdx.x == 0) part[part_base + blockIdx.x] = a[0];
+    }
+}
+
+}  // namespace sgn

@@ -19,6 +19,8 @@ GRIDS = [
     I.grid1d(2, 1.0), I.grid1d(8, 3.0), I.grid1d(256, 80.0), I.grid1d(4096, 400.0), I.grid1d(16384, 400.0),
     I.grid2d(2, 2, 1.0, 1.0), I.grid2d(8, 4, 2.0, 1.0), I.grid2d(64, 32, 5.0, 3.0), I.grid2d(32, 512, 1.0, 4.0),
     I.grid2d(512, 8, 4.0, 1.0), I.grid2d(256, 256, 20.0, 20.0), I.grid2d(1024, 1024, 200.0, 200.0),
+    # rows of 1024 points (the wave-private row pass): fewer rows than the XCD remap groups, and a multiple of eight
+    I.grid2d(1024, 4, 50.0, 1.0), I.grid2d(1024, 32, 100.0, 4.0),
 ]
 IDS = [f"{g.d}d-{g.nx}x{g.ny if g.d == 2 else 1}" for g in GRIDS]
 
