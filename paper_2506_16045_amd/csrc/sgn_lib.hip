@@ -729,20 +729,23 @@ inline bool wave_rows_enabled() {
     }();
     return on;
 }
+constexpr int WROW_RPB = 1;   // rows per block of the wave-private Krylov row pass
 template <typename T, int D>
 bool r1_wave(const PcgLaunch<T, D>& P) {
-    return D == 2 && P.d.nx == WROW_NX && P.d.ny <= PARTIALS_MAX && !P.native && wave_rows_enabled();
+    return D == 2 && P.d.nx == WROW_NX && P.d.ny % WROW_RPB == 0 && P.d.ny / WROW_RPB <= PARTIALS_MAX &&
+           !P.native && wave_rows_enabled();
 }
 // Blocks of the row pass, i.e. the p.Gp partials the next column pass reduces.
 template <typename T, int D>
-int r1_blocks(const PcgLaunch<T, D>& P) { return r1_wave(P) ? P.d.ny : P.rl.g.nblocks; }
+int r1_blocks(const PcgLaunch<T, D>& P) { return r1_wave(P) ? P.d.ny / WROW_RPB : P.rl.g.nblocks; }
 
 template <typename T, int D>
 sgn_status pcg_r1(PcgLaunch<T, D>& P, bool curvature = false) {
     ProfScope ps(P.ctx, SGN_KERNEL_PCG_R1 + (sizeof(T) == 4 ? 6 : 0), true);
     double* part = curvature ? P.partials : nullptr;
     if (r1_wave(P)) {
-        hipExtLaunchKernelGGL(k_pcg_r1w<T>, dim3(P.d.ny), dim3(192), 0, P.ctx->stream, ps.a, ps.b, 0, P.d.ny,
+        hipExtLaunchKernelGGL(k_pcg_r1w<T, WROW_RPB>, dim3(P.d.ny / WROW_RPB), dim3(192 * WROW_RPB), 0,
+                              P.ctx->stream, ps.a, ps.b, 0, P.d.ny,
                               twiddles<T>(P.ctx), P.sc, P.b.H, P.d.NS, P.eta, P.gh, part, PART_C2);
         CHECK_LAUNCH(P.ctx);
         return SGN_OK;

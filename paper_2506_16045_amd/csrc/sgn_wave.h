@@ -28,25 +28,60 @@ constexpr int WROW_S1 = 72;     // first exchange: row stride of the (k1, l) lay
 constexpr int WROW_S2 = 73;     // second exchange: row stride of the (j1, lambda) layout
 
 // Orders this wave's LDS accesses around a cross-lane exchange: LDS performs
-// one wave's accesses in issue order, so only the compiler needs fencing.
+// one wave's accesses in issue order, so only the compiler needs fencing.  The
+// fences name LDS only, so global loads in flight are not waited for.
 __device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// Block barrier that orders LDS only.  __syncthreads() fences all memory, which
+// makes every wave wait for its global loads in flight (vmcnt(0)) at the
+// barrier; the row passes keep their row and coefficient loads in flight across
+// their LDS barriers.
+__device__ __forceinline__ void block_lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 
-// t[k] = a^k for k = 0..7 from a, a^2, a^4 (at most three factors per power).
+// v[k] *= a^k for k = 1..7 from a, a^2, a^4 (the conjugates for the inverse):
+// each slot is multiplied by the factors of its binary digits in turn, so no
+// table of powers is held in registers.
 template <typename T>
-__device__ __forceinline__ void wave_pow7(cpx<T> a1, cpx<T> a2, cpx<T> a4, cpx<T> (&t)[8]) {
-    t[0] = C<T>(1, 0);
-    t[1] = a1;
-    t[2] = a2;
-    t[3] = a1 * a2;
-    t[4] = a4;
-    t[5] = a1 * a4;
-    t[6] = a2 * a4;
-    t[7] = t[3] * a4;
+__device__ __forceinline__ void wave_twiddle7(cpx<T> (&v)[8], cpx<T> a1, cpx<T> a2, cpx<T> a4, bool inverse) {
+    if (inverse) {
+        a1 = cj(a1);
+        a2 = cj(a2);
+        a4 = cj(a4);
+    }
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        if (k & 1) v[k] = v[k] * a1;
+        if (k & 2) v[k] = v[k] * a2;
+        if (k & 4) v[k] = v[k] * a4;
+    }
+}
+
+// Per-block LDS table of the twiddle bases the wave transforms read, filled once
+// at block start from the global table, so no stage waits on an L2 access.
+template <typename T>
+struct WaveTwl {
+    cpx<T> a[3][64];  // W512^{l}, W512^{2l}, W512^{4l}      (first stage, l = lane)
+    cpx<T> b[3][8];   // W64^{l1}, W64^{2 l1}, W64^{4 l1}    (second stage, l1 = lane & 7)
+    cpx<T> r[64];     // W1024^{l}                          (real-to-complex split)
+};
+constexpr int WAVE_TWL_ENTRIES = 3 * 64 + 3 * 8 + 64;
+
+// Entry e of the table (flat index over a, b, r), read from the global table.
+template <typename T>
+__device__ __forceinline__ cpx<T> wave_twl_entry(const cpx<T>* __restrict__ tw_all, int e) {
+    const cpx<T>* t512 = tw_size(tw_all, WROW_M);
+    if (e < 192) return t512[(1 << (e >> 6)) * (e & 63)];
+    if (e < 216) return t512[8 * (1 << ((e - 192) >> 3)) * ((e - 192) & 7)];
+    return tw_size(tw_all, WROW_NX)[e - 216];
 }
 
 // W16^j, j = 0..7: W1024^{lane + 64 j} = W1024^{lane} W16^j.
@@ -68,18 +103,14 @@ __device__ __forceinline__ cpx<T> w16(int j) {
 // 512-point FFT of one field held by one wave.  In: v[s] = x[lane + 64 s];
 // out: v[s] = X[lane + 64 s] (forward: exp(-i), inverse: exp(+i), unnormalised).
 // buf: this wave's WROW_BUF entries of LDS.
-// Twiddles come from the global table (W_L^j = exp(-2 pi i j / L) at tw_size(L)):
-// per stage three bases a, a^2, a^4, the other powers by products.
+// Twiddles: per stage three bases a, a^2, a^4 from the block's LDS table, the
+// other powers by products.
 template <typename T>
-__device__ __forceinline__ void wave_fft512(cpx<T> (&v)[8], cpx<T>* buf, const cpx<T>* __restrict__ tw_all,
-                                            int lane, bool inverse) {
-    const cpx<T>* t512 = tw_size(tw_all, WROW_M);
-    cpx<T> t[8];
+__device__ __forceinline__ void wave_fft512(cpx<T> (&v)[8], cpx<T>* buf, const WaveTwl<T>& tl, int lane,
+                                            bool inverse) {
     // first stage: 8-point DFT over m, twiddle W512^{l k1}; lane l holds k1 = 0..7
     dft_small<T, 8>(v, inverse);
-    wave_pow7(t512[lane], t512[2 * lane], t512[4 * lane], t);
-#pragma unroll
-    for (int k = 1; k < 8; ++k) v[k] = v[k] * (inverse ? cj(t[k]) : t[k]);
+    wave_twiddle7(v, tl.a[0][lane], tl.a[1][lane], tl.a[2][lane], inverse);
 #pragma unroll
     for (int k = 0; k < 8; ++k) buf[k * WROW_S1 + lane] = v[k];
     wave_lds_sync();
@@ -92,11 +123,9 @@ __device__ __forceinline__ void wave_fft512(cpx<T> (&v)[8], cpx<T>* buf, const c
     wave_lds_sync();
     dft_small<T, 8>(v, inverse);
     {
-        const int l1 = lane & 7;   // W64^{l1 j1} = W512^{8 l1 j1}
-        wave_pow7(t512[8 * l1], t512[16 * l1], t512[32 * l1], t);
+        const int l1 = lane & 7;   // W64^{l1 j1}
+        wave_twiddle7(v, tl.b[0][l1], tl.b[1][l1], tl.b[2][l1], inverse);
     }
-#pragma unroll
-    for (int k = 1; k < 8; ++k) v[k] = v[k] * (inverse ? cj(t[k]) : t[k]);
 #pragma unroll
     for (int j = 0; j < 8; ++j) buf[j * WROW_S2 + lane + (lane >> 3)] = v[j];
     wave_lds_sync();
@@ -168,50 +197,66 @@ __device__ __forceinline__ void wave_r2c_store(const cpx<T> (&v)[8], cpx<T>* buf
 // forward-transforms its field of (a, w) and stores it.  Launch: ny blocks of
 // 192 threads; part[part_base + block] receives the block's curvature sum.
 // Three waves per SIMD: at 1024 rows the whole grid (12 waves per CU) is then
-// resident at once.  eta and grad h are read in the pointwise phase: holding
-// them from the start costs 36 more registers per lane, which spilled at three
-// waves per SIMD and was slower (24.5 against 20.7 us at 1024^2, FP64).
-template <typename T>
-__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) k_pcg_r1w(int ny, const cpx<T>* __restrict__ tw,
+// resident at once.
+template <typename T, int RPB>
+__global__ void __launch_bounds__(192 * RPB) __attribute__((amdgpu_waves_per_eu(3))) k_pcg_r1w(int ny, const cpx<T>* __restrict__ tw,
                                                  SolveScal* __restrict__ sc, cpx<T>* H, size_t NS,
                                                  const T* __restrict__ eta, const T* __restrict__ gh,
                                                  double* __restrict__ part, int part_base) {
+    // eta and grad h of the wave's pointwise slots are loaded before the inverse
+    // transform, so their latency hides behind it
+    constexpr bool PF = true;
     if (sc->done) return;
-    __shared__ cpx<T> lds[3][WROW_BUF];
+    __shared__ cpx<T> ldsa[RPB][3][WROW_BUF];
+    __shared__ WaveTwl<T> tl;
     __shared__ double red[16];
-    const int f = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int y = xcd_remap(blockIdx.x, gridDim.x);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rb = wv / 3, f = wv - 3 * rb;
+    cpx<T> (&lds)[3][WROW_BUF] = ldsa[rb];
+    const int y = xcd_remap(blockIdx.x, gridDim.x) * RPB + rb;
     cpx<T>* Hrow = H + (size_t)f * NS + y;
     cpx<T>* buf = lds[f];
-    // every global load of the wave is issued before the first LDS access
+    // twiddle table first (L2-resident; one L2 round trip per block instead of
+    // one per transform stage), then the row's transposed loads.  Row loads in
+    // flight across a block barrier were spilled to scratch by the compiler, so
+    // the table's barrier comes before them.
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int e = threadIdx.x + i * blockDim.x;
+        if (e < WAVE_TWL_ENTRIES) (&tl.a[0][0])[e] = wave_twl_entry<T>(tw, e);
+    }
+    block_lds_barrier();
     cpx<T> X[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) X[s] = Hrow[(size_t)(lane + 64 * s) * ny];
     const cpx<T> XM = lane == 0 ? Hrow[(size_t)WROW_M * ny] : C<T>(0, 0);
-    const cpx<T> r1 = tw_size(tw, WROW_NX)[lane];
     cpx<T> v[8];
-    wave_c2r_split<T>(v, X, XM, buf, r1, lane);
+    wave_c2r_split<T>(v, X, XM, buf, tl.r[lane], lane);
     const size_t npts = (size_t)WROW_NX * ny;
     const int m0 = 3 * f;
     const int ms = f == 2 ? 2 : 3;
     const cpx<T>* er = reinterpret_cast<const cpx<T>*>(eta + (size_t)y * WROW_NX);
     const cpx<T>* gxr = reinterpret_cast<const cpx<T>*>(gh + (size_t)y * WROW_NX);
     const cpx<T>* gyr = reinterpret_cast<const cpx<T>*>(gh + npts + (size_t)y * WROW_NX);
-    wave_fft512<T>(v, buf, tw, lane, true);
+    cpx<T> pe[3], px[3], py[3];
+    auto load_coeffs = [&]() {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (i < ms) {
+                const int n = lane + 64 * (m0 + i);
+                pe[i] = er[n];
+                px[i] = gxr[n];
+                py[i] = gyr[n];
+            }
+        }
+    };
+    if (PF) load_coeffs();
+    wave_fft512<T>(v, buf, tl, lane, true);
 #pragma unroll
     for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
-    __syncthreads();
+    block_lds_barrier();
 
-    cpx<T> pe[3], px[3], py[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        if (i < ms) {
-            const int n = lane + 64 * (m0 + i);
-            pe[i] = er[n];
-            px[i] = gxr[n];
-            py[i] = gyr[n];
-        }
-    }
+    if (!PF) load_coeffs();
     double acc = 0.0;
     const T third = (T)1 / (T)3, half = (T)0.5;
 #pragma unroll
@@ -242,17 +287,22 @@ __global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) k
             lds[2][n] = C<T>(ww[0], ww[1]);
         }
     }
-    __syncthreads();
+    // the block's curvature sum: waves in order after the barrier that also
+    // publishes the pointwise results
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) red[wv] = acc;
+    block_lds_barrier();
+    if (part && threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int i = 0; i < 3 * RPB; ++i) sum += red[i];
+        part[part_base + blockIdx.x] = sum;
+    }
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = buf[lane + 64 * s];
     wave_lds_sync();
-    wave_fft512<T>(v, buf, tw, lane, false);
-    wave_r2c_store<T>(v, buf, r1, lane, Hrow, ny, (T)1);
-    if (part) {
-        double a[1] = {acc};
-        block_sum<1>(a, red);
-        if (threadIdx.x == 0) part[part_base + blockIdx.x] = a[0];
-    }
+    wave_fft512<T>(v, buf, tl, lane, false);
+    wave_r2c_store<T>(v, buf, tl.r[lane], lane, Hrow, ny, (T)1);
 }
 
 }  // namespace sgn
