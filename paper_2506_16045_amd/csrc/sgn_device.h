@@ -133,9 +133,19 @@ __device__ __forceinline__ void dft_small(cpx<T> (&v)[R], bool inverse) {
     }
 }
 
+// LDS index swizzle of the intermediate Stockham layouts: bits 0-2 of an index
+// are XORed with a function of bits 3-5, which permutes every aligned group of 8
+// entries.  The first passes write at strides R and R^2 entries; swizzled, eight
+// consecutive threads then write eight different 16-byte bank groups (radix 4
+// and radix 8).
+__device__ __forceinline__ int lds_swz(int i) {
+    return i ^ (((i >> 3) & 7) ^ (((i >> 4) & 1) << 2));
+}
+
 template <typename T, int R, int NB, int NF>
 __device__ __forceinline__ void fft_pass(cpx<T>* buf, int fstride, int M, int t, int TPX,
-                                         const cpx<T>* __restrict__ twm, bool inverse, int Ns, int sh) {
+                                         const cpx<T>* __restrict__ twm, bool inverse, int Ns, int sh,
+                                         bool swz_in = false, bool swz_out = false) {
     const int MR = M / R;
     cpx<T> v[NB][NF][R];
 #pragma unroll
@@ -152,9 +162,12 @@ __device__ __forceinline__ void fft_pass(cpx<T>* buf, int fstride, int M, int t,
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const cpx<T>* bf = buf + f * fstride;
-                v[i][f][0] = bf[j];
+                v[i][f][0] = bf[swz_in ? lds_swz(j) : j];
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[i][f][r] = bf[j + r * MR] * w[r];
+                for (int r = 1; r < R; ++r) {
+                    const int a = j + r * MR;
+                    v[i][f][r] = bf[swz_in ? lds_swz(a) : a] * w[r];
+                }
             }
         }
     }
@@ -170,14 +183,19 @@ __device__ __forceinline__ void fft_pass(cpx<T>* buf, int fstride, int M, int t,
                 dft_small<T, R>(v[i][f], inverse);
                 cpx<T>* bf = buf + f * fstride;
 #pragma unroll
-                for (int q = 0; q < R; ++q) bf[o + q * Ns] = v[i][f][q];
+                for (int q = 0; q < R; ++q) {
+                    const int a = o + q * Ns;
+                    bf[swz_out ? lds_swz(a) : a] = v[i][f][q];
+                }
             }
         }
     }
     __syncthreads();
 }
 
-template <typename T, int EPC, int NF>
+// SWZ: the passes between the first and the last keep their data in the
+// swizzled layout (lds_swz); input and output are in the natural layout.
+template <typename T, int EPC, int NF, bool SWZ = false>
 __device__ __forceinline__ void lds_fft(cpx<T>* buf, int fstride, int M, int t, int TPX,
                                         const cpx<T>* __restrict__ twm, bool inverse) {
     constexpr int NB8 = EPC / 8 > 0 ? EPC / 8 : 1;
@@ -189,20 +207,35 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int fstride, int M, int t, 
     const int logM = ilog2(M);
     int Ns = 1;
     int logNs = 0;
+    bool sw = false;   // the layout the next pass reads
+    auto last = [&](int R) { return Ns * R == M; };
     if (R8) {
-        for (; Ns * 8 <= M; Ns <<= 3, logNs += 3)
-            fft_pass<T, 8, NB8, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 3));
+        for (; Ns * 8 <= M; Ns <<= 3, logNs += 3) {
+            const bool so = SWZ && !last(8);
+            fft_pass<T, 8, NB8, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 3), sw, so);
+            sw = so;
+        }
     } else {
-        for (; Ns * 16 <= M; Ns <<= 2, logNs += 2)
-            fft_pass<T, 4, NB4, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 2));
+        for (; Ns * 16 <= M; Ns <<= 2, logNs += 2) {
+            const bool so = SWZ && !last(4);
+            fft_pass<T, 4, NB4, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 2), sw, so);
+            sw = so;
+        }
     }
     if (Ns * 4 <= M) {
-        fft_pass<T, 4, NB4, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 2));
+        const bool so = SWZ && !last(4);
+        fft_pass<T, 4, NB4, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 2), sw, so);
+        sw = so;
         Ns <<= 2;
         logNs += 2;
     }
-    if (Ns * 2 <= M) fft_pass<T, 2, NB2, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 1));
+    if (Ns * 2 <= M) fft_pass<T, 2, NB2, NF>(buf, fstride, M, t, TPX, twm, inverse, Ns, logM - (logNs + 1), sw, false);
 }
+
+// Column transforms take the swizzled intermediate layouts in FP64 (16-byte
+// entries, where the first passes' strided writes conflict).
+template <typename T>
+constexpr bool col_swz() { return sizeof(T) == 8; }
 
 // ---------------------------------------------------------------------------
 // Row geometry: a block holds R rows of TPR threads each; row r of the block is
@@ -472,7 +505,7 @@ __device__ __forceinline__ void col_load(const ColGeom& g, const ColThread<T>& c
             }
         }
         __syncthreads();
-        lds_fft<T, EPC, NF>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, false);
+        lds_fft<T, EPC, NF, col_swz<T>()>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, false);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
 #pragma unroll
@@ -500,7 +533,7 @@ __device__ __forceinline__ void col_store(const ColGeom& g, const ColThread<T>& 
             }
         }
         __syncthreads();
-        lds_fft<T, EPC, NF>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, true);
+        lds_fft<T, EPC, NF, col_swz<T>()>(ct.buf, ct.fstride, ny, ct.t, g.TPC, twm, true);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
 #pragma unroll

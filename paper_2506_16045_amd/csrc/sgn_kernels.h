@@ -550,7 +550,7 @@ __device__ __forceinline__ void col_fft_regs(const ColGeom& g, const ColThread<T
         if (j < g.ny) ct.buf[j] = v[e];
     }
     __syncthreads();
-    lds_fft<T, EPC, 1>(ct.buf, ct.fstride, g.ny, ct.t, g.TPC, twm, inverse);
+    lds_fft<T, EPC, 1, col_swz<T>()>(ct.buf, ct.fstride, g.ny, ct.t, g.TPC, twm, inverse);
 #pragma unroll
     for (int e = 0; e < EPC; ++e) {
         const int j = ct.t + g.TPC * e;
@@ -573,7 +573,7 @@ __device__ __forceinline__ void col_fft_group(const ColGeom& g, const ColThread<
             if (j < g.ny) ct.buf[f * ct.fstride + j] = v[f][e];
         }
     __syncthreads();
-    lds_fft<T, EPC, NF>(ct.buf, ct.fstride, g.ny, ct.t, g.TPC, twm, inverse);
+    lds_fft<T, EPC, NF, col_swz<T>()>(ct.buf, ct.fstride, g.ny, ct.t, g.TPC, twm, inverse);
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll

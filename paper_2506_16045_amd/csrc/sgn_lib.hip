@@ -366,6 +366,19 @@ struct ProfScope {
 
 // ---- generic passes --------------------------------------------------------
 
+// Row passes on 2D rows of 1024 points run as wave-private transforms
+// (sgn_wave.h); SGN_WAVE_ROWS=0 selects the block-wide passes.
+inline bool wave_rows_enabled() {
+    static const bool on = [] {
+        const char* e = getenv("SGN_WAVE_ROWS");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+inline bool wave_rows(const Dims& d) {
+    return d.D == 2 && d.nx == WROW_NX && d.ny % WROW_WPB == 0 && wave_rows_enabled();
+}
+
 // cmb (optional): fields from cmb->first on are read as src + (c1 a + c2 b)
 // (at most MAXF fields in that case).
 template <typename T, typename Tin>
@@ -384,6 +397,12 @@ sgn_status rows_fwd(sgn_ctx* ctx, const Dims& d, std::vector<const Tin*> src, st
         for (int i = 0; i < s.n; ++i) {
             s.p[i] = src[f0 + i];
             t.p[i] = dst[f0 + i];
+        }
+        if (wave_rows(d)) {
+            hipLaunchKernelGGL((k_rows_fwd_w<T, Tin>), dim3(s.n * d.ny / WROW_WPB), dim3(64 * WROW_WPB), 0,
+                               ctx->stream, d.ny, s, t, twiddles<T>(ctx), scale, cm);
+            CHECK_LAUNCH(ctx);
+            continue;
         }
         const bool multi = row_lds_bytes<T>(L.g, 3) <= LDS_MULTI_MAX;
         const size_t lds = row_lds_bytes<T>(L.g, multi ? 3 : 1);
@@ -426,6 +445,12 @@ sgn_status rows_inv(sgn_ctx* ctx, const Dims& d, std::vector<const cpx<T>*> src,
             s.p[i] = src[f0 + i];
             t.p[i] = dst[f0 + i];
             if (offs) of.p[i] = (*offs)[f0 + i];
+        }
+        if (wave_rows(d)) {
+            hipLaunchKernelGGL((k_rows_inv_w<T, Tout>), dim3(s.n * d.ny / WROW_WPB), dim3(64 * WROW_WPB), 0,
+                               ctx->stream, d.ny, s, t, twiddles<T>(ctx), scale, acc, of, offs_acc ? 1 : 0);
+            CHECK_LAUNCH(ctx);
+            continue;
         }
         const bool multi = row_lds_bytes<T>(L.g, 3) <= LDS_MULTI_MAX;
         const size_t lds = row_lds_bytes<T>(L.g, multi ? 3 : 1);
@@ -720,15 +745,6 @@ sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc, const cpx<fl
     return SGN_OK;
 }
 
-// The Krylov row pass on 2D rows of 1024 points runs as wave-private transforms
-// (k_pcg_r1w, one block per row); SGN_WAVE_ROWS=0 selects the block-wide pass.
-inline bool wave_rows_enabled() {
-    static const bool on = [] {
-        const char* e = getenv("SGN_WAVE_ROWS");
-        return !(e && e[0] == '0');
-    }();
-    return on;
-}
 constexpr int WROW_RPB = 1;   // rows per block of the wave-private Krylov row pass
 template <typename T, int D>
 bool r1_wave(const PcgLaunch<T, D>& P) {
@@ -1965,6 +1981,8 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
         };
         // the forward pass holds no pointwise state: its fields go three at a time
         const size_t l3 = row_lds_bytes<double>(RL.g, 3);
+        // (one wave per field and row measured slower here, 47 -> 58 us at 1024^2:
+        // the nine fields' waves each re-read the shared inputs)
         if (RL.epc == 4 && RL.threads <= 256 && l3 <= LDS_MULTI_MAX) {
             HIPCHK(ctx, allow_lds(k_rhs_rows_fwd<D, 4, 3, 256>, l3));
             hipLaunchKernelGGL((k_rhs_rows_fwd<D, 4, 3, 256>), dim3(RL.g.nblocks), dim3(RL.threads), l3,
@@ -2021,7 +2039,12 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
             CHECK_LAUNCH(ctx);
             return SGN_OK;
         };
-        if (RL.epc == 4 && RL.threads <= 256)
+        if (D == 2 && wave_rows(d) && q.n == 8) {
+            hipLaunchKernelGGL(k_rhs_rows_inv_w, dim3(d.ny), dim3(512), 0, ctx->stream, d.ny, q, eta, u, gh, eta_t,
+                               U_t, HA, ctx->tw64, 1.0);
+            CHECK_LAUNCH(ctx);
+            s = SGN_OK;
+        } else if (RL.epc == 4 && RL.threads <= 256)
             s = launch(k_rhs_rows_inv<D, 4, 1, 256>);
         else if (RL.epc == 4)
             s = launch(k_rhs_rows_inv<D, 4, 1, 1024>);

@@ -103,14 +103,32 @@ __device__ __forceinline__ cpx<T> w16(int j) {
 // 512-point FFT of one field held by one wave.  In: v[s] = x[lane + 64 s];
 // out: v[s] = X[lane + 64 s] (forward: exp(-i), inverse: exp(+i), unnormalised).
 // buf: this wave's WROW_BUF entries of LDS.
-// Twiddles: per stage three bases a, a^2, a^4 from the block's LDS table, the
-// other powers by products.
+// The six twiddle bases of one lane's transform stages.
 template <typename T>
-__device__ __forceinline__ void wave_fft512(cpx<T> (&v)[8], cpx<T>* buf, const WaveTwl<T>& tl, int lane,
+struct WaveBases {
+    cpx<T> a1, a2, a4;  // W512^{l}, W512^{2l}, W512^{4l}      (l = lane)
+    cpx<T> b1, b2, b4;  // W64^{l1}, W64^{2 l1}, W64^{4 l1}    (l1 = lane & 7)
+};
+template <typename T>
+__device__ __forceinline__ WaveBases<T> wave_bases(const WaveTwl<T>& tl, int lane) {
+    const int l1 = lane & 7;
+    return WaveBases<T>{tl.a[0][lane], tl.a[1][lane], tl.a[2][lane], tl.b[0][l1], tl.b[1][l1], tl.b[2][l1]};
+}
+// From the global table, for kernels whose waves run without a block barrier.
+template <typename T>
+__device__ __forceinline__ WaveBases<T> wave_bases(const cpx<T>* __restrict__ tw_all, int lane) {
+    const cpx<T>* t512 = tw_size(tw_all, WROW_M);
+    const int l1 = lane & 7;
+    return WaveBases<T>{t512[lane], t512[2 * lane], t512[4 * lane], t512[8 * l1], t512[16 * l1], t512[32 * l1]};
+}
+
+// Twiddles: per stage three bases a, a^2, a^4, the other powers by products.
+template <typename T>
+__device__ __forceinline__ void wave_fft512(cpx<T> (&v)[8], cpx<T>* buf, const WaveBases<T>& wb, int lane,
                                             bool inverse) {
     // first stage: 8-point DFT over m, twiddle W512^{l k1}; lane l holds k1 = 0..7
     dft_small<T, 8>(v, inverse);
-    wave_twiddle7(v, tl.a[0][lane], tl.a[1][lane], tl.a[2][lane], inverse);
+    wave_twiddle7(v, wb.a1, wb.a2, wb.a4, inverse);
 #pragma unroll
     for (int k = 0; k < 8; ++k) buf[k * WROW_S1 + lane] = v[k];
     wave_lds_sync();
@@ -122,10 +140,7 @@ __device__ __forceinline__ void wave_fft512(cpx<T> (&v)[8], cpx<T>* buf, const W
     }
     wave_lds_sync();
     dft_small<T, 8>(v, inverse);
-    {
-        const int l1 = lane & 7;   // W64^{l1 j1}
-        wave_twiddle7(v, tl.b[0][l1], tl.b[1][l1], tl.b[2][l1], inverse);
-    }
+    wave_twiddle7(v, wb.b1, wb.b2, wb.b4, inverse);   // W64^{l1 j1}
 #pragma unroll
     for (int j = 0; j < 8; ++j) buf[j * WROW_S2 + lane + (lane >> 3)] = v[j];
     wave_lds_sync();
@@ -251,7 +266,7 @@ __global__ void __launch_bounds__(192 * RPB) __attribute__((amdgpu_waves_per_eu(
         }
     };
     if (PF) load_coeffs();
-    wave_fft512<T>(v, buf, tl, lane, true);
+    wave_fft512<T>(v, buf, wave_bases<T>(tl, lane), lane, true);
 #pragma unroll
     for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
     block_lds_barrier();
@@ -301,8 +316,232 @@ __global__ void __launch_bounds__(192 * RPB) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = buf[lane + 64 * s];
     wave_lds_sync();
-    wave_fft512<T>(v, buf, tl, lane, false);
+    wave_fft512<T>(v, buf, wave_bases<T>(tl, lane), lane, false);
     wave_r2c_store<T>(v, buf, tl.r[lane], lane, Hrow, ny, (T)1);
+}
+
+}  // namespace sgn
+
+namespace sgn {
+
+// ---------------------------------------------------------------------------
+// Plain row transforms and the right-hand side's inverse row pass on rows of
+// 1024 points, one wave per (field, row).  The plain passes need no exchange
+// between waves, so their blocks hold WROW_WPB independent waves and no block
+// barrier; the waves of a field take consecutive rows, so the transposed H
+// lines of neighbouring rows are touched on one XCD.
+// ---------------------------------------------------------------------------
+constexpr int WROW_WPB = 4;
+
+struct WaveRow {
+    int f, y;
+};
+__device__ __forceinline__ WaveRow wave_row_of(int ny) {
+    const int w = xcd_remap(blockIdx.x, gridDim.x) * WROW_WPB + (int)(threadIdx.x >> 6);
+    const int f = w / ny;
+    return WaveRow{f, w - f * ny};
+}
+
+// Forward transform of one real row held as v[s] = (x_2n, x_2n+1), n = lane + 64 s,
+// into the half spectrum at Hrow[kx * ny], each value times scale.
+template <typename T>
+__device__ __forceinline__ void wave_row_forward(cpx<T> (&v)[8], cpx<T>* buf, const cpx<T>* __restrict__ tw,
+                                                 int lane, cpx<T>* Hrow, int ny, T scale) {
+    const WaveBases<T> wb = wave_bases<T>(tw, lane);
+    const cpx<T> r1 = tw_size(tw, WROW_NX)[lane];
+    wave_fft512<T>(v, buf, wb, lane, false);
+    wave_r2c_store<T>(v, buf, r1, lane, Hrow, ny, scale);
+}
+
+// Inverse transform of the half-spectrum row at Hrow[kx * ny] into
+// v[s] = (x_2n, x_2n+1), n = lane + 64 s (nx times the inverse DFT).
+template <typename T>
+__device__ __forceinline__ void wave_row_inverse(cpx<T> (&v)[8], cpx<T>* buf, const cpx<T>* __restrict__ tw,
+                                                 int lane, const cpx<T>* Hrow, int ny) {
+    cpx<T> X[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) X[s] = Hrow[(size_t)(lane + 64 * s) * ny];
+    const cpx<T> XM = lane == 0 ? Hrow[(size_t)WROW_M * ny] : C<T>(0, 0);
+    const WaveBases<T> wb = wave_bases<T>(tw, lane);
+    const cpx<T> r1 = tw_size(tw, WROW_NX)[lane];
+    wave_c2r_split<T>(v, X, XM, buf, r1, lane);
+    wave_fft512<T>(v, buf, wb, lane, true);
+}
+
+// Forward row transforms of src.n physical fields (the k_rows_fwd contract:
+// fields from cmb.first on are read as src + c1 a + c2 b).  Launch:
+// src.n * ny / WROW_WPB blocks of 64 WROW_WPB threads.
+template <typename T, typename Tin>
+__global__ void __launch_bounds__(64 * WROW_WPB) k_rows_fwd_w(int ny, PtrList<const Tin, MAXF> src,
+                                                              PtrList<cpx<T>, MAXF> dst,
+                                                              const cpx<T>* __restrict__ tw, T scale,
+                                                              RowCombo<Tin> cmb) {
+    __shared__ cpx<T> ldsw[WROW_WPB][WROW_BUF];
+    const int lane = threadIdx.x & 63;
+    const WaveRow wr = wave_row_of(ny);
+    if (wr.f >= src.n) return;
+    cpx<T>* buf = ldsw[threadIdx.x >> 6];
+    const size_t o = (size_t)wr.y * WROW_NX;
+    const cpx<Tin>* sf = reinterpret_cast<const cpx<Tin>*>(src.p[wr.f] + o);
+    const int k = wr.f - cmb.first;
+    const bool comb = cmb.first >= 0 && k >= 0;
+    cpx<T> v[8];
+    if (comb) {
+        const cpx<Tin>* ca = reinterpret_cast<const cpx<Tin>*>(cmb.a[k] + o);
+        const cpx<Tin>* cb = cmb.b[k] ? reinterpret_cast<const cpx<Tin>*>(cmb.b[k] + o) : nullptr;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int n = lane + 64 * s;
+            const cpx<Tin> x = sf[n], a = ca[n];
+            double t0 = cmb.c1 * (double)a.re, t1 = cmb.c1 * (double)a.im;
+            if (cb) {
+                const cpx<Tin> b = cb[n];
+                t0 += cmb.c2 * (double)b.re;
+                t1 += cmb.c2 * (double)b.im;
+            }
+            v[s] = C<T>((T)((double)x.re + t0), (T)((double)x.im + t1));
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const cpx<Tin> x = sf[lane + 64 * s];
+            v[s] = C<T>((T)x.re, (T)x.im);
+        }
+    }
+    wave_row_forward<T>(v, buf, tw, lane, dst.p[wr.f] + wr.y, ny, scale);
+}
+
+// Inverse row transforms of src.n H fields (the k_rows_inv contract:
+// dst = acc dst + scale value; offs_f = new - old, or += with oacc).  Launch as
+// k_rows_fwd_w.
+template <typename T, typename Tout>
+__global__ void __launch_bounds__(64 * WROW_WPB) k_rows_inv_w(int ny, PtrList<const cpx<T>, MAXF> src,
+                                                              PtrList<Tout, MAXF> dst,
+                                                              const cpx<T>* __restrict__ tw, T scale, T acc,
+                                                              PtrList<Tout, MAXF> offs, int oacc) {
+    __shared__ cpx<T> ldsw[WROW_WPB][WROW_BUF];
+    const int lane = threadIdx.x & 63;
+    const WaveRow wr = wave_row_of(ny);
+    if (wr.f >= src.n) return;
+    cpx<T>* buf = ldsw[threadIdx.x >> 6];
+    cpx<T> v[8];
+    wave_row_inverse<T>(v, buf, tw, lane, src.p[wr.f] + wr.y, ny);
+    const size_t o = (size_t)wr.y * WROW_NX;
+    cpx<Tout>* d = reinterpret_cast<cpx<Tout>*>(dst.p[wr.f] + o);
+    cpx<Tout>* od = offs.n > 0 ? reinterpret_cast<cpx<Tout>*>(offs.p[wr.f] + o) : nullptr;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int n = lane + 64 * s;
+        T v0 = scale * v[s].re, v1 = scale * v[s].im;
+        cpx<Tout> old = C<Tout>(0, 0);
+        if (acc != (T)0 || od) old = d[n];
+        if (acc != (T)0) {
+            v0 += acc * (T)old.re;
+            v1 += acc * (T)old.im;
+        }
+        if (od) {
+            const Tout d0 = (Tout)v0 - old.re, d1 = (Tout)v1 - old.im;
+            if (oacc) {
+                const cpx<Tout> p = od[n];
+                od[n] = C<Tout>(p.re + d0, p.im + d1);
+            } else {
+                od[n] = C<Tout>(d0, d1);
+            }
+        }
+        d[n] = C<Tout>((Tout)v0, (Tout)v1);
+    }
+}
+
+// Inverse row transforms of the 2D right-hand side's eight derivative fields
+// (m = div(eta u), delta = div u, grad delta, grad eta, grad beta) and the
+// pointwise right-hand side (the k_rhs_rows_inv contract): one block per row,
+// wave q inverse-transforms field q into LDS; after a barrier wave q forms, at
+// the points of its slot q, eta_t = -m, U_t = -eta grad(eta - h) - T grad h and
+// S of Def:bigF (S, T from P = u.grad(delta) - delta^2 and Q = u.grad(beta));
+// after a second barrier wave 0 forward-transforms S into Sdst.  Launch: ny
+// blocks of 512 threads.
+__global__ void __launch_bounds__(512) k_rhs_rows_inv_w(int ny, PtrList<const cpx<double>, MAXF> src,
+                                                        const double* __restrict__ eta,
+                                                        const double* __restrict__ u,
+                                                        const double* __restrict__ gh, double* __restrict__ eta_t,
+                                                        double* __restrict__ U_t, cpx<double>* __restrict__ Sdst,
+                                                        const cpx<double>* __restrict__ tw, double scale) {
+    __shared__ cpx<double> ldsr[8][WROW_BUF];
+    __shared__ WaveTwl<double> tl;
+    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int y = xcd_remap(blockIdx.x, gridDim.x);
+    if (threadIdx.x < WAVE_TWL_ENTRIES) (&tl.a[0][0])[threadIdx.x] = wave_twl_entry<double>(tw, threadIdx.x);
+    block_lds_barrier();
+    cpx<double>* buf = ldsr[q];
+    const cpx<double>* Hrow = src.p[q] + y;
+    cpx<double> X[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) X[s] = Hrow[(size_t)(lane + 64 * s) * ny];
+    const cpx<double> XM = lane == 0 ? Hrow[(size_t)WROW_M * ny] : C<double>(0, 0);
+    // inputs at this wave's pointwise slot (n = lane + 64 q), in flight during the transform
+    const size_t npts = (size_t)WROW_NX * ny, o = (size_t)y * WROW_NX;
+    const int n = lane + 64 * q;
+    const cpx<double> pe = reinterpret_cast<const cpx<double>*>(eta + o)[n];
+    const cpx<double> pu0 = reinterpret_cast<const cpx<double>*>(u + o)[n];
+    const cpx<double> pu1 = reinterpret_cast<const cpx<double>*>(u + npts + o)[n];
+    const cpx<double> ph0 = reinterpret_cast<const cpx<double>*>(gh + o)[n];
+    const cpx<double> ph1 = reinterpret_cast<const cpx<double>*>(gh + npts + o)[n];
+    cpx<double> v[8];
+    wave_c2r_split<double>(v, X, XM, buf, tl.r[lane], lane);
+    wave_fft512<double>(v, buf, wave_bases<double>(tl, lane), lane, true);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
+    block_lds_barrier();
+    double Sv[2], et[2], ut0[2], ut1[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        double qv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const cpx<double> z = ldsr[i][n];
+            qv[i] = scale * (p ? z.im : z.re);
+        }
+        const double e0 = p ? pe.im : pe.re;
+        const double uc[2] = {p ? pu0.im : pu0.re, p ? pu1.im : pu1.re};
+        const double hc[2] = {p ? ph0.im : ph0.re, p ? ph1.im : ph1.re};
+        double A0 = qv[0];                       // m
+        et[p] = -qv[0];
+        double A1 = qv[1];                       // delta
+        double A2 = -qv[1] * qv[1];
+        A2 += uc[0] * qv[2];                     // P = u.grad(delta) - delta^2
+        A2 += uc[1] * qv[3];
+        {
+            double bt = 0.0;
+            bt += hc[0] * uc[0];
+            bt += hc[1] * uc[1];
+            const double e2 = e0 * e0, mm = A0, d0 = A1, pp = A2;
+            A0 = e2 * e0 / 3.0 * pp + e2 * mm * d0 + e0 * mm * bt;   // S
+            A1 = e2 / 2.0 * pp + e0 * mm * d0 + mm * bt;             // T
+        }
+        const double U0 = -e0 * (qv[4] - hc[0]);
+        const double U1 = -e0 * (qv[5] - hc[1]);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {            // Q = u.grad(beta)
+            const double t = uc[c] * qv[6 + c];
+            A0 += e0 * e0 / 2.0 * t;
+            A1 += e0 * t;
+        }
+        ut0[p] = U0 - hc[0] * A1;
+        ut1[p] = U1 - hc[1] * A1;
+        Sv[p] = A0;
+    }
+    reinterpret_cast<cpx<double>*>(eta_t + o)[n] = C<double>(et[0], et[1]);
+    reinterpret_cast<cpx<double>*>(U_t + o)[n] = C<double>(ut0[0], ut0[1]);
+    reinterpret_cast<cpx<double>*>(U_t + npts + o)[n] = C<double>(ut1[0], ut1[1]);
+    // slot n of field 0 is read by this wave only, so S takes its place
+    ldsr[0][n] = C<double>(Sv[0], Sv[1]);
+    block_lds_barrier();
+    if (q != 0) return;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = buf[lane + 64 * s];
+    wave_lds_sync();
+    wave_fft512<double>(v, buf, wave_bases<double>(tl, lane), lane, false);
+    wave_r2c_store<double>(v, buf, tl.r[lane], lane, Sdst + y, ny, 1.0);
 }
 
 }  // namespace sgn
