@@ -64,7 +64,7 @@ HBM_PEAK_GBS = 8000.0    # MI355X HBM3E, 8 TB/s
 PROFILES = os.path.join(ROOT, "profiles")
 # kernel code and the launch shapes chosen for it
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_16045_amd", "csrc", f)
-                  for f in ("sgn_device.h", "sgn_kernels.h", "sgn_lib.hip")]
+                  for f in ("sgn_device.h", "sgn_kernels.h", "sgn_wave.h", "sgn_lib.hip")]
 
 
 def kernel_bytes(kind: str, d: int, nx: int, ny: int, word: int) -> float:

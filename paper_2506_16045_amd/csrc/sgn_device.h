@@ -482,20 +482,36 @@ __device__ __forceinline__ ColThread<T> col_thread(const ColGeom& g, cpx<T>* lds
     return col_thread_at<T>(g, lds, blockIdx.x);
 }
 
-// Load NF columns of H (or S) and optionally transform them along y.
+// Load NF columns of H (or S) into registers (col_fetch), then optionally
+// transform them along y (col_fft); col_load does both.
+// Entry (column kx, row j) of a column-layout field, clamped in range (entry 0
+// of the field where the lane has no entry), and whether it is a real entry.
+// The loads through it are unconditional: predicated loads make the compiler
+// wait for every load in flight (see partials_fetch).
+template <typename T>
+__device__ __forceinline__ size_t col_index(const ColGeom& g, const ColThread<T>& ct, int j, bool& ok) {
+    ok = ct.valid && j < g.ny;
+    return ok ? (size_t)ct.kx * g.ny + j : 0;
+}
+// A lane without an entry (a column past nx/2 in the last block) holds a copy
+// of entry 0: finite, transformed with its column and never stored or summed
+// (the callers guard outputs and weights by ct.valid).
 template <typename T, int EPC, int NF>
-__device__ __forceinline__ void col_load(const ColGeom& g, const ColThread<T>& ct, const cpx<T>* const (&H)[NF],
-                                         bool fft, const cpx<T>* twm, cpx<T> (&v)[NF][EPC]) {
-    const int ny = g.ny;
+__device__ __forceinline__ void col_fetch(const ColGeom& g, const ColThread<T>& ct, const cpx<T>* const (&H)[NF],
+                                          cpx<T> (&v)[NF][EPC]) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
+    for (int e = 0; e < EPC; ++e) {
+        bool ok;
+        const size_t idx = col_index(g, ct, ct.t + g.TPC * e, ok);
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            const int j = ct.t + g.TPC * e;
-            if (j < ny) v[f][e] = ct.valid ? H[f][(size_t)ct.kx * ny + j] : C<T>(0, 0);
-        }
+        for (int f = 0; f < NF; ++f) v[f][e] = H[f][idx];
     }
-    if (fft && ny > 1) {
+}
+template <typename T, int EPC, int NF>
+__device__ __forceinline__ void col_fft(const ColGeom& g, const ColThread<T>& ct, const cpx<T>* twm,
+                                        cpx<T> (&v)[NF][EPC]) {
+    const int ny = g.ny;
+    if (ny > 1) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
 #pragma unroll
@@ -516,6 +532,19 @@ __device__ __forceinline__ void col_load(const ColGeom& g, const ColThread<T>& c
         }
         __syncthreads();
     }
+}
+// col_load: lanes without an entry hold zeros.
+template <typename T, int EPC, int NF>
+__device__ __forceinline__ void col_load(const ColGeom& g, const ColThread<T>& ct, const cpx<T>* const (&H)[NF],
+                                         bool fft, const cpx<T>* twm, cpx<T> (&v)[NF][EPC]) {
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int j = ct.t + g.TPC * e;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (j < g.ny) v[f][e] = ct.valid ? H[f][(size_t)ct.kx * g.ny + j] : C<T>(0, 0);
+    }
+    if (fft) col_fft<T, EPC, NF>(g, ct, twm, v);
 }
 
 // Optionally inverse-transform NF columns along y, then store them to H (or S).
@@ -556,13 +585,25 @@ __device__ __forceinline__ void col_store(const ColGeom& g, const ColThread<T>& 
     }
 }
 
+// Block barrier that orders LDS only.  __syncthreads() fences all memory, which
+// makes every wave wait for its global loads in flight (vmcnt(0)) at the
+// barrier; kernels that issue their data loads before a reduction or an LDS
+// exchange keep them in flight across such barriers.
+__device__ __forceinline__ void block_lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic reductions.  Each block reduces NACC doubles in a fixed tree
 // (wave shuffles, then waves in order) and writes them to partials[block];
 // the last block to finish sums the partials in block order, so the result
 // does not depend on scheduling.
 // ---------------------------------------------------------------------------
-template <int NACC>
+// LDS_ONLY: the barriers order LDS only (global loads in flight stay in flight);
+// the arithmetic, and so the result, is the same.
+template <int NACC, bool LDS_ONLY = false>
 __device__ __forceinline__ void block_sum(double (&v)[NACC], double* red /*LDS, NACC*16*/) {
 #pragma unroll
     for (int a = 0; a < NACC; ++a) {
@@ -578,7 +619,10 @@ __device__ __forceinline__ void block_sum(double (&v)[NACC], double* red /*LDS, 
 #pragma unroll
         for (int a = 0; a < NACC; ++a) red[a * 16 + wave] = v[a];
     }
-    __syncthreads();
+    if (LDS_ONLY)
+        block_lds_barrier();
+    else
+        __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int a = 0; a < NACC; ++a) {
@@ -587,7 +631,10 @@ __device__ __forceinline__ void block_sum(double (&v)[NACC], double* red /*LDS, 
             v[a] = s;
         }
     }
-    __syncthreads();
+    if (LDS_ONLY)
+        block_lds_barrier();
+    else
+        __syncthreads();
 }
 
 // Sum of the per-block partials (layout partials[NACC*b + a]) by the whole
@@ -596,7 +643,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NACC], double* red /*LDS, 
 // The order, and so the value, is the same in every kernel that reduces the same
 // partials, whatever its block size (at least 256 threads).  Every thread of the
 // block must call it.
-template <int NACC>
+template <int NACC, bool LDS_ONLY = false>
 __device__ __forceinline__ void final_sum(const double* __restrict__ partials, unsigned nblocks,
                                           double (&v)[NACC], double* red) {
 #pragma unroll
@@ -605,7 +652,41 @@ __device__ __forceinline__ void final_sum(const double* __restrict__ partials, u
 #pragma unroll
         for (int a = 0; a < NACC; ++a) v[a] += partials[(size_t)NACC * b + a];
     }
-    block_sum<NACC>(v, red);
+    block_sum<NACC, LDS_ONLY>(v, red);
+}
+
+// final_sum in two steps, so that a kernel can issue the partials' loads ahead
+// of its data loads (a wait for a load also waits for every load issued before
+// it): partials_fetch loads the partials of up to 256 PF_K blocks (every
+// reducing launch: PARTIALS_MAX) into registers, partials_sum adds them in
+// final_sum's order, so the result is the same bits.  No loop: a load inside a
+// loop makes the compiler wait for every load in flight at the loop entry.
+constexpr int PF_K = 16;
+template <int NACC>
+__device__ __forceinline__ void partials_fetch(const double* __restrict__ partials, unsigned nblocks,
+                                               double (&pb)[PF_K][NACC]) {
+    // branch-free: every lane loads an in-range entry (predicated loads would
+    // make the compiler wait for all loads); partials_sum drops the extra ones
+#pragma unroll
+    for (int k = 0; k < PF_K; ++k) {
+        const unsigned b = threadIdx.x + 256u * k;
+        const unsigned bc = (threadIdx.x < 256 && b < nblocks) ? b : 0u;
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) pb[k][a] = partials[(size_t)NACC * bc + a];
+    }
+}
+template <int NACC, bool LDS_ONLY = false>
+__device__ __forceinline__ void partials_sum(const double* __restrict__ partials, unsigned nblocks,
+                                             const double (&pb)[PF_K][NACC], double (&v)[NACC], double* red) {
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) v[a] = 0.0;
+#pragma unroll
+    for (int k = 0; k < PF_K; ++k) {
+        const bool ok = threadIdx.x < 256 && threadIdx.x + 256u * k < nblocks;
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) v[a] += ok ? pb[k][a] : 0.0;
+    }
+    block_sum<NACC, LDS_ONLY>(v, red);
 }
 
 // Maximum of the per-block partials by the whole last block (order independent);

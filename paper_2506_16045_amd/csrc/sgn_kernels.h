@@ -23,7 +23,8 @@ struct SolveScal {
     int init_bb;              // 1: ||b|| is the norm of the initial residual
 };
 
-constexpr int PARTIALS_MAX = 4096;  // blocks of a reducing launch
+constexpr int PARTIALS_MAX = 4096;  // blocks of a reducing launch (256 PF_K)
+static_assert(PARTIALS_MAX <= 256 * PF_K, "prefetched partials cover every reducing launch");
 // regions of the partials buffer (doubles)
 constexpr int PART_C2 = 0;                       // p.Gp of the row pass (one per row block)
 constexpr int PART_C3 = 4096;                    // (r.z, r.r) of the update pass (two per column block)
@@ -724,11 +725,18 @@ __global__ void __launch_bounds__(256) k_cols_precond(ColGeom g, PtrList<const c
 // ---------------------------------------------------------------------------
 
 // Broadcast thread 0's value to the block.
+template <bool LDS_ONLY = false>
 __device__ __forceinline__ double bcast(double v, double* slot) {
     if (threadIdx.x == 0) *slot = v;
-    __syncthreads();
+    if (LDS_ONLY)
+        block_lds_barrier();
+    else
+        __syncthreads();
     const double r = *slot;
-    __syncthreads();
+    if (LDS_ONLY)
+        block_lds_barrier();
+    else
+        __syncthreads();
     return r;
 }
 
@@ -782,6 +790,8 @@ __global__ void __launch_bounds__(256) k_pcg_c1(ColGeom g, const cpx<T>* __restr
     if (MODE == C1_UPDATE) {
         if (pcg_iterate_state(sc, part, nb3, red, slot, beta_d)) return;
     }
+    // (loading r and p ahead of this reduction, in flight across it, measured
+    // slower: 17.0 -> 18.5 us at 1024^2 FP64)
     const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D + 1));
     const ColThread<T> ct = col_thread<T>(g, lds);
     const T beta = (T)beta_d, sig = (T)sc->sig, alp = (T)sc->alp, inv_n = (T)sc->inv_n;
@@ -1020,17 +1030,33 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
                                                  cpx<T>* __restrict__ xh, const cpx<T>* __restrict__ bh,
                                                  cpx<T>* __restrict__ rh, double* __restrict__ part, int nb_r1,
                                                  T tpx, T tpy) {
-    if (sc->done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     __shared__ double red[32];
     __shared__ double slot[1];
+    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D + 1));
+    const ColThread<T> ct = col_thread<T>(g, lds);
+    // the row pass's columns do not depend on alpha: loaded right after the
+    // partials of the reduction, in flight across it (LDS-only barriers)
+    if (sc->done) return;
+    double pb[PF_K][1];
+    if (MODE == C2_UPDATE) partials_fetch<1>(part + PART_C2, nb_r1, pb);
+    if (MODE == C2_RESID_INIT) partials_fetch<1>(part + PART_GEN, nb_r1, pb);
+    __builtin_amdgcn_sched_barrier(0);   // the partials' loads first
+    cpx<T> in[D + 1][EPC];
+    {
+        const cpx<T>* srcs[D + 1];
+#pragma unroll
+        for (int c = 0; c <= D; ++c) srcs[c] = H + c * NS;
+        col_fetch<T, EPC, D + 1>(g, ct, srcs, in);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep the data loads ahead of the reduction
     T alpha = (T)0;
     bool zero_x = false;
     if (MODE == C2_RESID_INIT) {
         double tot[1];
-        final_sum<1>(part + PART_GEN, nb_r1, tot, red);
-        const double bb = bcast(tot[0], slot) * sc->inv_n;
+        partials_sum<1, true>(part + PART_GEN, nb_r1, pb, tot, red);
+        const double bb = bcast<true>(tot[0], slot) * sc->inv_n;
         const bool bad = !(bb == bb) || bb > 1.0e300;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sc->bb = bb;
@@ -1044,8 +1070,8 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
     }
     if (MODE == C2_UPDATE) {
         double tot[1];
-        final_sum<1>(part + PART_C2, nb_r1, tot, red);
-        const double pq = bcast(tot[0], slot);
+        partials_sum<1, true>(part + PART_C2, nb_r1, pb, tot, red);
+        const double pq = bcast<true>(tot[0], slot);
         const double a = sc->rho / pq;
         alpha = (T)a;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1056,13 +1082,7 @@ __global__ void __launch_bounds__(256) k_pcg_c2(ColGeom g, const cpx<T>* __restr
             sc->first = 0;
         }
     }
-    const cpx<T>* twm = twl_setup<T>(tw, g.ny, lds + col_lds_data(g, D + 1));
-    const ColThread<T> ct = col_thread<T>(g, lds);
-    cpx<T> in[D + 1][EPC];
-    const cpx<T>* srcs[D + 1];
-#pragma unroll
-    for (int c = 0; c <= D; ++c) srcs[c] = H + c * NS;
-    col_load<T, EPC, D + 1>(g, ct, srcs, true, twm, in);
+    col_fft<T, EPC, D + 1>(g, ct, twm, in);
     const T kx = wavenumber<T>(ct.kx, g.nx, tpx);
     const T sig = (T)sc->sig, alp = (T)sc->alp;
     const double w = ct.valid ? half_weight(ct.kx, g.nx) : 0.0;

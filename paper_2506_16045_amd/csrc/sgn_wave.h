@@ -36,15 +36,6 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
-// Block barrier that orders LDS only.  __syncthreads() fences all memory, which
-// makes every wave wait for its global loads in flight (vmcnt(0)) at the
-// barrier; the row passes keep their row and coefficient loads in flight across
-// their LDS barriers.
-__device__ __forceinline__ void block_lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 
 // v[k] *= a^k for k = 1..7 from a, a^2, a^4 (the conjugates for the inverse):
@@ -221,7 +212,9 @@ __global__ void __launch_bounds__(192 * RPB) __attribute__((amdgpu_waves_per_eu(
     // eta and grad h of the wave's pointwise slots are loaded before the inverse
     // transform, so their latency hides behind it
     constexpr bool PF = true;
-    if (sc->done) return;
+    // the stop flag is read here and tested after the twiddle table is staged,
+    // so its latency hides behind the table's loads
+    const int done = sc->done;
     __shared__ cpx<T> ldsa[RPB][3][WROW_BUF];
     __shared__ WaveTwl<T> tl;
     __shared__ double red[16];
@@ -241,6 +234,7 @@ __global__ void __launch_bounds__(192 * RPB) __attribute__((amdgpu_waves_per_eu(
         if (e < WAVE_TWL_ENTRIES) (&tl.a[0][0])[e] = wave_twl_entry<T>(tw, e);
     }
     block_lds_barrier();
+    if (done) return;
     cpx<T> X[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) X[s] = Hrow[(size_t)(lane + 64 * s) * ny];
