@@ -724,6 +724,13 @@ sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc, const cpx<fl
         CHECK_LAUNCH(P.ctx);
         return SGN_OK;
     }
+    if (mode == C1_UPDATE && col_wave(P)) {
+        hipExtLaunchKernelGGL(k_pcg_c1w<T>, dim3(L.g.nblocks), dim3(WCOL_THREADS), 0, P.ctx->stream, ps.a, ps.b, 0,
+                              P.d.nx, twiddles<T>(P.ctx), P.sc, (const double*)P.partials, P.cl.g.nblocks,
+                              (const cpx<T>*)P.b.rh, P.b.ph, P.b.H, P.d.NS, (T)P.d.tpx, (T)P.d.tpy);
+        CHECK_LAUNCH(P.ctx);
+        return SGN_OK;
+    }
     auto launch = [&](auto k, cpx<T>* ph) -> sgn_status {
         HIPCHK(P.ctx, allow_lds(k, lds));
         hipExtLaunchKernelGGL(k, dim3(L.g.nblocks), dim3(L.threads), lds, P.ctx->stream, ps.a, ps.b, 0, L.g,
@@ -750,6 +757,15 @@ template <typename T, int D>
 bool r1_wave(const PcgLaunch<T, D>& P) {
     return D == 2 && P.d.nx == WROW_NX && P.d.ny % WROW_RPB == 0 && P.d.ny / WROW_RPB <= PARTIALS_MAX &&
            !P.native && wave_rows_enabled();
+}
+// The FP32 Krylov loop's column passes on columns of 1024 points run as
+// wave-private transforms too (k_pcg_c1w, k_pcg_c2w: one column per block, as the
+// block kernels).  In FP64 the block kernels are faster (1024^2: C1 16.9 against
+// 24.2 us, C2 21.8 against 26.1 us with the wave passes).
+template <typename T, int D>
+bool col_wave(const PcgLaunch<T, D>& P) {
+    return sizeof(T) == 4 && D == 2 && P.d.ny == WCOL_NY && P.cl.g.Cb == 1 && !P.native && !P.wall &&
+           wave_rows_enabled();
 }
 // Blocks of the row pass, i.e. the p.Gp partials the next column pass reduces.
 template <typename T, int D>
@@ -814,6 +830,16 @@ sgn_status pcg_c2_mode(PcgLaunch<T, D>& P, const cpx<T>* bh, cpx<T>* rh_out, con
             return SGN_OK;
         } else {
             return fail(P.ctx, SGN_EINVAL, "pcg_c2: wall column pass takes updates and the initial residual only");
+        }
+    }
+    if constexpr (MODE == C2_UPDATE) {
+        if (col_wave(P)) {
+            hipExtLaunchKernelGGL(k_pcg_c2w<T>, dim3(L.g.nblocks), dim3(WCOL_THREADS), 0, P.ctx->stream, ps.a, ps.b,
+                                  0, P.d.nx, twiddles<T>(P.ctx), P.sc, (const cpx<T>*)P.b.H, P.d.NS,
+                                  (const cpx<T>*)P.b.ph, P.b.xh, rh_out, P.partials, nb_red, (T)P.d.tpx,
+                                  (T)P.d.tpy);
+            CHECK_LAUNCH(P.ctx);
+            return SGN_OK;
         }
     }
     if (L.epc == 2) return P.wall ? launch(k_pcg_c2<T, 2, D, MODE, true>) : launch(k_pcg_c2<T, 2, D, MODE>);

@@ -539,3 +539,190 @@ __global__ void __launch_bounds__(512) k_rhs_rows_inv_w(int ny, PtrList<const cp
 }
 
 }  // namespace sgn
+
+namespace sgn {
+
+// ---------------------------------------------------------------------------
+// Column transforms of 1024 points (complex, along y) by two waves per column
+// and field.  Forward (decimation in frequency): wave h forms
+//   h = 0: x[n] + x[n+512],   h = 1: (x[n] - x[n+512]) W1024^n,   n < 512,
+// and its 512-point transform gives X[2k + h]; both waves read the whole column
+// (the second read is served by the caches), so the forward direction needs
+// no exchange between waves.  Inverse (decimation in time): wave h transforms
+// X[2k + h] to e_h[n], and x[n] = e_0[n] + W1024^{-n} e_1[n], x[n+512] =
+// e_0[n] - W1024^{-n} e_1[n] after one exchange.  A block holds one column of
+// three fields (six waves); each wave's LDS region is its exchange buffer and
+// then holds its half of the spectrum compactly (X[2k + h] at entry k).
+// ---------------------------------------------------------------------------
+constexpr int WCOL_NY = 1024;
+constexpr int WCOL_THREADS = 384;
+
+// Wave h's forward transform of the column whose entries lo[s] = x[lane + 64 s]
+// and hi[s] = x[lane + 64 s + 512] it holds; v[s] = X[2 (lane + 64 s) + h].
+template <typename T>
+__device__ __forceinline__ void wave_col_forward(cpx<T> (&v)[8], const cpx<T> (&lo)[8], const cpx<T> (&hi)[8],
+                                                 int h, cpx<T>* buf, const WaveTwl<T>& tl, int lane) {
+    const cpx<T> r1 = tl.r[lane];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = h == 0 ? lo[s] + hi[s] : (lo[s] - hi[s]) * (r1 * w16<T>(s));
+    wave_fft512<T>(v, buf, wave_bases<T>(tl, lane), lane, false);
+}
+
+// Krylov update pass (MODE C2_UPDATE of k_pcg_c2) on columns of 1024 points:
+// reduce p.Gp -> alpha; y-FFT of the row pass's (a_x, a_y, w); q = a - i k w;
+// x += alpha p; r -= alpha q; z = A^{-1} r; partial r.z, r.r per column.  Launch:
+// nx/2 + 1 blocks of 384 threads.
+template <typename T>
+__global__ void __launch_bounds__(WCOL_THREADS) k_pcg_c2w(int nx, const cpx<T>* __restrict__ tw,
+                                                          SolveScal* __restrict__ sc, const cpx<T>* __restrict__ H,
+                                                          size_t NS, const cpx<T>* __restrict__ ph,
+                                                          cpx<T>* __restrict__ xh, cpx<T>* __restrict__ rh,
+                                                          double* __restrict__ part, int nb_r1, T tpx, T tpy) {
+    if (sc->done) return;
+    __shared__ cpx<T> ldsb[6][WROW_BUF];
+    __shared__ WaveTwl<T> tl;
+    __shared__ double red[32];
+    __shared__ double slot[1];
+    constexpr int NY = WCOL_NY;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int f = wv >> 1, h = wv & 1;
+    const int kx = blockIdx.x;
+    if (threadIdx.x < WAVE_TWL_ENTRIES) (&tl.a[0][0])[threadIdx.x] = wave_twl_entry<T>(tw, threadIdx.x);
+    // the partials of the reduction, then the columns (in flight across it)
+    double pb[PF_K][1];
+    partials_fetch<1>(part + PART_C2, nb_r1, pb);
+    __builtin_amdgcn_sched_barrier(0);
+    const cpx<T>* col = H + (size_t)f * NS + (size_t)kx * NY;
+    cpx<T> lo[8], hi[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        lo[s] = col[lane + 64 * s];
+        hi[s] = col[lane + 64 * s + 512];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double tot[1];
+    partials_sum<1, true>(part + PART_C2, nb_r1, pb, tot, red);
+    const double pq = bcast<true>(tot[0], slot);
+    const double a = sc->rho / pq;
+    const T alpha = (T)a;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->alpha = a;
+        sc->rho_prev = sc->rho;
+        sc->iter = sc->iter + 1;
+        sc->first = 0;
+    }
+    cpx<T>* buf = ldsb[wv];
+    cpx<T> v[8];
+    wave_col_forward<T>(v, lo, hi, h, buf, tl, lane);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
+    block_lds_barrier();
+    const T kxw = wavenumber<T>(kx, nx, tpx);
+    const T sig = (T)sc->sig, alp = (T)sc->alp;
+    const double w = half_weight(kx, nx);
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int j = threadIdx.x + WCOL_THREADS * i;
+        if (j < NY) {
+            const size_t idx = (size_t)kx * NY + j;
+            const T ky = wavenumber<T>(j, NY, tpy);
+            const cpx<T> wq = ldsb[4 + (j & 1)][j >> 1];
+            cpx<T> r[2], z[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const T kc = (c == 0) ? kxw : ky;
+                const cpx<T> q = ldsb[2 * c + (j & 1)][j >> 1] - ik(kc, wq);
+                xh[c * NS + idx] = xh[c * NS + idx] + alpha * ph[c * NS + idx];
+                r[c] = rh[c * NS + idx] - alpha * q;
+                rh[c * NS + idx] = r[c];
+            }
+            precond_mode<T, 2>(kxw, ky, sig, alp, r, z);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                acc[0] += w * ((double)r[c].re * (double)z[c].re + (double)r[c].im * (double)z[c].im);
+                acc[1] += w * ((double)r[c].re * (double)r[c].re + (double)r[c].im * (double)r[c].im);
+            }
+        }
+    }
+    block_sum<2>(acc, red);
+    if (threadIdx.x == 0) {
+        part[PART_C3 + 2 * blockIdx.x] = acc[0];
+        part[PART_C3 + 2 * blockIdx.x + 1] = acc[1];
+    }
+}
+
+// Krylov direction pass (MODE C1_UPDATE of k_pcg_c1) on columns of 1024 points:
+// reduce r.z, r.r -> stop test, beta; z = A^{-1} r; p = z + beta p; emit
+// (p, div p)/N and y-IFFT it into H.  Launch: nx/2 + 1 blocks of 384 threads.
+template <typename T>
+__global__ void __launch_bounds__(WCOL_THREADS) k_pcg_c1w(int nx, const cpx<T>* __restrict__ tw,
+                                                          SolveScal* __restrict__ sc, const double* __restrict__ part,
+                                                          int nb3, const cpx<T>* __restrict__ rh,
+                                                          cpx<T>* __restrict__ ph, cpx<T>* __restrict__ H, size_t NS,
+                                                          T tpx, T tpy) {
+    if (sc->done) return;
+    __shared__ cpx<T> ldsb[6][WROW_BUF];
+    __shared__ WaveTwl<T> tl;
+    __shared__ double red[32];
+    __shared__ double slot[2];
+    constexpr int NY = WCOL_NY;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int f = wv >> 1, h = wv & 1;
+    const int kx = blockIdx.x;
+    if (threadIdx.x < WAVE_TWL_ENTRIES) (&tl.a[0][0])[threadIdx.x] = wave_twl_entry<T>(tw, threadIdx.x);
+    double beta_d = 0.0;
+    if (pcg_iterate_state(sc, part, nb3, red, slot, beta_d)) return;
+    const T beta = (T)beta_d, sig = (T)sc->sig, alp = (T)sc->alp, inv_n = (T)sc->inv_n;
+    const T kxw = wavenumber<T>(kx, nx, tpx);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int j = threadIdx.x + WCOL_THREADS * i;
+        if (j < NY) {
+            const size_t idx = (size_t)kx * NY + j;
+            const T ky = wavenumber<T>(j, NY, tpy);
+            cpx<T> r[2], z[2], p[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) r[c] = rh[c * NS + idx];
+            precond_mode<T, 2>(kxw, ky, sig, alp, r, z);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                // beta = 0 on the first iteration: p = z without reading the
+                // previous (unset) direction
+                p[c] = (beta != (T)0) ? z[c] + beta * ph[c * NS + idx] : z[c];
+                ph[c * NS + idx] = p[c];
+            }
+            const cpx<T> dv = ik(kxw, p[0]) + ik(ky, p[1]);
+            ldsb[0 + (j & 1)][j >> 1] = inv_n * p[0];
+            ldsb[2 + (j & 1)][j >> 1] = inv_n * p[1];
+            ldsb[4 + (j & 1)][j >> 1] = inv_n * dv;
+        }
+    }
+    block_lds_barrier();
+    cpx<T>* buf = ldsb[wv];
+    cpx<T> v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = buf[lane + 64 * s];
+    wave_lds_sync();
+    wave_fft512<T>(v, buf, wave_bases<T>(tl, lane), lane, true);
+    // e_0 (h = 0) or W1024^{-n} e_1 (h = 1) at entry n = lane + 64 s
+    if (h == 1) {
+        const cpx<T> r1 = tl.r[lane];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = v[s] * cj(r1 * w16<T>(s));
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
+    block_lds_barrier();
+    const cpx<T>* other = ldsb[wv ^ 1];
+    cpx<T>* out = H + (size_t)f * NS + (size_t)kx * NY + (h ? 512 : 0);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int n = lane + 64 * s;
+        const cpx<T> o = other[n];
+        out[n] = h == 0 ? v[s] + o : o - v[s];
+    }
+}
+
+}  // namespace sgn

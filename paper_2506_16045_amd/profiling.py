@@ -38,10 +38,10 @@ def kernel_family(demangled: str, grid_size: int = 0, n: int = 0):
     if re.search(r"k_cols_lin_jobs<double, 4, [34], 3>", demangled) and n:
         jobs = round(grid_size / (256 * (n // 2 + 1)))
         return ("rhs_cols", "f64") if jobs == 3 else ("rhs_flux", "f64") if jobs == 2 else None
-    m = re.search(r"k_pcg_(c1|r1w?|c2|init)<(double|float)(?:, (\d+))?(?:, (\d+))?(?:, (\d+|true|false))?", demangled)
+    m = re.search(r"k_pcg_(c1|r1|c2|init)w?<(double|float)(?:, (\d+))?(?:, (\d+))?(?:, (\d+|true|false))?", demangled)
     if not m:
         return None
-    fam, typ = m.group(1).rstrip("w"), m.group(2)   # k_pcg_r1w: the wave-private row pass
+    fam, typ = m.group(1), m.group(2)   # k_pcg_r1w, k_pcg_c1w, k_pcg_c2w: the wave-private passes
     mode = m.group(5)
     if fam == "c1" and mode not in (None, "0"):
         return None           # initial-residual copy mode, not the loop pass
