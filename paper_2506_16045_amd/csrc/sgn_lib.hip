@@ -2007,8 +2007,10 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
         };
         // the forward pass holds no pointwise state: its fields go three at a time
         const size_t l3 = row_lds_bytes<double>(RL.g, 3);
-        // (one wave per field and row measured slower here, 47 -> 58 us at 1024^2:
-        // the nine fields' waves each re-read the shared inputs)
+        // (wave-private forms measured slower at 1024^2: one wave per field and row
+        // 47 -> 58 us, each field's wave re-reading the shared inputs; one wave per
+        // row and group of fields sharing inputs 47 -> 65 us, the group's fields
+        // transformed one after another in each wave)
         if (RL.epc == 4 && RL.threads <= 256 && l3 <= LDS_MULTI_MAX) {
             HIPCHK(ctx, allow_lds(k_rhs_rows_fwd<D, 4, 3, 256>, l3));
             hipLaunchKernelGGL((k_rhs_rows_fwd<D, 4, 3, 256>), dim3(RL.g.nblocks), dim3(RL.threads), l3,
