@@ -21,6 +21,7 @@ struct SolveScal {
     int iter, max_iter, done, converged, flat, status;
     int first;                // 1 until the first update (beta = 0)
     int init_bb;              // 1: ||b|| is the norm of the initial residual
+    int outer;                // refinement steps taken (mixed precision)
 };
 
 constexpr int PARTIALS_MAX = 4096;  // blocks of a reducing launch (256 PF_K)
@@ -854,6 +855,7 @@ __device__ __forceinline__ void publish_flags(const SolveScal* sc, int* d, int s
     v[3] = sc->converged;
     v[4] = sc->flat;
     v[5] = sc->status;
+    v[7] = sc->outer;
     v[6] = seq;
 }
 __global__ void __launch_bounds__(256) k_pcg_check(SolveScal* __restrict__ sc, const double* __restrict__ part,
@@ -1448,6 +1450,7 @@ __global__ void k_init_scal(SolveScal* __restrict__ sc, double tol, int max_iter
     sc->status = 0;
     sc->first = 1;
     sc->init_bb = init_bb;
+    sc->outer = 0;
     if (have_coeffs) {
         sc->sig = sig;
         sc->alp = alp;
@@ -1456,24 +1459,48 @@ __global__ void k_init_scal(SolveScal* __restrict__ sc, double tol, int max_iter
     }
 }
 
-// Inner solve of the refinement: coefficients from the outer solve.
-// Inner solve of a refinement step: the coefficients of the outer solve, and an
-// inner tolerance no tighter than the outer target needs.  With outer residual
-// r, target tol ||b|| and inner stop ||r_in|| <= t ||r||, the inner tolerance is
-// t = max(t_min, c tol ||b|| / ||r||) (c2 = c^2): once r is within a few orders
-// of the target, the inner solve stops as soon as the corrected outer residual
-// will meet it, instead of always reducing by t_min.
-__global__ void k_inner_setup(const SolveScal* __restrict__ s, SolveScal* __restrict__ d, double c2) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        d->sig = s->sig;
-        d->alp = s->alp;
-        d->kap = s->kap;
-        d->flat = s->flat;
-        if (s->rr > 0.0 && s->bb > 0.0) {
-            const double t2 = c2 * s->tol2 * (s->bb / s->rr);
-            if (t2 > d->tol2) d->tol2 = t2 < 0.25 ? t2 : 0.25;
-        }
+// One refinement step enqueued without a host round trip: k_inner_open starts
+// the inner FP32 solve d of the step (the scalars of k_init_scal, the outer
+// solve's coefficients), or, when the outer solve s has already converged, marks
+// the inner solve done so that every kernel of the step returns at once.  The
+// inner tolerance is no tighter than the outer target needs: with outer residual
+// r, target tol ||b|| and inner stop ||r_in|| <= t ||r||, t = max(t_min,
+// c tol ||b|| / ||r||) (c2 = c^2), so once r is within a few orders of the target
+// the inner solve stops as soon as the corrected outer residual will meet it.
+// k_inner_close adds the step's inner iterations and the step itself to the
+// outer solve's counters (s->iter, s->outer) unless it was skipped.
+__global__ void k_inner_open(const SolveScal* __restrict__ s, SolveScal* __restrict__ d, double tol, int max_iter,
+                             double inv_n, double c2) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (s->done) {
+        d->done = 1;
+        return;
     }
+    d->rho = d->rho_prev = d->alpha = d->beta = d->bb = d->rr = d->pq = d->relres = 0.0;
+    d->tol2 = tol * tol;
+    d->inv_n = inv_n;
+    d->iter = 0;
+    d->max_iter = max_iter;
+    d->done = 0;
+    d->converged = 0;
+    d->status = 0;
+    d->first = 1;
+    d->init_bb = 1;
+    d->outer = 0;
+    d->sig = s->sig;
+    d->alp = s->alp;
+    d->kap = s->kap;
+    d->flat = s->flat;
+    if (s->rr > 0.0 && s->bb > 0.0) {
+        const double t2 = c2 * s->tol2 * (s->bb / s->rr);
+        if (t2 > d->tol2) d->tol2 = t2 < 0.25 ? t2 : 0.25;
+    }
+}
+__global__ void k_inner_close(SolveScal* __restrict__ s, const SolveScal* __restrict__ d) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (s->done) return;
+    s->iter += d->iter;
+    s->outer += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1717,6 +1744,7 @@ __global__ void __launch_bounds__(256) k_inner_start(int nx, int ny, size_t NS, 
                                                      cpx<float>* __restrict__ r32, cpx<float>* __restrict__ x32,
                                                      double* __restrict__ part, float tpx, float tpy) {
     __shared__ double red[32];
+    if (sc->done) return;   // the refinement had already converged (see k_inner_open)
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->first = 1;
     const float sig = (float)sc->sig, alp = (float)sc->alp;
     double acc[2] = {0.0, 0.0};

@@ -1036,6 +1036,7 @@ sgn_status pcg_chunk(PcgLaunch<T, D>& P, int chunk, bool* published) {
 // Integer state of a solve after its last readback.
 struct LoopOut {
     int iter = 0, done = 0, converged = 0, status = 0;
+    int outer = -1;   // refinement steps taken (published flags only; -1 unknown)
 };
 
 // Read iter, max_iter, done, converged, flat, status of a solve (synchronises the stream).
@@ -1091,6 +1092,7 @@ sgn_status wait_loop_readback(sgn_ctx* ctx, LoopOut* out) {
     out->done = f[2];
     out->converged = f[3];
     out->status = f[5];
+    out->outer = ctx->dpub ? f[7] : -1;
     return SGN_OK;
 }
 
@@ -1394,37 +1396,11 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
     LoopOut lo;
-    for (; outer < max_outer; ++outer) {
-        if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
-        if ((s = read_loop(ctx, P.sc, &lo)) != SGN_OK) return s;
-        if (lo.done) break;
-        // inner FP32 solve of G dx = r from dx = 0; ||b_inner|| = ||r_outer||
-        if ((s = init_scal(ctx, Q.sc, inner_tol, o.max_iter, d.inv_n, nullptr, 1)) != SGN_OK) return s;
-        hipLaunchKernelGGL(k_inner_setup, dim3(1), dim3(64), 0, ctx->stream, (const SolveScal*)P.sc, Q.sc,
-                           INNER_SAFETY2);
-        {
-            ProfScope ps(ctx, SGN_KERNEL_PCG_INIT + 6);
-            // r32 = r, x32 = 0 and the inner solve's first partials, in one pass
-            hipLaunchKernelGGL((k_inner_start<D>), dim3(Q.cl.g.nblocks), dim3(256), 0, ctx->stream, d.nx, d.ny, d.NS,
-                               Q.sc, (const cpx<double>*)P.b.rh, Q.b.rh, Q.b.xh, Q.partials, (float)d.tpx,
-                               (float)d.tpy);
-            CHECK_LAUNCH(ctx);
-        }
-        LoopOut li;
-        if ((s = pcg_loop<float, D>(Q, o.max_iter, o.check_every, &li)) != SGN_OK) return s;
-        total_inner += li.iter;
-        // x_hat += dx_hat inside the pass that starts G x_hat; r_hat = b_hat - G x_hat
-        // (FP64) with its dot products; stop test
-        if ((s = pcg_c1<double, D>(P, C1_ACCUM, nullptr, Q.b.xh)) != SGN_OK) return s;
-        if ((s = pcg_r1<double, D>(P)) != SGN_OK) return s;
-        if ((s = pcg_c2<double, D>(P, C2_RESID, P.b.bh, P.b.rh)) != SGN_OK) return s;
-    }
-    if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
-    {
+    auto store = [&]() -> sgn_status {
         auto k = P.cl.epc == 2 ? k_cols_from_S<double, 2, D> : k_cols_from_S<double, 4, D>;
         HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
-        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D), ctx->stream, P.cl.g, ctx->tw64,
-                           (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
+        hipLaunchKernelGGL(k, dim3(P.cl.g.nblocks), dim3(P.cl.threads), col_lds_bytes<double>(P.cl.g, D),
+                           ctx->stream, P.cl.g, ctx->tw64, (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
         CHECK_LAUNCH(ctx);
         std::vector<const cpx<double>*> hs;
         std::vector<double*> ud;
@@ -1432,7 +1408,82 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
             hs.push_back(P.b.H + c * d.NS);
             ud.push_back(u + c * d.N);
         }
-        if ((s = rows_inv<double, double>(ctx, d, hs, ud)) != SGN_OK) return s;
+        return rows_inv<double, double>(ctx, d, hs, ud);
+    };
+    // the inner FP32 solve of one refinement step and the FP64 residual after it;
+    // k_inner_open marks the inner solve done when the outer stop test has
+    // already converged, so that every kernel of the step returns at once
+    auto open_inner = [&]() -> sgn_status {
+        hipLaunchKernelGGL(k_inner_open, dim3(1), dim3(64), 0, ctx->stream, (const SolveScal*)P.sc, Q.sc, inner_tol,
+                           o.max_iter, d.inv_n, INNER_SAFETY2);
+        CHECK_LAUNCH(ctx);
+        ProfScope ps(ctx, SGN_KERNEL_PCG_INIT + 6);
+        // r32 = r, x32 = 0 and the inner solve's first partials, in one pass
+        hipLaunchKernelGGL((k_inner_start<D>), dim3(Q.cl.g.nblocks), dim3(256), 0, ctx->stream, d.nx, d.ny, d.NS, Q.sc,
+                           (const cpx<double>*)P.b.rh, Q.b.rh, Q.b.xh, Q.partials, (float)d.tpx, (float)d.tpy);
+        CHECK_LAUNCH(ctx);
+        return SGN_OK;
+    };
+    auto close_inner = [&]() -> sgn_status {
+        hipLaunchKernelGGL(k_inner_close, dim3(1), dim3(64), 0, ctx->stream, P.sc, (const SolveScal*)Q.sc);
+        CHECK_LAUNCH(ctx);
+        // x_hat += dx_hat inside the pass that starts G x_hat; r_hat = b_hat - G x_hat
+        // (FP64) with its dot products
+        sgn_status t;
+        if ((t = pcg_c1<double, D>(P, C1_ACCUM, nullptr, Q.b.xh)) != SGN_OK) return t;
+        if ((t = pcg_r1<double, D>(P)) != SGN_OK) return t;
+        return pcg_c2<double, D>(P, C2_RESID, P.b.bh, P.b.rh);
+    };
+    // stop test of the initial residual (a step after it returns at once if it converged)
+    if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
+    if (ctx->stage) {
+        // Stepper solves: refinement steps are enqueued without waiting for the
+        // host; the inner solve runs a fixed chunk of iterations sized from the
+        // stepping state's previous solve (one that has not converged in it still
+        // yields a correction: the FP64 residual decides, and the next step's
+        // chunk is twice as long).  The host reads the flags once per step, with
+        // the store of the result already enqueued behind them; steps and inner
+        // iterations are counted on the device.  The chunk depends only on the
+        // state's own history, so a run's result does not depend on what else
+        // its context solved.
+        int& last_in = ctx->stage_last[1];
+        int chunk_in = std::max(1, std::min(o.max_iter, last_in > 0 ? last_in + 1 : o.check_every));
+        while (outer < max_outer) {
+            if ((s = open_inner()) != SGN_OK) return s;
+            if ((s = pcg_chunk_eager<float, D>(Q, chunk_in)) != SGN_OK) return s;
+            if ((s = close_inner()) != SGN_OK) return s;
+            ++outer;
+            if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
+            if ((s = issue_loop_readback(ctx, P.sc)) != SGN_OK) return s;
+            if ((s = store()) != SGN_OK) return s;
+            if ((s = wait_loop_readback(ctx, &lo)) != SGN_OK) return s;
+            if (lo.done) break;
+            chunk_in = std::min(o.max_iter, 2 * chunk_in);
+        }
+        if (lo.outer > 0) last_in = (lo.iter + lo.outer - 1) / lo.outer;
+    } else {
+        // Standalone and served solves: every inner solve runs to its own
+        // tolerance (host-checked chunks), so the result does not depend on the
+        // context's earlier solves.
+        if ((s = read_loop(ctx, P.sc, &lo)) != SGN_OK) return s;
+        while (!lo.done && outer < max_outer) {
+            if ((s = open_inner()) != SGN_OK) return s;
+            LoopOut li;
+            if ((s = pcg_loop<float, D>(Q, o.max_iter, o.check_every, &li)) != SGN_OK) return s;
+            if ((s = close_inner()) != SGN_OK) return s;
+            ++outer;
+            if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
+            if ((s = read_loop(ctx, P.sc, &lo)) != SGN_OK) return s;
+        }
+        if ((s = store()) != SGN_OK) return s;
+    }
+    if (lo.outer >= 0) {   // the device's counts (published with the flags)
+        total_inner = lo.iter;
+        outer = lo.outer;
+    } else {
+        if ((s = read_scal(ctx, P.sc)) != SGN_OK) return s;
+        total_inner = ctx->hscal->iter;
+        outer = ctx->hscal->outer;
     }
     if (ctx->stage && lo.done) {
         if (info) {

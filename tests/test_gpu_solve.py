@@ -53,10 +53,19 @@ def _oracle_solve(g, eta, gh, fl, b, tol, x0=None):
                       tol=tol, max_iter=2000)
 
 
-def _rows_1024(ny, seed):
-    """Rows of 1024 points over few rows (the wave-private Krylov row pass):
-    random positive depth and smooth bathymetry, b = G u* for a smooth u*."""
+def _rows_1024(ny, seed, nx=1024):
+    """Rows of 1024 points over few rows (the wave-private Krylov row pass), or
+    with nx < 1024 and ny = 1024 columns of 1024 points over few columns (the
+    wave-private FP32 column passes of the mixed form): random positive depth and
+    smooth bathymetry, b = G u* for a smooth u*."""
+    if nx != 1024:
+        g = I.grid2d(nx, 1024, 100.0 * nx / 1024, 100.0)
+        return _fields_b(g, seed)
     g = I.grid2d(1024, ny, 100.0, 100.0 * ny / 1024)
+    return _fields_b(g, seed)
+
+
+def _fields_b(g, seed):
     rng = np.random.default_rng(seed)
     eta = I.random_positive_depth(g, rng, 0.6, 1.6)
     h = 1.0 + 0.2 * I.random_smooth_field(g, rng, modes=3)
@@ -69,6 +78,7 @@ CASES = [
     ("1d-test-problem-256", lambda: I.pcg_test_problem_1d(256, 1.0, 1.0)),
     ("2d-rows1024-ny4", lambda: _rows_1024(4, 61)),
     ("2d-rows1024-ny32", lambda: _rows_1024(32, 62)),
+    ("2d-cols1024-nx16", lambda: _rows_1024(1024, 63, nx=16)),
     ("1d-test-problem-4096-eta4", lambda: I.pcg_test_problem_1d(4096, 4.0, 0.5)),
     ("1d-test-problem-16384", lambda: I.pcg_test_problem_1d(16384, 1.0, 1.0)),
     ("2d-elliptic-bump-64-a1b1", lambda: I.elliptical_bump_2d(64, 1.0, 1.0)),
