@@ -224,23 +224,35 @@ __global__ void __launch_bounds__(192 * RPB) __attribute__((amdgpu_waves_per_eu(
     const int y = xcd_remap(blockIdx.x, gridDim.x) * RPB + rb;
     cpx<T>* Hrow = H + (size_t)f * NS + y;
     cpx<T>* buf = lds[f];
-    // twiddle table first (L2-resident; one L2 round trip per block instead of
-    // one per transform stage), then the row's transposed loads.  Row loads in
+    // FP64: twiddle table first (L2-resident; one L2 round trip per block instead
+    // of one per transform stage), then the row's transposed loads (row loads in
     // flight across a block barrier were spilled to scratch by the compiler, so
-    // the table's barrier comes before them.
+    // the table's barrier comes before them).  FP32 has the registers to hold
+    // the lane's seven twiddle bases: they are loaded with the row, no table.
+    constexpr bool TWREG = sizeof(T) == 4;
+    WaveBases<T> wbr;
+    cpx<T> r1r;
+    if (TWREG) {
+        if (done) return;
+        wbr = wave_bases<T>(tw, lane);
+        r1r = tw_size(tw, WROW_NX)[lane];
+    } else {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int e = threadIdx.x + i * blockDim.x;
-        if (e < WAVE_TWL_ENTRIES) (&tl.a[0][0])[e] = wave_twl_entry<T>(tw, e);
+        for (int i = 0; i < 2; ++i) {
+            const int e = threadIdx.x + i * blockDim.x;
+            if (e < WAVE_TWL_ENTRIES) (&tl.a[0][0])[e] = wave_twl_entry<T>(tw, e);
+        }
+        block_lds_barrier();
+        if (done) return;
     }
-    block_lds_barrier();
-    if (done) return;
+    auto bases = [&]() { return TWREG ? wbr : wave_bases<T>(tl, lane); };
+    auto r1 = [&]() { return TWREG ? r1r : tl.r[lane]; };
     cpx<T> X[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) X[s] = Hrow[(size_t)(lane + 64 * s) * ny];
     const cpx<T> XM = lane == 0 ? Hrow[(size_t)WROW_M * ny] : C<T>(0, 0);
     cpx<T> v[8];
-    wave_c2r_split<T>(v, X, XM, buf, tl.r[lane], lane);
+    wave_c2r_split<T>(v, X, XM, buf, r1(), lane);
     const size_t npts = (size_t)WROW_NX * ny;
     const int m0 = 3 * f;
     const int ms = f == 2 ? 2 : 3;
@@ -260,7 +272,7 @@ __global__ void __launch_bounds__(192 * RPB) __attribute__((amdgpu_waves_per_eu(
         }
     };
     if (PF) load_coeffs();
-    wave_fft512<T>(v, buf, wave_bases<T>(tl, lane), lane, true);
+    wave_fft512<T>(v, buf, bases(), lane, true);
 #pragma unroll
     for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
     block_lds_barrier();
@@ -310,8 +322,8 @@ __global__ void __launch_bounds__(192 * RPB) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = buf[lane + 64 * s];
     wave_lds_sync();
-    wave_fft512<T>(v, buf, wave_bases<T>(tl, lane), lane, false);
-    wave_r2c_store<T>(v, buf, tl.r[lane], lane, Hrow, ny, (T)1);
+    wave_fft512<T>(v, buf, bases(), lane, false);
+    wave_r2c_store<T>(v, buf, r1(), lane, Hrow, ny, (T)1);
 }
 
 }  // namespace sgn
