@@ -752,10 +752,14 @@ sgn_status pcg_c1(PcgLaunch<T, D>& P, int mode, const cpx<T>* xsrc, const cpx<fl
     return SGN_OK;
 }
 
-constexpr int WROW_RPB = 1;   // rows per block of the wave-private Krylov row pass
+// Rows per wave of the wave-private Krylov row pass: two in FP32 (16-byte
+// accesses to the transposed layout), one in FP64 (two would not fit the
+// registers of three waves per SIMD).
+template <typename T>
+constexpr int r1_rows() { return sizeof(T) == 4 ? 2 : 1; }
 template <typename T, int D>
 bool r1_wave(const PcgLaunch<T, D>& P) {
-    return D == 2 && P.d.nx == WROW_NX && P.d.ny % WROW_RPB == 0 && P.d.ny / WROW_RPB <= PARTIALS_MAX &&
+    return D == 2 && P.d.nx == WROW_NX && P.d.ny % r1_rows<T>() == 0 && P.d.ny / r1_rows<T>() <= PARTIALS_MAX &&
            !P.native && wave_rows_enabled();
 }
 // The FP32 Krylov loop's column passes on columns of 1024 points run as
@@ -769,14 +773,14 @@ bool col_wave(const PcgLaunch<T, D>& P) {
 }
 // Blocks of the row pass, i.e. the p.Gp partials the next column pass reduces.
 template <typename T, int D>
-int r1_blocks(const PcgLaunch<T, D>& P) { return r1_wave(P) ? P.d.ny / WROW_RPB : P.rl.g.nblocks; }
+int r1_blocks(const PcgLaunch<T, D>& P) { return r1_wave(P) ? P.d.ny / r1_rows<T>() : P.rl.g.nblocks; }
 
 template <typename T, int D>
 sgn_status pcg_r1(PcgLaunch<T, D>& P, bool curvature = false) {
     ProfScope ps(P.ctx, SGN_KERNEL_PCG_R1 + (sizeof(T) == 4 ? 6 : 0), true);
     double* part = curvature ? P.partials : nullptr;
     if (r1_wave(P)) {
-        hipExtLaunchKernelGGL(k_pcg_r1w<T, WROW_RPB>, dim3(P.d.ny / WROW_RPB), dim3(192 * WROW_RPB), 0,
+        hipExtLaunchKernelGGL(k_pcg_r1w<T, r1_rows<T>()>, dim3(P.d.ny / r1_rows<T>()), dim3(192), 0,
                               P.ctx->stream, ps.a, ps.b, 0, P.d.ny,
                               twiddles<T>(P.ctx), P.sc, P.b.H, P.d.NS, P.eta, P.gh, part, PART_C2);
         CHECK_LAUNCH(P.ctx);
@@ -1396,6 +1400,10 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
     const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
     LoopOut lo;
+    // u = IFFT(x_hat) and the stepper's offset record (as in the FP64 solve: the
+    // guess was formed from the base while pcg_start loaded it); a store after a
+    // further refinement step adds its difference to the offset
+    int stores = 0;
     auto store = [&]() -> sgn_status {
         auto k = P.cl.epc == 2 ? k_cols_from_S<double, 2, D> : k_cols_from_S<double, 4, D>;
         HIPCHK(ctx, allow_lds(k, col_lds_bytes<double>(P.cl.g, D)));
@@ -1403,12 +1411,13 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
                            ctx->stream, P.cl.g, ctx->tw64, (const cpx<double>*)P.b.xh, d.NS, P.b.H, d.inv_n);
         CHECK_LAUNCH(ctx);
         std::vector<const cpx<double>*> hs;
-        std::vector<double*> ud;
+        std::vector<double*> ud, od;
         for (int c = 0; c < D; ++c) {
             hs.push_back(P.b.H + c * d.NS);
             ud.push_back(u + c * d.N);
+            if (ctx->gx_off) od.push_back(ctx->gx_off + c * d.N);
         }
-        return rows_inv<double, double>(ctx, d, hs, ud);
+        return rows_inv<double, double>(ctx, d, hs, ud, 1.0, 0.0, ctx->gx_off ? &od : nullptr, stores++ > 0);
     };
     // the inner FP32 solve of one refinement step and the FP64 residual after it;
     // k_inner_open marks the inner solve done when the outer stop test has
@@ -2598,9 +2607,10 @@ sgn_status stage_solve(sgn_state* st, int slot, const double* eta, const double*
     StateBufs& b = st->b;
     const size_t DN = (size_t)st->d.D * st->d.N;
     const bool ex = o.guess == SGN_GUESS_EXTRAPOLATE;
-    // FP64 PCG on the row/column path forms the guess and records the offset inside
-    // its first and last passes; the other paths do both with separate passes
-    const bool fused = ex && o.precision == SGN_FP64 && o.method == SGN_PCG &&
+    // PCG on the row/column path (FP64 and mixed) forms the guess and records the
+    // offset inside its first and last passes; the one-workgroup 1D solve does
+    // both with separate passes
+    const bool fused = ex && (o.precision == SGN_FP64 || o.precision == SGN_MIXED) && o.method == SGN_PCG &&
                        !(st->d.D == 1 && st->d.nx <= BATCH_NMAX);
     sgn_status s;
     int& cnt = st->gx_count[slot];

@@ -91,9 +91,6 @@ __device__ __forceinline__ cpx<T> w16(int j) {
     }
 }
 
-// 512-point FFT of one field held by one wave.  In: v[s] = x[lane + 64 s];
-// out: v[s] = X[lane + 64 s] (forward: exp(-i), inverse: exp(+i), unnormalised).
-// buf: this wave's WROW_BUF entries of LDS.
 // The six twiddle bases of one lane's transform stages.
 template <typename T>
 struct WaveBases {
@@ -113,36 +110,85 @@ __device__ __forceinline__ WaveBases<T> wave_bases(const cpx<T>* __restrict__ tw
     return WaveBases<T>{t512[lane], t512[2 * lane], t512[4 * lane], t512[8 * l1], t512[16 * l1], t512[32 * l1]};
 }
 
+// 512-point FFT of one field held by one wave.  In: v[s] = x[lane + 64 s];
+// out: v[s] = X[lane + 64 s] (forward: exp(-i), inverse: exp(+i), unnormalised).
 // Twiddles: per stage three bases a, a^2, a^4, the other powers by products.
-template <typename T>
-__device__ __forceinline__ void wave_fft512(cpx<T> (&v)[8], cpx<T>* buf, const WaveBases<T>& wb, int lane,
-                                            bool inverse) {
+// NR rows of one field held by one wave go through the stages in lockstep: their
+// exchanges share the wave's synchronisations, and entry e of row r sits at
+// buf[NR e + r], so the rows' entries of one exchange index are adjacent in LDS
+// (one 16-byte access for two FP32 rows).  buf: NR WROW_BUF entries.
+template <typename T, int NR>
+__device__ __forceinline__ void wave_fft512_rows(cpx<T> (&v)[NR][8], cpx<T>* buf, const WaveBases<T>& wb,
+                                                 int lane, bool inverse) {
     // first stage: 8-point DFT over m, twiddle W512^{l k1}; lane l holds k1 = 0..7
-    dft_small<T, 8>(v, inverse);
-    wave_twiddle7(v, wb.a1, wb.a2, wb.a4, inverse);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) buf[k * WROW_S1 + lane] = v[k];
+    for (int r = 0; r < NR; ++r) {
+        dft_small<T, 8>(v[r], inverse);
+        wave_twiddle7(v[r], wb.a1, wb.a2, wb.a4, inverse);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) buf[NR * (k * WROW_S1 + lane) + r] = v[r][k];
     wave_lds_sync();
     // second stage: lane = l1 + 8 k1 takes l2 = 0..7 of l = l1 + 8 l2
     {
         const int l1 = lane & 7, k1 = lane >> 3;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = buf[k1 * WROW_S1 + l1 + 8 * q];
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) v[r][q] = buf[NR * (k1 * WROW_S1 + l1 + 8 * q) + r];
     }
     wave_lds_sync();
-    dft_small<T, 8>(v, inverse);
-    wave_twiddle7(v, wb.b1, wb.b2, wb.b4, inverse);   // W64^{l1 j1}
 #pragma unroll
-    for (int j = 0; j < 8; ++j) buf[j * WROW_S2 + lane + (lane >> 3)] = v[j];
+    for (int r = 0; r < NR; ++r) {
+        dft_small<T, 8>(v[r], inverse);
+        wave_twiddle7(v[r], wb.b1, wb.b2, wb.b4, inverse);   // W64^{l1 j1}
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) buf[NR * (j * WROW_S2 + lane + (lane >> 3)) + r] = v[r][j];
     wave_lds_sync();
     // third stage: lane = k1 + 8 j1 takes l1 = 0..7 (written by lane l1 + 8 k1)
     {
         const int k1 = lane & 7, j1 = lane >> 3;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = buf[j1 * WROW_S2 + q + 9 * k1];
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) v[r][q] = buf[NR * (j1 * WROW_S2 + q + 9 * k1) + r];
     }
     wave_lds_sync();
-    dft_small<T, 8>(v, inverse);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dft_small<T, 8>(v[r], inverse);
+}
+template <typename T>
+__device__ __forceinline__ void wave_fft512(cpx<T> (&v)[8], cpx<T>* buf, const WaveBases<T>& wb, int lane,
+                                            bool inverse) {
+    wave_fft512_rows<T, 1>(reinterpret_cast<cpx<T>(&)[1][8]>(v), buf, wb, lane, inverse);
+}
+
+// Entry e of NR consecutive rows of a transposed field (rows are its fast
+// index, so the entries are adjacent): one 16-byte access for two FP32 rows.
+template <typename T, int NR>
+__device__ __forceinline__ void rows_load(const cpx<T>* p, cpx<T> (&x)[NR]) {
+    if constexpr (NR == 2 && sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        x[0] = C<T>(q.x, q.y);
+        x[1] = C<T>(q.z, q.w);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) x[r] = p[r];
+    }
+}
+template <typename T, int NR>
+__device__ __forceinline__ void rows_store(cpx<T>* p, const cpx<T> (&x)[NR]) {
+    if constexpr (NR == 2 && sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(x[0].re, x[0].im, x[1].re, x[1].im);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) p[r] = x[r];
+    }
 }
 
 // Half spectrum of one real row (H layout: entry kx at Hrow[kx * ny], kx = 0..M)
@@ -150,78 +196,120 @@ __device__ __forceinline__ void wave_fft512(cpx<T> (&v)[8], cpx<T>* buf, const W
 // i (X_k - X*_{M-k}) W1024^{-k}, Z_0 = (X_0 + X_M) + i (X_0 - X_M) on the real
 // parts.  X: the loaded entries X[lane + 64 s]; XM: X[M] (lane 0).
 // The loaded entries go to LDS and are read back with their mirrors, so they
-// do not stay live in registers across the exchange.
-template <typename T>
-__device__ __forceinline__ void wave_c2r_split(cpx<T> (&v)[8], const cpx<T> (&X)[8], cpx<T> XM, cpx<T>* buf,
-                                               cpx<T> r1, int lane) {
+// do not stay live in registers across the exchange.  NR rows in lockstep, LDS
+// layout as in wave_fft512_rows.
+template <typename T, int NR>
+__device__ __forceinline__ void wave_c2r_split_rows(cpx<T> (&v)[NR][8], const cpx<T> (&X)[NR][8],
+                                                    const cpx<T> (&XM)[NR], cpx<T>* buf, cpx<T> r1, int lane) {
+    T x0[NR];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = X[s];
-    const T x0 = X[0].re;
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) buf[NR * (lane + 64 * s) + r] = X[r][s];
+        x0[r] = X[r][0].re;
+    }
     wave_lds_sync();
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         const cpx<T> wk = cj(r1 * w16<T>(s));
-        const cpx<T> xk = buf[lane + 64 * s];
-        const cpx<T> xm = buf[(WROW_M - lane - 64 * s) & (WROW_M - 1)];
-        v[s] = (xk + cj(xm)) + mul_i((xk - cj(xm)) * wk);
+        const int m = (WROW_M - lane - 64 * s) & (WROW_M - 1);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const cpx<T> xk = buf[NR * (lane + 64 * s) + r];
+            const cpx<T> xm = buf[NR * m + r];
+            v[r][s] = (xk + cj(xm)) + mul_i((xk - cj(xm)) * wk);
+        }
     }
     wave_lds_sync();
-    if (lane == 0) v[0] = C<T>(x0 + XM.re, x0 - XM.re);
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r][0] = C<T>(x0[r] + XM[r].re, x0[r] - XM[r].re);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void wave_c2r_split(cpx<T> (&v)[8], const cpx<T> (&X)[8], cpx<T> XM, cpx<T>* buf,
+                                               cpx<T> r1, int lane) {
+    const cpx<T> xm[1] = {XM};
+    wave_c2r_split_rows<T, 1>(reinterpret_cast<cpx<T>(&)[1][8]>(v), reinterpret_cast<const cpx<T>(&)[1][8]>(X), xm,
+                              buf, r1, lane);
 }
 
 // Forward transform output Z[lane + 64 s] (v) to the half spectrum,
 // X_k = (Z_k + Z*_{M-k})/2 - i W1024^k (Z_k - Z*_{M-k})/2, X_0 and X_M from Z_0,
-// each multiplied by scale and stored at Hrow[kx * ny].
-template <typename T>
-__device__ __forceinline__ void wave_r2c_store(const cpx<T> (&v)[8], cpx<T>* buf, cpx<T> r1, int lane,
-                                               cpx<T>* Hrow, int ny, T scale) {
+// each multiplied by scale and stored at Hrow[kx * ny] (NR rows: row r at
+// Hrow + r, the rows' entries stored together).
+template <typename T, int NR>
+__device__ __forceinline__ void wave_r2c_store_rows(const cpx<T> (&v)[NR][8], cpx<T>* buf, cpx<T> r1, int lane,
+                                                    cpx<T>* Hrow, int ny, T scale) {
+    cpx<T> z0[NR];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
-    const cpx<T> z0 = v[0];
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) buf[NR * (lane + 64 * s) + r] = v[r][s];
+        z0[r] = v[r][0];
+    }
     wave_lds_sync();
     const T half = (T)0.5;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         const int k = lane + 64 * s;
         const cpx<T> wk = r1 * w16<T>(s);
-        const cpx<T> zk = buf[k], zm = buf[(WROW_M - lane - 64 * s) & (WROW_M - 1)];
-        cpx<T> X = half * (zk + cj(zm)) - half * mul_i(wk * (zk - cj(zm)));
-        if (k == 0) X = C<T>(zk.re + zk.im, 0);
-        Hrow[(size_t)k * ny] = scale * X;
+        const int m = (WROW_M - lane - 64 * s) & (WROW_M - 1);
+        cpx<T> X[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const cpx<T> zk = buf[NR * k + r], zm = buf[NR * m + r];
+            X[r] = half * (zk + cj(zm)) - half * mul_i(wk * (zk - cj(zm)));
+            if (k == 0) X[r] = C<T>(zk.re + zk.im, 0);
+            X[r] = scale * X[r];
+        }
+        rows_store<T, NR>(Hrow + (size_t)k * ny, X);
     }
-    if (lane == 0) Hrow[(size_t)WROW_M * ny] = scale * C<T>(z0.re - z0.im, 0);
+    if (lane == 0) {
+        cpx<T> X[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) X[r] = scale * C<T>(z0[r].re - z0[r].im, 0);
+        rows_store<T, NR>(Hrow + (size_t)WROW_M * ny, X);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void wave_r2c_store(const cpx<T> (&v)[8], cpx<T>* buf, cpx<T> r1, int lane,
+                                               cpx<T>* Hrow, int ny, T scale) {
+    wave_r2c_store_rows<T, 1>(reinterpret_cast<const cpx<T>(&)[1][8]>(v), buf, r1, lane, Hrow, ny, scale);
 }
 
 // Krylov row pass (the G apply's x-direction work, Def:G) on rows of 1024
-// points: one block per row, one wave per field (p_x, p_y, div p).  Each wave
-// loads its field's half-spectrum row, splits and inverse-transforms it, and
-// leaves the real row in its LDS region; after a block barrier wave f forms the
-// pointwise products of the slots [3f, 3f + 3) of all three fields
+// points: one block per NR consecutive rows, one wave per field (p_x, p_y,
+// div p) holding the field's NR rows.  Each wave loads its field's half-spectrum
+// rows, splits and inverse-transforms them, and leaves the real rows in its LDS
+// region; after a block barrier wave f forms the pointwise products of the slots
+// [3f, 3f + 3) of all three fields
 //   a = eta p + grad h (eta^2/2 div p + eta beta),  w = eta^3/3 div p + eta^2/2 beta,
 // beta = grad h . p, and the B-density eta|p|^2 + div p w + beta (eta^2/2 div p +
 // eta beta) of the curvature p.Gp (section 3.1); after a second barrier each wave
-// forward-transforms its field of (a, w) and stores it.  Launch: ny blocks of
-// 192 threads; part[part_base + block] receives the block's curvature sum.
-// Three waves per SIMD: at 1024 rows the whole grid (12 waves per CU) is then
-// resident at once.
-template <typename T, int RPB>
-__global__ void __launch_bounds__(192 * RPB) __attribute__((amdgpu_waves_per_eu(3))) k_pcg_r1w(int ny, const cpx<T>* __restrict__ tw,
+// forward-transforms its field of (a, w) and stores it.  Launch: ny / NR blocks
+// of 192 threads; part[part_base + block] receives the block's curvature sum.
+// Three waves per SIMD: at 1024 rows and NR = 1 the whole grid (12 waves per CU)
+// is then resident at once.  NR = 2 (FP32): the transposed H layout holds the
+// two rows' entries of one kx side by side, so each lane moves 16 bytes per
+// access instead of 8 and a wave's loads, stores and exchanges serve two rows.
+template <typename T, int NR>
+__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) k_pcg_r1w(int ny, const cpx<T>* __restrict__ tw,
                                                  SolveScal* __restrict__ sc, cpx<T>* H, size_t NS,
                                                  const T* __restrict__ eta, const T* __restrict__ gh,
                                                  double* __restrict__ part, int part_base) {
+    static_assert(NR == 1 || (NR == 2 && sizeof(T) == 4), "two rows per wave in FP32 only");
     // eta and grad h of the wave's pointwise slots are loaded before the inverse
     // transform, so their latency hides behind it
     constexpr bool PF = true;
     // the stop flag is read here and tested after the twiddle table is staged,
     // so its latency hides behind the table's loads
     const int done = sc->done;
-    __shared__ cpx<T> ldsa[RPB][3][WROW_BUF];
+    __shared__ __align__(16) cpx<T> lds[3][NR * WROW_BUF];
     __shared__ WaveTwl<T> tl;
-    __shared__ double red[16];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int rb = wv / 3, f = wv - 3 * rb;
-    cpx<T> (&lds)[3][WROW_BUF] = ldsa[rb];
-    const int y = xcd_remap(blockIdx.x, gridDim.x) * RPB + rb;
+    __shared__ double red[4];
+    const int f = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int y = xcd_remap(blockIdx.x, gridDim.x) * NR;
     cpx<T>* Hrow = H + (size_t)f * NS + y;
     cpx<T>* buf = lds[f];
     // FP64: twiddle table first (L2-resident; one L2 round trip per block instead
@@ -247,83 +335,99 @@ __global__ void __launch_bounds__(192 * RPB) __attribute__((amdgpu_waves_per_eu(
     }
     auto bases = [&]() { return TWREG ? wbr : wave_bases<T>(tl, lane); };
     auto r1 = [&]() { return TWREG ? r1r : tl.r[lane]; };
-    cpx<T> X[8];
+    cpx<T> X[NR][8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) X[s] = Hrow[(size_t)(lane + 64 * s) * ny];
-    const cpx<T> XM = lane == 0 ? Hrow[(size_t)WROW_M * ny] : C<T>(0, 0);
-    cpx<T> v[8];
-    wave_c2r_split<T>(v, X, XM, buf, r1(), lane);
+    for (int s = 0; s < 8; ++s) {
+        cpx<T> x[NR];
+        rows_load<T, NR>(Hrow + (size_t)(lane + 64 * s) * ny, x);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) X[r][s] = x[r];
+    }
+    cpx<T> XM[NR];
+    if (lane == 0) {
+        rows_load<T, NR>(Hrow + (size_t)WROW_M * ny, XM);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) XM[r] = C<T>(0, 0);
+    }
+    cpx<T> v[NR][8];
+    wave_c2r_split_rows<T, NR>(v, X, XM, buf, r1(), lane);
     const size_t npts = (size_t)WROW_NX * ny;
     const int m0 = 3 * f;
     const int ms = f == 2 ? 2 : 3;
+    // row r of eta (grad h) as complex pairs: entry n at er[r WROW_M + n]
     const cpx<T>* er = reinterpret_cast<const cpx<T>*>(eta + (size_t)y * WROW_NX);
     const cpx<T>* gxr = reinterpret_cast<const cpx<T>*>(gh + (size_t)y * WROW_NX);
     const cpx<T>* gyr = reinterpret_cast<const cpx<T>*>(gh + npts + (size_t)y * WROW_NX);
-    cpx<T> pe[3], px[3], py[3];
+    cpx<T> pe[NR][3], px[NR][3], py[NR][3];
     auto load_coeffs = [&]() {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            if (i < ms) {
-                const int n = lane + 64 * (m0 + i);
-                pe[i] = er[n];
-                px[i] = gxr[n];
-                py[i] = gyr[n];
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                if (i < ms) {
+                    const int n = r * WROW_M + lane + 64 * (m0 + i);
+                    pe[r][i] = er[n];
+                    px[r][i] = gxr[n];
+                    py[r][i] = gyr[n];
+                }
             }
-        }
     };
     if (PF) load_coeffs();
-    wave_fft512<T>(v, buf, bases(), lane, true);
+    wave_fft512_rows<T, NR>(v, buf, bases(), lane, true);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) buf[NR * (lane + 64 * s) + r] = v[r][s];
     block_lds_barrier();
 
     if (!PF) load_coeffs();
     double acc = 0.0;
     const T third = (T)1 / (T)3, half = (T)0.5;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        if (i < ms) {
-            const int n = lane + 64 * (m0 + i);
-            cpx<T> p0 = lds[0][n], p1 = lds[1][n], dv = lds[2][n];
-            const T et2[2] = {pe[i].re, pe[i].im};
-            const T hx2[2] = {px[i].re, px[i].im};
-            const T hy2[2] = {py[i].re, py[i].im};
-            T a0[2], a1[2], ww[2];
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const T et = et2[s];
-                const T pxs = s ? p0.im : p0.re, pys = s ? p1.im : p1.re, dl = s ? dv.im : dv.re;
-                const T bt = hx2[s] * pxs + hy2[s] * pys;
-                const T e2 = et * et;
-                const T w1 = third * e2 * et * dl + half * e2 * bt;
-                const T w2 = half * e2 * dl + et * bt;
-                const double pp = (double)pxs * (double)pxs + (double)pys * (double)pys;
-                acc += (double)et * pp + (double)dl * (double)w1 + (double)bt * (double)w2;
-                a0[s] = et * pxs + hx2[s] * w2;
-                a1[s] = et * pys + hy2[s] * w2;
-                ww[s] = w1;
+        for (int i = 0; i < 3; ++i) {
+            if (i < ms) {
+                const int n = NR * (lane + 64 * (m0 + i)) + r;
+                cpx<T> p0 = lds[0][n], p1 = lds[1][n], dv = lds[2][n];
+                const T et2[2] = {pe[r][i].re, pe[r][i].im};
+                const T hx2[2] = {px[r][i].re, px[r][i].im};
+                const T hy2[2] = {py[r][i].re, py[r][i].im};
+                T a0[2], a1[2], ww[2];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const T et = et2[s];
+                    const T pxs = s ? p0.im : p0.re, pys = s ? p1.im : p1.re, dl = s ? dv.im : dv.re;
+                    const T bt = hx2[s] * pxs + hy2[s] * pys;
+                    const T e2 = et * et;
+                    const T w1 = third * e2 * et * dl + half * e2 * bt;
+                    const T w2 = half * e2 * dl + et * bt;
+                    const double pp = (double)pxs * (double)pxs + (double)pys * (double)pys;
+                    acc += (double)et * pp + (double)dl * (double)w1 + (double)bt * (double)w2;
+                    a0[s] = et * pxs + hx2[s] * w2;
+                    a1[s] = et * pys + hy2[s] * w2;
+                    ww[s] = w1;
+                }
+                lds[0][n] = C<T>(a0[0], a0[1]);
+                lds[1][n] = C<T>(a1[0], a1[1]);
+                lds[2][n] = C<T>(ww[0], ww[1]);
             }
-            lds[0][n] = C<T>(a0[0], a0[1]);
-            lds[1][n] = C<T>(a1[0], a1[1]);
-            lds[2][n] = C<T>(ww[0], ww[1]);
         }
-    }
     // the block's curvature sum: waves in order after the barrier that also
     // publishes the pointwise results
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) red[wv] = acc;
+    if (lane == 0) red[f] = acc;
     block_lds_barrier();
-    if (part && threadIdx.x == 0) {
-        double sum = 0.0;
-        for (int i = 0; i < 3 * RPB; ++i) sum += red[i];
-        part[part_base + blockIdx.x] = sum;
-    }
+    if (part && threadIdx.x == 0) part[part_base + blockIdx.x] = red[0] + red[1] + red[2];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) v[s] = buf[lane + 64 * s];
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r][s] = buf[NR * (lane + 64 * s) + r];
     wave_lds_sync();
-    wave_fft512<T>(v, buf, bases(), lane, false);
-    wave_r2c_store<T>(v, buf, r1(), lane, Hrow, ny, (T)1);
+    wave_fft512_rows<T, NR>(v, buf, bases(), lane, false);
+    wave_r2c_store_rows<T, NR>(v, buf, r1(), lane, Hrow, ny, (T)1);
 }
 
 }  // namespace sgn
