@@ -858,8 +858,15 @@ __device__ __forceinline__ void publish_flags(const SolveScal* sc, int* d, int s
     v[7] = sc->outer;
     v[6] = seq;
 }
+__device__ __forceinline__ void inner_close(SolveScal* s, const SolveScal* d);
+// With inner set (the FP32 inner solve of a refinement step that has just
+// ended), thread 0 first adds that step to the counters (see inner_close).
 __global__ void __launch_bounds__(256) k_pcg_check(SolveScal* __restrict__ sc, const double* __restrict__ part,
-                                                   int nb3, int* pub, int seq) {
+                                                   int nb3, int* pub, int seq, const SolveScal* __restrict__ inner) {
+    if (inner) {
+        if (threadIdx.x == 0) inner_close(sc, inner);
+        __syncthreads();
+    }
     if (!sc->done) {
         __shared__ double red[32];
         __shared__ double slot[2];
@@ -1459,19 +1466,20 @@ __global__ void k_init_scal(SolveScal* __restrict__ sc, double tol, int max_iter
     }
 }
 
-// One refinement step enqueued without a host round trip: k_inner_open starts
-// the inner FP32 solve d of the step (the scalars of k_init_scal, the outer
-// solve's coefficients), or, when the outer solve s has already converged, marks
-// the inner solve done so that every kernel of the step returns at once.  The
-// inner tolerance is no tighter than the outer target needs: with outer residual
-// r, target tol ||b|| and inner stop ||r_in|| <= t ||r||, t = max(t_min,
-// c tol ||b|| / ||r||) (c2 = c^2), so once r is within a few orders of the target
-// the inner solve stops as soon as the corrected outer residual will meet it.
-// k_inner_close adds the step's inner iterations and the step itself to the
-// outer solve's counters (s->iter, s->outer) unless it was skipped.
-__global__ void k_inner_open(const SolveScal* __restrict__ s, SolveScal* __restrict__ d, double tol, int max_iter,
-                             double inv_n, double c2) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One refinement step enqueued without a host round trip: inner_open (run by
+// the first thread of k_inner_start) starts the inner FP32 solve d of the step
+// (the scalars of k_init_scal, the outer solve's coefficients), or, when the
+// outer solve s has already converged, marks the inner solve done so that every
+// kernel of the step returns at once.  The inner tolerance is no tighter than
+// the outer target needs: with outer residual r, target tol ||b|| and inner stop
+// ||r_in|| <= t ||r||, t = max(t_min, c tol ||b|| / ||r||) (c2 = c^2), so once r
+// is within a few orders of the target the inner solve stops as soon as the
+// corrected outer residual will meet it.  inner_close (run by k_pcg_check's
+// first thread after the step's FP64 residual) adds the step's inner iterations
+// and the step itself to the outer solve's counters (s->iter, s->outer) unless
+// it was skipped.
+__device__ __forceinline__ void inner_open(const SolveScal* __restrict__ s, SolveScal* __restrict__ d, double tol,
+                                           int max_iter, double inv_n, double c2) {
     if (s->done) {
         d->done = 1;
         return;
@@ -1496,8 +1504,7 @@ __global__ void k_inner_open(const SolveScal* __restrict__ s, SolveScal* __restr
         if (t2 > d->tol2) d->tol2 = t2 < 0.25 ? t2 : 0.25;
     }
 }
-__global__ void k_inner_close(SolveScal* __restrict__ s, const SolveScal* __restrict__ d) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void inner_close(SolveScal* s, const SolveScal* d) {
     if (s->done) return;
     s->iter += d->iter;
     s->outer += 1;
@@ -1736,17 +1743,20 @@ __global__ void k_zero_c(size_t n, void* __restrict__ p) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = 0.0;
 }
 
-// Start of an FP32 inner solve from the FP64 outer residual: r32 = (float) r,
-// x32 = 0, and the partials of r32.z, r32.r32, in one pass.
+// Start of an FP32 inner solve from the FP64 outer residual: the inner solve's
+// scalars (inner_open, first thread), r32 = (float) r, x32 = 0, and the
+// partials of r32.z, r32.r32, in one pass.  The other blocks read only the
+// outer scalars s, so the first thread's writes to sc race with nothing.
 template <int D>
-__global__ void __launch_bounds__(256) k_inner_start(int nx, int ny, size_t NS, SolveScal* __restrict__ sc,
-                                                     const cpx<double>* __restrict__ r64,
+__global__ void __launch_bounds__(256) k_inner_start(int nx, int ny, size_t NS, const SolveScal* __restrict__ s,
+                                                     SolveScal* __restrict__ sc, double tol, int max_iter,
+                                                     double inv_n, double c2, const cpx<double>* __restrict__ r64,
                                                      cpx<float>* __restrict__ r32, cpx<float>* __restrict__ x32,
                                                      double* __restrict__ part, float tpx, float tpy) {
     __shared__ double red[32];
-    if (sc->done) return;   // the refinement had already converged (see k_inner_open)
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->first = 1;
-    const float sig = (float)sc->sig, alp = (float)sc->alp;
+    if (blockIdx.x == 0 && threadIdx.x == 0) inner_open(s, sc, tol, max_iter, inv_n, c2);
+    if (s->done) return;   // the refinement had already converged
+    const float sig = (float)s->sig, alp = (float)s->alp;
     double acc[2] = {0.0, 0.0};
     const int nsi = (int)NS;
     const int lny = ilog2(ny);

@@ -956,24 +956,25 @@ sgn_status init_scal(sgn_ctx* ctx, SolveScal* sc, double tol, int max_iter, doub
 
 // Stop test; with pub set it also publishes the loop flags (sequence number seq).
 template <typename T, int D>
-sgn_status pcg_check(PcgLaunch<T, D>& P, int* pub = nullptr, int seq = 0) {
+sgn_status pcg_check(PcgLaunch<T, D>& P, int* pub = nullptr, int seq = 0, const SolveScal* inner = nullptr) {
     hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, P.ctx->stream, P.sc, (const double*)P.partials,
-                       P.cl.g.nblocks, pub, seq);
+                       P.cl.g.nblocks, pub, seq, inner);
     CHECK_LAUNCH(P.ctx);
     return SGN_OK;
 }
 
 // One chunk of `chunk` PCG iterations followed by the stop test (publishing the
-// flags with sequence number seq when pub is set).
+// flags with sequence number seq when pub is set; none when check is false, for
+// an inner solve whose state is discarded after the chunk).
 template <typename T, int D>
-sgn_status pcg_chunk_eager(PcgLaunch<T, D>& P, int chunk, int* pub = nullptr, int seq = 0) {
+sgn_status pcg_chunk_eager(PcgLaunch<T, D>& P, int chunk, int* pub = nullptr, int seq = 0, bool check = true) {
     for (int c = 0; c < chunk; ++c) {
         sgn_status s;
         if ((s = pcg_c1<T, D>(P, C1_UPDATE, nullptr)) != SGN_OK) return s;
         if ((s = pcg_r1<T, D>(P, true)) != SGN_OK) return s;
         if ((s = pcg_c2<T, D>(P, C2_UPDATE, nullptr, nullptr)) != SGN_OK) return s;
     }
-    return pcg_check<T, D>(P, pub, seq);
+    return check ? pcg_check<T, D>(P, pub, seq) : SGN_OK;
 }
 
 // The same chunk replayed from a HIP graph (captured on the second use of a
@@ -1420,28 +1421,30 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
         return rows_inv<double, double>(ctx, d, hs, ud, 1.0, 0.0, ctx->gx_off ? &od : nullptr, stores++ > 0);
     };
     // the inner FP32 solve of one refinement step and the FP64 residual after it;
-    // k_inner_open marks the inner solve done when the outer stop test has
-    // already converged, so that every kernel of the step returns at once
+    // the inner solve is marked done at once when the outer stop test has already
+    // converged, so that every kernel of the step returns at once
     auto open_inner = [&]() -> sgn_status {
-        hipLaunchKernelGGL(k_inner_open, dim3(1), dim3(64), 0, ctx->stream, (const SolveScal*)P.sc, Q.sc, inner_tol,
-                           o.max_iter, d.inv_n, INNER_SAFETY2);
-        CHECK_LAUNCH(ctx);
         ProfScope ps(ctx, SGN_KERNEL_PCG_INIT + 6);
-        // r32 = r, x32 = 0 and the inner solve's first partials, in one pass
-        hipLaunchKernelGGL((k_inner_start<D>), dim3(Q.cl.g.nblocks), dim3(256), 0, ctx->stream, d.nx, d.ny, d.NS, Q.sc,
+        // the inner scalars, r32 = r, x32 = 0 and the inner solve's first partials,
+        // in one pass
+        hipLaunchKernelGGL((k_inner_start<D>), dim3(Q.cl.g.nblocks), dim3(256), 0, ctx->stream, d.nx, d.ny, d.NS,
+                           (const SolveScal*)P.sc, Q.sc, inner_tol, o.max_iter, d.inv_n, INNER_SAFETY2,
                            (const cpx<double>*)P.b.rh, Q.b.rh, Q.b.xh, Q.partials, (float)d.tpx, (float)d.tpy);
         CHECK_LAUNCH(ctx);
         return SGN_OK;
     };
     auto close_inner = [&]() -> sgn_status {
-        hipLaunchKernelGGL(k_inner_close, dim3(1), dim3(64), 0, ctx->stream, P.sc, (const SolveScal*)Q.sc);
-        CHECK_LAUNCH(ctx);
         // x_hat += dx_hat inside the pass that starts G x_hat; r_hat = b_hat - G x_hat
         // (FP64) with its dot products
         sgn_status t;
         if ((t = pcg_c1<double, D>(P, C1_ACCUM, nullptr, Q.b.xh)) != SGN_OK) return t;
         if ((t = pcg_r1<double, D>(P)) != SGN_OK) return t;
         return pcg_c2<double, D>(P, C2_RESID, P.b.bh, P.b.rh);
+    };
+    // the outer stop test after a refinement step, which first counts the step
+    // and its inner iterations
+    auto check_outer = [&](int* pub) -> sgn_status {
+        return pcg_check<double, D>(P, pub, ctx->pub_seq, (const SolveScal*)Q.sc);
     };
     // stop test of the initial residual (a step after it returns at once if it converged)
     if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
@@ -1459,11 +1462,14 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
         int chunk_in = std::max(1, std::min(o.max_iter, last_in > 0 ? last_in + 1 : o.check_every));
         while (outer < max_outer) {
             if ((s = open_inner()) != SGN_OK) return s;
-            if ((s = pcg_chunk_eager<float, D>(Q, chunk_in)) != SGN_OK) return s;
+            if ((s = pcg_chunk_eager<float, D>(Q, chunk_in, nullptr, 0, false)) != SGN_OK) return s;
             if ((s = close_inner()) != SGN_OK) return s;
             ++outer;
-            if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
-            if ((s = issue_loop_readback(ctx, P.sc)) != SGN_OK) return s;
+            // the stop test publishes the flags itself when the context has a
+            // host-coherent flag buffer
+            if (ctx->dpub) next_pub_seq(ctx);
+            if ((s = check_outer(ctx->dpub)) != SGN_OK) return s;
+            if ((s = issue_loop_readback(ctx, P.sc, ctx->dpub != nullptr)) != SGN_OK) return s;
             if ((s = store()) != SGN_OK) return s;
             if ((s = wait_loop_readback(ctx, &lo)) != SGN_OK) return s;
             if (lo.done) break;
@@ -1481,7 +1487,7 @@ sgn_status solve_mixed(sgn_ctx* ctx, const Dims& d, const double* eta, const dou
             if ((s = pcg_loop<float, D>(Q, o.max_iter, o.check_every, &li)) != SGN_OK) return s;
             if ((s = close_inner()) != SGN_OK) return s;
             ++outer;
-            if ((s = pcg_check<double, D>(P)) != SGN_OK) return s;
+            if ((s = check_outer(nullptr)) != SGN_OK) return s;
             if ((s = read_loop(ctx, P.sc, &lo)) != SGN_OK) return s;
         }
         if ((s = store()) != SGN_OK) return s;
