@@ -202,23 +202,21 @@ __global__ void __launch_bounds__(MAXT) k_rows_inv(RowGeom g, PtrList<const cpx<
 // ---------------------------------------------------------------------------
 
 // Source field i of the right-hand side's forward transforms at one point:
-// [u_c (D), eta u_c (D), eta, -eta u_a u_b (a <= b), beta = grad h . u].  The
-// momentum flux enters negated: its divergence is later summed with grad S in
-// the spectral domain, so both reach U_t through one pair of inverse transforms.
+// [u_c (D), eta u_c (D), eta, -eta u_1 u_D, beta = grad h . u].  The momentum
+// flux enters negated: its divergence is later summed with grad S in the
+// spectral domain, so both reach U_t through one pair of inverse transforms.
+// In 2D only the mixed flux -eta u_x u_y is transformed here: the diagonal
+// terms reach U_t only through d_x (eta u_x^2) and d_y (eta u_y^2), so the
+// inverse pass folds them into S_x = S - eta u_x^2 and S_y = S - eta u_y^2, and
+// (U_t)_x gains d_x S_x - d_y (eta u_x u_y), (U_t)_y gains d_y S_y - d_x (eta u_x u_y).
 template <int D>
 __device__ __forceinline__ double rhs_source(int i, double e, const double (&uc)[D], const double (&hc)[D]) {
     if (i < D) return uc[i];
     if (i < 2 * D) return e * uc[i - D];
     if (i == 2 * D) return e;
-    if (D == 1) {
-        if (i == 3) return -(e * uc[0] * uc[0]);
-        return hc[0] * uc[0];
-    }
-    if (i == 5) return -(e * uc[0] * uc[0]);
-    if (i == 6) return -(e * uc[0] * uc[1 % D]);
-    if (i == 7) return -(e * uc[1 % D] * uc[1 % D]);
+    if (i == 2 * D + 1) return -(e * uc[0] * uc[D - 1]);
     double b = hc[0] * uc[0];
-    b += hc[1 % D] * uc[1 % D];
+    if (D == 2) b += hc[1 % D] * uc[1 % D];
     return b;
 }
 
@@ -240,7 +238,7 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_fwd(RowGeom g, const double* 
     const cpx<double>* twm = twl_setup<double>(tw, g.M, lds + row_lds_data(g, NFG));
     const RowThread<double> rt = row_thread<double>(g, lds);
     const size_t npts = (size_t)g.nx * g.ny;
-    constexpr int NFLD = 2 * D + 1 + (D == 2 ? 3 : 1) + 1;
+    constexpr int NFLD = 2 * D + 3;
     // the inputs of this thread's points: eta, u_c and beta (the last field)
     constexpr bool KEEP = MAXT <= 256;
     constexpr int EK = KEEP ? EPC : 1;
@@ -327,12 +325,14 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_fwd(RowGeom g, const double* 
 // e^2/2 Q, T = e^2/2 P + e m delta + m beta + e Q with P = u.grad(delta) -
 // delta^2 and Q = u.grad(beta) (the reading u.grad(u.grad h)), so that at most
 // four values per point are live.  S's forward row transform goes to Sdst
-// (grad S is added to U_t later).
+// (grad S is added to U_t later); in 2D S_x = S - eta u_x^2 goes to Sdst and
+// S_y = S - eta u_y^2 to Sydst (see rhs_source).
 template <int D, int EPC, int NFG, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_rhs_rows_inv(RowGeom g, PtrList<const cpx<double>, MAXF> src,
                                                        const double* __restrict__ eta, const double* __restrict__ u,
                                                        const double* __restrict__ gh, double* __restrict__ eta_t,
                                                        double* __restrict__ U_t, cpx<double>* __restrict__ Sdst,
+                                                       cpx<double>* __restrict__ Sydst,
                                                        const cpx<double>* __restrict__ tw, double scale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<double>* lds = reinterpret_cast<cpx<double>*>(smem_raw);
@@ -405,24 +405,42 @@ __global__ void __launch_bounds__(MAXT) k_rhs_rows_inv(RowGeom g, PtrList<const 
             }
         }
     }
-    // U_t = U_t - T grad h; S forward-transformed
-    cpx<double> zs[1][EPC];
+    // U_t = U_t - T grad h; S (2D: S_x, S_y) forward-transformed
+    cpx<double> zs[D][EPC];
 #pragma unroll
     for (int e = 0; e < EPC; ++e) {
         const int j = rt.t + g.TPR * e;
-        zs[0][e] = C<double>(0, 0);
+#pragma unroll
+        for (int c = 0; c < D; ++c) zs[c][e] = C<double>(0, 0);
         if (j < g.M && rt.valid) {
             const size_t o = (size_t)rt.y * g.nx + 2 * j;
+            double sc[D][2];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
 #pragma unroll
-                for (int c = 0; c < D; ++c) U_t[c * npts + o + s] = Ut[c][e][s] - gh[c * npts + o + s] * A1[e][s];
+                for (int c = 0; c < D; ++c) {
+                    U_t[c * npts + o + s] = Ut[c][e][s] - gh[c * npts + o + s] * A1[e][s];
+                    if (D == 2) {
+                        const double uc = u[c * npts + o + s];
+                        sc[c][s] = A0[e][s] - eta[o + s] * uc * uc;
+                    } else {
+                        sc[c][s] = A0[e][s];
+                    }
+                }
             }
-            zs[0][e] = C<double>(A0[e][0], A0[e][1]);
+#pragma unroll
+            for (int c = 0; c < D; ++c) zs[c][e] = C<double>(sc[c][0], sc[c][1]);
         }
     }
-    cpx<double>* Hs1[1] = {Sdst};
-    row_forward<double, EPC, 1>(g, rt, zs, Hs1, tw, twm, 1.0);
+    // one field at a time: the launch's LDS holds NFG fields
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        cpx<double> z1[1][EPC];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) z1[0][e] = zs[c][e];
+        cpx<double>* H1[1] = {c == 0 ? Sdst : Sydst};
+        row_forward<double, EPC, 1>(g, rt, z1, H1, tw, twm, 1.0);
+    }
 }
 
 // Linear spectral operators on columns: out_o = sum_i c(code[o][i], k) in_i, with

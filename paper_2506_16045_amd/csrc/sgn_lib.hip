@@ -648,8 +648,7 @@ struct RhsBufs {
 RhsBufs carve_rhs(Carve& cv, const Dims& d) {
     RhsBufs b;
     const int D = d.D;
-    const int nd2 = D == 2 ? 3 : 1;
-    b.nH = (2 * D + 1) + (nd2 + 1) + (2 * D + 2) + (2 * D);
+    b.nH = (2 * D + 1) + 2 + (2 * D + 2) + (2 * D);
     b.H = cv.take<cpx<double>>((size_t)b.nH * d.NS);
     return b;
 }
@@ -2039,19 +2038,19 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     carve_common(cv);
     RhsBufs b = carve_rhs(cv, d);
     const size_t N = d.N, NS = d.NS;
-    const int nd2 = D == 2 ? 3 : 1;
     // a 2D grid between walls on its own points: eta, grad h, u (and the results)
     // in transform order; only the column operators differ
     const bool wall = D == 2 && ctx->wall_native;
     cpx<double>* HA = b.H;                    // 2D + 1
-    cpx<double>* HB = HA + (2 * D + 1) * NS;  // nd2 + 1
-    cpx<double>* OA = HB + (nd2 + 1) * NS;    // 2D + 2
+    cpx<double>* HB = HA + (2 * D + 1) * NS;  // 2
+    cpx<double>* OA = HB + 2 * NS;            // 2D + 2
     cpx<double>* OB = OA + (2 * D + 2) * NS;  // 2D
     sgn_status s;
-    // products and forward transforms: group A = [u_c, eta u_c, eta], group B = [eta u_i u_j, beta]
+    // products and forward transforms: group A = [u_c, eta u_c, eta], group B =
+    // [-eta u_1 u_D, beta] (the source fields of rhs_source)
     std::vector<cpx<double>*> dA, dB;
     for (int i = 0; i < 2 * D + 1; ++i) dA.push_back(HA + i * NS);
-    for (int i = 0; i < nd2 + 1; ++i) dB.push_back(HB + i * NS);
+    for (int i = 0; i < 2; ++i) dB.push_back(HB + i * NS);
     // the fused right-hand-side row passes transform their fields one at a time
     // (lockstep groups need more registers than the pointwise state leaves)
     // (the fused right-hand-side row passes keep 256-thread blocks: their pointwise
@@ -2106,7 +2105,7 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
         std::vector<LinJobSpec> jobs = {
             {{cA[0], cA[1]}, {oA[0], oA[1], oA[2]}, {{2, 3}, {4, 5}, {5, 6}}, {1, 2}, {0, 1, 2}},
             {{cA[2], cA[3], cA[4]}, {oA[3], oA[4], oA[5]}, {{2, 3, 0}, {0, 0, 2}, {0, 0, 3}}, {1, 2, 0}, {0, 1, 2}},
-            {{cB[3]}, {oB[0], oB[1]}, {{2}, {3}}, {0}, {1, 2}},
+            {{cB[1]}, {oB[0], oB[1]}, {{2}, {3}}, {0}, {1, 2}},
         };
         if ((s = cols_lin_jobs(ctx, d, jobs, d.inv_n, SGN_KERNEL_RHS_COLS, wall)) != SGN_OK) return s;
     } else {
@@ -2116,7 +2115,9 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     }
     // back to physical: Q = [m, delta, d delta (D), d eta (D), d beta (D)], consumed
     // pointwise into eta_t, U_t (without grad S - div(eta u (x) u)) and S, whose row
-    // transform goes to HA (slot 0)
+    // transform goes to HA (slot 0; in 2D S_x = S - eta u_x^2 there and S_y =
+    // S - eta u_y^2 in slot 1, the inputs of the column pass in slots 0 and 1
+    // having been consumed)
     {
         ProfScope ps(ctx, D == 2 ? SGN_KERNEL_RHS_ROWS_INV : SGN_KERNEL_ROWS);
         PtrList<const cpx<double>, MAXF> q{};
@@ -2129,13 +2130,13 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
         auto launch = [&](auto k) -> sgn_status {
             HIPCHK(ctx, allow_lds(k, rlds));
             hipLaunchKernelGGL(k, dim3(RL.g.nblocks), dim3(RL.threads), rlds, ctx->stream, RL.g, q, eta, u, gh, eta_t,
-                               U_t, HA, ctx->tw64, 1.0);
+                               U_t, HA, D == 2 ? HA + NS : nullptr, ctx->tw64, 1.0);
             CHECK_LAUNCH(ctx);
             return SGN_OK;
         };
         if (D == 2 && wave_rows(d) && q.n == 8) {
             hipLaunchKernelGGL(k_rhs_rows_inv_w, dim3(d.ny), dim3(512), 0, ctx->stream, d.ny, q, eta, u, gh, eta_t,
-                               U_t, HA, ctx->tw64, 1.0);
+                               U_t, HA, HA + NS, ctx->tw64, 1.0);
             CHECK_LAUNCH(ctx);
             s = SGN_OK;
         } else if (RL.epc == 4 && RL.threads <= 256)
@@ -2151,10 +2152,10 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     std::vector<cpx<double>*> gS;
     for (int c = 0; c < D; ++c) gS.push_back(OA + c * NS);
     if (D == 2) {
-        // one job per component, side by side (S and the mixed flux term are
-        // transformed by both; the shorter chain per block wins over the saved work)
-        std::vector<LinJobSpec> fj = {{{HA, cB[0], cB[1]}, {gS[0]}, {{2, 2, 3}}, {0, 0, 3}, {1}},
-                                      {{HA, cB[1], cB[2]}, {gS[1]}, {{3, 2, 3}}, {0, 3, 0}, {2}}};
+        // (U_t)_x += d_x S_x + d_y (-eta u_x u_y), (U_t)_y += d_x (-eta u_x u_y) +
+        // d_y S_y: three transformed inputs, two outputs, one job
+        std::vector<LinJobSpec> fj = {
+            {{HA, cB[0], HA + NS}, {gS[0], gS[1]}, {{2, 3, 0}, {0, 2, 3}}, {0, 3, 0}, {1, 2}}};
         if ((s = cols_lin_jobs(ctx, d, fj, d.inv_n, SGN_KERNEL_RHS_FLUX, wall)) != SGN_OK) return s;
     } else {
         if ((s = cols_lin<double>(ctx, d, {HA, cB[0]}, gS, {{2, 2}}, d.inv_n)) != SGN_OK) return s;

@@ -567,14 +567,16 @@ __global__ void __launch_bounds__(64 * WROW_WPB) k_rows_inv_w(int ny, PtrList<co
 // pointwise right-hand side (the k_rhs_rows_inv contract): one block per row,
 // wave q inverse-transforms field q into LDS; after a barrier wave q forms, at
 // the points of its slot q, eta_t = -m, U_t = -eta grad(eta - h) - T grad h and
-// S of Def:bigF (S, T from P = u.grad(delta) - delta^2 and Q = u.grad(beta));
-// after a second barrier wave 0 forward-transforms S into Sdst.  Launch: ny
-// blocks of 512 threads.
+// S of Def:bigF (S, T from P = u.grad(delta) - delta^2 and Q = u.grad(beta)),
+// kept as S_x = S - eta u_x^2 and S_y = S - eta u_y^2 (see rhs_source); after a
+// second barrier waves 0 and 1 forward-transform S_x into Sdst and S_y into
+// Sydst.  Launch: ny blocks of 512 threads.
 __global__ void __launch_bounds__(512) k_rhs_rows_inv_w(int ny, PtrList<const cpx<double>, MAXF> src,
                                                         const double* __restrict__ eta,
                                                         const double* __restrict__ u,
                                                         const double* __restrict__ gh, double* __restrict__ eta_t,
                                                         double* __restrict__ U_t, cpx<double>* __restrict__ Sdst,
+                                                        cpx<double>* __restrict__ Sydst,
                                                         const cpx<double>* __restrict__ tw, double scale) {
     __shared__ cpx<double> ldsr[8][WROW_BUF];
     __shared__ WaveTwl<double> tl;
@@ -602,7 +604,7 @@ __global__ void __launch_bounds__(512) k_rhs_rows_inv_w(int ny, PtrList<const cp
 #pragma unroll
     for (int s = 0; s < 8; ++s) buf[lane + 64 * s] = v[s];
     block_lds_barrier();
-    double Sv[2], et[2], ut0[2], ut1[2];
+    double Sx[2], Sy[2], et[2], ut0[2], ut1[2];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         double qv[8];
@@ -638,20 +640,23 @@ __global__ void __launch_bounds__(512) k_rhs_rows_inv_w(int ny, PtrList<const cp
         }
         ut0[p] = U0 - hc[0] * A1;
         ut1[p] = U1 - hc[1] * A1;
-        Sv[p] = A0;
+        Sx[p] = A0 - e0 * uc[0] * uc[0];
+        Sy[p] = A0 - e0 * uc[1] * uc[1];
     }
     reinterpret_cast<cpx<double>*>(eta_t + o)[n] = C<double>(et[0], et[1]);
     reinterpret_cast<cpx<double>*>(U_t + o)[n] = C<double>(ut0[0], ut0[1]);
     reinterpret_cast<cpx<double>*>(U_t + npts + o)[n] = C<double>(ut1[0], ut1[1]);
-    // slot n of field 0 is read by this wave only, so S takes its place
-    ldsr[0][n] = C<double>(Sv[0], Sv[1]);
+    // slot n of fields 0 and 1 is read by this wave only, so S_x and S_y take
+    // their places
+    ldsr[0][n] = C<double>(Sx[0], Sx[1]);
+    ldsr[1][n] = C<double>(Sy[0], Sy[1]);
     block_lds_barrier();
-    if (q != 0) return;
+    if (q > 1) return;
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = buf[lane + 64 * s];
     wave_lds_sync();
     wave_fft512<double>(v, buf, wave_bases<double>(tl, lane), lane, false);
-    wave_r2c_store<double>(v, buf, tl.r[lane], lane, Sdst + y, ny, 1.0);
+    wave_r2c_store<double>(v, buf, tl.r[lane], lane, (q == 0 ? Sdst : Sydst) + y, ny, 1.0);
 }
 
 }  // namespace sgn

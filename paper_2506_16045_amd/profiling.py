@@ -37,7 +37,7 @@ def kernel_family(demangled: str, grid_size: int = 0, n: int = 0):
         return "rhs_rows_inv", "f64"
     if re.search(r"k_cols_lin_jobs<double, 4, [34], 3>", demangled) and n:
         jobs = round(grid_size / (256 * (n // 2 + 1)))
-        return ("rhs_cols", "f64") if jobs == 3 else ("rhs_flux", "f64") if jobs == 2 else None
+        return ("rhs_cols", "f64") if jobs == 3 else ("rhs_flux", "f64") if jobs == 1 else None
     m = re.search(r"k_pcg_(c1|r1|c2|init)w?<(double|float)(?:, (\d+))?(?:, (\d+))?(?:, (\d+|true|false))?", demangled)
     if not m:
         return None
