@@ -2095,6 +2095,10 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
     for (int i = 0; i < 2 * D + 2; ++i) oA.push_back(OA + i * NS);
     for (int i = 0; i < 2 * D; ++i) oB.push_back(OB + i * NS);
     // codes: 1 id, 2 ikx, 3 iky, 4 (ikx)^2, 5 (ikx)(iky), 6 (iky)^2
+    // Periodic rows of 1024 points: the inverse row pass (k_rhs_rows_inv_w) forms
+    // the x-derivatives of delta, eta and beta itself (i k_x times a row spectrum
+    // it loads anyway), so the column pass skips those three outputs.
+    const bool dx_rows = D == 2 && !wall && wave_rows(d);
     if (D == 2) {
         // the column operators, split by shared inputs so that each block holds
         // at most three transformed inputs in registers, run side by side in one
@@ -2107,6 +2111,13 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
             {{cA[2], cA[3], cA[4]}, {oA[3], oA[4], oA[5]}, {{2, 3, 0}, {0, 0, 2}, {0, 0, 3}}, {1, 2, 0}, {0, 1, 2}},
             {{cB[1]}, {oB[0], oB[1]}, {{2}, {3}}, {0}, {1, 2}},
         };
+        if (dx_rows) {
+            // d_x delta, d_x eta and d_x beta are formed by the inverse row pass
+            // from delta's output and the row spectra of eta and beta
+            jobs = {{{cA[0], cA[1]}, {oA[0], oA[2]}, {{2, 3}, {5, 6}}, {1, 2}, {0, 2}},
+                    {{cA[2], cA[3], cA[4]}, {oA[3], oA[5]}, {{2, 3, 0}, {0, 0, 3}}, {1, 2, 0}, {0, 2}},
+                    {{cB[1]}, {oB[1]}, {{3}}, {0}, {2}}};
+        }
         if ((s = cols_lin_jobs(ctx, d, jobs, d.inv_n, SGN_KERNEL_RHS_COLS, wall)) != SGN_OK) return s;
     } else {
         if ((s = cols_lin<double>(ctx, d, cA, oA, {{2, 0, 0}, {4, 0, 0}, {0, 2, 0}, {0, 0, 2}}, d.inv_n)) != SGN_OK)
@@ -2135,8 +2146,16 @@ sgn_status rhs_impl(sgn_ctx* ctx, const Dims& d, const double* eta, const double
             return SGN_OK;
         };
         if (D == 2 && wave_rows(d) && q.n == 8) {
+            RowDx dx{};
+            if (dx_rows) {
+                q.p[2] = OA;                       // delta's output: d_x delta = i k_x delta
+                q.p[4] = HA + 2 * D * NS;          // eta's row spectrum
+                q.p[6] = HB + NS;                  // beta's row spectrum
+                dx.f[2] = 1.0;
+                dx.f[4] = dx.f[6] = 1.0 / d.nx;
+            }
             hipLaunchKernelGGL(k_rhs_rows_inv_w, dim3(d.ny), dim3(512), 0, ctx->stream, d.ny, q, eta, u, gh, eta_t,
-                               U_t, HA, HA + NS, ctx->tw64, 1.0);
+                               U_t, HA, HA + NS, ctx->tw64, 1.0, dx, d.tpx);
             CHECK_LAUNCH(ctx);
             s = SGN_OK;
         } else if (RL.epc == 4 && RL.threads <= 256)

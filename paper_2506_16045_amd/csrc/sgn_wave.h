@@ -571,13 +571,22 @@ __global__ void __launch_bounds__(64 * WROW_WPB) k_rows_inv_w(int ny, PtrList<co
 // kept as S_x = S - eta u_x^2 and S_y = S - eta u_y^2 (see rhs_source); after a
 // second barrier waves 0 and 1 forward-transform S_x into Sdst and S_y into
 // Sydst.  Launch: ny blocks of 512 threads.
+// An x-derivative field needs no column transform: with dx.f[q] != 0, wave q
+// loads the row spectrum src.p[q] of the field it differentiates (a column
+// pass output, f = 1, or a forward row transform, f = 1/nx, the column pass's
+// scale of 1/(nx ny) times the ny of its y round trip) and multiplies entry kx
+// by i k_x f before the inverse transform (the Nyquist entry has no wavenumber).
+struct RowDx {
+    double f[8];
+};
 __global__ void __launch_bounds__(512) k_rhs_rows_inv_w(int ny, PtrList<const cpx<double>, MAXF> src,
                                                         const double* __restrict__ eta,
                                                         const double* __restrict__ u,
                                                         const double* __restrict__ gh, double* __restrict__ eta_t,
                                                         double* __restrict__ U_t, cpx<double>* __restrict__ Sdst,
                                                         cpx<double>* __restrict__ Sydst,
-                                                        const cpx<double>* __restrict__ tw, double scale) {
+                                                        const cpx<double>* __restrict__ tw, double scale, RowDx dx,
+                                                        double tpx) {
     __shared__ cpx<double> ldsr[8][WROW_BUF];
     __shared__ WaveTwl<double> tl;
     const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -589,7 +598,8 @@ __global__ void __launch_bounds__(512) k_rhs_rows_inv_w(int ny, PtrList<const cp
     cpx<double> X[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) X[s] = Hrow[(size_t)(lane + 64 * s) * ny];
-    const cpx<double> XM = lane == 0 ? Hrow[(size_t)WROW_M * ny] : C<double>(0, 0);
+    cpx<double> XM = lane == 0 ? Hrow[(size_t)WROW_M * ny] : C<double>(0, 0);
+    const double fq = dx.f[q];
     // inputs at this wave's pointwise slot (n = lane + 64 q), in flight during the transform
     const size_t npts = (size_t)WROW_NX * ny, o = (size_t)y * WROW_NX;
     const int n = lane + 64 * q;
@@ -598,6 +608,11 @@ __global__ void __launch_bounds__(512) k_rhs_rows_inv_w(int ny, PtrList<const cp
     const cpx<double> pu1 = reinterpret_cast<const cpx<double>*>(u + npts + o)[n];
     const cpx<double> ph0 = reinterpret_cast<const cpx<double>*>(gh + o)[n];
     const cpx<double> ph1 = reinterpret_cast<const cpx<double>*>(gh + npts + o)[n];
+    if (fq != 0.0) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) X[s] = ik(wavenumber<double>(lane + 64 * s, WROW_NX, tpx) * fq, X[s]);
+        XM = C<double>(0, 0);
+    }
     cpx<double> v[8];
     wave_c2r_split<double>(v, X, XM, buf, tl.r[lane], lane);
     wave_fft512<double>(v, buf, wave_bases<double>(tl, lane), lane, true);
