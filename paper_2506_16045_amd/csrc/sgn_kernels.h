@@ -1247,31 +1247,40 @@ __global__ void __launch_bounds__(256) k_pcg_setup(ColGeom g, const cpx<T>* __re
             const cpx<T>* srcs[D];
 #pragma unroll
             for (int c = 0; c < D; ++c) srcs[c] = Hu + c * NS;
-            col_load<T, EPC, D>(g, ct, srcs, true, twm, vu);
+            col_load<T, EPC, D>(g, ct, srcs, false, twm, vu);
         }
-        cpx<T> o[D + 1][EPC];
+        // the row pass's u0 columns need no y round trip: IFFT_y(x_hat / N) of
+        // x_hat = FFT_y(u0 rows) is the u0 rows times ny / N, stored as loaded;
+        // only div x_hat is formed in the spectral domain and inverse-transformed
+        const T sraw = inv_n * (T)g.ny;
+        if (ct.valid) {
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int j = ct.t + g.TPC * e;
+                if (j < g.ny) {
+#pragma unroll
+                    for (int c = 0; c < D; ++c) H[c * NS + (size_t)ct.kx * g.ny + j] = sraw * vu[c][e];
+                }
+            }
+        }
+        col_fft<T, EPC, D>(g, ct, twm, vu);
+        cpx<T> o[1][EPC];
 #pragma unroll
         for (int e = 0; e < EPC; ++e) {
             const int j = ct.t + g.TPC * e;
-#pragma unroll
-            for (int c = 0; c <= D; ++c) o[c][e] = C<T>(0, 0);
+            o[0][e] = C<T>(0, 0);
             if (ct.valid && j < g.ny) {
                 const size_t idx = (size_t)ct.kx * g.ny + j;
                 const T ky = (D == 2) ? wavenumber<T>(j, g.ny, tpy) : (T)0;
 #pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    xh[c * NS + idx] = vu[c][e];
-                    o[c][e] = inv_n * vu[c][e];
-                }
+                for (int c = 0; c < D; ++c) xh[c * NS + idx] = vu[c][e];
                 cpx<T> dv = ik(kx, vu[0][e]);
                 if (D == 2) dv = dv + ik(ky, vu[1 % D][e]);
-                o[D][e] = inv_n * dv;
+                o[0][e] = inv_n * dv;
             }
         }
-        cpx<T>* dsts[D + 1];
-#pragma unroll
-        for (int c = 0; c <= D; ++c) dsts[c] = H + c * NS;
-        col_store<T, EPC, D + 1>(g, ct, o, dsts, true, twm);
+        cpx<T>* dsts[1] = {H + D * NS};
+        col_store<T, EPC, 1>(g, ct, o, dsts, true, twm);
         return;
     }
     cpx<T> vb[D][EPC];
