@@ -193,6 +193,14 @@ typedef enum sgn_kernel_kind {
 } sgn_kernel_kind;
 sgn_status sgn_profile_begin(sgn_ctx *ctx);
 sgn_status sgn_profile_end(sgn_ctx *ctx, int64_t *launches, double *total_ms, int32_t nkinds);
+/* The individual launches timed between the last sgn_profile_begin and
+ * sgn_profile_end, in launch order: kinds[i] (an sgn_kernel_kind) and ms[i]
+ * (event time in milliseconds) for i < min(cap, count), host arrays of cap
+ * entries; *count receives the number recorded.  A Krylov pass launched after
+ * its solve has converged returns at once, so a family's durations are
+ * bimodal: callers that price launches by the bytes a full pass moves can
+ * tell the two apart here.  SGN_EINVAL on null pointers or cap < 0. */
+sgn_status sgn_profile_launches(const sgn_ctx *ctx, int32_t *kinds, float *ms, int64_t cap, int64_t *count);
 
 /* Bytes of workspace any single call below needs for this grid and precision. */
 size_t sgn_workspace_bytes(const sgn_grid *grid, int32_t precision);

@@ -36,6 +36,7 @@ struct sgn_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_next = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_marks;
+    std::vector<std::pair<int, float>> prof_last;   // the last profile's launches (kind, ms)
     // PCG iteration chunks captured as HIP graphs on a private stream and replayed
     // on `stream`; keyed by everything the captured launches depend on
     struct GraphEntry {
@@ -3130,9 +3131,11 @@ sgn_status sgn_profile_end(sgn_ctx* ctx, int64_t* launches, double* total_ms, in
         launches[k] = 0;
         total_ms[k] = 0.0;
     }
+    ctx->prof_last.clear();
     for (auto& m : ctx->prof_marks) {
         float ms = 0.0f;
         HIPCHK(ctx, hipEventElapsedTime(&ms, m.second.first, m.second.second));
+        ctx->prof_last.push_back({m.first, ms});
         if (m.first >= 0 && m.first < nkinds) {
             launches[m.first] += 1;
             total_ms[m.first] += ms;
@@ -3140,6 +3143,17 @@ sgn_status sgn_profile_end(sgn_ctx* ctx, int64_t* launches, double* total_ms, in
     }
     ctx->prof_marks.clear();
     ctx->ev_next = 0;
+    return SGN_OK;
+}
+
+sgn_status sgn_profile_launches(const sgn_ctx* ctx, int32_t* kinds, float* ms, int64_t cap, int64_t* count) {
+    if (!ctx || !count || cap < 0 || (cap > 0 && (!kinds || !ms))) return SGN_EINVAL;
+    const int64_t n = (int64_t)ctx->prof_last.size();
+    *count = n;
+    for (int64_t i = 0; i < n && i < cap; ++i) {
+        kinds[i] = ctx->prof_last[(size_t)i].first;
+        ms[i] = ctx->prof_last[(size_t)i].second;
+    }
     return SGN_OK;
 }
 

@@ -59,8 +59,13 @@ def kernel_stats(db_path: str):
     dem = demangle(agg)
     out = []
     for name, durs in agg.items():
+        # only the Krylov loop passes return early; other kernels' durations vary
+        # with their arguments (field counts), not with convergence
+        loop = re.search(r"k_pcg_(c1|r1|c2)w?<", dem[name]) is not None
+        full, early = split_launches(durs) if loop else (durs, [])
         out.append({"name": dem[name], "calls": len(durs), "total_ns": sum(durs),
-                    "avg_ns": sum(durs) / len(durs), "min_ns": min(durs), "max_ns": max(durs)})
+                    "avg_ns": sum(durs) / len(durs), "min_ns": min(durs), "max_ns": max(durs),
+                    "early": len(early), "avg_full_ns": sum(full) / len(full) if full else 0.0})
     out.sort(key=lambda r: -r["total_ns"])
     return out
 
@@ -70,12 +75,16 @@ def kernel_summary_md(db_path: str, command: str, title: str, top: int = 25) -> 
     total = sum(r["total_ns"] for r in st)
     lines = [f"# {title}", "", "Command:", "", "```", command, "```", "",
              f"Kernels: {len(st)} distinct, total GPU kernel time {total / 1e6:.2f} ms.", "",
-             "| kernel | calls | total ms | avg us | min us | max us | share |",
-             "|---|---|---|---|---|---|---|"]
+             "Early exits (Krylov loop passes only): launches shorter than half the kernel's median (a",
+             "pass launched after its solve has converged returns at once); `avg us (full)` averages the",
+             "other launches, the figure the bench's roofline prices with the bytes of a full pass.", "",
+             "| kernel | calls | total ms | avg us | min us | max us | share | early exits | avg us (full) |",
+             "|---|---|---|---|---|---|---|---|---|"]
     for r in st[:top]:
         nm = r["name"].split("(")[0].replace("|", "/")
         lines.append(f"| `{nm}` | {r['calls']} | {r['total_ns'] / 1e6:.3f} | {r['avg_ns'] / 1e3:.2f} | "
-                     f"{r['min_ns'] / 1e3:.2f} | {r['max_ns'] / 1e3:.2f} | {100 * r['total_ns'] / total:.1f}% |")
+                     f"{r['min_ns'] / 1e3:.2f} | {r['max_ns'] / 1e3:.2f} | {100 * r['total_ns'] / total:.1f}% | "
+                     f"{r['early']} | {r['avg_full_ns'] / 1e3:.2f} |")
     return "\n".join(lines) + "\n"
 
 
@@ -162,3 +171,18 @@ def traffic_by_kernel(fetch_db: str, write_db: str, calib_bytes: int, pattern: s
         out["kernels"].append({"kernel": nm, "grid_size": g, "dispatches": len(d["fetch"]),
                                "fetch_bytes": f, "write_bytes": w, "hbm_bytes_per_launch": f + w})
     return out
+
+
+def split_launches(durations):
+    """(full, early) launches of one kernel family: a Krylov pass launched after
+    its solve has converged returns at once, so a family's durations are bimodal;
+    launches shorter than half the family's median are the early exits.  (The
+    median is a full launch as long as fewer than half return early, which the
+    chunk sizing of the solves keeps so.)"""
+    ds = sorted(durations)
+    if not ds:
+        return [], []
+    med = ds[len(ds) // 2]
+    full = [d for d in durations if d >= 0.5 * med]
+    early = [d for d in durations if d < 0.5 * med]
+    return full, early

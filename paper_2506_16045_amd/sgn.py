@@ -105,6 +105,8 @@ _SIGS = {
     "sgn_version": (ctypes.c_char_p, []),
     "sgn_profile_begin": (_S, [_P]),
     "sgn_profile_end": (_S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), _I]),
+    "sgn_profile_launches": (_S, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                                  ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "sgn_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
     "sgn_gmres_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I]),
     "sgn_bathy_prepare": (_S, [_P, ctypes.POINTER(Grid), _P, _P, ctypes.POINTER(_I), _P]),
@@ -328,6 +330,21 @@ class Context:
         ms = (ctypes.c_double * n)()
         self._check(_lib.sgn_profile_end(self._h, cnt, ms, n))
         return {k: (int(cnt[i]), float(ms[i])) for i, k in enumerate(self.KERNEL_KINDS)}
+
+    def profile_launches(self):
+        """{kernel family: [milliseconds of each launch]} of the last profile, in launch
+        order (sgn_profile_launches)."""
+        count = ctypes.c_int64(0)
+        self._check(_lib.sgn_profile_launches(self._h, None, None, 0, ctypes.byref(count)))
+        cap = count.value
+        kinds = (ctypes.c_int32 * max(cap, 1))()
+        ms = (ctypes.c_float * max(cap, 1))()
+        self._check(_lib.sgn_profile_launches(self._h, kinds, ms, cap, ctypes.byref(count)))
+        out = {k: [] for k in self.KERNEL_KINDS}
+        for i in range(min(cap, count.value)):
+            if 0 <= kinds[i] < len(self.KERNEL_KINDS):
+                out[self.KERNEL_KINDS[kinds[i]]].append(float(ms[i]))
+        return out
 
     # -- entry points ----------------------------------------------------------
     def bathy_prepare(self, g, h: torch.Tensor):

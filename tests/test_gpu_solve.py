@@ -182,3 +182,21 @@ def test_full_size_2d_solve_residual_property(ctx):
         r = U - op.apply_G(cfg["eta"], gh, _n(u), g)
         assert np.linalg.norm(r) <= 1.5e-10 * np.linalg.norm(U)
         assert rel(_n(u), cfg["u"]) <= 1e-8
+
+
+def test_profile_launches_match_the_family_totals(ctx):
+    """sgn_profile_launches returns every launch the profile timed: per family the
+    same count and (to float rounding) the same summed time as sgn_profile_end, and
+    the Krylov row pass of a 2D solve is among them."""
+    from paper_2506_16045_amd import sgn
+    g, eta, h, b = _rows_1024(32, 64)
+    gh, _ = op.bathy_gradient(h, g)
+    print("profile launches 1024x32 fp64 solve", flush=True)
+    ctx.profile_begin()
+    ctx.krylov_solve(g, _t(eta), _t(gh), _t(b), opts=sgn.solve_opts(tol=1e-12))
+    totals = ctx.profile_end()
+    per = ctx.profile_launches()
+    assert len(per["pcg_r1"]) >= 2
+    for k, (n, ms) in totals.items():
+        assert len(per[k]) == n, k
+        assert abs(sum(per[k]) - ms) <= 1e-4 * max(ms, 1e-3), k
