@@ -143,3 +143,25 @@ def test_linimp3_choice_equals_the_oracles():
             assert abs(r - r_o) <= 1e-12 and abs(th - th_o) <= 1e-12 * th_o, (kappa, margin)
     with pytest.raises(sgn.SgnError):
         sgn.linimp3_choose(0.5)
+
+
+def test_launch_split_separates_early_exits():
+    """The bench prices full Krylov launches only: a family's bimodal durations
+    split at half the median (early exits of converged solves below it)."""
+    from paper_2506_16045_amd import profiling
+    full, early = profiling.split_launches([21.0, 4.1, 22.5, 20.8, 3.9, 24.0, 21.7])
+    assert sorted(early) == [3.9, 4.1] and len(full) == 5
+    assert profiling.split_launches([]) == ([], [])
+    full, early = profiling.split_launches([10.0, 10.5, 9.8])
+    assert early == [] and len(full) == 3
+
+
+def test_kernel_family_names_the_right_hand_side_launches():
+    """The rocprof summaries map the right-hand side's column launches by their
+    job count: three jobs (derivatives) and one (flux) at 1024^2."""
+    from paper_2506_16045_amd import profiling
+    name = "void sgn::k_cols_lin_jobs<double, 4, 3, 3>(sgn::ColGeom, ...)"
+    cols = 256 * 513
+    assert profiling.kernel_family(name, 3 * cols, 1024) == ("rhs_cols", "f64")
+    assert profiling.kernel_family(name, cols, 1024) == ("rhs_flux", "f64")
+    assert profiling.kernel_family("void sgn::k_pcg_r1w<float, 2>(int, ...)") == ("pcg_r1", "f32")
